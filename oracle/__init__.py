@@ -1,0 +1,181 @@
+"""CPU oracle for the population forward of tensorized NEAT.
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import this package.  It shares no
+code with the GPU library (``paper_2404_01817_amd``) and neither imports the
+other.
+
+Two independent formulations live here:
+
+* ``neat_oracle.c`` (loaded through ctypes): the plain definition of the
+  paper's inference (Section 3.3) on adjacency lists, in IEEE double, plus a
+  float instantiation of the same code and a first-order fp32 error bound.
+* ``dense.py``: the paper's own dense formulation (N_order and the expanded
+  connection tensor C_exp of Section 3.3) written out in numpy, used to
+  cross-check the C oracle.
+
+Status bits (per genome): BAD_VALUE 1, DUP_KEY 2, MISSING_IO 4, BAD_REF 8,
+INTO_INPUT 16, DUP_EDGE 32, CYCLE 64.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "neat_oracle.c")
+_INC = os.path.join(_HERE, "neat_oracle_forward.inc")
+LIB_PATH = os.path.join(_HERE, "liboracle.so")
+
+BAD_VALUE, DUP_KEY, MISSING_IO, BAD_REF, INTO_INPUT, DUP_EDGE, CYCLE = (
+    1, 2, 4, 8, 16, 32, 64)
+
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the C oracle with gcc (plain -O2, no fast-math, no FMA
+    contraction) into ``oracle/liboracle.so``."""
+    if not force and os.path.exists(LIB_PATH):
+        newest = max(os.path.getmtime(_SRC), os.path.getmtime(_INC))
+        if os.path.getmtime(LIB_PATH) >= newest:
+            return LIB_PATH
+    tmp = LIB_PATH + ".tmp%d" % os.getpid()
+    cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math",
+           "-fPIC", "-shared", "-Wall", "-o", tmp, _SRC, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, LIB_PATH)
+    return LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        build(force=False)
+        lib = ctypes.CDLL(LIB_PATH)
+        i32, i64, vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p
+        lib.oracle_transform.argtypes = [i32] * 5 + [vp] * 5
+        lib.oracle_transform.restype = i32
+        for name in ("oracle_forward_f64", "oracle_forward_f32"):
+            fn = getattr(lib, name)
+            fn.argtypes = [i32] * 5 + [vp, vp, vp, i64, i32, vp, vp]
+            fn.restype = i32
+        _lib = lib
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+def _check_genomes(nodes, conns, I, O):
+    nodes = np.ascontiguousarray(nodes, dtype=np.float32)
+    conns = np.ascontiguousarray(conns, dtype=np.float32)
+    if nodes.ndim != 3 or nodes.shape[2] != 5:
+        raise ValueError("nodes must be [P, N_max, 5]")
+    if conns.ndim != 3 or conns.shape[2] != 4 or conns.shape[0] != nodes.shape[0]:
+        raise ValueError("conns must be [P, C_max, 4]")
+    return nodes, conns
+
+
+def transform(nodes, conns, I: int, O: int):
+    """Transformation stage: returns (order [P,N_max] i32, level [P,N_max]
+    i32, status [P] u32).  ``order`` lists node rows by (level, key), -1
+    padded; rejected genomes get all -1 rows."""
+    nodes, conns = _check_genomes(nodes, conns, I, O)
+    P, N, _ = nodes.shape
+    C = conns.shape[1]
+    order = np.empty((P, N), np.int32)
+    level = np.empty((P, N), np.int32)
+    status = np.empty((P,), np.uint32)
+    rc = _load().oracle_transform(P, N, C, I, O, _ptr(nodes), _ptr(conns),
+                                  _ptr(order), _ptr(level), _ptr(status))
+    if rc != 0:
+        raise RuntimeError("oracle_transform failed: %d" % rc)
+    return order, level, status
+
+
+def forward(nodes, conns, inputs, I: int, O: int, shared_inputs=False,
+            precision="f64", with_beta=True):
+    """Transformation + calculation.
+
+    ``inputs`` is [P, B, I] (or [B, I] with ``shared_inputs``), float32.
+    Returns outputs [P, B, O] (float64 or float32) and, for f64 with
+    ``with_beta``, beta [P, B, O]: a first-order bound on the error of an fp32
+    evaluation of the same graph (inf where fp32 may overflow)."""
+    nodes, conns = _check_genomes(nodes, conns, I, O)
+    P, N, _ = nodes.shape
+    C = conns.shape[1]
+    x = np.ascontiguousarray(inputs, dtype=np.float32)
+    if shared_inputs:
+        if x.ndim != 2 or x.shape[1] != I:
+            raise ValueError("shared inputs must be [B, I]")
+        B, stride = x.shape[0], 0
+    else:
+        if x.ndim != 3 or x.shape[0] != P or x.shape[2] != I:
+            raise ValueError("inputs must be [P, B, I]")
+        B, stride = x.shape[1], x.shape[1] * I
+    lib = _load()
+    if precision == "f64":
+        y = np.empty((P, B, O), np.float64)
+        beta = np.empty((P, B, O), np.float64) if with_beta else None
+        rc = lib.oracle_forward_f64(P, N, C, I, O, _ptr(nodes), _ptr(conns),
+                                    _ptr(x), stride, B, _ptr(y),
+                                    _ptr(beta) if beta is not None else None)
+        if rc != 0:
+            raise RuntimeError("oracle_forward_f64 failed: %d" % rc)
+        return (y, beta) if with_beta else y
+    if precision == "f32":
+        y = np.empty((P, B, O), np.float32)
+        rc = lib.oracle_forward_f32(P, N, C, I, O, _ptr(nodes), _ptr(conns),
+                                    _ptr(x), stride, B, _ptr(y), None)
+        if rc != 0:
+            raise RuntimeError("oracle_forward_f32 failed: %d" % rc)
+        return y
+    raise ValueError("precision must be 'f64' or 'f32'")
+
+
+def order_keys(nodes, order):
+    """Express an order (node rows) as node keys, -1 padded."""
+    nodes = np.asarray(nodes)
+    P, N = order.shape
+    out = np.full((P, N), -1, np.int64)
+    for p in range(P):
+        for i in range(N):
+            r = order[p, i]
+            if r >= 0:
+                out[p, i] = int(nodes[p, r, 0])
+    return out
+
+
+def within_tolerance(y_gpu, y64, beta, atol=1e-5):
+    """The parity rule for fp32 results against the f64 oracle.
+
+    An output passes when
+      * beta is infinite (fp32 may overflow there; only counted), or
+      * the oracle value is NaN and the fp32 value is NaN too, or
+      * |y_gpu - y64| <= atol + 2 * beta.
+    Returns (ok_mask, stats)."""
+    y_gpu = np.asarray(y_gpu, dtype=np.float64)
+    y64 = np.asarray(y64, dtype=np.float64)
+    beta = np.asarray(beta, dtype=np.float64)
+    unbounded = np.isinf(beta)
+    ref_nan = np.isnan(y64) & ~unbounded
+    finite = ~unbounded & ~np.isnan(y64)
+    err = np.where(finite, np.abs(y_gpu - y64), 0.0)
+    err = np.where(np.isnan(err), np.inf, err)
+    ok = unbounded | (ref_nan & np.isnan(y_gpu)) | (finite & (err <= atol + 2.0 * beta))
+    well = finite & (beta <= 1e-6)
+    stats = {
+        "n": int(y64.size),
+        "max_abs_err_well_conditioned": float(err[well].max()) if well.any() else 0.0,
+        "max_abs_err": float(err[finite].max()) if finite.any() else 0.0,
+        "n_ill_conditioned": int((finite & (beta > 1e-6)).sum()),
+        "n_unbounded": int(unbounded.sum()),
+        "n_nan_ref": int(ref_nan.sum()),
+        "n_fail": int((~ok).sum()),
+    }
+    return ok, stats

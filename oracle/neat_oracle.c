@@ -1,0 +1,341 @@
+/*
+ * neat_oracle.c -- plain CPU oracle for the population forward of tensorized
+ * NEAT (Wang et al., "Tensorized NeuroEvolution of Augmenting Topologies for
+ * GPU Acceleration", GECCO 2024).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the
+ * CPU-baseline leg of the benchmark load this library.  It shares no source,
+ * header, table or helper with the GPU library, and the GPU library never
+ * calls it.
+ *
+ * What it computes is the plain definition behind Section 3.3 ("Tensorized
+ * Network Inference"): a feedforward evaluation of each genome's graph.  The
+ * paper's tensors (node order N_order, expanded connections C_exp) are only a
+ * fast way of doing that, so this file works on adjacency lists instead:
+ *
+ *   - Section 3.1 (Tensorized Encodings): a node row is
+ *     (key, bias, response, act, agg); a connection row is
+ *     (in key, out key, enabled, weight); rows padded with NaN are absent.
+ *   - Section 3.3: the transformation topologically sorts the nodes and keeps
+ *     the enabled connections' attributes; disabled rows become absent (NaN)
+ *     cells.  The calculation sets v[input] = I, then walks the order and
+ *     sets v[k] = f_n(f_c(v | incoming)), with f_c(x | w) = w x and
+ *     f_n(x | b, agg, act) = act(agg(x) + b); the outputs are v[output].
+ *   - Appendix (genome interface): input keys are 0..I-1 and output keys are
+ *     I..I+O-1.
+ *
+ * Readings where the paper is silent or ambiguous (each listed with its
+ * reason in the design notes):
+ *   - connection ends are node KEYS (historical markers), resolved to rows;
+ *   - the topological order is the level-synchronous Kahn order, ties broken
+ *     by key: nodes sorted by (level, key), level = longest path from a node
+ *     without incoming enabled edges;
+ *   - node value = act(bias + response * agg(incoming)), agg of nothing = 0
+ *     (response is a node attribute in the paper's hyper-parameters; every
+ *     experiment there keeps it at 1, where this equals f_n);
+ *   - act codes: 0 identity, 1 tanh, 2 sigmoid, 3 relu, 4 sin, 5 gaussian
+ *     exp(-z^2), 6 abs; agg codes: 0 sum, 1 product, 2 max, 3 min, 4 mean.
+ *     NaN propagates through every one of them (max/min/relu included);
+ *   - incoming values are aggregated in ascending source-key order;
+ *   - malformed genomes are flagged in a status bit-mask and produce NaN.
+ *
+ * Floating point: the reference arithmetic is IEEE double (oracle_forward_f64).
+ * The same code is also instantiated in float (oracle_forward_f32) so the
+ * tests can check the first-order error bound beta that the f64 version
+ * propagates for an fp32 evaluation of the same graph.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* status bits (per genome) */
+enum {
+    ST_BAD_VALUE = 1u,   /* non-integer / out-of-range key, code or flag */
+    ST_DUP_KEY = 2u,     /* two valid nodes share a key                  */
+    ST_MISSING_IO = 4u,  /* an input or output key is absent             */
+    ST_BAD_REF = 8u,     /* enabled connection names an absent key       */
+    ST_INTO_INPUT = 16u, /* enabled connection ends at an input node     */
+    ST_DUP_EDGE = 32u,   /* two enabled connections with the same ends   */
+    ST_CYCLE = 64u       /* the enabled connections contain a cycle      */
+};
+
+#define NODE_W 5
+#define CONN_W 4
+#define KEY_LIMIT 16777216.0 /* 2^24: keys stay exact in float */
+#define N_ACT 7
+#define N_AGG 5
+
+#define ORACLE_E_INVALID (-1)
+#define ORACLE_E_NOMEM (-3)
+#define ORACLE_E_SELFCHECK (-100)
+
+typedef struct {
+    int src, dst; /* node rows */
+    float w;
+} o_edge;
+
+/* Everything the transformation of one genome produces. */
+typedef struct {
+    uint32_t status;
+    int nvalid;
+    int *order;  /* [N_max] rows by (level, key), -1 padded */
+    int *level;  /* [N_max] level per row, -1 for absent rows */
+    o_edge *edges; /* resolved enabled edges */
+    int nedges;
+} o_genome;
+
+static int is_int_in(double x, double lo, double hi_excl) {
+    return !isnan(x) && x == floor(x) && x >= lo && x < hi_excl;
+}
+
+/* Row of the valid, well-keyed node whose key equals k, or -1. */
+static int find_row(const float *nodes, int N_max, float k) {
+    for (int r = 0; r < N_max; ++r) {
+        float key = nodes[r * NODE_W + 0];
+        if (isnan(key) || !is_int_in(key, 0.0, KEY_LIMIT)) continue;
+        if (key == k) return r;
+    }
+    return -1;
+}
+
+static void genome_free(o_genome *g) {
+    free(g->order);
+    free(g->level);
+    free(g->edges);
+    memset(g, 0, sizeof(*g));
+}
+
+/*
+ * Transformation of one genome (Section 3.3, first stage), plus the validity
+ * checks that make the encoding of Section 3.1 well defined.
+ */
+static int genome_transform(const float *nodes, const float *conns, int N_max,
+                            int C_max, int I, int O, o_genome *g) {
+    memset(g, 0, sizeof(*g));
+    g->order = (int *)malloc(sizeof(int) * (size_t)N_max);
+    g->level = (int *)malloc(sizeof(int) * (size_t)N_max);
+    g->edges = (o_edge *)malloc(sizeof(o_edge) * (size_t)(C_max > 0 ? C_max : 1));
+    if (!g->order || !g->level || !g->edges) return ORACLE_E_NOMEM;
+    for (int r = 0; r < N_max; ++r) {
+        g->order[r] = -1;
+        g->level[r] = -1;
+    }
+    uint32_t st = 0;
+
+    /* 1. node rows: a row is present iff its key (column 0) is not NaN */
+    for (int r = 0; r < N_max; ++r) {
+        const float *n = nodes + (size_t)r * NODE_W;
+        if (isnan(n[0])) continue;
+        g->nvalid++;
+        if (!is_int_in(n[0], 0.0, KEY_LIMIT)) st |= ST_BAD_VALUE;
+        if (!is_int_in(n[3], 0.0, (double)N_ACT)) st |= ST_BAD_VALUE;
+        if (!is_int_in(n[4], 0.0, (double)N_AGG)) st |= ST_BAD_VALUE;
+    }
+    /* duplicate keys among well-formed keys */
+    for (int r = 0; r < N_max; ++r) {
+        float kr = nodes[r * NODE_W];
+        if (isnan(kr) || !is_int_in(kr, 0.0, KEY_LIMIT)) continue;
+        for (int q = r + 1; q < N_max; ++q) {
+            float kq = nodes[q * NODE_W];
+            if (isnan(kq) || !is_int_in(kq, 0.0, KEY_LIMIT)) continue;
+            if (kq == kr) st |= ST_DUP_KEY;
+        }
+    }
+    /* input keys 0..I-1 and output keys I..I+O-1 must exist */
+    for (int k = 0; k < I + O; ++k)
+        if (find_row(nodes, N_max, (float)k) < 0) st |= ST_MISSING_IO;
+
+    /* 2. connection rows: padding iff column 0 is NaN; disabled rows ignored */
+    for (int r = 0; r < C_max; ++r) {
+        const float *c = conns + (size_t)r * CONN_W;
+        if (isnan(c[0])) continue;
+        if (c[2] == 0.0f) continue;
+        if (c[2] != 1.0f) {
+            st |= ST_BAD_VALUE;
+            continue;
+        }
+        int s = find_row(nodes, N_max, c[0]);
+        int d = find_row(nodes, N_max, c[1]);
+        if (s < 0 || d < 0) {
+            st |= ST_BAD_REF;
+            continue;
+        }
+        if (nodes[d * NODE_W] < (float)I) st |= ST_INTO_INPUT;
+        if (s == d) st |= ST_CYCLE;
+        for (int e = 0; e < g->nedges; ++e)
+            if (g->edges[e].src == s && g->edges[e].dst == d) st |= ST_DUP_EDGE;
+        g->edges[g->nedges].src = s;
+        g->edges[g->nedges].dst = d;
+        g->edges[g->nedges].w = c[3];
+        g->nedges++;
+    }
+
+    /* 3. levels by level-synchronous Kahn, only for an otherwise clean genome */
+    if (st == 0) {
+        int *indeg = (int *)calloc((size_t)N_max, sizeof(int));
+        char *emitted = (char *)calloc((size_t)N_max, 1);
+        char *ready = (char *)calloc((size_t)N_max, 1);
+        if (!indeg || !emitted || !ready) {
+            free(indeg), free(emitted), free(ready);
+            return ORACLE_E_NOMEM;
+        }
+        for (int e = 0; e < g->nedges; ++e) indeg[g->edges[e].dst]++;
+        int done = 0;
+        for (int lvl = 0;; ++lvl) {
+            int nready = 0;
+            for (int r = 0; r < N_max; ++r) {
+                ready[r] = 0;
+                if (isnan(nodes[r * NODE_W]) || emitted[r]) continue;
+                if (indeg[r] == 0) {
+                    ready[r] = 1;
+                    nready++;
+                }
+            }
+            if (nready == 0) break;
+            for (int r = 0; r < N_max; ++r) {
+                if (!ready[r]) continue;
+                emitted[r] = 1;
+                g->level[r] = lvl;
+                done++;
+            }
+            for (int e = 0; e < g->nedges; ++e)
+                if (ready[g->edges[e].src]) indeg[g->edges[e].dst]--;
+        }
+        if (done < g->nvalid) st |= ST_CYCLE;
+        free(indeg), free(emitted), free(ready);
+    }
+
+    /* 4. order: valid rows sorted by (level, key); all -1 when rejected */
+    if (st == 0) {
+        int n = 0;
+        for (int r = 0; r < N_max; ++r)
+            if (!isnan(nodes[r * NODE_W])) g->order[n++] = r;
+        for (int i = 1; i < n; ++i) { /* insertion sort, plain and stable */
+            int x = g->order[i];
+            int j = i - 1;
+            while (j >= 0) {
+                int y = g->order[j];
+                int before = g->level[x] < g->level[y] ||
+                             (g->level[x] == g->level[y] &&
+                              nodes[x * NODE_W] < nodes[y * NODE_W]);
+                if (!before) break;
+                g->order[j + 1] = y;
+                --j;
+            }
+            g->order[j + 1] = x;
+        }
+    } else {
+        for (int r = 0; r < N_max; ++r) {
+            g->order[r] = -1;
+            g->level[r] = -1;
+        }
+    }
+    g->status = st;
+    return 0;
+}
+
+static int check_dims(int P, int N_max, int C_max, int I, int O) {
+    if (P < 0 || N_max < 1 || C_max < 0 || I < 1 || O < 1) return 0;
+    if (I + O > N_max) return 0;
+    return 1;
+}
+
+/* Public: transformation of a whole population (order, level, status). */
+int oracle_transform(int P, int N_max, int C_max, int I, int O,
+                     const float *nodes, const float *conns, int32_t *order,
+                     int32_t *level, uint32_t *status) {
+    if (!check_dims(P, N_max, C_max, I, O)) return ORACLE_E_INVALID;
+    for (int p = 0; p < P; ++p) {
+        o_genome g;
+        int rc = genome_transform(nodes + (size_t)p * N_max * NODE_W,
+                                  conns + (size_t)p * C_max * CONN_W, N_max,
+                                  C_max, I, O, &g);
+        if (rc != 0) {
+            genome_free(&g);
+            return rc;
+        }
+        for (int r = 0; r < N_max; ++r) {
+            order[(size_t)p * N_max + r] = g.order[r];
+            level[(size_t)p * N_max + r] = g.level[r];
+        }
+        status[p] = g.status;
+        genome_free(&g);
+    }
+    return 0;
+}
+
+/* Incoming edges of every row, each list sorted by ascending source key. */
+typedef struct {
+    int *off;   /* [N_max + 1] */
+    int *src;   /* [nedges] */
+    float *w;   /* [nedges] */
+} o_incoming;
+
+static int build_incoming(const float *nodes, int N_max, const o_genome *g,
+                          o_incoming *in) {
+    in->off = (int *)calloc((size_t)N_max + 1, sizeof(int));
+    in->src = (int *)malloc(sizeof(int) * (size_t)(g->nedges > 0 ? g->nedges : 1));
+    in->w = (float *)malloc(sizeof(float) * (size_t)(g->nedges > 0 ? g->nedges : 1));
+    if (!in->off || !in->src || !in->w) return ORACLE_E_NOMEM;
+    int k = 0;
+    for (int d = 0; d < N_max; ++d) {
+        in->off[d] = k;
+        for (int e = 0; e < g->nedges; ++e) {
+            if (g->edges[e].dst != d) continue;
+            /* insert keeping ascending source key */
+            int j = k;
+            float key = nodes[g->edges[e].src * NODE_W];
+            while (j > in->off[d] && nodes[in->src[j - 1] * NODE_W] > key) {
+                in->src[j] = in->src[j - 1];
+                in->w[j] = in->w[j - 1];
+                --j;
+            }
+            in->src[j] = g->edges[e].src;
+            in->w[j] = g->edges[e].w;
+            ++k;
+        }
+    }
+    in->off[N_max] = k;
+    return 0;
+}
+
+static void incoming_free(o_incoming *in) {
+    free(in->off);
+    free(in->src);
+    free(in->w);
+}
+
+/* The calculation stage, instantiated for double (with the fp32 error bound
+ * beta) and for float. */
+#define REAL double
+#define SUFFIX(name) name##_f64
+#define WITH_BETA 1
+#define R_TANH tanh
+#define R_EXP exp
+#define R_SIN sin
+#define R_FABS fabs
+#include "neat_oracle_forward.inc"
+#undef REAL
+#undef SUFFIX
+#undef WITH_BETA
+#undef R_TANH
+#undef R_EXP
+#undef R_SIN
+#undef R_FABS
+
+#define REAL float
+#define SUFFIX(name) name##_f32
+#define WITH_BETA 0
+#define R_TANH tanhf
+#define R_EXP expf
+#define R_SIN sinf
+#define R_FABS fabsf
+#include "neat_oracle_forward.inc"
+#undef REAL
+#undef SUFFIX
+#undef WITH_BETA
+#undef R_TANH
+#undef R_EXP
+#undef R_SIN
+#undef R_FABS
