@@ -1,0 +1,155 @@
+/*
+ * neat.h -- C ABI of the MI355X population forward of tensorized NEAT
+ * (Wang et al., "Tensorized NeuroEvolution of Augmenting Topologies for GPU
+ * Acceleration", GECCO 2024).
+ *
+ * The library evaluates a whole population of variable-topology genomes at
+ * once.  Following Section 3.3, inference is split in two stages:
+ *
+ *   transformation  neat_topo_sort  -- once per genome: validate the padded
+ *                   encoding, topologically sort the nodes, and build a
+ *                   compact per-genome "program" (the role of the paper's
+ *                   N_order and expanded connections C_exp);
+ *   calculation     neat_forward    -- many times: run every genome's program
+ *                   over a batch of input vectors.
+ *
+ * ENCODING (Section 3.1).  A population of P genomes is two fp32 tensors,
+ * row-major and contiguous:
+ *   nodes [P][N_max][5] = (key, bias, response, act, agg)
+ *   conns [P][C_max][4] = (in key, out key, enabled, weight)
+ * A node row is present iff its key is not NaN; a connection row is present
+ * iff its in key is not NaN (NaN padding, Section 3.1).  Keys are integers in
+ * [0, 2^24).  Connection ends are node KEYS (historical markers), not rows.
+ * Input nodes have keys 0..I-1 and output nodes keys I..I+O-1 (the paper's
+ * genome interface, appendix).  Activation codes: 0 identity, 1 tanh,
+ * 2 sigmoid 1/(1+e^-z), 3 relu, 4 sin, 5 gaussian e^(-z^2), 6 abs.
+ * Aggregation codes: 0 sum, 1 product, 2 max, 3 min, 4 mean.
+ *
+ * SEMANTICS (Section 3.3).  For each genome and each input vector x:
+ * v[input key i] = x[i]; then, in topological order, every non-input node u
+ * gets v[u] = act(bias + response * agg({w * v[src] : enabled src -> u}))
+ * with agg of an empty set = 0; the outputs are v[key I+j].  The order is the
+ * level-synchronous Kahn order: level(u) = 0 without incoming enabled edges,
+ * else 1 + max level of its sources; nodes sorted by (level, key).  Incoming
+ * terms are combined in ascending source-key order.  NaN propagates through
+ * every activation and aggregation.
+ *
+ * STATUS.  Per-genome problems never fail a call: they set bits in the
+ * genome's status word and the genome's outputs become NaN.  Bits:
+ *   NEAT_ST_BAD_VALUE  1  non-integer / out-of-range key, act or agg code,
+ *                         or an enabled flag other than 0 and 1
+ *   NEAT_ST_DUP_KEY    2  two present nodes share a key
+ *   NEAT_ST_MISSING_IO 4  an input or output key is absent
+ *   NEAT_ST_BAD_REF    8  an enabled connection names an absent key
+ *   NEAT_ST_INTO_INPUT 16 an enabled connection ends at an input node
+ *   NEAT_ST_DUP_EDGE   32 two enabled connections share (in, out)
+ *   NEAT_ST_CYCLE      64 a self-loop, or a cycle found by the sort (the sort
+ *                         runs only when no other bit is set)
+ * Disabled connection rows are ignored entirely, whatever they contain.
+ *
+ * CONVENTIONS.  All tensor pointers are DEVICE pointers owned by the caller;
+ * the library never frees them.  Calls are asynchronous on the given HIP
+ * stream (hipStream_t passed as void*, NULL = the default stream) and return
+ * only argument and launch errors.  Return codes: 0 OK, > 0 pending, < 0
+ * error (NEAT_E_*); neat_last_error() gives the calling thread's last error
+ * message.  Entry points are reentrant; no exception crosses the ABI.
+ */
+#ifndef NEAT_H
+#define NEAT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define NEAT_OK 0
+#define NEAT_PENDING 1
+#define NEAT_E_INVALID (-1)
+#define NEAT_E_HIP (-2)
+#define NEAT_E_NOMEM (-3)
+#define NEAT_E_TOO_LARGE (-4)
+#define NEAT_E_UNKNOWN_TICKET (-5)
+#define NEAT_E_SHUTDOWN (-6)
+
+#define NEAT_ST_BAD_VALUE 1u
+#define NEAT_ST_DUP_KEY 2u
+#define NEAT_ST_MISSING_IO 4u
+#define NEAT_ST_BAD_REF 8u
+#define NEAT_ST_INTO_INPUT 16u
+#define NEAT_ST_DUP_EDGE 32u
+#define NEAT_ST_CYCLE 64u
+
+/* Largest supported sizes: node rows are addressed with 16 bits. */
+#define NEAT_MAX_NODES 1024
+#define NEAT_MAX_CONNS 16384
+
+/* Shape of one population.  Requires P >= 0, 1 <= N_max <= NEAT_MAX_NODES,
+ * 0 <= C_max <= NEAT_MAX_CONNS, I >= 1, O >= 1, I + O <= N_max. */
+typedef struct {
+    int32_t P, N_max, C_max, I, O;
+} neat_dims;
+
+/* Bytes of the opaque per-population program written by neat_topo_sort
+ * (P genomes; each genome's part is 256-byte aligned).  0 on invalid dims. */
+size_t neat_program_bytes(const neat_dims *dims);
+
+/*
+ * Transformation stage (Section 3.3, "transformation"; encoding of Section
+ * 3.1).  One launch over the population:
+ *   nodes   [P][N_max][5] f32, conns [P][C_max][4] f32   (read)
+ *   order   [P][N_max] i32  node ROWS in (level, key) order, -1 padded
+ *   level   [P][N_max] i32  level of each node row, -1 for absent rows
+ *   status  [P] u32         bit-mask above; rejected genomes get all -1 rows
+ *   program neat_program_bytes(dims) bytes, or NULL to skip building it
+ * order, level and status may each be NULL when not wanted.  The program is
+ * what neat_forward consumes; it stays valid as long as the caller keeps it.
+ * Errors: NEAT_E_INVALID (bad dims, NULL nodes/conns with P > 0, or a
+ * population whose per-genome working set does not fit in LDS), NEAT_E_HIP.
+ */
+int neat_topo_sort(const neat_dims *dims, const float *nodes, const float *conns,
+                   int32_t *order, int32_t *level, uint32_t *status,
+                   void *program, void *stream);
+
+/*
+ * Calculation stage (Section 3.3, "calculation"), one launch over
+ * population x inputs:
+ *   program  built by neat_topo_sort for the same dims (read)
+ *   inputs   f32; genome g's input vector b is at
+ *            inputs[g * input_genome_stride + b * I + i]
+ *            (input_genome_stride = 0: one input block shared by all genomes;
+ *            otherwise >= B * I)
+ *   B        input vectors per genome (>= 0)
+ *   outputs  [P][B][O] f32 (written); NaN for genomes with status != 0
+ * Errors: NEAT_E_INVALID, NEAT_E_HIP.
+ */
+int neat_forward(const neat_dims *dims, const void *program, const float *inputs,
+                 int64_t input_genome_stride, int32_t B, float *outputs,
+                 void *stream);
+
+/*
+ * Calculation stage for CPPN substrate queries (the paper's CPPN/HyperNEAT
+ * workloads, Section 1 and Section 4): genomes with I = 5 inputs are
+ * evaluated on all pairs of a side x side grid of substrate points whose
+ * coordinates are c[i] = (2i - (side-1)) / (side-1) rounded to fp32.  Point p
+ * is (c[p % side], c[p / side]); query q in [first, first + Q) pairs point
+ * q / side^2 (x1, y1) with point q % side^2 (x2, y2); the fifth input is 1.
+ * The inputs are generated in the kernel and never read from memory.
+ *   outputs [P][Q][O] f32.  Requires I == 5, 2 <= side <= 256,
+ *   0 <= first, first + Q <= side^4.
+ */
+int neat_forward_grid(const neat_dims *dims, const void *program, int32_t side,
+                      int64_t first, int32_t Q, float *outputs, void *stream);
+
+/* Message for the calling thread's most recent error ("" if none). */
+const char *neat_last_error(void);
+
+/* Static description of a return code. */
+const char *neat_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NEAT_H */

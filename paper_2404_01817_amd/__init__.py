@@ -1,0 +1,112 @@
+"""MI355X-native population forward of tensorized NEAT (Wang et al., GECCO
+2024): transformation (topological sort + program build) and calculation
+(forward over population x inputs) as hand-written HIP kernels for gfx950
+behind the C ABI of ``include/neat.h``.
+
+The functions here marshal torch tensors into that ABI.  torch supplies
+device memory and the current HIP stream; nothing is computed in Python.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional, Tuple
+
+from ._lib import Dims, NeatError, check, lib
+
+__all__ = ["Dims", "NeatError", "dims_of", "program_bytes", "topo_sort", "forward",
+           "forward_grid"]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t) -> Optional[ctypes.c_void_p]:
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _dev_f32(t, name):
+    torch = _torch()
+    if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+        raise ValueError("%s must be a contiguous float32 CUDA tensor" % name)
+
+
+def dims_of(nodes, conns, I: int, O: int) -> Dims:
+    if nodes.dim() != 3 or nodes.shape[2] != 5:
+        raise ValueError("nodes must be [P, N_max, 5]")
+    if conns.dim() != 3 or conns.shape[2] != 4 or conns.shape[0] != nodes.shape[0]:
+        raise ValueError("conns must be [P, C_max, 4]")
+    return Dims(nodes.shape[0], nodes.shape[1], conns.shape[1], I, O)
+
+
+def program_bytes(dims: Dims) -> int:
+    return int(lib().neat_program_bytes(ctypes.byref(dims)))
+
+
+def topo_sort(nodes, conns, I: int, O: int, program=None, stream=None,
+              want_order: bool = True):
+    """Transformation stage.  nodes [P,N_max,5], conns [P,C_max,4] float32 on
+    the GPU.  Returns (order, level, status, program) as device tensors
+    (order/level None unless ``want_order``)."""
+    torch = _torch()
+    _dev_f32(nodes, "nodes")
+    _dev_f32(conns, "conns")
+    d = dims_of(nodes, conns, I, O)
+    dev = nodes.device
+    order = level = None
+    if want_order:
+        order = torch.empty((d.P, d.N_max), dtype=torch.int32, device=dev)
+        level = torch.empty((d.P, d.N_max), dtype=torch.int32, device=dev)
+    status = torch.empty((d.P,), dtype=torch.int32, device=dev)
+    if program is None:
+        program = torch.empty((max(program_bytes(d), 4) // 4,), dtype=torch.int32, device=dev)
+    check(lib().neat_topo_sort(ctypes.byref(d), _ptr(nodes), _ptr(conns), _ptr(order),
+                               _ptr(level), _ptr(status), _ptr(program), _stream(stream)))
+    return order, level, status, program
+
+
+def forward(dims: Dims, program, inputs, B: int, shared_inputs: bool = False,
+            outputs=None, stream=None):
+    """Calculation stage.  inputs [P,B,I] (or [B,I] when shared) float32 on the
+    GPU; returns outputs [P,B,O]."""
+    torch = _torch()
+    _dev_f32(inputs, "inputs")
+    if shared_inputs:
+        stride = 0
+        if inputs.numel() < B * dims.I:
+            raise ValueError("shared inputs smaller than B * I")
+    else:
+        stride = B * dims.I
+        if inputs.numel() < dims.P * stride:
+            raise ValueError("inputs smaller than P * B * I")
+    if outputs is None:
+        outputs = torch.empty((dims.P, B, dims.O), dtype=torch.float32, device=inputs.device)
+    else:
+        _dev_f32(outputs, "outputs")
+        if outputs.numel() < dims.P * B * dims.O:
+            raise ValueError("outputs smaller than P * B * O")
+    check(lib().neat_forward(ctypes.byref(dims), _ptr(program), _ptr(inputs), stride, B,
+                             _ptr(outputs), _stream(stream)))
+    return outputs
+
+
+def forward_grid(dims: Dims, program, side: int, first: int, Q: int, outputs=None,
+                 stream=None):
+    """CPPN substrate queries generated in the kernel; returns [P,Q,O]."""
+    torch = _torch()
+    if outputs is None:
+        outputs = torch.empty((dims.P, Q, dims.O), dtype=torch.float32, device=program.device)
+    else:
+        _dev_f32(outputs, "outputs")
+        if outputs.numel() < dims.P * Q * dims.O:
+            raise ValueError("outputs smaller than P * Q * O")
+    check(lib().neat_forward_grid(ctypes.byref(dims), _ptr(program), side, first, Q,
+                                  _ptr(outputs), _stream(stream)))
+    return outputs

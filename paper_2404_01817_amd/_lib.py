@@ -1,0 +1,64 @@
+"""ctypes binding of libneat.so (the C ABI in include/neat.h).
+
+Argument marshalling only: torch tensors provide device memory and streams;
+every step of the computation runs in the library's HIP kernels.  The library
+must have been built (``python -m paper_2404_01817_amd.build``); there is no
+fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libneat.so")
+
+NEAT_OK = 0
+NEAT_PENDING = 1
+
+
+class NeatError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("neat error %d: %s" % (code, msg))
+        self.code = code
+
+
+class Dims(ctypes.Structure):
+    _fields_ = [("P", ctypes.c_int32), ("N_max", ctypes.c_int32),
+                ("C_max", ctypes.c_int32), ("I", ctypes.c_int32), ("O", ctypes.c_int32)]
+
+
+_lib = None
+
+# exported symbol -> (restype, argtypes)
+_vp, _i32, _i64, _sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+SIGNATURES = {
+    "neat_program_bytes": (_sz, [ctypes.POINTER(Dims)]),
+    "neat_topo_sort": (_i32, [ctypes.POINTER(Dims), _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "neat_forward": (_i32, [ctypes.POINTER(Dims), _vp, _vp, _i64, _i32, _vp, _vp]),
+    "neat_forward_grid": (_i32, [ctypes.POINTER(Dims), _vp, _i32, _i64, _i32, _vp, _vp]),
+    "neat_last_error": (ctypes.c_char_p, []),
+    "neat_strerror": (ctypes.c_char_p, [_i32]),
+}
+
+
+def lib():
+    """Load libneat.so (raises if it was not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                "libneat.so is not built; run `python -m paper_2404_01817_amd.build`")
+        l = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(l, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = l
+    return _lib
+
+
+def check(rc: int) -> int:
+    if rc < 0:
+        raise NeatError(rc, lib().neat_last_error().decode())
+    return rc

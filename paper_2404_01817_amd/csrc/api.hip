@@ -1,0 +1,160 @@
+// api.hip -- the C ABI declared in include/neat.h: argument checks, error
+// reporting and kernel launches for the transformation and calculation
+// stages.
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+
+#include "launch.h"
+#include "neat.h"
+#include "program.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+    return fail(NEAT_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+// Largest dynamic LDS allocation of one workgroup on the current device.
+size_t max_lds_bytes() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 65536;
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess ||
+        v <= 0)
+        return 65536;
+    return (size_t)v;
+}
+
+int check_dims(const neat_dims *d) {
+    if (!d) return fail(NEAT_E_INVALID, "dims is NULL");
+    if (d->P < 0) return fail(NEAT_E_INVALID, "P = %d < 0", d->P);
+    if (d->N_max < 1 || d->N_max > NEAT_MAX_NODES)
+        return fail(NEAT_E_INVALID, "N_max = %d outside [1, %d]", d->N_max, NEAT_MAX_NODES);
+    if (d->C_max < 0 || d->C_max > NEAT_MAX_CONNS)
+        return fail(NEAT_E_INVALID, "C_max = %d outside [0, %d]", d->C_max, NEAT_MAX_CONNS);
+    if (d->I < 1 || d->O < 1 || d->I + d->O > d->N_max)
+        return fail(NEAT_E_INVALID, "need I >= 1, O >= 1, I + O <= N_max (I=%d O=%d N_max=%d)",
+                    d->I, d->O, d->N_max);
+    return NEAT_OK;
+}
+
+bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+}  // namespace
+
+extern "C" {
+
+const char *neat_last_error(void) { return g_last_error.c_str(); }
+
+const char *neat_strerror(int code) {
+    switch (code) {
+    case NEAT_OK: return "ok";
+    case NEAT_PENDING: return "pending";
+    case NEAT_E_INVALID: return "invalid argument";
+    case NEAT_E_HIP: return "HIP runtime error";
+    case NEAT_E_NOMEM: return "out of device memory";
+    case NEAT_E_TOO_LARGE: return "request larger than the admission cap";
+    case NEAT_E_UNKNOWN_TICKET: return "unknown ticket";
+    case NEAT_E_SHUTDOWN: return "server shut down";
+    }
+    return "unknown code";
+}
+
+size_t neat_program_bytes(const neat_dims *d) {
+    if (check_dims(d) != NEAT_OK) return 0;
+    return (size_t)d->P * (size_t)neat::prog_words(d->N_max, d->C_max, d->O) * sizeof(int32_t);
+}
+
+int neat_topo_sort(const neat_dims *d, const float *nodes, const float *conns, int32_t *order,
+                   int32_t *level, uint32_t *status, void *program, void *stream) {
+    int rc = check_dims(d);
+    if (rc != NEAT_OK) return rc;
+    if (d->P == 0) return NEAT_OK;
+    if (!nodes || (!conns && d->C_max > 0))
+        return fail(NEAT_E_INVALID, "nodes or conns is NULL");
+    if (!aligned(conns, 16)) return fail(NEAT_E_INVALID, "conns must be 16-byte aligned");
+    if (program && !aligned(program, 16))
+        return fail(NEAT_E_INVALID, "program must be 16-byte aligned");
+    const size_t lds = neat::topo_lds_bytes(d->N_max, d->C_max);
+    if (lds > max_lds_bytes())
+        return fail(NEAT_E_INVALID,
+                    "N_max=%d, C_max=%d needs %zu B of LDS per genome, device allows %zu",
+                    d->N_max, d->C_max, lds, max_lds_bytes());
+    hipError_t e = neat::launch_topo(d->P, d->N_max, d->C_max, d->I, d->O, nodes, conns, order,
+                                     level, status, (int32_t *)program, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "topo_sort launch");
+    return NEAT_OK;
+}
+
+int neat_forward(const neat_dims *d, const void *program, const float *inputs,
+                 int64_t input_genome_stride, int32_t B, float *outputs, void *stream) {
+    int rc = check_dims(d);
+    if (rc != NEAT_OK) return rc;
+    if (B < 0) return fail(NEAT_E_INVALID, "B = %d < 0", B);
+    if (d->P == 0 || B == 0) return NEAT_OK;
+    if (!program || !inputs || !outputs)
+        return fail(NEAT_E_INVALID, "program, inputs or outputs is NULL");
+    if (!aligned(program, 16)) return fail(NEAT_E_INVALID, "program must be 16-byte aligned");
+    if (input_genome_stride != 0 && input_genome_stride < (int64_t)B * d->I)
+        return fail(NEAT_E_INVALID, "input_genome_stride %lld < B * I = %lld",
+                    (long long)input_genome_stride, (long long)B * d->I);
+    if (input_genome_stride < 0) return fail(NEAT_E_INVALID, "negative input_genome_stride");
+    const long long blocks = (long long)d->P * ((B + 63) / 64);
+    if (blocks * 64 >= (1ll << 32))
+        return fail(NEAT_E_INVALID, "P * B too large for one launch (%lld workgroups)", blocks);
+    const size_t lds = neat::forward_lds_bytes(d->N_max);
+    if (lds > max_lds_bytes())
+        return fail(NEAT_E_INVALID, "N_max=%d needs %zu B of LDS per wave, device allows %zu",
+                    d->N_max, lds, max_lds_bytes());
+    hipError_t e = neat::launch_forward(d->P, d->N_max, d->C_max, d->I, d->O,
+                                        (const int32_t *)program, inputs, input_genome_stride, B,
+                                        outputs, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "forward launch");
+    return NEAT_OK;
+}
+
+int neat_forward_grid(const neat_dims *d, const void *program, int32_t side, int64_t first,
+                      int32_t Q, float *outputs, void *stream) {
+    int rc = check_dims(d);
+    if (rc != NEAT_OK) return rc;
+    if (d->I != 5) return fail(NEAT_E_INVALID, "grid queries need I = 5, got %d", d->I);
+    if (side < 2 || side > 256) return fail(NEAT_E_INVALID, "side = %d outside [2, 256]", side);
+    const long long nq = (long long)side * side * side * side;
+    if (Q < 0 || first < 0 || first + Q > nq)
+        return fail(NEAT_E_INVALID, "queries [%lld, %lld) outside [0, %lld)", (long long)first,
+                    (long long)first + Q, nq);
+    if (d->P == 0 || Q == 0) return NEAT_OK;
+    if (!program || !outputs) return fail(NEAT_E_INVALID, "program or outputs is NULL");
+    if (!aligned(program, 16)) return fail(NEAT_E_INVALID, "program must be 16-byte aligned");
+    const long long blocks = (long long)d->P * ((Q + 63) / 64);
+    if (blocks * 64 >= (1ll << 32))
+        return fail(NEAT_E_INVALID, "P * Q too large for one launch (%lld workgroups)", blocks);
+    const size_t lds = neat::forward_lds_bytes(d->N_max);
+    if (lds > max_lds_bytes())
+        return fail(NEAT_E_INVALID, "N_max=%d needs %zu B of LDS per wave, device allows %zu",
+                    d->N_max, lds, max_lds_bytes());
+    hipError_t e = neat::launch_forward_grid(d->P, d->N_max, d->C_max, d->I, d->O,
+                                             (const int32_t *)program, side, first, Q, outputs,
+                                             (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "forward_grid launch");
+    return NEAT_OK;
+}
+
+}  // extern "C"

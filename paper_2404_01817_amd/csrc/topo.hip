@@ -1,0 +1,378 @@
+// topo.hip -- the transformation stage (Section 3.3) for a whole population.
+//
+// One workgroup per genome; thread t owns node row t (the block has
+// round_up(N_max, 64) threads).  Everything of one genome lives in LDS:
+//
+//   1. node rows: presence (key not NaN), key / act / agg validity;
+//   2. key -> row map: a stable rank of every well-formed key (counting the
+//      smaller keys), which gives the keys in sorted order for binary search
+//      and detects duplicate keys; presence of the input/output keys;
+//   3. connection rows, read as one float4 each: padding and disabled rows
+//      are dropped, enabled rows are resolved through the key map into
+//      (source row, destination row) and counted into in/out degrees;
+//   4. exclusive scans of the degrees (wave shuffles + a cross-wave pass) and
+//      a scatter into in- and out-adjacency lists; duplicate edges are found
+//      inside each destination's in-list;
+//   5. level-synchronous Kahn: every round, the nodes with in-degree 0 form
+//      the frontier; lanes are assigned to nodes in key-rank order, so a
+//      ballot + mbcnt prefix count gives each frontier node its position in
+//      (level, key) order; emitted nodes decrement their successors' in-degree
+//      with LDS atomics; nodes never emitted mean a cycle;
+//   6. the program (program.h): records in topological order, in-edges sorted
+//      by source key, source positions, level starts.
+#include <hip/hip_runtime.h>
+
+#include "launch.h"
+#include "neat.h"
+#include "program.h"
+
+namespace neat {
+namespace {
+
+constexpr float KEY_LIMIT = 16777216.0f;  // 2^24
+
+__device__ __forceinline__ bool is_int_in(float x, float lo, float hi_excl) {
+    // NaN fails every comparison
+    return x >= lo && x < hi_excl && x == floorf(x);
+}
+
+// Row of the well-formed key equal to k (first row among duplicates), or -1.
+__device__ __forceinline__ int find_row(float k, const int *skey, const int *srow, int n) {
+    if (!is_int_in(k, 0.0f, KEY_LIMIT)) return -1;
+    const int key = (int)k;
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (skey[mid] < key) lo = mid + 1;
+        else hi = mid;
+    }
+    return (lo < n && skey[lo] == key) ? srow[lo] : -1;
+}
+
+__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63u); }
+__device__ __forceinline__ int wave_id() { return (int)(threadIdx.x >> 6); }
+
+// number of set bits of m below this lane
+__device__ __forceinline__ int mbcnt(unsigned long long m) {
+    return (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
+                                          __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
+}
+
+// Block-wide exclusive scan of one value per thread; *total receives the sum.
+// Contains two barriers; every thread of the block must call it.
+__device__ int block_excl_scan(int v, int *s_wave, int *total) {
+    const int lane = lane_id(), wave = wave_id(), nw = (int)(blockDim.x >> 6);
+    int x = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int y = __shfl_up(x, d, 64);
+        if (lane >= d) x += y;
+    }
+    if (lane == 63) s_wave[wave] = x;
+    __syncthreads();
+    int base = 0, tot = 0;
+    for (int w = 0; w < nw; ++w) {
+        const int c = s_wave[w];
+        base += (w < wave) ? c : 0;
+        tot += c;
+    }
+    __syncthreads();
+    *total = tot;
+    return base + x - v;
+}
+
+struct TopoArgs {
+    const float *nodes;
+    const float *conns;
+    int32_t *order;
+    int32_t *level;
+    uint32_t *status;
+    int32_t *prog;
+    int N, C, I, O, prog_words;
+};
+
+__global__ __launch_bounds__(1024) void topo_kernel(TopoArgs a) {
+    extern __shared__ int smem[];
+    __shared__ unsigned s_status;
+    __shared__ int s_nvalid, s_ngood;
+    __shared__ int s_wave[16];
+
+    const int N = a.N, C = a.C, I = a.I, O = a.O;
+    const int t = (int)threadIdx.x, W = (int)blockDim.x;
+    const size_t g = blockIdx.x;
+
+    int *s_key = smem;            // [N] key of row, -1 absent, -2 malformed
+    int *s_skey = s_key + N;      // [N] well-formed keys by stable rank; later level of row
+    int *s_srow = s_skey + N;     // [N] row by rank
+    int *s_indeg = s_srow + N;    // [N] in-degree, consumed by Kahn
+    int *s_deg = s_indeg + N;     // [N] in-degree kept for the program
+    int *s_inoff = s_deg + N;     // [N+1]
+    int *s_outoff = s_inoff + N + 1;  // [N+1]
+    int *s_curo = s_outoff + N + 1;   // [N] out-degree, out cursor, later edge begin by row
+    int *s_curi = s_curo + N;     // [N] io presence, in cursor, later row by position
+    int *s_pos = s_curi + N;      // [N] position of row
+    int *e_src = s_pos + N;       // [C] source row of connection row, -1 if unused
+    int *e_dst = e_src + C;       // [C]
+    int *in_list = e_dst + C;     // [C] connection rows grouped by destination
+    int *out_list = in_list + C;  // [C] destination rows grouped by source
+
+    const float *nodes = a.nodes + g * (size_t)N * 5;
+    const float *conns = a.conns + g * (size_t)C * 4;
+
+    if (t == 0) {
+        s_status = 0u;
+        s_nvalid = 0;
+        s_ngood = 0;
+    }
+    for (int i = t; i < N; i += W) {
+        s_indeg[i] = 0;
+        s_curo[i] = 0;
+        s_curi[i] = 0;
+        s_pos[i] = -1;
+    }
+    __syncthreads();
+
+    // ---- 1. node rows
+    unsigned st = 0u;
+    int key = -1, act = 0, agg = 0;
+    float bias = 0.0f, resp = 0.0f;
+    if (t < N) {
+        const float *n = nodes + (size_t)t * 5;
+        const float kf = n[0];
+        bias = n[1];
+        resp = n[2];
+        const float af = n[3], gf = n[4];
+        if (!isnan(kf)) {
+            atomicAdd(&s_nvalid, 1);
+            const bool key_ok = is_int_in(kf, 0.0f, KEY_LIMIT);
+            if (!key_ok) st |= NEAT_ST_BAD_VALUE;
+            if (!is_int_in(af, 0.0f, (float)N_ACT) || !is_int_in(gf, 0.0f, (float)N_AGG))
+                st |= NEAT_ST_BAD_VALUE;
+            else {
+                act = (int)af;
+                agg = (int)gf;
+            }
+            key = key_ok ? (int)kf : -2;
+        }
+        s_key[t] = key;
+    }
+    __syncthreads();
+
+    // ---- 2. stable key rank, duplicate keys, input/output presence
+    if (key >= 0) {
+        int less = 0, eq_before = 0, eq = 0;
+        for (int q = 0; q < N; ++q) {
+            const int kq = s_key[q];
+            if (kq < 0) continue;
+            less += (kq < key);
+            if (kq == key && q != t) {
+                ++eq;
+                eq_before += (q < t);
+            }
+        }
+        const int rank = less + eq_before;
+        if (eq) st |= NEAT_ST_DUP_KEY;
+        s_skey[rank] = key;
+        s_srow[rank] = t;
+        if (key < I + O) s_curi[key] = 1;
+        atomicAdd(&s_ngood, 1);
+    }
+    __syncthreads();
+    if (t < I + O && s_curi[t] == 0) st |= NEAT_ST_MISSING_IO;
+    const int ngood = s_ngood;
+
+    // ---- 3. connection rows
+    for (int c = t; c < C; c += W) {
+        const float4 row = reinterpret_cast<const float4 *>(conns)[c];
+        int src = -1, dst = -1;
+        if (!isnan(row.x) && row.z != 0.0f) {
+            if (row.z != 1.0f) {
+                st |= NEAT_ST_BAD_VALUE;
+            } else {
+                const int s = find_row(row.x, s_skey, s_srow, ngood);
+                const int d = find_row(row.y, s_skey, s_srow, ngood);
+                if (s < 0 || d < 0) {
+                    st |= NEAT_ST_BAD_REF;
+                } else {
+                    if (s_key[d] < I) st |= NEAT_ST_INTO_INPUT;
+                    if (s == d) st |= NEAT_ST_CYCLE;
+                    src = s;
+                    dst = d;
+                    atomicAdd(&s_indeg[d], 1);
+                    atomicAdd(&s_curo[s], 1);
+                }
+            }
+        }
+        e_src[c] = src;
+        e_dst[c] = dst;
+    }
+    __syncthreads();
+
+    // ---- 4. adjacency lists (counting sort by destination and by source)
+    {
+        const int din = (t < N) ? s_indeg[t] : 0;
+        const int dout = (t < N) ? s_curo[t] : 0;
+        int tin, tout;
+        const int ein = block_excl_scan(din, s_wave, &tin);
+        const int eout = block_excl_scan(dout, s_wave, &tout);
+        if (t < N) {
+            s_inoff[t] = ein;
+            s_outoff[t] = eout;
+            s_deg[t] = din;
+            s_curo[t] = 0;
+            s_curi[t] = 0;
+        }
+        if (t == 0) {
+            s_inoff[N] = tin;
+            s_outoff[N] = tout;
+        }
+    }
+    __syncthreads();
+    for (int c = t; c < C; c += W) {
+        const int s = e_src[c];
+        if (s < 0) continue;
+        const int d = e_dst[c];
+        in_list[s_inoff[d] + atomicAdd(&s_curi[d], 1)] = c;
+        out_list[s_outoff[s] + atomicAdd(&s_curo[s], 1)] = d;
+    }
+    __syncthreads();
+    for (int c = t; c < C; c += W) {
+        const int s = e_src[c];
+        if (s < 0) continue;
+        const int d = e_dst[c];
+        for (int k = s_inoff[d]; k < s_inoff[d + 1]; ++k) {
+            const int c2 = in_list[k];
+            if (c2 != c && e_src[c2] == s) st |= NEAT_ST_DUP_EDGE;
+        }
+    }
+    if (st) atomicOr(&s_status, st);
+    __syncthreads();
+    unsigned status = s_status;
+    const int nvalid = s_nvalid;
+
+    // ---- 5. level-synchronous Kahn over key ranks
+    int n_levels = 0;
+    int my_level = -1;
+    const int my_row = (status == 0u && t < nvalid) ? s_srow[t] : -1;
+    if (status == 0u) {
+        const int lane = lane_id(), wave = wave_id(), nw = W >> 6;
+        bool emitted = false;
+        int base = 0;
+        for (;;) {
+            const bool ready = my_row >= 0 && !emitted && s_indeg[my_row] == 0;
+            const unsigned long long m = __ballot(ready);
+            if (lane == 0) s_wave[wave] = __popcll(m);
+            __syncthreads();
+            int wbase = 0, total = 0;
+            for (int w = 0; w < nw; ++w) {
+                const int c = s_wave[w];
+                wbase += (w < wave) ? c : 0;
+                total += c;
+            }
+            if (total == 0) break;  // uniform across the block
+            if (ready) {
+                s_pos[my_row] = base + wbase + mbcnt(m);
+                my_level = n_levels;
+                emitted = true;
+                for (int k = s_outoff[my_row]; k < s_outoff[my_row + 1]; ++k)
+                    atomicSub(&s_indeg[out_list[k]], 1);
+            }
+            __syncthreads();
+            base += total;
+            ++n_levels;
+        }
+        if (base < nvalid) status |= NEAT_ST_CYCLE;
+    }
+    __syncthreads();  // s_pos complete; s_skey is free and now holds levels
+    if (my_row >= 0) s_skey[my_row] = my_level;
+    if (status == 0u && t < N && s_key[t] != -1) s_curi[s_pos[t]] = t;  // row by position
+    __syncthreads();
+
+    // ---- outputs: order, level, status
+    const bool ok = status == 0u;
+    if (a.order) {
+        if (t < N && (!ok || t >= nvalid)) a.order[g * N + t] = -1;
+        if (ok && t < N && s_key[t] != -1) a.order[g * N + s_pos[t]] = t;
+    }
+    if (a.level && t < N) a.level[g * N + t] = (ok && s_key[t] != -1) ? s_skey[t] : -1;
+    if (a.status && t == 0) a.status[g] = status;
+    if (!a.prog) return;
+
+    // ---- 6. program
+    int32_t *prog = a.prog + g * (size_t)a.prog_words;
+    float *progf = reinterpret_cast<float *>(prog);
+    if (t == 0) {
+        prog[HDR_NVALID] = ok ? nvalid : 0;
+        prog[HDR_NEDGES] = ok ? s_inoff[N] : 0;
+        prog[HDR_STATUS] = (int32_t)status;
+        prog[HDR_NLEVELS] = ok ? n_levels : 0;
+        prog[HDR_I] = I;
+        prog[HDR_O] = O;
+    }
+    if (!ok) return;  // uniform
+    // output positions: rank I + j holds key I + j
+    if (t < O) prog[out_off() + t] = s_pos[s_srow[I + t]];
+    // first edge of every position, in topological order
+    {
+        const int row = (t < nvalid) ? s_curi[t] : -1;
+        const int deg = (t >= I && t < nvalid) ? s_deg[row] : 0;
+        int tot;
+        const int eb = block_excl_scan(deg, s_wave, &tot);
+        if (t >= I && t < nvalid) {
+            prog[ebeg_off(N, C, O) + (t - I)] = eb;
+            s_curo[row] = eb;  // edge begin by row; the record comes from the row's owner
+        }
+        // level starts: position t opens a level when its level differs from t-1
+        if (t < nvalid) {
+            const int lv = s_skey[row];
+            if (t == 0 || s_skey[s_curi[t - 1]] != lv) prog[lvl_off(N, C, O) + lv] = t;
+        }
+        if (t == 0) prog[lvl_off(N, C, O) + n_levels] = nvalid;
+    }
+    __syncthreads();
+    if (t < N && s_key[t] >= 0) {
+        const int p = s_pos[t];
+        if (p >= I) {
+            const int k = p - I;
+            const int deg = s_deg[t];
+            int32_t *rec = prog + rec_off(O) + REC_WORDS * k;
+            rec[0] = (int32_t)pack_rec(deg, act, agg);
+            progf[rec_off(O) + REC_WORDS * k + 1] = bias;
+            progf[rec_off(O) + REC_WORDS * k + 2] = resp;
+            progf[rec_off(O) + REC_WORDS * k + 3] = deg ? 1.0f / (float)deg : 0.0f;
+        }
+    }
+    // edges: slot = first edge of the destination + number of in-edges with
+    // a smaller source key (keys are unique here, duplicates were rejected)
+    for (int c = t; c < C; c += W) {
+        const int s = e_src[c];
+        if (s < 0) continue;
+        const int d = e_dst[c];
+        const int ks = s_key[s];
+        int j = 0;
+        for (int k = s_inoff[d]; k < s_inoff[d + 1]; ++k) j += (s_key[e_src[in_list[k]]] < ks);
+        const int e = s_curo[d] + j;
+        prog[edge_off(N, O) + EDGE_WORDS * e] = s_pos[s];
+        progf[edge_off(N, O) + EDGE_WORDS * e + 1] = conns[(size_t)c * 4 + 3];
+    }
+}
+
+}  // namespace
+
+size_t topo_lds_bytes(int N, int C) { return sizeof(int) * ((size_t)10 * N + 2 + (size_t)4 * C); }
+
+int topo_block_threads(int N) {
+    int w = round_up(N, 64);
+    return w < 64 ? 64 : w;
+}
+
+hipError_t launch_topo(int P, int N, int C, int I, int O, const float *nodes,
+                       const float *conns, int32_t *order, int32_t *level,
+                       uint32_t *status, int32_t *prog, hipStream_t stream) {
+    TopoArgs a{nodes, conns, order, level, status, prog, N, C, I, O, prog_words(N, C, O)};
+    hipLaunchKernelGGL(topo_kernel, dim3((unsigned)P), dim3((unsigned)topo_block_threads(N)),
+                       topo_lds_bytes(N, C), stream, a);
+    return hipGetLastError();
+}
+
+}  // namespace neat
