@@ -119,13 +119,19 @@ int neat_forward(const neat_dims *d, const void *program, const float *inputs,
     const long long blocks = (long long)d->P * ((B + 63) / 64);
     if (blocks * 64 >= (1ll << 32))
         return fail(NEAT_E_INVALID, "P * B too large for one launch (%lld workgroups)", blocks);
-    const size_t lds = neat::forward_lds_bytes(d->N_max);
-    if (lds > max_lds_bytes())
-        return fail(NEAT_E_INVALID, "N_max=%d needs %zu B of LDS per wave, device allows %zu",
-                    d->N_max, lds, max_lds_bytes());
-    hipError_t e = neat::launch_forward(d->P, d->N_max, d->C_max, d->I, d->O,
-                                        (const int32_t *)program, inputs, input_genome_stride, B,
-                                        outputs, (hipStream_t)stream);
+    hipError_t e;
+    if (d->N_max <= neat::REG_MAX_NODES) {
+        e = neat::launch_forward_reg(d->P, d->N_max, d->C_max, d->I, d->O,
+                                     (const int32_t *)program, inputs, input_genome_stride, B,
+                                     outputs, (hipStream_t)stream);
+    } else {
+        const size_t lds = neat::forward_lds_bytes(d->N_max);
+        if (lds > max_lds_bytes())
+            return fail(NEAT_E_INVALID, "N_max=%d needs %zu B of LDS per wave, device allows %zu",
+                        d->N_max, lds, max_lds_bytes());
+        e = neat::launch_forward(d->P, d->N_max, d->C_max, d->I, d->O, (const int32_t *)program,
+                                 inputs, input_genome_stride, B, outputs, (hipStream_t)stream);
+    }
     if (e != hipSuccess) return hip_fail(e, "forward launch");
     return NEAT_OK;
 }
@@ -146,13 +152,20 @@ int neat_forward_grid(const neat_dims *d, const void *program, int32_t side, int
     const long long blocks = (long long)d->P * ((Q + 63) / 64);
     if (blocks * 64 >= (1ll << 32))
         return fail(NEAT_E_INVALID, "P * Q too large for one launch (%lld workgroups)", blocks);
-    const size_t lds = neat::forward_lds_bytes(d->N_max);
-    if (lds > max_lds_bytes())
-        return fail(NEAT_E_INVALID, "N_max=%d needs %zu B of LDS per wave, device allows %zu",
-                    d->N_max, lds, max_lds_bytes());
-    hipError_t e = neat::launch_forward_grid(d->P, d->N_max, d->C_max, d->I, d->O,
-                                             (const int32_t *)program, side, first, Q, outputs,
-                                             (hipStream_t)stream);
+    hipError_t e;
+    if (d->N_max <= neat::REG_MAX_NODES) {
+        e = neat::launch_forward_reg_grid(d->P, d->N_max, d->C_max, d->I, d->O,
+                                          (const int32_t *)program, side, first, Q, outputs,
+                                          (hipStream_t)stream);
+    } else {
+        const size_t lds = neat::forward_lds_bytes(d->N_max);
+        if (lds > max_lds_bytes())
+            return fail(NEAT_E_INVALID, "N_max=%d needs %zu B of LDS per wave, device allows %zu",
+                        d->N_max, lds, max_lds_bytes());
+        e = neat::launch_forward_grid(d->P, d->N_max, d->C_max, d->I, d->O,
+                                      (const int32_t *)program, side, first, Q, outputs,
+                                      (hipStream_t)stream);
+    }
     if (e != hipSuccess) return hip_fail(e, "forward_grid launch");
     return NEAT_OK;
 }

@@ -17,6 +17,7 @@
 #include "launch.h"
 #include "neat.h"
 #include "program.h"
+#include "act.h"
 
 namespace neat {
 namespace {
@@ -34,19 +35,6 @@ typedef const __attribute__((address_space(4))) i32x2 cint2_t;
 
 __device__ __forceinline__ cprog_t *as_const(const int32_t *p) {
     return (cprog_t *)(p);
-}
-
-__device__ __forceinline__ float act_eval(int act, float z) {
-    switch (act) {
-    case ACT_IDENTITY: return z;
-    case ACT_TANH: return tanhf(z);
-    case ACT_SIGMOID: return 1.0f / (1.0f + expf(-z));
-    case ACT_RELU: return (z > 0.0f || z != z) ? z : 0.0f;
-    case ACT_SIN: return sinf(z);
-    case ACT_GAUSS: return expf(-(z * z));
-    case ACT_ABS: return fabsf(z);
-    }
-    return __builtin_nanf("");
 }
 
 // Run the program of one genome for the lane's sample; v points at the
@@ -166,7 +154,7 @@ __device__ __forceinline__ void stage_inputs(const float *__restrict__ in, float
     }
 }
 
-__global__ __launch_bounds__(TILE) void forward_lane_kernel(FwdArgs a) {
+__global__ __launch_bounds__(TILE) void forward_lds_kernel(FwdArgs a) {
     extern __shared__ float sv[];
     const int t = (int)threadIdx.x;
     const int g = (int)(blockIdx.x / (unsigned)a.tiles);
@@ -237,7 +225,7 @@ hipError_t launch_forward(int P, int N, int C, int I, int O, const int32_t *prog
     a.tiles = (B + TILE - 1) / TILE;
     a.prog_words = prog_words(N, C, O);
     const unsigned blocks = (unsigned)((long long)P * a.tiles);
-    hipLaunchKernelGGL(forward_lane_kernel, dim3(blocks), dim3(TILE), forward_lds_bytes(N),
+    hipLaunchKernelGGL(forward_lds_kernel, dim3(blocks), dim3(TILE), forward_lds_bytes(N),
                        stream, a);
     return hipGetLastError();
 }

@@ -32,4 +32,16 @@ hipError_t launch_forward_grid(int P, int N, int C, int I, int O, const int32_t 
                                int side, int64_t first, int Q, float *outputs,
                                hipStream_t stream);
 
+// Register-resident forward (N_max <= 64): LDS bytes per wave, launchers.
+size_t forward_reg_lds_bytes(int I);
+hipError_t launch_forward_reg(int P, int N, int C, int I, int O, const int32_t *prog,
+                              const float *inputs, int64_t gstride, int B, float *outputs,
+                              hipStream_t stream);
+hipError_t launch_forward_reg_grid(int P, int N, int C, int I, int O, const int32_t *prog,
+                                   int side, int64_t first, int Q, float *outputs,
+                                   hipStream_t stream);
+
+// Largest N_max the register-resident forward handles.
+constexpr int REG_MAX_NODES = 64;
+
 }  // namespace neat

@@ -46,8 +46,11 @@ __host__ __device__ constexpr int ebeg_off(int N, int C, int O) {
 }
 // first position of level l, l = 0..n_levels (N + 1 words)
 __host__ __device__ constexpr int lvl_off(int N, int C, int O) { return ebeg_off(N, C, O) + N; }
+// 16 words of slack after the last array: the forward kernels read edge
+// records 8 at a time (16 words) and may run past the last edge.
+constexpr int PROG_SLACK = 16;
 __host__ __device__ constexpr int prog_words(int N, int C, int O) {
-    return round_up(lvl_off(N, C, O) + N + 1, 64);
+    return round_up(lvl_off(N, C, O) + N + 1 + PROG_SLACK, 64);
 }
 
 __host__ __device__ inline uint32_t pack_rec(int deg, int act, int agg) {

@@ -168,7 +168,7 @@ def test_storage_invariants_bit_identical():
     junk[:, :, 2] = 0.0
     free = np.isnan(c2[:, :, 0])
     for p in range(50):
-        rows = np.nonzero(free[p])[0]
+        rows = np.nonzero(free[p])[0][:56]
         c2[p, rows] = junk[p, :len(rows)]
     o2, l2, s2, y2 = _gpu(n2, c2, I, O, x)
     assert (s0 == 0).all() and (s2 == 0).all()
@@ -226,3 +226,70 @@ def test_all_genomes_rejected():
     order, level, status, y = _gpu(n, pop.conns, pop.I, pop.O, pop.inputs)
     assert (status == 1).all() and (order == -1).all() and (level == -1).all()
     assert np.isnan(y).all()
+
+
+@pytest.mark.parametrize("N,I,O", [(32, 5, 2), (33, 5, 2), (64, 40, 3), (64, 10, 4),
+                                   (65, 10, 4), (48, 31, 1), (64, 33, 2), (8, 3, 1)])
+def test_forward_kernel_shapes(N, I, O):
+    """Both halves of the register-resident value vector (positions < 32 and
+    >= 32, inputs in either half), and the switch to the LDS kernel above 64
+    nodes."""
+    rng = np.random.default_rng(N * 100 + I)
+    P, B, C = 40, 150, 4 * N
+    nodes = np.full((P, N, 5), np.nan, np.float32)
+    conns = np.full((P, C, 4), np.nan, np.float32)
+    for p in range(P):
+        h = int(rng.integers(0, N - I - O + 1))
+        synth.make_genome(rng, N, C, I, O, h, lambda na: int(rng.integers(1, min(C, na) + 1)),
+                          synth.CONTROL_ACTS, synth.ALL_AGGS, nodes_out=nodes[p],
+                          conns_out=conns[p])
+    x = rng.standard_normal((P, B, I)).astype(np.float32)
+    order, level, status, y = _gpu(nodes, conns, I, O, x)
+    _assert_transform_exact(nodes, conns, I, O, order, level, status)
+    y64, beta = oracle.forward(nodes, conns, x, I, O)
+    _assert_outputs(y, y64, beta, "shape N=%d I=%d O=%d" % (N, I, O))
+
+
+def test_wide_fan_in_every_aggregation():
+    """Nodes with more incoming edges than the eight the forward keeps in
+    registers (24 and 40 terms), for every aggregation."""
+    for I in (24, 40):
+        O = 5
+        nodes = {i: (i, 0, 1, 0, 0) for i in range(I)}
+        for j in range(O):
+            nodes[I + j] = (I + j, 0.1 * j, 1.0, synth.ACT_TANH if j % 2 else 0, j)
+        rng = np.random.default_rng(I)
+        conns, r = {}, 0
+        for j in range(O):
+            for i in rng.permutation(I):
+                conns[r] = (int(i), I + j, 1, float(rng.standard_normal() * 0.7))
+                r += 1
+        n, c = genome(I + O, r, nodes, conns)
+        x = rng.uniform(0.5, 1.5, (1, 200, I)).astype(np.float32)
+        order, level, status, y = _gpu(n, c, I, O, x)
+        _assert_transform_exact(n, c, I, O, order, level, status)
+        y64, beta = oracle.forward(n, c, x, I, O)
+        _assert_outputs(y, y64, beta, "fan-in %d" % I)
+
+
+def test_device_activations_accuracy():
+    """Each activation on its own (one input -> one output, weight 1, bias 0)
+    over a dense sweep: absolute error against the double-precision value
+    stays within a few fp32 units in the last place (plus the rounding of
+    the argument, which the bound beta carries)."""
+    z = np.concatenate([np.linspace(-30, 30, 60001), np.linspace(-1e-3, 1e-3, 2001),
+                        [0.0, -0.0, 1e-30, -1e-30, 88.0, -88.0, 100.0, -100.0, 1e4, -1e4,
+                         np.inf, -np.inf, np.nan]]).astype(np.float32)
+    gens = []
+    for act in range(7):
+        gens.append(genome(2, 1, {0: (0, 0, 1, 0, 0), 1: (1, 0, 1, act, 0)},
+                           {0: (0, 1, 1, 1.0)}))
+    n, c = stack(gens)
+    order, level, status, y = _gpu(n, c, 1, 1, z[:, None], shared=True)
+    y64, beta = oracle.forward(n, c, z[:, None], 1, 1, shared_inputs=True)
+    for act in range(7):
+        fin = np.isfinite(y64[act, :, 0])
+        err = np.abs(y[act, fin, 0].astype(np.float64) - y64[act, fin, 0])
+        print("act", act, "max abs err", err.max())
+        assert np.all(err <= beta[act, fin, 0]), act
+        assert np.array_equal(np.isnan(y[act, :, 0]), np.isnan(y64[act, :, 0])), act
