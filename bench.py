@@ -45,11 +45,12 @@ def log(args, *a):
         print(*a, file=sys.stderr, flush=True)
 
 
-def program_bytes_read(prog_words, O, n_valid, n_edges, I):
-    """Bytes of the program a forward must read once per genome: header,
-    output positions, one 16-byte record per computed node, 8 bytes per edge."""
+def program_bytes_read(O, n_valid, n_edges, I):
+    """Bytes of the program a forward must read once per genome: the 64-byte
+    header, the output slots, one 32-byte record per computed node and
+    8 bytes per enabled connection."""
     n_comp = np.maximum(n_valid - I, 0)
-    return int(((16 + O) * 4 + 16 * n_comp + 8 * n_edges).sum())
+    return int((64 + 4 * O + 32 * n_comp + 8 * n_edges).sum())
 
 
 def main():
@@ -114,19 +115,34 @@ def main():
 
     # algorithmic bytes of the forward launch
     pw = neat.program_bytes(d) // 4 // pop.P
-    hdr = prog.view(pop.P, pw)[:, :4].cpu().numpy()
+    hdr = prog.view(pop.P, pw)[:, :8].cpu().numpy()
     st = status.cpu().numpy()
     n_bad = int((st != 0).sum())
-    pbytes = program_bytes_read(pw, pop.O, hdr[:, 0], hdr[:, 1], pop.I)
+    pbytes = program_bytes_read(pop.O, hdr[:, 0], hdr[:, 7], pop.I)  # valid nodes, edges
     fwd_bytes = pop.P * pop.B * (pop.I + pop.O) * 4 + pbytes
     fwd_avg_s = float(fwd_ms.mean()) / 1e3
     achieved = fwd_bytes / fwd_avg_s / 1e9
-    roofline = {"kernel": "forward_lane_kernel", "bound": "hbm",
+    roofline = {"kernel": "forward (lane per sample)", "bound": "hbm",
                 "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                 "algorithmic_bytes_per_launch": fwd_bytes,
                 "bytes_per_genome_input": round(fwd_bytes / units, 2),
                 "avg_launch_us": round(fwd_avg_s * 1e6, 1)}
+
+    # each forward variant on the same program, for the record
+    variants = {}
+    for name, var in (("reg", neat.FWD_REG), ("lds", neat.FWD_LDS)):
+        try:
+            t0e, t1e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            neat.forward(d, prog, tx, pop.B, outputs=out, variant=var)
+            t0e.record(stream)
+            for _ in range(5):
+                neat.forward(d, prog, tx, pop.B, outputs=out, variant=var)
+            t1e.record(stream)
+            torch.cuda.synchronize()
+            variants[name] = round(t0e.elapsed_time(t1e) / 5, 4)
+        except neat.NeatError:
+            variants[name] = None
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -154,6 +170,7 @@ def main():
                    "P": pop.P, "B": pop.B, "N_max": 50, "C_max": 200, "I": 17, "O": 6},
         "topo_ms": round(float(np.median(topo_ms)), 4),
         "forward_ms": round(float(np.median(fwd_ms)), 4),
+        "forward_variant_ms": variants,
         "rejected_genomes": n_bad,
         "roofline": roofline,
         "cpu_baseline": cpu,

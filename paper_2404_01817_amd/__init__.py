@@ -11,7 +11,7 @@ from __future__ import annotations
 import ctypes
 from typing import Optional, Tuple
 
-from ._lib import Dims, NeatError, check, lib
+from ._lib import FWD_AUTO, FWD_LDS, FWD_REG, Dims, NeatError, check, lib
 
 __all__ = ["Dims", "NeatError", "dims_of", "program_bytes", "topo_sort", "forward",
            "forward_grid"]
@@ -73,7 +73,7 @@ def topo_sort(nodes, conns, I: int, O: int, program=None, stream=None,
 
 
 def forward(dims: Dims, program, inputs, B: int, shared_inputs: bool = False,
-            outputs=None, stream=None):
+            outputs=None, stream=None, variant: int = 0):
     """Calculation stage.  inputs [P,B,I] (or [B,I] when shared) float32 on the
     GPU; returns outputs [P,B,O]."""
     torch = _torch()
@@ -92,8 +92,8 @@ def forward(dims: Dims, program, inputs, B: int, shared_inputs: bool = False,
         _dev_f32(outputs, "outputs")
         if outputs.numel() < dims.P * B * dims.O:
             raise ValueError("outputs smaller than P * B * O")
-    check(lib().neat_forward(ctypes.byref(dims), _ptr(program), _ptr(inputs), stride, B,
-                             _ptr(outputs), _stream(stream)))
+    check(lib().neat_forward_ex(ctypes.byref(dims), _ptr(program), _ptr(inputs), stride, B,
+                                _ptr(outputs), variant, _stream(stream)))
     return outputs
 
 

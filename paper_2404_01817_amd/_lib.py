@@ -15,6 +15,7 @@ LIB_PATH = os.path.join(PKG, "libneat.so")
 
 NEAT_OK = 0
 NEAT_PENDING = 1
+FWD_AUTO, FWD_REG, FWD_LDS = 0, 1, 2
 
 
 class NeatError(RuntimeError):
@@ -36,6 +37,7 @@ SIGNATURES = {
     "neat_program_bytes": (_sz, [ctypes.POINTER(Dims)]),
     "neat_topo_sort": (_i32, [ctypes.POINTER(Dims), _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "neat_forward": (_i32, [ctypes.POINTER(Dims), _vp, _vp, _i64, _i32, _vp, _vp]),
+    "neat_forward_ex": (_i32, [ctypes.POINTER(Dims), _vp, _vp, _i64, _i32, _vp, _i32, _vp]),
     "neat_forward_grid": (_i32, [ctypes.POINTER(Dims), _vp, _i32, _i64, _i32, _vp, _vp]),
     "neat_last_error": (ctypes.c_char_p, []),
     "neat_strerror": (ctypes.c_char_p, [_i32]),

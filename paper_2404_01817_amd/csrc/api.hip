@@ -103,37 +103,50 @@ int neat_topo_sort(const neat_dims *d, const float *nodes, const float *conns, i
     return NEAT_OK;
 }
 
-int neat_forward(const neat_dims *d, const void *program, const float *inputs,
-                 int64_t input_genome_stride, int32_t B, float *outputs, void *stream) {
+static int forward_common(const neat_dims *d, const void *program, const float *inputs,
+                          int64_t input_genome_stride, int32_t B, float *outputs, int variant,
+                          bool grid, int32_t side, int64_t first, void *stream) {
+    if (variant == NEAT_FWD_AUTO) variant = neat::forward_default_variant(d->N_max);
+    if (variant != NEAT_FWD_REG && variant != NEAT_FWD_LDS)
+        return fail(NEAT_E_INVALID, "unknown forward variant %d", variant);
+    if (variant == NEAT_FWD_REG && neat::layout_of(d->N_max) == neat::LAYOUT_WIDE)
+        return fail(NEAT_E_INVALID, "register variant needs N_max <= 60 (N_max = %d)", d->N_max);
+    const long long blocks = (long long)d->P * ((B + 63) / 64);
+    if (blocks * 64 >= (1ll << 32))
+        return fail(NEAT_E_INVALID, "P * B too large for one launch (%lld tiles)", blocks);
+    const size_t lds = neat::forward_launch_lds_bytes(d->P, B, d->N_max, d->I, variant, grid);
+    if (lds > max_lds_bytes())
+        return fail(NEAT_E_INVALID, "N_max=%d, I=%d need %zu B of LDS per workgroup, device allows %zu",
+                    d->N_max, d->I, lds, max_lds_bytes());
+    hipError_t e = neat::launch_forward(d->P, d->N_max, d->C_max, d->I, d->O,
+                                        (const int32_t *)program, inputs, input_genome_stride, B,
+                                        outputs, variant, grid, side, first, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "forward launch");
+    return NEAT_OK;
+}
+
+int neat_forward_ex(const neat_dims *d, const void *program, const float *inputs,
+                    int64_t input_genome_stride, int32_t B, float *outputs, int32_t variant,
+                    void *stream) {
     int rc = check_dims(d);
     if (rc != NEAT_OK) return rc;
     if (B < 0) return fail(NEAT_E_INVALID, "B = %d < 0", B);
+    if (input_genome_stride < 0) return fail(NEAT_E_INVALID, "negative input_genome_stride");
+    if (input_genome_stride != 0 && input_genome_stride < (int64_t)B * d->I)
+        return fail(NEAT_E_INVALID, "input_genome_stride %lld < B * I = %lld",
+                    (long long)input_genome_stride, (long long)B * d->I);
     if (d->P == 0 || B == 0) return NEAT_OK;
     if (!program || !inputs || !outputs)
         return fail(NEAT_E_INVALID, "program, inputs or outputs is NULL");
     if (!aligned(program, 16)) return fail(NEAT_E_INVALID, "program must be 16-byte aligned");
-    if (input_genome_stride != 0 && input_genome_stride < (int64_t)B * d->I)
-        return fail(NEAT_E_INVALID, "input_genome_stride %lld < B * I = %lld",
-                    (long long)input_genome_stride, (long long)B * d->I);
-    if (input_genome_stride < 0) return fail(NEAT_E_INVALID, "negative input_genome_stride");
-    const long long blocks = (long long)d->P * ((B + 63) / 64);
-    if (blocks * 64 >= (1ll << 32))
-        return fail(NEAT_E_INVALID, "P * B too large for one launch (%lld workgroups)", blocks);
-    hipError_t e;
-    if (d->N_max <= neat::REG_MAX_NODES) {
-        e = neat::launch_forward_reg(d->P, d->N_max, d->C_max, d->I, d->O,
-                                     (const int32_t *)program, inputs, input_genome_stride, B,
-                                     outputs, (hipStream_t)stream);
-    } else {
-        const size_t lds = neat::forward_lds_bytes(d->N_max);
-        if (lds > max_lds_bytes())
-            return fail(NEAT_E_INVALID, "N_max=%d needs %zu B of LDS per wave, device allows %zu",
-                        d->N_max, lds, max_lds_bytes());
-        e = neat::launch_forward(d->P, d->N_max, d->C_max, d->I, d->O, (const int32_t *)program,
-                                 inputs, input_genome_stride, B, outputs, (hipStream_t)stream);
-    }
-    if (e != hipSuccess) return hip_fail(e, "forward launch");
-    return NEAT_OK;
+    return forward_common(d, program, inputs, input_genome_stride, B, outputs, variant, false, 0,
+                          0, stream);
+}
+
+int neat_forward(const neat_dims *d, const void *program, const float *inputs,
+                 int64_t input_genome_stride, int32_t B, float *outputs, void *stream) {
+    return neat_forward_ex(d, program, inputs, input_genome_stride, B, outputs, NEAT_FWD_AUTO,
+                           stream);
 }
 
 int neat_forward_grid(const neat_dims *d, const void *program, int32_t side, int64_t first,
@@ -149,25 +162,8 @@ int neat_forward_grid(const neat_dims *d, const void *program, int32_t side, int
     if (d->P == 0 || Q == 0) return NEAT_OK;
     if (!program || !outputs) return fail(NEAT_E_INVALID, "program or outputs is NULL");
     if (!aligned(program, 16)) return fail(NEAT_E_INVALID, "program must be 16-byte aligned");
-    const long long blocks = (long long)d->P * ((Q + 63) / 64);
-    if (blocks * 64 >= (1ll << 32))
-        return fail(NEAT_E_INVALID, "P * Q too large for one launch (%lld workgroups)", blocks);
-    hipError_t e;
-    if (d->N_max <= neat::REG_MAX_NODES) {
-        e = neat::launch_forward_reg_grid(d->P, d->N_max, d->C_max, d->I, d->O,
-                                          (const int32_t *)program, side, first, Q, outputs,
-                                          (hipStream_t)stream);
-    } else {
-        const size_t lds = neat::forward_lds_bytes(d->N_max);
-        if (lds > max_lds_bytes())
-            return fail(NEAT_E_INVALID, "N_max=%d needs %zu B of LDS per wave, device allows %zu",
-                        d->N_max, lds, max_lds_bytes());
-        e = neat::launch_forward_grid(d->P, d->N_max, d->C_max, d->I, d->O,
-                                      (const int32_t *)program, side, first, Q, outputs,
-                                      (hipStream_t)stream);
-    }
-    if (e != hipSuccess) return hip_fail(e, "forward_grid launch");
-    return NEAT_OK;
+    return forward_common(d, program, nullptr, 0, Q, outputs, NEAT_FWD_AUTO, true, side, first,
+                          stream);
 }
 
 }  // extern "C"

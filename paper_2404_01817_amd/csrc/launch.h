@@ -19,29 +19,19 @@ hipError_t launch_topo(int P, int N, int C, int I, int O, const float *nodes,
                        const float *conns, int32_t *order, int32_t *level,
                        uint32_t *status, int32_t *prog, hipStream_t stream);
 
-// Dynamic LDS bytes of the lane-per-sample forward for N node positions.
-size_t forward_lds_bytes(int N);
+// Forward variants (value store of the lane-per-sample mapping).
+constexpr int FWD_AUTO = 0;
+constexpr int FWD_REG = 1;  // value vector in VGPRs (N_max <= 60)
+constexpr int FWD_LDS = 2;  // value vector in LDS rows (any N_max)
+
+int forward_default_variant(int N);
+// LDS bytes of one forward launch (all waves of a workgroup).
+size_t forward_launch_lds_bytes(int P, int B, int N, int I, int variant, bool grid);
 
 // inputs: per-genome stride in floats (0 = shared); B vectors per genome.
+// grid: CPPN queries generated in the kernel (I == 5, side, first).
 hipError_t launch_forward(int P, int N, int C, int I, int O, const int32_t *prog,
                           const float *inputs, int64_t gstride, int B, float *outputs,
-                          hipStream_t stream);
-
-// CPPN grid queries generated in the kernel (I == 5).
-hipError_t launch_forward_grid(int P, int N, int C, int I, int O, const int32_t *prog,
-                               int side, int64_t first, int Q, float *outputs,
-                               hipStream_t stream);
-
-// Register-resident forward (N_max <= 64): LDS bytes per wave, launchers.
-size_t forward_reg_lds_bytes(int I);
-hipError_t launch_forward_reg(int P, int N, int C, int I, int O, const int32_t *prog,
-                              const float *inputs, int64_t gstride, int B, float *outputs,
-                              hipStream_t stream);
-hipError_t launch_forward_reg_grid(int P, int N, int C, int I, int O, const int32_t *prog,
-                                   int side, int64_t first, int Q, float *outputs,
-                                   hipStream_t stream);
-
-// Largest N_max the register-resident forward handles.
-constexpr int REG_MAX_NODES = 64;
+                          int variant, bool grid, int side, int64_t first, hipStream_t stream);
 
 }  // namespace neat

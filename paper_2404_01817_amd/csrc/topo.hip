@@ -298,62 +298,119 @@ __global__ __launch_bounds__(1024) void topo_kernel(TopoArgs a) {
     if (a.status && t == 0) a.status[g] = status;
     if (!a.prog) return;
 
-    // ---- 6. program
+    // ---- 6. program (layout in program.h)
+    const int L = layout_of(N);
     int32_t *prog = a.prog + g * (size_t)a.prog_words;
     float *progf = reinterpret_cast<float *>(prog);
     if (t == 0) {
         prog[HDR_NVALID] = ok ? nvalid : 0;
-        prog[HDR_NEDGES] = ok ? s_inoff[N] : 0;
         prog[HDR_STATUS] = (int32_t)status;
         prog[HDR_NLEVELS] = ok ? n_levels : 0;
         prog[HDR_I] = I;
         prog[HDR_O] = O;
+        prog[HDR_LAYOUT] = L;
+        prog[HDR_NREAL] = ok ? s_inoff[N] : 0;
+        if (!ok) prog[HDR_NEDGES] = 0;
     }
     if (!ok) return;  // uniform
-    // output positions: rank I + j holds key I + j
-    if (t < O) prog[out_off() + t] = s_pos[s_srow[I + t]];
-    // first edge of every position, in topological order
+    // output slots: rank I + j holds key I + j
+    if (t < O) prog[out_off() + t] = slot_of(L, s_pos[s_srow[I + t]]);
+    // owner of a computed row: incoming edges per half, padded to even counts
+    const bool computed = t < N && s_key[t] >= 0 && s_pos[t] >= I;
+    int n_lo = 0, n_hi = 0, first_lo = -1, first_hi = -1;
+    if (computed) {
+        int klo = 0x7fffffff, khi = 0x7fffffff;
+        for (int k = s_inoff[t]; k < s_inoff[t + 1]; ++k) {
+            const int c2 = in_list[k];
+            const int src = e_src[c2];
+            const int ks = s_key[src];
+            if (half_of(L, slot_of(L, s_pos[src]))) {
+                ++n_hi;
+                if (ks < khi) khi = ks, first_hi = c2;
+            } else {
+                ++n_lo;
+                if (ks < klo) klo = ks, first_lo = c2;
+            }
+        }
+    }
+    const int pad_lo = n_lo + (n_lo & 1), pad_hi = n_hi + (n_hi & 1);
+    __syncthreads();  // every owner has read s_deg / s_indeg of the sort phase
+    if (computed) {
+        s_indeg[t] = pad_lo;
+        s_deg[t] = pad_lo + pad_hi;
+    }
+    __syncthreads();
+    // first edge of every position, in topological order; level starts
     {
         const int row = (t < nvalid) ? s_curi[t] : -1;
-        const int deg = (t >= I && t < nvalid) ? s_deg[row] : 0;
+        const int cnt = (t >= I && t < nvalid) ? s_deg[row] : 0;
         int tot;
-        const int eb = block_excl_scan(deg, s_wave, &tot);
+        const int eb = block_excl_scan(cnt, s_wave, &tot);
         if (t >= I && t < nvalid) {
             prog[ebeg_off(N, C, O) + (t - I)] = eb;
-            s_curo[row] = eb;  // edge begin by row; the record comes from the row's owner
+            s_curo[row] = eb;  // edge begin by row
         }
-        // level starts: position t opens a level when its level differs from t-1
         if (t < nvalid) {
             const int lv = s_skey[row];
             if (t == 0 || s_skey[s_curi[t - 1]] != lv) prog[lvl_off(N, C, O) + lv] = t;
         }
-        if (t == 0) prog[lvl_off(N, C, O) + n_levels] = nvalid;
-    }
-    __syncthreads();
-    if (t < N && s_key[t] >= 0) {
-        const int p = s_pos[t];
-        if (p >= I) {
-            const int k = p - I;
-            const int deg = s_deg[t];
-            int32_t *rec = prog + rec_off(O) + REC_WORDS * k;
-            rec[0] = (int32_t)pack_rec(deg, act, agg);
-            progf[rec_off(O) + REC_WORDS * k + 1] = bias;
-            progf[rec_off(O) + REC_WORDS * k + 2] = resp;
-            progf[rec_off(O) + REC_WORDS * k + 3] = deg ? 1.0f / (float)deg : 0.0f;
+        if (t == 0) {
+            prog[lvl_off(N, C, O) + n_levels] = nvalid;
+            prog[HDR_NEDGES] = tot;
         }
     }
-    // edges: slot = first edge of the destination + number of in-edges with
-    // a smaller source key (keys are unique here, duplicates were rejected)
+    __syncthreads();
+    const int eoff = edge_off(N, O);
+    if (computed) {
+        const int k = s_pos[t] - I;
+        const int eb = s_curo[t];
+        const int deg = n_lo + n_hi;
+        const int r0 = rec_off(O) + REC_WORDS * k;
+        prog[r0 + REC_NLO] = pad_lo >> 1;
+        prog[r0 + REC_NHI] = pad_hi >> 1;
+        prog[r0 + REC_ACT] = act;
+        prog[r0 + REC_AGG] = agg;
+        progf[r0 + REC_BIAS] = bias;
+        progf[r0 + REC_RESP] = resp;
+        progf[r0 + REC_SCALE] = (agg == AGG_MEAN && deg) ? 1.0f / (float)deg : 1.0f;
+        prog[r0 + REC_DST] = slot_of(L, s_pos[t]);
+        // neutral padding edge of each odd half
+        for (int h = 0; h < 2; ++h) {
+            const int n = h ? n_hi : n_lo;
+            if (!(n & 1)) continue;
+            const int e = eb + (h ? pad_lo : 0) + n;
+            int slot;
+            float w = 1.0f;
+            if (agg == AGG_SUM || agg == AGG_MEAN) {
+                slot = zero_slot(L, N, h);
+            } else if (agg == AGG_PRODUCT) {
+                slot = zero_slot(L, N, h) + 1;
+            } else {
+                const int c2 = h ? first_hi : first_lo;
+                slot = slot_of(L, s_pos[e_src[c2]]);
+                w = conns[(size_t)c2 * 4 + 3];
+            }
+            prog[eoff + EDGE_WORDS * e] = slot;
+            progf[eoff + EDGE_WORDS * e + 1] = w;
+        }
+    }
+    // real edges: first edge of the destination's half + number of in-edges
+    // in that half with a smaller source key (keys are unique here)
     for (int c = t; c < C; c += W) {
         const int s = e_src[c];
         if (s < 0) continue;
         const int d = e_dst[c];
+        const int sl = slot_of(L, s_pos[s]);
+        const int h = half_of(L, sl);
         const int ks = s_key[s];
         int j = 0;
-        for (int k = s_inoff[d]; k < s_inoff[d + 1]; ++k) j += (s_key[e_src[in_list[k]]] < ks);
-        const int e = s_curo[d] + j;
-        prog[edge_off(N, O) + EDGE_WORDS * e] = s_pos[s];
-        progf[edge_off(N, O) + EDGE_WORDS * e + 1] = conns[(size_t)c * 4 + 3];
+        for (int k = s_inoff[d]; k < s_inoff[d + 1]; ++k) {
+            const int s2 = e_src[in_list[k]];
+            j += (s_key[s2] < ks) && (half_of(L, slot_of(L, s_pos[s2])) == h);
+        }
+        const int e = s_curo[d] + (h ? s_indeg[d] : 0) + j;
+        prog[eoff + EDGE_WORDS * e] = sl;
+        progf[eoff + EDGE_WORDS * e + 1] = conns[(size_t)c * 4 + 3];
     }
 }
 

@@ -22,7 +22,7 @@ def _neat():
     return neat
 
 
-def _gpu(nodes, conns, I, O, x=None, shared=False, grid=None):
+def _gpu(nodes, conns, I, O, x=None, shared=False, grid=None, variant=0):
     """Run transformation (+ calculation) on cuda:0; numpy results."""
     neat = _neat()
     dev = torch.device("cuda:0")
@@ -34,7 +34,7 @@ def _gpu(nodes, conns, I, O, x=None, shared=False, grid=None):
     if x is not None:
         tx = torch.from_numpy(np.ascontiguousarray(x)).to(dev)
         B = x.shape[0] if shared else x.shape[1]
-        y = neat.forward(d, prog, tx, B, shared_inputs=shared)
+        y = neat.forward(d, prog, tx, B, shared_inputs=shared, variant=variant)
     elif grid is not None:
         side, first, Q = grid
         y = neat.forward_grid(d, prog, side, first, Q)
@@ -95,11 +95,14 @@ def test_tiny_config():
     _assert_outputs(y, y64, beta, "tiny")
 
 
+@pytest.mark.parametrize("variant", [0, 2])
 @pytest.mark.parametrize("P,B", [(300, 130), (64, 64), (37, 1), (5, 191)])
-def test_control_small_full_compare(P, B):
-    """Mixed activations/aggregations, several sample tiles and a ragged tail."""
+def test_control_small_full_compare(P, B, variant):
+    """Mixed activations/aggregations, several sample tiles and a ragged tail;
+    both value stores (registers, LDS rows)."""
     pop = synth.control(seed=11 + P, P=P, B=B)
-    order, level, status, y = _gpu(pop.nodes, pop.conns, pop.I, pop.O, pop.inputs)
+    order, level, status, y = _gpu(pop.nodes, pop.conns, pop.I, pop.O, pop.inputs,
+                                   variant=variant)
     _assert_transform_exact(pop.nodes, pop.conns, pop.I, pop.O, order, level, status)
     y64, beta = oracle.forward(pop.nodes, pop.conns, pop.inputs, pop.I, pop.O)
     _assert_outputs(y, y64, beta, "control P=%d B=%d" % (P, B))
@@ -228,9 +231,11 @@ def test_all_genomes_rejected():
     assert np.isnan(y).all()
 
 
-@pytest.mark.parametrize("N,I,O", [(32, 5, 2), (33, 5, 2), (64, 40, 3), (64, 10, 4),
-                                   (65, 10, 4), (48, 31, 1), (64, 33, 2), (8, 3, 1)])
-def test_forward_kernel_shapes(N, I, O):
+@pytest.mark.parametrize("variant", [0, 2])
+@pytest.mark.parametrize("N,I,O", [(30, 5, 2), (31, 5, 2), (33, 5, 2), (60, 40, 3),
+                                   (61, 10, 4), (64, 10, 4), (48, 31, 1), (60, 33, 2),
+                                   (8, 3, 1), (47, 29, 2)])
+def test_forward_kernel_shapes(N, I, O, variant):
     """Both halves of the register-resident value vector (positions < 32 and
     >= 32, inputs in either half), and the switch to the LDS kernel above 64
     nodes."""
@@ -244,10 +249,10 @@ def test_forward_kernel_shapes(N, I, O):
                           synth.CONTROL_ACTS, synth.ALL_AGGS, nodes_out=nodes[p],
                           conns_out=conns[p])
     x = rng.standard_normal((P, B, I)).astype(np.float32)
-    order, level, status, y = _gpu(nodes, conns, I, O, x)
+    order, level, status, y = _gpu(nodes, conns, I, O, x, variant=variant)
     _assert_transform_exact(nodes, conns, I, O, order, level, status)
     y64, beta = oracle.forward(nodes, conns, x, I, O)
-    _assert_outputs(y, y64, beta, "shape N=%d I=%d O=%d" % (N, I, O))
+    _assert_outputs(y, y64, beta, "shape N=%d I=%d O=%d variant=%d" % (N, I, O, variant))
 
 
 def test_wide_fan_in_every_aggregation():
