@@ -31,10 +31,8 @@
  * with agg of an empty set = 0; the outputs are v[key I+j].  The order is the
  * level-synchronous Kahn order: level(u) = 0 without incoming enabled edges,
  * else 1 + max level of its sources; nodes sorted by (level, key).  Incoming
- * terms are combined in a fixed order that depends only on the genome and
- * N_max (ascending source key; for 30 < N_max <= 60 the sources stored in
- * the first 32 value slots come first).  NaN propagates through every
- * activation and aggregation.
+ * terms are combined in ascending source-key order.  NaN propagates through
+ * every activation and aggregation.
  *
  * STATUS.  Per-genome problems never fail a call: they set bits in the
  * genome's status word and the genome's outputs become NaN.  Bits:
@@ -133,7 +131,7 @@ int neat_forward(const neat_dims *dims, const void *program, const float *inputs
 /* Forward variants: how the lane-per-sample kernels keep the node values.
  * NEAT_FWD_AUTO picks one from N_max; the others exist for tuning. */
 #define NEAT_FWD_AUTO 0
-#define NEAT_FWD_REG 1 /* registers; needs N_max <= 60 */
+#define NEAT_FWD_REG 1 /* registers, node loop in assembly; needs N_max <= 62 */
 #define NEAT_FWD_LDS 2 /* LDS rows; any N_max */
 
 /*

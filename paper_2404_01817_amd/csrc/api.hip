@@ -110,7 +110,7 @@ static int forward_common(const neat_dims *d, const void *program, const float *
     if (variant != NEAT_FWD_REG && variant != NEAT_FWD_LDS)
         return fail(NEAT_E_INVALID, "unknown forward variant %d", variant);
     if (variant == NEAT_FWD_REG && neat::layout_of(d->N_max) == neat::LAYOUT_WIDE)
-        return fail(NEAT_E_INVALID, "register variant needs N_max <= 60 (N_max = %d)", d->N_max);
+        return fail(NEAT_E_INVALID, "register variant needs N_max <= 62 (N_max = %d)", d->N_max);
     const long long blocks = (long long)d->P * ((B + 63) / 64);
     if (blocks * 64 >= (1ll << 32))
         return fail(NEAT_E_INVALID, "P * B too large for one launch (%lld tiles)", blocks);

@@ -8,13 +8,15 @@
 // cache.
 //
 // Two stores for the value vector v of Section 3.3 (slots, see program.h):
-//   RegStore  32 or 64 VGPRs per lane, indexed through the GPR-index mode
-//             with the program's uniform slot numbers (layouts REG32, REG64);
+//   AsmStore  64 VGPRs per lane (v0..v63, layout REG, N_max <= 62); the node
+//             loop is the assembly of node_loop_asm.h, which indexes the
+//             registers in GPR-index mode with the program's uniform slots;
 //   LdsStore  one LDS row of 64 lanes per slot (any layout; rows are 256 B,
-//             so lane l of every row sits in bank l).
-// Edges come in pairs (the program pads each half to an even count with a
-// neutral edge), so the inner loop has no per-edge tests.  The next node's
-// record is fetched while the current node computes.
+//             so lane l of every row sits in bank l), node loop in C++.
+// Edges come in pairs (the program pads each node to an even count with a
+// neutral edge) and the first two pairs sit in the node's record, so the
+// inner loops have no per-edge tests.  The next record is fetched while the
+// current node computes.
 //
 // Inputs of the next tile are copied HBM -> LDS by the DMA path of
 // global_load_lds (16-byte pieces when aligned) while the current tile
@@ -26,6 +28,7 @@
 #include "act.h"
 #include "launch.h"
 #include "neat.h"
+#include "node_loop_asm.h"
 #include "program.h"
 
 namespace neat {
@@ -38,7 +41,7 @@ typedef float f32x32 __attribute__((ext_vector_type(32)));
 typedef int i32x8 __attribute__((ext_vector_type(8)));
 typedef int i32x16 __attribute__((ext_vector_type(16)));
 typedef const __attribute__((address_space(4))) int32_t cprog_t;
-typedef const __attribute__((address_space(4))) i32x8 cint8_t;
+typedef const __attribute__((address_space(4))) i32x8 cint8_t;  // unused
 typedef const __attribute__((address_space(4))) i32x16 cint16_t;
 typedef __attribute__((address_space(1))) const void gvoid;
 typedef __attribute__((address_space(3))) void lvoid;
@@ -46,40 +49,6 @@ typedef __attribute__((address_space(3))) void lvoid;
 __device__ __forceinline__ float fbits(int b) { return __int_as_float(b); }
 
 // ---------------------------------------------------------------- stores
-template <int NV>
-struct RegStore;
-
-template <>
-struct RegStore<32> {
-    f32x32 lo;
-    __device__ __forceinline__ float get_lo(int s) const { return lo[s]; }
-    __device__ __forceinline__ float get_hi(int s) const { return lo[s]; }
-    template <bool HI>
-    __device__ __forceinline__ void set(int s, float x) { lo[s] = x; }
-    __device__ __forceinline__ void init(int /*N*/) {
-        lo[30] = 0.0f;
-        lo[31] = 1.0f;
-    }
-};
-
-template <>
-struct RegStore<64> {
-    f32x32 lo, hi;
-    __device__ __forceinline__ float get_lo(int s) const { return lo[s]; }
-    __device__ __forceinline__ float get_hi(int s) const { return hi[s - 32]; }
-    template <bool HI>
-    __device__ __forceinline__ void set(int s, float x) {
-        if (HI) hi[s - 32] = x;
-        else lo[s] = x;
-    }
-    __device__ __forceinline__ void init(int /*N*/) {
-        lo[30] = 0.0f;
-        lo[31] = 1.0f;
-        hi[30] = 0.0f;
-        hi[31] = 1.0f;
-    }
-};
-
 struct LdsStore {
     float *col;  // this lane's column: slot s at col[s * TILE]
     int layout;
@@ -88,104 +57,149 @@ struct LdsStore {
     template <bool HI>
     __device__ __forceinline__ void set(int s, float x) { col[s * TILE] = x; }
     __device__ __forceinline__ void init(int N) {
-        const int z0 = zero_slot(layout, N, 0);
+        const int z0 = zero_slot(layout, N);
         col[z0 * TILE] = 0.0f;
         col[(z0 + 1) * TILE] = 1.0f;
-        if (layout == LAYOUT_REG64) {
-            col[62 * TILE] = 0.0f;
-            col[63 * TILE] = 1.0f;
-        }
     }
 };
 
-// ---------------------------------------------------------------- edges
-// Combine n pairs of terms w * v[slot] (edges from e) into acc.
-template <int AGG, bool HIGH, class Store>
-__device__ __forceinline__ float combine_pairs(float acc, cprog_t *e, int n, const Store &v) {
-    for (int p = 0; p < n; p += 4) {
-        const i32x16 ch = *(cint16_t *)(e + 4 * p);
+// Value vector pinned to v0..v63 for the assembly node loop
+// (node_loop_asm.h).  Slots are absolute (0..63); M0, which the GPR-index
+// mode overwrites, is saved and restored around every access.
+struct AsmStore {
+    f32x32 lo, hi;
+    __device__ __forceinline__ float get(int s) const {
+        float x;
+        asm volatile(
+            "s_mov_b32 s91, m0\n\t"
+            "s_set_gpr_idx_on %3, gpr_idx(SRC0)\n\t"
+            "v_mov_b32_e32 %0, v0\n\t"
+            "s_set_gpr_idx_off\n\t"
+            "s_mov_b32 m0, s91"
+            : "=&v"(x)
+            : "{v[0:31]}"(lo), "{v[32:63]}"(hi), "s"(s)
+            : "s91");
+        return x;
+    }
+    __device__ __forceinline__ float get_lo(int s) const { return get(s); }
+    __device__ __forceinline__ float get_hi(int s) const { return get(s); }
+    template <bool HI>
+    __device__ __forceinline__ void set(int s, float x) {
+        asm volatile(
+            "s_mov_b32 s91, m0\n\t"
+            "s_set_gpr_idx_on %2, gpr_idx(DST)\n\t"
+            "v_mov_b32_e32 v0, %3\n\t"
+            "s_set_gpr_idx_off\n\t"
+            "s_mov_b32 m0, s91"
+            : "+{v[0:31]}"(lo), "+{v[32:63]}"(hi)
+            : "s"(s), "v"(x)
+            : "s91");
+    }
+    __device__ __forceinline__ void init(int /*N*/) {
+        set<true>(62, 0.0f);
+        set<true>(63, 1.0f);
+    }
+    // all computed nodes of the genome (node_loop_asm.h)
+    __device__ __forceinline__ void run(const int32_t *rec, const int32_t *edg, int n) {
+        asm volatile(NEAT_NODE_LOOP_ASM
+                     : "+{v[0:31]}"(lo), "+{v[32:63]}"(hi)
+                     : [rec] "s"(rec), [edg] "s"(edg), [n] "s"(n)
+                     : NEAT_NODE_LOOP_CLOBBERS);
+    }
+};
+
+// ---------------------------------------------------------------- nodes (C++)
+// One term w * v[slot] combined into acc (class ACLS); NaN terms of a max
+// are remembered in nan (the hardware max ignores NaN).
+template <int ACLS, class Store>
+__device__ __forceinline__ void combine(float &acc, float &nan, int slot, float w, const Store &v) {
+    const float x = v.get_lo(slot);
+    if (ACLS == ACLS_SUM) {
+        acc = fmaf(w, x, acc);
+    } else if (ACLS == ACLS_PROD) {
+        acc *= w * x;
+    } else {
+        const float t = w * x;
+        acc = fmaxf(acc, t);
+        nan = (t != t) ? t : nan;
+    }
+}
+
+// pairs edge pairs: the first two from the record (r), then the overflow
+// array from e, four words per pair.
+template <int ACLS, class Store>
+__device__ __forceinline__ float aggregate(const i32x16 &r, cprog_t *e, int pairs,
+                                           const Store &v) {
+    float acc = ACLS == ACLS_SUM ? 0.0f : (ACLS == ACLS_PROD ? 1.0f : -__builtin_inff());
+    float nan = 0.0f;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            if (p + q < n) {
-#pragma unroll
-                for (int u = 0; u < 2; ++u) {
-                    const int slot = ch[4 * q + 2 * u];
-                    const float w = fbits(ch[4 * q + 2 * u + 1]);
-                    const float x = HIGH ? v.get_hi(slot) : v.get_lo(slot);
-                    if (AGG == AGG_SUM) {
-                        acc = fmaf(w, x, acc);
-                    } else if (AGG == AGG_PRODUCT) {
-                        acc *= w * x;
-                    } else {
-                        const float t = w * x;
-                        acc = ((AGG == AGG_MAX ? t > acc : t < acc) || t != t) ? t : acc;
-                    }
-                }
-            }
+    for (int p = 0; p < REC_INLINE_PAIRS; ++p) {
+        if (p < pairs) {
+            combine<ACLS>(acc, nan, r[REC_PAIRS + 4 * p], fbits(r[REC_PAIRS + 4 * p + 1]), v);
+            combine<ACLS>(acc, nan, r[REC_PAIRS + 4 * p + 2], fbits(r[REC_PAIRS + 4 * p + 3]),
+                          v);
         }
     }
+    for (int p = 0; p < pairs - REC_INLINE_PAIRS; ++p) {
+        combine<ACLS>(acc, nan, e[4 * p], fbits(e[4 * p + 1]), v);
+        combine<ACLS>(acc, nan, e[4 * p + 2], fbits(e[4 * p + 3]), v);
+    }
+    if (ACLS == ACLS_MAX) acc = (nan != nan) ? nan : acc;
     return acc;
 }
 
-template <int AGG, bool TWO_HALVES, class Store>
-__device__ __forceinline__ float aggregate(cprog_t *e, int nlo, int nhi, const Store &v) {
-    float acc = AGG == AGG_SUM ? 0.0f
-                               : (AGG == AGG_PRODUCT ? 1.0f
-                                                     : (AGG == AGG_MAX ? -__builtin_inff()
-                                                                       : __builtin_inff()));
-    acc = combine_pairs<AGG, false>(acc, e, nlo, v);
-    if (TWO_HALVES) acc = combine_pairs<AGG, true>(acc, e + 4 * nlo, nhi, v);
-    return acc;
-}
-
-// ---------------------------------------------------------------- nodes
-// Evaluate records k0 .. k1-1, all writing the same half (DST_HI).
-template <bool DST_HI, bool TWO_HALVES, class Store>
-__device__ __forceinline__ void run_nodes(cprog_t *rec, cprog_t *edges, int k0, int k1, int &ep,
-                                          i32x8 &r, Store &v) {
-    for (int k = k0; k < k1; ++k) {
-        const int nlo = r[REC_NLO], nhi = r[REC_NHI];
-        const int act = r[REC_ACT], agg = r[REC_AGG];
-        const float bias = fbits(r[REC_BIAS]), resp = fbits(r[REC_RESP]);
-        const float scale = fbits(r[REC_SCALE]);
-        const int dst = r[REC_DST];
-        // next record (the record array has room for N records)
-        const i32x8 rn = *(cint8_t *)(rec + REC_WORDS * (k + 1));
-        cprog_t *e = edges + EDGE_WORDS * ep;
-        float a = 0.0f;
-        if (nlo + nhi > 0) {
-            if (agg == AGG_SUM || agg == AGG_MEAN)
-                a = aggregate<AGG_SUM, TWO_HALVES>(e, nlo, nhi, v) * scale;
-            else if (agg == AGG_PRODUCT)
-                a = aggregate<AGG_PRODUCT, TWO_HALVES>(e, nlo, nhi, v);
-            else if (agg == AGG_MAX)
-                a = aggregate<AGG_MAX, TWO_HALVES>(e, nlo, nhi, v);
-            else
-                a = aggregate<AGG_MIN, TWO_HALVES>(e, nlo, nhi, v);
-        }
-        ep += 2 * (nlo + nhi);
-        v.template set<DST_HI>(dst, act_eval(act, fmaf(resp, a, bias)));
-        r = rn;
-    }
+// Lane select with a uniform 64-bit mask (all ones or zero): mask ? b : a.
+__device__ __forceinline__ float sel_mask(float a, float b, unsigned long long mask) {
+    float r;
+    asm volatile("v_cndmask_b32_e64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "s"(mask));
+    return r;
 }
 
 template <class Store>
-__device__ __forceinline__ void run_program(cprog_t *prog, int N, int O, int I, int layout,
+__device__ __forceinline__ void run_program(cprog_t *prog, int N, int O, int I, int /*layout*/,
                                             Store &v) {
     const int ncomp = prog[HDR_NVALID] - I;
     if (ncomp <= 0) return;
     cprog_t *rec = prog + rec_off(O);
-    cprog_t *edges = prog + edge_off(N, O);
-    i32x8 r = *(cint8_t *)rec;
-    int ep = 0;
-    if (layout == LAYOUT_REG64) {
-        // records whose position is < 30 write the low half and read only it
-        const int split = min(ncomp, max(0, 30 - I));
-        run_nodes<false, false>(rec, edges, 0, split, ep, r, v);
-        run_nodes<true, true>(rec, edges, split, ncomp, ep, r, v);
-    } else {
-        run_nodes<false, false>(rec, edges, 0, ncomp, ep, r, v);
+    cprog_t *e = prog + edge_off(N, O);
+    i32x16 r = *(cint16_t *)rec;
+    for (int k = 0; k < ncomp; ++k) {
+        const unsigned code = (unsigned)r[REC_CODE];
+        const int pairs = (int)(code & 0xffffu), acls = (int)((code >> 16) & 3u);
+        const int xcls = (int)((code >> 18) & 3u), dst = (int)(code >> 20);
+        const float bias = fbits(r[REC_BIAS]), resp = fbits(r[REC_RESP]);
+        const float cf = fbits(r[REC_C]), ea = fbits(r[REC_EA]), eb = fbits(r[REC_EB]);
+        const unsigned long long mask =
+            ((unsigned long long)(unsigned)r[REC_MASK + 1] << 32) | (unsigned)r[REC_MASK];
+        // next record (the record array has room for N records)
+        const i32x16 rn = *(cint16_t *)(rec + REC_WORDS * (k + 1));
+        float a;
+        if (acls == ACLS_SUM) a = aggregate<ACLS_SUM>(r, e, pairs, v);
+        else if (acls == ACLS_PROD) a = aggregate<ACLS_PROD>(r, e, pairs, v);
+        else a = aggregate<ACLS_MAX>(r, e, pairs, v);
+        if (pairs > REC_INLINE_PAIRS) e += 4 * (pairs - REC_INLINE_PAIRS);
+        const float z = fmaf(resp, a, bias);
+        float y;
+        if (xcls == XCLS_PL) {
+            // identity, abs, relu: z above 0 (or NaN) passes, else c z or 0
+            y = !(z <= 0.0f) ? z : sel_mask(z * cf, 0.0f, mask);
+        } else if (xcls == XCLS_EXPO) {
+            // sigmoid, tanh: ea + eb / (1 + 2^(c z)); gaussian: 2^(c z z)
+            const float ex = exp2_hw(cf * sel_mask(z, z * z, mask));
+            y = sel_mask(fmaf(eb, rcp_hw(1.0f + ex), ea), ex, mask);
+        } else {
+            y = act_sin(z);
+        }
+        v.template set<false>(dst, y);
+        r = rn;
     }
+}
+
+__device__ __forceinline__ void run_program(cprog_t *prog, int N, int O, int I, int /*layout*/,
+                                            AsmStore &v) {
+    const int ncomp = prog[HDR_NVALID] - I;
+    const int32_t *p = (const int32_t *)prog;
+    v.run(p + rec_off(O), p + edge_off(N, O), ncomp > 0 ? ncomp : 0);
 }
 
 // ---------------------------------------------------------------- tiles
@@ -233,12 +247,9 @@ __device__ __forceinline__ void wait_dma() {
 }
 
 template <class Store>
-__device__ __forceinline__ void place_inputs(Store &v, const float *cur, int I, int layout,
+__device__ __forceinline__ void place_inputs(Store &v, const float *cur, int I, int /*layout*/,
                                              int lane) {
-    // slot of input i: i, or i + 2 from position 30 on in the REG64 layout
-    const int ilo = layout == LAYOUT_REG64 ? min(I, 30) : I;
-    for (int i = 0; i < ilo; ++i) v.template set<false>(i, cur[lane * I + i]);
-    for (int i = ilo; i < I; ++i) v.template set<true>(i + 2, cur[lane * I + i]);
+    for (int i = 0; i < I; ++i) v.template set<false>(i, cur[lane * I + i]);  // slot i
 }
 
 template <class Store>
@@ -301,18 +312,18 @@ __device__ __forceinline__ void forward_body(const FwdArgs &a, float *stage, Sto
             float *o = out_g + (size_t)(t * TILE + lane) * O;
             for (int j = 0; j < O; ++j) {
                 const int s = prog[out_off() + j];
-                o[j] = (s < 32) ? v.get_lo(s) : v.get_hi(s);
+                o[j] = v.get_lo(s);
             }
         }
     }
 }
 
-template <int NV, bool GRID>
-__global__ __launch_bounds__(TILE *WAVES) void forward_reg_kernel(FwdArgs a) {
+template <bool GRID>
+__global__ __launch_bounds__(TILE *WAVES) void forward_asm_kernel(FwdArgs a) {
     extern __shared__ float smem[];
-    RegStore<NV> v;
+    AsmStore v;
     const size_t stage = GRID ? 0 : (size_t)2 * TILE * a.I;
-    forward_body<RegStore<NV>, GRID>(a, smem + (threadIdx.x / TILE) * stage, v);
+    forward_body<AsmStore, GRID>(a, smem + (threadIdx.x / TILE) * stage, v);
 }
 
 template <bool GRID>
@@ -377,21 +388,10 @@ hipError_t launch_forward(int P, int N, int C, int I, int O, const int32_t *prog
     const dim3 block(TILE * a.wpg);
     const size_t lds = forward_lds_bytes(N, I, variant, grid) * a.wpg;
     if (variant == FWD_REG) {
-        if (a.layout == LAYOUT_REG32) {
-            if (grid)
-                hipLaunchKernelGGL((forward_reg_kernel<32, true>), dim3(blocks), block, lds,
-                                   stream, a);
-            else
-                hipLaunchKernelGGL((forward_reg_kernel<32, false>), dim3(blocks), block, lds,
-                                   stream, a);
-        } else {
-            if (grid)
-                hipLaunchKernelGGL((forward_reg_kernel<64, true>), dim3(blocks), block, lds,
-                                   stream, a);
-            else
-                hipLaunchKernelGGL((forward_reg_kernel<64, false>), dim3(blocks), block, lds,
-                                   stream, a);
-        }
+        if (grid)
+            hipLaunchKernelGGL((forward_asm_kernel<true>), dim3(blocks), block, lds, stream, a);
+        else
+            hipLaunchKernelGGL((forward_asm_kernel<false>), dim3(blocks), block, lds, stream, a);
     } else {
         if (grid)
             hipLaunchKernelGGL((forward_lds_kernel<true>), dim3(blocks), block, lds, stream, a);

@@ -21,7 +21,7 @@ hipError_t launch_topo(int P, int N, int C, int I, int O, const float *nodes,
 
 // Forward variants (value store of the lane-per-sample mapping).
 constexpr int FWD_AUTO = 0;
-constexpr int FWD_REG = 1;  // value vector in VGPRs (N_max <= 60)
+constexpr int FWD_REG = 1;  // value vector in VGPRs, node loop in assembly (N_max <= 62)
 constexpr int FWD_LDS = 2;  // value vector in LDS rows (any N_max)
 
 int forward_default_variant(int N);

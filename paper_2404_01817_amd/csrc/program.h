@@ -9,19 +9,18 @@
 //
 // Each position is stored in a value SLOT of the forward kernels' value
 // vector.  The slot numbering depends only on N_max (layout_of):
-//   REG32  N_max <= 30: slot = position; slots 30, 31 hold the constants
-//          0 and 1;
-//   REG64  N_max <= 60: positions 0..29 -> slots 0..29, positions >= 30 ->
-//          slot + 2; slots 30, 31 and 62, 63 hold 0 and 1 (one pair in each
-//          32-slot half);
-//   WIDE   otherwise: slot = position; slots N_max, N_max + 1 hold 0 and 1.
+//   REG   N_max <= 62: slot = position, 64 slots, slots 62 and 63 hold the
+//         constants 0 and 1 (the register-resident forward);
+//   WIDE  otherwise: slot = position, N_max + 2 slots, the constants at
+//         slots N_max and N_max + 1 (LDS rows).
 // A node's incoming edges are stored as (source slot, weight) in ascending
-// source-key order, first those whose source lies in slots 0..31 ("low
-// half"), then the others (REG64 only; the other layouts have one half).
-// Each half is padded to an even count with one neutral edge, so kernels
-// consume edges in pairs without per-edge tests: for sum and mean a term
-// 1 * v[zero slot], for product 1 * v[one slot], for max and min a copy of
-// the half's first edge.  None of these changes any result.
+// source-key order, padded to an even count with one neutral edge, so the
+// kernels consume edges in pairs without per-edge tests: for sum and mean a
+// term 1 * v[zero slot], for product 1 * v[one slot], for max and min a copy
+// of the node's first edge.  None of these changes any result.  The first
+// two pairs live in the node's record (one scalar load brings a node and its
+// usual in-edges); further pairs follow in the overflow edge array, node
+// after node.
 //
 // All fields are 32-bit words; one genome's program is prog_words() words,
 // a multiple of 64 (256 bytes), so every genome starts on its own lines.
@@ -43,49 +42,63 @@ constexpr int HDR_LAYOUT = 6;
 constexpr int HDR_NREAL = 7;    // enabled edges (without padding)
 constexpr int HDR_WORDS = 16;
 
-enum Layout { LAYOUT_REG32 = 0, LAYOUT_REG64 = 1, LAYOUT_WIDE = 2 };
+enum Layout { LAYOUT_REG = 0, LAYOUT_WIDE = 1 };
 
-__host__ __device__ constexpr int layout_of(int N) {
-    return N <= 30 ? LAYOUT_REG32 : (N <= 60 ? LAYOUT_REG64 : LAYOUT_WIDE);
-}
-__host__ __device__ constexpr int slot_of(int layout, int p) {
-    return (layout == LAYOUT_REG64 && p >= 30) ? p + 2 : p;
-}
+__host__ __device__ constexpr int layout_of(int N) { return N <= 62 ? LAYOUT_REG : LAYOUT_WIDE; }
+__host__ __device__ constexpr int slot_of(int /*layout*/, int p) { return p; }
 // number of value slots the forward kernels hold per sample
 __host__ __device__ constexpr int n_slots(int layout, int N) {
-    return layout == LAYOUT_REG32 ? 32 : (layout == LAYOUT_REG64 ? 64 : N + 2);
+    return layout == LAYOUT_REG ? 64 : N + 2;
 }
-// slot of the constant 0 (the constant 1 is the next slot) in a half
-__host__ __device__ constexpr int zero_slot(int layout, int N, int half) {
-    return layout == LAYOUT_REG32 ? 30 : (layout == LAYOUT_REG64 ? (half ? 62 : 30) : N);
-}
-__host__ __device__ constexpr int half_of(int layout, int slot) {
-    return (layout == LAYOUT_REG64 && slot >= 32) ? 1 : 0;
+// slot of the constant 0 (the constant 1 is the next slot)
+__host__ __device__ constexpr int zero_slot(int layout, int N) {
+    return layout == LAYOUT_REG ? 62 : N;
 }
 
-// node record (8 words), record k describes position I + k:
-constexpr int REC_NLO = 0;    // edge pairs from the low half
-constexpr int REC_NHI = 1;    // edge pairs from the high half
-constexpr int REC_ACT = 2;
-constexpr int REC_AGG = 3;
-constexpr int REC_BIAS = 4;   // float
-constexpr int REC_RESP = 5;   // float
-constexpr int REC_SCALE = 6;  // float: 1 / in-degree for mean, else 1
-constexpr int REC_DST = 7;    // slot of the node
-constexpr int REC_WORDS = 8;
+// node record (16 words), record k describes position I + k.  The
+// aggregation and activation are folded into a few classes so the forward
+// branches little:
+//   aggregation class: SUM (sum, mean, and any node without incoming
+//   edges), PROD, MAX (max; min is stored as max over negated weights with
+//   the response negated, since min(t) = -max(-t) exactly);
+//   z = bias + response' * agg(terms), response' = response / in-degree for
+//   mean, -response for min, else response;
+//   activation class PL (identity, relu, abs): y = z if !(z <= 0), else
+//   (mask ? 0 : c * z) with c = 1 (identity), -1 (abs), 0 + mask (relu);
+//   EXPO (sigmoid, tanh, gaussian): e = 2^(c * u) with u = z (u = z*z and
+//   mask for the gaussian); y = mask ? e : ea + eb / (1 + e), with
+//   (c, ea, eb) = (-log2 e, 0, 1) sigmoid, (2 log2 e, 1, -2) tanh;
+//   SIN: y = sin z.
+constexpr int REC_CODE = 0;   // pairs | aggregation class << 16 | activation class << 18 | dst slot << 20
+constexpr int REC_BIAS = 1;   // float
+constexpr int REC_RESP = 2;   // float, response'
+constexpr int REC_C = 3;      // float
+constexpr int REC_EA = 4;     // float
+constexpr int REC_EB = 5;     // float
+constexpr int REC_MASK = 6;   // two words: 64-bit lane mask, all ones or zero
+constexpr int REC_PAIRS = 8;  // the node's first two edge pairs (8 words)
+constexpr int REC_WORDS = 16;
+constexpr int REC_INLINE_PAIRS = 2;
+enum AggClass { ACLS_SUM = 0, ACLS_PROD = 1, ACLS_MAX = 2 };
+enum ActClass { XCLS_PL = 0, XCLS_EXPO = 1, XCLS_SIN = 2 };
+__host__ __device__ constexpr uint32_t rec_code(int pairs, int acls, int xcls, int dst) {
+    return (uint32_t)pairs | ((uint32_t)acls << 16) | ((uint32_t)xcls << 18) |
+           ((uint32_t)dst << 20);
+}
 // edge (2 words): source slot, weight
 constexpr int EDGE_WORDS = 2;
 
 __host__ __device__ constexpr int round_up(int x, int m) { return (x + m - 1) / m * m; }
 
-// capacity in edges: the connections plus one padding edge per half per node
-__host__ __device__ constexpr int edge_cap(int N, int C) { return C + 2 * N; }
+// capacity of the overflow edge array: the connections plus one padding
+// edge per node
+__host__ __device__ constexpr int edge_cap(int N, int C) { return C + N; }
 
 // output slots: O words (padded to 8)
 __host__ __device__ constexpr int out_off() { return HDR_WORDS; }
 __host__ __device__ constexpr int rec_off(int O) { return HDR_WORDS + round_up(O, 8); }
 __host__ __device__ constexpr int edge_off(int N, int O) { return rec_off(O) + REC_WORDS * N; }
-// first edge index of record k (N words)
+// first overflow edge of record k (N words)
 __host__ __device__ constexpr int ebeg_off(int N, int C, int O) {
     return edge_off(N, O) + EDGE_WORDS * edge_cap(N, C);
 }

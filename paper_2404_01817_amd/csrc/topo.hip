@@ -315,32 +315,25 @@ __global__ __launch_bounds__(1024) void topo_kernel(TopoArgs a) {
     if (!ok) return;  // uniform
     // output slots: rank I + j holds key I + j
     if (t < O) prog[out_off() + t] = slot_of(L, s_pos[s_srow[I + t]]);
-    // owner of a computed row: incoming edges per half, padded to even counts
+    // owner of a computed row: in-degree, first in-edge (min source key),
+    // pairs after padding to an even count, overflow edges beyond the record
     const bool computed = t < N && s_key[t] >= 0 && s_pos[t] >= I;
-    int n_lo = 0, n_hi = 0, first_lo = -1, first_hi = -1;
+    int deg = 0, first = -1;
     if (computed) {
-        int klo = 0x7fffffff, khi = 0x7fffffff;
+        int kmin = 0x7fffffff;
         for (int k = s_inoff[t]; k < s_inoff[t + 1]; ++k) {
             const int c2 = in_list[k];
-            const int src = e_src[c2];
-            const int ks = s_key[src];
-            if (half_of(L, slot_of(L, s_pos[src]))) {
-                ++n_hi;
-                if (ks < khi) khi = ks, first_hi = c2;
-            } else {
-                ++n_lo;
-                if (ks < klo) klo = ks, first_lo = c2;
-            }
+            const int ks = s_key[e_src[c2]];
+            ++deg;
+            if (ks < kmin) kmin = ks, first = c2;
         }
     }
-    const int pad_lo = n_lo + (n_lo & 1), pad_hi = n_hi + (n_hi & 1);
-    __syncthreads();  // every owner has read s_deg / s_indeg of the sort phase
-    if (computed) {
-        s_indeg[t] = pad_lo;
-        s_deg[t] = pad_lo + pad_hi;
-    }
+    const int pairs = (deg + 1) >> 1;
+    const int over = pairs > REC_INLINE_PAIRS ? 2 * (pairs - REC_INLINE_PAIRS) : 0;
     __syncthreads();
-    // first edge of every position, in topological order; level starts
+    if (computed) s_deg[t] = over;
+    __syncthreads();
+    // first overflow edge of every position, in topological order; level starts
     {
         const int row = (t < nvalid) ? s_curi[t] : -1;
         const int cnt = (t >= I && t < nvalid) ? s_deg[row] : 0;
@@ -348,7 +341,7 @@ __global__ __launch_bounds__(1024) void topo_kernel(TopoArgs a) {
         const int eb = block_excl_scan(cnt, s_wave, &tot);
         if (t >= I && t < nvalid) {
             prog[ebeg_off(N, C, O) + (t - I)] = eb;
-            s_curo[row] = eb;  // edge begin by row
+            s_curo[row] = eb;  // overflow begin by row
         }
         if (t < nvalid) {
             const int lv = s_skey[row];
@@ -363,54 +356,78 @@ __global__ __launch_bounds__(1024) void topo_kernel(TopoArgs a) {
     const int eoff = edge_off(N, O);
     if (computed) {
         const int k = s_pos[t] - I;
-        const int eb = s_curo[t];
-        const int deg = n_lo + n_hi;
         const int r0 = rec_off(O) + REC_WORDS * k;
-        prog[r0 + REC_NLO] = pad_lo >> 1;
-        prog[r0 + REC_NHI] = pad_hi >> 1;
-        prog[r0 + REC_ACT] = act;
-        prog[r0 + REC_AGG] = agg;
+        const int ob = s_curo[t];
+        const int acls = deg == 0 ? ACLS_SUM
+                                  : (agg == AGG_PRODUCT ? ACLS_PROD
+                                                        : ((agg == AGG_MAX || agg == AGG_MIN)
+                                                               ? ACLS_MAX
+                                                               : ACLS_SUM));
+        // response folded with the mean's 1 / degree and min's sign
+        const float rp = deg == 0 ? resp
+                                  : (agg == AGG_MEAN ? resp * (1.0f / (float)deg)
+                                                     : (agg == AGG_MIN ? -resp : resp));
+        int xcls = XCLS_PL, mask = 0;
+        float cf = 1.0f, xa = 0.0f, xb = 0.0f;
+        if (act == ACT_ABS) cf = -1.0f;
+        if (act == ACT_RELU) cf = 0.0f, mask = -1;
+        if (act == ACT_SIGMOID) xcls = XCLS_EXPO, cf = -1.4426950216293335f, xa = 0.0f, xb = 1.0f;
+        if (act == ACT_TANH) xcls = XCLS_EXPO, cf = 2.885390043258667f, xa = 1.0f, xb = -2.0f;
+        if (act == ACT_GAUSS) xcls = XCLS_EXPO, cf = -1.4426950216293335f, mask = -1;
+        if (act == ACT_SIN) xcls = XCLS_SIN;
+        prog[r0 + REC_CODE] = (int32_t)rec_code(pairs, acls, xcls, slot_of(L, s_pos[t]));
         progf[r0 + REC_BIAS] = bias;
-        progf[r0 + REC_RESP] = resp;
-        progf[r0 + REC_SCALE] = (agg == AGG_MEAN && deg) ? 1.0f / (float)deg : 1.0f;
-        prog[r0 + REC_DST] = slot_of(L, s_pos[t]);
-        // neutral padding edge of each odd half
-        for (int h = 0; h < 2; ++h) {
-            const int n = h ? n_hi : n_lo;
-            if (!(n & 1)) continue;
-            const int e = eb + (h ? pad_lo : 0) + n;
+        progf[r0 + REC_RESP] = rp;
+        progf[r0 + REC_C] = cf;
+        progf[r0 + REC_EA] = xa;
+        progf[r0 + REC_EB] = xb;
+        prog[r0 + REC_MASK] = mask;
+        prog[r0 + REC_MASK + 1] = mask;
+        // unused inline edges: a harmless (constant slot, 0) pair
+        for (int j = 2 * pairs; j < 2 * REC_INLINE_PAIRS; ++j) {
+            prog[r0 + REC_PAIRS + 2 * j] = zero_slot(L, N);
+            progf[r0 + REC_PAIRS + 2 * j + 1] = 0.0f;
+        }
+        // neutral padding edge when the in-degree is odd
+        if (deg & 1) {
             int slot;
             float w = 1.0f;
             if (agg == AGG_SUM || agg == AGG_MEAN) {
-                slot = zero_slot(L, N, h);
+                slot = zero_slot(L, N);
             } else if (agg == AGG_PRODUCT) {
-                slot = zero_slot(L, N, h) + 1;
-            } else {
-                const int c2 = h ? first_hi : first_lo;
-                slot = slot_of(L, s_pos[e_src[c2]]);
-                w = conns[(size_t)c2 * 4 + 3];
+                slot = zero_slot(L, N) + 1;
+            } else {  // max / min: the first edge again (min stores -w)
+                slot = slot_of(L, s_pos[e_src[first]]);
+                w = conns[(size_t)first * 4 + 3];
+                if (agg == AGG_MIN) w = -w;
             }
-            prog[eoff + EDGE_WORDS * e] = slot;
-            progf[eoff + EDGE_WORDS * e + 1] = w;
+            const int widx = deg < 2 * REC_INLINE_PAIRS ? r0 + REC_PAIRS + 2 * deg
+                                                         : eoff + EDGE_WORDS * (ob + deg - 4);
+            prog[widx] = slot;
+            progf[widx + 1] = w;
         }
     }
-    // real edges: first edge of the destination's half + number of in-edges
-    // in that half with a smaller source key (keys are unique here)
+    // aggregation code and overflow begin by row for the edge writers
+    int *s_agg = s_deg;
+    if (computed) s_agg[t] = agg;
+    __syncthreads();
+    // real edges: index j = number of in-edges of the destination with a
+    // smaller source key (keys are unique here); j < 4 in the record, the
+    // rest in the overflow array
     for (int c = t; c < C; c += W) {
         const int s = e_src[c];
         if (s < 0) continue;
         const int d = e_dst[c];
-        const int sl = slot_of(L, s_pos[s]);
-        const int h = half_of(L, sl);
         const int ks = s_key[s];
         int j = 0;
-        for (int k = s_inoff[d]; k < s_inoff[d + 1]; ++k) {
-            const int s2 = e_src[in_list[k]];
-            j += (s_key[s2] < ks) && (half_of(L, slot_of(L, s_pos[s2])) == h);
-        }
-        const int e = s_curo[d] + (h ? s_indeg[d] : 0) + j;
-        prog[eoff + EDGE_WORDS * e] = sl;
-        progf[eoff + EDGE_WORDS * e + 1] = conns[(size_t)c * 4 + 3];
+        for (int k = s_inoff[d]; k < s_inoff[d + 1]; ++k) j += (s_key[e_src[in_list[k]]] < ks);
+        const int rd = rec_off(O) + REC_WORDS * (s_pos[d] - I);
+        const int widx = j < 2 * REC_INLINE_PAIRS ? rd + REC_PAIRS + 2 * j
+                                                   : eoff + EDGE_WORDS * (s_curo[d] + j - 4);
+        // min is stored as max over negated weights (negation is exact)
+        const float w = conns[(size_t)c * 4 + 3];
+        prog[widx] = slot_of(L, s_pos[s]);
+        progf[widx + 1] = s_agg[d] == AGG_MIN ? -w : w;
     }
 }
 
