@@ -37,6 +37,9 @@ def parse():
                     help="genomes of the workload the CPU oracle is timed on")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quiet", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="after the timed region, copy 256 MiB once (a plain copy kernel "
+                         "of known size, which calibrates HBM byte counters)")
     return ap.parse_args()
 
 
@@ -46,11 +49,13 @@ def log(args, *a):
 
 
 def program_bytes_read(O, n_valid, n_edges, I):
-    """Bytes of the program a forward must read once per genome: the 64-byte
-    header, the output slots, one 32-byte record per computed node and
-    8 bytes per enabled connection."""
+    """Algorithmic program bytes a forward reads once per genome: a 64-byte
+    header, 4 bytes per output slot, 16 bytes per computed node (bias,
+    response, activation and aggregation, edge count) and 8 bytes per enabled
+    connection (source, weight).  The stored records are larger (64 bytes,
+    with the first edges inline); this counts what the method needs."""
     n_comp = np.maximum(n_valid - I, 0)
-    return int((64 + 4 * O + 32 * n_comp + 8 * n_edges).sum())
+    return int((64 + 4 * O + 16 * n_comp + 8 * n_edges).sum())
 
 
 def main():
@@ -114,8 +119,7 @@ def main():
     value = units / (step_ms / 1e3)
 
     # algorithmic bytes of the forward launch
-    pw = neat.program_bytes(d) // 4 // pop.P
-    hdr = prog.view(pop.P, pw)[:, :8].cpu().numpy()
+    hdr = neat.program_headers(d, prog).cpu().numpy()
     st = status.cpu().numpy()
     n_bad = int((st != 0).sum())
     pbytes = program_bytes_read(pop.O, hdr[:, 0], hdr[:, 7], pop.I)  # valid nodes, edges
@@ -131,7 +135,7 @@ def main():
 
     # each forward variant on the same program, for the record
     variants = {}
-    for name, var in (("reg", neat.FWD_REG), ("lds", neat.FWD_LDS)):
+    for name, var in (("reg", neat.FWD_REG), ("reg2", neat.FWD_REG2), ("lds", neat.FWD_LDS)):
         try:
             t0e, t1e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             neat.forward(d, prog, tx, pop.B, outputs=out, variant=var)
@@ -143,6 +147,15 @@ def main():
             variants[name] = round(t0e.elapsed_time(t1e) / 5, 4)
         except neat.NeatError:
             variants[name] = None
+
+    if args.copy_probe:
+        src = torch.ones((64 << 20,), dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(args, "copy probe: 256 MiB read, 256 MiB written")
+        del src, dst
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -92,8 +92,19 @@ typedef struct {
 } neat_dims;
 
 /* Bytes of the opaque per-population program written by neat_topo_sort
- * (P genomes; each genome's part is 256-byte aligned).  0 on invalid dims. */
+ * (P genomes; each genome's part is 256-byte aligned, followed by a
+ * population part).  0 on invalid dims. */
 size_t neat_program_bytes(const neat_dims *dims);
+
+/* Bytes between consecutive genomes' parts of the program (genome g's part
+ * starts at g times this).  Each part begins with a diagnostic header of
+ * sixteen 32-bit words: [0] nodes in use (0 when rejected), [1] stored
+ * edges including padding, [2] status, [3] levels, [4] I, [5] O, [6] slot
+ * class (0..3, see NEAT_FWD_AUTO), [7] enabled edges, [8] value slots in use
+ * (the largest set of simultaneously live values; for N_max <= 62, where
+ * every genome fits the smallest class, the nodes in use).  0 on invalid
+ * dims. */
+size_t neat_program_stride(const neat_dims *dims);
 
 /*
  * Transformation stage (Section 3.3, "transformation"; encoding of Section
@@ -128,17 +139,23 @@ int neat_forward(const neat_dims *dims, const void *program, const float *inputs
                  int64_t input_genome_stride, int32_t B, float *outputs,
                  void *stream);
 
-/* Forward variants: how the lane-per-sample kernels keep the node values.
- * NEAT_FWD_AUTO picks one from N_max; the others exist for tuning. */
+/* Forward variants: where the lane-per-sample kernels keep the node values.
+ * The program build gives every genome a slot class from its largest set of
+ * simultaneously live values (<= 62, <= 126, <= 222 values in registers,
+ * more in LDS rows); NEAT_FWD_AUTO runs each class's genomes with that
+ * class's kernel, two samples per lane for the smallest class when B > 64.
+ * The others exist for tuning and testing. */
 #define NEAT_FWD_AUTO 0
-#define NEAT_FWD_REG 1 /* registers, node loop in assembly; needs N_max <= 62 */
-#define NEAT_FWD_LDS 2 /* LDS rows; any N_max */
+#define NEAT_FWD_REG 1  /* registers, one sample per lane (LDS rows for the LDS class) */
+#define NEAT_FWD_LDS 2  /* every genome in LDS rows */
+#define NEAT_FWD_REG2 3 /* as NEAT_FWD_REG, two samples per lane for the smallest class */
 
 /*
- * neat_forward with an explicit variant (NEAT_FWD_*); same arguments,
- * results equal within the fp32 parity tolerance (the variants may sum in a
- * different but fixed order).  Errors as neat_forward, plus NEAT_E_INVALID
- * for an unknown or inapplicable variant.
+ * neat_forward with an explicit variant (NEAT_FWD_*); same arguments.  All
+ * variants run the same operations in the same order and give identical
+ * bits.  Errors as neat_forward, plus NEAT_E_INVALID for an unknown variant
+ * and NEAT_E_TOO_LARGE when a genome's values do not fit in LDS (N_max
+ * beyond about 600 for genomes whose live set exceeds 222 values).
  */
 int neat_forward_ex(const neat_dims *dims, const void *program, const float *inputs,
                     int64_t input_genome_stride, int32_t B, float *outputs, int32_t variant,

@@ -11,7 +11,7 @@ from __future__ import annotations
 import ctypes
 from typing import Optional, Tuple
 
-from ._lib import FWD_AUTO, FWD_LDS, FWD_REG, Dims, NeatError, check, lib
+from ._lib import FWD_AUTO, FWD_LDS, FWD_REG, FWD_REG2, Dims, NeatError, check, lib
 
 __all__ = ["Dims", "NeatError", "dims_of", "program_bytes", "topo_sort", "forward",
            "forward_grid"]
@@ -48,6 +48,18 @@ def dims_of(nodes, conns, I: int, O: int) -> Dims:
 
 def program_bytes(dims: Dims) -> int:
     return int(lib().neat_program_bytes(ctypes.byref(dims)))
+
+
+def program_words_per_genome(dims: Dims) -> int:
+    """32-bit words between consecutive genomes' parts of the program."""
+    return int(lib().neat_program_stride(ctypes.byref(dims))) // 4
+
+
+def program_headers(dims: Dims, program):
+    """The diagnostic header words [P, 16] of every genome (device tensor
+    view; see neat_program_stride)."""
+    w = program_words_per_genome(dims)
+    return program[:dims.P * w].view(dims.P, w)[:, :16]
 
 
 def topo_sort(nodes, conns, I: int, O: int, program=None, stream=None,

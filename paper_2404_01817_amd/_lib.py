@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(PKG, "libneat.so")
 
 NEAT_OK = 0
 NEAT_PENDING = 1
-FWD_AUTO, FWD_REG, FWD_LDS = 0, 1, 2
+FWD_AUTO, FWD_REG, FWD_LDS, FWD_REG2 = 0, 1, 2, 3
 
 
 class NeatError(RuntimeError):
@@ -35,6 +35,7 @@ _lib = None
 _vp, _i32, _i64, _sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
 SIGNATURES = {
     "neat_program_bytes": (_sz, [ctypes.POINTER(Dims)]),
+    "neat_program_stride": (_sz, [ctypes.POINTER(Dims)]),
     "neat_topo_sort": (_i32, [ctypes.POINTER(Dims), _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "neat_forward": (_i32, [ctypes.POINTER(Dims), _vp, _vp, _i64, _i32, _vp, _vp]),
     "neat_forward_ex": (_i32, [ctypes.POINTER(Dims), _vp, _vp, _i64, _i32, _vp, _i32, _vp]),

@@ -79,7 +79,13 @@ const char *neat_strerror(int code) {
 
 size_t neat_program_bytes(const neat_dims *d) {
     if (check_dims(d) != NEAT_OK) return 0;
-    return (size_t)d->P * (size_t)neat::prog_words(d->N_max, d->C_max, d->O) * sizeof(int32_t);
+    return (size_t)(neat::pop_off(d->P, d->N_max, d->C_max, d->O) + neat::pop_words(d->P)) *
+           sizeof(int32_t);
+}
+
+size_t neat_program_stride(const neat_dims *d) {
+    if (check_dims(d) != NEAT_OK) return 0;
+    return (size_t)neat::prog_words(d->N_max, d->C_max, d->O) * sizeof(int32_t);
 }
 
 int neat_topo_sort(const neat_dims *d, const float *nodes, const float *conns, int32_t *order,
@@ -106,22 +112,27 @@ int neat_topo_sort(const neat_dims *d, const float *nodes, const float *conns, i
 static int forward_common(const neat_dims *d, const void *program, const float *inputs,
                           int64_t input_genome_stride, int32_t B, float *outputs, int variant,
                           bool grid, int32_t side, int64_t first, void *stream) {
-    if (variant == NEAT_FWD_AUTO) variant = neat::forward_default_variant(d->N_max);
-    if (variant != NEAT_FWD_REG && variant != NEAT_FWD_LDS)
+    if (variant < NEAT_FWD_AUTO || variant > NEAT_FWD_REG2)
         return fail(NEAT_E_INVALID, "unknown forward variant %d", variant);
-    if (variant == NEAT_FWD_REG && neat::layout_of(d->N_max) == neat::LAYOUT_WIDE)
-        return fail(NEAT_E_INVALID, "register variant needs N_max <= 62 (N_max = %d)", d->N_max);
-    const long long blocks = (long long)d->P * ((B + 63) / 64);
-    if (blocks * 64 >= (1ll << 32))
-        return fail(NEAT_E_INVALID, "P * B too large for one launch (%lld tiles)", blocks);
-    const size_t lds = neat::forward_launch_lds_bytes(d->P, B, d->N_max, d->I, variant, grid);
-    if (lds > max_lds_bytes())
-        return fail(NEAT_E_INVALID, "N_max=%d, I=%d need %zu B of LDS per workgroup, device allows %zu",
-                    d->N_max, d->I, lds, max_lds_bytes());
-    hipError_t e = neat::launch_forward(d->P, d->N_max, d->C_max, d->I, d->O,
-                                        (const int32_t *)program, inputs, input_genome_stride, B,
-                                        outputs, variant, grid, side, first, (hipStream_t)stream);
-    if (e != hipSuccess) return hip_fail(e, "forward launch");
+    const long long tiles = (long long)d->P * ((B + 63) / 64);
+    if (tiles >= (1ll << 31))
+        return fail(NEAT_E_INVALID, "P * B too large for one launch (%lld tiles)", tiles);
+    neat::FwdJob job{};
+    job.prog = (const int32_t *)program;
+    job.inputs = inputs;
+    job.outputs = outputs;
+    job.gstride = input_genome_stride;
+    job.first = first;
+    job.P = d->P, job.N = d->N_max, job.C = d->C_max, job.I = d->I, job.O = d->O, job.B = B;
+    job.side = grid ? side : 0;
+    std::vector<neat::FwdKernelLaunch> plan;
+    char err[256] = "";
+    int rc = neat::forward_plan(&job, 1, variant, max_lds_bytes(), plan, err, sizeof(err));
+    if (rc != NEAT_OK) return fail(rc, "%s", err);
+    for (const neat::FwdKernelLaunch &k : plan) {
+        hipError_t e = neat::forward_launch(k, nullptr, (hipStream_t)stream);
+        if (e != hipSuccess) return hip_fail(e, "forward launch");
+    }
     return NEAT_OK;
 }
 

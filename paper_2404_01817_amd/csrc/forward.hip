@@ -1,29 +1,41 @@
 // forward.hip -- the calculation stage (Section 3.3) over population x inputs.
 //
 // Mapping "lane per sample": a 64-lane wave evaluates one genome on a run of
-// 64-sample tiles, one sample per lane.  The genome's program is uniform
-// across the wave, so it is read with scalar loads and every branch on a
-// node's activation or aggregation is a scalar branch.  A workgroup holds up
-// to four waves working on the same genome, so they share the CU's scalar
-// cache.
+// sample tiles, one or two samples per lane.  The genome's program is
+// uniform across the wave, so it is read with scalar loads and every branch
+// on a node's activation or aggregation is a scalar branch.  A workgroup
+// holds up to four waves working on the same genome, so they share the
+// CU's scalar cache.
 //
-// Two stores for the value vector v of Section 3.3 (slots, see program.h):
-//   AsmStore  64 VGPRs per lane (v0..v63, layout REG, N_max <= 62); the node
-//             loop is the assembly of node_loop_asm.h, which indexes the
-//             registers in GPR-index mode with the program's uniform slots;
-//   LdsStore  one LDS row of 64 lanes per slot (any layout; rows are 256 B,
-//             so lane l of every row sits in bank l), node loop in C++.
-// Edges come in pairs (the program pads each node to an even count with a
-// neutral edge) and the first two pairs sit in the node's record, so the
-// inner loops have no per-edge tests.  The next record is fetched while the
-// current node computes.
+// Value stores (the value vector v of Section 3.3, slots and slot classes
+// in program.h), one kernel per store:
+//   R64    v0..v63, one sample per lane            (class R64)
+//   R64X2  v0..v63 and v64..v127, two samples       (class R64)
+//   R128   v0..v127, one sample                     (class R128)
+//   R224   v0..v223, one sample                     (class R224)
+//   LDS    one LDS row of 64 lanes per slot         (class LDS; any class
+//          when chosen explicitly)
+// The register stores run one assembly block per tile (node_loop_asm.h):
+// inputs from the LDS staging area into the registers, the DMA of the next
+// tile's inputs, the node loop in GPR-index mode with the program's uniform
+// slots, and the outputs into an LDS output area, which the C++ code then
+// writes to HBM with coalesced 16-byte stores.  The LDS store runs the same
+// node operations in C++.
+//
+// Work units.  A launch covers one or more populations ("items"); item j
+// contributes P_j x groups_j units, unit (i, group) being the group's waves
+// on the i-th genome of the item's list for the kernel's class (the class
+// list the transformation wrote, or all genomes).  Units past the list's
+// length exit at once.  Workgroups are remapped so consecutive units share
+// an XCD (workgroups are dealt to the 8 XCDs round robin).
 //
 // Inputs of the next tile are copied HBM -> LDS by the DMA path of
 // global_load_lds (16-byte pieces when aligned) while the current tile
-// computes; each lane then moves its own sample's inputs into v.  Outputs
-// are stored from v directly.  Workgroups are remapped so consecutive
-// genomes share an XCD (workgroups are dealt to the 8 XCDs round robin).
+// computes; each lane then moves its own samples' inputs into v.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
 
 #include "act.h"
 #include "launch.h"
@@ -34,118 +46,24 @@
 namespace neat {
 namespace {
 
-constexpr int TILE = 64;
-constexpr int WAVES = 4;  // waves per workgroup, all on one genome
+constexpr int WAVE = 64;
 
 typedef float f32x32 __attribute__((ext_vector_type(32)));
-typedef int i32x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef int i32x16 __attribute__((ext_vector_type(16)));
 typedef const __attribute__((address_space(4))) int32_t cprog_t;
-typedef const __attribute__((address_space(4))) i32x8 cint8_t;  // unused
 typedef const __attribute__((address_space(4))) i32x16 cint16_t;
+typedef const __attribute__((address_space(4))) FwdItem citem_t;
 typedef __attribute__((address_space(1))) const void gvoid;
 typedef __attribute__((address_space(3))) void lvoid;
 
 __device__ __forceinline__ float fbits(int b) { return __int_as_float(b); }
 
-// ---------------------------------------------------------------- stores
-struct LdsStore {
-    float *col;  // this lane's column: slot s at col[s * TILE]
-    int layout;
-    __device__ __forceinline__ float get_lo(int s) const { return col[s * TILE]; }
-    __device__ __forceinline__ float get_hi(int s) const { return col[s * TILE]; }
-    template <bool HI>
-    __device__ __forceinline__ void set(int s, float x) { col[s * TILE] = x; }
-    __device__ __forceinline__ void init(int N) {
-        const int z0 = zero_slot(layout, N);
-        col[z0 * TILE] = 0.0f;
-        col[(z0 + 1) * TILE] = 1.0f;
-    }
-};
-
-// Value vector pinned to v0..v63 for the assembly node loop
-// (node_loop_asm.h).  Slots are absolute (0..63); M0, which the GPR-index
-// mode overwrites, is saved and restored around every access.
-struct AsmStore {
-    f32x32 lo, hi;
-    __device__ __forceinline__ float get(int s) const {
-        float x;
-        asm volatile(
-            "s_mov_b32 s91, m0\n\t"
-            "s_set_gpr_idx_on %3, gpr_idx(SRC0)\n\t"
-            "v_mov_b32_e32 %0, v0\n\t"
-            "s_set_gpr_idx_off\n\t"
-            "s_mov_b32 m0, s91"
-            : "=&v"(x)
-            : "{v[0:31]}"(lo), "{v[32:63]}"(hi), "s"(s)
-            : "s91");
-        return x;
-    }
-    __device__ __forceinline__ float get_lo(int s) const { return get(s); }
-    __device__ __forceinline__ float get_hi(int s) const { return get(s); }
-    template <bool HI>
-    __device__ __forceinline__ void set(int s, float x) {
-        asm volatile(
-            "s_mov_b32 s91, m0\n\t"
-            "s_set_gpr_idx_on %2, gpr_idx(DST)\n\t"
-            "v_mov_b32_e32 v0, %3\n\t"
-            "s_set_gpr_idx_off\n\t"
-            "s_mov_b32 m0, s91"
-            : "+{v[0:31]}"(lo), "+{v[32:63]}"(hi)
-            : "s"(s), "v"(x)
-            : "s91");
-    }
-    __device__ __forceinline__ void init(int /*N*/) {
-        set<true>(62, 0.0f);
-        set<true>(63, 1.0f);
-    }
-    // all computed nodes of the genome (node_loop_asm.h)
-    __device__ __forceinline__ void run(const int32_t *rec, const int32_t *edg, int n) {
-        asm volatile(NEAT_NODE_LOOP_ASM
-                     : "+{v[0:31]}"(lo), "+{v[32:63]}"(hi)
-                     : [rec] "s"(rec), [edg] "s"(edg), [n] "s"(n)
-                     : NEAT_NODE_LOOP_CLOBBERS);
-    }
-};
-
-// ---------------------------------------------------------------- nodes (C++)
-// One term w * v[slot] combined into acc (class ACLS); NaN terms of a max
-// are remembered in nan (the hardware max ignores NaN).
-template <int ACLS, class Store>
-__device__ __forceinline__ void combine(float &acc, float &nan, int slot, float w, const Store &v) {
-    const float x = v.get_lo(slot);
-    if (ACLS == ACLS_SUM) {
-        acc = fmaf(w, x, acc);
-    } else if (ACLS == ACLS_PROD) {
-        acc *= w * x;
-    } else {
-        const float t = w * x;
-        acc = fmaxf(acc, t);
-        nan = (t != t) ? t : nan;
-    }
-}
-
-// pairs edge pairs: the first two from the record (r), then the overflow
-// array from e, four words per pair.
-template <int ACLS, class Store>
-__device__ __forceinline__ float aggregate(const i32x16 &r, cprog_t *e, int pairs,
-                                           const Store &v) {
-    float acc = ACLS == ACLS_SUM ? 0.0f : (ACLS == ACLS_PROD ? 1.0f : -__builtin_inff());
-    float nan = 0.0f;
-#pragma unroll
-    for (int p = 0; p < REC_INLINE_PAIRS; ++p) {
-        if (p < pairs) {
-            combine<ACLS>(acc, nan, r[REC_PAIRS + 4 * p], fbits(r[REC_PAIRS + 4 * p + 1]), v);
-            combine<ACLS>(acc, nan, r[REC_PAIRS + 4 * p + 2], fbits(r[REC_PAIRS + 4 * p + 3]),
-                          v);
-        }
-    }
-    for (int p = 0; p < pairs - REC_INLINE_PAIRS; ++p) {
-        combine<ACLS>(acc, nan, e[4 * p], fbits(e[4 * p + 1]), v);
-        combine<ACLS>(acc, nan, e[4 * p + 2], fbits(e[4 * p + 3]), v);
-    }
-    if (ACLS == ACLS_MAX) acc = (nan != nan) ? nan : acc;
-    return acc;
+// NaN-propagating maximum of three (IEEE 754-2019 maximum)
+__device__ __forceinline__ float maximum3(float a, float b, float c) {
+    float r;
+    asm volatile("v_maximum3_f32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    return r;
 }
 
 // Lane select with a uniform 64-bit mask (all ones or zero): mask ? b : a.
@@ -155,9 +73,113 @@ __device__ __forceinline__ float sel_mask(float a, float b, unsigned long long m
     return r;
 }
 
-template <class Store>
-__device__ __forceinline__ void run_program(cprog_t *prog, int N, int O, int I, int /*layout*/,
-                                            Store &v) {
+// ---------------------------------------------------------------- stores
+struct LdsStore {
+    static constexpr int SPL = 1;
+    float *col;  // this lane's column: slot s at col[s * WAVE]
+    template <int H>
+    __device__ __forceinline__ float get(int s) const {
+        return col[s * WAVE];
+    }
+    template <int H>
+    __device__ __forceinline__ void set(int s, float x) {
+        col[s * WAVE] = x;
+    }
+    __device__ __forceinline__ void init(int zs) {
+        col[zs * WAVE] = 0.0f;
+        col[(zs + 1) * WAVE] = 1.0f;
+    }
+};
+
+// Register stores: one tile block of node_loop_asm.h per tile.  Operands as
+// documented there; every value register lives only inside the block.
+#define NEAT_TILE_OPERANDS                                                               \
+    [rec] "s"(rec), [edg] "s"(edg), [n] "s"(n), [zs] "s"(zs), [ni] "s"(ni), [dm0] "s"(dm0),  \
+        [dn] "s"(dn), [dvec] "s"(dvec), [dsrc] "s"(dsrc), [lane] "v"(lane),                 \
+        [outs] "s"(outs), [no] "s"(no), [om0] "s"(om0)
+#define NEAT_TILE_FN(TILE, CLOB)                                                          \
+    __device__ __forceinline__ static void tile(const int32_t *rec, const int32_t *edg,   \
+                                                int n, int zs, int ni, unsigned dm0,      \
+                                                int dn, int dvec, const float *dsrc,      \
+                                                unsigned lane, const int32_t *outs, int no, \
+                                                unsigned om0) {                           \
+        n = __builtin_amdgcn_readfirstlane(n);                                            \
+        zs = __builtin_amdgcn_readfirstlane(zs);                                          \
+        ni = __builtin_amdgcn_readfirstlane(ni);                                          \
+        no = __builtin_amdgcn_readfirstlane(no);                                          \
+        dm0 = __builtin_amdgcn_readfirstlane(dm0);                                        \
+        om0 = __builtin_amdgcn_readfirstlane(om0);                                        \
+        dn = __builtin_amdgcn_readfirstlane(dn);                                          \
+        dvec = __builtin_amdgcn_readfirstlane(dvec);                                      \
+        asm volatile(TILE : : NEAT_TILE_OPERANDS : CLOB, "memory");                     \
+    }
+
+template <int K>
+struct AsmTile;
+template <>
+struct AsmTile<KIND_R64> {
+    static constexpr int SPL = 1;
+    NEAT_TILE_FN(NEAT_TILE_S1_64, NEAT_CLOB_S1_64)
+};
+template <>
+struct AsmTile<KIND_R64X2> {
+    static constexpr int SPL = 2;
+    NEAT_TILE_FN(NEAT_TILE_S2_64, NEAT_CLOB_S2_64)
+};
+template <>
+struct AsmTile<KIND_R128> {
+    static constexpr int SPL = 1;
+    NEAT_TILE_FN(NEAT_TILE_S1_128, NEAT_CLOB_S1_128)
+};
+template <>
+struct AsmTile<KIND_R224> {
+    static constexpr int SPL = 1;
+    NEAT_TILE_FN(NEAT_TILE_S1_224, NEAT_CLOB_S1_224)
+};
+
+// ---------------------------------------------------------------- nodes (C++)
+// The LDS store's node loop: the operations of node_loop_asm.h in the same
+// order, so both give identical bits.
+template <int ACLS>
+__device__ __forceinline__ void pair(float &acc, bool first, int s0, float w0, int s1, float w1,
+                                     const LdsStore &v) {
+    const float x0 = v.get<0>(s0), x1 = v.get<0>(s1);
+    if (ACLS == ACLS_SUM) {
+        acc = first ? x0 * w0 : fmaf(x0, w0, acc);
+        acc = fmaf(x1, w1, acc);
+    } else if (ACLS == ACLS_PROD) {
+        if (first) {
+            acc = x0 * w0;
+            acc = acc * (x1 * w1);
+        } else {
+            const float ta = x0 * w0, tb = x1 * w1;
+            acc = acc * ta;
+            acc = acc * tb;
+        }
+    } else {
+        const float ta = x0 * w0, tb = x1 * w1;
+        acc = first ? maximum3(ta, tb, tb) : maximum3(acc, ta, tb);
+    }
+}
+
+// pairs (>= 1) edge pairs: the first two from the record r, then the
+// overflow array from e, four words per pair.
+template <int ACLS>
+__device__ __forceinline__ float aggregate(const i32x16 &r, cprog_t *e, int pairs,
+                                           const LdsStore &v) {
+    float acc = 0.0f;
+    pair<ACLS>(acc, true, r[REC_PAIRS], fbits(r[REC_PAIRS + 1]), r[REC_PAIRS + 2],
+               fbits(r[REC_PAIRS + 3]), v);
+    if (pairs > 1)
+        pair<ACLS>(acc, false, r[REC_PAIRS + 4], fbits(r[REC_PAIRS + 5]), r[REC_PAIRS + 6],
+                   fbits(r[REC_PAIRS + 7]), v);
+    for (int p = 0; p < pairs - REC_INLINE_PAIRS; ++p)
+        pair<ACLS>(acc, false, e[4 * p], fbits(e[4 * p + 1]), e[4 * p + 2], fbits(e[4 * p + 3]),
+                   v);
+    return acc;
+}
+
+__device__ __forceinline__ void run_program(cprog_t *prog, int N, int O, int I, LdsStore &v) {
     const int ncomp = prog[HDR_NVALID] - I;
     if (ncomp <= 0) return;
     cprog_t *rec = prog + rec_off(O);
@@ -174,56 +196,42 @@ __device__ __forceinline__ void run_program(cprog_t *prog, int N, int O, int I, 
         // next record (the record array has room for N records)
         const i32x16 rn = *(cint16_t *)(rec + REC_WORDS * (k + 1));
         float a;
-        if (acls == ACLS_SUM) a = aggregate<ACLS_SUM>(r, e, pairs, v);
-        else if (acls == ACLS_PROD) a = aggregate<ACLS_PROD>(r, e, pairs, v);
-        else a = aggregate<ACLS_MAX>(r, e, pairs, v);
+        if (acls == ACLS_PROD) a = aggregate<ACLS_PROD>(r, e, pairs, v);
+        else if (acls == ACLS_MAX) a = aggregate<ACLS_MAX>(r, e, pairs, v);
+        else a = pairs == 0 ? 0.0f : aggregate<ACLS_SUM>(r, e, pairs, v);
         if (pairs > REC_INLINE_PAIRS) e += 4 * (pairs - REC_INLINE_PAIRS);
         const float z = fmaf(resp, a, bias);
         float y;
-        if (xcls == XCLS_PL) {
-            // identity, abs, relu: z above 0 (or NaN) passes, else c z or 0
-            y = !(z <= 0.0f) ? z : sel_mask(z * cf, 0.0f, mask);
-        } else if (xcls == XCLS_EXPO) {
+        if (xcls == XCLS_EXPO) {
             // sigmoid, tanh: ea + eb / (1 + 2^(c z)); gaussian: 2^(c z z)
-            const float ex = exp2_hw(cf * sel_mask(z, z * z, mask));
+            const float ex = exp2_hw(sel_mask(z, z * z, mask) * cf);
             y = sel_mask(fmaf(eb, rcp_hw(1.0f + ex), ea), ex, mask);
-        } else {
+        } else if (xcls == XCLS_SIN) {
             y = act_sin(z);
+        } else {
+            // identity, abs, relu: maximum(z, mask ? 0 : c z)
+            const float t = sel_mask(z * cf, 0.0f, mask);
+            y = maximum3(z, t, t);
         }
-        v.template set<false>(dst, y);
+        v.set<0>(dst, y);
         r = rn;
     }
 }
 
-__device__ __forceinline__ void run_program(cprog_t *prog, int N, int O, int I, int /*layout*/,
-                                            AsmStore &v) {
-    const int ncomp = prog[HDR_NVALID] - I;
-    const int32_t *p = (const int32_t *)prog;
-    v.run(p + rec_off(O), p + edge_off(N, O), ncomp > 0 ? ncomp : 0);
-}
 
 // ---------------------------------------------------------------- tiles
-struct FwdArgs {
-    const int32_t *prog;
-    const float *inputs;
-    float *outputs;
-    long long gstride;  // floats between genomes' input blocks (0 = shared)
-    long long first;    // grid mode: first query
-    int N, C, I, O, B, tiles, tpw, chunks, wpg, groups, prog_words, side, vec4, layout;
-};
-
 // Workgroup b is dealt to XCD b % 8; give each XCD a contiguous range.
-__device__ __forceinline__ int xcd_item(unsigned b, unsigned n) {
+__device__ __forceinline__ long long xcd_item(unsigned b, unsigned n) {
     const unsigned x = b & 7u, q = b >> 3, per = n >> 3, rem = n & 7u;
-    return (int)(x * per + (x < rem ? x : rem) + q);
+    return (long long)(x * per + (x < rem ? x : rem) + q);
 }
 
 // Issue the DMA of n consecutive floats src[0..n) into lds[0..n).
 __device__ __forceinline__ void dma_inputs(const float *src, float *lds, int n, int vec4) {
-    const int lane = (int)(threadIdx.x & (TILE - 1));
+    const int lane = (int)(threadIdx.x & (WAVE - 1));
     if (vec4) {
         const int n4 = n >> 2;
-        for (int c = 0; c < n4; c += TILE)
+        for (int c = 0; c < n4; c += WAVE)
             if (c + lane < n4)
                 __builtin_amdgcn_global_load_lds((gvoid *)(src + 4 * (c + lane)),
                                                  (lvoid *)(lds + 4 * c), 16, 0, 0);
@@ -232,7 +240,7 @@ __device__ __forceinline__ void dma_inputs(const float *src, float *lds, int n, 
             __builtin_amdgcn_global_load_lds((gvoid *)(src + 4 * n4 + lane),
                                              (lvoid *)(lds + 4 * n4), 4, 0, 0);
     } else {
-        for (int c = 0; c < n; c += TILE)
+        for (int c = 0; c < n; c += WAVE)
             if (c + lane < n)
                 __builtin_amdgcn_global_load_lds((gvoid *)(src + c + lane), (lvoid *)(lds + c), 4,
                                                  0, 0);
@@ -246,99 +254,222 @@ __device__ __forceinline__ void wait_dma() {
     __builtin_amdgcn_wave_barrier();
 }
 
-template <class Store>
-__device__ __forceinline__ void place_inputs(Store &v, const float *cur, int I, int /*layout*/,
-                                             int lane) {
-    for (int i = 0; i < I; ++i) v.template set<false>(i, cur[lane * I + i]);  // slot i
+// Grid-point coordinate -1 + 2 i / (side - 1).
+__device__ __forceinline__ float grid_coord(int i, int side) {
+    return (float)(2 * i - (side - 1)) / (float)(side - 1);
 }
 
-template <class Store>
+template <int H, class Store>
 __device__ __forceinline__ void place_grid(Store &v, long long q, int side) {
     const int pts = side * side;
     const int p1 = (int)(q / pts), p2 = (int)(q - (long long)p1 * pts);
-    const float den = (float)(side - 1);
-    v.template set<false>(0, (float)(2 * (p1 % side) - (side - 1)) / den);
-    v.template set<false>(1, (float)(2 * (p1 / side) - (side - 1)) / den);
-    v.template set<false>(2, (float)(2 * (p2 % side) - (side - 1)) / den);
-    v.template set<false>(3, (float)(2 * (p2 / side) - (side - 1)) / den);
-    v.template set<false>(4, 1.0f);
+    v.template set<H>(0, grid_coord(p1 % side, side));
+    v.template set<H>(1, grid_coord(p1 / side, side));
+    v.template set<H>(2, grid_coord(p2 % side, side));
+    v.template set<H>(3, grid_coord(p2 / side, side));
+    v.template set<H>(4, 1.0f);
 }
 
-// stage: this wave's input staging area (2 x TILE x I floats, unused in GRID)
-template <class Store, bool GRID>
-__device__ __forceinline__ void forward_body(const FwdArgs &a, float *stage, Store &v) {
-    const int lane = (int)(threadIdx.x & (TILE - 1));
-    const int wave = (int)(threadIdx.x / TILE);
-    const int grp = xcd_item(blockIdx.x, gridDim.x);
-    const int g = grp / a.groups;
-    const int chunk = (grp - g * a.groups) * a.wpg + wave;
-    if (wave >= a.wpg || chunk >= a.chunks) return;
-    const int t0 = chunk * a.tpw;
-    const int t1 = min(a.tiles, t0 + a.tpw);
-    const int N = a.N, I = a.I, O = a.O, B = a.B, L = a.layout;
-    cprog_t *prog = (cprog_t *)(a.prog + (size_t)g * a.prog_words);
-    float *out_g = a.outputs + (size_t)g * B * O;
-    if (t0 >= t1) return;
+template <int H, class Store>
+__device__ __forceinline__ void store_outputs(const Store &v, cprog_t *prog, float *o, int O) {
+    for (int j = 0; j < O; ++j) o[j] = v.template get<H>(prog[out_off() + j]);
+}
 
+// LDS byte address of a pointer into the workgroup's LDS.
+__device__ __forceinline__ unsigned lds_addr(const float *p) {
+    return (unsigned)(uintptr_t)(const __attribute__((address_space(3))) float *)p;
+}
+
+// Copy n floats of a tile's outputs from the LDS output area to HBM
+// (16-byte pieces when the destination allows).
+__device__ __forceinline__ void flush_outputs(const float *ostage, float *dst, int n) {
+    const int lane = (int)(threadIdx.x & (WAVE - 1));
+    int c0 = 0;
+    if (((uintptr_t)dst & 15) == 0) {
+        const int n4 = n >> 2;
+        for (int c = lane; c < n4; c += WAVE)
+            reinterpret_cast<float4 *>(dst)[c] = reinterpret_cast<const float4 *>(ostage)[c];
+        c0 = 4 * n4;
+    }
+    for (int c = c0 + lane; c < n; c += WAVE) dst[c] = ostage[c];
+}
+
+// Chunk range [t0, t1) of this wave in a unit, or false when it has none.
+__device__ __forceinline__ bool wave_tiles(citem_t *it, int grp, int *t0, int *t1) {
+    // the wave index is uniform; say so, so everything derived stays scalar
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE));
+    const int wpg = it->wpg;
+    const int chunk = grp * wpg + wave;
+    if (wave >= wpg || chunk >= it->chunks) return false;
+    *t0 = chunk * it->tpw;
+    *t1 = min(it->tiles, *t0 + it->tpw);
+    return *t0 < *t1;
+}
+
+// Rejected genome: NaN outputs for the wave's samples.
+__device__ __forceinline__ void fill_nan(float *out_g, int first, int end, int O) {
+    const int lane = (int)(threadIdx.x & (WAVE - 1));
+    for (int e = first * O + lane; e < end * O; e += WAVE) out_g[e] = __builtin_nanf("");
+}
+
+// The waves of one unit with a register store: genome g, this wave's tiles.
+// area: the wave's LDS (input staging TS x I floats, then output staging
+// TS x O floats).
+template <int K, bool GRID>
+__device__ __forceinline__ void forward_unit_reg(citem_t *it, int g, int grp, float *area,
+                                                 int stage_floats) {
+    constexpr int SPL = AsmTile<K>::SPL;
+    constexpr int TS = WAVE * SPL;  // samples per tile
+    int t0, t1;
+    if (!wave_tiles(it, grp, &t0, &t1)) return;
+    const unsigned lane = threadIdx.x & (WAVE - 1);
+    const int N = it->N, I = it->I, O = it->O, B = it->B, side = GRID ? it->side : 0;
+    cprog_t *prog = (cprog_t *)(it->prog + (size_t)g * it->prog_words);
+    float *out_g = it->outputs + (size_t)g * B * O;
     if (prog[HDR_STATUS] != 0) {
-        const int e1 = min(B, t1 * TILE) * O;
-        for (int e = t0 * TILE * O + lane; e < e1; e += TILE) out_g[e] = __builtin_nanf("");
+        fill_nan(out_g, t0 * TS, min(B, t1 * TS), O);
         return;
     }
-
-    const float *in_g = GRID ? nullptr : a.inputs + (size_t)g * a.gstride;
-    float *buf0 = stage, *buf1 = stage + TILE * I;
-    if (!GRID)
-        dma_inputs(in_g + (size_t)t0 * TILE * I, buf0, min(TILE, B - t0 * TILE) * I, a.vec4);
-    v.init(N);
+    const int32_t *p = (const int32_t *)prog;
+    const int32_t *rec = p + rec_off(O), *edg = p + edge_off(N, O), *outs = p + out_off();
+    const int ncomp = max(prog[HDR_NVALID] - I, 0);
+    const int zs = zero_slot(prog[HDR_CLASS], N);
+    float *istage = area, *ostage = area + stage_floats;
+    const unsigned ibase = lds_addr(istage), obase = lds_addr(ostage);
+    const float *in_g = GRID ? nullptr : it->inputs + (size_t)g * it->gstride;
+    const int vec4 = it->vec4;
+    if (!GRID) dma_inputs(in_g + (size_t)t0 * TS * I, istage, min(TS, B - t0 * TS) * I, vec4);
 
     for (int t = t0; t < t1; ++t) {
-        const int nb = min(TILE, B - t * TILE);
         if (GRID) {
-            place_grid(v, a.first + (long long)t * TILE + lane, a.side);
+            // grid queries: the five inputs of each of the lane's samples
+            for (int h = 0; h < SPL; ++h) {
+                const long long q = it->first + (long long)t * TS + h * WAVE + lane;
+                const int pts = side * side;
+                const int p1 = (int)(q / pts), p2 = (int)(q - (long long)p1 * pts);
+                float *x = istage + (h * WAVE + lane) * 5;
+                x[0] = grid_coord(p1 % side, side);
+                x[1] = grid_coord(p1 / side, side);
+                x[2] = grid_coord(p2 % side, side);
+                x[3] = grid_coord(p2 / side, side);
+                x[4] = 1.0f;
+            }
         } else {
             wait_dma();
-            place_inputs(v, ((t - t0) & 1) ? buf1 : buf0, I, L, lane);
+        }
+        if (t > t0) flush_outputs(ostage, out_g + (size_t)(t - 1) * TS * O, TS * O);
+        int dn = 0, dvec = 0;
+        const float *dsrc = in_g;
+        if (!GRID && t + 1 < t1) {
+            const int nf = min(TS, B - (t + 1) * TS) * I;
+            dvec = (vec4 && (nf & 3) == 0) ? 1 : 0;
+            dn = dvec ? nf >> 2 : nf;
+            dsrc = in_g + (size_t)(t + 1) * TS * I;
+        }
+        AsmTile<K>::tile(rec, edg, ncomp, zs, I, ibase, dn, dvec, dsrc, lane, outs, O, obase);
+    }
+    flush_outputs(ostage, out_g + (size_t)(t1 - 1) * TS * O, (min(B, t1 * TS) - (t1 - 1) * TS) * O);
+}
+
+// The waves of one unit with the LDS store.  stage: the wave's input
+// staging area (TS x I floats; unused for grid items).
+template <bool GRID>
+__device__ __forceinline__ void forward_unit_lds(citem_t *it, int g, int grp, float *stage,
+                                                 LdsStore &v) {
+    constexpr int TS = WAVE;
+    int t0, t1;
+    if (!wave_tiles(it, grp, &t0, &t1)) return;
+    const int lane = (int)(threadIdx.x & (WAVE - 1));
+    const int N = it->N, I = it->I, O = it->O, B = it->B, side = GRID ? it->side : 0;
+    cprog_t *prog = (cprog_t *)(it->prog + (size_t)g * it->prog_words);
+    float *out_g = it->outputs + (size_t)g * B * O;
+    if (prog[HDR_STATUS] != 0) {
+        fill_nan(out_g, t0 * TS, min(B, t1 * TS), O);
+        return;
+    }
+    const float *in_g = GRID ? nullptr : it->inputs + (size_t)g * it->gstride;
+    const int vec4 = it->vec4;
+    if (!GRID) dma_inputs(in_g + (size_t)t0 * TS * I, stage, min(TS, B - t0 * TS) * I, vec4);
+    v.init(zero_slot(prog[HDR_CLASS], N));
+    for (int t = t0; t < t1; ++t) {
+        const int nb = min(TS, B - t * TS);
+        if (GRID) {
+            place_grid<0>(v, it->first + (long long)t * TS + lane, side);
+        } else {
+            wait_dma();
+            for (int i = 0; i < I; ++i) v.set<0>(i, stage[lane * I + i]);
             if (t + 1 < t1) {
-                // every lane has read its inputs before the other buffer refills
+                // every lane has read its inputs before the buffer refills
                 __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
                 __builtin_amdgcn_wave_barrier();
-                dma_inputs(in_g + (size_t)(t + 1) * TILE * I, ((t - t0) & 1) ? buf0 : buf1,
-                           min(TILE, B - (t + 1) * TILE) * I, a.vec4);
+                dma_inputs(in_g + (size_t)(t + 1) * TS * I, stage, min(TS, B - (t + 1) * TS) * I,
+                           vec4);
             }
         }
-        run_program(prog, N, O, I, L, v);
-        if (lane < nb) {
-            float *o = out_g + (size_t)(t * TILE + lane) * O;
-            for (int j = 0; j < O; ++j) {
-                const int s = prog[out_off() + j];
-                o[j] = v.get_lo(s);
-            }
-        }
+        run_program(prog, N, O, I, v);
+        if (lane < nb) store_outputs<0>(v, prog, out_g + (size_t)(t * TS + lane) * O, O);
     }
 }
 
-template <bool GRID>
-__global__ __launch_bounds__(TILE *WAVES) void forward_asm_kernel(FwdArgs a) {
-    extern __shared__ float smem[];
-    AsmStore v;
-    const size_t stage = GRID ? 0 : (size_t)2 * TILE * a.I;
-    forward_body<AsmStore, GRID>(a, smem + (threadIdx.x / TILE) * stage, v);
+// Item holding unit u (items sorted by unit0; the first has unit0 = 0).
+__device__ __forceinline__ citem_t *find_item(const FwdItem *table, int n, long long u) {
+    citem_t *items = (citem_t *)table;
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (items[mid].unit0 <= u) lo = mid;
+        else hi = mid - 1;
+    }
+    return items + lo;
 }
 
-template <bool GRID>
-__global__ __launch_bounds__(TILE *WAVES) void forward_lds_kernel(FwdArgs a) {
-    extern __shared__ float smem[];
-    const size_t stage = GRID ? 0 : (size_t)2 * TILE * a.I;
-    const size_t rows = (size_t)n_slots(a.layout, a.N) * TILE;
-    float *base = smem + (threadIdx.x / TILE) * (stage + rows);
-    LdsStore v;
-    v.col = base + stage + (threadIdx.x & (TILE - 1));
-    v.layout = a.layout;
-    forward_body<LdsStore, GRID>(a, base, v);
+// The launch argument in the kernarg segment (FwdLaunch is the kernel's only
+// argument, so it sits at offset 0; its inline item is its first member).
+__device__ __forceinline__ const __attribute__((address_space(4))) FwdLaunch *launch_arg() {
+    return (const __attribute__((address_space(4))) FwdLaunch *)
+        __builtin_amdgcn_kernarg_segment_ptr();
 }
 
-int choose_chunks(int P, int tiles, int *tpw) {
+// One unit: find its item and genome, then run the unit's waves with a
+// fresh value store (nothing carries over from one unit to the next).
+template <int K, bool GRID>
+__device__ __forceinline__ void run_unit(long long u, float *wave_area) {
+    const auto *L = launch_arg();
+    citem_t *it = L->items ? find_item(L->items, L->n_items, u) : (citem_t *)&L->one;
+    const long long local = u - it->unit0;
+    const int groups = it->groups;
+    const int i = (int)(local / groups), grp = (int)(local - (long long)i * groups);
+    int g = i;
+    const int cls = it->cls;
+    if (cls >= 0) {
+        cprog_t *pop = (cprog_t *)it->pop;
+        if (i >= pop[POP_COUNT + cls]) return;
+        g = pop[POP_IDS + pop[POP_BEGIN + cls] + i];
+    }
+    if constexpr (K == KIND_LDS) {
+        LdsStore v;
+        v.col = wave_area + L->stage_floats + (threadIdx.x & (WAVE - 1));
+        forward_unit_lds<GRID>(it, g, grp, wave_area, v);
+    } else {
+        forward_unit_reg<K, GRID>(it, g, grp, wave_area, L->stage_floats);
+    }
+}
+
+// PERSIST: a grid smaller than the unit count, each workgroup looping.
+// GRID: CPPN grid queries generated in the kernel instead of read inputs.
+template <int K, bool PERSIST, bool GRID>
+__global__ __launch_bounds__(WAVE *FWD_MAX_WAVES) void forward_kernel(FwdLaunch L) {
+    extern __shared__ float smem[];
+    float *wave_area = smem + (size_t)(threadIdx.x / WAVE) * L.wave_floats;
+    const long long u0 = xcd_item(blockIdx.x, gridDim.x);
+    if (!PERSIST) {
+        if (u0 < L.units) run_unit<K, GRID>(u0, wave_area);
+        return;
+    }
+    for (long long u = u0; u < L.units; u += gridDim.x) run_unit<K, GRID>(u, wave_area);
+}
+
+int choose_chunks(long long P, int tiles, int *tpw) {
     // aim at ~32k waves: enough to fill 256 CUs several times over while a
     // wave still reuses its genome's program across a run of tiles
     const long long target = 32768;
@@ -349,55 +480,146 @@ int choose_chunks(int P, int tiles, int *tpw) {
     return (tiles + *tpw - 1) / *tpw;
 }
 
+int samples_per_lane(int kind) { return kind == KIND_R64X2 ? 2 : 1; }
+
+// kernel of class c under a variant
+int kind_of(int variant, int cls, int B) {
+    if (variant == FWD_LDS) return KIND_LDS;
+    switch (cls) {
+    case CLS_R64:
+        if (variant == FWD_REG2 || (variant == FWD_AUTO && B > WAVE)) return KIND_R64X2;
+        return KIND_R64;
+    case CLS_R128: return KIND_R128;
+    case CLS_R224: return KIND_R224;
+    }
+    return KIND_LDS;
+}
+
 }  // namespace
 
-size_t forward_lds_bytes(int N, int I, int variant, bool grid) {
-    const size_t stage = grid ? 0 : (size_t)2 * TILE * I;
-    if (variant == FWD_REG) return sizeof(float) * stage;
-    return sizeof(float) * (stage + (size_t)n_slots(layout_of(N), N) * TILE);
+const char *kind_name(int kind) {
+    static const char *names[] = {"r64", "r64x2", "r128", "r224", "lds"};
+    return kind >= 0 && kind < N_KINDS ? names[kind] : "?";
 }
 
-int forward_default_variant(int N) { return layout_of(N) == LAYOUT_WIDE ? FWD_LDS : FWD_REG; }
-
-size_t forward_launch_lds_bytes(int P, int B, int N, int I, int variant, bool grid) {
-    int tpw;
-    const int tiles = (B + TILE - 1) / TILE;
-    const int chunks = choose_chunks(P, tiles, &tpw);
-    const int wpg = chunks < WAVES ? chunks : WAVES;
-    return forward_lds_bytes(N, I, variant, grid) * (size_t)wpg;
-}
-
-hipError_t launch_forward(int P, int N, int C, int I, int O, const int32_t *prog,
-                          const float *inputs, int64_t gstride, int B, float *outputs,
-                          int variant, bool grid, int side, int64_t first, hipStream_t stream) {
-    FwdArgs a{};
-    a.prog = prog;
-    a.inputs = inputs;
-    a.outputs = outputs;
-    a.gstride = gstride;
-    a.first = first;
-    a.N = N, a.C = C, a.I = I, a.O = O, a.B = B, a.side = side;
-    a.layout = layout_of(N);
-    a.tiles = (B + TILE - 1) / TILE;
-    a.chunks = choose_chunks(P, a.tiles, &a.tpw);
-    a.wpg = a.chunks < WAVES ? a.chunks : WAVES;
-    a.groups = (a.chunks + a.wpg - 1) / a.wpg;
-    a.prog_words = prog_words(N, C, O);
-    a.vec4 = (!grid && ((uintptr_t)inputs % 16 == 0) && (gstride % 4 == 0)) ? 1 : 0;
-    const unsigned blocks = (unsigned)((long long)P * a.groups);
-    const dim3 block(TILE * a.wpg);
-    const size_t lds = forward_lds_bytes(N, I, variant, grid) * a.wpg;
-    if (variant == FWD_REG) {
-        if (grid)
-            hipLaunchKernelGGL((forward_asm_kernel<true>), dim3(blocks), block, lds, stream, a);
-        else
-            hipLaunchKernelGGL((forward_asm_kernel<false>), dim3(blocks), block, lds, stream, a);
-    } else {
-        if (grid)
-            hipLaunchKernelGGL((forward_lds_kernel<true>), dim3(blocks), block, lds, stream, a);
-        else
-            hipLaunchKernelGGL((forward_lds_kernel<false>), dim3(blocks), block, lds, stream, a);
+int forward_plan(const FwdJob *jobs, int n, int variant, size_t max_lds,
+                 std::vector<FwdKernelLaunch> &out, char *err, size_t errlen) {
+    out.clear();
+    // one launch per (kernel, input mode)
+    constexpr int NL = 2 * N_KINDS;
+    FwdKernelLaunch k[NL];
+    int rows_max[NL], stage_max[NL], ostage_max[NL];
+    for (int x = 0; x < NL; ++x) {
+        k[x] = FwdKernelLaunch{};
+        k[x].kind = x / 2;
+        k[x].grid_mode = x & 1;
+        rows_max[x] = stage_max[x] = ostage_max[x] = 0;
     }
+    for (int j = 0; j < n; ++j) {
+        const FwdJob &J = jobs[j];
+        if (J.P == 0 || J.B == 0) continue;
+        const int top = max_class(J.N);
+        // FWD_LDS takes every genome in one pass over all genomes; the other
+        // variants take class c's genomes with class c's kernel
+        const int c_lo = variant == FWD_LDS ? -1 : 0;
+        const int c_hi = variant == FWD_LDS ? -1 : top;
+        for (int c = c_lo; c <= c_hi; ++c) {
+            const int kind = kind_of(variant, c < 0 ? CLS_LDS : c, J.B);
+            FwdItem it{};
+            it.prog = J.prog;
+            it.inputs = J.inputs;
+            it.outputs = J.outputs;
+            it.gstride = J.gstride;
+            it.first = J.first;
+            it.pop = J.prog + pop_off(J.P, J.N, J.C, J.O);
+            // populations of N_max <= 62 are all R64 and have no class list
+            it.cls = (c < 0 || top == CLS_R64) ? -1 : c;
+            it.P = J.P, it.N = J.N, it.I = J.I, it.O = J.O, it.B = J.B, it.side = J.side;
+            it.prog_words = prog_words(J.N, J.C, J.O);
+            const int TS = WAVE * samples_per_lane(kind);
+            it.tiles = (J.B + TS - 1) / TS;
+            it.chunks = choose_chunks(J.P, it.tiles, &it.tpw);
+            it.vec4 = (!J.side && ((uintptr_t)J.inputs % 16 == 0) && (J.gstride % 4 == 0)) ? 1 : 0;
+            const int x = 2 * kind + (J.side ? 1 : 0);
+            k[x].items.push_back(it);
+            if (!J.side || kind != KIND_LDS) stage_max[x] = std::max(stage_max[x], TS * J.I);
+            if (kind != KIND_LDS) ostage_max[x] = std::max(ostage_max[x], TS * J.O);
+            if (kind == KIND_LDS) rows_max[x] = std::max(rows_max[x], class_slots(top, J.N));
+        }
+    }
+    for (int x = 0; x < NL; ++x) {
+        FwdKernelLaunch &K = k[x];
+        const int kind = K.kind;
+        if (K.items.empty()) continue;
+        const size_t rows = kind == KIND_LDS ? (size_t)rows_max[x] * WAVE : (size_t)ostage_max[x];
+        const size_t wave_floats = (size_t)stage_max[x] + rows;
+        const size_t wave_bytes = wave_floats * sizeof(float);
+        int waves = FWD_MAX_WAVES;
+        while (waves > 1 && wave_bytes * waves > max_lds) --waves;
+        if (wave_bytes > max_lds) {
+            snprintf(err, errlen,
+                     "forward kernel %s needs %zu B of LDS per wave (value rows %d, input "
+                     "staging %d floats), device allows %zu",
+                     kind_name(kind), wave_bytes, kind == KIND_LDS ? rows_max[x] : 0,
+                     stage_max[x], max_lds);
+            return NEAT_E_TOO_LARGE;
+        }
+        long long units = 0;
+        for (FwdItem &it : K.items) {
+            it.wpg = std::min(it.chunks, waves);
+            it.groups = (it.chunks + it.wpg - 1) / it.wpg;
+            it.unit0 = units;
+            units += (long long)it.P * it.groups;
+        }
+        K.args.wave_floats = (int)wave_floats;
+        K.args.stage_floats = stage_max[x];
+        K.args.units = units;
+        K.block = (unsigned)(WAVE * waves);
+        K.lds = wave_bytes * waves;
+        // the LDS store limits the workgroups a CU holds: loop over units with
+        // a grid of a few per CU instead of one workgroup per unit
+        const long long cap = kind == KIND_LDS
+                                  ? 256ll * 2 * std::max<long long>(1, (long long)(163840 / K.lds))
+                                  : (1ll << 31) - 1;
+        K.args.persistent = units > cap ? 1 : 0;
+        K.grid = (unsigned)std::min(units, cap);
+        if (K.items.size() == 1) K.args.one = K.items[0];
+        out.push_back(K);
+    }
+    return NEAT_OK;
+}
+
+hipError_t forward_launch(const FwdKernelLaunch &k, const FwdItem *dev_items, hipStream_t stream) {
+    FwdLaunch L = k.args;
+    if (k.items.size() == 1 && dev_items == nullptr) {
+        L.items = nullptr;
+        L.n_items = 1;
+    } else {
+        L.items = dev_items;
+        L.n_items = (int)k.items.size();
+    }
+#define NEAT_LAUNCH2(KIND, GRID)                                                           \
+    if (L.persistent)                                                                      \
+        hipLaunchKernelGGL((forward_kernel<KIND, true, GRID>), dim3(k.grid), dim3(k.block),   \
+                           k.lds, stream, L);                                              \
+    else                                                                                   \
+        hipLaunchKernelGGL((forward_kernel<KIND, false, GRID>), dim3(k.grid), dim3(k.block),  \
+                           k.lds, stream, L);
+#define NEAT_LAUNCH(KIND)                                                                  \
+    if (k.grid_mode) {                                                                     \
+        NEAT_LAUNCH2(KIND, true)                                                           \
+    } else {                                                                               \
+        NEAT_LAUNCH2(KIND, false)                                                          \
+    }
+    switch (k.kind) {
+    case KIND_R64: NEAT_LAUNCH(KIND_R64) break;
+    case KIND_R64X2: NEAT_LAUNCH(KIND_R64X2) break;
+    case KIND_R128: NEAT_LAUNCH(KIND_R128) break;
+    case KIND_R224: NEAT_LAUNCH(KIND_R224) break;
+    default: NEAT_LAUNCH(KIND_LDS) break;
+    }
+#undef NEAT_LAUNCH
+#undef NEAT_LAUNCH2
     return hipGetLastError();
 }
 

@@ -1,0 +1,500 @@
+#!/usr/bin/env python3
+"""Generate node_loop_asm.h: the forward kernels' node loop in gfx950
+assembly, one variant per value-vector shape.
+
+The node loop evaluates, for every computed node of a genome in topological
+order, v[dst] = act(bias + response * agg(w * v[src])) (the calculation
+stage, Section 3.3), for one wave with one or two samples per lane.  The
+value vector lives in VGPRs and is indexed with the program's uniform slot
+numbers in GPR-index mode; records and edges are read with scalar loads.
+
+Each variant is one tile of samples as a single assembly block: the
+tile's inputs are moved from the LDS staging area into the value vectors,
+the DMA of the next tile's inputs into that staging area is issued, the
+node loop runs, and the outputs are written to an LDS output area.  No
+value crosses from one block to the next, so the value vectors are plain
+clobbers and the compiler never holds or copies them.
+
+Variants (name: samples per lane, value slots, VGPRs of the value vectors):
+  S1_64   1 sample,  64 slots,  v0..v63
+  S2_64   2 samples, 64 slots,  v0..v63 (first) and v64..v127 (second)
+  S1_128  1 sample, 128 slots,  v0..v127
+  S1_224  1 sample, 224 slots,  v0..v223
+Scratch VGPRs follow the value vectors.
+
+Run as ``python gen_node_loop.py`` to rewrite node_loop_asm.h next to it;
+the build does this before compiling, so the header always matches.
+"""
+from __future__ import annotations
+
+import os
+import sys
+
+VARIANTS = [
+    # name, samples per lane, value-vector bases, first scratch VGPR
+    ("S1_64", 1, (0,), 64),
+    ("S2_64", 2, (0, 64), 128),
+    ("S1_128", 1, (0,), 128),
+    ("S1_224", 1, (0,), 224),
+]
+
+# scalar register map (shared by all variants)
+REC_A = ("s40", "s41", "s42", "s43", "s44", "s45", "s[46:47]",
+         "s48", "s49", "s50", "s51", "s52", "s53", "s54", "s55")
+REC_B = ("s56", "s57", "s58", "s59", "s60", "s61", "s[62:63]",
+         "s64", "s65", "s66", "s67", "s68", "s69", "s70", "s71")
+SGPR_CLOBBERS = ["s%d" % i for i in range(40, 92)]
+
+# sine: k = rint(z * 2/pi); r = z - k * pi/2 (pi/2 split in two fp32 parts);
+# Taylor polynomials of sin (degree 9) and cos (degree 10) on [-pi/4, pi/4]
+TWO_OVER_PI = "0x3f22f983"
+NEG_PIO2_HI = "0xbfc90fdb"
+PIO2_LO = "0x333bbd2e"
+SIN_C = ("0x3638ef1d", "0xb9500d01", "0x3c088889", "0xbe2aaaab")
+COS_C = ("0xb493f27e", "0x37d00d01", "0xbab60b61", "0x3d2aaaab", "0xbf000000")
+
+
+class Regs:
+    """Scratch VGPR names of one variant (per sample h)."""
+
+    ROLES = ("acc", "ta", "tb", "z", "y", "k", "r", "r2", "q", "p", "w")
+
+    def __init__(self, spl, bases, scratch):
+        self.spl = spl
+        self.bases = ["v%d" % b for b in bases]
+        self.names = {}
+        n = scratch
+        for role in self.ROLES:
+            self.names[role] = ["v%d" % (n + h) for h in range(spl)]
+            n += spl
+        # tile section registers: input buffers, staging addresses, DMA address
+        self.buf = [["v%d" % (scratch + 8 * h + k) for k in range(8)] for h in range(spl)]
+        self.addr = ["v%d" % (scratch + 8 * spl + h) for h in range(spl)]
+        d = scratch + 8 * spl + spl
+        d += d & 1  # 64-bit VGPR operands are even-aligned
+        self.dma = "v[%d:%d]" % (d, d + 1)
+        n = max(n, d + 2)
+        self.last = n - 1
+        assert self.last <= 255
+
+    def __getattr__(self, role):
+        return self.names[role]
+
+
+def lines(*xs):
+    return list(xs)
+
+
+def per_sample(R, fmt):
+    """One instruction per sample: fmt formatted with each sample's names."""
+    out = []
+    for h in range(R.spl):
+        d = {k: v[h] for k, v in R.names.items()}
+        d["val"] = R.bases[h]
+        out.append(fmt.format(**d))
+    return out
+
+
+def seq(R, *fmts):
+    """Instructions for all samples, interleaved: fmt 1 for every sample,
+    then fmt 2 ...  With two samples the other sample's instruction sits
+    between a result and its use; with one, the caller adds wait states."""
+    out = []
+    for f in fmts:
+        out += per_sample(R, f)
+    return out
+
+
+def nop_if_single(R, n=0):
+    return ["s_nop %d" % n] if R.spl == 1 else []
+
+
+# --------------------------------------------------------------- aggregation
+def read_pair(R, s0, w0, s1, w1, op0, op1):
+    """Indexed reads of one edge pair: op0 applied with (slot s0, weight w0),
+    op1 with (s1, w1).  op formats get {val} (the indexed value register) and
+    {w} (the weight SGPR)."""
+    out = ["s_set_gpr_idx_on %s, gpr_idx(SRC0)" % s0]
+    out += per_sample(R, op0.replace("{w}", w0))
+    out += ["s_set_gpr_idx_idx %s" % s1]
+    out += per_sample(R, op1.replace("{w}", w1))
+    out += ["s_set_gpr_idx_off"]
+    return out
+
+
+def pair(R, cls, first, s0, w0, s1, w1):
+    if cls == "sum":
+        op0 = ("v_mul_f32_e64 {acc}, {val}, {w}" if first else
+               "v_fmac_f32_e64 {acc}, {val}, {w}")
+        return read_pair(R, s0, w0, s1, w1, op0, "v_fmac_f32_e64 {acc}, {val}, {w}")
+    if cls == "prod":
+        if first:
+            return (read_pair(R, s0, w0, s1, w1, "v_mul_f32_e64 {acc}, {val}, {w}",
+                              "v_mul_f32_e64 {tb}, {val}, {w}")
+                    + seq(R, "v_mul_f32_e32 {acc}, {acc}, {tb}"))
+        return (read_pair(R, s0, w0, s1, w1, "v_mul_f32_e64 {ta}, {val}, {w}",
+                          "v_mul_f32_e64 {tb}, {val}, {w}")
+                + seq(R, "v_mul_f32_e32 {acc}, {acc}, {ta}", "v_mul_f32_e32 {acc}, {acc}, {tb}"))
+    assert cls == "max"
+    comb = ("v_maximum3_f32 {acc}, {ta}, {tb}, {tb}" if first else
+            "v_maximum3_f32 {acc}, {acc}, {ta}, {tb}")
+    return (read_pair(R, s0, w0, s1, w1, "v_mul_f32_e64 {ta}, {val}, {w}",
+                      "v_mul_f32_e64 {tb}, {val}, {w}")
+            + seq(R, comb))
+
+
+def aggregate(R, X, cls, rec):
+    """One aggregation class over the node's pairs (s88 of them, >= 1 unless
+    the class is sum): the record's two inline pairs, then the overflow
+    array in chunks of two pairs.  Leaves agg in acc and jumps to Lagg."""
+    p = rec[7:15]
+    done = "Lagg_%s%%=" % X
+    K = cls[0]
+    out = []
+    if cls == "sum":
+        out += ["s_cmp_eq_u32 s88, 0", "s_cbranch_scc1 Lzero_%s%%=" % X]
+    out += pair(R, cls, True, p[0], p[1], p[2], p[3])
+    out += ["s_cmp_eq_u32 s88, 1", "s_cbranch_scc1 " + done]
+    out += pair(R, cls, False, p[4], p[5], p[6], p[7])
+    out += ["s_cmp_le_u32 s88, 2", "s_cbranch_scc1 " + done,
+            # overflow pairs: s87 left, read from s[82:83]; s[84:85] moves past them
+            "s_sub_u32 s87, s88, 2",
+            "s_mov_b64 s[82:83], s[84:85]",
+            "s_lshl_b32 s89, s87, 4",
+            "s_add_u32 s84, s84, s89",
+            "s_addc_u32 s85, s85, 0",
+            "Lo%s_%s%%=:" % (K, X),
+            "s_load_dwordx8 s[72:79], s[82:83], 0x0",
+            "s_waitcnt lgkmcnt(0)"]
+    out += pair(R, cls, False, "s72", "s73", "s74", "s75")
+    out += ["s_cmp_eq_u32 s87, 1", "s_cbranch_scc1 " + done]
+    out += pair(R, cls, False, "s76", "s77", "s78", "s79")
+    out += ["s_sub_u32 s87, s87, 2",
+            "s_add_u32 s82, s82, 32",
+            "s_addc_u32 s83, s83, 0",
+            "s_cmp_eq_u32 s87, 0",
+            "s_cbranch_scc0 Lo%s_%s%%=" % (K, X),
+            "s_branch " + done]
+    return out
+
+
+# --------------------------------------------------------------- activation
+def act_pl(R, C, MASK):
+    # identity, abs, relu: maximum(z, mask ? 0 : c z), NaN-propagating
+    return seq(R, "v_mul_f32_e64 {ta}, {z}, " + C,
+               "v_cndmask_b32_e64 {ta}, {ta}, 0, " + MASK,
+               "v_maximum3_f32 {y}, {z}, {ta}, {ta}")
+
+
+def act_expo(R, C, EA, EB, MASK):
+    # e = 2^(c u), u = mask ? z z : z;  y = mask ? e : ea + eb / (1 + e)
+    out = seq(R, "v_mul_f32_e32 {ta}, {z}, {z}",
+              "v_cndmask_b32_e64 {ta}, {z}, {ta}, " + MASK,
+              "v_mul_f32_e64 {ta}, {ta}, " + C,
+              "v_exp_f32_e32 {ta}, {ta}")
+    out += nop_if_single(R)
+    out += seq(R, "v_add_f32_e32 {tb}, 1.0, {ta}",
+               "v_rcp_f32_e32 {tb}, {tb}")
+    out += nop_if_single(R)
+    out += seq(R, "v_mov_b32_e32 {y}, " + EA,
+               "v_fmac_f32_e64 {y}, " + EB + ", {tb}",
+               "v_cndmask_b32_e64 {y}, {y}, {ta}, " + MASK)
+    return out
+
+
+def act_sin(R):
+    s1, s2, s3, s4 = SIN_C
+    c1, c2, c3, c4, c5 = COS_C
+    return seq(
+        R,
+        "v_mul_f32_e32 {k}, " + TWO_OVER_PI + ", {z}",
+        "v_rndne_f32_e32 {k}, {k}",
+        "v_fmamk_f32 {r}, {k}, " + NEG_PIO2_HI + ", {z}",
+        "v_fmac_f32_e32 {r}, " + PIO2_LO + ", {k}",
+        "v_cvt_i32_f32_e32 {q}, {k}",
+        "v_mul_f32_e32 {r2}, {r}, {r}",
+        # sin r = r + r^3 (s4 + r^2 (s3 + r^2 (s2 + r^2 s1)))
+        "v_mov_b32_e32 {p}, " + s1,
+        "v_fmaak_f32 {p}, {r2}, {p}, " + s2,
+        "v_fmaak_f32 {p}, {r2}, {p}, " + s3,
+        "v_fmaak_f32 {p}, {r2}, {p}, " + s4,
+        "v_mul_f32_e32 {w}, {r}, {r2}",
+        "v_fmac_f32_e32 {r}, {w}, {p}",
+        # cos r = 1 + r^2 (c5 + r^2 (c4 + r^2 (c3 + r^2 (c2 + r^2 c1))))
+        "v_mov_b32_e32 {p}, " + c1,
+        "v_fmaak_f32 {p}, {r2}, {p}, " + c2,
+        "v_fmaak_f32 {p}, {r2}, {p}, " + c3,
+        "v_fmaak_f32 {p}, {r2}, {p}, " + c4,
+        "v_fmaak_f32 {p}, {r2}, {p}, " + c5,
+        "v_fma_f32 {p}, {r2}, {p}, 1.0",
+        # odd quadrant: cos; quadrants 2 and 3: negate (bit 1 of k -> sign)
+        "v_and_b32_e32 {w}, 1, {q}",
+        "v_sub_u32_e32 {w}, 0, {w}",
+        "v_bfi_b32 {y}, {w}, {p}, {r}",
+        "v_lshlrev_b32_e32 {w}, 30, {q}",
+        "v_and_b32_e32 {w}, 0x80000000, {w}",
+        "v_xor_b32_e32 {y}, {y}, {w}")
+
+
+# --------------------------------------------------------------- node, loop
+def node(R, X, rec, pref):
+    CODE, BIAS, RESP, C, EA, EB, MASK = rec[:7]
+    out = ["Lnode_%s%%=:" % X,
+           "s_waitcnt lgkmcnt(0)",
+           "s_add_u32 s86, s86, 64",
+           "s_load_dwordx16 %s, s[80:81], s86" % pref,
+           "s_and_b32 s88, %s, 0xffff" % CODE,
+           "s_bitcmp1_b32 %s, 16" % CODE,
+           "s_cbranch_scc1 Lprod_%s%%=" % X,
+           "s_bitcmp1_b32 %s, 17" % CODE,
+           "s_cbranch_scc1 Lmax_%s%%=" % X]
+    out += aggregate(R, X, "sum", rec)
+    out += ["Lzero_%s%%=:" % X] + seq(R, "v_mov_b32_e32 {acc}, 0") + ["s_branch Lagg_%s%%=" % X]
+    out += ["Lprod_%s%%=:" % X] + aggregate(R, X, "prod", rec)
+    out += ["Lmax_%s%%=:" % X] + aggregate(R, X, "max", rec)
+    # z = bias + response' * agg
+    out += ["Lagg_%s%%=:" % X]
+    out += seq(R, "v_mov_b32_e32 {z}, " + BIAS, "v_fmac_f32_e64 {z}, " + RESP + ", {acc}")
+    out += ["s_bitcmp1_b32 %s, 18" % CODE, "s_cbranch_scc1 Lexpo_%s%%=" % X,
+            "s_bitcmp1_b32 %s, 19" % CODE, "s_cbranch_scc1 Lsin_%s%%=" % X]
+    out += act_pl(R, C, MASK) + ["s_branch Lwr_%s%%=" % X]
+    out += ["Lexpo_%s%%=:" % X] + act_expo(R, C, EA, EB, MASK) + ["s_branch Lwr_%s%%=" % X]
+    out += ["Lsin_%s%%=:" % X] + act_sin(R)
+    # v[dst] = y
+    out += ["Lwr_%s%%=:" % X,
+            "s_lshr_b32 s89, %s, 20" % CODE,
+            "s_set_gpr_idx_on s89, gpr_idx(DST)"]
+    out += per_sample(R, "v_mov_b32_e32 {val}, {y}")
+    out += ["s_set_gpr_idx_off",
+            "s_cmp_eq_u32 s86, s91",
+            "s_cbranch_scc1 Ldone%="]
+    return out
+
+
+def node_loop(R):
+    """All computed nodes: %[rec] record 0, %[edg] overflow edges, %[n]
+    records.  M0 is saved in s90 by the caller."""
+    out = ["s_mov_b64 s[80:81], %[rec]",
+           "s_mov_b64 s[84:85], %[edg]",
+           "s_lshl_b32 s91, %[n], 6",
+           "s_mov_b32 s86, 0",
+           "s_cmp_eq_u32 s91, 0",
+           "s_cbranch_scc1 Ldone%=",
+           "s_load_dwordx16 s[40:55], s[80:81], 0x0"]
+    out += node(R, "A", REC_A, "s[56:71]")
+    out += node(R, "B", REC_B, "s[40:55]")
+    out += ["s_branch Lnode_A%=",
+            "Ldone%=:",
+            "s_waitcnt lgkmcnt(0)"]
+    return out
+
+
+def place_inputs(R):
+    """v[i] = staged input i of the lane's sample(s), i < %[ni], eight at a
+    time (ds_read2 pairs, one index setting per eight moves).  The last
+    group may write up to seven slots past the inputs: those belong to
+    computed nodes (written before any read) or the constants (set after),
+    and the reads past the lane's inputs stay inside the staging areas."""
+    # lane l's first input: %[dm0] + 4 l ni (+ 256 ni for the second sample)
+    out = ["s_lshl_b32 s41, %[ni], 2",
+           "v_mul_u32_u24_e32 %s, s41, %%[lane]" % R.addr[0],
+           "v_add_u32_e32 %s, %%[dm0], %s" % (R.addr[0], R.addr[0])]
+    if R.spl == 2:
+        out += ["s_lshl_b32 s41, %[ni], 8",
+                "v_add_u32_e32 %s, s41, %s" % (R.addr[1], R.addr[0])]
+    out += ["s_mov_b32 s40, 0",
+            "s_cmp_eq_u32 %[ni], 0",
+            "s_cbranch_scc1 Lpl_done%=",
+            "Lpl%=:"]
+    for h in range(R.spl):
+        b = R.buf[h]
+        for k in range(0, 8, 2):
+            lo, hi = int(b[k][1:]), int(b[k + 1][1:])
+            out.append("ds_read2_b32 v[%d:%d], %s offset0:%d offset1:%d"
+                       % (lo, hi, R.addr[h], k, k + 1))
+    for h in range(R.spl):
+        out.append("v_add_u32_e32 %s, 32, %s" % (R.addr[h], R.addr[h]))
+    out += ["s_waitcnt lgkmcnt(0)",
+            "s_set_gpr_idx_on s40, gpr_idx(DST)"]
+    for h in range(R.spl):
+        base = int(R.bases[h][1:])
+        for k in range(8):
+            out.append("v_mov_b32_e32 v%d, %s" % (base + k, R.buf[h][k]))
+    out += ["s_set_gpr_idx_off",
+            "s_add_u32 s40, s40, 8",
+            "s_cmp_lt_u32 s40, %[ni]",
+            "s_cbranch_scc1 Lpl%=",
+            "Lpl_done%=:",
+            # the constants 0 and 1 at the zero slot
+            "s_set_gpr_idx_on %[zs], gpr_idx(DST)"]
+    for h in range(R.spl):
+        base = int(R.bases[h][1:])
+        out += ["v_mov_b32_e32 v%d, 0" % base, "v_mov_b32_e32 v%d, 1.0" % (base + 1)]
+    out += ["s_set_gpr_idx_off"]
+    return out
+
+
+def dma_next(R):
+    """Copy the next tile's inputs HBM -> LDS staging (the inputs just
+    placed have been read): %[dn] pieces of 16 bytes (%[dvec] = 1) or 4
+    bytes, lane l reading piece l of each round of 64 from %[dsrc] onward,
+    to %[dm0] + piece offset.  Rounds mask off lanes past the last piece."""
+    d0 = R.dma[2:R.dma.index(":")]
+    d1 = R.dma[R.dma.index(":") + 1:-1]
+    out = ["s_cmp_eq_u32 %[dn], 0",
+           "s_cbranch_scc1 Ldma_done%=",
+           "s_mov_b64 s[42:43], exec",
+           "s_cmp_eq_u32 %[dvec], 0",
+           "s_cselect_b32 s41, 2, 4",
+           "v_lshlrev_b32_e32 v%s, s41, %%[lane]" % d0,
+           "v_mov_b32_e32 v%s, 0" % d1,
+           "v_lshl_add_u64 %s, %s, 0, %%[dsrc]" % (R.dma, R.dma),
+           "s_mov_b32 s40, 0",
+           "s_mov_b32 m0, %[dm0]",
+           "s_cmp_eq_u32 %[dvec], 0",
+           "s_cbranch_scc1 Ldma1%="]
+    for tag, op, step in (("4", "global_load_lds_dwordx4", 1024), ("1", "global_load_lds_dword", 256)):
+        if tag == "1":
+            out += ["Ldma1%=:"]
+        out += ["s_mov_b64 s[46:47], %d" % step,
+                "Ldl%s%%=:" % tag,
+                "s_sub_u32 s41, %[dn], s40",
+                "v_cmp_gt_u32_e64 s[44:45], s41, %[lane]",
+                "s_and_b64 exec, s[42:43], s[44:45]",
+                "s_nop 0",
+                "%s %s, off" % (op, R.dma),
+                "s_mov_b64 exec, s[42:43]",
+                "v_lshl_add_u64 %s, %s, 0, s[46:47]" % (R.dma, R.dma),
+                "s_add_u32 m0, m0, %d" % step,
+                "s_add_u32 s40, s40, 64",
+                "s_cmp_lt_u32 s40, %[dn]",
+                "s_cbranch_scc1 Ldl%s%%=" % tag,
+                "s_branch Ldma_done%="]
+    out += ["Ldma_done%=:"]
+    return out
+
+
+def write_outputs(R):
+    """Output j of the lane's sample(s) -> LDS output area %[om0] + 4 (l O
+    + j) for lane l (+ 256 O for the second sample), slots from %[outs],
+    O = %[no]."""
+    out = ["s_mov_b64 s[44:45], %[outs]",
+           "s_mov_b32 s40, 0",
+           "s_lshl_b32 s41, %[no], 2",
+           "v_mul_u32_u24_e32 %s, s41, %%[lane]" % R.addr[0],
+           "v_add_u32_e32 %s, %%[om0], %s" % (R.addr[0], R.addr[0])]
+    if R.spl == 2:
+        out += ["s_lshl_b32 s41, %[no], 8",
+                "v_add_u32_e32 %s, s41, %s" % (R.addr[1], R.addr[0])]
+    out += ["Lout%=:",
+            "s_load_dwordx8 s[48:55], s[44:45], 0x0",
+            "s_waitcnt lgkmcnt(0)"]
+    for k in range(8):
+        out += ["s_set_gpr_idx_on s%d, gpr_idx(SRC0)" % (48 + k)]
+        for h in range(R.spl):
+            out += ["v_mov_b32_e32 %s, %s" % (R.buf[h][k], R.bases[h])]
+        out += ["s_set_gpr_idx_off"]
+        for h in range(R.spl):
+            out += ["ds_write_b32 %s, %s offset:%d" % (R.addr[h], R.buf[h][k], 4 * k)]
+        out += ["s_add_u32 s40, s40, 1",
+                "s_cmp_ge_u32 s40, %[no]",
+                "s_cbranch_scc1 Lout_done%="]
+    for h in range(R.spl):
+        out.append("v_add_u32_e32 %s, 32, %s" % (R.addr[h], R.addr[h]))
+    out += ["s_add_u32 s44, s44, 32",
+            "s_addc_u32 s45, s45, 0",
+            "s_branch Lout%=",
+            "Lout_done%=:"]
+    return out
+
+
+def tile(R):
+    return (["s_mov_b32 s90, m0"] + place_inputs(R) + dma_next(R) + node_loop(R)
+            + write_outputs(R) + ["s_mov_b32 m0, s90"])
+
+
+HEADER = """\
+// node_loop_asm.h -- GENERATED by gen_node_loop.py; edit that script.
+//
+// One tile of the calculation stage (Section 3.3) in gfx950 assembly, for
+// one wave with one or two samples per lane: for every computed node in
+// topological order, v[dst] = act(bias + response * agg(w * v[src])).
+//
+// A tile block (NEAT_TILE_<variant>) does, in order:
+//   1. v[i] = input i of the lane's sample(s), i < %[ni], from the LDS
+//      staging area at byte address %[dm0] (sample s's inputs at + 4 s ni;
+//      lane l holds samples l and, with two per lane, 64 + l); then the
+//      constants 0 and 1 at slots %[zs], %[zs] + 1;
+//   2. the DMA of the next tile's inputs into the staging area: %[dn]
+//      pieces of 16 bytes (%[dvec] = 1) or 4 bytes (%[dvec] = 0) from the
+//      global address %[dsrc] onward, lane l taking piece l of each round
+//      of 64; %[lane] is the lane id (the only VGPR operand);
+//   3. the node loop over %[n] records from %[rec], overflow edges from
+//      %[edg];
+//   4. output j of each sample s = v[slot j] (slots at %[outs], j < %[no])
+//      to the LDS output area at %[om0] + 4 (s O + j).
+// The value vectors (slot s of sample h in v[base_h + s]; every slot the
+// program names is below the variant's slot count) live only inside the
+// block and are listed as clobbers with the scratch VGPRs after them.
+//
+// Scalar registers: s40..s55 record buffer A, s56..s71 record buffer B
+// (16-word records with the node's first two edge pairs; the next record
+// is prefetched while the current one runs), s72..s79 two overflow pairs,
+// s80:81 record array, s82:83 overflow read pointer, s84:85 overflow edges
+// of the current node, s86 record byte offset, s87 pairs left, s88 pairs of
+// the node, s89 scratch, s90 saved M0, s91 end offset; steps 1, 2 and 4 use
+// s40..s55 before and after the node loop.
+// Reads of v[slot] and the write of v[dst] use GPR-index mode with the
+// program's uniform slots; an indexed read of a pair keeps the mode on and
+// only moves the index, and every sample of the lane shares it.
+//
+// Aggregation classes (program.h): sum (mean folds 1/degree into the
+// response), product, max (min is max over negated weights with negated
+// response), the first pair initialising the accumulator and an empty sum
+// giving 0.  Max uses the NaN-propagating maximum.  Activation classes: PL
+// (identity, abs, relu) as maximum(z, mask ? 0 : c z); EXPO (sigmoid, tanh,
+// gaussian) on the hardware base-2 exponential and reciprocal; SIN by
+// Cody-Waite reduction and Taylor polynomials.  The C++ node loop of the
+// LDS store performs the same operations in the same order.
+//
+// Hazards: a transcendental's result is read no sooner than one instruction
+// later (with two samples the other sample's instruction sits between); a
+// write of M0 is followed by one wait state before the LDS DMA reads it.
+#pragma once
+"""
+
+
+def c_string(lines_):
+    return "\n".join('    "  %s\\n"' % l if not l.endswith(":") else '    "%s\\n"' % l
+                     for l in lines_)
+
+
+def generate():
+    parts = [HEADER]
+    for name, spl, bases, scratch in VARIANTS:
+        R = Regs(spl, bases, scratch)
+        body = tile(R)
+        parts.append("// %s: %d sample(s) per lane, value vectors at %s, scratch v%d..v%d\n"
+                     % (name, spl, ", ".join("v%d" % b for b in bases), scratch, R.last))
+        parts.append("#define NEAT_TILE_%s \\\n%s\n" % (name, " \\\n".join(
+            c_string([l]) for l in body)))
+        vclob = ['"v%d"' % i for i in range(0, R.last + 1)]
+        clob = vclob + ['"%s"' % s for s in SGPR_CLOBBERS] + ['"vcc"', '"scc"']
+        rows = [", ".join(clob[i:i + 12]) for i in range(0, len(clob), 12)]
+        parts.append("#define NEAT_CLOB_%s \\\n    %s\n" % (name, ", \\\n    ".join(rows)))
+        parts.append("#define NEAT_SCRATCH_%s %d\n\n" % (name, scratch))
+    return "\n".join(parts)
+
+
+def main(argv):
+    here = os.path.dirname(os.path.abspath(__file__))
+    path = argv[1] if len(argv) > 1 else os.path.join(here, "node_loop_asm.h")
+    text = generate()
+    old = open(path).read() if os.path.exists(path) else None
+    if old != text:
+        with open(path, "w") as f:
+            f.write(text)
+
+
+if __name__ == "__main__":
+    main(sys.argv)

@@ -7,6 +7,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <vector>
 
 namespace neat {
 
@@ -19,19 +20,70 @@ hipError_t launch_topo(int P, int N, int C, int I, int O, const float *nodes,
                        const float *conns, int32_t *order, int32_t *level,
                        uint32_t *status, int32_t *prog, hipStream_t stream);
 
-// Forward variants (value store of the lane-per-sample mapping).
-constexpr int FWD_AUTO = 0;
-constexpr int FWD_REG = 1;  // value vector in VGPRs, node loop in assembly (N_max <= 62)
-constexpr int FWD_LDS = 2;  // value vector in LDS rows (any N_max)
+// Forward variants (value stores of the lane-per-sample mapping).
+constexpr int FWD_AUTO = 0;  // per slot class: registers, R64 with two samples per lane when B > 64
+constexpr int FWD_REG = 1;   // registers, one sample per lane (LDS rows for the LDS class)
+constexpr int FWD_LDS = 2;   // every genome in LDS rows
+constexpr int FWD_REG2 = 3;  // as FWD_REG, R64 genomes two samples per lane
 
-int forward_default_variant(int N);
-// LDS bytes of one forward launch (all waves of a workgroup).
-size_t forward_launch_lds_bytes(int P, int B, int N, int I, int variant, bool grid);
+// Forward kernels, one per value store.
+enum FwdKind { KIND_R64 = 0, KIND_R64X2, KIND_R128, KIND_R224, KIND_LDS, N_KINDS };
+constexpr int FWD_MAX_WAVES = 4;  // waves per workgroup
 
-// inputs: per-genome stride in floats (0 = shared); B vectors per genome.
-// grid: CPPN queries generated in the kernel (I == 5, side, first).
-hipError_t launch_forward(int P, int N, int C, int I, int O, const int32_t *prog,
-                          const float *inputs, int64_t gstride, int B, float *outputs,
-                          int variant, bool grid, int side, int64_t first, hipStream_t stream);
+// One population of a forward call.
+struct FwdJob {
+    const int32_t *prog;  // programs of neat_topo_sort (+ population area)
+    const float *inputs;  // [P or 1][B][I] with gstride floats between genomes
+    float *outputs;       // [P][B][O]
+    int64_t gstride;
+    int64_t first;        // grid mode: first query
+    int P, N, C, I, O, B;
+    int side;             // > 0: grid mode (CPPN queries generated in the kernel)
+};
+
+// One population in one forward kernel (device-visible, read with scalar
+// loads): the genomes of class cls (or all when cls < 0), P x groups units
+// starting at unit0.
+struct FwdItem {
+    const int32_t *prog;
+    const float *inputs;
+    float *outputs;
+    const int32_t *pop;  // population area (class lists)
+    long long gstride, first, unit0;
+    int P, N, I, O, B, side, vec4, cls;
+    int tiles, tpw, chunks, wpg, groups, prog_words;
+};
+
+// Kernel argument: one item inline, or a device table of items.
+struct FwdLaunch {
+    FwdItem one;
+    const FwdItem *items;  // nullptr: the inline item
+    long long units;
+    int n_items;
+    int wave_floats;   // LDS floats per wave: input staging, then value rows (LDS
+                       // store) or the output staging (register stores)
+    int stage_floats;
+    int persistent;    // workgroups loop over units
+};
+
+struct FwdKernelLaunch {
+    int kind;
+    int grid_mode;  // items generate CPPN grid queries
+    unsigned grid, block;
+    size_t lds;
+    FwdLaunch args;
+    std::vector<FwdItem> items;
+};
+
+const char *kind_name(int kind);
+
+// Plan the kernels of a forward over n populations: one launch per value
+// store in use, each covering its genomes of every population.  Returns
+// NEAT_OK or an error code with a message in err.
+int forward_plan(const FwdJob *jobs, int n, int variant, size_t max_lds,
+                 std::vector<FwdKernelLaunch> &out, char *err, size_t errlen);
+// Launch one planned kernel.  dev_items: the launch's items in device memory
+// (may be nullptr when the launch has a single item, passed inline).
+hipError_t forward_launch(const FwdKernelLaunch &k, const FwdItem *dev_items, hipStream_t stream);
 
 }  // namespace neat

@@ -8,11 +8,17 @@
 // 0..I-1, and every computed node p >= I has one record.
 //
 // Each position is stored in a value SLOT of the forward kernels' value
-// vector.  The slot numbering depends only on N_max (layout_of):
-//   REG   N_max <= 62: slot = position, 64 slots, slots 62 and 63 hold the
-//         constants 0 and 1 (the register-resident forward);
-//   WIDE  otherwise: slot = position, N_max + 2 slots, the constants at
-//         slots N_max and N_max + 1 (LDS rows).
+// vector.  For N_max <= 62 the slot is the position.  Otherwise slots are
+// reused: the program build walks the positions in order
+// and gives each value a free slot (a value's slot is freed after its last
+// reader, so the reader's own result may take it), which keeps the number
+// of slots at the largest number of simultaneously live values.  Inputs
+// hold slots 0..I-1; outputs are never freed.  That number decides the
+// genome's SLOT CLASS and where the two constant slots (0 and 1) sit:
+//   R64   <= 62 values: 64 register slots, constants at 62 and 63;
+//   R128  <= 126 values: 128 register slots, constants at 126 and 127;
+//   R224  <= 222 values: 224 register slots, constants at 222 and 223;
+//   LDS   otherwise: N_max + 2 LDS rows, constants at N_max and N_max + 1.
 // A node's incoming edges are stored as (source slot, weight) in ascending
 // source-key order, padded to an even count with one neutral edge, so the
 // kernels consume edges in pairs without per-edge tests: for sum and mean a
@@ -21,6 +27,10 @@
 // two pairs live in the node's record (one scalar load brings a node and its
 // usual in-edges); further pairs follow in the overflow edge array, node
 // after node.
+//
+// After the P genome programs, a population area lists the genomes by slot
+// class (written by the classification step for N_max > 62 only; smaller
+// populations are all R64).
 //
 // All fields are 32-bit words; one genome's program is prog_words() words,
 // a multiple of 64 (256 bytes), so every genome starts on its own lines.
@@ -38,22 +48,25 @@ constexpr int HDR_STATUS = 2;   // status bit-mask (NEAT_ST_*)
 constexpr int HDR_NLEVELS = 3;  // number of levels
 constexpr int HDR_I = 4;
 constexpr int HDR_O = 5;
-constexpr int HDR_LAYOUT = 6;
+constexpr int HDR_CLASS = 6;    // slot class
 constexpr int HDR_NREAL = 7;    // enabled edges (without padding)
+constexpr int HDR_SLOTS = 8;    // value slots in use (largest live set; nodes when N_max <= 62)
 constexpr int HDR_WORDS = 16;
 
-enum Layout { LAYOUT_REG = 0, LAYOUT_WIDE = 1 };
+enum SlotClass { CLS_R64 = 0, CLS_R128 = 1, CLS_R224 = 2, CLS_LDS = 3 };
+constexpr int N_CLASSES = 4;
 
-__host__ __device__ constexpr int layout_of(int N) { return N <= 62 ? LAYOUT_REG : LAYOUT_WIDE; }
-__host__ __device__ constexpr int slot_of(int /*layout*/, int p) { return p; }
-// number of value slots the forward kernels hold per sample
-__host__ __device__ constexpr int n_slots(int layout, int N) {
-    return layout == LAYOUT_REG ? 64 : N + 2;
+__host__ __device__ constexpr int class_of(int live) {
+    return live <= 62 ? CLS_R64 : (live <= 126 ? CLS_R128 : (live <= 222 ? CLS_R224 : CLS_LDS));
+}
+// the largest class a genome of N_max nodes can need (live <= N_max)
+__host__ __device__ constexpr int max_class(int N) { return class_of(N); }
+// number of value slots of a class (registers or LDS rows)
+__host__ __device__ constexpr int class_slots(int cls, int N) {
+    return cls == CLS_R64 ? 64 : (cls == CLS_R128 ? 128 : (cls == CLS_R224 ? 224 : N + 2));
 }
 // slot of the constant 0 (the constant 1 is the next slot)
-__host__ __device__ constexpr int zero_slot(int layout, int N) {
-    return layout == LAYOUT_REG ? 62 : N;
-}
+__host__ __device__ constexpr int zero_slot(int cls, int N) { return class_slots(cls, N) - 2; }
 
 // node record (16 words), record k describes position I + k.  The
 // aggregation and activation are folded into a few classes so the forward
@@ -109,6 +122,18 @@ __host__ __device__ constexpr int lvl_off(int N, int C, int O) { return ebeg_off
 constexpr int PROG_SLACK = 16;
 __host__ __device__ constexpr int prog_words(int N, int C, int O) {
     return round_up(lvl_off(N, C, O) + N + 1 + PROG_SLACK, 64);
+}
+
+// population area (after P programs): POP_COUNT + c genomes of class c,
+// POP_BEGIN + c their first entry in the id list at POP_IDS
+constexpr int POP_COUNT = 0;
+constexpr int POP_BEGIN = 4;
+constexpr int POP_IDS = 64;
+__host__ __device__ constexpr long long pop_off(long long P, int N, int C, int O) {
+    return P * prog_words(N, C, O);
+}
+__host__ __device__ constexpr long long pop_words(long long P) {
+    return POP_IDS + (P + 63) / 64 * 64;
 }
 
 enum Act { ACT_IDENTITY = 0, ACT_TANH, ACT_SIGMOID, ACT_RELU, ACT_SIN, ACT_GAUSS, ACT_ABS };

@@ -18,8 +18,12 @@
 //      ballot + mbcnt prefix count gives each frontier node its position in
 //      (level, key) order; emitted nodes decrement their successors' in-degree
 //      with LDS atomics; nodes never emitted mean a cycle;
-//   6. the program (program.h): records in topological order, in-edges sorted
-//      by source key, source positions, level starts.
+//   6. value slots by liveness (a sequential scan over the positions that
+//      hands each value a free slot and frees it after its last reader),
+//      then the program (program.h): records in topological order, in-edges
+//      sorted by source key, source slots, level starts.
+//
+// classify_kernel then lists the genomes of a population by slot class.
 #include <hip/hip_runtime.h>
 
 #include "launch.h"
@@ -115,6 +119,8 @@ __global__ __launch_bounds__(1024) void topo_kernel(TopoArgs a) {
     int *e_dst = e_src + C;       // [C]
     int *in_list = e_dst + C;     // [C] connection rows grouped by destination
     int *out_list = in_list + C;  // [C] destination rows grouped by source
+    int *s_slot = out_list + C;   // [N] value slot of row
+    int *s_stack = s_slot + N;    // [N] free slots
 
     const float *nodes = a.nodes + g * (size_t)N * 5;
     const float *conns = a.conns + g * (size_t)C * 4;
@@ -298,23 +304,74 @@ __global__ __launch_bounds__(1024) void topo_kernel(TopoArgs a) {
     if (a.status && t == 0) a.status[g] = status;
     if (!a.prog) return;
 
-    // ---- 6. program (layout in program.h)
-    const int L = layout_of(N);
+    // ---- 6. value slots, then the program (layout in program.h)
+    __shared__ int s_used;
     int32_t *prog = a.prog + g * (size_t)a.prog_words;
     float *progf = reinterpret_cast<float *>(prog);
+    if (!ok) {
+        if (t == 0) {
+            prog[HDR_NVALID] = 0;
+            prog[HDR_NEDGES] = 0;
+            prog[HDR_STATUS] = (int32_t)status;
+            prog[HDR_NLEVELS] = 0;
+            prog[HDR_I] = I;
+            prog[HDR_O] = O;
+            prog[HDR_CLASS] = CLS_R64;
+            prog[HDR_NREAL] = 0;
+            prog[HDR_SLOTS] = 0;
+        }
+        return;  // uniform
+    }
+    // last reading position of every value (s_indeg is free after Kahn);
+    // outputs are read after the last node
+    int *s_last = s_indeg;
+    if (t < N && s_key[t] != -1) {
+        int last = s_pos[t];
+        for (int k = s_outoff[t]; k < s_outoff[t + 1]; ++k) last = max(last, s_pos[out_list[k]]);
+        if (s_key[t] >= I && s_key[t] < I + O) last = nvalid;
+        s_last[t] = last;
+    }
+    __syncthreads();
+    if (t == 0 && max_class(N) == CLS_R64) {
+        // every genome fits the 64-slot class: slot = position
+        for (int p = 0; p < nvalid; ++p) s_slot[s_curi[p]] = p;
+        s_used = nvalid;
+    } else if (t == 0) {
+        // input p (position p, key p) keeps slot p; a value whose last
+        // reader is position p frees its slot before p takes one, since a
+        // node reads all its sources before writing its own value
+        int top = 0, used = I;
+        for (int p = 0; p < I; ++p) s_slot[s_curi[p]] = p;
+        for (int p = 0; p < I; ++p)
+            if (s_last[s_curi[p]] == p) s_stack[top++] = p;  // unread inputs
+        for (int p = I; p < nvalid; ++p) {
+            const int row = s_curi[p];
+            for (int k = s_inoff[row]; k < s_inoff[row + 1]; ++k) {
+                const int src = e_src[in_list[k]];
+                if (s_last[src] == p) s_stack[top++] = s_slot[src];
+            }
+            const int sl = top > 0 ? s_stack[--top] : used++;
+            s_slot[row] = sl;
+            if (s_last[row] == p) s_stack[top++] = sl;  // never read
+        }
+        s_used = used;
+    }
+    __syncthreads();
+    const int used = s_used;
+    const int cls = class_of(used);
+    const int zs = zero_slot(cls, N);
     if (t == 0) {
-        prog[HDR_NVALID] = ok ? nvalid : 0;
-        prog[HDR_STATUS] = (int32_t)status;
-        prog[HDR_NLEVELS] = ok ? n_levels : 0;
+        prog[HDR_NVALID] = nvalid;
+        prog[HDR_STATUS] = 0;
+        prog[HDR_NLEVELS] = n_levels;
         prog[HDR_I] = I;
         prog[HDR_O] = O;
-        prog[HDR_LAYOUT] = L;
-        prog[HDR_NREAL] = ok ? s_inoff[N] : 0;
-        if (!ok) prog[HDR_NEDGES] = 0;
+        prog[HDR_CLASS] = cls;
+        prog[HDR_NREAL] = s_inoff[N];
+        prog[HDR_SLOTS] = used;
     }
-    if (!ok) return;  // uniform
     // output slots: rank I + j holds key I + j
-    if (t < O) prog[out_off() + t] = slot_of(L, s_pos[s_srow[I + t]]);
+    if (t < O) prog[out_off() + t] = s_slot[s_srow[I + t]];
     // owner of a computed row: in-degree, first in-edge (min source key),
     // pairs after padding to an even count, overflow edges beyond the record
     const bool computed = t < N && s_key[t] >= 0 && s_pos[t] >= I;
@@ -375,7 +432,7 @@ __global__ __launch_bounds__(1024) void topo_kernel(TopoArgs a) {
         if (act == ACT_TANH) xcls = XCLS_EXPO, cf = 2.885390043258667f, xa = 1.0f, xb = -2.0f;
         if (act == ACT_GAUSS) xcls = XCLS_EXPO, cf = -1.4426950216293335f, mask = -1;
         if (act == ACT_SIN) xcls = XCLS_SIN;
-        prog[r0 + REC_CODE] = (int32_t)rec_code(pairs, acls, xcls, slot_of(L, s_pos[t]));
+        prog[r0 + REC_CODE] = (int32_t)rec_code(pairs, acls, xcls, s_slot[t]);
         progf[r0 + REC_BIAS] = bias;
         progf[r0 + REC_RESP] = rp;
         progf[r0 + REC_C] = cf;
@@ -385,7 +442,7 @@ __global__ __launch_bounds__(1024) void topo_kernel(TopoArgs a) {
         prog[r0 + REC_MASK + 1] = mask;
         // unused inline edges: a harmless (constant slot, 0) pair
         for (int j = 2 * pairs; j < 2 * REC_INLINE_PAIRS; ++j) {
-            prog[r0 + REC_PAIRS + 2 * j] = zero_slot(L, N);
+            prog[r0 + REC_PAIRS + 2 * j] = zs;
             progf[r0 + REC_PAIRS + 2 * j + 1] = 0.0f;
         }
         // neutral padding edge when the in-degree is odd
@@ -393,11 +450,11 @@ __global__ __launch_bounds__(1024) void topo_kernel(TopoArgs a) {
             int slot;
             float w = 1.0f;
             if (agg == AGG_SUM || agg == AGG_MEAN) {
-                slot = zero_slot(L, N);
+                slot = zs;
             } else if (agg == AGG_PRODUCT) {
-                slot = zero_slot(L, N) + 1;
+                slot = zs + 1;
             } else {  // max / min: the first edge again (min stores -w)
-                slot = slot_of(L, s_pos[e_src[first]]);
+                slot = s_slot[e_src[first]];
                 w = conns[(size_t)first * 4 + 3];
                 if (agg == AGG_MIN) w = -w;
             }
@@ -426,14 +483,56 @@ __global__ __launch_bounds__(1024) void topo_kernel(TopoArgs a) {
                                                    : eoff + EDGE_WORDS * (s_curo[d] + j - 4);
         // min is stored as max over negated weights (negation is exact)
         const float w = conns[(size_t)c * 4 + 3];
-        prog[widx] = slot_of(L, s_pos[s]);
+        prog[widx] = s_slot[s];
         progf[widx + 1] = s_agg[d] == AGG_MIN ? -w : w;
+    }
+}
+
+// List the genomes of a population by slot class (one workgroup of 1024
+// threads; thread t takes a contiguous run of genomes, so the lists are in
+// genome order).  Rejected genomes go with R64: every forward kernel writes
+// their NaN rows.
+__global__ __launch_bounds__(1024) void classify_kernel(const int32_t *prog, int prog_words,
+                                                        int P, int32_t *pop) {
+    __shared__ int s_wave[16];
+    const int t = (int)threadIdx.x, W = (int)blockDim.x;
+    const int per = (P + W - 1) / W;
+    const int g0 = min(P, t * per), g1 = min(P, g0 + per);
+    int cnt[N_CLASSES] = {0, 0, 0, 0};
+    for (int g = g0; g < g1; ++g) {
+        const int c = prog[(size_t)g * prog_words + HDR_CLASS];
+#pragma unroll
+        for (int k = 0; k < N_CLASSES; ++k) cnt[k] += (c == k) || (k == 0 && (c < 0 || c >= N_CLASSES));
+    }
+    int base[N_CLASSES], tot[N_CLASSES];
+#pragma unroll
+    for (int c = 0; c < N_CLASSES; ++c) base[c] = block_excl_scan(cnt[c], s_wave, &tot[c]);
+    int begin = 0;
+#pragma unroll
+    for (int c = 0; c < N_CLASSES; ++c) {
+        if (t == 0) {
+            pop[POP_COUNT + c] = tot[c];
+            pop[POP_BEGIN + c] = begin;
+        }
+        base[c] += begin;
+        begin += tot[c];
+    }
+    for (int g = g0; g < g1; ++g) {
+        int c = prog[(size_t)g * prog_words + HDR_CLASS];
+        c = c < 0 || c >= N_CLASSES ? 0 : c;
+        // select the class's cursor without dynamic register indexing
+        int pos = base[0];
+#pragma unroll
+        for (int k = 1; k < N_CLASSES; ++k) pos = (c == k) ? base[k] : pos;
+        pop[POP_IDS + pos] = g;
+#pragma unroll
+        for (int k = 0; k < N_CLASSES; ++k) base[k] += (c == k);
     }
 }
 
 }  // namespace
 
-size_t topo_lds_bytes(int N, int C) { return sizeof(int) * ((size_t)10 * N + 2 + (size_t)4 * C); }
+size_t topo_lds_bytes(int N, int C) { return sizeof(int) * ((size_t)12 * N + 2 + (size_t)4 * C); }
 
 int topo_block_threads(int N) {
     int w = round_up(N, 64);
@@ -446,6 +545,12 @@ hipError_t launch_topo(int P, int N, int C, int I, int O, const float *nodes,
     TopoArgs a{nodes, conns, order, level, status, prog, N, C, I, O, prog_words(N, C, O)};
     hipLaunchKernelGGL(topo_kernel, dim3((unsigned)P), dim3((unsigned)topo_block_threads(N)),
                        topo_lds_bytes(N, C), stream, a);
+    if (prog && max_class(N) != CLS_R64) {
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(classify_kernel, dim3(1), dim3(1024), 0, stream, prog, a.prog_words, P,
+                           prog + pop_off(P, N, C, O));
+    }
     return hipGetLastError();
 }
 

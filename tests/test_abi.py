@@ -39,9 +39,13 @@ def test_program_bytes_and_invalid_dims():
     lib = _lib.lib()
     d = _lib.Dims(10, 50, 200, 17, 6)
     nb = lib.neat_program_bytes(ctypes.byref(d))
-    assert nb > 0 and nb % (256 * 10) == 0
+    # P per-genome programs of 256-byte multiples, then the population area
+    # (a 256-byte header and one word per genome, padded to 64 words)
     d1 = _lib.Dims(1, 50, 200, 17, 6)
-    assert lib.neat_program_bytes(ctypes.byref(d1)) * 10 == nb
+    nb1 = lib.neat_program_bytes(ctypes.byref(d1))
+    per = (nb1 - 512)
+    assert nb > 0 and per > 0 and per % 256 == 0
+    assert nb == 10 * per + 512
     for bad in [(1, 0, 4, 1, 1), (1, 8, 4, 0, 1), (1, 8, 4, 4, 5), (-1, 8, 4, 1, 1),
                 (1, 2000, 4, 1, 1), (1, 8, -1, 1, 1)]:
         db = _lib.Dims(*bad)

@@ -95,7 +95,7 @@ def test_tiny_config():
     _assert_outputs(y, y64, beta, "tiny")
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3])
 @pytest.mark.parametrize("P,B", [(300, 130), (64, 64), (37, 1), (5, 191)])
 def test_control_small_full_compare(P, B, variant):
     """Mixed activations/aggregations, several sample tiles and a ragged tail;
@@ -232,16 +232,19 @@ def test_all_genomes_rejected():
     assert np.isnan(y).all()
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2])
-@pytest.mark.parametrize("N,I,O", [(30, 5, 2), (33, 5, 2), (60, 40, 3), (62, 20, 3),
-                                   (63, 10, 4), (64, 10, 4), (48, 31, 1), (62, 45, 2),
-                                   (8, 3, 1), (47, 29, 2)])
+# Shapes: inputs filling most of the 64-slot class, N_max around the class
+# boundaries, and many outputs (live to the end) to force each slot class:
+# O = 70 -> 128 register slots, O = 150 -> 224, O = 240 -> LDS rows.
+SHAPES = [(30, 5, 2), (33, 5, 2), (60, 40, 3), (62, 20, 3), (63, 10, 4), (64, 10, 4),
+          (48, 31, 1), (62, 45, 2), (8, 3, 1), (47, 29, 2), (100, 10, 70), (130, 60, 20),
+          (200, 10, 150), (300, 20, 240)]
+
+
+@pytest.mark.parametrize("variant", [0, 1, 2, 3])
+@pytest.mark.parametrize("N,I,O", SHAPES)
 def test_forward_kernel_shapes(N, I, O, variant):
-    if variant == 1 and N > 62:
-        pytest.skip("the register store holds 64 value slots (N_max <= 62)")
-    """Both halves of the register-resident value vector (positions < 32 and
-    >= 32, inputs in either half), and the switch to the LDS kernel above 64
-    nodes."""
+    """Every value store and slot class: inputs spread over the value
+    vector, the class boundaries, and outputs beyond one group of eight."""
     rng = np.random.default_rng(N * 100 + I)
     P, B, C = 40, 150, 4 * N
     nodes = np.full((P, N, 5), np.nan, np.float32)
@@ -303,11 +306,81 @@ def test_device_activations_accuracy():
         assert np.array_equal(np.isnan(y[act, :, 0]), np.isnan(y64[act, :, 0])), act
 
 
-def test_register_and_lds_stores_agree_bitwise():
-    """The two value stores run the same operations in the same order, so
-    their outputs are identical bit for bit."""
+def _same_bits(a, b):
+    """Equal bit patterns, except that any NaN matches any NaN."""
+    nan = np.isnan(a)
+    return np.array_equal(nan, np.isnan(b)) and np.array_equal(a[~nan].view(np.uint32),
+                                                                 b[~nan].view(np.uint32))
+
+
+@pytest.mark.parametrize("which", ["control", "classes"])
+def test_value_stores_agree_bitwise(which):
+    """All value stores run the same operations in the same order, so their
+    outputs are identical bit for bit (registers with one or two samples per
+    lane, any slot class, and LDS rows)."""
     neat = _neat()
-    pop = synth.control(seed=31, P=200, B=150)
-    a = _gpu(pop.nodes, pop.conns, pop.I, pop.O, pop.inputs, variant=neat.FWD_REG)[3]
-    b = _gpu(pop.nodes, pop.conns, pop.I, pop.O, pop.inputs, variant=neat.FWD_LDS)[3]
-    assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+    if which == "control":
+        pop = synth.control(seed=31, P=200, B=150)
+        nodes, conns, I, O, x = pop.nodes, pop.conns, pop.I, pop.O, pop.inputs
+    else:
+        pops = synth.uneven(seed=9, n_pops=3, P_range=(20, 40), N_range=(150, 400),
+                            B_range=(70, 140))
+        pop = max(pops, key=lambda q: q.N_max)
+        nodes, conns, I, O, x = pop.nodes, pop.conns, pop.I, pop.O, pop.inputs
+    ys = [_gpu(nodes, conns, I, O, x, variant=v)[3]
+          for v in (neat.FWD_REG, neat.FWD_LDS, neat.FWD_REG2, neat.FWD_AUTO)]
+    for k in range(1, len(ys)):
+        assert _same_bits(ys[0], ys[k]), k
+
+
+def _max_live(nodes, conns, I, O, order_rows):
+    """Largest number of values held at once by a slot allocator that frees
+    a value after its last reader (the reader may reuse the slot), keeps
+    inputs from the start and outputs to the end."""
+    valid = ~np.isnan(nodes[:, 0])
+    key = {r: int(nodes[r, 0]) for r in np.nonzero(valid)[0]}
+    rows = [r for r in order_rows if r >= 0]
+    pos = {r: p for p, r in enumerate(rows)}
+    row_of = {k: r for r, k in key.items()}
+    n = len(rows)
+    last = {r: pos[r] for r in rows}
+    for c in conns:
+        if np.isnan(c[0]) or c[2] != 1.0:
+            continue
+        s, d = row_of[int(c[0])], row_of[int(c[1])]
+        last[s] = max(last[s], pos[d])
+    for r in rows:
+        if I <= key[r] < I + O:
+            last[r] = n
+    best = I
+    for p in range(I, n):
+        # values defined before p still needed after p, plus p itself;
+        # unread inputs are dropped once the first computed node runs
+        live = sum(1 for r in rows[:p] if last[r] > p) + 1
+        best = max(best, live)
+    return best
+
+
+def test_slot_allocation_is_the_largest_live_set():
+    """The program build's slot count equals the largest live set, and the
+    slot class follows from it (program header words)."""
+    neat = _neat()
+    pops = synth.uneven(seed=13, n_pops=4, P_range=(4, 8), N_range=(20, 300), B_range=(1, 2))
+    for pop in pops:
+        dev = torch.device("cuda:0")
+        tn = torch.from_numpy(pop.nodes).to(dev)
+        tc = torch.from_numpy(pop.conns).to(dev)
+        order, level, status, prog = neat.topo_sort(tn, tc, pop.I, pop.O)
+        d = neat.dims_of(tn, tc, pop.I, pop.O)
+        hdr = neat.program_headers(d, prog).cpu().numpy()
+        order = order.cpu().numpy()
+        for g in range(pop.P):
+            if status[g].item() != 0:
+                continue
+            if pop.N_max <= 62:
+                m = int((order[g] >= 0).sum())  # slot = position
+            else:
+                m = _max_live(pop.nodes[g], pop.conns[g], pop.I, pop.O, order[g])
+            assert hdr[g, 8] == m, (pop.N_max, g, hdr[g, 8], m)
+            cls = 0 if m <= 62 else 1 if m <= 126 else 2 if m <= 222 else 3
+            assert hdr[g, 6] == cls
