@@ -175,6 +175,49 @@ int neat_forward_ex(const neat_dims *dims, const void *program, const float *inp
 int neat_forward_grid(const neat_dims *dims, const void *program, int32_t side,
                       int64_t first, int32_t Q, float *outputs, void *stream);
 
+/*
+ * Batched path: many populations in one call (the paper evaluates a whole
+ * population as one tensor program, Section 3.3; this extends the batch
+ * across populations of different shapes).  Each item is one population:
+ * when nodes is non-NULL its transformation runs first (writing program and,
+ * when non-NULL, status), then its calculation on TENSOR inputs (grid_side =
+ * 0, as neat_forward) or on CPPN grid queries (grid_side > 0, as
+ * neat_forward_grid with Q = B).  The calculations of all items run as one
+ * launch per value-store kernel whose work units cover every population.
+ *
+ * The launches are recorded once into a HIP graph held by *plan: pass a
+ * plan set to NULL the first time; a later call with the same items (same
+ * bytes) replays the graph; other items rebuild it (the old plan is freed).
+ * The plan owns device memory (work-unit tables) and the graph; free it with
+ * neat_batch_plan_free.  A plan must not be used by two threads at once.
+ * All tensors are caller-owned device pointers as elsewhere; an item may be
+ * replayed with new contents in the same buffers.
+ * Errors: NEAT_E_INVALID (any item's arguments, message names the item),
+ * NEAT_E_TOO_LARGE (a genome's values exceed LDS), NEAT_E_NOMEM, NEAT_E_HIP.
+ * On error *plan is left as it was.
+ */
+typedef struct {
+    neat_dims dims;
+    const float *nodes;          /* [P][N_max][5], or NULL: program already built */
+    const float *conns;          /* [P][C_max][4] (read when nodes is non-NULL) */
+    uint32_t *status;            /* [P] or NULL */
+    void *program;               /* neat_program_bytes(&dims) bytes */
+    const float *inputs;         /* TENSOR mode: as for neat_forward; else unused */
+    int64_t input_genome_stride; /* TENSOR mode */
+    int32_t B;                   /* vectors (TENSOR) or queries (GRID) per genome */
+    int32_t grid_side;           /* 0: TENSOR mode; else the grid side (I must be 5) */
+    int64_t grid_first;          /* GRID mode: first query */
+    float *outputs;              /* [P][B][O] */
+} neat_batch_item;
+
+typedef struct neat_batch_plan neat_batch_plan;
+
+int neat_forward_batch(const neat_batch_item *items, int32_t n, neat_batch_plan **plan,
+                       void *stream);
+void neat_batch_plan_free(neat_batch_plan *plan);
+/* Kernel launches one replay of the plan makes (0 for NULL). */
+int32_t neat_batch_plan_launches(const neat_batch_plan *plan);
+
 /* Message for the calling thread's most recent error ("" if none). */
 const char *neat_last_error(void);
 

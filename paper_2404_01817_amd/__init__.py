@@ -11,7 +11,8 @@ from __future__ import annotations
 import ctypes
 from typing import Optional, Tuple
 
-from ._lib import FWD_AUTO, FWD_LDS, FWD_REG, FWD_REG2, Dims, NeatError, check, lib
+from ._lib import (FWD_AUTO, FWD_LDS, FWD_REG, FWD_REG2, BatchItem, Dims, NeatError, check,
+                   lib)
 
 __all__ = ["Dims", "NeatError", "dims_of", "program_bytes", "topo_sort", "forward",
            "forward_grid"]
@@ -122,3 +123,58 @@ def forward_grid(dims: Dims, program, side: int, first: int, Q: int, outputs=Non
     check(lib().neat_forward_grid(ctypes.byref(dims), _ptr(program), side, first, Q,
                                   _ptr(outputs), _stream(stream)))
     return outputs
+
+
+def batch_item(dims: Dims, program, outputs, inputs=None, B: int = 0,
+               shared_inputs: bool = False, nodes=None, conns=None, status=None,
+               grid_side: int = 0, grid_first: int = 0) -> BatchItem:
+    """One population of a batch (neat_batch_item).  With nodes/conns the
+    batch also runs its transformation into ``program`` (and ``status``).
+    TENSOR mode: inputs [P,B,I] (or [B,I] when shared); GRID mode
+    (grid_side > 0): B queries from grid_first."""
+    if grid_side:
+        stride = 0
+    else:
+        _dev_f32(inputs, "inputs")
+        stride = 0 if shared_inputs else B * dims.I
+    def addr(t):
+        return None if t is None else t.data_ptr()
+
+    it = BatchItem()
+    it.dims = dims
+    it.nodes, it.conns, it.status = addr(nodes), addr(conns), addr(status)
+    it.program = addr(program)
+    it.inputs = addr(inputs)
+    it.input_genome_stride = stride
+    it.B = B
+    it.grid_side = grid_side
+    it.grid_first = grid_first
+    it.outputs = addr(outputs)
+    return it
+
+
+class BatchPlan:
+    """A batch recorded into a HIP graph by neat_forward_batch; running it
+    again with the same items replays the graph."""
+
+    def __init__(self):
+        self._h = ctypes.c_void_p(None)
+
+    def run(self, items, stream=None):
+        arr = (BatchItem * len(items))(*items)
+        check(lib().neat_forward_batch(arr, len(items), ctypes.byref(self._h), _stream(stream)))
+
+    @property
+    def launches(self) -> int:
+        return int(lib().neat_batch_plan_launches(self._h))
+
+    def free(self):
+        if self._h.value:
+            lib().neat_batch_plan_free(self._h)
+            self._h = ctypes.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass

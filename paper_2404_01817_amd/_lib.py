@@ -29,6 +29,15 @@ class Dims(ctypes.Structure):
                 ("C_max", ctypes.c_int32), ("I", ctypes.c_int32), ("O", ctypes.c_int32)]
 
 
+class BatchItem(ctypes.Structure):
+    """neat_batch_item."""
+    _fields_ = [("dims", Dims), ("nodes", ctypes.c_void_p), ("conns", ctypes.c_void_p),
+                ("status", ctypes.c_void_p), ("program", ctypes.c_void_p),
+                ("inputs", ctypes.c_void_p), ("input_genome_stride", ctypes.c_int64),
+                ("B", ctypes.c_int32), ("grid_side", ctypes.c_int32),
+                ("grid_first", ctypes.c_int64), ("outputs", ctypes.c_void_p)]
+
+
 _lib = None
 
 # exported symbol -> (restype, argtypes)
@@ -40,6 +49,10 @@ SIGNATURES = {
     "neat_forward": (_i32, [ctypes.POINTER(Dims), _vp, _vp, _i64, _i32, _vp, _vp]),
     "neat_forward_ex": (_i32, [ctypes.POINTER(Dims), _vp, _vp, _i64, _i32, _vp, _i32, _vp]),
     "neat_forward_grid": (_i32, [ctypes.POINTER(Dims), _vp, _i32, _i64, _i32, _vp, _vp]),
+    "neat_forward_batch": (_i32, [ctypes.POINTER(BatchItem), _i32,
+                                  ctypes.POINTER(ctypes.c_void_p), _vp]),
+    "neat_batch_plan_free": (None, [_vp]),
+    "neat_batch_plan_launches": (_i32, [_vp]),
     "neat_last_error": (ctypes.c_char_p, []),
     "neat_strerror": (ctypes.c_char_p, [_i32]),
 }

@@ -9,13 +9,17 @@
 #include <mutex>
 #include <string>
 
+#include "abi.h"
 #include "launch.h"
 #include "neat.h"
 #include "program.h"
 
 namespace {
-
 thread_local std::string g_last_error;
+}  // namespace
+
+namespace neat {
+namespace abi {
 
 int fail(int code, const char *fmt, ...) {
     char buf[512];
@@ -57,7 +61,66 @@ int check_dims(const neat_dims *d) {
 
 bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
 
-}  // namespace
+int check_topo_args(const neat_dims *d, const float *nodes, const float *conns,
+                    const void *program) {
+    if (d->P > 0 && !nodes) return fail(NEAT_E_INVALID, "nodes is NULL");
+    if (d->P > 0 && d->C_max > 0 && !conns) return fail(NEAT_E_INVALID, "conns is NULL");
+    if (conns && !aligned(conns, 16)) return fail(NEAT_E_INVALID, "conns must be 16-byte aligned");
+    if (program && !aligned(program, 16))
+        return fail(NEAT_E_INVALID, "program must be 16-byte aligned");
+    const size_t lds = topo_lds_bytes(d->N_max, d->C_max);
+    if (lds > max_lds_bytes())
+        return fail(NEAT_E_INVALID,
+                    "N_max=%d, C_max=%d needs %zu B of LDS per genome, device allows %zu",
+                    d->N_max, d->C_max, lds, max_lds_bytes());
+    return NEAT_OK;
+}
+
+int check_forward_args(const neat_dims *d, const void *program, const float *inputs,
+                       int64_t stride, int32_t B, float *outputs, bool grid, int32_t side,
+                       int64_t first) {
+    if (B < 0) return fail(NEAT_E_INVALID, "B = %d < 0", B);
+    if (grid) {
+        if (d->I != 5) return fail(NEAT_E_INVALID, "grid queries need I = 5, got %d", d->I);
+        if (side < 2 || side > 256)
+            return fail(NEAT_E_INVALID, "side = %d outside [2, 256]", side);
+        const long long nq = (long long)side * side * side * side;
+        if (first < 0 || first + B > nq)
+            return fail(NEAT_E_INVALID, "queries [%lld, %lld) outside [0, %lld)",
+                        (long long)first, (long long)first + B, nq);
+    } else {
+        if (stride < 0) return fail(NEAT_E_INVALID, "negative input_genome_stride");
+        if (stride != 0 && stride < (int64_t)B * d->I)
+            return fail(NEAT_E_INVALID, "input_genome_stride %lld < B * I = %lld",
+                        (long long)stride, (long long)B * d->I);
+    }
+    if (d->P == 0 || B == 0) return NEAT_OK;
+    if (!program || !outputs || (!grid && !inputs))
+        return fail(NEAT_E_INVALID, "program, inputs or outputs is NULL");
+    if (!aligned(program, 16)) return fail(NEAT_E_INVALID, "program must be 16-byte aligned");
+    const long long tiles = (long long)d->P * ((B + 63) / 64);
+    if (tiles >= (1ll << 31))
+        return fail(NEAT_E_INVALID, "P * B too large for one launch (%lld tiles)", tiles);
+    return NEAT_OK;
+}
+
+FwdJob make_job(const neat_dims *d, const void *program, const float *inputs, int64_t stride,
+                int32_t B, float *outputs, int32_t side, int64_t first) {
+    FwdJob job{};
+    job.prog = (const int32_t *)program;
+    job.inputs = inputs;
+    job.outputs = outputs;
+    job.gstride = stride;
+    job.first = first;
+    job.P = d->P, job.N = d->N_max, job.C = d->C_max, job.I = d->I, job.O = d->O, job.B = B;
+    job.side = side;
+    return job;
+}
+
+}  // namespace abi
+}  // namespace neat
+
+using namespace neat::abi;
 
 extern "C" {
 
@@ -93,16 +156,8 @@ int neat_topo_sort(const neat_dims *d, const float *nodes, const float *conns, i
     int rc = check_dims(d);
     if (rc != NEAT_OK) return rc;
     if (d->P == 0) return NEAT_OK;
-    if (!nodes || (!conns && d->C_max > 0))
-        return fail(NEAT_E_INVALID, "nodes or conns is NULL");
-    if (!aligned(conns, 16)) return fail(NEAT_E_INVALID, "conns must be 16-byte aligned");
-    if (program && !aligned(program, 16))
-        return fail(NEAT_E_INVALID, "program must be 16-byte aligned");
-    const size_t lds = neat::topo_lds_bytes(d->N_max, d->C_max);
-    if (lds > max_lds_bytes())
-        return fail(NEAT_E_INVALID,
-                    "N_max=%d, C_max=%d needs %zu B of LDS per genome, device allows %zu",
-                    d->N_max, d->C_max, lds, max_lds_bytes());
+    rc = check_topo_args(d, nodes, conns, program);
+    if (rc != NEAT_OK) return rc;
     hipError_t e = neat::launch_topo(d->P, d->N_max, d->C_max, d->I, d->O, nodes, conns, order,
                                      level, status, (int32_t *)program, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "topo_sort launch");
@@ -110,24 +165,19 @@ int neat_topo_sort(const neat_dims *d, const float *nodes, const float *conns, i
 }
 
 static int forward_common(const neat_dims *d, const void *program, const float *inputs,
-                          int64_t input_genome_stride, int32_t B, float *outputs, int variant,
-                          bool grid, int32_t side, int64_t first, void *stream) {
+                          int64_t stride, int32_t B, float *outputs, int variant, bool grid,
+                          int32_t side, int64_t first, void *stream) {
+    int rc = check_dims(d);
+    if (rc != NEAT_OK) return rc;
     if (variant < NEAT_FWD_AUTO || variant > NEAT_FWD_REG2)
         return fail(NEAT_E_INVALID, "unknown forward variant %d", variant);
-    const long long tiles = (long long)d->P * ((B + 63) / 64);
-    if (tiles >= (1ll << 31))
-        return fail(NEAT_E_INVALID, "P * B too large for one launch (%lld tiles)", tiles);
-    neat::FwdJob job{};
-    job.prog = (const int32_t *)program;
-    job.inputs = inputs;
-    job.outputs = outputs;
-    job.gstride = input_genome_stride;
-    job.first = first;
-    job.P = d->P, job.N = d->N_max, job.C = d->C_max, job.I = d->I, job.O = d->O, job.B = B;
-    job.side = grid ? side : 0;
+    rc = check_forward_args(d, program, inputs, stride, B, outputs, grid, side, first);
+    if (rc != NEAT_OK || d->P == 0 || B == 0) return rc;
+    const neat::FwdJob job =
+        make_job(d, program, inputs, stride, B, outputs, grid ? side : 0, first);
     std::vector<neat::FwdKernelLaunch> plan;
     char err[256] = "";
-    int rc = neat::forward_plan(&job, 1, variant, max_lds_bytes(), plan, err, sizeof(err));
+    rc = neat::forward_plan(&job, 1, variant, max_lds_bytes(), plan, err, sizeof(err));
     if (rc != NEAT_OK) return fail(rc, "%s", err);
     for (const neat::FwdKernelLaunch &k : plan) {
         hipError_t e = neat::forward_launch(k, nullptr, (hipStream_t)stream);
@@ -139,17 +189,6 @@ static int forward_common(const neat_dims *d, const void *program, const float *
 int neat_forward_ex(const neat_dims *d, const void *program, const float *inputs,
                     int64_t input_genome_stride, int32_t B, float *outputs, int32_t variant,
                     void *stream) {
-    int rc = check_dims(d);
-    if (rc != NEAT_OK) return rc;
-    if (B < 0) return fail(NEAT_E_INVALID, "B = %d < 0", B);
-    if (input_genome_stride < 0) return fail(NEAT_E_INVALID, "negative input_genome_stride");
-    if (input_genome_stride != 0 && input_genome_stride < (int64_t)B * d->I)
-        return fail(NEAT_E_INVALID, "input_genome_stride %lld < B * I = %lld",
-                    (long long)input_genome_stride, (long long)B * d->I);
-    if (d->P == 0 || B == 0) return NEAT_OK;
-    if (!program || !inputs || !outputs)
-        return fail(NEAT_E_INVALID, "program, inputs or outputs is NULL");
-    if (!aligned(program, 16)) return fail(NEAT_E_INVALID, "program must be 16-byte aligned");
     return forward_common(d, program, inputs, input_genome_stride, B, outputs, variant, false, 0,
                           0, stream);
 }
@@ -162,17 +201,6 @@ int neat_forward(const neat_dims *d, const void *program, const float *inputs,
 
 int neat_forward_grid(const neat_dims *d, const void *program, int32_t side, int64_t first,
                       int32_t Q, float *outputs, void *stream) {
-    int rc = check_dims(d);
-    if (rc != NEAT_OK) return rc;
-    if (d->I != 5) return fail(NEAT_E_INVALID, "grid queries need I = 5, got %d", d->I);
-    if (side < 2 || side > 256) return fail(NEAT_E_INVALID, "side = %d outside [2, 256]", side);
-    const long long nq = (long long)side * side * side * side;
-    if (Q < 0 || first < 0 || first + Q > nq)
-        return fail(NEAT_E_INVALID, "queries [%lld, %lld) outside [0, %lld)", (long long)first,
-                    (long long)first + Q, nq);
-    if (d->P == 0 || Q == 0) return NEAT_OK;
-    if (!program || !outputs) return fail(NEAT_E_INVALID, "program or outputs is NULL");
-    if (!aligned(program, 16)) return fail(NEAT_E_INVALID, "program must be 16-byte aligned");
     return forward_common(d, program, nullptr, 0, Q, outputs, NEAT_FWD_AUTO, true, side, first,
                           stream);
 }

@@ -1,0 +1,142 @@
+"""GPU: the batched path (neat_forward_batch) against single-population
+calls and the oracle; graph replays."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2404_01817_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _neat():
+    import paper_2404_01817_amd as neat
+    return neat
+
+
+def _same_bits(a, b):
+    nan = np.isnan(a)
+    return np.array_equal(nan, np.isnan(b)) and np.array_equal(a[~nan].view(np.uint32),
+                                                                 b[~nan].view(np.uint32))
+
+
+class _Pop:
+    """Device buffers of one population of a batch."""
+
+    def __init__(self, pop, grid=None):
+        neat = _neat()
+        dev = torch.device("cuda:0")
+        self.pop = pop
+        self.nodes = torch.from_numpy(pop.nodes).to(dev)
+        self.conns = torch.from_numpy(pop.conns).to(dev)
+        self.d = neat.dims_of(self.nodes, self.conns, pop.I, pop.O)
+        self.prog = torch.empty((neat.program_bytes(self.d) // 4,), dtype=torch.int32, device=dev)
+        self.status = torch.empty((pop.P,), dtype=torch.int32, device=dev)
+        self.grid = grid
+        if grid is None:
+            self.x = torch.from_numpy(pop.inputs).to(dev)
+            self.B = pop.B
+        else:
+            self.x = None
+            self.B = grid[2]
+        self.y = torch.full((pop.P, self.B, pop.O), 7.0, dtype=torch.float32, device=dev)
+
+    def item(self, with_transform=True):
+        neat = _neat()
+        kw = dict(nodes=self.nodes, conns=self.conns, status=self.status) if with_transform else {}
+        if self.grid is None:
+            return neat.batch_item(self.d, self.prog, self.y, inputs=self.x, B=self.B, **kw)
+        side, first, Q = self.grid
+        return neat.batch_item(self.d, self.prog, self.y, B=Q, grid_side=side, grid_first=first,
+                               **kw)
+
+    def single(self):
+        """Outputs of the single-population calls."""
+        neat = _neat()
+        _, _, _, prog = neat.topo_sort(self.nodes, self.conns, self.pop.I, self.pop.O,
+                                       want_order=False)
+        if self.grid is None:
+            y = neat.forward(self.d, prog, self.x, self.B)
+        else:
+            y = neat.forward_grid(self.d, prog, *self.grid)
+        torch.cuda.synchronize()
+        return y.cpu().numpy()
+
+
+def _uneven(seed, n, N_range=(10, 300)):
+    return synth.uneven(seed=seed, n_pops=n, P_range=(3, 60), N_range=N_range, B_range=(1, 300))
+
+
+def test_batch_matches_single_calls_and_oracle():
+    """A batch of uneven populations (every slot class, TENSOR and GRID
+    items) gives the same bits as one call per population, and the
+    oracle's values within the parity rule."""
+    neat = _neat()
+    pops = [_Pop(p) for p in _uneven(21, 7)]
+    cppn = synth.cppn(seed=4, P=12)
+    pops.append(_Pop(cppn, grid=(16, 1000, 700)))
+    plan = neat.BatchPlan()
+    plan.run([p.item() for p in pops])
+    torch.cuda.synchronize()
+    assert plan.launches >= len(pops)
+    for k, p in enumerate(pops):
+        y = p.y.cpu().numpy()
+        assert _same_bits(y, p.single()), k
+        if p.grid is None:
+            y64, beta = oracle.forward(p.pop.nodes, p.pop.conns, p.pop.inputs, p.pop.I, p.pop.O)
+        else:
+            q = synth.grid_queries(p.grid[1], p.grid[2])
+            y64, beta = oracle.forward(p.pop.nodes, p.pop.conns, q, p.pop.I, p.pop.O,
+                                       shared_inputs=True)
+        ok, stats = oracle.within_tolerance(y, y64, beta)
+        assert stats["n_fail"] == 0, (k, stats)
+        st = p.status.cpu().numpy().astype(np.uint32)
+        assert np.array_equal(st, oracle.transform(p.pop.nodes, p.pop.conns, p.pop.I,
+                                                   p.pop.O)[2])
+    plan.free()
+
+
+def test_batch_graph_replays():
+    """Replays of the recorded graph, with eager work and new input contents
+    between them, each equal the eager single-population results; changing
+    the items rebuilds the plan."""
+    neat = _neat()
+    pops = [_Pop(p) for p in _uneven(22, 5, N_range=(10, 150))]
+    plan = neat.BatchPlan()
+    items = [p.item() for p in pops]
+    rng = np.random.default_rng(3)
+    for rep in range(4):
+        for p in pops:
+            p.x.copy_(torch.from_numpy(rng.standard_normal(tuple(p.x.shape)).astype(np.float32)))
+            p.y.fill_(7.0)
+        plan.run(items)
+        torch.cuda.synchronize()
+        # eager work between replays
+        junk = torch.randn(1 << 20, device="cuda:0").sum().item()
+        assert np.isfinite(junk)
+        for k, p in enumerate(pops):
+            assert _same_bits(p.y.cpu().numpy(), p.single()), (rep, k)
+    n0 = plan.launches
+    # forward only (programs already built), a different item list
+    items2 = [p.item(with_transform=False) for p in pops[:3]]
+    plan.run(items2)
+    torch.cuda.synchronize()
+    assert plan.launches < n0
+    for p in pops[:3]:
+        assert _same_bits(p.y.cpu().numpy(), p.single())
+    plan.free()
+
+
+def test_batch_argument_errors():
+    neat = _neat()
+    pops = [_Pop(p) for p in _uneven(23, 2, N_range=(10, 40))]
+    items = [p.item() for p in pops]
+    items[1].input_genome_stride = 1  # smaller than B * I
+    plan = neat.BatchPlan()
+    with pytest.raises(neat.NeatError, match="item 1"):
+        plan.run(items)
+    assert plan.launches == 0
