@@ -37,6 +37,14 @@ def parse():
                     help="genomes of the workload the CPU oracle is timed on")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quiet", action="store_true")
+    ap.add_argument("--workloads", default="control,batched,served,cppn",
+                    help="comma list: control (the headline line), batched (64 uneven "
+                         "populations in one recorded batch), served (Poisson request "
+                         "stream over 128 resident populations), cppn (grid queries)")
+    ap.add_argument("--served-seconds", type=float, default=20.0,
+                    help="length of the served request stream (latency counted after "
+                         "the first quarter)")
+    ap.add_argument("--served-rate", type=float, default=200.0, help="requests per second")
     ap.add_argument("--copy-probe", action="store_true",
                     help="after the timed region, copy 256 MiB once (a plain copy kernel "
                          "of known size, which calibrates HBM byte counters)")
@@ -56,6 +64,175 @@ def program_bytes_read(O, n_valid, n_edges, I):
     with the first edges inline); this counts what the method needs."""
     n_comp = np.maximum(n_valid - I, 0)
     return int((64 + 4 * O + 16 * n_comp + 8 * n_edges).sum())
+
+
+def bench_batched(args, torch, neat, synth):
+    """64 uneven populations (P, N_max, B log-uniform; C_max = 4 N_max) run
+    as one recorded batch: transformation + calculation of every population
+    per replay, and the calculation alone."""
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    pops = synth.uneven(seed=2)
+    log(args, "generated %d uneven populations in %.1fs" % (len(pops), time.time() - t0))
+    bufs = []
+    for pop in pops:
+        tn = torch.from_numpy(pop.nodes).to(dev)
+        tc = torch.from_numpy(pop.conns).to(dev)
+        tx = torch.from_numpy(pop.inputs).to(dev)
+        d = neat.dims_of(tn, tc, pop.I, pop.O)
+        prog = torch.empty((neat.program_bytes(d) // 4,), dtype=torch.int32, device=dev)
+        st = torch.empty((pop.P,), dtype=torch.int32, device=dev)
+        y = torch.empty((pop.P, pop.B, pop.O), dtype=torch.float32, device=dev)
+        bufs.append((pop, d, tn, tc, tx, prog, st, y))
+    full = [neat.batch_item(d, prog, y, inputs=tx, B=pop.B, nodes=tn, conns=tc, status=st)
+            for pop, d, tn, tc, tx, prog, st, y in bufs]
+    fwd_only = [neat.batch_item(d, prog, y, inputs=tx, B=pop.B)
+                for pop, d, tn, tc, tx, prog, st, y in bufs]
+    stream = torch.cuda.current_stream()
+    res = {}
+    for name, items in (("end_to_end", full), ("forward", fwd_only)):
+        plan = neat.BatchPlan()
+        for _ in range(max(1, args.warmup)):
+            plan.run(items)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.steps):
+            plan.run(items)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        res[name] = (e0.elapsed_time(e1) / args.steps, plan.launches)
+        plan.free()
+    units = sum(pop.P * pop.B for pop in pops)
+    fwd_bytes = 0
+    for pop, d, tn, tc, tx, prog, st, y in bufs:
+        hdr = neat.program_headers(d, prog).cpu().numpy()
+        fwd_bytes += pop.P * pop.B * (pop.I + pop.O) * 4
+        fwd_bytes += program_bytes_read(pop.O, hdr[:, 0], hdr[:, 7], pop.I)
+    ms_e2e, n_e2e = res["end_to_end"]
+    ms_fwd, n_fwd = res["forward"]
+    achieved = fwd_bytes / (ms_fwd / 1e3) / 1e9
+    return {
+        "workload": "uneven batch: 64 populations, P log-uniform [100, 4096], N_max "
+                    "log-uniform [10, 400], C_max = 4 N_max, B log-uniform [1, 512]",
+        "genomes": sum(pop.P for pop in pops), "genome_inputs": units,
+        "ms_end_to_end": round(ms_e2e, 4), "launches_end_to_end": n_e2e,
+        "value_end_to_end": round(units / (ms_e2e / 1e3), 1),
+        "ms_forward": round(ms_fwd, 4), "launches_forward": n_fwd,
+        "value_forward": round(units / (ms_fwd / 1e3), 1), "unit": "genome-inputs/s",
+        "roofline_forward": {"bound": "hbm", "achieved": round(achieved, 1),
+                             "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                             "frac": round(achieved / HBM_PEAK_GBS, 4),
+                             "algorithmic_bytes_per_launch": fwd_bytes},
+    }
+
+
+def bench_served(args, torch, neat, synth):
+    """Poisson request stream over 128 resident populations (P log-uniform
+    [64, 8192], N_max log-uniform [8, 256], C_max = 4 N_max); each request
+    takes a uniform population and B log-uniform [1, 256], inputs cut from
+    a 4 GiB pool of N(0,1) at a seed-derived offset.  Latency = completion
+    - scheduled arrival, over arrivals after the first quarter."""
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    pool = synth.served_pool(seed=3)
+    log(args, "generated %d resident populations in %.1fs" % (len(pool), time.time() - t0))
+    server = neat.Server(cap_bytes=64 << 30, max_inflight=4)
+    ids = []
+    for pop in pool:
+        tn = torch.from_numpy(pop.nodes).to(dev)
+        tc = torch.from_numpy(pop.conns).to(dev)
+        ids.append(server.register(tn, tc, pop.I, pop.O))
+        del tn, tc
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(3)
+    xpool = torch.randn((1 << 30,), generator=gen, device=dev)  # 4 GiB
+    ypool = torch.empty((1 << 30,), device=dev)
+    rng = np.random.default_rng(3)
+    n_req = int(args.served_rate * args.served_seconds)
+    arrivals = np.cumsum(rng.exponential(1.0 / args.served_rate, n_req))
+    which = rng.integers(0, len(pool), n_req)
+    Bs = np.rint(np.exp(rng.uniform(0.0, np.log(256.0), n_req))).astype(np.int64)
+    torch.cuda.synchronize()
+    server.reset_stats()
+    pending = {}  # ticket -> (k, output span end, submit delay)
+    done = []     # (k, latency_s)
+    y_at = 0
+    t_start = time.perf_counter()
+
+    def drain(block_until=None):
+        for t in list(pending):
+            r = server.poll(t)
+            if r is not None:
+                k, _, delay = pending.pop(t)
+                done.append((k, delay + (r.t_done_ns - r.t_submit_ns) * 1e-9))
+
+    for k in range(n_req):
+        pop, B = pool[which[k]], int(Bs[k])
+        nx, ny = pop.P * B * pop.I, pop.P * B * pop.O
+        xo = int(rng.integers(0, xpool.numel() - nx))
+        if y_at + ny > ypool.numel():
+            while pending:  # wrap the output pool once earlier requests are done
+                drain()
+            y_at = 0
+        while True:
+            now = time.perf_counter() - t_start
+            if now >= arrivals[k]:
+                break
+            drain()
+            if arrivals[k] - now > 2e-4:
+                time.sleep(1e-4)
+        t = server.submit(ids[which[k]], ypool[y_at:y_at + ny], inputs=xpool[xo:xo + nx],
+                          B=B, I=pop.I, tag=k)
+        pending[t] = (k, y_at + ny, time.perf_counter() - t_start - arrivals[k])
+        y_at += ny
+    while pending:
+        drain()
+    wall = time.perf_counter() - t_start
+    st = server.stats()
+    server.close()
+    lat = np.array([l for k, l in done if arrivals[k] >= 0.25 * args.served_seconds])
+    gi = int(sum(pool[which[k]].P * int(Bs[k]) for k in range(n_req)))
+    return {
+        "workload": "served: Poisson %.0f req/s for %.0f s over 128 resident populations "
+                    "(P log-uniform [64, 8192], N_max log-uniform [8, 256], C_max = 4 N_max), "
+                    "B log-uniform [1, 256]" % (args.served_rate, args.served_seconds),
+        "requests": n_req, "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
+        "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
+        "latency_counted": int(len(lat)), "genome_inputs": gi,
+        "throughput": round(gi / wall, 1), "unit": "genome-inputs/s",
+        "batches": int(st.batches), "mean_requests_per_batch": round(n_req / max(1, st.batches), 2),
+    }
+
+
+def bench_cppn(args, torch, neat, synth):
+    """CPPN substrate queries: P = 1000 genomes (I = 5, O = 1, N_max = 30,
+    C_max = 120, sin/gaussian/abs/tanh/sigmoid, sum) on all 65536 pairs of a
+    16 x 16 grid, inputs generated in the kernel."""
+    dev = torch.device("cuda:0")
+    pop = synth.cppn()
+    tn = torch.from_numpy(pop.nodes).to(dev)
+    tc = torch.from_numpy(pop.conns).to(dev)
+    d = neat.dims_of(tn, tc, pop.I, pop.O)
+    _, _, st, prog = neat.topo_sort(tn, tc, pop.I, pop.O, want_order=False)
+    Q = 65536
+    y = torch.empty((pop.P, Q, pop.O), device=dev)
+    for _ in range(max(1, args.warmup)):
+        neat.forward_grid(d, prog, 16, 0, Q, outputs=y)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.steps):
+        neat.forward_grid(d, prog, 16, 0, Q, outputs=y)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    units = pop.P * Q
+    return {"workload": "cppn: P=1000, N_max=30, C_max=120, I=5, O=1, 65536 grid queries "
+                        "per genome generated in the kernel",
+            "ms": round(ms, 4), "value": round(units / (ms / 1e3), 1),
+            "unit": "genome-inputs/s", "output_GBps": round(units * 4 / (ms / 1e3) / 1e9, 1)}
 
 
 def main():
@@ -171,6 +348,11 @@ def main():
                          "transformation + calculation, single thread (%.1f s)"
                          % (g, pop.B, dt)}
 
+    workloads = set(args.workloads.split(","))
+    batched = bench_batched(args, torch, neat, synth) if "batched" in workloads else None
+    served = bench_served(args, torch, neat, synth) if "served" in workloads else None
+    cppn = bench_cppn(args, torch, neat, synth) if "cppn" in workloads else None
+
     res = {
         "metric": "genome-input forwards/s", "value": round(value, 1),
         "unit": "genome-inputs/s", "n_gpus": 1, "steps": args.steps,
@@ -187,6 +369,9 @@ def main():
         "rejected_genomes": n_bad,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "batched": batched,
+        "served": served,
+        "cppn": cppn,
     }
     print(json.dumps(res), flush=True)
 

@@ -218,6 +218,83 @@ void neat_batch_plan_free(neat_batch_plan *plan);
 /* Kernel launches one replay of the plan makes (0 for NULL). */
 int32_t neat_batch_plan_launches(const neat_batch_plan *plan);
 
+/*
+ * Served path: resident populations and continuous batching.
+ *
+ * neat_server_register copies a population's encoding into library-owned
+ * device memory and runs its transformation once (Section 3.3: transform
+ * once, calculate many times); requests then name it by pop_id.
+ * neat_submit queues a calculation request and returns at once with a
+ * ticket.  A scheduler thread admits queued requests in arrival order while
+ * the bytes they touch (inputs, outputs and a small work-unit table per
+ * request, counted against cap_bytes) fit and fewer than max_inflight
+ * batches run; everything admitted together forms one batch (one launch per
+ * value-store kernel, as neat_forward_batch) on the next of max_inflight
+ * streams, so consecutive batches overlap on the device.  neat_poll reports
+ * a request's completion (and forgets the ticket once it reported done).
+ *
+ * Request tensors are caller-owned device pointers that must stay valid
+ * until neat_poll reports the request done.  Results equal those of
+ * neat_forward / neat_forward_grid for the same population and inputs, bit
+ * for bit, whatever else shares the batch.  All server calls are
+ * thread-safe.  Times are nanoseconds on a monotonic clock since the server
+ * was created.
+ */
+#define NEAT_INPUT_TENSOR 0 /* inputs as for neat_forward */
+#define NEAT_INPUT_GRID 1   /* CPPN grid queries as for neat_forward_grid, Q = B */
+
+typedef struct {
+    int32_t device;          /* HIP device index */
+    int32_t max_inflight;    /* batches running at once, 1..16 (one stream each) */
+    uint64_t cap_bytes;      /* admission cap on the bytes of running requests */
+} neat_server_cfg;
+
+typedef struct neat_server neat_server;
+
+typedef struct {
+    int32_t pop_id;              /* from neat_server_register */
+    int32_t input_mode;          /* NEAT_INPUT_TENSOR or NEAT_INPUT_GRID */
+    const float *inputs;         /* TENSOR: [P or 1][B][I] with input_genome_stride */
+    int64_t input_genome_stride; /* TENSOR: 0 = shared inputs, else >= B * I */
+    int32_t B;                   /* vectors (TENSOR) or queries (GRID) per genome */
+    int32_t grid_side;           /* GRID: 2..256 (the population's I must be 5) */
+    int64_t grid_first;          /* GRID: first query */
+    float *outputs;              /* [P][B][O] */
+    uint64_t tag;                /* returned in the result */
+} neat_request;
+
+typedef struct {
+    int32_t status;      /* NEAT_OK, or the error that ended the request (NEAT_E_SHUTDOWN
+                            for requests still queued when the server was destroyed) */
+    uint64_t tag;
+    int64_t t_submit_ns, t_admit_ns, t_done_ns;
+} neat_result;
+
+typedef struct {
+    uint64_t submitted, admitted, completed, rejected, batches, queued;
+    uint64_t genome_inputs;  /* completed P * B over all requests */
+    double p50_ms, p99_ms;   /* latency t_done - t_submit of completed requests */
+    double throughput;       /* genome_inputs / (last completion - first submission) per s */
+} neat_stats;
+
+/* Errors: NEAT_E_INVALID (bad cfg or device), NEAT_E_NOMEM, NEAT_E_HIP. */
+int neat_server_create(const neat_server_cfg *cfg, neat_server **server);
+/* Cancels queued requests, waits for running batches, frees everything. */
+int neat_server_destroy(neat_server *server);
+/* dims, nodes, conns as for neat_topo_sort (device pointers, read once).
+ * Genomes the transformation rejects give NaN outputs as usual. */
+int neat_server_register(neat_server *server, const neat_dims *dims, const float *nodes,
+                         const float *conns, int32_t *pop_id);
+/* Errors: NEAT_E_INVALID (arguments as neat_forward / neat_forward_grid),
+ * NEAT_E_TOO_LARGE (the request alone exceeds cap_bytes), NEAT_E_SHUTDOWN. */
+int neat_submit(neat_server *server, const neat_request *request, uint64_t *ticket);
+/* NEAT_OK (result filled, ticket forgotten), NEAT_PENDING, or
+ * NEAT_E_UNKNOWN_TICKET.  Never blocks. */
+int neat_poll(neat_server *server, uint64_t ticket, neat_result *result);
+/* Counters and latency percentiles since creation or the last reset. */
+int neat_server_stats(neat_server *server, neat_stats *stats);
+int neat_server_reset_stats(neat_server *server);
+
 /* Message for the calling thread's most recent error ("" if none). */
 const char *neat_last_error(void);
 

@@ -11,8 +11,8 @@ from __future__ import annotations
 import ctypes
 from typing import Optional, Tuple
 
-from ._lib import (FWD_AUTO, FWD_LDS, FWD_REG, FWD_REG2, BatchItem, Dims, NeatError, check,
-                   lib)
+from ._lib import (FWD_AUTO, FWD_LDS, FWD_REG, FWD_REG2, INPUT_GRID, INPUT_TENSOR, BatchItem,
+                   Dims, NeatError, Request, Result, ServerCfg, Stats, check, lib)
 
 __all__ = ["Dims", "NeatError", "dims_of", "program_bytes", "topo_sort", "forward",
            "forward_grid"]
@@ -176,5 +176,81 @@ class BatchPlan:
     def __del__(self):
         try:
             self.free()
+        except Exception:
+            pass
+
+
+class Server:
+    """Resident populations and continuous batching (neat_server_*)."""
+
+    def __init__(self, device: int = 0, cap_bytes: int = 64 << 30, max_inflight: int = 4):
+        cfg = ServerCfg(device, max_inflight, cap_bytes)
+        self._h = ctypes.c_void_p(None)
+        check(lib().neat_server_create(ctypes.byref(cfg), ctypes.byref(self._h)))
+
+    def register(self, nodes, conns, I: int, O: int) -> int:
+        """Copy a population (device tensors) into the server and transform
+        it once; returns its id."""
+        _dev_f32(nodes, "nodes")
+        _dev_f32(conns, "conns")
+        d = dims_of(nodes, conns, I, O)
+        pid = ctypes.c_int32(-1)
+        check(lib().neat_server_register(self._h, ctypes.byref(d), _ptr(nodes), _ptr(conns),
+                                         ctypes.byref(pid)))
+        return pid.value
+
+    def submit(self, pop_id: int, outputs, inputs=None, B: int = 0, shared_inputs=False,
+               grid_side: int = 0, grid_first: int = 0, tag: int = 0, I: int = 0) -> int:
+        """Queue one request; returns its ticket.  TENSOR mode needs I (the
+        population's input count) unless the inputs are shared."""
+        r = Request()
+        r.pop_id = pop_id
+        if grid_side:
+            r.input_mode = INPUT_GRID
+            r.grid_side, r.grid_first = grid_side, grid_first
+        else:
+            r.input_mode = INPUT_TENSOR
+            r.inputs = inputs.data_ptr()
+            r.input_genome_stride = 0 if shared_inputs else B * I
+        r.B = B
+        r.outputs = outputs.data_ptr()
+        r.tag = tag
+        t = ctypes.c_uint64(0)
+        check(lib().neat_submit(self._h, ctypes.byref(r), ctypes.byref(t)))
+        return t.value
+
+    def poll(self, ticket: int):
+        """None while pending, else the Result (the ticket is then forgotten)."""
+        res = Result()
+        rc = check(lib().neat_poll(self._h, ticket, ctypes.byref(res)))
+        return None if rc == 1 else res
+
+    def wait(self, ticket: int, timeout_s: float = 60.0):
+        import time
+        t_end = time.monotonic() + timeout_s
+        while True:
+            r = self.poll(ticket)
+            if r is not None:
+                return r
+            if time.monotonic() > t_end:
+                raise TimeoutError("ticket %d not done after %.1fs" % (ticket, timeout_s))
+            time.sleep(20e-6)
+
+    def stats(self) -> Stats:
+        st = Stats()
+        check(lib().neat_server_stats(self._h, ctypes.byref(st)))
+        return st
+
+    def reset_stats(self):
+        check(lib().neat_server_reset_stats(self._h))
+
+    def close(self):
+        if self._h.value:
+            check(lib().neat_server_destroy(self._h))
+            self._h = ctypes.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.close()
         except Exception:
             pass

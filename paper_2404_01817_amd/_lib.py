@@ -38,6 +38,39 @@ class BatchItem(ctypes.Structure):
                 ("grid_first", ctypes.c_int64), ("outputs", ctypes.c_void_p)]
 
 
+class ServerCfg(ctypes.Structure):
+    """neat_server_cfg."""
+    _fields_ = [("device", ctypes.c_int32), ("max_inflight", ctypes.c_int32),
+                ("cap_bytes", ctypes.c_uint64)]
+
+
+class Request(ctypes.Structure):
+    """neat_request."""
+    _fields_ = [("pop_id", ctypes.c_int32), ("input_mode", ctypes.c_int32),
+                ("inputs", ctypes.c_void_p), ("input_genome_stride", ctypes.c_int64),
+                ("B", ctypes.c_int32), ("grid_side", ctypes.c_int32),
+                ("grid_first", ctypes.c_int64), ("outputs", ctypes.c_void_p),
+                ("tag", ctypes.c_uint64)]
+
+
+class Result(ctypes.Structure):
+    """neat_result."""
+    _fields_ = [("status", ctypes.c_int32), ("tag", ctypes.c_uint64),
+                ("t_submit_ns", ctypes.c_int64), ("t_admit_ns", ctypes.c_int64),
+                ("t_done_ns", ctypes.c_int64)]
+
+
+class Stats(ctypes.Structure):
+    """neat_stats."""
+    _fields_ = [("submitted", ctypes.c_uint64), ("admitted", ctypes.c_uint64),
+                ("completed", ctypes.c_uint64), ("rejected", ctypes.c_uint64),
+                ("batches", ctypes.c_uint64), ("queued", ctypes.c_uint64),
+                ("genome_inputs", ctypes.c_uint64), ("p50_ms", ctypes.c_double),
+                ("p99_ms", ctypes.c_double), ("throughput", ctypes.c_double)]
+
+
+INPUT_TENSOR, INPUT_GRID = 0, 1
+
 _lib = None
 
 # exported symbol -> (restype, argtypes)
@@ -53,6 +86,14 @@ SIGNATURES = {
                                   ctypes.POINTER(ctypes.c_void_p), _vp]),
     "neat_batch_plan_free": (None, [_vp]),
     "neat_batch_plan_launches": (_i32, [_vp]),
+    "neat_server_create": (_i32, [ctypes.POINTER(ServerCfg), ctypes.POINTER(ctypes.c_void_p)]),
+    "neat_server_destroy": (_i32, [_vp]),
+    "neat_server_register": (_i32, [_vp, ctypes.POINTER(Dims), _vp, _vp,
+                                    ctypes.POINTER(ctypes.c_int32)]),
+    "neat_submit": (_i32, [_vp, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]),
+    "neat_poll": (_i32, [_vp, ctypes.c_uint64, ctypes.POINTER(Result)]),
+    "neat_server_stats": (_i32, [_vp, ctypes.POINTER(Stats)]),
+    "neat_server_reset_stats": (_i32, [_vp]),
     "neat_last_error": (ctypes.c_char_p, []),
     "neat_strerror": (ctypes.c_char_p, [_i32]),
 }

@@ -69,3 +69,18 @@ def test_program_bytes_and_invalid_dims():
     assert lib.neat_topo_sort(ctypes.byref(d0), None, None, None, None, None, None, None) == 0
     assert lib.neat_forward(ctypes.byref(d), None, None, 0, 0, None, None) == 0
     assert lib.neat_strerror(-4) == b"request larger than the admission cap"
+
+
+def test_server_create_reports_errors_without_crashing():
+    """Invalid configurations fail with NEAT_E_INVALID before touching a
+    device; on a machine without a GPU a valid one fails with an error code
+    too (never a silent host fallback)."""
+    lib = _lib.lib()
+    h = ctypes.c_void_p(None)
+    bad = _lib.ServerCfg(0, 0, 1 << 20)  # max_inflight = 0
+    rc = lib.neat_server_create(ctypes.byref(bad), ctypes.byref(h))
+    assert rc < 0 and h.value is None
+    assert lib.neat_server_create(None, ctypes.byref(h)) == -1
+    assert lib.neat_submit(None, None, None) == -1
+    assert lib.neat_poll(None, 1, None) == -1
+    assert lib.neat_server_destroy(None) == -1
