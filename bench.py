@@ -24,6 +24,25 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "forward_control_traffic.json")
+
+
+def measured_traffic():
+    """HBM bytes per launch of the control forward from the committed
+    counter profile (FETCH_SIZE and WRITE_SIZE, each scaled by what it reads
+    for a plain copy of known size), or None when the kernel sources have
+    changed since the counters were taken."""
+    import hashlib
+    try:
+        prof = json.load(open(TRAFFIC_PROFILE))
+        h = hashlib.sha256()
+        for f in prof["sources"]:
+            h.update(open(os.path.join(ROOT, f), "rb").read())
+        if h.hexdigest()[:16] != prof["source_hash"]:
+            return None
+        return int(prof["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def parse():
@@ -303,9 +322,9 @@ def main():
     fwd_bytes = pop.P * pop.B * (pop.I + pop.O) * 4 + pbytes
     fwd_avg_s = float(fwd_ms.mean()) / 1e3
     achieved = fwd_bytes / fwd_avg_s / 1e9
-    roofline = {"kernel": "forward (lane per sample)", "bound": "hbm",
+    roofline = {"kernel": "forward, 64-slot register store, two samples per lane", "bound": "hbm",
                 "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
                 "algorithmic_bytes_per_launch": fwd_bytes,
                 "bytes_per_genome_input": round(fwd_bytes / units, 2),
                 "avg_launch_us": round(fwd_avg_s * 1e6, 1)}
