@@ -7,9 +7,13 @@
 // (or four) per population, and small populations fill the GPU together.
 // The work-unit tables of those launches live in device memory owned by the
 // plan.  Transformations (items with nodes) are recorded before the
-// calculations, one launch (plus the class listing) per population.
+// calculations, batched the same way: one launch per workgroup-size bucket
+// (64, 128, 256, 512, 1024 threads) over the genomes of every population in
+// it, then one launch listing the genomes of every population by class.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cstdint>
 #include <new>
 #include <vector>
 
@@ -24,6 +28,7 @@ struct neat_batch_plan {
     std::vector<neat_batch_item> items;
     int device = -1;
     void *tables = nullptr;  // FwdItem tables of the multi-item launches
+    void *topo_tables = nullptr;  // TopoItem tables: buckets, then all items
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     int launches = 0;
@@ -36,6 +41,7 @@ void destroy(neat_batch_plan *p) {
     if (p->exec) (void)hipGraphExecDestroy(p->exec);
     if (p->graph) (void)hipGraphDestroy(p->graph);
     if (p->tables) (void)hipFree(p->tables);
+    if (p->topo_tables) (void)hipFree(p->topo_tables);
     delete p;
 }
 
@@ -54,15 +60,27 @@ int check_item(const neat_batch_item &it, int32_t k) {
     return NEAT_OK;
 }
 
+// Transformation launches: one per workgroup-size bucket, then the class
+// lists of every item.
+struct TopoLaunch {
+    int n;
+    long long blocks;
+    int threads;
+    size_t lds;
+    const neat::TopoItem *table;
+};
+
 // Record every launch of the batch on stream s.
-int record(const neat_batch_plan *p, const std::vector<neat::FwdKernelLaunch> &fw,
+int record(const std::vector<TopoLaunch> &topo, const neat::TopoItem *all_topo, int n_topo,
+           const std::vector<neat::FwdKernelLaunch> &fw,
            const std::vector<const neat::FwdItem *> &tab, hipStream_t s) {
-    for (const neat_batch_item &it : p->items) {
-        if (!it.nodes || it.dims.P == 0) continue;
-        const neat_dims &d = it.dims;
-        hipError_t e = neat::launch_topo(d.P, d.N_max, d.C_max, d.I, d.O, it.nodes, it.conns,
-                                         nullptr, nullptr, it.status, (int32_t *)it.program, s);
+    for (const TopoLaunch &t : topo) {
+        hipError_t e = neat::launch_topo_batch(t.table, t.n, t.blocks, t.threads, t.lds, s);
         if (e != hipSuccess) return hip_fail(e, "batch transformation launch");
+    }
+    if (n_topo) {
+        hipError_t e = neat::launch_classify_batch(all_topo, n_topo, s);
+        if (e != hipSuccess) return hip_fail(e, "batch class lists launch");
     }
     for (size_t k = 0; k < fw.size(); ++k) {
         hipError_t e = neat::forward_launch(fw[k], tab[k], s);
@@ -78,10 +96,39 @@ int build(const neat_batch_item *items, int32_t n, neat_batch_plan **out) {
     (void)hipGetDevice(&p->device);
 
     std::vector<neat::FwdJob> jobs;
-    int topo_launches = 0;
+    // transformations bucketed by workgroup size
+    static const int bucket_threads[] = {64, 128, 256, 512, 1024};
+    std::vector<neat::TopoItem> bucket[5], all_topo;
     for (const neat_batch_item &it : p->items) {
-        if (it.nodes && it.dims.P > 0)
-            topo_launches += 1 + (neat::max_class(it.dims.N_max) != 0 ? 1 : 0);
+        if (!it.nodes || it.dims.P == 0) continue;
+        const neat_dims &d = it.dims;
+        neat::TopoItem ti{it.nodes, it.conns, nullptr, nullptr, it.status, (int32_t *)it.program,
+                          d.P, d.N_max, d.C_max, d.I, d.O, neat::prog_words(d.N_max, d.C_max, d.O),
+                          0};
+        int b = 0;
+        while (bucket_threads[b] < neat::topo_block_threads(d.N_max)) ++b;
+        bucket[b].push_back(ti);
+        all_topo.push_back(ti);
+    }
+    std::vector<TopoLaunch> topo;
+    std::vector<neat::TopoItem> topo_host;
+    for (int b = 0; b < 5; ++b) {
+        if (bucket[b].empty()) continue;
+        TopoLaunch t{(int)bucket[b].size(), 0, 64, 0, nullptr};
+        for (neat::TopoItem &ti : bucket[b]) {
+            ti.block0 = t.blocks;
+            t.blocks += ti.P;
+            t.threads = std::max(t.threads, neat::topo_block_threads(ti.N));
+            t.lds = std::max(t.lds, neat::topo_lds_bytes(ti.N, ti.C));
+        }
+        t.table = (const neat::TopoItem *)(uintptr_t)topo_host.size();  // offset for now
+        topo_host.insert(topo_host.end(), bucket[b].begin(), bucket[b].end());
+        topo.push_back(t);
+    }
+    const size_t all_off = topo_host.size();
+    topo_host.insert(topo_host.end(), all_topo.begin(), all_topo.end());
+    const int topo_launches = (int)topo.size() + (all_topo.empty() ? 0 : 1);
+    for (const neat_batch_item &it : p->items) {
         if (it.dims.P == 0 || it.B == 0) continue;
         jobs.push_back(make_job(&it.dims, it.program, it.inputs, it.input_genome_stride, it.B,
                                 it.outputs, it.grid_side, it.grid_first));
@@ -122,6 +169,22 @@ int build(const neat_batch_item *items, int32_t n, neat_batch_plan **out) {
         }
     }
 
+    const neat::TopoItem *all_dev = nullptr;
+    if (!topo_host.empty()) {
+        hipError_t e = hipMalloc(&p->topo_tables, topo_host.size() * sizeof(neat::TopoItem));
+        if (e == hipSuccess)
+            e = hipMemcpy(p->topo_tables, topo_host.data(),
+                          topo_host.size() * sizeof(neat::TopoItem), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            destroy(p);
+            return e == hipErrorOutOfMemory ? fail(NEAT_E_NOMEM, "batch tables: out of memory")
+                                            : hip_fail(e, "batch tables");
+        }
+        const neat::TopoItem *base = (const neat::TopoItem *)p->topo_tables;
+        for (TopoLaunch &t : topo) t.table = base + (uintptr_t)t.table;
+        all_dev = base + all_off;
+    }
+
     // record the launches into a graph on a private stream
     hipStream_t cs = nullptr;
     hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
@@ -135,7 +198,7 @@ int build(const neat_batch_item *items, int32_t n, neat_batch_plan **out) {
         destroy(p);
         return hip_fail(e, "begin capture");
     }
-    rc = record(p, fw, tab, cs);
+    rc = record(topo, all_dev, (int)all_topo.size(), fw, tab, cs);
     hipGraph_t g = nullptr;
     e = hipStreamEndCapture(cs, &g);
     (void)hipStreamDestroy(cs);

@@ -23,11 +23,14 @@
 // node operations in C++.
 //
 // Work units.  A launch covers one or more populations ("items"); item j
-// contributes P_j x groups_j units, unit (i, group) being the group's waves
-// on the i-th genome of the item's list for the kernel's class (the class
-// list the transformation wrote, or all genomes).  Units past the list's
-// length exit at once.  Workgroups are remapped so consecutive units share
-// an XCD (workgroups are dealt to the 8 XCDs round robin).
+// contributes P_j x chunks_j wave units, unit (i, c) being run c of the
+// tiles of the i-th genome of the item's list for the kernel's class (the
+// class list the transformation wrote, or all genomes).  Each wave of a
+// workgroup takes its own unit, so consecutive waves share a genome when it
+// has several chunks and take different genomes when it has one.  Units
+// past the list's length exit at once.  Workgroups are remapped so
+// consecutive ones share an XCD (workgroups are dealt to the 8 XCDs round
+// robin).
 //
 // Inputs of the next tile are copied HBM -> LDS by the DMA path of
 // global_load_lds (16-byte pieces when aligned) while the current tile
@@ -294,13 +297,17 @@ __device__ __forceinline__ void flush_outputs(const float *ostage, float *dst, i
     for (int c = c0 + lane; c < n; c += WAVE) dst[c] = ostage[c];
 }
 
-// Chunk range [t0, t1) of this wave in a unit, or false when it has none.
-__device__ __forceinline__ bool wave_tiles(citem_t *it, int grp, int *t0, int *t1) {
-    // the wave index is uniform; say so, so everything derived stays scalar
-    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE));
-    const int wpg = it->wpg;
-    const int chunk = grp * wpg + wave;
-    if (wave >= wpg || chunk >= it->chunks) return false;
+// Bring words [0, n) of a genome's program into the L2 cache ahead of the
+// node loop's scalar loads: one 4-byte DMA per 128-byte line, landing in a
+// scratch LDS area (the caller waits for vmcnt(0) before reusing it).
+__device__ __forceinline__ void touch_lines(const int32_t *base, int n, float *lds_scratch) {
+    const int lane = (int)(threadIdx.x & (WAVE - 1));
+    for (int off = lane * 32; off < n; off += WAVE * 32)
+        __builtin_amdgcn_global_load_lds((gvoid *)(base + off), (lvoid *)lds_scratch, 4, 0, 0);
+}
+
+// Tile range [t0, t1) of run chunk, or false when it is empty.
+__device__ __forceinline__ bool wave_tiles(citem_t *it, int chunk, int *t0, int *t1) {
     *t0 = chunk * it->tpw;
     *t1 = min(it->tiles, *t0 + it->tpw);
     return *t0 < *t1;
@@ -316,12 +323,12 @@ __device__ __forceinline__ void fill_nan(float *out_g, int first, int end, int O
 // area: the wave's LDS (input staging TS x I floats, then output staging
 // TS x O floats).
 template <int K, bool GRID>
-__device__ __forceinline__ void forward_unit_reg(citem_t *it, int g, int grp, float *area,
+__device__ __forceinline__ void forward_unit_reg(citem_t *it, int g, int chunk, float *area,
                                                  int stage_floats) {
     constexpr int SPL = AsmTile<K>::SPL;
     constexpr int TS = WAVE * SPL;  // samples per tile
     int t0, t1;
-    if (!wave_tiles(it, grp, &t0, &t1)) return;
+    if (!wave_tiles(it, chunk, &t0, &t1)) return;
     const unsigned lane = threadIdx.x & (WAVE - 1);
     const int N = it->N, I = it->I, O = it->O, B = it->B, side = GRID ? it->side : 0;
     cprog_t *prog = (cprog_t *)(it->prog + (size_t)g * it->prog_words);
@@ -339,6 +346,11 @@ __device__ __forceinline__ void forward_unit_reg(citem_t *it, int g, int grp, fl
     const float *in_g = GRID ? nullptr : it->inputs + (size_t)g * it->gstride;
     const int vec4 = it->vec4;
     if (!GRID) dma_inputs(in_g + (size_t)t0 * TS * I, istage, min(TS, B - t0 * TS) * I, vec4);
+    // the records and overflow edges the node loop will read, in one burst
+    // (the first tile's wait covers it)
+    touch_lines(rec, REC_WORDS * ncomp, ostage);
+    touch_lines(edg, EDGE_WORDS * prog[HDR_NEDGES], ostage);
+    if (GRID) wait_dma();
 
     for (int t = t0; t < t1; ++t) {
         if (GRID) {
@@ -374,11 +386,11 @@ __device__ __forceinline__ void forward_unit_reg(citem_t *it, int g, int grp, fl
 // The waves of one unit with the LDS store.  stage: the wave's input
 // staging area (TS x I floats; unused for grid items).
 template <bool GRID>
-__device__ __forceinline__ void forward_unit_lds(citem_t *it, int g, int grp, float *stage,
+__device__ __forceinline__ void forward_unit_lds(citem_t *it, int g, int chunk, float *stage,
                                                  LdsStore &v) {
     constexpr int TS = WAVE;
     int t0, t1;
-    if (!wave_tiles(it, grp, &t0, &t1)) return;
+    if (!wave_tiles(it, chunk, &t0, &t1)) return;
     const int lane = (int)(threadIdx.x & (WAVE - 1));
     const int N = it->N, I = it->I, O = it->O, B = it->B, side = GRID ? it->side : 0;
     cprog_t *prog = (cprog_t *)(it->prog + (size_t)g * it->prog_words);
@@ -437,8 +449,8 @@ __device__ __forceinline__ void run_unit(long long u, float *wave_area) {
     const auto *L = launch_arg();
     citem_t *it = L->items ? find_item(L->items, L->n_items, u) : (citem_t *)&L->one;
     const long long local = u - it->unit0;
-    const int groups = it->groups;
-    const int i = (int)(local / groups), grp = (int)(local - (long long)i * groups);
+    const int chunks = it->chunks;
+    const int i = (int)(local / chunks), chunk = (int)(local - (long long)i * chunks);
     int g = i;
     const int cls = it->cls;
     if (cls >= 0) {
@@ -449,9 +461,9 @@ __device__ __forceinline__ void run_unit(long long u, float *wave_area) {
     if constexpr (K == KIND_LDS) {
         LdsStore v;
         v.col = wave_area + L->stage_floats + (threadIdx.x & (WAVE - 1));
-        forward_unit_lds<GRID>(it, g, grp, wave_area, v);
+        forward_unit_lds<GRID>(it, g, chunk, wave_area, v);
     } else {
-        forward_unit_reg<K, GRID>(it, g, grp, wave_area, L->stage_floats);
+        forward_unit_reg<K, GRID>(it, g, chunk, wave_area, L->stage_floats);
     }
 }
 
@@ -461,12 +473,19 @@ template <int K, bool PERSIST, bool GRID>
 __global__ __launch_bounds__(WAVE *FWD_MAX_WAVES) void forward_kernel(FwdLaunch L) {
     extern __shared__ float smem[];
     float *wave_area = smem + (size_t)(threadIdx.x / WAVE) * L.wave_floats;
-    const long long u0 = xcd_item(blockIdx.x, gridDim.x);
+    // the wave index is uniform; say so, so everything derived stays scalar
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE));
+    const long long waves = blockDim.x / WAVE;
+    const long long b0 = xcd_item(blockIdx.x, gridDim.x);
     if (!PERSIST) {
-        if (u0 < L.units) run_unit<K, GRID>(u0, wave_area);
+        const long long u = b0 * waves + wave;
+        if (u < L.units) run_unit<K, GRID>(u, wave_area);
         return;
     }
-    for (long long u = u0; u < L.units; u += gridDim.x) run_unit<K, GRID>(u, wave_area);
+    for (long long b = b0; b * waves < L.units; b += gridDim.x) {
+        const long long u = b * waves + wave;
+        if (u < L.units) run_unit<K, GRID>(u, wave_area);
+    }
 }
 
 int choose_chunks(long long P, int tiles, int *tpw) {
@@ -566,11 +585,10 @@ int forward_plan(const FwdJob *jobs, int n, int variant, size_t max_lds,
         }
         long long units = 0;
         for (FwdItem &it : K.items) {
-            it.wpg = std::min(it.chunks, waves);
-            it.groups = (it.chunks + it.wpg - 1) / it.wpg;
             it.unit0 = units;
-            units += (long long)it.P * it.groups;
+            units += (long long)it.P * it.chunks;
         }
+        const long long groups = (units + waves - 1) / waves;
         K.args.wave_floats = (int)wave_floats;
         K.args.stage_floats = stage_max[x];
         K.args.units = units;
@@ -581,8 +599,8 @@ int forward_plan(const FwdJob *jobs, int n, int variant, size_t max_lds,
         const long long cap = kind == KIND_LDS
                                   ? 256ll * 2 * std::max<long long>(1, (long long)(163840 / K.lds))
                                   : (1ll << 31) - 1;
-        K.args.persistent = units > cap ? 1 : 0;
-        K.grid = (unsigned)std::min(units, cap);
+        K.args.persistent = groups > cap ? 1 : 0;
+        K.grid = (unsigned)std::min(groups, cap);
         if (K.items.size() == 1) K.args.one = K.items[0];
         out.push_back(K);
     }

@@ -20,6 +20,26 @@ hipError_t launch_topo(int P, int N, int C, int I, int O, const float *nodes,
                        const float *conns, int32_t *order, int32_t *level,
                        uint32_t *status, int32_t *prog, hipStream_t stream);
 
+// One population of a transformation launch; workgroups block0 ..
+// block0 + P - 1 of a batched launch transform its genomes.
+struct TopoItem {
+    const float *nodes;
+    const float *conns;
+    int32_t *order;
+    int32_t *level;
+    uint32_t *status;
+    int32_t *prog;
+    int P, N, C, I, O, prog_words;
+    long long block0;
+};
+
+// Transformation of many populations in one launch (items in device memory,
+// sorted by block0; threads >= topo_block_threads and lds >= topo_lds_bytes
+// of every item), and the class lists of all of them (one workgroup each).
+hipError_t launch_topo_batch(const TopoItem *dev_items, int n, long long blocks, int threads,
+                             size_t lds, hipStream_t stream);
+hipError_t launch_classify_batch(const TopoItem *dev_items, int n, hipStream_t stream);
+
 // Forward variants (value stores of the lane-per-sample mapping).
 constexpr int FWD_AUTO = 0;  // per slot class: registers, R64 with two samples per lane when B > 64
 constexpr int FWD_REG = 1;   // registers, one sample per lane (LDS rows for the LDS class)
@@ -42,8 +62,9 @@ struct FwdJob {
 };
 
 // One population in one forward kernel (device-visible, read with scalar
-// loads): the genomes of class cls (or all when cls < 0), P x groups units
-// starting at unit0.
+// loads): the genomes of class cls (or all when cls < 0), P x chunks wave
+// units starting at unit0 (unit (i, c): tiles c tpw .. c tpw + tpw - 1 of
+// the i-th genome).
 struct FwdItem {
     const int32_t *prog;
     const float *inputs;
@@ -51,14 +72,14 @@ struct FwdItem {
     const int32_t *pop;  // population area (class lists)
     long long gstride, first, unit0;
     int P, N, I, O, B, side, vec4, cls;
-    int tiles, tpw, chunks, wpg, groups, prog_words;
+    int tiles, tpw, chunks, prog_words;
 };
 
 // Kernel argument: one item inline, or a device table of items.
 struct FwdLaunch {
     FwdItem one;
     const FwdItem *items;  // nullptr: the inline item
-    long long units;
+    long long units;   // wave units over all items
     int n_items;
     int wave_floats;   // LDS floats per wave: input staging, then value rows (LDS
                        // store) or the output staging (register stores)

@@ -85,17 +85,9 @@ __device__ int block_excl_scan(int v, int *s_wave, int *total) {
     return base + x - v;
 }
 
-struct TopoArgs {
-    const float *nodes;
-    const float *conns;
-    int32_t *order;
-    int32_t *level;
-    uint32_t *status;
-    int32_t *prog;
-    int N, C, I, O, prog_words;
-};
-
-__global__ __launch_bounds__(1024) void topo_kernel(TopoArgs a) {
+// Transformation of genome g of population a by the whole workgroup (any
+// block size of at least round_up(N_max, 64) threads).
+__device__ __forceinline__ void topo_genome(const TopoItem &a, size_t g) {
     extern __shared__ int smem[];
     __shared__ unsigned s_status;
     __shared__ int s_nvalid, s_ngood;
@@ -103,7 +95,6 @@ __global__ __launch_bounds__(1024) void topo_kernel(TopoArgs a) {
 
     const int N = a.N, C = a.C, I = a.I, O = a.O;
     const int t = (int)threadIdx.x, W = (int)blockDim.x;
-    const size_t g = blockIdx.x;
 
     int *s_key = smem;            // [N] key of row, -1 absent, -2 malformed
     int *s_skey = s_key + N;      // [N] well-formed keys by stable rank; later level of row
@@ -488,12 +479,28 @@ __global__ __launch_bounds__(1024) void topo_kernel(TopoArgs a) {
     }
 }
 
+__global__ __launch_bounds__(1024) void topo_kernel(TopoItem a) { topo_genome(a, blockIdx.x); }
+
+// Many populations: workgroup b transforms genome b - block0 of the item
+// whose range holds b (items sorted by block0).
+__global__ __launch_bounds__(1024) void topo_batch_kernel(const TopoItem *items, int n) {
+    int lo = 0, hi = n - 1;
+    const long long b = blockIdx.x;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (items[mid].block0 <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    const TopoItem it = items[lo];
+    topo_genome(it, (size_t)(b - it.block0));
+}
+
 // List the genomes of a population by slot class (one workgroup of 1024
 // threads; thread t takes a contiguous run of genomes, so the lists are in
 // genome order).  Rejected genomes go with R64: every forward kernel writes
 // their NaN rows.
-__global__ __launch_bounds__(1024) void classify_kernel(const int32_t *prog, int prog_words,
-                                                        int P, int32_t *pop) {
+__device__ __forceinline__ void classify_pop(const int32_t *prog, int prog_words, int P,
+                                             int32_t *pop) {
     __shared__ int s_wave[16];
     const int t = (int)threadIdx.x, W = (int)blockDim.x;
     const int per = (P + W - 1) / W;
@@ -530,6 +537,18 @@ __global__ __launch_bounds__(1024) void classify_kernel(const int32_t *prog, int
     }
 }
 
+__global__ __launch_bounds__(1024) void classify_kernel(const int32_t *prog, int prog_words,
+                                                        int P, int32_t *pop) {
+    classify_pop(prog, prog_words, P, pop);
+}
+
+// One workgroup per item (items of N_max <= 62 have no class list).
+__global__ __launch_bounds__(1024) void classify_batch_kernel(const TopoItem *items) {
+    const TopoItem it = items[blockIdx.x];
+    if (!it.prog || max_class(it.N) == CLS_R64) return;
+    classify_pop(it.prog, it.prog_words, it.P, it.prog + pop_off(it.P, it.N, it.C, it.O));
+}
+
 }  // namespace
 
 size_t topo_lds_bytes(int N, int C) { return sizeof(int) * ((size_t)12 * N + 2 + (size_t)4 * C); }
@@ -542,7 +561,7 @@ int topo_block_threads(int N) {
 hipError_t launch_topo(int P, int N, int C, int I, int O, const float *nodes,
                        const float *conns, int32_t *order, int32_t *level,
                        uint32_t *status, int32_t *prog, hipStream_t stream) {
-    TopoArgs a{nodes, conns, order, level, status, prog, N, C, I, O, prog_words(N, C, O)};
+    TopoItem a{nodes, conns, order, level, status, prog, P, N, C, I, O, prog_words(N, C, O), 0};
     hipLaunchKernelGGL(topo_kernel, dim3((unsigned)P), dim3((unsigned)topo_block_threads(N)),
                        topo_lds_bytes(N, C), stream, a);
     if (prog && max_class(N) != CLS_R64) {
@@ -551,6 +570,18 @@ hipError_t launch_topo(int P, int N, int C, int I, int O, const float *nodes,
         hipLaunchKernelGGL(classify_kernel, dim3(1), dim3(1024), 0, stream, prog, a.prog_words, P,
                            prog + pop_off(P, N, C, O));
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_topo_batch(const TopoItem *dev_items, int n, long long blocks, int threads,
+                             size_t lds, hipStream_t stream) {
+    hipLaunchKernelGGL(topo_batch_kernel, dim3((unsigned)blocks), dim3((unsigned)threads), lds,
+                       stream, dev_items, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_classify_batch(const TopoItem *dev_items, int n, hipStream_t stream) {
+    hipLaunchKernelGGL(classify_batch_kernel, dim3((unsigned)n), dim3(1024), 0, stream, dev_items);
     return hipGetLastError();
 }
 
