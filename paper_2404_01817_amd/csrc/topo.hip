@@ -85,6 +85,24 @@ __device__ int block_excl_scan(int v, int *s_wave, int *total) {
     return base + x - v;
 }
 
+// Block-wide inclusive prefix minimum of one value per thread.  Contains
+// two barriers; every thread of the block must call it.
+__device__ int block_incl_min(int v, int *s_wave) {
+    const int lane = lane_id(), wave = wave_id();
+    int x = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int y = __shfl_up(x, d, 64);
+        if (lane >= d) x = min(x, y);
+    }
+    if (lane == 63) s_wave[wave] = x;
+    __syncthreads();
+    int before = 0x7fffffff;
+    for (int w = 0; w < wave; ++w) before = min(before, s_wave[w]);
+    __syncthreads();
+    return min(before, x);
+}
+
 // Transformation of genome g of population a by the whole workgroup (any
 // block size of at least round_up(N_max, 64) threads).
 __device__ __forceinline__ void topo_genome(const TopoItem &a, size_t g) {
@@ -111,7 +129,8 @@ __device__ __forceinline__ void topo_genome(const TopoItem &a, size_t g) {
     int *in_list = e_dst + C;     // [C] connection rows grouped by destination
     int *out_list = in_list + C;  // [C] destination rows grouped by source
     int *s_slot = out_list + C;   // [N] value slot of row
-    int *s_stack = s_slot + N;    // [N] free slots
+    int *s_stack = s_slot + N;    // [N] slot allocation scratch
+    int *s_oval = s_stack + N;    // [N] slot allocation scratch
 
     const float *nodes = a.nodes + g * (size_t)N * 5;
     const float *conns = a.conns + g * (size_t)C * 4;
@@ -323,29 +342,101 @@ __device__ __forceinline__ void topo_genome(const TopoItem &a, size_t g) {
         s_last[t] = last;
     }
     __syncthreads();
-    if (t == 0 && max_class(N) == CLS_R64) {
+    if (max_class(N) == CLS_R64) {
         // every genome fits the 64-slot class: slot = position
-        for (int p = 0; p < nvalid; ++p) s_slot[s_curi[p]] = p;
-        s_used = nvalid;
-    } else if (t == 0) {
-        // input p (position p, key p) keeps slot p; a value whose last
-        // reader is position p frees its slot before p takes one, since a
-        // node reads all its sources before writing its own value
-        int top = 0, used = I;
-        for (int p = 0; p < I; ++p) s_slot[s_curi[p]] = p;
-        for (int p = 0; p < I; ++p)
-            if (s_last[s_curi[p]] == p) s_stack[top++] = p;  // unread inputs
-        for (int p = I; p < nvalid; ++p) {
-            const int row = s_curi[p];
-            for (int k = s_inoff[row]; k < s_inoff[row + 1]; ++k) {
-                const int src = e_src[in_list[k]];
-                if (s_last[src] == p) s_stack[top++] = s_slot[src];
-            }
-            const int sl = top > 0 ? s_stack[--top] : used++;
-            s_slot[row] = sl;
-            if (s_last[row] == p) s_stack[top++] = sl;  // never read
+        if (t < nvalid) s_slot[s_curi[t]] = t;
+        if (t == 0) s_used = nvalid;
+    } else {
+        // Slots by liveness, in parallel.  A value frees its slot for the
+        // position free_at: its last reader (which reads before writing),
+        // the next position when nothing reads it, I for unread inputs;
+        // outputs never.  Position p >= I takes a slot freed at p when there
+        // is one (the smallest such row), else the earliest-ranked slot freed
+        // before p and not yet taken, else a new slot.  Rank order is valid:
+        // a close that finds a free slot is preceded by more frees than
+        // earlier matched closes, so the free of its rank has happened.  A
+        // new slot is made only when none is free, so the count is the
+        // largest live set.  Each value hands its slot on at most once, so
+        // slots follow chains, resolved by pointer jumping.
+        int *s_free = s_last;     // by row: free position (INT_MAX: never)
+        int *s_dc = s_stack;      // by position: frees there (+ cursor << 16); later ancestor
+        int *s_pair = s_deg;      // by position: smallest row freed there
+        int *s_obase = s_curo;    // by position: rank of its first extra free
+        const int NEVER = 0x7fffffff;
+        if (t < N) {
+            s_dc[t] = 0;
+            s_pair[t] = NEVER;
         }
-        s_used = used;
+        __syncthreads();
+        if (t < N && s_key[t] != -1) {
+            const int p = s_pos[t], last = s_last[t];
+            const bool out = s_key[t] >= I && s_key[t] < I + O;
+            const int fa = out ? NEVER : (last > p ? last : (p < I ? I : p + 1));
+            s_free[t] = fa;
+            if (fa < nvalid) {
+                atomicAdd(&s_dc[fa], 1);
+                atomicMin(&s_pair[fa], t);
+            }
+        }
+        __syncthreads();
+        // per position: pairing, or an open (extra frees) / close (birth
+        // without a free at its position) event; clamped depth by scans
+        const bool vp = t >= I && t < nvalid;
+        const int d = vp ? (s_dc[t] & 0xffff) : 0;
+        const int pairrow = vp ? s_pair[t] : -1;
+        const int n_open = d > 1 ? d - 1 : 0, n_close = (vp && d == 0) ? 1 : 0;
+        int tot_open, tot_close;
+        const int ob = block_excl_scan(n_open, s_wave, &tot_open);
+        const int cb = block_excl_scan(n_close, s_wave, &tot_close);
+        const int u_before = -block_incl_min(ob - cb, s_wave);  // unmatched closes before
+        const int s_incl = ob + n_open - cb - n_close;
+        const int u_incl = max(u_before, -s_incl);
+        const bool unmatched = n_close && u_incl > u_before;
+        const int close_rank = cb - u_before;  // matched closes before this one
+        if (vp) s_obase[t] = ob;
+        if (t == nvalid - 1) s_used = I + u_incl;
+        __syncthreads();
+        // extra frees get their open ranks
+        if (t < N && s_key[t] != -1) {
+            const int fa = s_free[t];
+            if (fa < nvalid && s_pair[fa] != t) {
+                const int k = atomicAdd(&s_dc[fa], 0x10000) >> 16;
+                s_oval[s_obase[fa] + k] = t;
+            }
+        }
+        __syncthreads();
+        // ancestors: the value whose slot a birth takes; roots get slots
+        int *s_anc = s_dc;
+        if (t < nvalid) {
+            const int b = s_curi[t];
+            int anc = -1;
+            if (t < I) s_slot[b] = t;
+            else if (d > 0) anc = pairrow;
+            else if (!unmatched) anc = s_oval[close_rank];
+            else s_slot[b] = I + u_incl - 1;
+            s_anc[b] = anc;
+        }
+        __syncthreads();
+        bool more = true;
+        while (more) {
+            int anc = -1, slot = 0;
+            bool changed = false;
+            if (t < N && s_key[t] != -1) {
+                anc = s_anc[t];
+                if (anc >= 0) {
+                    const int aa = s_anc[anc];
+                    if (aa < 0) slot = s_slot[anc];
+                    changed = true;
+                    anc = aa;
+                }
+            }
+            __syncthreads();
+            if (changed) {
+                s_anc[t] = anc;
+                if (anc < 0) s_slot[t] = slot;
+            }
+            more = __syncthreads_or(changed);
+        }
     }
     __syncthreads();
     const int used = s_used;
@@ -551,7 +642,7 @@ __global__ __launch_bounds__(1024) void classify_batch_kernel(const TopoItem *it
 
 }  // namespace
 
-size_t topo_lds_bytes(int N, int C) { return sizeof(int) * ((size_t)12 * N + 2 + (size_t)4 * C); }
+size_t topo_lds_bytes(int N, int C) { return sizeof(int) * ((size_t)13 * N + 2 + (size_t)4 * C); }
 
 int topo_block_threads(int N) {
     int w = round_up(N, 64);
