@@ -39,6 +39,7 @@
 
 #include <algorithm>
 #include <cstdio>
+#include <cstdlib>
 
 #include "act.h"
 #include "launch.h"
@@ -69,16 +70,8 @@ __device__ __forceinline__ float maximum3(float a, float b, float c) {
     return r;
 }
 
-// Lane select with a uniform 64-bit mask (all ones or zero): mask ? b : a.
-__device__ __forceinline__ float sel_mask(float a, float b, unsigned long long mask) {
-    float r;
-    asm volatile("v_cndmask_b32_e64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "s"(mask));
-    return r;
-}
-
 // ---------------------------------------------------------------- stores
 struct LdsStore {
-    static constexpr int SPL = 1;
     float *col;  // this lane's column: slot s at col[s * WAVE]
     template <int H>
     __device__ __forceinline__ float get(int s) const {
@@ -165,21 +158,38 @@ __device__ __forceinline__ void pair(float &acc, bool first, int s0, float w0, i
     }
 }
 
-// pairs (>= 1) edge pairs: the first two from the record r, then the
+// pairs (>= 1) edge pairs: the first three from the record r, then the
 // overflow array from e, four words per pair.
 template <int ACLS>
 __device__ __forceinline__ float aggregate(const i32x16 &r, cprog_t *e, int pairs,
                                            const LdsStore &v) {
     float acc = 0.0f;
-    pair<ACLS>(acc, true, r[REC_PAIRS], fbits(r[REC_PAIRS + 1]), r[REC_PAIRS + 2],
-               fbits(r[REC_PAIRS + 3]), v);
-    if (pairs > 1)
-        pair<ACLS>(acc, false, r[REC_PAIRS + 4], fbits(r[REC_PAIRS + 5]), r[REC_PAIRS + 6],
-                   fbits(r[REC_PAIRS + 7]), v);
+#pragma unroll
+    for (int k = 0; k < REC_INLINE_PAIRS; ++k) {
+        if (k < pairs)
+            pair<ACLS>(acc, k == 0, r[REC_PAIRS + 4 * k], fbits(r[REC_PAIRS + 4 * k + 1]),
+                       r[REC_PAIRS + 4 * k + 2], fbits(r[REC_PAIRS + 4 * k + 3]), v);
+    }
     for (int p = 0; p < pairs - REC_INLINE_PAIRS; ++p)
         pair<ACLS>(acc, false, e[4 * p], fbits(e[4 * p + 1]), e[4 * p + 2], fbits(e[4 * p + 3]),
                    v);
     return acc;
+}
+
+// The activation of code act, as the assembly blocks compute it.
+__device__ __forceinline__ float activation(int act, float z) {
+    switch (act) {
+    case ACT_TANH: {
+        const float e = exp2_hw(2.885390043258667f * z);
+        return fmaf(rcp_hw(1.0f + e), -2.0f, 1.0f);
+    }
+    case ACT_SIGMOID: return rcp_hw(1.0f + exp2_hw(-1.4426950216293335f * z));
+    case ACT_RELU: return maximum3(z, 0.0f, 0.0f);
+    case ACT_SIN: return act_sin(z);
+    case ACT_GAUSS: return exp2_hw(-1.4426950216293335f * (z * z));
+    case ACT_ABS: return maximum3(z, -z, -z);
+    default: return z;  // identity
+    }
 }
 
 __device__ __forceinline__ void run_program(cprog_t *prog, int N, int O, int I, LdsStore &v) {
@@ -190,12 +200,10 @@ __device__ __forceinline__ void run_program(cprog_t *prog, int N, int O, int I, 
     i32x16 r = *(cint16_t *)rec;
     for (int k = 0; k < ncomp; ++k) {
         const unsigned code = (unsigned)r[REC_CODE];
-        const int pairs = (int)(code & 0xffffu), acls = (int)((code >> 16) & 3u);
-        const int xcls = (int)((code >> 18) & 3u), dst = (int)(code >> 20);
+        const int pairs = (int)(code & (unsigned)REC_PAIRS_MASK);
+        const int acls = (int)((code >> 14) & 3u), act = (int)((code >> 16) & 7u);
+        const int dst = (int)(code >> 20);
         const float bias = fbits(r[REC_BIAS]), resp = fbits(r[REC_RESP]);
-        const float cf = fbits(r[REC_C]), ea = fbits(r[REC_EA]), eb = fbits(r[REC_EB]);
-        const unsigned long long mask =
-            ((unsigned long long)(unsigned)r[REC_MASK + 1] << 32) | (unsigned)r[REC_MASK];
         // next record (the record array has room for N records)
         const i32x16 rn = *(cint16_t *)(rec + REC_WORDS * (k + 1));
         float a;
@@ -203,24 +211,10 @@ __device__ __forceinline__ void run_program(cprog_t *prog, int N, int O, int I, 
         else if (acls == ACLS_MAX) a = aggregate<ACLS_MAX>(r, e, pairs, v);
         else a = pairs == 0 ? 0.0f : aggregate<ACLS_SUM>(r, e, pairs, v);
         if (pairs > REC_INLINE_PAIRS) e += 4 * (pairs - REC_INLINE_PAIRS);
-        const float z = fmaf(resp, a, bias);
-        float y;
-        if (xcls == XCLS_EXPO) {
-            // sigmoid, tanh: ea + eb / (1 + 2^(c z)); gaussian: 2^(c z z)
-            const float ex = exp2_hw(sel_mask(z, z * z, mask) * cf);
-            y = sel_mask(fmaf(eb, rcp_hw(1.0f + ex), ea), ex, mask);
-        } else if (xcls == XCLS_SIN) {
-            y = act_sin(z);
-        } else {
-            // identity, abs, relu: maximum(z, mask ? 0 : c z)
-            const float t = sel_mask(z * cf, 0.0f, mask);
-            y = maximum3(z, t, t);
-        }
-        v.set<0>(dst, y);
+        v.set<0>(dst, activation(act, fmaf(resp, a, bias)));
         r = rn;
     }
 }
-
 
 // ---------------------------------------------------------------- tiles
 // Workgroup b is dealt to XCD b % 8; give each XCD a contiguous range.
@@ -488,10 +482,21 @@ __global__ __launch_bounds__(WAVE *FWD_MAX_WAVES) void forward_kernel(FwdLaunch 
     }
 }
 
+// Waves a forward launch aims at (NEAT_FWD_WAVES overrides, for tuning).
+long long wave_target() {
+    static const long long t = [] {
+        const char *e = getenv("NEAT_FWD_WAVES");
+        const long long v = e ? atoll(e) : 0;
+        return v >= 1024 ? v : 32768ll;
+    }();
+    return t;
+}
+
 int choose_chunks(long long P, int tiles, int *tpw) {
-    // aim at ~32k waves: enough to fill 256 CUs several times over while a
-    // wave still reuses its genome's program across a run of tiles
-    const long long target = 32768;
+    // aim at a wave count that fills 256 CUs several times over while a
+    // wave still reuses its genome's program across a run of tiles (and
+    // hides the first tile's input latency behind the others)
+    const long long target = wave_target();
     long long chunks = (target + P - 1) / (P > 0 ? P : 1);
     if (chunks < 1) chunks = 1;
     if (chunks > tiles) chunks = tiles;

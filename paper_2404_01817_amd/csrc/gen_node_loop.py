@@ -39,11 +39,18 @@ VARIANTS = [
 ]
 
 # scalar register map (shared by all variants)
-REC_A = ("s40", "s41", "s42", "s43", "s44", "s45", "s[46:47]",
-         "s48", "s49", "s50", "s51", "s52", "s53", "s54", "s55")
-REC_B = ("s56", "s57", "s58", "s59", "s60", "s61", "s[62:63]",
-         "s64", "s65", "s66", "s67", "s68", "s69", "s70", "s71")
-SGPR_CLOBBERS = ["s%d" % i for i in range(40, 92)]
+# record buffers: code, bias, response', (unused), three edge pairs
+REC_A = tuple("s%d" % i for i in range(40, 56))
+REC_B = tuple("s%d" % i for i in range(56, 72))
+SGPR_CLOBBERS = ["s%d" % i for i in range(40, 94)]
+INLINE_PAIRS = 3
+# code word fields (program.h)
+PAIRS_MASK = "0x3fff"
+ACLS_PROD_BIT, ACLS_MAX_BIT = 14, 15
+ACT_FIELD = "0x30010"  # s_bfe_u32 operand: 3 bits at bit 16
+DST_SHIFT = 20
+NEG_LOG2E = "0xbfb8aa3b"    # -log2(e)
+TWO_LOG2E = "0x4038aa3b"    # 2 log2(e)
 
 # sine: k = rint(z * 2/pi); r = z - k * pi/2 (pi/2 split in two fp32 parts);
 # Taylor polynomials of sin (degree 9) and cos (degree 10) on [-pi/4, pi/4]
@@ -145,61 +152,83 @@ def pair(R, cls, first, s0, w0, s1, w1):
 
 def aggregate(R, X, cls, rec):
     """One aggregation class over the node's pairs (s88 of them, >= 1 unless
-    the class is sum): the record's two inline pairs, then the overflow
-    array in chunks of two pairs.  Leaves agg in acc and jumps to Lagg."""
-    p = rec[7:15]
+    the class is sum): the record's three inline pairs, then the overflow
+    array in chunks of two pairs (the first chunk was requested at the
+    start of the node).  Leaves agg in acc and jumps to Lagg."""
+    p = rec[4:16]
     done = "Lagg_%s%%=" % X
     K = cls[0]
     out = []
     if cls == "sum":
         out += ["s_cmp_eq_u32 s88, 0", "s_cbranch_scc1 Lzero_%s%%=" % X]
-    out += pair(R, cls, True, p[0], p[1], p[2], p[3])
-    out += ["s_cmp_eq_u32 s88, 1", "s_cbranch_scc1 " + done]
-    out += pair(R, cls, False, p[4], p[5], p[6], p[7])
-    out += ["s_cmp_le_u32 s88, 2", "s_cbranch_scc1 " + done,
+    for k in range(INLINE_PAIRS):
+        out += pair(R, cls, k == 0, *p[4 * k:4 * k + 4])
+        if k < INLINE_PAIRS - 1:
+            out += ["s_cmp_eq_u32 s88, %d" % (k + 1), "s_cbranch_scc1 " + done]
+    out += ["s_cmp_le_u32 s88, %d" % INLINE_PAIRS, "s_cbranch_scc1 " + done,
             # overflow pairs: s87 left, read from s[82:83]; s[84:85] moves past them
-            "s_sub_u32 s87, s88, 2",
+            "s_sub_u32 s87, s88, %d" % INLINE_PAIRS,
             "s_mov_b64 s[82:83], s[84:85]",
             "s_lshl_b32 s89, s87, 4",
             "s_add_u32 s84, s84, s89",
             "s_addc_u32 s85, s85, 0",
             "Lo%s_%s%%=:" % (K, X),
-            "s_load_dwordx8 s[72:79], s[82:83], 0x0",
             "s_waitcnt lgkmcnt(0)"]
     out += pair(R, cls, False, "s72", "s73", "s74", "s75")
     out += ["s_cmp_eq_u32 s87, 1", "s_cbranch_scc1 " + done]
     out += pair(R, cls, False, "s76", "s77", "s78", "s79")
     out += ["s_sub_u32 s87, s87, 2",
+            "s_cmp_eq_u32 s87, 0",
+            "s_cbranch_scc1 " + done,
             "s_add_u32 s82, s82, 32",
             "s_addc_u32 s83, s83, 0",
-            "s_cmp_eq_u32 s87, 0",
-            "s_cbranch_scc0 Lo%s_%s%%=" % (K, X),
-            "s_branch " + done]
+            "s_load_dwordx8 s[72:79], s[82:83], 0x0",
+            "s_branch Lo%s_%s%%=" % (K, X)]
     return out
 
 
 # --------------------------------------------------------------- activation
-def act_pl(R, C, MASK):
-    # identity, abs, relu: maximum(z, mask ? 0 : c z), NaN-propagating
-    return seq(R, "v_mul_f32_e64 {ta}, {z}, " + C,
-               "v_cndmask_b32_e64 {ta}, {ta}, 0, " + MASK,
-               "v_maximum3_f32 {y}, {z}, {ta}, {ta}")
+# Activation blocks, one per code of the encoding (ACT_*): each leaves y in
+# the register it names (identity: z itself).
+def act_identity(R):
+    return [], "z"
 
 
-def act_expo(R, C, EA, EB, MASK):
-    # e = 2^(c u), u = mask ? z z : z;  y = mask ? e : ea + eb / (1 + e)
-    out = seq(R, "v_mul_f32_e32 {ta}, {z}, {z}",
-              "v_cndmask_b32_e64 {ta}, {z}, {ta}, " + MASK,
-              "v_mul_f32_e64 {ta}, {ta}, " + C,
-              "v_exp_f32_e32 {ta}, {ta}")
+def act_tanh(R):
+    # 1 - 2 / (1 + 2^(2 log2(e) z))
+    out = seq(R, "v_mul_f32_e32 {ta}, " + TWO_LOG2E + ", {z}", "v_exp_f32_e32 {ta}, {ta}")
     out += nop_if_single(R)
-    out += seq(R, "v_add_f32_e32 {tb}, 1.0, {ta}",
-               "v_rcp_f32_e32 {tb}, {tb}")
+    out += seq(R, "v_add_f32_e32 {tb}, 1.0, {ta}", "v_rcp_f32_e32 {tb}, {tb}")
     out += nop_if_single(R)
-    out += seq(R, "v_mov_b32_e32 {y}, " + EA,
-               "v_fmac_f32_e64 {y}, " + EB + ", {tb}",
-               "v_cndmask_b32_e64 {y}, {y}, {ta}, " + MASK)
-    return out
+    out += seq(R, "v_fma_f32 {y}, {tb}, -2.0, 1.0")
+    return out, "y"
+
+
+def act_sigmoid(R):
+    # 1 / (1 + 2^(-log2(e) z))
+    out = seq(R, "v_mul_f32_e32 {ta}, " + NEG_LOG2E + ", {z}", "v_exp_f32_e32 {ta}, {ta}")
+    out += nop_if_single(R)
+    out += seq(R, "v_add_f32_e32 {tb}, 1.0, {ta}", "v_rcp_f32_e32 {y}, {tb}")
+    out += nop_if_single(R)
+    return out, "y"
+
+
+def act_relu(R):
+    # maximum(z, 0), NaN-propagating
+    return seq(R, "v_maximum3_f32 {y}, {z}, 0, 0"), "y"
+
+
+def act_gauss(R):
+    # 2^(-log2(e) z z)
+    out = seq(R, "v_mul_f32_e32 {ta}, {z}, {z}", "v_mul_f32_e32 {ta}, " + NEG_LOG2E + ", {ta}",
+              "v_exp_f32_e32 {y}, {ta}")
+    out += nop_if_single(R)
+    return out, "y"
+
+
+def act_abs(R):
+    # maximum(z, -z), NaN-propagating
+    return seq(R, "v_maximum3_f32 {y}, {z}, -{z}, -{z}"), "y"
 
 
 def act_sin(R):
@@ -233,41 +262,92 @@ def act_sin(R):
         "v_bfi_b32 {y}, {w}, {p}, {r}",
         "v_lshlrev_b32_e32 {w}, 30, {q}",
         "v_and_b32_e32 {w}, 0x80000000, {w}",
-        "v_xor_b32_e32 {y}, {y}, {w}")
+        "v_xor_b32_e32 {y}, {y}, {w}"), "y"
+
+
+# in the order of the activation codes: identity, tanh, sigmoid, relu, sin,
+# gaussian, abs
+ACTS = (act_identity, act_tanh, act_sigmoid, act_relu, None, act_gauss, act_abs)
 
 
 # --------------------------------------------------------------- node, loop
-def node(R, X, rec, pref):
-    CODE, BIAS, RESP, C, EA, EB, MASK = rec[:7]
+INLINE_CONSTS = {"0", "1", "-1", "2", "4", "-2", "-4", "0.5", "-0.5", "1.0", "-1.0", "2.0",
+                 "-2.0", "4.0", "-4.0"}
+
+
+def encoded_bytes(line):
+    """Upper bound of an instruction's encoding: 8 bytes for VOP3 forms and
+    for anything carrying a 32-bit literal, else 4."""
+    op = line.split()[0]
+    if op.startswith(".") or op.endswith(":"):
+        return 0
+    args = [a.strip() for a in line[len(op):].replace(",", " ").split()]
+    literal = any(a.startswith("0x") or (a.lstrip("-").replace(".", "").isdigit() and
+                                         a not in INLINE_CONSTS and not a.startswith("offset"))
+                  for a in args)
+    vop3 = op.endswith("_e64") or op in ("v_fma_f32", "v_maximum3_f32", "v_bfi_b32",
+                                         "v_lshl_add_u64", "v_cmp_gt_u32_e64")
+    return 8 if (vop3 or literal or op in ("v_fmaak_f32", "v_fmamk_f32")) else 4
+
+
+def act_block_align(R):
+    """Byte alignment of the activation blocks (a power of two no smaller
+    than the largest block: sin with its tail)."""
+    return 256 if R.spl == 1 else 512
+
+
+def node(R, X, rec, pref, other):
+    CODE, BIAS, RESP = rec[:3]
     out = ["Lnode_%s%%=:" % X,
            "s_waitcnt lgkmcnt(0)",
            "s_add_u32 s86, s86, 64",
            "s_load_dwordx16 %s, s[80:81], s86" % pref,
-           "s_and_b32 s88, %s, 0xffff" % CODE,
-           "s_bitcmp1_b32 %s, 16" % CODE,
+           "s_and_b32 s88, %s, %s" % (CODE, PAIRS_MASK),
+           # request the first overflow chunk now when there is one
+           "s_cmp_le_u32 s88, %d" % INLINE_PAIRS,
+           "s_cbranch_scc1 Lnov_%s%%=" % X,
+           "s_load_dwordx8 s[72:79], s[84:85], 0x0",
+           "Lnov_%s%%=:" % X,
+           "s_bitcmp1_b32 %s, %d" % (CODE, ACLS_PROD_BIT),
            "s_cbranch_scc1 Lprod_%s%%=" % X,
-           "s_bitcmp1_b32 %s, 17" % CODE,
+           "s_bitcmp1_b32 %s, %d" % (CODE, ACLS_MAX_BIT),
            "s_cbranch_scc1 Lmax_%s%%=" % X]
     out += aggregate(R, X, "sum", rec)
     out += ["Lzero_%s%%=:" % X] + seq(R, "v_mov_b32_e32 {acc}, 0") + ["s_branch Lagg_%s%%=" % X]
     out += ["Lprod_%s%%=:" % X] + aggregate(R, X, "prod", rec)
     out += ["Lmax_%s%%=:" % X] + aggregate(R, X, "max", rec)
-    # z = bias + response' * agg
+    # z = bias + response' * agg, then jump to the activation's block
+    align = act_block_align(R)
+    shift = align.bit_length() - 1
     out += ["Lagg_%s%%=:" % X]
     out += seq(R, "v_mov_b32_e32 {z}, " + BIAS, "v_fmac_f32_e64 {z}, " + RESP + ", {acc}")
-    out += ["s_bitcmp1_b32 %s, 18" % CODE, "s_cbranch_scc1 Lexpo_%s%%=" % X,
-            "s_bitcmp1_b32 %s, 19" % CODE, "s_cbranch_scc1 Lsin_%s%%=" % X]
-    out += act_pl(R, C, MASK) + ["s_branch Lwr_%s%%=" % X]
-    out += ["Lexpo_%s%%=:" % X] + act_expo(R, C, EA, EB, MASK) + ["s_branch Lwr_%s%%=" % X]
-    out += ["Lsin_%s%%=:" % X] + act_sin(R)
-    # v[dst] = y
-    out += ["Lwr_%s%%=:" % X,
-            "s_lshr_b32 s89, %s, 20" % CODE,
-            "s_set_gpr_idx_on s89, gpr_idx(DST)"]
-    out += per_sample(R, "v_mov_b32_e32 {val}, {y}")
-    out += ["s_set_gpr_idx_off",
-            "s_cmp_eq_u32 s86, s91",
-            "s_cbranch_scc1 Ldone%="]
+    out += ["s_bfe_u32 s89, %s, %s" % (CODE, ACT_FIELD),
+            "s_lshl_b32 s89, s89, %d" % shift,
+            "s_getpc_b64 s[92:93]",
+            "Lpc_%s%%=:" % X,
+            "s_add_u32 s92, s92, s89",
+            "s_addc_u32 s93, s93, 0",
+            "s_add_u32 s92, s92, Lact_%s%%= - Lpc_%s%%=" % (X, X),
+            "s_addc_u32 s93, s93, 0",
+            "s_setpc_b64 s[92:93]",
+            ".p2align %d" % shift,
+            "Lact_%s%%=:" % X]
+    for k, fn in enumerate(ACTS):
+        body, yreg = fn(R) if fn is not None else act_sin(R)
+        # v[dst] = y; next node
+        body += ["s_lshr_b32 s89, %s, %d" % (CODE, DST_SHIFT),
+                 "s_set_gpr_idx_on s89, gpr_idx(DST)"]
+        body += per_sample(R, "v_mov_b32_e32 {val}, {%s}" % yreg)
+        body += ["s_set_gpr_idx_off",
+                 "s_cmp_eq_u32 s86, s91",
+                 "s_cbranch_scc1 Ldone%=",
+                 "s_branch Lnode_%s%%=" % other]
+        # the computed jump needs every block to fit its stride
+        size = sum(encoded_bytes(l) for l in body)
+        assert size <= align, "activation block %d needs %d > %d bytes" % (k, size, align)
+        if k:
+            out += [".p2align %d" % shift]
+        out += ["Lact%d_%s%%=:" % (k, X)] + body
     return out
 
 
@@ -281,10 +361,9 @@ def node_loop(R):
            "s_cmp_eq_u32 s91, 0",
            "s_cbranch_scc1 Ldone%=",
            "s_load_dwordx16 s[40:55], s[80:81], 0x0"]
-    out += node(R, "A", REC_A, "s[56:71]")
-    out += node(R, "B", REC_B, "s[40:55]")
-    out += ["s_branch Lnode_A%=",
-            "Ldone%=:",
+    out += node(R, "A", REC_A, "s[56:71]", "B")
+    out += node(R, "B", REC_B, "s[40:55]", "A")
+    out += ["Ldone%=:",
             "s_waitcnt lgkmcnt(0)"]
     return out
 
@@ -438,12 +517,13 @@ HEADER = """\
 // block and are listed as clobbers with the scratch VGPRs after them.
 //
 // Scalar registers: s40..s55 record buffer A, s56..s71 record buffer B
-// (16-word records with the node's first two edge pairs; the next record
-// is prefetched while the current one runs), s72..s79 two overflow pairs,
-// s80:81 record array, s82:83 overflow read pointer, s84:85 overflow edges
-// of the current node, s86 record byte offset, s87 pairs left, s88 pairs of
-// the node, s89 scratch, s90 saved M0, s91 end offset; steps 1, 2 and 4 use
-// s40..s55 before and after the node loop.
+// (16-word records with the node's first three edge pairs; the next record
+// is prefetched while the current one runs), s72..s79 two overflow pairs
+// (the first two requested at the start of the node), s80:81 record array,
+// s82:83 overflow read pointer, s84:85 overflow edges of the current node,
+// s86 record byte offset, s87 pairs left, s88 pairs of the node, s89
+// scratch, s90 saved M0, s91 end offset, s92:93 jump target; steps 1, 2 and
+// 4 use s40..s55 before and after the node loop.
 // Reads of v[slot] and the write of v[dst] use GPR-index mode with the
 // program's uniform slots; an indexed read of a pair keeps the mode on and
 // only moves the index, and every sample of the lane shares it.
@@ -451,10 +531,12 @@ HEADER = """\
 // Aggregation classes (program.h): sum (mean folds 1/degree into the
 // response), product, max (min is max over negated weights with negated
 // response), the first pair initialising the accumulator and an empty sum
-// giving 0.  Max uses the NaN-propagating maximum.  Activation classes: PL
-// (identity, abs, relu) as maximum(z, mask ? 0 : c z); EXPO (sigmoid, tanh,
-// gaussian) on the hardware base-2 exponential and reciprocal; SIN by
-// Cody-Waite reduction and Taylor polynomials.  The C++ node loop of the
+// giving 0.  Max uses the NaN-propagating maximum.  Activations: one block
+// per code, entered by a computed jump (blocks aligned to a fixed stride):
+// identity; relu maximum(z, 0) and abs maximum(z, -z); sigmoid, tanh and
+// gaussian on the hardware base-2 exponential and reciprocal; sin by
+// Cody-Waite reduction and Taylor polynomials.  Each block ends with the
+// write of v[dst] and the jump to the next node.  The C++ node loop of the
 // LDS store performs the same operations in the same order.
 //
 // Hazards: a transcendental's result is read no sooner than one instruction

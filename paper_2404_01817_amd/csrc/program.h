@@ -24,8 +24,8 @@
 // kernels consume edges in pairs without per-edge tests: for sum and mean a
 // term 1 * v[zero slot], for product 1 * v[one slot], for max and min a copy
 // of the node's first edge.  None of these changes any result.  The first
-// two pairs live in the node's record (one scalar load brings a node and its
-// usual in-edges); further pairs follow in the overflow edge array, node
+// three pairs live in the node's record (one scalar load brings a node and
+// its usual in-edges); further pairs follow in the overflow edge array, node
 // after node.
 //
 // After the P genome programs, a population area lists the genomes by slot
@@ -68,34 +68,25 @@ __host__ __device__ constexpr int class_slots(int cls, int N) {
 // slot of the constant 0 (the constant 1 is the next slot)
 __host__ __device__ constexpr int zero_slot(int cls, int N) { return class_slots(cls, N) - 2; }
 
-// node record (16 words), record k describes position I + k.  The
-// aggregation and activation are folded into a few classes so the forward
-// branches little:
-//   aggregation class: SUM (sum, mean, and any node without incoming
-//   edges), PROD, MAX (max; min is stored as max over negated weights with
-//   the response negated, since min(t) = -max(-t) exactly);
-//   z = bias + response' * agg(terms), response' = response / in-degree for
-//   mean, -response for min, else response;
-//   activation class PL (identity, relu, abs): y = z if !(z <= 0), else
-//   (mask ? 0 : c * z) with c = 1 (identity), -1 (abs), 0 + mask (relu);
-//   EXPO (sigmoid, tanh, gaussian): e = 2^(c * u) with u = z (u = z*z and
-//   mask for the gaussian); y = mask ? e : ea + eb / (1 + e), with
-//   (c, ea, eb) = (-log2 e, 0, 1) sigmoid, (2 log2 e, 1, -2) tanh;
-//   SIN: y = sin z.
-constexpr int REC_CODE = 0;   // pairs | aggregation class << 16 | activation class << 18 | dst slot << 20
+// node record (16 words), record k describes position I + k:
+//   code: pairs | aggregation class << 14 | activation << 16 | dst slot << 20
+//   bias, response', (unused), then the node's first three edge pairs.
+// Aggregation classes: SUM (sum, mean, and any node without incoming
+// edges), PROD, MAX (max; min is stored as max over negated weights with
+// the response negated, since min(t) = -max(-t) exactly);
+// z = bias + response' * agg(terms), response' = response / in-degree for
+// mean, -response for min, else response; y = act(z) with the activation
+// code of the encoding (ACT_*).
+constexpr int REC_CODE = 0;
 constexpr int REC_BIAS = 1;   // float
 constexpr int REC_RESP = 2;   // float, response'
-constexpr int REC_C = 3;      // float
-constexpr int REC_EA = 4;     // float
-constexpr int REC_EB = 5;     // float
-constexpr int REC_MASK = 6;   // two words: 64-bit lane mask, all ones or zero
-constexpr int REC_PAIRS = 8;  // the node's first two edge pairs (8 words)
+constexpr int REC_PAIRS = 4;  // the node's first three edge pairs (12 words)
 constexpr int REC_WORDS = 16;
-constexpr int REC_INLINE_PAIRS = 2;
+constexpr int REC_INLINE_PAIRS = 3;
+constexpr int REC_PAIRS_MASK = 0x3fff;
 enum AggClass { ACLS_SUM = 0, ACLS_PROD = 1, ACLS_MAX = 2 };
-enum ActClass { XCLS_PL = 0, XCLS_EXPO = 1, XCLS_SIN = 2 };
-__host__ __device__ constexpr uint32_t rec_code(int pairs, int acls, int xcls, int dst) {
-    return (uint32_t)pairs | ((uint32_t)acls << 16) | ((uint32_t)xcls << 18) |
+__host__ __device__ constexpr uint32_t rec_code(int pairs, int acls, int act, int dst) {
+    return (uint32_t)pairs | ((uint32_t)acls << 14) | ((uint32_t)act << 16) |
            ((uint32_t)dst << 20);
 }
 // edge (2 words): source slot, weight

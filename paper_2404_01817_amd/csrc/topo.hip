@@ -506,22 +506,10 @@ __device__ __forceinline__ void topo_genome(const TopoItem &a, size_t g) {
         const float rp = deg == 0 ? resp
                                   : (agg == AGG_MEAN ? resp * (1.0f / (float)deg)
                                                      : (agg == AGG_MIN ? -resp : resp));
-        int xcls = XCLS_PL, mask = 0;
-        float cf = 1.0f, xa = 0.0f, xb = 0.0f;
-        if (act == ACT_ABS) cf = -1.0f;
-        if (act == ACT_RELU) cf = 0.0f, mask = -1;
-        if (act == ACT_SIGMOID) xcls = XCLS_EXPO, cf = -1.4426950216293335f, xa = 0.0f, xb = 1.0f;
-        if (act == ACT_TANH) xcls = XCLS_EXPO, cf = 2.885390043258667f, xa = 1.0f, xb = -2.0f;
-        if (act == ACT_GAUSS) xcls = XCLS_EXPO, cf = -1.4426950216293335f, mask = -1;
-        if (act == ACT_SIN) xcls = XCLS_SIN;
-        prog[r0 + REC_CODE] = (int32_t)rec_code(pairs, acls, xcls, s_slot[t]);
+        prog[r0 + REC_CODE] = (int32_t)rec_code(pairs, acls, act, s_slot[t]);
         progf[r0 + REC_BIAS] = bias;
         progf[r0 + REC_RESP] = rp;
-        progf[r0 + REC_C] = cf;
-        progf[r0 + REC_EA] = xa;
-        progf[r0 + REC_EB] = xb;
-        prog[r0 + REC_MASK] = mask;
-        prog[r0 + REC_MASK + 1] = mask;
+        prog[r0 + REC_PAIRS - 1] = 0;
         // unused inline edges: a harmless (constant slot, 0) pair
         for (int j = 2 * pairs; j < 2 * REC_INLINE_PAIRS; ++j) {
             prog[r0 + REC_PAIRS + 2 * j] = zs;
@@ -541,7 +529,7 @@ __device__ __forceinline__ void topo_genome(const TopoItem &a, size_t g) {
                 if (agg == AGG_MIN) w = -w;
             }
             const int widx = deg < 2 * REC_INLINE_PAIRS ? r0 + REC_PAIRS + 2 * deg
-                                                         : eoff + EDGE_WORDS * (ob + deg - 4);
+                                                         : eoff + EDGE_WORDS * (ob + deg - 2 * REC_INLINE_PAIRS);
             prog[widx] = slot;
             progf[widx + 1] = w;
         }
@@ -562,7 +550,7 @@ __device__ __forceinline__ void topo_genome(const TopoItem &a, size_t g) {
         for (int k = s_inoff[d]; k < s_inoff[d + 1]; ++k) j += (s_key[e_src[in_list[k]]] < ks);
         const int rd = rec_off(O) + REC_WORDS * (s_pos[d] - I);
         const int widx = j < 2 * REC_INLINE_PAIRS ? rd + REC_PAIRS + 2 * j
-                                                   : eoff + EDGE_WORDS * (s_curo[d] + j - 4);
+                                                   : eoff + EDGE_WORDS * (s_curo[d] + j - 2 * REC_INLINE_PAIRS);
         // min is stored as max over negated weights (negation is exact)
         const float w = conns[(size_t)c * 4 + 3];
         prog[widx] = s_slot[s];
