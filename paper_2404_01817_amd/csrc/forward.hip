@@ -200,9 +200,9 @@ __device__ __forceinline__ void run_program(cprog_t *prog, int N, int O, int I, 
     i32x16 r = *(cint16_t *)rec;
     for (int k = 0; k < ncomp; ++k) {
         const unsigned code = (unsigned)r[REC_CODE];
-        const int pairs = (int)(code & (unsigned)REC_PAIRS_MASK);
+        const int pairs = r[REC_NPAIRS];
         const int acls = (int)((code >> 14) & 3u), act = (int)((code >> 16) & 7u);
-        const int dst = (int)(code >> 20);
+        const int dst = (int)(code & (unsigned)REC_DST_MASK);
         const float bias = fbits(r[REC_BIAS]), resp = fbits(r[REC_RESP]);
         // next record (the record array has room for N records)
         const i32x16 rn = *(cint16_t *)(rec + REC_WORDS * (k + 1));
@@ -342,7 +342,7 @@ __device__ __forceinline__ void forward_unit_reg(citem_t *it, int g, int chunk, 
     if (!GRID) dma_inputs(in_g + (size_t)t0 * TS * I, istage, min(TS, B - t0 * TS) * I, vec4);
     // the records and overflow edges the node loop will read, in one burst
     // (the first tile's wait covers it)
-    touch_lines(rec, REC_WORDS * ncomp, ostage);
+    touch_lines(rec, REC_WORDS * (ncomp + 1), ostage);
     touch_lines(edg, EDGE_WORDS * prog[HDR_NEDGES], ostage);
     if (GRID) wait_dma();
 

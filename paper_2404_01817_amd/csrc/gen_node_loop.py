@@ -39,16 +39,15 @@ VARIANTS = [
 ]
 
 # scalar register map (shared by all variants)
-# record buffers: code, bias, response', (unused), three edge pairs
+# record buffers: code, bias, response', pair count, three edge pairs
 REC_A = tuple("s%d" % i for i in range(40, 56))
 REC_B = tuple("s%d" % i for i in range(56, 72))
-SGPR_CLOBBERS = ["s%d" % i for i in range(40, 94)]
+SGPR_CLOBBERS = ["s%d" % i for i in range(40, 96)]
 INLINE_PAIRS = 3
 # code word fields (program.h)
-PAIRS_MASK = "0x3fff"
+DST_MASK = "0x7ff"
 ACLS_PROD_BIT, ACLS_MAX_BIT = 14, 15
 ACT_FIELD = "0x30010"  # s_bfe_u32 operand: 3 bits at bit 16
-DST_SHIFT = 20
 NEG_LOG2E = "0xbfb8aa3b"    # -log2(e)
 TWO_LOG2E = "0x4038aa3b"    # 2 log2(e)
 
@@ -151,23 +150,24 @@ def pair(R, cls, first, s0, w0, s1, w1):
 
 
 def aggregate(R, X, cls, rec):
-    """One aggregation class over the node's pairs (s88 of them, >= 1 unless
+    """One aggregation class over the node's pairs (rec[3] of them, >= 1 unless
     the class is sum): the record's three inline pairs, then the overflow
     array in chunks of two pairs (the first chunk was requested at the
     start of the node).  Leaves agg in acc and jumps to Lagg."""
     p = rec[4:16]
+    NP = rec[3]
     done = "Lagg_%s%%=" % X
     K = cls[0]
     out = []
     if cls == "sum":
-        out += ["s_cmp_eq_u32 s88, 0", "s_cbranch_scc1 Lzero_%s%%=" % X]
+        out += ["s_cmp_eq_u32 %s, 0" % NP, "s_cbranch_scc1 Lzero_%s%%=" % X]
     for k in range(INLINE_PAIRS):
         out += pair(R, cls, k == 0, *p[4 * k:4 * k + 4])
         if k < INLINE_PAIRS - 1:
-            out += ["s_cmp_eq_u32 s88, %d" % (k + 1), "s_cbranch_scc1 " + done]
-    out += ["s_cmp_le_u32 s88, %d" % INLINE_PAIRS, "s_cbranch_scc1 " + done,
+            out += ["s_cmp_eq_u32 %s, %d" % (NP, k + 1), "s_cbranch_scc1 " + done]
+    out += ["s_cmp_le_u32 %s, %d" % (NP, INLINE_PAIRS), "s_cbranch_scc1 " + done,
             # overflow pairs: s87 left, read from s[82:83]; s[84:85] moves past them
-            "s_sub_u32 s87, s88, %d" % INLINE_PAIRS,
+            "s_sub_u32 s87, %s, %d" % (NP, INLINE_PAIRS),
             "s_mov_b64 s[82:83], s[84:85]",
             "s_lshl_b32 s89, s87, 4",
             "s_add_u32 s84, s84, s89",
@@ -296,15 +296,17 @@ def act_block_align(R):
     return 256 if R.spl == 1 else 512
 
 
-def node(R, X, rec, pref, other):
-    CODE, BIAS, RESP = rec[:3]
+def node(R, X, rec, pref, other, base):
+    """One node with record buffer rec (the next record is loaded into
+    pref); base: SGPR pair holding the address of this copy's activation
+    blocks; other: the tag of the copy that runs the next node."""
+    CODE, BIAS, RESP, NP = rec[:4]
     out = ["Lnode_%s%%=:" % X,
            "s_waitcnt lgkmcnt(0)",
            "s_add_u32 s86, s86, 64",
            "s_load_dwordx16 %s, s[80:81], s86" % pref,
-           "s_and_b32 s88, %s, %s" % (CODE, PAIRS_MASK),
            # request the first overflow chunk now when there is one
-           "s_cmp_le_u32 s88, %d" % INLINE_PAIRS,
+           "s_cmp_le_u32 %s, %d" % (NP, INLINE_PAIRS),
            "s_cbranch_scc1 Lnov_%s%%=" % X,
            "s_load_dwordx8 s[72:79], s[84:85], 0x0",
            "Lnov_%s%%=:" % X,
@@ -319,28 +321,23 @@ def node(R, X, rec, pref, other):
     # z = bias + response' * agg, then jump to the activation's block
     align = act_block_align(R)
     shift = align.bit_length() - 1
+    blo, bhi = base
     out += ["Lagg_%s%%=:" % X]
     out += seq(R, "v_mov_b32_e32 {z}, " + BIAS, "v_fmac_f32_e64 {z}, " + RESP + ", {acc}")
     out += ["s_bfe_u32 s89, %s, %s" % (CODE, ACT_FIELD),
             "s_lshl_b32 s89, s89, %d" % shift,
-            "s_getpc_b64 s[92:93]",
-            "Lpc_%s%%=:" % X,
-            "s_add_u32 s92, s92, s89",
-            "s_addc_u32 s93, s93, 0",
-            "s_add_u32 s92, s92, Lact_%s%%= - Lpc_%s%%=" % (X, X),
-            "s_addc_u32 s93, s93, 0",
-            "s_setpc_b64 s[92:93]",
+            "s_add_u32 s88, %s, s89" % blo,
+            "s_addc_u32 s89, %s, 0" % bhi,
+            "s_setpc_b64 s[88:89]",
             ".p2align %d" % shift,
             "Lact_%s%%=:" % X]
     for k, fn in enumerate(ACTS):
         body, yreg = fn(R) if fn is not None else act_sin(R)
         # v[dst] = y; next node
-        body += ["s_lshr_b32 s89, %s, %d" % (CODE, DST_SHIFT),
+        body += ["s_and_b32 s89, %s, %s" % (CODE, DST_MASK),
                  "s_set_gpr_idx_on s89, gpr_idx(DST)"]
         body += per_sample(R, "v_mov_b32_e32 {val}, {%s}" % yreg)
         body += ["s_set_gpr_idx_off",
-                 "s_cmp_eq_u32 s86, s91",
-                 "s_cbranch_scc1 Ldone%=",
                  "s_branch Lnode_%s%%=" % other]
         # the computed jump needs every block to fit its stride
         size = sum(encoded_bytes(l) for l in body)
@@ -348,21 +345,27 @@ def node(R, X, rec, pref, other):
         if k:
             out += [".p2align %d" % shift]
         out += ["Lact%d_%s%%=:" % (k, X)] + body
+    # code ACT_END: the sentinel record after the last node
+    out += [".p2align %d" % shift, "Lact7_%s%%=:" % X, "s_branch Ldone%="]
     return out
 
 
 def node_loop(R):
-    """All computed nodes: %[rec] record 0, %[edg] overflow edges, %[n]
-    records.  M0 is saved in s90 by the caller."""
+    """All computed nodes: %[rec] record 0 (the records end with a sentinel),
+    %[edg] overflow edges.  M0 is saved in s90 by the caller."""
     out = ["s_mov_b64 s[80:81], %[rec]",
            "s_mov_b64 s[84:85], %[edg]",
-           "s_lshl_b32 s91, %[n], 6",
            "s_mov_b32 s86, 0",
-           "s_cmp_eq_u32 s91, 0",
-           "s_cbranch_scc1 Ldone%=",
-           "s_load_dwordx16 s[40:55], s[80:81], 0x0"]
-    out += node(R, "A", REC_A, "s[56:71]", "B")
-    out += node(R, "B", REC_B, "s[40:55]", "A")
+           "s_load_dwordx16 s[40:55], s[80:81], 0x0",
+           # addresses of the two copies' activation blocks
+           "s_getpc_b64 s[92:93]",
+           "Lpc%=:",
+           "s_add_u32 s94, s92, Lact_B%= - Lpc%=",
+           "s_addc_u32 s95, s93, 0",
+           "s_add_u32 s92, s92, Lact_A%= - Lpc%=",
+           "s_addc_u32 s93, s93, 0"]
+    out += node(R, "A", REC_A, "s[56:71]", "B", ("s92", "s93"))
+    out += node(R, "B", REC_B, "s[40:55]", "A", ("s94", "s95"))
     out += ["Ldone%=:",
             "s_waitcnt lgkmcnt(0)"]
     return out
@@ -508,8 +511,8 @@ HEADER = """\
 //      pieces of 16 bytes (%[dvec] = 1) or 4 bytes (%[dvec] = 0) from the
 //      global address %[dsrc] onward, lane l taking piece l of each round
 //      of 64; %[lane] is the lane id (the only VGPR operand);
-//   3. the node loop over %[n] records from %[rec], overflow edges from
-//      %[edg];
+//   3. the node loop over the records from %[rec] up to the sentinel record
+//      that follows the last node, overflow edges from %[edg];
 //   4. output j of each sample s = v[slot j] (slots at %[outs], j < %[no])
 //      to the LDS output area at %[om0] + 4 (s O + j).
 // The value vectors (slot s of sample h in v[base_h + s]; every slot the
@@ -521,9 +524,9 @@ HEADER = """\
 // is prefetched while the current one runs), s72..s79 two overflow pairs
 // (the first two requested at the start of the node), s80:81 record array,
 // s82:83 overflow read pointer, s84:85 overflow edges of the current node,
-// s86 record byte offset, s87 pairs left, s88 pairs of the node, s89
-// scratch, s90 saved M0, s91 end offset, s92:93 jump target; steps 1, 2 and
-// 4 use s40..s55 before and after the node loop.
+// s86 record byte offset, s87 pairs left, s88:89 jump target and scratch,
+// s90 saved M0, s92:93 and s94:95 the two copies' activation blocks; steps
+// 1, 2 and 4 use s40..s55 before and after the node loop.
 // Reads of v[slot] and the write of v[dst] use GPR-index mode with the
 // program's uniform slots; an indexed read of a pair keeps the mode on and
 // only moves the index, and every sample of the lane shares it.

@@ -69,8 +69,12 @@ __host__ __device__ constexpr int class_slots(int cls, int N) {
 __host__ __device__ constexpr int zero_slot(int cls, int N) { return class_slots(cls, N) - 2; }
 
 // node record (16 words), record k describes position I + k:
-//   code: pairs | aggregation class << 14 | activation << 16 | dst slot << 20
-//   bias, response', (unused), then the node's first three edge pairs.
+//   code: dst slot | aggregation class << 14 | activation << 16 (the
+//   register kernels index with the low 8 bits of the code word, and every
+//   register slot is below 256);
+//   bias, response', pair count, then the node's first three edge pairs.
+// After the last node a sentinel record (activation code ACT_END, no
+// pairs) ends the kernels' node loop.
 // Aggregation classes: SUM (sum, mean, and any node without incoming
 // edges), PROD, MAX (max; min is stored as max over negated weights with
 // the response negated, since min(t) = -max(-t) exactly);
@@ -80,14 +84,15 @@ __host__ __device__ constexpr int zero_slot(int cls, int N) { return class_slots
 constexpr int REC_CODE = 0;
 constexpr int REC_BIAS = 1;   // float
 constexpr int REC_RESP = 2;   // float, response'
+constexpr int REC_NPAIRS = 3; // edge pairs (after padding to an even count)
 constexpr int REC_PAIRS = 4;  // the node's first three edge pairs (12 words)
 constexpr int REC_WORDS = 16;
 constexpr int REC_INLINE_PAIRS = 3;
-constexpr int REC_PAIRS_MASK = 0x3fff;
+constexpr int REC_DST_MASK = 0x7ff;
+constexpr int ACT_END = 7;    // sentinel activation code
 enum AggClass { ACLS_SUM = 0, ACLS_PROD = 1, ACLS_MAX = 2 };
-__host__ __device__ constexpr uint32_t rec_code(int pairs, int acls, int act, int dst) {
-    return (uint32_t)pairs | ((uint32_t)acls << 14) | ((uint32_t)act << 16) |
-           ((uint32_t)dst << 20);
+__host__ __device__ constexpr uint32_t rec_code(int acls, int act, int dst) {
+    return (uint32_t)dst | ((uint32_t)acls << 14) | ((uint32_t)act << 16);
 }
 // edge (2 words): source slot, weight
 constexpr int EDGE_WORDS = 2;
