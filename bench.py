@@ -24,6 +24,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+# fp32 vector peak without packed math: 256 CUs x 4 SIMDs x 16 lanes x 2 flops
+# (fused multiply-add) x 2.4 GHz (packed fp32 would double it; this build does
+# not use packed fp32 instructions)
+VALU_PEAK_TFLOPS = 78.6
+# algorithmic flops of an activation (identity, tanh, sigmoid, relu, sin,
+# gaussian, abs): the arithmetic of its definition on the hardware's base-2
+# exponential and reciprocal, sin as range reduction + two short polynomials
+ACT_FLOPS = (0, 5, 4, 1, 15, 3, 1)
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "forward_control_traffic.json")
 
 
@@ -248,10 +256,24 @@ def bench_cppn(args, torch, neat, synth):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / args.steps
     units = pop.P * Q
+    # algorithmic flops per genome-input: 2 per enabled connection (multiply,
+    # add), 2 per computed node (response, bias) plus its activation's
+    flops = 0
+    for g in range(pop.P):
+        nd, cn = pop.nodes[g], pop.conns[g]
+        live = ~np.isnan(nd[:, 0])
+        comp = live & (nd[:, 0] >= pop.I)
+        en = (~np.isnan(cn[:, 0])) & (cn[:, 2] == 1.0)
+        flops += 2 * int(en.sum()) + int(sum(2 + ACT_FLOPS[int(a)] for a in nd[comp, 3]))
+    tflops = flops * Q / (ms / 1e3) / 1e12
     return {"workload": "cppn: P=1000, N_max=30, C_max=120, I=5, O=1, 65536 grid queries "
                         "per genome generated in the kernel",
             "ms": round(ms, 4), "value": round(units / (ms / 1e3), 1),
-            "unit": "genome-inputs/s", "output_GBps": round(units * 4 / (ms / 1e3) / 1e9, 1)}
+            "unit": "genome-inputs/s", "output_GBps": round(units * 4 / (ms / 1e3) / 1e9, 1),
+            "roofline": {"bound": "alu", "achieved": round(tflops, 2),
+                         "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": round(tflops / VALU_PEAK_TFLOPS, 4),
+                         "flops_per_genome_input": round(flops / pop.P, 1)}}
 
 
 def main():
