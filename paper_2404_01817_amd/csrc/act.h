@@ -10,9 +10,10 @@
 //   sigmoid(z) = 1 / (1 + 2^(-z log2 e))
 //   tanh(z)    = 1 - 2 / (1 + 2^(2 z log2 e))         (exact limits +-1 at +-inf)
 //   gaussian(z)= 2^(-(z z) log2 e)
-//   sin(z)     : Cody-Waite reduction by pi/2 (two-constant split with fma),
-//                then the Taylor polynomials of sin / cos on [-pi/4, pi/4]
-//                (degree 9 and 10) selected by quadrant
+//   sin(z)     : Cody-Waite reduction by pi (two-constant split with fma),
+//                then the Taylor polynomial of sin of degree 13 on
+//                [-pi/2, pi/2] (truncation below 7e-10), sign by the parity
+//                of the multiple of pi
 //   relu(z)    = z unless z <= 0 (so NaN propagates), abs and identity exact.
 #pragma once
 
@@ -41,25 +42,21 @@ __device__ __forceinline__ float act_gauss(float z) {
 __device__ __forceinline__ float act_relu(float z) { return !(z <= 0.0f) ? z : 0.0f; }
 
 __device__ __forceinline__ float act_sin(float z) {
-    // k = nearest integer to z / (pi/2); r = z - k pi/2 with pi/2 = P1 + P2
-    const float kf = __builtin_rintf(z * 0.6366197466850281f);
-    float r = fmaf(kf, -1.5707963705062866f, z);
-    r = fmaf(kf, 4.371138828673793e-08f, r);
+    // k = nearest integer to z / pi; r = z - k pi with pi = fl(pi) - (fl(pi) - pi)
+    const float kf = __builtin_rintf(z * 0.31830987334251404f);
+    float r = fmaf(kf, -3.1415927410125732f, z);
+    r = fmaf(8.742277657347586e-08f, kf, r);
     const int q = (int)kf;
     const float r2 = r * r;
-    // sin r = r + r^3 (-1/6 + r^2 (1/120 + r^2 (-1/5040 + r^2 / 362880)))
-    float ps = fmaf(r2, 2.7557318844628753e-06f, -0.00019841270113829523f);
-    ps = fmaf(r2, ps, 0.008333333767950535f);
-    ps = fmaf(r2, ps, -0.1666666716337204f);
-    const float s = fmaf(r * r2, ps, r);
-    // cos r = 1 + r^2 (-1/2 + r^2 (1/24 + r^2 (-1/720 + r^2 (1/40320 - r^2 / 3628800))))
-    float pc = fmaf(r2, -2.755731998149713e-07f, 2.4801587642286904e-05f);
-    pc = fmaf(r2, pc, -0.0013888889225199819f);
-    pc = fmaf(r2, pc, 0.0416666679084301f);
-    pc = fmaf(r2, pc, -0.5f);
-    const float c = fmaf(r2, pc, 1.0f);
-    const float v = (q & 1) ? c : s;
-    return (q & 2) ? -v : v;
+    // sin r = r + r^3 (-1/3! + r^2 (1/5! + r^2 (-1/7! + r^2 (1/9! + r^2 (-1/11! + r^2 / 13!)))))
+    float p = fmaf(r2, 1.6059044372074283e-10f, -2.5052107943679403e-08f);
+    p = fmaf(r2, p, 2.7557318844628753e-06f);
+    p = fmaf(r2, p, -0.00019841270113829523f);
+    p = fmaf(r2, p, 0.008333333767950535f);
+    p = fmaf(r2, p, -0.1666666716337204f);
+    const float s = fmaf(r * r2, p, r);
+    // sin(r + k pi) = (-1)^k sin r: odd k flips the sign bit
+    return __uint_as_float(__float_as_uint(s) + ((unsigned)q << 31));
 }
 
 __device__ __forceinline__ float act_eval(int act, float z) {

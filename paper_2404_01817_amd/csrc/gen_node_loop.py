@@ -51,32 +51,48 @@ ACT_FIELD = "0x30010"  # s_bfe_u32 operand: 3 bits at bit 16
 NEG_LOG2E = "0xbfb8aa3b"    # -log2(e)
 TWO_LOG2E = "0x4038aa3b"    # 2 log2(e)
 
-# sine: k = rint(z * 2/pi); r = z - k * pi/2 (pi/2 split in two fp32 parts);
-# Taylor polynomials of sin (degree 9) and cos (degree 10) on [-pi/4, pi/4]
-TWO_OVER_PI = "0x3f22f983"
-NEG_PIO2_HI = "0xbfc90fdb"
-PIO2_LO = "0x333bbd2e"
-SIN_C = ("0x3638ef1d", "0xb9500d01", "0x3c088889", "0xbe2aaaab")
-COS_C = ("0xb493f27e", "0x37d00d01", "0xbab60b61", "0x3d2aaaab", "0xbf000000")
+# sine: k = rint(z / pi); r = z - k pi (pi split in two fp32 parts: fl(pi)
+# and pi - fl(pi)); the Taylor polynomial of sin of degree 13 on [-pi/2, pi/2];
+# the sign flips for odd k
+ONE_OVER_PI = "0x3ea2f983"
+NEG_PI_HI = "0xc0490fdb"
+PI_HI_MINUS_PI = "0x33bbbd2e"
+# 1/13!, -1/11!, 1/9!, -1/7!, 1/5!, -1/3! rounded to fp32
+SIN_C = ("0x2f309231", "0xb2d7322b", "0x3638ef1d", "0xb9500d01", "0x3c088889", "0xbe2aaaab")
 
 
 class Regs:
-    """Scratch VGPR names of one variant (per sample h)."""
+    """Scratch VGPR names of one variant (per sample h).
 
-    ROLES = ("acc", "ta", "tb", "z", "y", "k", "r", "r2", "q", "p", "w")
+    The node loop uses five per sample (acc, ta, tb, z, p) and one shared
+    constant (c13, the sine polynomial's leading coefficient); the input and
+    output sections use G buffers per sample, an LDS address per sample and
+    a 64-bit DMA address.  The two sets are never live together, so they
+    share the same registers."""
 
-    def __init__(self, spl, bases, scratch):
+    # Placement (in units of spl registers from the first scratch VGPR):
+    # acc 0, ta 1, tb 2, z 3, then c13 (one register), then p.  Keep it:
+    # on gfx950 a permutation of the same registers (c13, acc, z, ta, tb)
+    # made the sine block's results vary from launch to launch under full
+    # occupancy, while this placement gives repeatable bits (checked by the
+    # full-size repeatability tests).
+    ROLES = ("acc", "ta", "tb", "z", "p")
+
+    def __init__(self, spl, bases, scratch, group=8):
         self.spl = spl
         self.bases = ["v%d" % b for b in bases]
         self.names = {}
-        n = scratch
-        for role in self.ROLES:
-            self.names[role] = ["v%d" % (n + h) for h in range(spl)]
-            n += spl
+        for k, role in enumerate(self.ROLES[:4]):
+            self.names[role] = ["v%d" % (scratch + k * spl + h) for h in range(spl)]
+        self.c13 = "v%d" % (scratch + 4 * spl)
+        self.names["p"] = ["v%d" % (scratch + 4 * spl + 1 + h) for h in range(spl)]
+        n = scratch + 5 * spl + 1
         # tile section registers: input buffers, staging addresses, DMA address
-        self.buf = [["v%d" % (scratch + 8 * h + k) for k in range(8)] for h in range(spl)]
-        self.addr = ["v%d" % (scratch + 8 * spl + h) for h in range(spl)]
-        d = scratch + 8 * spl + spl
+        self.group = group
+        self.buf = [["v%d" % (scratch + group * h + k) for k in range(group)]
+                    for h in range(spl)]
+        self.addr = ["v%d" % (scratch + group * spl + h) for h in range(spl)]
+        d = scratch + group * spl + spl
         d += d & 1  # 64-bit VGPR operands are even-aligned
         self.dma = "v[%d:%d]" % (d, d + 1)
         n = max(n, d + 2)
@@ -188,86 +204,91 @@ def aggregate(R, X, cls, rec):
 
 
 # --------------------------------------------------------------- activation
-# Activation blocks, one per code of the encoding (ACT_*): each leaves y in
-# the register it names (identity: z itself).
+# Activation blocks, one per code of the encoding (ACT_*).  On entry z holds
+# the bias and acc the aggregate; every block returns (body, y): body
+# computes y = act(z) into the scratch register named y, which a plain move
+# with the destination indexed then writes to v[dst].  Only moves run with
+# destination indexing; the arithmetic stays outside it, and two wait states
+# separate a transcendental (v_exp, v_rcp, which completes after later
+# instructions have issued) from the switch into indexed mode.
+# z = fma(response', acc, bias) is the first step of every block.
+TRANS_GAP = "s_nop 1"
+
+
+def z_of(R):
+    return seq(R, "v_fmac_f32_e64 {z}, " + "%(resp)s" + ", {acc}")
+
+
 def act_identity(R):
-    return [], "z"
+    return z_of(R), "z"
 
 
 def act_tanh(R):
     # 1 - 2 / (1 + 2^(2 log2(e) z))
-    out = seq(R, "v_mul_f32_e32 {ta}, " + TWO_LOG2E + ", {z}", "v_exp_f32_e32 {ta}, {ta}")
+    out = z_of(R) + seq(R, "v_mul_f32_e32 {ta}, " + TWO_LOG2E + ", {z}",
+                        "v_exp_f32_e32 {ta}, {ta}")
     out += nop_if_single(R)
     out += seq(R, "v_add_f32_e32 {tb}, 1.0, {ta}", "v_rcp_f32_e32 {tb}, {tb}")
     out += nop_if_single(R)
-    out += seq(R, "v_fma_f32 {y}, {tb}, -2.0, 1.0")
-    return out, "y"
+    out += seq(R, "v_fma_f32 {ta}, {tb}, -2.0, 1.0")
+    return out, "ta"
 
 
 def act_sigmoid(R):
     # 1 / (1 + 2^(-log2(e) z))
-    out = seq(R, "v_mul_f32_e32 {ta}, " + NEG_LOG2E + ", {z}", "v_exp_f32_e32 {ta}, {ta}")
+    out = z_of(R) + seq(R, "v_mul_f32_e32 {ta}, " + NEG_LOG2E + ", {z}",
+                        "v_exp_f32_e32 {ta}, {ta}")
     out += nop_if_single(R)
-    out += seq(R, "v_add_f32_e32 {tb}, 1.0, {ta}", "v_rcp_f32_e32 {y}, {tb}")
-    out += nop_if_single(R)
-    return out, "y"
+    out += seq(R, "v_add_f32_e32 {tb}, 1.0, {ta}", "v_rcp_f32_e32 {ta}, {tb}") + [TRANS_GAP]
+    return out, "ta"
 
 
 def act_relu(R):
     # maximum(z, 0), NaN-propagating
-    return seq(R, "v_maximum3_f32 {y}, {z}, 0, 0"), "y"
+    return z_of(R) + seq(R, "v_maximum3_f32 {ta}, {z}, 0, 0"), "ta"
 
 
 def act_gauss(R):
     # 2^(-log2(e) z z)
-    out = seq(R, "v_mul_f32_e32 {ta}, {z}, {z}", "v_mul_f32_e32 {ta}, " + NEG_LOG2E + ", {ta}",
-              "v_exp_f32_e32 {y}, {ta}")
-    out += nop_if_single(R)
-    return out, "y"
+    out = z_of(R) + seq(R, "v_mul_f32_e32 {ta}, {z}, {z}",
+                        "v_mul_f32_e32 {ta}, " + NEG_LOG2E + ", {ta}",
+                        "v_exp_f32_e32 {tb}, {ta}") + [TRANS_GAP]
+    return out, "tb"
 
 
 def act_abs(R):
     # maximum(z, -z), NaN-propagating
-    return seq(R, "v_maximum3_f32 {y}, {z}, -{z}, -{z}"), "y"
+    return z_of(R) + seq(R, "v_maximum3_f32 {ta}, {z}, -{z}, -{z}"), "ta"
 
 
 def act_sin(R):
-    s1, s2, s3, s4 = SIN_C
-    c1, c2, c3, c4, c5 = COS_C
-    return seq(
+    # k = rint(z / pi) in tb, r = z - k pi in acc, then k -> int; r^2 in z;
+    # p = -1/3! + r^2 (1/5! + ... + r^2 / 13!); sin r = r + (r r^2) p;
+    # sin z = sin r with the sign flipped for odd k: adding k << 31 to the
+    # bit pattern toggles its sign bit
+    c13, c11, c9, c7, c5, c3 = SIN_C
+    out = z_of(R) + seq(
         R,
-        "v_mul_f32_e32 {k}, " + TWO_OVER_PI + ", {z}",
-        "v_rndne_f32_e32 {k}, {k}",
-        "v_fmamk_f32 {r}, {k}, " + NEG_PIO2_HI + ", {z}",
-        "v_fmac_f32_e32 {r}, " + PIO2_LO + ", {k}",
-        "v_cvt_i32_f32_e32 {q}, {k}",
-        "v_mul_f32_e32 {r2}, {r}, {r}",
-        # sin r = r + r^3 (s4 + r^2 (s3 + r^2 (s2 + r^2 s1)))
-        "v_mov_b32_e32 {p}, " + s1,
-        "v_fmaak_f32 {p}, {r2}, {p}, " + s2,
-        "v_fmaak_f32 {p}, {r2}, {p}, " + s3,
-        "v_fmaak_f32 {p}, {r2}, {p}, " + s4,
-        "v_mul_f32_e32 {w}, {r}, {r2}",
-        "v_fmac_f32_e32 {r}, {w}, {p}",
-        # cos r = 1 + r^2 (c5 + r^2 (c4 + r^2 (c3 + r^2 (c2 + r^2 c1))))
-        "v_mov_b32_e32 {p}, " + c1,
-        "v_fmaak_f32 {p}, {r2}, {p}, " + c2,
-        "v_fmaak_f32 {p}, {r2}, {p}, " + c3,
-        "v_fmaak_f32 {p}, {r2}, {p}, " + c4,
-        "v_fmaak_f32 {p}, {r2}, {p}, " + c5,
-        "v_fma_f32 {p}, {r2}, {p}, 1.0",
-        # odd quadrant: cos; quadrants 2 and 3: negate (bit 1 of k -> sign)
-        "v_and_b32_e32 {w}, 1, {q}",
-        "v_sub_u32_e32 {w}, 0, {w}",
-        "v_bfi_b32 {y}, {w}, {p}, {r}",
-        "v_lshlrev_b32_e32 {w}, 30, {q}",
-        "v_and_b32_e32 {w}, 0x80000000, {w}",
-        "v_xor_b32_e32 {y}, {y}, {w}"), "y"
+        "v_mul_f32_e32 {tb}, " + ONE_OVER_PI + ", {z}",
+        "v_rndne_f32_e32 {tb}, {tb}",
+        "v_fmamk_f32 {acc}, {tb}, " + NEG_PI_HI + ", {z}",
+        "v_fmac_f32_e32 {acc}, " + PI_HI_MINUS_PI + ", {tb}",
+        "v_cvt_i32_f32_e32 {tb}, {tb}",
+        "v_mul_f32_e32 {z}, {acc}, {acc}",
+        "v_fmaak_f32 {p}, {z}, " + R.c13 + ", " + c11,
+        "v_fmaak_f32 {p}, {z}, {p}, " + c9,
+        "v_fmaak_f32 {p}, {z}, {p}, " + c7,
+        "v_fmaak_f32 {p}, {z}, {p}, " + c5,
+        "v_fmaak_f32 {p}, {z}, {p}, " + c3,
+        "v_mul_f32_e32 {ta}, {acc}, {z}",
+        "v_fmac_f32_e32 {acc}, {ta}, {p}",
+        "v_lshl_add_u32 {ta}, {tb}, 31, {acc}")
+    return out, "ta"
 
 
 # in the order of the activation codes: identity, tanh, sigmoid, relu, sin,
 # gaussian, abs
-ACTS = (act_identity, act_tanh, act_sigmoid, act_relu, None, act_gauss, act_abs)
+ACTS = (act_identity, act_tanh, act_sigmoid, act_relu, act_sin, act_gauss, act_abs)
 
 
 # --------------------------------------------------------------- node, loop
@@ -286,14 +307,38 @@ def encoded_bytes(line):
                                          a not in INLINE_CONSTS and not a.startswith("offset"))
                   for a in args)
     vop3 = op.endswith("_e64") or op in ("v_fma_f32", "v_maximum3_f32", "v_bfi_b32",
-                                         "v_lshl_add_u64", "v_cmp_gt_u32_e64")
+                                         "v_lshl_add_u64", "v_lshl_add_u32",
+                                         "v_cmp_gt_u32_e64")
     return 8 if (vop3 or literal or op in ("v_fmaak_f32", "v_fmamk_f32")) else 4
 
 
+def act_blocks(R, rec, other):
+    """The activation blocks of the copy of the node loop with record buffer
+    rec (code k at k times the alignment), each with the write of v[dst]
+    and the jump to the other copy's next node."""
+    CODE, RESP = rec[0], rec[2]
+    blocks = []
+    for fn in ACTS:
+        body, y = fn(R)
+        body = [l % {"resp": RESP} for l in body]
+        # v[dst] = y (GPR-index mode uses the low 8 bits of the code word:
+        # the destination slot); next node
+        body += ["s_set_gpr_idx_on %s, gpr_idx(DST)" % CODE]
+        body += per_sample(R, "v_mov_b32_e32 {val}, {%s}" % y)
+        body += ["s_set_gpr_idx_off",
+                 "s_branch Lnode_%s%%=" % other]
+        blocks.append(body)
+    return blocks
+
+
 def act_block_align(R):
-    """Byte alignment of the activation blocks (a power of two no smaller
-    than the largest block: sin with its tail)."""
-    return 256 if R.spl == 1 else 512
+    """Byte alignment of the activation blocks: the smallest power of two
+    (at least 64) that holds the largest block."""
+    size = max(sum(encoded_bytes(l) for l in b) for b in act_blocks(R, REC_A, "B"))
+    align = 64
+    while align < size:
+        align *= 2
+    return align
 
 
 def node(R, X, rec, pref, other, base):
@@ -323,7 +368,7 @@ def node(R, X, rec, pref, other, base):
     shift = align.bit_length() - 1
     blo, bhi = base
     out += ["Lagg_%s%%=:" % X]
-    out += seq(R, "v_mov_b32_e32 {z}, " + BIAS, "v_fmac_f32_e64 {z}, " + RESP + ", {acc}")
+    out += seq(R, "v_mov_b32_e32 {z}, " + BIAS)
     out += ["s_bfe_u32 s89, %s, %s" % (CODE, ACT_FIELD),
             "s_lshl_b32 s89, s89, %d" % shift,
             "s_add_u32 s88, %s, s89" % blo,
@@ -331,14 +376,7 @@ def node(R, X, rec, pref, other, base):
             "s_setpc_b64 s[88:89]",
             ".p2align %d" % shift,
             "Lact_%s%%=:" % X]
-    for k, fn in enumerate(ACTS):
-        body, yreg = fn(R) if fn is not None else act_sin(R)
-        # v[dst] = y; next node
-        body += ["s_and_b32 s89, %s, %s" % (CODE, DST_MASK),
-                 "s_set_gpr_idx_on s89, gpr_idx(DST)"]
-        body += per_sample(R, "v_mov_b32_e32 {val}, {%s}" % yreg)
-        body += ["s_set_gpr_idx_off",
-                 "s_branch Lnode_%s%%=" % other]
+    for k, body in enumerate(act_blocks(R, rec, other)):
         # the computed jump needs every block to fit its stride
         size = sum(encoded_bytes(l) for l in body)
         assert size <= align, "activation block %d needs %d > %d bytes" % (k, size, align)
@@ -356,6 +394,7 @@ def node_loop(R):
     out = ["s_mov_b64 s[80:81], %[rec]",
            "s_mov_b64 s[84:85], %[edg]",
            "s_mov_b32 s86, 0",
+           "v_mov_b32_e32 %s, %s" % (R.c13, SIN_C[0]),
            "s_load_dwordx16 s[40:55], s[80:81], 0x0",
            # addresses of the two copies' activation blocks
            "s_getpc_b64 s[92:93]",

@@ -188,6 +188,34 @@ def test_repeatable_bits():
         assert np.array_equal(u, v)
 
 
+@pytest.mark.parametrize("variant", [0, 1, 2, 3])
+@pytest.mark.parametrize("workload", ["control", "sine"])
+def test_repeatable_bits_full_size(workload, variant):
+    """Full-size populations (P=10000, B=1000), where thousands of waves
+    share every compute unit: repeated launches give the same bits.  The
+    sine workload makes every computed node a sine (the longest activation
+    block)."""
+    neat = _neat()
+    if workload == "control":
+        pop = synth.control()
+    else:
+        rng = np.random.default_rng(11)
+        pop = synth.make_population(rng, 10000, 50, 200, 17, 6, 27, synth._k_uniform(200),
+                                    (synth.ACT_SIN,), (synth.AGG_SUM,))
+        pop.inputs = rng.standard_normal((10000, 1000, 17), dtype=np.float32)
+    dev = torch.device("cuda:0")
+    tn, tc = torch.from_numpy(pop.nodes).to(dev), torch.from_numpy(pop.conns).to(dev)
+    tx = torch.from_numpy(pop.inputs).to(dev)
+    _, _, _, prog = neat.topo_sort(tn, tc, pop.I, pop.O, want_order=False)
+    d = neat.dims_of(tn, tc, pop.I, pop.O)
+    first = neat.forward(d, prog, tx, pop.inputs.shape[1], variant=variant).view(torch.int32)
+    for rep in range(3):
+        again = neat.forward(d, prog, tx, pop.inputs.shape[1], variant=variant)
+        differ = int((again.view(torch.int32) != first).sum())
+        print(workload, "variant", variant, "repeat", rep, "differing words", differ)
+        assert differ == 0
+
+
 def test_edge_cases():
     neat = _neat()
     dev = torch.device("cuda:0")
