@@ -199,9 +199,10 @@ __device__ __forceinline__ void run_program(cprog_t *prog, int N, int O, int I, 
     cprog_t *e = prog + edge_off(N, O);
     i32x16 r = *(cint16_t *)rec;
     for (int k = 0; k < ncomp; ++k) {
-        const unsigned code = (unsigned)r[REC_CODE];
-        const int pairs = r[REC_NPAIRS];
-        const int acls = (int)((code >> 14) & 3u), act = (int)((code >> 16) & 7u);
+        const unsigned code = (unsigned)r[REC_CODE], np = (unsigned)r[REC_NPAIRS];
+        const int pairs = (int)(np & (unsigned)REC_NPAIRS_MASK);
+        const int acls = slot_class((int)(np >> REC_FIELD_SHIFT));
+        const int act = (int)(code >> REC_FIELD_SHIFT);
         const int dst = (int)(code & (unsigned)REC_DST_MASK);
         const float bias = fbits(r[REC_BIAS]), resp = fbits(r[REC_RESP]);
         // next record (the record array has room for N records)

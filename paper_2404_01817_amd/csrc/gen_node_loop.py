@@ -44,10 +44,20 @@ REC_A = tuple("s%d" % i for i in range(40, 56))
 REC_B = tuple("s%d" % i for i in range(56, 72))
 SGPR_CLOBBERS = ["s%d" % i for i in range(40, 96)]
 INLINE_PAIRS = 3
-# code word fields (program.h)
-DST_MASK = "0x7ff"
-ACLS_PROD_BIT, ACLS_MAX_BIT = 14, 15
-ACT_FIELD = "0x30010"  # s_bfe_u32 operand: 3 bits at bit 16
+# Record fields (program.h): the code word holds the destination slot in
+# its low bits and the activation's table slot at bit 24; the pair-count
+# word holds the pair count in its low 14 bits and the aggregation entry's
+# table slot at bit 24.  Table (per copy of the node loop, one stride per
+# slot): activation blocks 0..6, the end of the loop at 7, then the
+# aggregation entries, one per (class, pairs): sum with 0..3 pairs and with
+# overflow, product and max with 1..3 pairs and with overflow.
+FIELD_SHIFT = 24
+NP_MASK = "0x3fff"
+TAB_END = 7
+AGG_ENTRIES = [("sum", 0), ("sum", 1), ("sum", 2), ("sum", 3), ("sum", "ov"),
+               ("prod", 1), ("prod", 2), ("prod", 3), ("prod", "ov"),
+               ("max", 1), ("max", 2), ("max", 3), ("max", "ov")]
+TAB_AGG0 = 8
 NEG_LOG2E = "0xbfb8aa3b"    # -log2(e)
 TWO_LOG2E = "0x4038aa3b"    # 2 log2(e)
 
@@ -165,31 +175,30 @@ def pair(R, cls, first, s0, w0, s1, w1):
             + seq(R, comb))
 
 
-def aggregate(R, X, cls, rec):
-    """One aggregation class over the node's pairs (rec[3] of them, >= 1 unless
-    the class is sum): the record's three inline pairs, then the overflow
-    array in chunks of two pairs (the first chunk was requested at the
-    start of the node).  Leaves agg in acc and jumps to Lagg."""
+def inline_pairs(R, cls, rec, k):
+    """The first k (<= 3) of the node's pairs, from its record."""
     p = rec[4:16]
-    NP = rec[3]
-    done = "Lagg_%s%%=" % X
-    K = cls[0]
     out = []
-    if cls == "sum":
-        out += ["s_cmp_eq_u32 %s, 0" % NP, "s_cbranch_scc1 Lzero_%s%%=" % X]
-    for k in range(INLINE_PAIRS):
-        out += pair(R, cls, k == 0, *p[4 * k:4 * k + 4])
-        if k < INLINE_PAIRS - 1:
-            out += ["s_cmp_eq_u32 %s, %d" % (NP, k + 1), "s_cbranch_scc1 " + done]
-    out += ["s_cmp_le_u32 %s, %d" % (NP, INLINE_PAIRS), "s_cbranch_scc1 " + done,
-            # overflow pairs: s87 left, read from s[82:83]; s[84:85] moves past them
-            "s_sub_u32 s87, %s, %d" % (NP, INLINE_PAIRS),
-            "s_mov_b64 s[82:83], s[84:85]",
-            "s_lshl_b32 s89, s87, 4",
-            "s_add_u32 s84, s84, s89",
-            "s_addc_u32 s85, s85, 0",
-            "Lo%s_%s%%=:" % (K, X),
-            "s_waitcnt lgkmcnt(0)"]
+    for j in range(k):
+        out += pair(R, cls, j == 0, *p[4 * j:4 * j + 4])
+    return out
+
+
+def overflow_loop(R, X, cls, rec):
+    """Pairs after the third: s87 = pairs - 3 of them from the overflow
+    array, two at a time (the first two were requested at the entry), then
+    s[84:85] moves past them.  Ends where the aggregate is complete."""
+    NP = rec[3]
+    K = cls[0]
+    done = "Lovd%s_%s%%=" % (K, X)
+    out = ["s_and_b32 s87, %s, %s" % (NP, NP_MASK),
+           "s_sub_u32 s87, s87, %d" % INLINE_PAIRS,
+           "s_mov_b64 s[82:83], s[84:85]",
+           "s_lshl_b32 s89, s87, 4",
+           "s_add_u32 s84, s84, s89",
+           "s_addc_u32 s85, s85, 0",
+           "Lo%s_%s%%=:" % (K, X),
+           "s_waitcnt lgkmcnt(0)"]
     out += pair(R, cls, False, "s72", "s73", "s74", "s75")
     out += ["s_cmp_eq_u32 s87, 1", "s_cbranch_scc1 " + done]
     out += pair(R, cls, False, "s76", "s77", "s78", "s79")
@@ -199,8 +208,41 @@ def aggregate(R, X, cls, rec):
             "s_add_u32 s82, s82, 32",
             "s_addc_u32 s83, s83, 0",
             "s_load_dwordx8 s[72:79], s[82:83], 0x0",
-            "s_branch Lo%s_%s%%=" % (K, X)]
+            "s_branch Lo%s_%s%%=" % (K, X),
+            done + ":"]
     return out
+
+
+def jump(word, base, shift):
+    """Computed jump to the table slot held at bit 24 of word."""
+    lo, hi = base
+    return ["s_lshr_b32 s88, %s, %d" % (word, shift),
+            "s_add_u32 s88, s88, %s" % lo,
+            "s_addc_u32 s89, %s, 0" % hi,
+            "s_setpc_b64 s[88:89]"]
+
+
+def to_activation(R, rec, base, shift):
+    """z = bias (the activation block finishes z), then the jump to the
+    node's activation block."""
+    return seq(R, "v_mov_b32_e32 {z}, " + rec[1]) + jump(rec[0], base, shift)
+
+
+def agg_entry(R, X, cls, k, rec, pref, base, shift):
+    """Table entry for a node of class cls with k pairs (or "ov": three in
+    the record, the rest in the overflow array): request the record after
+    the next one into pref, aggregate, and jump to the activation."""
+    out = ["s_add_u32 s86, s86, 64",
+           "s_load_dwordx16 %s, s[80:81], s86" % pref]
+    if k == "ov":
+        out += ["s_load_dwordx8 s[72:79], s[84:85], 0x0"]
+        out += inline_pairs(R, cls, rec, INLINE_PAIRS)
+        out += ["s_branch Lov%s_%s%%=" % (cls[0], X)]
+        return out
+    if k == 0:
+        out += seq(R, "v_mov_b32_e32 {acc}, 0")
+    out += inline_pairs(R, cls, rec, k)
+    return out + to_activation(R, rec, base, shift)
 
 
 # --------------------------------------------------------------- activation
@@ -312,99 +354,90 @@ def encoded_bytes(line):
     return 8 if (vop3 or literal or op in ("v_fmaak_f32", "v_fmamk_f32")) else 4
 
 
-def act_blocks(R, rec, other):
+def act_blocks(R, rec, orec, obase, shift):
     """The activation blocks of the copy of the node loop with record buffer
-    rec (code k at k times the alignment), each with the write of v[dst]
-    and the jump to the other copy's next node."""
+    rec, each with the write of v[dst] and the jump into the next node's
+    aggregation entry (record orec, the other copy's table at obase)."""
     CODE, RESP = rec[0], rec[2]
     blocks = []
     for fn in ACTS:
         body, y = fn(R)
         body = [l % {"resp": RESP} for l in body]
         # v[dst] = y (GPR-index mode uses the low 8 bits of the code word:
-        # the destination slot); next node
+        # the destination slot); next node, once its record is in
         body += ["s_set_gpr_idx_on %s, gpr_idx(DST)" % CODE]
         body += per_sample(R, "v_mov_b32_e32 {val}, {%s}" % y)
-        body += ["s_set_gpr_idx_off",
-                 "s_branch Lnode_%s%%=" % other]
+        body += ["s_set_gpr_idx_off", "s_waitcnt lgkmcnt(0)"]
+        body += jump(orec[3], obase, shift)
         blocks.append(body)
     return blocks
 
 
-def act_block_align(R):
-    """Byte alignment of the activation blocks: the smallest power of two
-    (at least 64) that holds the largest block."""
-    size = max(sum(encoded_bytes(l) for l in b) for b in act_blocks(R, REC_A, "B"))
-    align = 64
-    while align < size:
-        align *= 2
-    return align
+def table(R, X, rec, pref, base, orec, obase, shift):
+    """The slots of one copy's table, in order."""
+    slots = act_blocks(R, rec, orec, obase, shift)
+    slots.append(["s_branch Ldone%="])
+    for cls, k in AGG_ENTRIES:
+        slots.append(agg_entry(R, X, cls, k, rec, pref, base, shift))
+    return slots
 
 
-def node(R, X, rec, pref, other, base):
-    """One node with record buffer rec (the next record is loaded into
-    pref); base: SGPR pair holding the address of this copy's activation
-    blocks; other: the tag of the copy that runs the next node."""
-    CODE, BIAS, RESP, NP = rec[:4]
-    out = ["Lnode_%s%%=:" % X,
-           "s_waitcnt lgkmcnt(0)",
-           "s_add_u32 s86, s86, 64",
-           "s_load_dwordx16 %s, s[80:81], s86" % pref,
-           # request the first overflow chunk now when there is one
-           "s_cmp_le_u32 %s, %d" % (NP, INLINE_PAIRS),
-           "s_cbranch_scc1 Lnov_%s%%=" % X,
-           "s_load_dwordx8 s[72:79], s[84:85], 0x0",
-           "Lnov_%s%%=:" % X,
-           "s_bitcmp1_b32 %s, %d" % (CODE, ACLS_PROD_BIT),
-           "s_cbranch_scc1 Lprod_%s%%=" % X,
-           "s_bitcmp1_b32 %s, %d" % (CODE, ACLS_MAX_BIT),
-           "s_cbranch_scc1 Lmax_%s%%=" % X]
-    out += aggregate(R, X, "sum", rec)
-    out += ["Lzero_%s%%=:" % X] + seq(R, "v_mov_b32_e32 {acc}, 0") + ["s_branch Lagg_%s%%=" % X]
-    out += ["Lprod_%s%%=:" % X] + aggregate(R, X, "prod", rec)
-    out += ["Lmax_%s%%=:" % X] + aggregate(R, X, "max", rec)
-    # z = bias + response' * agg, then jump to the activation's block
-    align = act_block_align(R)
-    shift = align.bit_length() - 1
-    blo, bhi = base
-    out += ["Lagg_%s%%=:" % X]
-    out += seq(R, "v_mov_b32_e32 {z}, " + BIAS)
-    out += ["s_bfe_u32 s89, %s, %s" % (CODE, ACT_FIELD),
-            "s_lshl_b32 s89, s89, %d" % shift,
-            "s_add_u32 s88, %s, s89" % blo,
-            "s_addc_u32 s89, %s, 0" % bhi,
-            "s_setpc_b64 s[88:89]",
-            ".p2align %d" % shift,
-            "Lact_%s%%=:" % X]
-    for k, body in enumerate(act_blocks(R, rec, other)):
-        # the computed jump needs every block to fit its stride
+def table_stride(R):
+    """Bytes per table slot: the smallest power of two (at least 64) that
+    holds the largest slot."""
+    size = max(sum(encoded_bytes(l) for l in b)
+               for b in table(R, "A", REC_A, "s[56:71]", ("s92", "s93"), REC_B,
+                              ("s94", "s95"), 16))
+    stride = 64
+    while stride < size:
+        stride *= 2
+    return stride
+
+
+def copy(R, X, rec, pref, base, orec, obase):
+    """One copy of the node loop: its table, then the overflow tails of its
+    three aggregation classes (each ends with the jump to the activation)."""
+    stride = table_stride(R)
+    shift = FIELD_SHIFT - (stride.bit_length() - 1)
+    align = stride.bit_length() - 1
+    out = [".p2align %d" % align, "Ltab_%s%%=:" % X]
+    for k, body in enumerate(table(R, X, rec, pref, base, orec, obase, shift)):
         size = sum(encoded_bytes(l) for l in body)
-        assert size <= align, "activation block %d needs %d > %d bytes" % (k, size, align)
+        assert size <= stride, "table slot %d needs %d > %d bytes" % (k, size, stride)
         if k:
-            out += [".p2align %d" % shift]
-        out += ["Lact%d_%s%%=:" % (k, X)] + body
-    # code ACT_END: the sentinel record after the last node
-    out += [".p2align %d" % shift, "Lact7_%s%%=:" % X, "s_branch Ldone%="]
+            out += [".p2align %d" % align]
+        out += body
+    for cls in ("sum", "prod", "max"):
+        out += ["Lov%s_%s%%=:" % (cls[0], X)] + overflow_loop(R, X, cls, rec)
+        out += to_activation(R, rec, base, shift)
     return out
 
 
 def node_loop(R):
-    """All computed nodes: %[rec] record 0 (the records end with a sentinel),
-    %[edg] overflow edges.  M0 is saved in s90 by the caller."""
+    """All computed nodes: %[rec] record 0 (the records end with a sentinel
+    whose entry is the end of the loop), %[edg] overflow edges.  Copy A runs
+    the nodes at even positions (record buffer s40..s55), copy B the odd
+    ones (s56..s71); each node's entry requests the next node's record into
+    the other buffer, and its activation block waits for it and jumps into
+    that node's entry.  M0 is saved in s90 by the caller."""
+    stride = table_stride(R)
+    shift = FIELD_SHIFT - (stride.bit_length() - 1)
     out = ["s_mov_b64 s[80:81], %[rec]",
            "s_mov_b64 s[84:85], %[edg]",
            "s_mov_b32 s86, 0",
            "v_mov_b32_e32 %s, %s" % (R.c13, SIN_C[0]),
            "s_load_dwordx16 s[40:55], s[80:81], 0x0",
-           # addresses of the two copies' activation blocks
+           # addresses of the two copies' tables
            "s_getpc_b64 s[92:93]",
            "Lpc%=:",
-           "s_add_u32 s94, s92, Lact_B%= - Lpc%=",
+           "s_add_u32 s94, s92, Ltab_B%= - Lpc%=",
            "s_addc_u32 s95, s93, 0",
-           "s_add_u32 s92, s92, Lact_A%= - Lpc%=",
-           "s_addc_u32 s93, s93, 0"]
-    out += node(R, "A", REC_A, "s[56:71]", "B", ("s92", "s93"))
-    out += node(R, "B", REC_B, "s[40:55]", "A", ("s94", "s95"))
+           "s_add_u32 s92, s92, Ltab_A%= - Lpc%=",
+           "s_addc_u32 s93, s93, 0",
+           "s_waitcnt lgkmcnt(0)"]
+    out += jump(REC_A[3], ("s92", "s93"), shift)
+    out += copy(R, "A", REC_A, "s[56:71]", ("s92", "s93"), REC_B, ("s94", "s95"))
+    out += copy(R, "B", REC_B, "s[40:55]", ("s94", "s95"), REC_A, ("s92", "s93"))
     out += ["Ldone%=:",
             "s_waitcnt lgkmcnt(0)"]
     return out

@@ -69,12 +69,16 @@ __host__ __device__ constexpr int class_slots(int cls, int N) {
 __host__ __device__ constexpr int zero_slot(int cls, int N) { return class_slots(cls, N) - 2; }
 
 // node record (16 words), record k describes position I + k:
-//   code: dst slot | aggregation class << 14 | activation << 16 (the
-//   register kernels index with the low 8 bits of the code word, and every
-//   register slot is below 256);
-//   bias, response', pair count, then the node's first three edge pairs.
-// After the last node a sentinel record (activation code ACT_END, no
-// pairs) ends the kernels' node loop.
+//   code: dst slot | activation << 24 (the register kernels index with
+//   the low 8 bits of the code word, and every register slot is below 256);
+//   bias, response', pairs: pair count | aggregation entry << 24, then the
+//   node's first three edge pairs.
+// The register kernels jump on the fields at bit 24: each copy of their
+// node loop has a table with one slot per activation code (0..6), the end
+// of the loop (TAB_END) and one aggregation entry per (class, pair count):
+// sum with 0..3 pairs or more (overflow), product and max with 1..3 pairs
+// or more.  After the last node a sentinel record (code ACT_END, entry
+// TAB_END, no pairs) ends the loop.
 // Aggregation classes: SUM (sum, mean, and any node without incoming
 // edges), PROD, MAX (max; min is stored as max over negated weights with
 // the response negated, since min(t) = -max(-t) exactly);
@@ -84,16 +88,34 @@ __host__ __device__ constexpr int zero_slot(int cls, int N) { return class_slots
 constexpr int REC_CODE = 0;
 constexpr int REC_BIAS = 1;   // float
 constexpr int REC_RESP = 2;   // float, response'
-constexpr int REC_NPAIRS = 3; // edge pairs (after padding to an even count)
+constexpr int REC_NPAIRS = 3; // pair count (after padding to an even count) | entry << 24
 constexpr int REC_PAIRS = 4;  // the node's first three edge pairs (12 words)
 constexpr int REC_WORDS = 16;
 constexpr int REC_INLINE_PAIRS = 3;
 constexpr int REC_DST_MASK = 0x7ff;
+constexpr int REC_FIELD_SHIFT = 24;
+constexpr int REC_NPAIRS_MASK = 0x3fff;
 constexpr int ACT_END = 7;    // sentinel activation code
 enum AggClass { ACLS_SUM = 0, ACLS_PROD = 1, ACLS_MAX = 2 };
-__host__ __device__ constexpr uint32_t rec_code(int acls, int act, int dst) {
-    return (uint32_t)dst | ((uint32_t)acls << 14) | ((uint32_t)act << 16);
+// table slots
+constexpr int TAB_END = 7;
+constexpr int TAB_AGG0 = 8;   // first aggregation entry: sum with 0 pairs
+constexpr int TAB_SLOTS = TAB_AGG0 + 13;
+__host__ __device__ constexpr int agg_slot(int acls, int pairs) {
+    return TAB_AGG0 + (acls == ACLS_SUM ? (pairs < 4 ? pairs : 4)
+                                        : 4 * acls + (pairs < 4 ? pairs : 4));
 }
+__host__ __device__ constexpr int slot_class(int slot) {
+    return slot < TAB_AGG0 + 5 ? ACLS_SUM : (slot < TAB_AGG0 + 9 ? ACLS_PROD : ACLS_MAX);
+}
+__host__ __device__ constexpr uint32_t rec_code(int act, int dst) {
+    return (uint32_t)dst | ((uint32_t)act << REC_FIELD_SHIFT);
+}
+__host__ __device__ constexpr uint32_t rec_npairs(int acls, int pairs) {
+    return (uint32_t)pairs | ((uint32_t)agg_slot(acls, pairs) << REC_FIELD_SHIFT);
+}
+constexpr uint32_t REC_SENTINEL_CODE = (uint32_t)ACT_END << REC_FIELD_SHIFT;
+constexpr uint32_t REC_SENTINEL_NPAIRS = (uint32_t)TAB_END << REC_FIELD_SHIFT;
 // edge (2 words): source slot, weight
 constexpr int EDGE_WORDS = 2;
 

@@ -494,7 +494,9 @@ __device__ __forceinline__ void topo_genome(const TopoItem &a, size_t g) {
         // N records and at most N - I of them are nodes)
         if (t < REC_WORDS) {
             const int rs = rec_off(O) + REC_WORDS * (nvalid - I) + t;
-            prog[rs] = t == REC_CODE ? (int32_t)rec_code(ACLS_SUM, ACT_END, 0) : 0;
+            prog[rs] = t == REC_CODE     ? (int32_t)REC_SENTINEL_CODE
+                       : t == REC_NPAIRS ? (int32_t)REC_SENTINEL_NPAIRS
+                                         : 0;
         }
     }
     __syncthreads();
@@ -512,10 +514,10 @@ __device__ __forceinline__ void topo_genome(const TopoItem &a, size_t g) {
         const float rp = deg == 0 ? resp
                                   : (agg == AGG_MEAN ? resp * (1.0f / (float)deg)
                                                      : (agg == AGG_MIN ? -resp : resp));
-        prog[r0 + REC_CODE] = (int32_t)rec_code(acls, act, s_slot[t]);
+        prog[r0 + REC_CODE] = (int32_t)rec_code(act, s_slot[t]);
         progf[r0 + REC_BIAS] = bias;
         progf[r0 + REC_RESP] = rp;
-        prog[r0 + REC_NPAIRS] = pairs;
+        prog[r0 + REC_NPAIRS] = (int32_t)rec_npairs(acls, pairs);
         // unused inline edges: a harmless (constant slot, 0) pair
         for (int j = 2 * pairs; j < 2 * REC_INLINE_PAIRS; ++j) {
             prog[r0 + REC_PAIRS + 2 * j] = zs;
