@@ -366,6 +366,22 @@ def main():
         except neat.NeatError:
             variants[name] = None
 
+    # what a plain device copy (torch) reaches on this GPU, for context: a
+    # 2 GiB copy (4 GiB moved), well past the on-package cache
+    src = torch.ones((512 << 20,), dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    c0.record(stream)
+    for _ in range(5):
+        dst.copy_(src)
+    c1.record(stream)
+    torch.cuda.synchronize()
+    copy_gbs = 2 * src.numel() * 4 / (c0.elapsed_time(c1) / 5 / 1e3) / 1e9
+    del src, dst
+    roofline["copy_GBps"] = round(copy_gbs, 1)
+    roofline["frac_of_copy"] = round(achieved / copy_gbs, 4)
+
     if args.copy_probe:
         src = torch.ones((64 << 20,), dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
