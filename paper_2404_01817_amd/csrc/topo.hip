@@ -40,17 +40,38 @@ __device__ __forceinline__ bool is_int_in(float x, float lo, float hi_excl) {
     return x >= lo && x < hi_excl && x == floorf(x);
 }
 
+// Key -> row table: open addressing with linear probing in H = hash_size(N)
+// slots (a power of two, at least twice the rows, so probes end at an empty
+// slot).  Every well-formed key is inserted with the smallest row holding it.
+constexpr int HASH_EMPTY = -1;
+__host__ __device__ constexpr int hash_size(int N) {
+    int h = 64;
+    while (h < 2 * N) h *= 2;
+    return h;
+}
+__device__ __forceinline__ int hash_slot(int key, int H) {
+    return (int)(((unsigned)key * 2654435761u) >> 8) & (H - 1);
+}
+__device__ __forceinline__ void hash_insert(int *hkey, int *hrow, int H, int key, int row) {
+    int h = hash_slot(key, H);
+    for (;;) {
+        const int old = atomicCAS(&hkey[h], HASH_EMPTY, key);
+        if (old == HASH_EMPTY || old == key) {
+            atomicMin(&hrow[h], row);
+            return;
+        }
+        h = (h + 1) & (H - 1);
+    }
+}
 // Row of the well-formed key equal to k (first row among duplicates), or -1.
-__device__ __forceinline__ int find_row(float k, const int *skey, const int *srow, int n) {
+__device__ __forceinline__ int find_row(float k, const int *hkey, const int *hrow, int H) {
     if (!is_int_in(k, 0.0f, KEY_LIMIT)) return -1;
     const int key = (int)k;
-    int lo = 0, hi = n;
-    while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (skey[mid] < key) lo = mid + 1;
-        else hi = mid;
+    for (int h = hash_slot(key, H);; h = (h + 1) & (H - 1)) {
+        const int kk = hkey[h];
+        if (kk == key) return hrow[h];
+        if (kk == HASH_EMPTY) return -1;
     }
-    return (lo < n && skey[lo] == key) ? srow[lo] : -1;
 }
 
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63u); }
@@ -108,7 +129,7 @@ __device__ int block_incl_min(int v, int *s_wave) {
 __device__ __forceinline__ void topo_genome(const TopoItem &a, size_t g) {
     extern __shared__ int smem[];
     __shared__ unsigned s_status;
-    __shared__ int s_nvalid, s_ngood;
+    __shared__ int s_nvalid;
     __shared__ int s_wave[16];
 
     const int N = a.N, C = a.C, I = a.I, O = a.O;
@@ -131,20 +152,40 @@ __device__ __forceinline__ void topo_genome(const TopoItem &a, size_t g) {
     int *s_slot = out_list + C;   // [N] value slot of row
     int *s_stack = s_slot + N;    // [N] slot allocation scratch
     int *s_oval = s_stack + N;    // [N] slot allocation scratch
+    const int H = hash_size(N);
+    int *h_key = s_oval + N;      // [H] key -> row table: keys
+    int *h_row = h_key + H;       // [H] rows
 
     const float *nodes = a.nodes + g * (size_t)N * 5;
     const float *conns = a.conns + g * (size_t)C * 4;
+    const float4 *conns4 = reinterpret_cast<const float4 *>(conns);
+
+    // the first connection rows of this thread and its node row, requested
+    // together before anything waits on memory
+    constexpr int CPRE = 4;
+    float4 cpre[CPRE];
+#pragma unroll
+    for (int k = 0; k < CPRE; ++k)
+        if (t + k * W < C) cpre[k] = conns4[t + k * W];
+    float nrow[5];
+    if (t < N) {
+#pragma unroll
+        for (int k = 0; k < 5; ++k) nrow[k] = nodes[(size_t)t * 5 + k];
+    }
 
     if (t == 0) {
         s_status = 0u;
         s_nvalid = 0;
-        s_ngood = 0;
     }
     for (int i = t; i < N; i += W) {
         s_indeg[i] = 0;
         s_curo[i] = 0;
         s_curi[i] = 0;
         s_pos[i] = -1;
+    }
+    for (int i = t; i < H; i += W) {
+        h_key[i] = HASH_EMPTY;
+        h_row[i] = 0x7fffffff;
     }
     __syncthreads();
 
@@ -153,11 +194,10 @@ __device__ __forceinline__ void topo_genome(const TopoItem &a, size_t g) {
     int key = -1, act = 0, agg = 0;
     float bias = 0.0f, resp = 0.0f;
     if (t < N) {
-        const float *n = nodes + (size_t)t * 5;
-        const float kf = n[0];
-        bias = n[1];
-        resp = n[2];
-        const float af = n[3], gf = n[4];
+        const float kf = nrow[0];
+        bias = nrow[1];
+        resp = nrow[2];
+        const float af = nrow[3], gf = nrow[4];
         if (!isnan(kf)) {
             atomicAdd(&s_nvalid, 1);
             const bool key_ok = is_int_in(kf, 0.0f, KEY_LIMIT);
@@ -169,6 +209,7 @@ __device__ __forceinline__ void topo_genome(const TopoItem &a, size_t g) {
                 agg = (int)gf;
             }
             key = key_ok ? (int)kf : -2;
+            if (key_ok) hash_insert(h_key, h_row, H, key, t);
         }
         s_key[t] = key;
     }
@@ -191,22 +232,19 @@ __device__ __forceinline__ void topo_genome(const TopoItem &a, size_t g) {
         s_skey[rank] = key;
         s_srow[rank] = t;
         if (key < I + O) s_curi[key] = 1;
-        atomicAdd(&s_ngood, 1);
     }
     __syncthreads();
     if (t < I + O && s_curi[t] == 0) st |= NEAT_ST_MISSING_IO;
-    const int ngood = s_ngood;
 
-    // ---- 3. connection rows
-    for (int c = t; c < C; c += W) {
-        const float4 row = reinterpret_cast<const float4 *>(conns)[c];
+    // ---- 3. connection rows (the prefetched ones first)
+    auto connection = [&](int c, const float4 row) {
         int src = -1, dst = -1;
         if (!isnan(row.x) && row.z != 0.0f) {
             if (row.z != 1.0f) {
                 st |= NEAT_ST_BAD_VALUE;
             } else {
-                const int s = find_row(row.x, s_skey, s_srow, ngood);
-                const int d = find_row(row.y, s_skey, s_srow, ngood);
+                const int s = find_row(row.x, h_key, h_row, H);
+                const int d = find_row(row.y, h_key, h_row, H);
                 if (s < 0 || d < 0) {
                     st |= NEAT_ST_BAD_REF;
                 } else {
@@ -221,7 +259,11 @@ __device__ __forceinline__ void topo_genome(const TopoItem &a, size_t g) {
         }
         e_src[c] = src;
         e_dst[c] = dst;
-    }
+    };
+#pragma unroll
+    for (int k = 0; k < CPRE; ++k)
+        if (t + k * W < C) connection(t + k * W, cpre[k]);
+    for (int c = t + CPRE * W; c < C; c += W) connection(c, conns4[c]);
     __syncthreads();
 
     // ---- 4. adjacency lists (counting sort by destination and by source)
@@ -439,6 +481,11 @@ __device__ __forceinline__ void topo_genome(const TopoItem &a, size_t g) {
         }
     }
     __syncthreads();
+    // source key of every in-edge (the out lists are no longer needed), for
+    // the per-node scans below
+    int *in_key = out_list;
+    for (int k = t; k < s_inoff[N]; k += W) in_key[k] = s_key[e_src[in_list[k]]];
+    __syncthreads();
     const int used = s_used;
     const int cls = class_of(used);
     const int zs = zero_slot(cls, N);
@@ -461,10 +508,9 @@ __device__ __forceinline__ void topo_genome(const TopoItem &a, size_t g) {
     if (computed) {
         int kmin = 0x7fffffff;
         for (int k = s_inoff[t]; k < s_inoff[t + 1]; ++k) {
-            const int c2 = in_list[k];
-            const int ks = s_key[e_src[c2]];
+            const int ks = in_key[k];
             ++deg;
-            if (ks < kmin) kmin = ks, first = c2;
+            if (ks < kmin) kmin = ks, first = in_list[k];
         }
     }
     const int pairs = (deg + 1) >> 1;
@@ -555,7 +601,7 @@ __device__ __forceinline__ void topo_genome(const TopoItem &a, size_t g) {
         const int d = e_dst[c];
         const int ks = s_key[s];
         int j = 0;
-        for (int k = s_inoff[d]; k < s_inoff[d + 1]; ++k) j += (s_key[e_src[in_list[k]]] < ks);
+        for (int k = s_inoff[d]; k < s_inoff[d + 1]; ++k) j += (in_key[k] < ks);
         const int rd = rec_off(O) + REC_WORDS * (s_pos[d] - I);
         const int widx = j < 2 * REC_INLINE_PAIRS ? rd + REC_PAIRS + 2 * j
                                                    : eoff + EDGE_WORDS * (s_curo[d] + j - 2 * REC_INLINE_PAIRS);
@@ -638,7 +684,9 @@ __global__ __launch_bounds__(1024) void classify_batch_kernel(const TopoItem *it
 
 }  // namespace
 
-size_t topo_lds_bytes(int N, int C) { return sizeof(int) * ((size_t)13 * N + 2 + (size_t)4 * C); }
+size_t topo_lds_bytes(int N, int C) {
+    return sizeof(int) * ((size_t)13 * N + 2 + (size_t)4 * C + 2 * (size_t)hash_size(N));
+}
 
 int topo_block_threads(int N) {
     int w = round_up(N, 64);
