@@ -182,6 +182,7 @@ __device__ __forceinline__ void topo_genome(const TopoItem &a, size_t g) {
         s_curo[i] = 0;
         s_curi[i] = 0;
         s_pos[i] = -1;
+        s_skey[i] = -1;
     }
     for (int i = t; i < H; i += W) {
         h_key[i] = HASH_EMPTY;
@@ -212,28 +213,43 @@ __device__ __forceinline__ void topo_genome(const TopoItem &a, size_t g) {
             if (key_ok) hash_insert(h_key, h_row, H, key, t);
         }
         s_key[t] = key;
+        // (key, row) in one word when rows fit in 8 bits (keys are below 2^24)
+        if (N <= 256) s_stack[t] = key >= 0 ? (int)(((unsigned)key << 8) | (unsigned)t) : -1;
     }
     __syncthreads();
 
-    // ---- 2. stable key rank, duplicate keys, input/output presence
+    // ---- 2. stable key rank (by key, then row), duplicate keys,
+    // input/output presence
+    int rank = -1;
     if (key >= 0) {
-        int less = 0, eq_before = 0, eq = 0;
-        for (int q = 0; q < N; ++q) {
-            const int kq = s_key[q];
-            if (kq < 0) continue;
-            less += (kq < key);
-            if (kq == key && q != t) {
-                ++eq;
-                eq_before += (q < t);
+        if (N <= 256) {
+            // rank = number of (key, row) words below this row's (the words
+            // are distinct; absent and malformed rows hold the largest)
+            const unsigned mine = ((unsigned)key << 8) | (unsigned)t;
+            const unsigned *comp = reinterpret_cast<const unsigned *>(s_stack);
+            int less = 0;
+#pragma unroll 8
+            for (int q = 0; q < N; ++q) less += comp[q] < mine;
+            rank = less;
+        } else {
+            int less = 0, eq_before = 0;
+            for (int q = 0; q < N; ++q) {
+                const int kq = s_key[q];
+                if (kq < 0) continue;
+                less += (kq < key);
+                eq_before += (kq == key && q < t);
             }
+            rank = less + eq_before;
         }
-        const int rank = less + eq_before;
-        if (eq) st |= NEAT_ST_DUP_KEY;
         s_skey[rank] = key;
         s_srow[rank] = t;
         if (key < I + O) s_curi[key] = 1;
     }
     __syncthreads();
+    // equal keys hold neighbouring ranks (the other entries are -1)
+    if (rank >= 0 && ((rank > 0 && s_skey[rank - 1] == key) ||
+                      (rank + 1 < N && s_skey[rank + 1] == key)))
+        st |= NEAT_ST_DUP_KEY;
     if (t < I + O && s_curi[t] == 0) st |= NEAT_ST_MISSING_IO;
 
     // ---- 3. connection rows (the prefetched ones first)

@@ -156,6 +156,39 @@ def test_uneven_populations():
         _assert_outputs(y, y64, beta, "uneven N=%d" % pop.N_max)
 
 
+@pytest.mark.parametrize("N", [50, 300])
+def test_planted_defects_status_bit_exact(N):
+    """Duplicated keys, dangling references, edges into inputs and malformed
+    values planted in every third genome, for node counts on both sides of
+    the transformation's 256-row boundary: status, order and level match
+    the oracle bit for bit."""
+    rng = np.random.default_rng(N)
+    pop = synth.make_population(rng, 60, N, 4 * N, 6, 3, N - 9, synth._k_density(4 * N),
+                                synth.CONTROL_ACTS, synth.ALL_AGGS)
+    nodes, conns = pop.nodes.copy(), pop.conns.copy()
+    for g in range(0, 60, 3):
+        rows = np.nonzero(~np.isnan(nodes[g, :, 0]))[0]
+        kind = (g // 3) % 5
+        if kind == 0:    # a hidden (or output) key repeated on another row
+            nodes[g, rows[-1], 0] = nodes[g, rows[-2], 0]
+        elif kind == 1:  # an input key repeated
+            nodes[g, rows[-1], 0] = nodes[g, rows[0], 0]
+        elif kind == 2:  # an enabled connection to a missing key
+            c = np.nonzero(conns[g, :, 2] == 1.0)[0]
+            if len(c):
+                conns[g, c[0], 1] = 10 ** 6
+        elif kind == 3:  # an edge into an input
+            c = np.nonzero(~np.isnan(conns[g, :, 0]))[0]
+            if len(c):
+                conns[g, c[-1], 1] = 0.0
+                conns[g, c[-1], 2] = 1.0
+        else:            # a fractional key
+            nodes[g, rows[-1], 0] = 7.5
+    order, level, status, _ = _gpu(nodes, conns, pop.I, pop.O)
+    _assert_transform_exact(nodes, conns, pop.I, pop.O, order, level, status)
+    assert (status[0::3] != 0).all()
+
+
 def test_storage_invariants_bit_identical():
     """NaN padding rows, disabled junk rows and permuted storage give the
     same order (as keys) and bit-identical outputs on the GPU (N_max 50 -> 58
