@@ -609,11 +609,12 @@ __device__ __forceinline__ void topo_genome(const TopoItem &a, size_t g) {
     if (computed) s_agg[t] = agg;
     __syncthreads();
     // real edges: index j = number of in-edges of the destination with a
-    // smaller source key (keys are unique here); j < 4 in the record, the
-    // rest in the overflow array
-    for (int c = t; c < C; c += W) {
+    // smaller source key (keys are unique here); j < 6 in the record, the
+    // rest in the overflow array.  The thread that read a connection row
+    // writes its edge (weights of the prefetched rows are still in registers)
+    auto edge = [&](int c, float w) {
         const int s = e_src[c];
-        if (s < 0) continue;
+        if (s < 0) return;
         const int d = e_dst[c];
         const int ks = s_key[s];
         int j = 0;
@@ -622,10 +623,13 @@ __device__ __forceinline__ void topo_genome(const TopoItem &a, size_t g) {
         const int widx = j < 2 * REC_INLINE_PAIRS ? rd + REC_PAIRS + 2 * j
                                                    : eoff + EDGE_WORDS * (s_curo[d] + j - 2 * REC_INLINE_PAIRS);
         // min is stored as max over negated weights (negation is exact)
-        const float w = conns[(size_t)c * 4 + 3];
         prog[widx] = s_slot[s];
         progf[widx + 1] = s_agg[d] == AGG_MIN ? -w : w;
-    }
+    };
+#pragma unroll
+    for (int k = 0; k < CPRE; ++k)
+        if (t + k * W < C) edge(t + k * W, cpre[k].w);
+    for (int c = t + CPRE * W; c < C; c += W) edge(c, conns[(size_t)c * 4 + 3]);
 }
 
 __global__ __launch_bounds__(1024) void topo_kernel(TopoItem a) { topo_genome(a, blockIdx.x); }
