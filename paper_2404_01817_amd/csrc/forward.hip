@@ -257,6 +257,21 @@ __device__ __forceinline__ float grid_coord(int i, int side) {
     return (float)(2 * i - (side - 1)) / (float)(side - 1);
 }
 
+// Largest number of grid coordinates (side of the substrate grid).
+constexpr int GRID_MAX_SIDE = 256;
+
+// (p / d, p % d) for p < 2^24 and a uniform divisor d (< 2^16) with its
+// reciprocal rd: the float estimate is off by at most one either way.
+__device__ __forceinline__ void divmod_small(unsigned p, unsigned d, float rd, unsigned *q,
+                                             unsigned *r) {
+    int qq = (int)((float)p * rd);
+    int rr = (int)p - qq * (int)d;
+    if (rr >= (int)d) rr -= (int)d, ++qq;
+    if (rr < 0) rr += (int)d, --qq;
+    *q = (unsigned)qq;
+    *r = (unsigned)rr;
+}
+
 template <int H, class Store>
 __device__ __forceinline__ void place_grid(Store &v, long long q, int side) {
     const int pts = side * side;
@@ -341,6 +356,14 @@ __device__ __forceinline__ void forward_unit_reg(citem_t *it, int g, int chunk, 
     const float *in_g = GRID ? nullptr : it->inputs + (size_t)g * it->gstride;
     const int vec4 = it->vec4;
     if (!GRID) dma_inputs(in_g + (size_t)t0 * TS * I, istage, min(TS, B - t0 * TS) * I, vec4);
+    // grid queries: the side coordinates, once per unit, after the staging
+    float *ctab = istage + TS * I;
+    const unsigned pts = (unsigned)(side * side);
+    const float rside = GRID ? 1.0f / (float)side : 0.0f;
+    if (GRID) {
+        for (int i = (int)lane; i < side; i += WAVE) ctab[i] = grid_coord(i, side);
+        __builtin_amdgcn_wave_barrier();
+    }
     // the records and overflow edges the node loop will read, in one burst
     // (the first tile's wait covers it)
     touch_lines(rec, REC_WORDS * (ncomp + 1), ostage);
@@ -349,16 +372,28 @@ __device__ __forceinline__ void forward_unit_reg(citem_t *it, int g, int chunk, 
 
     for (int t = t0; t < t1; ++t) {
         if (GRID) {
-            // grid queries: the five inputs of each of the lane's samples
+            // grid queries: the five inputs of each of the lane's samples.
+            // Queries are below side^4 <= 2^32; the tile's first one is split
+            // into its two points once, each lane adds its offset (< 128)
+            const unsigned q0 = (unsigned)(it->first + (long long)t * TS);
+            const unsigned p1_0 = q0 / pts, p2_0 = q0 - p1_0 * pts;
             for (int h = 0; h < SPL; ++h) {
-                const long long q = it->first + (long long)t * TS + h * WAVE + lane;
-                const int pts = side * side;
-                const int p1 = (int)(q / pts), p2 = (int)(q - (long long)p1 * pts);
+                unsigned p1 = p1_0, p2 = p2_0 + (unsigned)(h * WAVE) + lane;
+                if (pts >= (unsigned)TS) {
+                    if (p2 >= pts) p2 -= pts, ++p1;
+                } else {
+                    p1 += p2 / pts;
+                    p2 %= pts;
+                }
+                unsigned y1, x1, y2, x2;
+                divmod_small(p1, (unsigned)side, rside, &y1, &x1);
+                divmod_small(p2, (unsigned)side, rside, &y2, &x2);
+                y1 = min(y1, (unsigned)side - 1u);  // lanes past the last query
                 float *x = istage + (h * WAVE + lane) * 5;
-                x[0] = grid_coord(p1 % side, side);
-                x[1] = grid_coord(p1 / side, side);
-                x[2] = grid_coord(p2 % side, side);
-                x[3] = grid_coord(p2 / side, side);
+                x[0] = ctab[x1];
+                x[1] = ctab[y1];
+                x[2] = ctab[x2];
+                x[3] = ctab[y2];
                 x[4] = 1.0f;
             }
         } else {
@@ -567,7 +602,10 @@ int forward_plan(const FwdJob *jobs, int n, int variant, size_t max_lds,
             it.vec4 = (!J.side && ((uintptr_t)J.inputs % 16 == 0) && (J.gstride % 4 == 0)) ? 1 : 0;
             const int x = 2 * kind + (J.side ? 1 : 0);
             k[x].items.push_back(it);
-            if (!J.side || kind != KIND_LDS) stage_max[x] = std::max(stage_max[x], TS * J.I);
+            // register kernels on grid queries keep the coordinates after
+            // the staged inputs
+            if (!J.side || kind != KIND_LDS)
+                stage_max[x] = std::max(stage_max[x], TS * J.I + (J.side ? GRID_MAX_SIDE : 0));
             if (kind != KIND_LDS) ostage_max[x] = std::max(ostage_max[x], TS * J.O);
             if (kind == KIND_LDS) rows_max[x] = std::max(rows_max[x], class_slots(top, J.N));
         }
