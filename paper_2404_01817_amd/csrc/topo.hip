@@ -34,6 +34,11 @@ namespace neat {
 namespace {
 
 constexpr float KEY_LIMIT = 16777216.0f;  // 2^24
+// Genomes per workgroup when N_max <= 64 (one wave each).  Measured on the
+// control workload (10000 genomes, N_max 50): 1 -> 59 us, 2 -> 61 us,
+// 4 -> 62.5 us, so one genome per workgroup, with the one-wave group's
+// barrier-free synchronisation.
+constexpr int TOPO_GPB = 1;
 
 __device__ __forceinline__ bool is_int_in(float x, float lo, float hi_excl) {
     // NaN fails every comparison
@@ -106,34 +111,96 @@ __device__ int block_excl_scan(int v, int *s_wave, int *total) {
     return base + x - v;
 }
 
-// Block-wide inclusive prefix minimum of one value per thread.  Contains
-// two barriers; every thread of the block must call it.
-__device__ int block_incl_min(int v, int *s_wave) {
-    const int lane = lane_id(), wave = wave_id();
+// The threads transforming one genome: the whole workgroup, or one wave of
+// it when the workgroup holds several genomes (N_max <= 64, so one wave
+// covers the rows).  Barriers and scans are over the group: a one-wave
+// group needs no s_barrier (its lanes run together and its LDS operations
+// complete in order), only a fence that keeps the compiler from moving
+// memory operations across the synchronisation point.
+template <bool ONE>
+struct Grp {
+    int t, W;        // thread in the group, group size
+    int lane, wave;  // lane and wave within the group
+    int nw;          // waves in the group (1 when ONE)
+    int *sh;         // the group's scalars (SH_*) and per-wave partials
+};
+constexpr int SH_STATUS = 0, SH_NVALID = 1, SH_USED = 2, SH_WAVE = 4, SH_WORDS = 20;
+
+template <bool ONE>
+__device__ __forceinline__ void gsync(const Grp<ONE> &G) {
+    if (ONE) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+        __syncthreads();
+    }
+}
+
+template <bool ONE>
+__device__ __forceinline__ bool gsync_or(const Grp<ONE> &G, bool x) {
+    if (ONE) {
+        gsync(G);
+        return __ballot(x) != 0ull;
+    }
+    return __syncthreads_or(x);
+}
+
+// Exclusive scan of one value per thread over the group; *total receives
+// the sum.  Every thread of the group must call it.
+template <bool ONE>
+__device__ __forceinline__ int group_excl_scan(const Grp<ONE> &G, int v, int *total) {
     int x = v;
 #pragma unroll
     for (int d = 1; d < 64; d <<= 1) {
         const int y = __shfl_up(x, d, 64);
-        if (lane >= d) x = min(x, y);
+        if (G.lane >= d) x += y;
     }
-    if (lane == 63) s_wave[wave] = x;
-    __syncthreads();
+    if (ONE) {
+        *total = __shfl(x, 63, 64);
+        return x - v;
+    }
+    if (G.lane == 63) G.sh[SH_WAVE + G.wave] = x;
+    gsync(G);
+    int base = 0, tot = 0;
+    for (int w = 0; w < G.nw; ++w) {
+        const int c = G.sh[SH_WAVE + w];
+        base += (w < G.wave) ? c : 0;
+        tot += c;
+    }
+    gsync(G);
+    *total = tot;
+    return base + x - v;
+}
+
+// Inclusive prefix minimum of one value per thread over the group.
+template <bool ONE>
+__device__ __forceinline__ int group_incl_min(const Grp<ONE> &G, int v) {
+    int x = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int y = __shfl_up(x, d, 64);
+        if (G.lane >= d) x = min(x, y);
+    }
+    if (ONE) return x;
+    if (G.lane == 63) G.sh[SH_WAVE + G.wave] = x;
+    gsync(G);
     int before = 0x7fffffff;
-    for (int w = 0; w < wave; ++w) before = min(before, s_wave[w]);
-    __syncthreads();
+    for (int w = 0; w < G.wave; ++w) before = min(before, G.sh[SH_WAVE + w]);
+    gsync(G);
     return min(before, x);
 }
 
-// Transformation of genome g of population a by the whole workgroup (any
-// block size of at least round_up(N_max, 64) threads).
-__device__ __forceinline__ void topo_genome(const TopoItem &a, size_t g) {
-    extern __shared__ int smem[];
-    __shared__ unsigned s_status;
-    __shared__ int s_nvalid;
-    __shared__ int s_wave[16];
+// Transformation of genome g of population a by group G (at least
+// round_up(N_max, 64) threads), in the LDS words at smem.
+template <bool ONE>
+__device__ __forceinline__ void topo_genome(const TopoItem &a, size_t g, const Grp<ONE> &G,
+                                            int *smem) {
+    unsigned &s_status = *reinterpret_cast<unsigned *>(&G.sh[SH_STATUS]);
+    int &s_nvalid = G.sh[SH_NVALID];
 
     const int N = a.N, C = a.C, I = a.I, O = a.O;
-    const int t = (int)threadIdx.x, W = (int)blockDim.x;
+    const int t = G.t, W = G.W;
 
     int *s_key = smem;            // [N] key of row, -1 absent, -2 malformed
     int *s_skey = s_key + N;      // [N] well-formed keys by stable rank; later level of row
@@ -188,7 +255,7 @@ __device__ __forceinline__ void topo_genome(const TopoItem &a, size_t g) {
         h_key[i] = HASH_EMPTY;
         h_row[i] = 0x7fffffff;
     }
-    __syncthreads();
+    gsync(G);
 
     // ---- 1. node rows
     unsigned st = 0u;
@@ -216,7 +283,7 @@ __device__ __forceinline__ void topo_genome(const TopoItem &a, size_t g) {
         // (key, row) in one word when rows fit in 8 bits (keys are below 2^24)
         if (N <= 256) s_stack[t] = key >= 0 ? (int)(((unsigned)key << 8) | (unsigned)t) : -1;
     }
-    __syncthreads();
+    gsync(G);
 
     // ---- 2. stable key rank (by key, then row), duplicate keys,
     // input/output presence
@@ -245,7 +312,7 @@ __device__ __forceinline__ void topo_genome(const TopoItem &a, size_t g) {
         s_srow[rank] = t;
         if (key < I + O) s_curi[key] = 1;
     }
-    __syncthreads();
+    gsync(G);
     // equal keys hold neighbouring ranks (the other entries are -1)
     if (rank >= 0 && ((rank > 0 && s_skey[rank - 1] == key) ||
                       (rank + 1 < N && s_skey[rank + 1] == key)))
@@ -280,15 +347,15 @@ __device__ __forceinline__ void topo_genome(const TopoItem &a, size_t g) {
     for (int k = 0; k < CPRE; ++k)
         if (t + k * W < C) connection(t + k * W, cpre[k]);
     for (int c = t + CPRE * W; c < C; c += W) connection(c, conns4[c]);
-    __syncthreads();
+    gsync(G);
 
     // ---- 4. adjacency lists (counting sort by destination and by source)
     {
         const int din = (t < N) ? s_indeg[t] : 0;
         const int dout = (t < N) ? s_curo[t] : 0;
         int tin, tout;
-        const int ein = block_excl_scan(din, s_wave, &tin);
-        const int eout = block_excl_scan(dout, s_wave, &tout);
+        const int ein = group_excl_scan(G, din, &tin);
+        const int eout = group_excl_scan(G, dout, &tout);
         if (t < N) {
             s_inoff[t] = ein;
             s_outoff[t] = eout;
@@ -301,7 +368,7 @@ __device__ __forceinline__ void topo_genome(const TopoItem &a, size_t g) {
             s_outoff[N] = tout;
         }
     }
-    __syncthreads();
+    gsync(G);
     for (int c = t; c < C; c += W) {
         const int s = e_src[c];
         if (s < 0) continue;
@@ -309,7 +376,7 @@ __device__ __forceinline__ void topo_genome(const TopoItem &a, size_t g) {
         in_list[s_inoff[d] + atomicAdd(&s_curi[d], 1)] = c;
         out_list[s_outoff[s] + atomicAdd(&s_curo[s], 1)] = d;
     }
-    __syncthreads();
+    gsync(G);
     for (int c = t; c < C; c += W) {
         const int s = e_src[c];
         if (s < 0) continue;
@@ -320,7 +387,7 @@ __device__ __forceinline__ void topo_genome(const TopoItem &a, size_t g) {
         }
     }
     if (st) atomicOr(&s_status, st);
-    __syncthreads();
+    gsync(G);
     unsigned status = s_status;
     const int nvalid = s_nvalid;
 
@@ -329,17 +396,17 @@ __device__ __forceinline__ void topo_genome(const TopoItem &a, size_t g) {
     int my_level = -1;
     const int my_row = (status == 0u && t < nvalid) ? s_srow[t] : -1;
     if (status == 0u) {
-        const int lane = lane_id(), wave = wave_id(), nw = W >> 6;
+        const int lane = G.lane, wave = G.wave, nw = G.nw;
         bool emitted = false;
         int base = 0;
         for (;;) {
             const bool ready = my_row >= 0 && !emitted && s_indeg[my_row] == 0;
             const unsigned long long m = __ballot(ready);
-            if (lane == 0) s_wave[wave] = __popcll(m);
-            __syncthreads();
+            if (lane == 0) G.sh[SH_WAVE + wave] = __popcll(m);
+            gsync(G);
             int wbase = 0, total = 0;
             for (int w = 0; w < nw; ++w) {
-                const int c = s_wave[w];
+                const int c = G.sh[SH_WAVE + w];
                 wbase += (w < wave) ? c : 0;
                 total += c;
             }
@@ -351,16 +418,16 @@ __device__ __forceinline__ void topo_genome(const TopoItem &a, size_t g) {
                 for (int k = s_outoff[my_row]; k < s_outoff[my_row + 1]; ++k)
                     atomicSub(&s_indeg[out_list[k]], 1);
             }
-            __syncthreads();
+            gsync(G);
             base += total;
             ++n_levels;
         }
         if (base < nvalid) status |= NEAT_ST_CYCLE;
     }
-    __syncthreads();  // s_pos complete; s_skey is free and now holds levels
+    gsync(G);  // s_pos complete; s_skey is free and now holds levels
     if (my_row >= 0) s_skey[my_row] = my_level;
     if (status == 0u && t < N && s_key[t] != -1) s_curi[s_pos[t]] = t;  // row by position
-    __syncthreads();
+    gsync(G);
 
     // ---- outputs: order, level, status
     const bool ok = status == 0u;
@@ -373,7 +440,7 @@ __device__ __forceinline__ void topo_genome(const TopoItem &a, size_t g) {
     if (!a.prog) return;
 
     // ---- 6. value slots, then the program (layout in program.h)
-    __shared__ int s_used;
+    int &s_used = G.sh[SH_USED];
     int32_t *prog = a.prog + g * (size_t)a.prog_words;
     float *progf = reinterpret_cast<float *>(prog);
     if (!ok) {
@@ -399,7 +466,7 @@ __device__ __forceinline__ void topo_genome(const TopoItem &a, size_t g) {
         if (s_key[t] >= I && s_key[t] < I + O) last = nvalid;
         s_last[t] = last;
     }
-    __syncthreads();
+    gsync(G);
     if (max_class(N) == CLS_R64) {
         // every genome fits the 64-slot class: slot = position
         if (t < nvalid) s_slot[s_curi[t]] = t;
@@ -425,7 +492,7 @@ __device__ __forceinline__ void topo_genome(const TopoItem &a, size_t g) {
             s_dc[t] = 0;
             s_pair[t] = NEVER;
         }
-        __syncthreads();
+        gsync(G);
         if (t < N && s_key[t] != -1) {
             const int p = s_pos[t], last = s_last[t];
             const bool out = s_key[t] >= I && s_key[t] < I + O;
@@ -436,7 +503,7 @@ __device__ __forceinline__ void topo_genome(const TopoItem &a, size_t g) {
                 atomicMin(&s_pair[fa], t);
             }
         }
-        __syncthreads();
+        gsync(G);
         // per position: pairing, or an open (extra frees) / close (birth
         // without a free at its position) event; clamped depth by scans
         const bool vp = t >= I && t < nvalid;
@@ -444,16 +511,16 @@ __device__ __forceinline__ void topo_genome(const TopoItem &a, size_t g) {
         const int pairrow = vp ? s_pair[t] : -1;
         const int n_open = d > 1 ? d - 1 : 0, n_close = (vp && d == 0) ? 1 : 0;
         int tot_open, tot_close;
-        const int ob = block_excl_scan(n_open, s_wave, &tot_open);
-        const int cb = block_excl_scan(n_close, s_wave, &tot_close);
-        const int u_before = -block_incl_min(ob - cb, s_wave);  // unmatched closes before
+        const int ob = group_excl_scan(G, n_open, &tot_open);
+        const int cb = group_excl_scan(G, n_close, &tot_close);
+        const int u_before = -group_incl_min(G, ob - cb);  // unmatched closes before
         const int s_incl = ob + n_open - cb - n_close;
         const int u_incl = max(u_before, -s_incl);
         const bool unmatched = n_close && u_incl > u_before;
         const int close_rank = cb - u_before;  // matched closes before this one
         if (vp) s_obase[t] = ob;
         if (t == nvalid - 1) s_used = I + u_incl;
-        __syncthreads();
+        gsync(G);
         // extra frees get their open ranks
         if (t < N && s_key[t] != -1) {
             const int fa = s_free[t];
@@ -462,7 +529,7 @@ __device__ __forceinline__ void topo_genome(const TopoItem &a, size_t g) {
                 s_oval[s_obase[fa] + k] = t;
             }
         }
-        __syncthreads();
+        gsync(G);
         // ancestors: the value whose slot a birth takes; roots get slots
         int *s_anc = s_dc;
         if (t < nvalid) {
@@ -474,7 +541,7 @@ __device__ __forceinline__ void topo_genome(const TopoItem &a, size_t g) {
             else s_slot[b] = I + u_incl - 1;
             s_anc[b] = anc;
         }
-        __syncthreads();
+        gsync(G);
         bool more = true;
         while (more) {
             int anc = -1, slot = 0;
@@ -488,20 +555,20 @@ __device__ __forceinline__ void topo_genome(const TopoItem &a, size_t g) {
                     anc = aa;
                 }
             }
-            __syncthreads();
+            gsync(G);
             if (changed) {
                 s_anc[t] = anc;
                 if (anc < 0) s_slot[t] = slot;
             }
-            more = __syncthreads_or(changed);
+            more = gsync_or(G, changed);
         }
     }
-    __syncthreads();
+    gsync(G);
     // source key of every in-edge (the out lists are no longer needed), for
     // the per-node scans below
     int *in_key = out_list;
     for (int k = t; k < s_inoff[N]; k += W) in_key[k] = s_key[e_src[in_list[k]]];
-    __syncthreads();
+    gsync(G);
     const int used = s_used;
     const int cls = class_of(used);
     const int zs = zero_slot(cls, N);
@@ -531,15 +598,15 @@ __device__ __forceinline__ void topo_genome(const TopoItem &a, size_t g) {
     }
     const int pairs = (deg + 1) >> 1;
     const int over = pairs > REC_INLINE_PAIRS ? 2 * (pairs - REC_INLINE_PAIRS) : 0;
-    __syncthreads();
+    gsync(G);
     if (computed) s_deg[t] = over;
-    __syncthreads();
+    gsync(G);
     // first overflow edge of every position, in topological order; level starts
     {
         const int row = (t < nvalid) ? s_curi[t] : -1;
         const int cnt = (t >= I && t < nvalid) ? s_deg[row] : 0;
         int tot;
-        const int eb = block_excl_scan(cnt, s_wave, &tot);
+        const int eb = group_excl_scan(G, cnt, &tot);
         if (t >= I && t < nvalid) {
             prog[ebeg_off(N, C, O) + (t - I)] = eb;
             s_curo[row] = eb;  // overflow begin by row
@@ -561,7 +628,7 @@ __device__ __forceinline__ void topo_genome(const TopoItem &a, size_t g) {
                                          : 0;
         }
     }
-    __syncthreads();
+    gsync(G);
     const int eoff = edge_off(N, O);
     if (computed) {
         const int k = s_pos[t] - I;
@@ -607,7 +674,7 @@ __device__ __forceinline__ void topo_genome(const TopoItem &a, size_t g) {
     // aggregation code and overflow begin by row for the edge writers
     int *s_agg = s_deg;
     if (computed) s_agg[t] = agg;
-    __syncthreads();
+    gsync(G);
     // real edges: index j = number of in-edges of the destination with a
     // smaller source key (keys are unique here); j < 6 in the record, the
     // rest in the overflow array.  The thread that read a connection row
@@ -632,11 +699,38 @@ __device__ __forceinline__ void topo_genome(const TopoItem &a, size_t g) {
     for (int c = t + CPRE * W; c < C; c += W) edge(c, conns[(size_t)c * 4 + 3]);
 }
 
-__global__ __launch_bounds__(1024) void topo_kernel(TopoItem a) { topo_genome(a, blockIdx.x); }
+// gpb genomes per workgroup, each group with its own lds_words of LDS: ONE,
+// one wave per genome (N_max <= 64; any gpb); else the whole workgroup
+// (gpb == 1).
+template <bool ONE>
+__device__ __forceinline__ void topo_groups(const TopoItem &a, long long b, int gpb,
+                                            int lds_words) {
+    extern __shared__ int smem[];
+    const int slot = ONE ? (int)(threadIdx.x >> 6) : 0;
+    Grp<ONE> G;
+    if (ONE) {
+        G.t = (int)(threadIdx.x & 63u), G.W = 64, G.lane = G.t, G.wave = 0, G.nw = 1;
+    } else {
+        G.t = (int)threadIdx.x, G.W = (int)blockDim.x, G.lane = G.t & 63, G.wave = G.t >> 6;
+        G.nw = G.W >> 6;
+    }
+    int *base = smem + (size_t)slot * lds_words;
+    G.sh = base;
+    const long long g = b * gpb + slot;
+    if (g >= a.P) return;  // a whole group (a wave when gpb > 1)
+    topo_genome(a, (size_t)g, G, base + SH_WORDS);
+}
 
-// Many populations: workgroup b transforms genome b - block0 of the item
-// whose range holds b (items sorted by block0).
-__global__ __launch_bounds__(1024) void topo_batch_kernel(const TopoItem *items, int n) {
+template <bool ONE>
+__global__ __launch_bounds__(1024) void topo_kernel(TopoItem a, int gpb, int lds_words) {
+    topo_groups<ONE>(a, blockIdx.x, gpb, lds_words);
+}
+
+// Many populations: workgroup b transforms genomes (b - block0) gpb .. of the
+// item whose range holds b (items sorted by block0).
+template <bool ONE>
+__global__ __launch_bounds__(1024) void topo_batch_kernel(const TopoItem *items, int n, int gpb,
+                                                          int lds_words) {
     int lo = 0, hi = n - 1;
     const long long b = blockIdx.x;
     while (lo < hi) {
@@ -645,7 +739,7 @@ __global__ __launch_bounds__(1024) void topo_batch_kernel(const TopoItem *items,
         else hi = mid - 1;
     }
     const TopoItem it = items[lo];
-    topo_genome(it, (size_t)(b - it.block0));
+    topo_groups<ONE>(it, b - it.block0, gpb, lds_words);
 }
 
 // List the genomes of a population by slot class (one workgroup of 1024
@@ -705,7 +799,18 @@ __global__ __launch_bounds__(1024) void classify_batch_kernel(const TopoItem *it
 }  // namespace
 
 size_t topo_lds_bytes(int N, int C) {
-    return sizeof(int) * ((size_t)13 * N + 2 + (size_t)4 * C + 2 * (size_t)hash_size(N));
+    return sizeof(int) *
+           ((size_t)SH_WORDS + (size_t)13 * N + 2 + (size_t)4 * C + 2 * (size_t)hash_size(N));
+}
+
+int topo_genomes_per_block(int N, int C) {
+    // several one-wave genomes per workgroup, so a CU is not held to one
+    // wave per workgroup slot; the workgroup stays within 64 KB of LDS
+    if (N > 64 || TOPO_GPB == 1) return 1;
+    const size_t L = topo_lds_bytes(N, C);
+    int gpb = TOPO_GPB;
+    while (gpb > 1 && gpb * L > 65536) gpb >>= 1;
+    return gpb;
 }
 
 int topo_block_threads(int N) {
@@ -717,8 +822,18 @@ hipError_t launch_topo(int P, int N, int C, int I, int O, const float *nodes,
                        const float *conns, int32_t *order, int32_t *level,
                        uint32_t *status, int32_t *prog, hipStream_t stream) {
     TopoItem a{nodes, conns, order, level, status, prog, P, N, C, I, O, prog_words(N, C, O), 0};
-    hipLaunchKernelGGL(topo_kernel, dim3((unsigned)P), dim3((unsigned)topo_block_threads(N)),
-                       topo_lds_bytes(N, C), stream, a);
+    const int gpb = topo_genomes_per_block(N, C);
+    const size_t L = topo_lds_bytes(N, C);
+    if (P > 0) {
+        const dim3 grid((unsigned)((P + gpb - 1) / gpb));
+        const dim3 block((unsigned)(N <= 64 ? 64 * gpb : topo_block_threads(N)));
+        if (N <= 64)
+            hipLaunchKernelGGL(topo_kernel<true>, grid, block, gpb * L, stream, a, gpb,
+                               (int)(L / sizeof(int)));
+        else
+            hipLaunchKernelGGL(topo_kernel<false>, grid, block, gpb * L, stream, a, gpb,
+                               (int)(L / sizeof(int)));
+    }
     if (prog && max_class(N) != CLS_R64) {
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
@@ -729,9 +844,15 @@ hipError_t launch_topo(int P, int N, int C, int I, int O, const float *nodes,
 }
 
 hipError_t launch_topo_batch(const TopoItem *dev_items, int n, long long blocks, int threads,
-                             size_t lds, hipStream_t stream) {
-    hipLaunchKernelGGL(topo_batch_kernel, dim3((unsigned)blocks), dim3((unsigned)threads), lds,
-                       stream, dev_items, n);
+                             size_t lds, int gpb, hipStream_t stream) {
+    // lds: the bytes of one genome's group; each of the gpb groups gets them
+    // one-wave groups whenever every genome fits a wave (64-thread bucket)
+    if (threads == 64 * gpb)
+        hipLaunchKernelGGL(topo_batch_kernel<true>, dim3((unsigned)blocks), dim3((unsigned)threads),
+                           gpb * lds, stream, dev_items, n, gpb, (int)(lds / sizeof(int)));
+    else
+        hipLaunchKernelGGL(topo_batch_kernel<false>, dim3((unsigned)blocks), dim3((unsigned)threads),
+                           gpb * lds, stream, dev_items, n, gpb, (int)(lds / sizeof(int)));
     return hipGetLastError();
 }
 
