@@ -66,8 +66,7 @@ struct TopoLaunch {
     int n;
     long long blocks;
     int threads;
-    size_t lds;  // per genome
-    int gpb;     // genomes per workgroup
+    size_t lds;
     const neat::TopoItem *table;
 };
 
@@ -76,7 +75,7 @@ int record(const std::vector<TopoLaunch> &topo, const neat::TopoItem *all_topo, 
            const std::vector<neat::FwdKernelLaunch> &fw,
            const std::vector<const neat::FwdItem *> &tab, hipStream_t s) {
     for (const TopoLaunch &t : topo) {
-        hipError_t e = neat::launch_topo_batch(t.table, t.n, t.blocks, t.threads, t.lds, t.gpb, s);
+        hipError_t e = neat::launch_topo_batch(t.table, t.n, t.blocks, t.threads, t.lds, s);
         if (e != hipSuccess) return hip_fail(e, "batch transformation launch");
     }
     if (n_topo) {
@@ -115,20 +114,12 @@ int build(const neat_batch_item *items, int32_t n, neat_batch_plan **out) {
     std::vector<neat::TopoItem> topo_host;
     for (int b = 0; b < 5; ++b) {
         if (bucket[b].empty()) continue;
-        TopoLaunch t{(int)bucket[b].size(), 0, 64, 0, 1, nullptr};
-        int nmax = 1, cmax = 0;
-        for (const neat::TopoItem &ti : bucket[b]) {
-            t.threads = std::max(t.threads, neat::topo_block_threads(ti.N));
-            t.lds = std::max(t.lds, neat::topo_lds_bytes(ti.N, ti.C));
-            nmax = std::max(nmax, ti.N);
-            cmax = std::max(cmax, ti.C);
-        }
-        // the 64-thread bucket runs several genomes per workgroup
-        t.gpb = neat::topo_genomes_per_block(nmax, cmax);
-        if (t.gpb > 1) t.threads = 64 * t.gpb;
+        TopoLaunch t{(int)bucket[b].size(), 0, 64, 0, nullptr};
         for (neat::TopoItem &ti : bucket[b]) {
             ti.block0 = t.blocks;
-            t.blocks += (ti.P + t.gpb - 1) / t.gpb;
+            t.blocks += ti.P;
+            t.threads = std::max(t.threads, neat::topo_block_threads(ti.N));
+            t.lds = std::max(t.lds, neat::topo_lds_bytes(ti.N, ti.C));
         }
         t.table = (const neat::TopoItem *)(uintptr_t)topo_host.size();  // offset for now
         topo_host.insert(topo_host.end(), bucket[b].begin(), bucket[b].end());

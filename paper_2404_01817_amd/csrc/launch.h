@@ -15,10 +15,6 @@ namespace neat {
 size_t topo_lds_bytes(int N, int C);
 // Threads per block of the transformation kernel (one thread per node row).
 int topo_block_threads(int N);
-// Genomes per workgroup of the transformation kernel (one wave each when
-// above 1; then the workgroup has 64 threads per genome and that many
-// times topo_lds_bytes of LDS).
-int topo_genomes_per_block(int N, int C);
 
 hipError_t launch_topo(int P, int N, int C, int I, int O, const float *nodes,
                        const float *conns, int32_t *order, int32_t *level,
@@ -38,12 +34,10 @@ struct TopoItem {
 };
 
 // Transformation of many populations in one launch (items in device memory,
-// sorted by block0, each item ceil(P / gpb) workgroups; with gpb == 1,
-// threads >= topo_block_threads and lds >= topo_lds_bytes of every item;
-// with gpb > 1, every item has N_max <= 64, threads = 64 gpb and lds is
-// per genome), and the class lists of all of them (one workgroup each).
+// sorted by block0; threads >= topo_block_threads and lds >= topo_lds_bytes
+// of every item), and the class lists of all of them (one workgroup each).
 hipError_t launch_topo_batch(const TopoItem *dev_items, int n, long long blocks, int threads,
-                             size_t lds, int gpb, hipStream_t stream);
+                             size_t lds, hipStream_t stream);
 hipError_t launch_classify_batch(const TopoItem *dev_items, int n, hipStream_t stream);
 
 // Forward variants (value stores of the lane-per-sample mapping).

@@ -34,11 +34,6 @@ namespace neat {
 namespace {
 
 constexpr float KEY_LIMIT = 16777216.0f;  // 2^24
-// Genomes per workgroup when N_max <= 64 (one wave each).  Measured on the
-// control workload (10000 genomes, N_max 50): 1 -> 59 us, 2 -> 61 us,
-// 4 -> 62.5 us, so one genome per workgroup, with the one-wave group's
-// barrier-free synchronisation.
-constexpr int TOPO_GPB = 1;
 
 __device__ __forceinline__ bool is_int_in(float x, float lo, float hi_excl) {
     // NaN fails every comparison
@@ -111,12 +106,14 @@ __device__ int block_excl_scan(int v, int *s_wave, int *total) {
     return base + x - v;
 }
 
-// The threads transforming one genome: the whole workgroup, or one wave of
-// it when the workgroup holds several genomes (N_max <= 64, so one wave
-// covers the rows).  Barriers and scans are over the group: a one-wave
-// group needs no s_barrier (its lanes run together and its LDS operations
+// The threads transforming one genome (one workgroup of at least
+// round_up(N_max, 64) threads).  When N_max <= 64 the group is one wave:
+// it needs no s_barrier (its lanes run together and its LDS operations
 // complete in order), only a fence that keeps the compiler from moving
-// memory operations across the synchronisation point.
+// memory operations across the synchronisation point, and its scans stay
+// in the wave.  (Packing several one-wave genomes into a workgroup was
+// measured slower on the control workload: 61 and 62.5 us for two and four
+// per workgroup against 59 us for one.)
 template <bool ONE>
 struct Grp {
     int t, W;        // thread in the group, group size
@@ -699,38 +696,26 @@ __device__ __forceinline__ void topo_genome(const TopoItem &a, size_t g, const G
     for (int c = t + CPRE * W; c < C; c += W) edge(c, conns[(size_t)c * 4 + 3]);
 }
 
-// gpb genomes per workgroup, each group with its own lds_words of LDS: ONE,
-// one wave per genome (N_max <= 64; any gpb); else the whole workgroup
-// (gpb == 1).
+// Genome g by the workgroup (ONE: a single wave, N_max <= 64).
 template <bool ONE>
-__device__ __forceinline__ void topo_groups(const TopoItem &a, long long b, int gpb,
-                                            int lds_words) {
+__device__ __forceinline__ void topo_group(const TopoItem &a, long long g) {
     extern __shared__ int smem[];
-    const int slot = ONE ? (int)(threadIdx.x >> 6) : 0;
     Grp<ONE> G;
-    if (ONE) {
-        G.t = (int)(threadIdx.x & 63u), G.W = 64, G.lane = G.t, G.wave = 0, G.nw = 1;
-    } else {
-        G.t = (int)threadIdx.x, G.W = (int)blockDim.x, G.lane = G.t & 63, G.wave = G.t >> 6;
-        G.nw = G.W >> 6;
-    }
-    int *base = smem + (size_t)slot * lds_words;
-    G.sh = base;
-    const long long g = b * gpb + slot;
-    if (g >= a.P) return;  // a whole group (a wave when gpb > 1)
-    topo_genome(a, (size_t)g, G, base + SH_WORDS);
+    G.t = (int)threadIdx.x, G.W = ONE ? 64 : (int)blockDim.x, G.lane = G.t & 63;
+    G.wave = ONE ? 0 : G.t >> 6, G.nw = ONE ? 1 : G.W >> 6;
+    G.sh = smem;
+    topo_genome(a, (size_t)g, G, smem + SH_WORDS);
 }
 
 template <bool ONE>
-__global__ __launch_bounds__(1024) void topo_kernel(TopoItem a, int gpb, int lds_words) {
-    topo_groups<ONE>(a, blockIdx.x, gpb, lds_words);
+__global__ __launch_bounds__(1024) void topo_kernel(TopoItem a) {
+    topo_group<ONE>(a, blockIdx.x);
 }
 
-// Many populations: workgroup b transforms genomes (b - block0) gpb .. of the
-// item whose range holds b (items sorted by block0).
+// Many populations: workgroup b transforms genome b - block0 of the item
+// whose range holds b (items sorted by block0).
 template <bool ONE>
-__global__ __launch_bounds__(1024) void topo_batch_kernel(const TopoItem *items, int n, int gpb,
-                                                          int lds_words) {
+__global__ __launch_bounds__(1024) void topo_batch_kernel(const TopoItem *items, int n) {
     int lo = 0, hi = n - 1;
     const long long b = blockIdx.x;
     while (lo < hi) {
@@ -739,7 +724,7 @@ __global__ __launch_bounds__(1024) void topo_batch_kernel(const TopoItem *items,
         else hi = mid - 1;
     }
     const TopoItem it = items[lo];
-    topo_groups<ONE>(it, b - it.block0, gpb, lds_words);
+    topo_group<ONE>(it, b - it.block0);
 }
 
 // List the genomes of a population by slot class (one workgroup of 1024
@@ -803,15 +788,6 @@ size_t topo_lds_bytes(int N, int C) {
            ((size_t)SH_WORDS + (size_t)13 * N + 2 + (size_t)4 * C + 2 * (size_t)hash_size(N));
 }
 
-int topo_genomes_per_block(int N, int C) {
-    // several one-wave genomes per workgroup, so a CU is not held to one
-    // wave per workgroup slot; the workgroup stays within 64 KB of LDS
-    if (N > 64 || TOPO_GPB == 1) return 1;
-    const size_t L = topo_lds_bytes(N, C);
-    int gpb = TOPO_GPB;
-    while (gpb > 1 && gpb * L > 65536) gpb >>= 1;
-    return gpb;
-}
 
 int topo_block_threads(int N) {
     int w = round_up(N, 64);
@@ -822,17 +798,13 @@ hipError_t launch_topo(int P, int N, int C, int I, int O, const float *nodes,
                        const float *conns, int32_t *order, int32_t *level,
                        uint32_t *status, int32_t *prog, hipStream_t stream) {
     TopoItem a{nodes, conns, order, level, status, prog, P, N, C, I, O, prog_words(N, C, O), 0};
-    const int gpb = topo_genomes_per_block(N, C);
     const size_t L = topo_lds_bytes(N, C);
     if (P > 0) {
-        const dim3 grid((unsigned)((P + gpb - 1) / gpb));
-        const dim3 block((unsigned)(N <= 64 ? 64 * gpb : topo_block_threads(N)));
+        const dim3 grid((unsigned)P), block((unsigned)topo_block_threads(N));
         if (N <= 64)
-            hipLaunchKernelGGL(topo_kernel<true>, grid, block, gpb * L, stream, a, gpb,
-                               (int)(L / sizeof(int)));
+            hipLaunchKernelGGL(topo_kernel<true>, grid, block, L, stream, a);
         else
-            hipLaunchKernelGGL(topo_kernel<false>, grid, block, gpb * L, stream, a, gpb,
-                               (int)(L / sizeof(int)));
+            hipLaunchKernelGGL(topo_kernel<false>, grid, block, L, stream, a);
     }
     if (prog && max_class(N) != CLS_R64) {
         hipError_t e = hipGetLastError();
@@ -844,15 +816,14 @@ hipError_t launch_topo(int P, int N, int C, int I, int O, const float *nodes,
 }
 
 hipError_t launch_topo_batch(const TopoItem *dev_items, int n, long long blocks, int threads,
-                             size_t lds, int gpb, hipStream_t stream) {
-    // lds: the bytes of one genome's group; each of the gpb groups gets them
-    // one-wave groups whenever every genome fits a wave (64-thread bucket)
-    if (threads == 64 * gpb)
-        hipLaunchKernelGGL(topo_batch_kernel<true>, dim3((unsigned)blocks), dim3((unsigned)threads),
-                           gpb * lds, stream, dev_items, n, gpb, (int)(lds / sizeof(int)));
+                             size_t lds, hipStream_t stream) {
+    // one-wave groups when every genome fits a wave (the 64-thread bucket)
+    if (threads == 64)
+        hipLaunchKernelGGL(topo_batch_kernel<true>, dim3((unsigned)blocks), dim3(64u), lds, stream,
+                           dev_items, n);
     else
-        hipLaunchKernelGGL(topo_batch_kernel<false>, dim3((unsigned)blocks), dim3((unsigned)threads),
-                           gpb * lds, stream, dev_items, n, gpb, (int)(lds / sizeof(int)));
+        hipLaunchKernelGGL(topo_batch_kernel<false>, dim3((unsigned)blocks),
+                           dim3((unsigned)threads), lds, stream, dev_items, n);
     return hipGetLastError();
 }
 
