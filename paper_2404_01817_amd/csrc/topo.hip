@@ -121,7 +121,7 @@ struct Grp {
     int nw;          // waves in the group (1 when ONE)
     int *sh;         // the group's scalars (SH_*) and per-wave partials
 };
-constexpr int SH_STATUS = 0, SH_NVALID = 1, SH_USED = 2, SH_WAVE = 4, SH_WORDS = 20;
+constexpr int SH_STATUS = 0, SH_NVALID = 1, SH_USED = 2, SH_WIDE = 3, SH_WAVE = 4, SH_WORDS = 20;
 
 template <bool ONE>
 __device__ __forceinline__ void gsync(const Grp<ONE> &G) {
@@ -240,6 +240,7 @@ __device__ __forceinline__ void topo_genome(const TopoItem &a, size_t g, const G
     if (t == 0) {
         s_status = 0u;
         s_nvalid = 0;
+        G.sh[SH_WIDE] = 0;
     }
     for (int i = t; i < N; i += W) {
         s_indeg[i] = 0;
@@ -255,6 +256,7 @@ __device__ __forceinline__ void topo_genome(const TopoItem &a, size_t g, const G
     gsync(G);
 
     // ---- 1. node rows
+    const int rb = N <= 256 ? 8 : 10;  // row bits of the packed (key, row) words
     unsigned st = 0u;
     int key = -1, act = 0, agg = 0;
     float bias = 0.0f, resp = 0.0f;
@@ -277,19 +279,23 @@ __device__ __forceinline__ void topo_genome(const TopoItem &a, size_t g, const G
             if (key_ok) hash_insert(h_key, h_row, H, key, t);
         }
         s_key[t] = key;
-        // (key, row) in one word when rows fit in 8 bits (keys are below 2^24)
-        if (N <= 256) s_stack[t] = key >= 0 ? (int)(((unsigned)key << 8) | (unsigned)t) : -1;
+        // (key, row) in one word: rows take rb bits, keys the rest (always
+        // room when rows fit in 8 bits, keys being below 2^24; with 10 row
+        // bits a key of 2^22 or more marks the genome as wide)
+        if (key >= 0 && rb == 10 && key >= (1 << 22)) G.sh[SH_WIDE] = 1;
+        s_stack[t] = key >= 0 ? (int)(((unsigned)key << rb) | (unsigned)t) : -1;
     }
     gsync(G);
 
     // ---- 2. stable key rank (by key, then row), duplicate keys,
     // input/output presence
     int rank = -1;
+    const bool packed = G.sh[SH_WIDE] == 0;
     if (key >= 0) {
-        if (N <= 256) {
+        if (packed) {
             // rank = number of (key, row) words below this row's (the words
             // are distinct; absent and malformed rows hold the largest)
-            const unsigned mine = ((unsigned)key << 8) | (unsigned)t;
+            const unsigned mine = ((unsigned)key << rb) | (unsigned)t;
             const unsigned *comp = reinterpret_cast<const unsigned *>(s_stack);
             int less = 0;
 #pragma unroll 8

@@ -184,9 +184,19 @@ def test_planted_defects_status_bit_exact(N):
                 conns[g, c[-1], 2] = 1.0
         else:            # a fractional key
             nodes[g, rows[-1], 0] = 7.5
+    # every third genome from the second on: hidden keys moved to 2^22 and
+    # above (valid keys; connections follow), the transformation's wide-key
+    # ranking
+    for g in range(1, 60, 3):
+        hidden = nodes[g, :, 0] >= pop.I + pop.O
+        nodes[g, hidden, 0] += 5000000.0
+        for col in (0, 1):
+            moved = conns[g, :, col] >= pop.I + pop.O
+            conns[g, moved, col] += 5000000.0
     order, level, status, _ = _gpu(nodes, conns, pop.I, pop.O)
     _assert_transform_exact(nodes, conns, pop.I, pop.O, order, level, status)
     assert (status[0::3] != 0).all()
+    assert (status[1::3] == 0).any()
 
 
 def test_storage_invariants_bit_identical():
