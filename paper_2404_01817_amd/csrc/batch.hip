@@ -10,6 +10,9 @@
 // calculations, batched the same way: one launch per workgroup-size bucket
 // (64, 128, 256, 512, 1024 threads) over the genomes of every population in
 // it, then one launch listing the genomes of every population by class.
+// The launches of each stage are independent and are recorded as parallel
+// branches of the graph (the forward kernels after the class lists), so a
+// long launch's tail overlaps the others.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -70,23 +73,45 @@ struct TopoLaunch {
     const neat::TopoItem *table;
 };
 
-// Record every launch of the batch on stream s.
+// Capture streams: the launches of one stage (the transformation buckets,
+// then the forward kernels) are independent, so they are recorded as
+// parallel branches of the graph; the class lists wait for every bucket.
+constexpr int N_BRANCH = 6;
+
+// Every stream of cs joins stream 0 (fork: 0 -> others; join: others -> 0).
+hipError_t link(hipStream_t *cs, bool fork, hipEvent_t *ev) {
+    for (int i = 1; i < N_BRANCH; ++i) {
+        hipStream_t from = fork ? cs[0] : cs[i], to = fork ? cs[i] : cs[0];
+        hipError_t e = hipEventRecord(ev[i], from);
+        if (e == hipSuccess) e = hipStreamWaitEvent(to, ev[i], 0);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// Record every launch of the batch; cs[0] is capturing, the other streams
+// are forked from it and joined back at the end.
 int record(const std::vector<TopoLaunch> &topo, const neat::TopoItem *all_topo, int n_topo,
            const std::vector<neat::FwdKernelLaunch> &fw,
-           const std::vector<const neat::FwdItem *> &tab, hipStream_t s) {
-    for (const TopoLaunch &t : topo) {
-        hipError_t e = neat::launch_topo_batch(t.table, t.n, t.blocks, t.threads, t.lds, s);
+           const std::vector<const neat::FwdItem *> &tab, hipStream_t *cs, hipEvent_t *ev) {
+    hipError_t e = link(cs, true, ev);
+    for (size_t k = 0; e == hipSuccess && k < topo.size(); ++k) {
+        const TopoLaunch &t = topo[k];
+        e = neat::launch_topo_batch(t.table, t.n, t.blocks, t.threads, t.lds, cs[k % N_BRANCH]);
         if (e != hipSuccess) return hip_fail(e, "batch transformation launch");
     }
-    if (n_topo) {
-        hipError_t e = neat::launch_classify_batch(all_topo, n_topo, s);
+    if (e == hipSuccess) e = link(cs, false, ev);
+    if (e == hipSuccess && n_topo) {
+        e = neat::launch_classify_batch(all_topo, n_topo, cs[0]);
         if (e != hipSuccess) return hip_fail(e, "batch class lists launch");
     }
-    for (size_t k = 0; k < fw.size(); ++k) {
-        hipError_t e = neat::forward_launch(fw[k], tab[k], s);
+    if (e == hipSuccess) e = link(cs, true, ev);
+    for (size_t k = 0; e == hipSuccess && k < fw.size(); ++k) {
+        e = neat::forward_launch(fw[k], tab[k], cs[k % N_BRANCH]);
         if (e != hipSuccess) return hip_fail(e, "batch forward launch");
     }
-    return NEAT_OK;
+    if (e == hipSuccess) e = link(cs, false, ev);
+    return e == hipSuccess ? NEAT_OK : hip_fail(e, "batch stream fork or join");
 }
 
 int build(const neat_batch_item *items, int32_t n, neat_batch_plan **out) {
@@ -185,23 +210,36 @@ int build(const neat_batch_item *items, int32_t n, neat_batch_plan **out) {
         all_dev = base + all_off;
     }
 
-    // record the launches into a graph on a private stream
-    hipStream_t cs = nullptr;
-    hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
-    if (e != hipSuccess) {
-        destroy(p);
-        return hip_fail(e, "capture stream");
+    // record the launches into a graph on private streams (default
+    // priority), the branches of each stage on streams forked from cs[0]
+    hipStream_t cs[N_BRANCH] = {};
+    hipEvent_t ev[N_BRANCH] = {};
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < N_BRANCH && e == hipSuccess; ++i) {
+        e = hipStreamCreateWithFlags(&cs[i], hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&ev[i], hipEventDisableTiming);
     }
-    e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    auto release = [&]() {
+        for (int i = 0; i < N_BRANCH; ++i) {
+            if (ev[i]) (void)hipEventDestroy(ev[i]);
+            if (cs[i]) (void)hipStreamDestroy(cs[i]);
+        }
+    };
     if (e != hipSuccess) {
-        (void)hipStreamDestroy(cs);
+        release();
+        destroy(p);
+        return hip_fail(e, "capture streams");
+    }
+    e = hipStreamBeginCapture(cs[0], hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        release();
         destroy(p);
         return hip_fail(e, "begin capture");
     }
-    rc = record(topo, all_dev, (int)all_topo.size(), fw, tab, cs);
+    rc = record(topo, all_dev, (int)all_topo.size(), fw, tab, cs, ev);
     hipGraph_t g = nullptr;
-    e = hipStreamEndCapture(cs, &g);
-    (void)hipStreamDestroy(cs);
+    e = hipStreamEndCapture(cs[0], &g);
+    release();
     p->graph = g;
     if (rc != NEAT_OK || e != hipSuccess) {
         destroy(p);
