@@ -145,6 +145,37 @@ def test_grid_inputs_match_generator():
         assert np.array_equal(y[0, :, 0], synth.grid_queries()[:, j])
 
 
+def _grid_reference(side, first, Q):
+    """x1, y1, x2, y2 of queries first .. first+Q-1 (coordinates divided in
+    fp32, as the definition rounds them)."""
+    i = np.arange(side, dtype=np.float32)
+    c = (np.float32(2) * i - np.float32(side - 1)) / np.float32(side - 1)
+    q = np.arange(first, first + Q, dtype=np.int64)
+    pts = side * side
+    p1, p2 = q // pts, q % pts
+    return np.stack([c[p1 % side], c[p1 // side], c[p2 % side], c[p2 // side]], axis=1)
+
+
+@pytest.mark.parametrize("side,first,Q", [
+    (2, 0, 16), (3, 0, 81), (5, 7, 600), (11, 0, 14641), (12, 100, 20000), (17, 0, 83521),
+    (100, 0, 5000), (100, 10 ** 8 - 3000, 3000), (100, 12345678, 777),
+    (256, 2 ** 32 - 1000, 1000), (256, 2 ** 31 + 5, 300), (256, 0, 70000)])
+def test_grid_inputs_many_sides(side, first, Q):
+    """Grid queries for small and large sides, partial tiles and the end of
+    the query range: the four coordinates equal the definition bit for bit
+    (identity networks pass each input through)."""
+    gens = []
+    for j in range(4):
+        nodes = {i: (i, 0, 1, 0, 0) for i in range(5)}
+        nodes[5] = (5, 0.0, 1.0, 0, 0)
+        gens.append(genome(6, 1, nodes, {0: (j, 5, 1, 1.0)}))
+    n, c = stack(gens)
+    *_, y = _gpu(n, c, 5, 1, grid=(side, first, Q))
+    ref = _grid_reference(side, first, Q)
+    for j in range(4):
+        assert np.array_equal(y[j, :, 0], ref[:, j]), (side, first, Q, j)
+
+
 def test_uneven_populations():
     """Node counts up to 400 (multi-wave sort), I/O drawn per population."""
     pops = synth.uneven(seed=5, n_pops=6, P_range=(3, 40), N_range=(10, 400),
