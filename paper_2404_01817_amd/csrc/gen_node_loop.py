@@ -230,8 +230,8 @@ def to_activation(R, rec, base, shift):
 
 def agg_entry(R, X, cls, k, rec, pref, base, shift):
     """Table entry for a node of class cls with k pairs (or "ov": three in
-    the record, the rest in the overflow array): request the record after
-    the next one into pref, aggregate, and jump to the activation."""
+    the record, the rest in the overflow array): request the next node's
+    record into pref, aggregate, and jump to the activation."""
     out = ["s_add_u32 s86, s86, 64",
            "s_load_dwordx16 %s, s[80:81], s86" % pref]
     if k == "ov":
@@ -339,8 +339,8 @@ INLINE_CONSTS = {"0", "1", "-1", "2", "4", "-2", "-4", "0.5", "-0.5", "1.0", "-1
 
 
 def encoded_bytes(line):
-    """Upper bound of an instruction's encoding: 8 bytes for VOP3 forms and
-    for anything carrying a 32-bit literal, else 4."""
+    """Upper bound of an instruction's encoding: 8 bytes for VOP3 forms,
+    scalar memory loads and anything carrying a 32-bit literal, else 4."""
     op = line.split()[0]
     if op.startswith(".") or op.endswith(":"):
         return 0
@@ -351,7 +351,8 @@ def encoded_bytes(line):
     vop3 = op.endswith("_e64") or op in ("v_fma_f32", "v_maximum3_f32", "v_bfi_b32",
                                          "v_lshl_add_u64", "v_lshl_add_u32",
                                          "v_cmp_gt_u32_e64")
-    return 8 if (vop3 or literal or op in ("v_fmaak_f32", "v_fmamk_f32")) else 4
+    smem = op.startswith("s_load") or op.startswith("s_buffer_load")
+    return 8 if (vop3 or literal or smem or op in ("v_fmaak_f32", "v_fmamk_f32")) else 4
 
 
 def act_blocks(R, rec, orec, obase, shift):
