@@ -59,9 +59,15 @@ def _load():
         i32, i64, vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p
         lib.oracle_transform.argtypes = [i32] * 5 + [vp] * 5
         lib.oracle_transform.restype = i32
+        lib.oracle_transform_recurrent.argtypes = [i32] * 5 + [vp] * 5
+        lib.oracle_transform_recurrent.restype = i32
         for name in ("oracle_forward_f64", "oracle_forward_f32"):
             fn = getattr(lib, name)
             fn.argtypes = [i32] * 5 + [vp, vp, vp, i64, i32, vp, vp]
+            fn.restype = i32
+        for name in ("oracle_forward_recurrent_f64", "oracle_forward_recurrent_f32"):
+            fn = getattr(lib, name)
+            fn.argtypes = [i32] * 5 + [vp, vp, vp, i64, i32, i32, vp, vp]
             fn.restype = i32
         _lib = lib
     return _lib
@@ -81,21 +87,34 @@ def _check_genomes(nodes, conns, I, O):
     return nodes, conns
 
 
-def transform(nodes, conns, I: int, O: int):
+def transform(nodes, conns, I: int, O: int, recurrent: bool = False):
     """Transformation stage: returns (order [P,N_max] i32, level [P,N_max]
     i32, status [P] u32).  ``order`` lists node rows by (level, key), -1
-    padded; rejected genomes get all -1 rows."""
+    padded; rejected genomes get all -1 rows.  With ``recurrent`` cycles are
+    allowed (CYCLE is never set), every valid row has level 0 and the order
+    is plain key order."""
     nodes, conns = _check_genomes(nodes, conns, I, O)
     P, N, _ = nodes.shape
     C = conns.shape[1]
     order = np.empty((P, N), np.int32)
     level = np.empty((P, N), np.int32)
     status = np.empty((P,), np.uint32)
-    rc = _load().oracle_transform(P, N, C, I, O, _ptr(nodes), _ptr(conns),
-                                  _ptr(order), _ptr(level), _ptr(status))
+    fn = _load().oracle_transform_recurrent if recurrent else _load().oracle_transform
+    rc = fn(P, N, C, I, O, _ptr(nodes), _ptr(conns), _ptr(order), _ptr(level), _ptr(status))
     if rc != 0:
         raise RuntimeError("oracle_transform failed: %d" % rc)
     return order, level, status
+
+
+def _inputs(inputs, P, I, shared_inputs):
+    x = np.ascontiguousarray(inputs, dtype=np.float32)
+    if shared_inputs:
+        if x.ndim != 2 or x.shape[1] != I:
+            raise ValueError("shared inputs must be [B, I]")
+        return x, x.shape[0], 0
+    if x.ndim != 3 or x.shape[0] != P or x.shape[2] != I:
+        raise ValueError("inputs must be [P, B, I]")
+    return x, x.shape[1], x.shape[1] * I
 
 
 def forward(nodes, conns, inputs, I: int, O: int, shared_inputs=False,
@@ -106,34 +125,45 @@ def forward(nodes, conns, inputs, I: int, O: int, shared_inputs=False,
     Returns outputs [P, B, O] (float64 or float32) and, for f64 with
     ``with_beta``, beta [P, B, O]: a first-order bound on the error of an fp32
     evaluation of the same graph (inf where fp32 may overflow)."""
+    return _forward(nodes, conns, inputs, I, O, shared_inputs, precision, with_beta, None)
+
+
+def forward_recurrent(nodes, conns, inputs, I: int, O: int, K: int, shared_inputs=False,
+                      precision="f64", with_beta=True):
+    """Recurrent transformation + K synchronous sweeps (a reading; see
+    neat_oracle_forward.inc): v0 = inputs at the input keys, 0 elsewhere;
+    every sweep recomputes every non-input node from the previous sweep's
+    values; the outputs are the values after sweep K.  Returns as
+    ``forward``."""
+    if K < 0:
+        raise ValueError("K must be >= 0")
+    return _forward(nodes, conns, inputs, I, O, shared_inputs, precision, with_beta, K)
+
+
+def _forward(nodes, conns, inputs, I, O, shared_inputs, precision, with_beta, K):
     nodes, conns = _check_genomes(nodes, conns, I, O)
     P, N, _ = nodes.shape
     C = conns.shape[1]
-    x = np.ascontiguousarray(inputs, dtype=np.float32)
-    if shared_inputs:
-        if x.ndim != 2 or x.shape[1] != I:
-            raise ValueError("shared inputs must be [B, I]")
-        B, stride = x.shape[0], 0
-    else:
-        if x.ndim != 3 or x.shape[0] != P or x.shape[2] != I:
-            raise ValueError("inputs must be [P, B, I]")
-        B, stride = x.shape[1], x.shape[1] * I
+    x, B, stride = _inputs(inputs, P, I, shared_inputs)
     lib = _load()
+    rec = K is not None
+    extra = (K,) if rec else ()
     if precision == "f64":
+        fn = lib.oracle_forward_recurrent_f64 if rec else lib.oracle_forward_f64
         y = np.empty((P, B, O), np.float64)
         beta = np.empty((P, B, O), np.float64) if with_beta else None
-        rc = lib.oracle_forward_f64(P, N, C, I, O, _ptr(nodes), _ptr(conns),
-                                    _ptr(x), stride, B, _ptr(y),
-                                    _ptr(beta) if beta is not None else None)
+        rc = fn(P, N, C, I, O, _ptr(nodes), _ptr(conns), _ptr(x), stride, B, *extra, _ptr(y),
+                _ptr(beta) if beta is not None else None)
         if rc != 0:
-            raise RuntimeError("oracle_forward_f64 failed: %d" % rc)
+            raise RuntimeError("oracle forward (f64) failed: %d" % rc)
         return (y, beta) if with_beta else y
     if precision == "f32":
+        fn = lib.oracle_forward_recurrent_f32 if rec else lib.oracle_forward_f32
         y = np.empty((P, B, O), np.float32)
-        rc = lib.oracle_forward_f32(P, N, C, I, O, _ptr(nodes), _ptr(conns),
-                                    _ptr(x), stride, B, _ptr(y), None)
+        rc = fn(P, N, C, I, O, _ptr(nodes), _ptr(conns), _ptr(x), stride, B, *extra, _ptr(y),
+                None)
         if rc != 0:
-            raise RuntimeError("oracle_forward_f32 failed: %d" % rc)
+            raise RuntimeError("oracle forward (f32) failed: %d" % rc)
         return y
     raise ValueError("precision must be 'f64' or 'f32'")
 

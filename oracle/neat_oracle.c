@@ -37,7 +37,11 @@
  *     exp(-z^2), 6 abs; agg codes: 0 sum, 1 product, 2 max, 3 min, 4 mean.
  *     NaN propagates through every one of them (max/min/relu included);
  *   - incoming values are aggregated in ascending source-key order;
- *   - malformed genomes are flagged in a status bit-mask and produce NaN.
+ *   - malformed genomes are flagged in a status bit-mask and produce NaN;
+ *   - recurrent networks (Section 3.3 and Appendix A name them; only the
+ *     feedforward calculation is defined): cycles are allowed, the nodes keep
+ *     key order, and K synchronous sweeps update every non-input node from the
+ *     previous sweep's values, starting from the inputs and 0 elsewhere.
  *
  * Floating point: the reference arithmetic is IEEE double (oracle_forward_f64).
  * The same code is also instantiated in float (oracle_forward_f32) so the
@@ -111,7 +115,7 @@ static void genome_free(o_genome *g) {
  * checks that make the encoding of Section 3.1 well defined.
  */
 static int genome_transform(const float *nodes, const float *conns, int N_max,
-                            int C_max, int I, int O, o_genome *g) {
+                            int C_max, int I, int O, int recurrent, o_genome *g) {
     memset(g, 0, sizeof(*g));
     g->order = (int *)malloc(sizeof(int) * (size_t)N_max);
     g->level = (int *)malloc(sizeof(int) * (size_t)N_max);
@@ -162,7 +166,7 @@ static int genome_transform(const float *nodes, const float *conns, int N_max,
             continue;
         }
         if (nodes[d * NODE_W] < (float)I) st |= ST_INTO_INPUT;
-        if (s == d) st |= ST_CYCLE;
+        if (s == d && !recurrent) st |= ST_CYCLE;
         for (int e = 0; e < g->nedges; ++e)
             if (g->edges[e].src == s && g->edges[e].dst == d) st |= ST_DUP_EDGE;
         g->edges[g->nedges].src = s;
@@ -171,8 +175,14 @@ static int genome_transform(const float *nodes, const float *conns, int N_max,
         g->nedges++;
     }
 
-    /* 3. levels by level-synchronous Kahn, only for an otherwise clean genome */
-    if (st == 0) {
+    /* 3. levels by level-synchronous Kahn, only for an otherwise clean genome.
+     * A recurrent network has no levels: every valid node gets level 0, so
+     * the order below is plain key order. */
+    if (st == 0 && recurrent) {
+        for (int r = 0; r < N_max; ++r)
+            if (!isnan(nodes[r * NODE_W])) g->level[r] = 0;
+    }
+    if (st == 0 && !recurrent) {
         int *indeg = (int *)calloc((size_t)N_max, sizeof(int));
         char *emitted = (char *)calloc((size_t)N_max, 1);
         char *ready = (char *)calloc((size_t)N_max, 1);
@@ -241,16 +251,15 @@ static int check_dims(int P, int N_max, int C_max, int I, int O) {
     return 1;
 }
 
-/* Public: transformation of a whole population (order, level, status). */
-int oracle_transform(int P, int N_max, int C_max, int I, int O,
-                     const float *nodes, const float *conns, int32_t *order,
-                     int32_t *level, uint32_t *status) {
+static int transform_population(int P, int N_max, int C_max, int I, int O,
+                                const float *nodes, const float *conns, int recurrent,
+                                int32_t *order, int32_t *level, uint32_t *status) {
     if (!check_dims(P, N_max, C_max, I, O)) return ORACLE_E_INVALID;
     for (int p = 0; p < P; ++p) {
         o_genome g;
         int rc = genome_transform(nodes + (size_t)p * N_max * NODE_W,
                                   conns + (size_t)p * C_max * CONN_W, N_max,
-                                  C_max, I, O, &g);
+                                  C_max, I, O, recurrent, &g);
         if (rc != 0) {
             genome_free(&g);
             return rc;
@@ -263,6 +272,24 @@ int oracle_transform(int P, int N_max, int C_max, int I, int O,
         genome_free(&g);
     }
     return 0;
+}
+
+/* Public: transformation of a whole population (order, level, status). */
+int oracle_transform(int P, int N_max, int C_max, int I, int O,
+                     const float *nodes, const float *conns, int32_t *order,
+                     int32_t *level, uint32_t *status) {
+    return transform_population(P, N_max, C_max, I, O, nodes, conns, 0, order, level,
+                                status);
+}
+
+/* Public: the same checks for a recurrent network (cycles and self-loops are
+ * allowed, so CYCLE is never set); order is the valid rows in key order and
+ * level is 0 for every valid row. */
+int oracle_transform_recurrent(int P, int N_max, int C_max, int I, int O,
+                               const float *nodes, const float *conns, int32_t *order,
+                               int32_t *level, uint32_t *status) {
+    return transform_population(P, N_max, C_max, I, O, nodes, conns, 1, order, level,
+                                status);
 }
 
 /* Incoming edges of every row, each list sorted by ascending source key. */

@@ -27,7 +27,9 @@ and action sizes they take):
   connection density U[0.1, 0.6], seed 2;
 * ``served``: a pool of 128 populations for the request stream, seed 3;
 * ``cppn``: P=1000, I=5 (x1, y1, x2, y2, 1), O=1, N_max=30, C_max=120, CPPN
-  activations + sum, queried on all pairs of a 16x16 grid, seed 4.
+  activations + sum, queried on all pairs of a 16x16 grid, seed 4;
+* ``recurrent_control``: the control shapes with recurrent connections (any
+  pair into a non-input node, self-loops and cycles included), seed 5.
 """
 from __future__ import annotations
 
@@ -91,7 +93,7 @@ def make_genome(rng, N_max: int, C_max: int, I: int, O: int, n_hidden: int,
                 n_conns, acts: Sequence[int], aggs: Sequence[int],
                 p_enabled: float = P_ENABLED, outputs_last: bool = False,
                 nodes_out: Optional[np.ndarray] = None,
-                conns_out: Optional[np.ndarray] = None):
+                conns_out: Optional[np.ndarray] = None, recurrent: bool = False):
     """Draw one genome into NaN-filled ``nodes_out`` [N_max,5] and
     ``conns_out`` [C_max,4] (allocated when None).
 
@@ -99,7 +101,9 @@ def make_genome(rng, N_max: int, C_max: int, I: int, O: int, n_hidden: int,
     pairs to the number of connections to draw.  With ``outputs_last`` the
     topological permutation is hidden nodes first, then outputs (edges go
     from lower to higher generation index); otherwise it is random, so
-    outputs may feed hidden nodes."""
+    outputs may feed hidden nodes.  With ``recurrent`` every pair (input or
+    non-input -> non-input) is allowed, self-loops and both directions
+    included, so the enabled edges may form cycles."""
     assert I >= 1 and O >= 1 and I + O + n_hidden <= N_max
     nodes = nodes_out if nodes_out is not None else np.full((N_max, 5), np.nan, np.float32)
     conns = conns_out if conns_out is not None else np.full((C_max, 4), np.nan, np.float32)
@@ -123,7 +127,7 @@ def make_genome(rng, N_max: int, C_max: int, I: int, O: int, n_hidden: int,
                                np.arange(I, I + O)])
     else:
         topo = nonin[rng.permutation(M)]
-    n_allowed = I * M + M * (M - 1) // 2
+    n_allowed = I * M + (M * M if recurrent else M * (M - 1) // 2)
     K = n_conns(n_allowed) if callable(n_conns) else int(n_conns)
     K = max(0, min(K, n_allowed, C_max))
     if K:
@@ -133,10 +137,14 @@ def make_genome(rng, N_max: int, C_max: int, I: int, O: int, n_hidden: int,
         a = q < I * M
         src[a] = q[a] // M
         dst[a] = topo[q[a] % M]
-        iu, ju = _triu(M)
         qb = q[~a] - I * M
-        src[~a] = topo[iu[qb]]
-        dst[~a] = topo[ju[qb]]
+        if recurrent:
+            src[~a] = nonin[qb // M]
+            dst[~a] = nonin[qb % M]
+        else:
+            iu, ju = _triu(M)
+            src[~a] = topo[iu[qb]]
+            dst[~a] = topo[ju[qb]]
         crow = rng.choice(C_max, size=K, replace=False)
         conns[crow, 0] = src
         conns[crow, 1] = dst
@@ -147,7 +155,7 @@ def make_genome(rng, N_max: int, C_max: int, I: int, O: int, n_hidden: int,
 
 def make_population(rng, P: int, N_max: int, C_max: int, I: int, O: int,
                     hidden_max: int, conns_fn, acts, aggs,
-                    outputs_last: bool = False) -> Population:
+                    outputs_last: bool = False, recurrent: bool = False) -> Population:
     nodes = np.full((P, N_max, 5), np.nan, np.float32)
     conns = np.full((P, C_max, 4), np.nan, np.float32)
     hidden_max = min(hidden_max, N_max - I - O)
@@ -155,7 +163,7 @@ def make_population(rng, P: int, N_max: int, C_max: int, I: int, O: int,
         h = int(rng.integers(0, hidden_max + 1))
         make_genome(rng, N_max, C_max, I, O, h, lambda na: conns_fn(rng, na),
                     acts, aggs, outputs_last=outputs_last,
-                    nodes_out=nodes[p], conns_out=conns[p])
+                    nodes_out=nodes[p], conns_out=conns[p], recurrent=recurrent)
     return Population(nodes, conns, I, O)
 
 
@@ -190,6 +198,19 @@ def control(seed: int = 1, P: int = 10000, B: int = 1000,
     rng = np.random.default_rng(seed)
     pop = make_population(rng, P, 50, 200, 17, 6, 27, _k_uniform(200),
                           CONTROL_ACTS, ALL_AGGS)
+    if with_inputs:
+        pop.inputs = rng.standard_normal((P, B, 17), dtype=np.float32)
+    return pop
+
+
+def recurrent_control(seed: int = 5, P: int = 10000, B: int = 1000,
+                      with_inputs: bool = True) -> Population:
+    """The control-policy shapes (P=10000, I=17, O=6, N_max=50, C_max=200,
+    B=1000) with recurrent connections: any pair into a non-input node,
+    self-loops and cycles included."""
+    rng = np.random.default_rng(seed)
+    pop = make_population(rng, P, 50, 200, 17, 6, 27, _k_uniform(200),
+                          CONTROL_ACTS, ALL_AGGS, recurrent=True)
     if with_inputs:
         pop.inputs = rng.standard_normal((P, B, 17), dtype=np.float32)
     return pop
