@@ -64,10 +64,11 @@ def parse():
                     help="genomes of the workload the CPU oracle is timed on")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quiet", action="store_true")
-    ap.add_argument("--workloads", default="control,batched,served,cppn",
+    ap.add_argument("--workloads", default="control,batched,served,cppn,recurrent",
                     help="comma list: control (the headline line), batched (64 uneven "
                          "populations in one recorded batch), served (Poisson request "
-                         "stream over 128 resident populations), cppn (grid queries)")
+                         "stream over 128 resident populations), cppn (grid queries), "
+                         "recurrent (K sweeps of networks with cycles)")
     ap.add_argument("--served-seconds", type=float, default=20.0,
                     help="length of the served request stream (latency counted after "
                          "the first quarter)")
@@ -276,6 +277,69 @@ def bench_cppn(args, torch, neat, synth):
                          "flops_per_genome_input": round(flops / pop.P, 1)}}
 
 
+def bench_recurrent(args, torch, neat, synth):
+    """Recurrent networks: the control shapes with cycles (P=10000, N_max=50,
+    C_max=200, B=1000), K=4 synchronous sweeps; transformation + calculation
+    per step."""
+    dev = torch.device("cuda:0")
+    pop = synth.recurrent_control(P=args.P, B=args.B)
+    K = 4
+    tn = torch.from_numpy(pop.nodes).to(dev)
+    tc = torch.from_numpy(pop.conns).to(dev)
+    tx = torch.from_numpy(pop.inputs).to(dev)
+    d = neat.dims_of(tn, tc, pop.I, pop.O)
+    prog = torch.empty((neat.program_bytes(d) // 4,), dtype=torch.int32, device=dev)
+    out = torch.empty((pop.P, pop.B, pop.O), dtype=torch.float32, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        neat.topo_sort(tn, tc, pop.I, pop.O, program=prog, want_order=False, recurrent=True)
+        neat.forward_recurrent(d, prog, tx, pop.B, K, outputs=out)
+
+    for _ in range(max(1, args.warmup)):
+        step()
+    torch.cuda.synchronize()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        ev[k][0].record(stream)
+        neat.topo_sort(tn, tc, pop.I, pop.O, program=prog, want_order=False, recurrent=True)
+        ev[k][1].record(stream)
+        neat.forward_recurrent(d, prog, tx, pop.B, K, outputs=out)
+        ev[k][2].record(stream)
+    torch.cuda.synchronize()
+    step_ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    fwd_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in ev]))
+    topo_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in ev]))
+    units = pop.P * pop.B
+    # algorithmic work per genome-input: K sweeps of 2 flops per enabled
+    # connection plus 2 + the activation's per computed node
+    hdr = neat.program_headers(d, prog).cpu().numpy()
+    flops = 0
+    for g in range(pop.P):
+        if hdr[g, 2] != 0:
+            continue
+        nd = pop.nodes[g]
+        comp = (~np.isnan(nd[:, 0])) & (nd[:, 0] >= pop.I)
+        flops += 2 * int(hdr[g, 7]) + int(sum(2 + ACT_FLOPS[int(a)] for a in nd[comp, 3]))
+    flops *= K * pop.B
+    tflops = flops / (fwd_ms / 1e3) / 1e12
+    fwd_bytes = units * (pop.I + pop.O) * 4 + program_bytes_read(pop.O, hdr[:, 0], hdr[:, 7],
+                                                                 pop.I)
+    return {"workload": "recurrent control-policy population: P=%d, N_max=50, C_max=200, "
+                        "I=17, O=6, B=%d, cycles allowed, K=%d synchronous sweeps, "
+                        "transformation + calculation" % (pop.P, pop.B, K),
+            "ms_per_step": round(step_ms, 4), "topo_ms": round(topo_ms, 4),
+            "forward_ms": round(fwd_ms, 4),
+            "value": round(units / (step_ms / 1e3), 1), "unit": "genome-inputs/s",
+            "rejected_genomes": int((hdr[:, 2] != 0).sum()),
+            "roofline": {"kernel": "recurrent forward, LDS value columns", "bound": "alu",
+                         "achieved": round(tflops, 2), "peak": VALU_PEAK_TFLOPS,
+                         "unit": "TFLOP/s", "frac": round(tflops / VALU_PEAK_TFLOPS, 4),
+                         "flops_per_genome_input": round(flops / units, 1),
+                         "hbm_GBps": round(fwd_bytes / (fwd_ms / 1e3) / 1e9, 1)}}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -415,6 +479,8 @@ def main():
     batched = bench_batched(args, torch, neat, synth) if "batched" in workloads else None
     served = bench_served(args, torch, neat, synth) if "served" in workloads else None
     cppn = bench_cppn(args, torch, neat, synth) if "cppn" in workloads else None
+    recurrent = (bench_recurrent(args, torch, neat, synth) if "recurrent" in workloads
+                 else None)
 
     res = {
         "metric": "genome-input forwards/s", "value": round(value, 1),
@@ -435,6 +501,7 @@ def main():
         "batched": batched,
         "served": served,
         "cppn": cppn,
+        "recurrent": recurrent,
     }
     print(json.dumps(res), flush=True)
 

@@ -176,6 +176,43 @@ int neat_forward_grid(const neat_dims *dims, const void *program, int32_t side,
                       int64_t first, int32_t Q, float *outputs, void *stream);
 
 /*
+ * Recurrent networks.  The paper sorts networks into feedforward and
+ * recurrent ones by whether their graph has cycles (Section 3.3; Appendix A's
+ * network_type) and defines only the feedforward calculation; here a
+ * recurrent network is evaluated by K synchronous sweeps:
+ *   v0[input key i] = x_i, v0[every other node] = 0;
+ *   sweep t = 1..K: v_t[u] = act(bias + response * agg(w * v_{t-1}[src]))
+ *   for every non-input node u at once (in-edges in ascending source-key
+ *   order, agg of no edges = 0), inputs keep x;  y_j = v_K[key I + j].
+ *
+ * neat_topo_sort_recurrent: the checks and status bits of neat_topo_sort
+ * except that cycles and self-loops are allowed (CYCLE is never set); order
+ * lists the valid rows in key order, level is 0 for every valid row (-1 for
+ * absent rows, all -1 for rejected genomes); the program (same size,
+ * neat_program_bytes) holds one record per non-input node in key order and
+ * one value slot per node.  Arguments, ownership and errors as
+ * neat_topo_sort.
+ */
+int neat_topo_sort_recurrent(const neat_dims *dims, const float *nodes, const float *conns,
+                             int32_t *order, int32_t *level, uint32_t *status, void *program,
+                             void *stream);
+
+/*
+ * neat_forward_recurrent: K >= 0 sweeps over a program built by
+ * neat_topo_sort_recurrent for the same dims; inputs, input_genome_stride,
+ * B and outputs as neat_forward (NaN outputs for genomes with status != 0;
+ * K = 0 gives the initial values, 0).  The values of one sample live in
+ * LDS, twice (previous and current sweep): NEAT_E_TOO_LARGE when
+ * 4 * 64 * (I + 2 * slots) bytes exceed the device's LDS per workgroup,
+ * slots being N_max + 2 for N_max > 222 (so N_max up to about 300), else
+ * 64, 128 or 224.  Errors: NEAT_E_INVALID (dims, NULL pointers, K < 0, a
+ * stride below B * I), NEAT_E_TOO_LARGE, NEAT_E_HIP.
+ */
+int neat_forward_recurrent(const neat_dims *dims, const void *program, const float *inputs,
+                           int64_t input_genome_stride, int32_t B, int32_t K, float *outputs,
+                           void *stream);
+
+/*
  * Batched path: many populations in one call (the paper evaluates a whole
  * population as one tensor program, Section 3.3; this extends the batch
  * across populations of different shapes).  Each item is one population:

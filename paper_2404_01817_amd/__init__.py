@@ -15,7 +15,7 @@ from ._lib import (FWD_AUTO, FWD_LDS, FWD_REG, FWD_REG2, INPUT_GRID, INPUT_TENSO
                    Dims, NeatError, Request, Result, ServerCfg, Stats, check, lib)
 
 __all__ = ["Dims", "NeatError", "dims_of", "program_bytes", "topo_sort", "forward",
-           "forward_grid"]
+           "forward_grid", "forward_recurrent"]
 
 
 def _torch():
@@ -64,10 +64,12 @@ def program_headers(dims: Dims, program):
 
 
 def topo_sort(nodes, conns, I: int, O: int, program=None, stream=None,
-              want_order: bool = True):
+              want_order: bool = True, recurrent: bool = False):
     """Transformation stage.  nodes [P,N_max,5], conns [P,C_max,4] float32 on
     the GPU.  Returns (order, level, status, program) as device tensors
-    (order/level None unless ``want_order``)."""
+    (order/level None unless ``want_order``).  ``recurrent``: cycles allowed,
+    key order, a program for ``forward_recurrent``
+    (neat_topo_sort_recurrent)."""
     torch = _torch()
     _dev_f32(nodes, "nodes")
     _dev_f32(conns, "conns")
@@ -80,15 +82,13 @@ def topo_sort(nodes, conns, I: int, O: int, program=None, stream=None,
     status = torch.empty((d.P,), dtype=torch.int32, device=dev)
     if program is None:
         program = torch.empty((max(program_bytes(d), 4) // 4,), dtype=torch.int32, device=dev)
-    check(lib().neat_topo_sort(ctypes.byref(d), _ptr(nodes), _ptr(conns), _ptr(order),
-                               _ptr(level), _ptr(status), _ptr(program), _stream(stream)))
+    fn = lib().neat_topo_sort_recurrent if recurrent else lib().neat_topo_sort
+    check(fn(ctypes.byref(d), _ptr(nodes), _ptr(conns), _ptr(order), _ptr(level), _ptr(status),
+             _ptr(program), _stream(stream)))
     return order, level, status, program
 
 
-def forward(dims: Dims, program, inputs, B: int, shared_inputs: bool = False,
-            outputs=None, stream=None, variant: int = 0):
-    """Calculation stage.  inputs [P,B,I] (or [B,I] when shared) float32 on the
-    GPU; returns outputs [P,B,O]."""
+def _io(dims, inputs, B, shared_inputs, outputs):
     torch = _torch()
     _dev_f32(inputs, "inputs")
     if shared_inputs:
@@ -105,8 +105,26 @@ def forward(dims: Dims, program, inputs, B: int, shared_inputs: bool = False,
         _dev_f32(outputs, "outputs")
         if outputs.numel() < dims.P * B * dims.O:
             raise ValueError("outputs smaller than P * B * O")
+    return stride, outputs
+
+
+def forward(dims: Dims, program, inputs, B: int, shared_inputs: bool = False,
+            outputs=None, stream=None, variant: int = 0):
+    """Calculation stage.  inputs [P,B,I] (or [B,I] when shared) float32 on the
+    GPU; returns outputs [P,B,O]."""
+    stride, outputs = _io(dims, inputs, B, shared_inputs, outputs)
     check(lib().neat_forward_ex(ctypes.byref(dims), _ptr(program), _ptr(inputs), stride, B,
                                 _ptr(outputs), variant, _stream(stream)))
+    return outputs
+
+
+def forward_recurrent(dims: Dims, program, inputs, B: int, K: int,
+                      shared_inputs: bool = False, outputs=None, stream=None):
+    """K synchronous sweeps of a recurrent network (program from
+    ``topo_sort(..., recurrent=True)``); returns outputs [P,B,O]."""
+    stride, outputs = _io(dims, inputs, B, shared_inputs, outputs)
+    check(lib().neat_forward_recurrent(ctypes.byref(dims), _ptr(program), _ptr(inputs), stride,
+                                       B, K, _ptr(outputs), _stream(stream)))
     return outputs
 
 

@@ -199,6 +199,50 @@ int neat_forward(const neat_dims *d, const void *program, const float *inputs,
                            stream);
 }
 
+int neat_topo_sort_recurrent(const neat_dims *d, const float *nodes, const float *conns,
+                             int32_t *order, int32_t *level, uint32_t *status, void *program,
+                             void *stream) {
+    int rc = check_dims(d);
+    if (rc != NEAT_OK) return rc;
+    if (d->P == 0) return NEAT_OK;
+    rc = check_topo_args(d, nodes, conns, program);
+    if (rc != NEAT_OK) return rc;
+    hipError_t e = neat::launch_topo(d->P, d->N_max, d->C_max, d->I, d->O, nodes, conns, order,
+                                     level, status, (int32_t *)program, (hipStream_t)stream, 1);
+    if (e != hipSuccess) return hip_fail(e, "topo_sort_recurrent launch");
+    return NEAT_OK;
+}
+
+int neat_forward_recurrent(const neat_dims *d, const void *program, const float *inputs,
+                           int64_t input_genome_stride, int32_t B, int32_t K, float *outputs,
+                           void *stream) {
+    int rc = check_dims(d);
+    if (rc != NEAT_OK) return rc;
+    if (K < 0) return fail(NEAT_E_INVALID, "K = %d < 0", K);
+    rc = check_forward_args(d, program, inputs, input_genome_stride, B, outputs, false, 0, 0);
+    if (rc != NEAT_OK || d->P == 0 || B == 0) return rc;
+    const size_t lds = neat::recurrent_lds_bytes(d->N_max, d->I);
+    if (lds > max_lds_bytes())
+        return fail(NEAT_E_TOO_LARGE,
+                    "recurrent forward with N_max=%d, I=%d needs %zu B of LDS per wave, device "
+                    "allows %zu",
+                    d->N_max, d->I, lds, max_lds_bytes());
+    neat::RecLaunch L{};
+    L.prog = (const int32_t *)program;
+    L.inputs = inputs;
+    L.outputs = outputs;
+    L.gstride = input_genome_stride;
+    L.prog_words = neat::prog_words(d->N_max, d->C_max, d->O);
+    L.P = d->P, L.N = d->N_max, L.I = d->I, L.O = d->O, L.B = B, L.K = K;
+    L.tiles = (B + 63) / 64;
+    L.rows = neat::class_slots(neat::max_class(d->N_max), d->N_max);
+    L.stage_floats = 64 * d->I;
+    L.vec4 = (aligned(inputs, 16) && input_genome_stride % 4 == 0) ? 1 : 0;
+    hipError_t e = neat::recurrent_launch(L, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "forward_recurrent launch");
+    return NEAT_OK;
+}
+
 int neat_forward_grid(const neat_dims *d, const void *program, int32_t side, int64_t first,
                       int32_t Q, float *outputs, void *stream) {
     return forward_common(d, program, nullptr, 0, Q, outputs, NEAT_FWD_AUTO, true, side, first,

@@ -192,7 +192,10 @@ __device__ __forceinline__ float activation(int act, float z) {
     }
 }
 
-__device__ __forceinline__ void run_program(cprog_t *prog, int N, int O, int I, LdsStore &v) {
+// Every computed node of the program in record order; the aggregations read
+// src and the results go to dst (the same store for a feedforward network).
+__device__ __forceinline__ void run_program(cprog_t *prog, int N, int O, int I,
+                                            const LdsStore &src, LdsStore &dst) {
     const int ncomp = prog[HDR_NVALID] - I;
     if (ncomp <= 0) return;
     cprog_t *rec = prog + rec_off(O);
@@ -203,16 +206,16 @@ __device__ __forceinline__ void run_program(cprog_t *prog, int N, int O, int I, 
         const int pairs = (int)(np & (unsigned)REC_NPAIRS_MASK);
         const int acls = slot_class((int)(np >> REC_FIELD_SHIFT));
         const int act = (int)(code >> REC_FIELD_SHIFT);
-        const int dst = (int)(code & (unsigned)REC_DST_MASK);
+        const int slot = (int)(code & (unsigned)REC_DST_MASK);
         const float bias = fbits(r[REC_BIAS]), resp = fbits(r[REC_RESP]);
         // next record (the record array has room for N records)
         const i32x16 rn = *(cint16_t *)(rec + REC_WORDS * (k + 1));
         float a;
-        if (acls == ACLS_PROD) a = aggregate<ACLS_PROD>(r, e, pairs, v);
-        else if (acls == ACLS_MAX) a = aggregate<ACLS_MAX>(r, e, pairs, v);
-        else a = pairs == 0 ? 0.0f : aggregate<ACLS_SUM>(r, e, pairs, v);
+        if (acls == ACLS_PROD) a = aggregate<ACLS_PROD>(r, e, pairs, src);
+        else if (acls == ACLS_MAX) a = aggregate<ACLS_MAX>(r, e, pairs, src);
+        else a = pairs == 0 ? 0.0f : aggregate<ACLS_SUM>(r, e, pairs, src);
         if (pairs > REC_INLINE_PAIRS) e += 4 * (pairs - REC_INLINE_PAIRS);
-        v.set<0>(dst, activation(act, fmaf(resp, a, bias)));
+        dst.set<0>(slot, activation(act, fmaf(resp, a, bias)));
         r = rn;
     }
 }
@@ -455,9 +458,56 @@ __device__ __forceinline__ void forward_unit_lds(citem_t *it, int g, int chunk, 
                            vec4);
             }
         }
-        run_program(prog, N, O, I, v);
+        run_program(prog, N, O, I, v, v);
         if (lane < nb) store_outputs<0>(v, prog, out_g + (size_t)(t * TS + lane) * O, O);
     }
+}
+
+// ---------------------------------------------------------------- recurrent
+// Recurrent networks (read as K synchronous sweeps; the program comes from
+// the recurrent transformation: records in key order, one slot per node).
+// One wave per (genome, tile of 64 samples).  The lane's values live in two
+// LDS columns, the previous sweep's (cur) and the one being written (nxt),
+// which swap after every sweep: v0 = the inputs at slots 0..I-1 and 0 at
+// the other nodes; every sweep runs all records reading cur and writing nxt.
+__global__ __launch_bounds__(WAVE) void recurrent_kernel(RecLaunch L) {
+    extern __shared__ float smem[];
+    const long long u = xcd_item(blockIdx.x, gridDim.x);
+    if (u >= (long long)L.P * L.tiles) return;
+    const int g = (int)(u / L.tiles), t = (int)(u - (long long)g * L.tiles);
+    const int lane = (int)(threadIdx.x & (WAVE - 1));
+    const int I = L.I, O = L.O, N = L.N;
+    cprog_t *prog = (cprog_t *)(L.prog + (size_t)g * L.prog_words);
+    float *out_g = L.outputs + (size_t)g * L.B * O;
+    const int s0 = t * WAVE, nb = min(WAVE, L.B - s0);
+    if (prog[HDR_STATUS] != 0) {
+        fill_nan(out_g, s0, s0 + nb, O);
+        return;
+    }
+    float *stage = smem;
+    dma_inputs(L.inputs + (size_t)g * L.gstride + (size_t)s0 * I, stage, nb * I, L.vec4);
+    LdsStore cur, nxt;
+    cur.col = smem + L.stage_floats + lane;
+    nxt.col = cur.col + (size_t)L.rows * WAVE;
+    const int nvalid = prog[HDR_NVALID];
+    for (int s = I; s < nvalid; ++s) cur.set<0>(s, 0.0f);
+    cur.init(zero_slot(prog[HDR_CLASS], N));
+    nxt.init(zero_slot(prog[HDR_CLASS], N));
+    wait_dma();
+    // lanes past the tile's last sample read stale staging words; their
+    // results are never stored
+    for (int i = 0; i < I; ++i) {
+        const float x = stage[lane * I + i];
+        cur.set<0>(i, x);
+        nxt.set<0>(i, x);
+    }
+    for (int k = 0; k < L.K; ++k) {
+        run_program(prog, N, O, I, cur, nxt);
+        float *c = cur.col;
+        cur.col = nxt.col;
+        nxt.col = c;
+    }
+    if (lane < nb) store_outputs<0>(cur, prog, out_g + (size_t)(s0 + lane) * O, O);
 }
 
 // Item holding unit u (items sorted by unit0; the first has unit0 = 0).
@@ -656,6 +706,18 @@ int forward_plan(const FwdJob *jobs, int n, int variant, size_t max_lds,
         out.push_back(K);
     }
     return NEAT_OK;
+}
+
+size_t recurrent_lds_bytes(int N, int I) {
+    return sizeof(float) * (size_t)WAVE * ((size_t)I + 2 * (size_t)class_slots(max_class(N), N));
+}
+
+hipError_t recurrent_launch(const RecLaunch &L, hipStream_t stream) {
+    const long long blocks = (long long)L.P * L.tiles;
+    if (blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL(recurrent_kernel, dim3((unsigned)blocks), dim3(WAVE),
+                       recurrent_lds_bytes(L.N, L.I), stream, L);
+    return hipGetLastError();
 }
 
 hipError_t forward_launch(const FwdKernelLaunch &k, const FwdItem *dev_items, hipStream_t stream) {

@@ -18,10 +18,12 @@ int topo_block_threads(int N);
 
 hipError_t launch_topo(int P, int N, int C, int I, int O, const float *nodes,
                        const float *conns, int32_t *order, int32_t *level,
-                       uint32_t *status, int32_t *prog, hipStream_t stream);
+                       uint32_t *status, int32_t *prog, hipStream_t stream,
+                       int recurrent = 0);
 
 // One population of a transformation launch; workgroups block0 ..
-// block0 + P - 1 of a batched launch transform its genomes.
+// block0 + P - 1 of a batched launch transform its genomes.  recurrent:
+// cycles allowed, nodes in key order, one value slot per node.
 struct TopoItem {
     const float *nodes;
     const float *conns;
@@ -31,6 +33,7 @@ struct TopoItem {
     int32_t *prog;
     int P, N, C, I, O, prog_words;
     long long block0;
+    int recurrent;
 };
 
 // Transformation of many populations in one launch (items in device memory,
@@ -106,5 +109,18 @@ int forward_plan(const FwdJob *jobs, int n, int variant, size_t max_lds,
 // Launch one planned kernel.  dev_items: the launch's items in device memory
 // (may be nullptr when the launch has a single item, passed inline).
 hipError_t forward_launch(const FwdKernelLaunch &k, const FwdItem *dev_items, hipStream_t stream);
+
+// Recurrent calculation: K synchronous sweeps, one wave per (genome, tile of
+// 64 samples), rows = class_slots(max_class(N), N) LDS rows per value
+// column, stage_floats = 64 I.
+struct RecLaunch {
+    const int32_t *prog;
+    const float *inputs;
+    float *outputs;
+    long long gstride;
+    int prog_words, P, N, I, O, B, K, tiles, rows, stage_floats, vec4;
+};
+size_t recurrent_lds_bytes(int N, int I);
+hipError_t recurrent_launch(const RecLaunch &L, hipStream_t stream);
 
 }  // namespace neat

@@ -335,7 +335,7 @@ __device__ __forceinline__ void topo_genome(const TopoItem &a, size_t g, const G
                     st |= NEAT_ST_BAD_REF;
                 } else {
                     if (s_key[d] < I) st |= NEAT_ST_INTO_INPUT;
-                    if (s == d) st |= NEAT_ST_CYCLE;
+                    if (s == d && !a.recurrent) st |= NEAT_ST_CYCLE;
                     src = s;
                     dst = d;
                     atomicAdd(&s_indeg[d], 1);
@@ -394,11 +394,18 @@ __device__ __forceinline__ void topo_genome(const TopoItem &a, size_t g, const G
     unsigned status = s_status;
     const int nvalid = s_nvalid;
 
-    // ---- 5. level-synchronous Kahn over key ranks
+    // ---- 5. level-synchronous Kahn over key ranks (a recurrent network has
+    // no order to find: every node takes its key rank as position, level 0)
     int n_levels = 0;
     int my_level = -1;
     const int my_row = (status == 0u && t < nvalid) ? s_srow[t] : -1;
-    if (status == 0u) {
+    if (status == 0u && a.recurrent) {
+        if (my_row >= 0) {
+            s_pos[my_row] = t;
+            my_level = 0;
+        }
+        n_levels = nvalid > 0 ? 1 : 0;
+    } else if (status == 0u) {
         const int lane = G.lane, wave = G.wave, nw = G.nw;
         bool emitted = false;
         int base = 0;
@@ -470,8 +477,9 @@ __device__ __forceinline__ void topo_genome(const TopoItem &a, size_t g, const G
         s_last[t] = last;
     }
     gsync(G);
-    if (max_class(N) == CLS_R64) {
-        // every genome fits the 64-slot class: slot = position
+    if (max_class(N) == CLS_R64 || a.recurrent) {
+        // every genome fits the 64-slot class, or every value stays live
+        // from one sweep to the next: slot = position
         if (t < nvalid) s_slot[s_curi[t]] = t;
         if (t == 0) s_used = nvalid;
     } else {
@@ -802,8 +810,9 @@ int topo_block_threads(int N) {
 
 hipError_t launch_topo(int P, int N, int C, int I, int O, const float *nodes,
                        const float *conns, int32_t *order, int32_t *level,
-                       uint32_t *status, int32_t *prog, hipStream_t stream) {
-    TopoItem a{nodes, conns, order, level, status, prog, P, N, C, I, O, prog_words(N, C, O), 0};
+                       uint32_t *status, int32_t *prog, hipStream_t stream, int recurrent) {
+    TopoItem a{nodes,   conns, order, level, status, prog, P, N, C, I, O, prog_words(N, C, O),
+               0,       recurrent ? 1 : 0};
     const size_t L = topo_lds_bytes(N, C);
     if (P > 0) {
         const dim3 grid((unsigned)P), block((unsigned)topo_block_threads(N));
