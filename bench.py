@@ -333,7 +333,8 @@ def bench_recurrent(args, torch, neat, synth):
             "forward_ms": round(fwd_ms, 4),
             "value": round(units / (step_ms / 1e3), 1), "unit": "genome-inputs/s",
             "rejected_genomes": int((hdr[:, 2] != 0).sum()),
-            "roofline": {"kernel": "recurrent forward, LDS value columns", "bound": "alu",
+            "roofline": {"kernel": "recurrent forward, 64-slot register store (read and "
+                                   "write vectors)", "bound": "alu",
                          "achieved": round(tflops, 2), "peak": VALU_PEAK_TFLOPS,
                          "unit": "TFLOP/s", "frac": round(tflops / VALU_PEAK_TFLOPS, 4),
                          "flops_per_genome_input": round(flops / units, 1),

@@ -221,6 +221,21 @@ int neat_forward_recurrent(const neat_dims *d, const void *program, const float 
     if (K < 0) return fail(NEAT_E_INVALID, "K = %d < 0", K);
     rc = check_forward_args(d, program, inputs, input_genome_stride, B, outputs, false, 0, 0);
     if (rc != NEAT_OK || d->P == 0 || B == 0) return rc;
+    if (neat::max_class(d->N_max) == neat::CLS_R64) {
+        // every genome fits the 64-slot register store
+        neat::FwdJob job = make_job(d, program, inputs, input_genome_stride, B, outputs, 0, 0);
+        job.recurrent = 1;
+        job.sweeps = K;
+        std::vector<neat::FwdKernelLaunch> plan;
+        char err[256] = "";
+        rc = neat::forward_plan(&job, 1, NEAT_FWD_AUTO, max_lds_bytes(), plan, err, sizeof(err));
+        if (rc != NEAT_OK) return fail(rc, "%s", err);
+        for (const neat::FwdKernelLaunch &k : plan) {
+            hipError_t e = neat::forward_launch(k, nullptr, (hipStream_t)stream);
+            if (e != hipSuccess) return hip_fail(e, "forward_recurrent launch");
+        }
+        return NEAT_OK;
+    }
     const size_t lds = neat::recurrent_lds_bytes(d->N_max, d->I);
     if (lds > max_lds_bytes())
         return fail(NEAT_E_TOO_LARGE,

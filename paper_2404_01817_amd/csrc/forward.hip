@@ -93,12 +93,14 @@ struct LdsStore {
     [rec] "s"(rec), [edg] "s"(edg), [n] "s"(n), [zs] "s"(zs), [ni] "s"(ni), [dm0] "s"(dm0),  \
         [dn] "s"(dn), [dvec] "s"(dvec), [dsrc] "s"(dsrc), [lane] "v"(lane),                 \
         [outs] "s"(outs), [no] "s"(no), [om0] "s"(om0)
-#define NEAT_TILE_FN(TILE, CLOB)                                                          \
+// EXTRA: more operands (the recurrent block's sweep count), or nothing
+#define NEAT_NSW_OPERAND , [nsw] "s"(nsw)
+#define NEAT_TILE_FN(TILE, CLOB, EXTRA)                                                   \
     __device__ __forceinline__ static void tile(const int32_t *rec, const int32_t *edg,   \
                                                 int n, int zs, int ni, unsigned dm0,      \
                                                 int dn, int dvec, const float *dsrc,      \
                                                 unsigned lane, const int32_t *outs, int no, \
-                                                unsigned om0) {                           \
+                                                unsigned om0, int nsw) {                  \
         n = __builtin_amdgcn_readfirstlane(n);                                            \
         zs = __builtin_amdgcn_readfirstlane(zs);                                          \
         ni = __builtin_amdgcn_readfirstlane(ni);                                          \
@@ -107,7 +109,8 @@ struct LdsStore {
         om0 = __builtin_amdgcn_readfirstlane(om0);                                        \
         dn = __builtin_amdgcn_readfirstlane(dn);                                          \
         dvec = __builtin_amdgcn_readfirstlane(dvec);                                      \
-        asm volatile(TILE : : NEAT_TILE_OPERANDS : CLOB, "memory");                     \
+        nsw = __builtin_amdgcn_readfirstlane(nsw);                                        \
+        asm volatile(TILE : : NEAT_TILE_OPERANDS EXTRA : CLOB, "memory");               \
     }
 
 template <int K>
@@ -115,22 +118,27 @@ struct AsmTile;
 template <>
 struct AsmTile<KIND_R64> {
     static constexpr int SPL = 1;
-    NEAT_TILE_FN(NEAT_TILE_S1_64, NEAT_CLOB_S1_64)
+    NEAT_TILE_FN(NEAT_TILE_S1_64, NEAT_CLOB_S1_64, )
 };
 template <>
 struct AsmTile<KIND_R64X2> {
     static constexpr int SPL = 2;
-    NEAT_TILE_FN(NEAT_TILE_S2_64, NEAT_CLOB_S2_64)
+    NEAT_TILE_FN(NEAT_TILE_S2_64, NEAT_CLOB_S2_64, )
 };
 template <>
 struct AsmTile<KIND_R128> {
     static constexpr int SPL = 1;
-    NEAT_TILE_FN(NEAT_TILE_S1_128, NEAT_CLOB_S1_128)
+    NEAT_TILE_FN(NEAT_TILE_S1_128, NEAT_CLOB_S1_128, )
 };
 template <>
 struct AsmTile<KIND_R224> {
     static constexpr int SPL = 1;
-    NEAT_TILE_FN(NEAT_TILE_S1_224, NEAT_CLOB_S1_224)
+    NEAT_TILE_FN(NEAT_TILE_S1_224, NEAT_CLOB_S1_224, )
+};
+template <>
+struct AsmTile<KIND_R64REC> {
+    static constexpr int SPL = 1;
+    NEAT_TILE_FN(NEAT_TILE_S1_64R, NEAT_CLOB_S1_64R, NEAT_NSW_OPERAND)
 };
 
 // ---------------------------------------------------------------- nodes (C++)
@@ -418,7 +426,8 @@ __device__ __forceinline__ void forward_unit_reg(citem_t *it, int g, int chunk, 
             dn = dvec ? nf >> 2 : nf;
             dsrc = in_g + (size_t)(t + 1) * TS * I;
         }
-        AsmTile<K>::tile(rec, edg, ncomp, zs, I, ibase, dn, dvec, dsrc, lane, outs, O, obase);
+        AsmTile<K>::tile(rec, edg, ncomp, zs, I, ibase, dn, dvec, dsrc, lane, outs, O, obase,
+                         it->sweeps);
     }
     flush_outputs(ostage, out_g + (size_t)(t1 - 1) * TS * O, (min(B, t1 * TS) - (t1 - 1) * TS) * O);
 }
@@ -615,7 +624,7 @@ int kind_of(int variant, int cls, int B) {
 }  // namespace
 
 const char *kind_name(int kind) {
-    static const char *names[] = {"r64", "r64x2", "r128", "r224", "lds"};
+    static const char *names[] = {"r64", "r64x2", "r128", "r224", "lds", "r64rec"};
     return kind >= 0 && kind < N_KINDS ? names[kind] : "?";
 }
 
@@ -637,11 +646,12 @@ int forward_plan(const FwdJob *jobs, int n, int variant, size_t max_lds,
         if (J.P == 0 || J.B == 0) continue;
         const int top = max_class(J.N);
         // FWD_LDS takes every genome in one pass over all genomes; the other
-        // variants take class c's genomes with class c's kernel
-        const int c_lo = variant == FWD_LDS ? -1 : 0;
-        const int c_hi = variant == FWD_LDS ? -1 : top;
+        // variants take class c's genomes with class c's kernel; a recurrent
+        // job (N_max <= 62) takes every genome with the recurrent kernel
+        const int c_lo = (variant == FWD_LDS || J.recurrent) ? -1 : 0;
+        const int c_hi = (variant == FWD_LDS || J.recurrent) ? -1 : top;
         for (int c = c_lo; c <= c_hi; ++c) {
-            const int kind = kind_of(variant, c < 0 ? CLS_LDS : c, J.B);
+            const int kind = J.recurrent ? KIND_R64REC : kind_of(variant, c < 0 ? CLS_LDS : c, J.B);
             FwdItem it{};
             it.prog = J.prog;
             it.inputs = J.inputs;
@@ -653,6 +663,7 @@ int forward_plan(const FwdJob *jobs, int n, int variant, size_t max_lds,
             it.cls = (c < 0 || top == CLS_R64) ? -1 : c;
             it.P = J.P, it.N = J.N, it.I = J.I, it.O = J.O, it.B = J.B, it.side = J.side;
             it.prog_words = prog_words(J.N, J.C, J.O);
+            it.sweeps = J.recurrent ? J.sweeps : 0;
             const int TS = WAVE * samples_per_lane(kind);
             it.tiles = (J.B + TS - 1) / TS;
             it.chunks = choose_chunks(J.P, it.tiles, &it.tpw);
@@ -747,6 +758,7 @@ hipError_t forward_launch(const FwdKernelLaunch &k, const FwdItem *dev_items, hi
     case KIND_R64X2: NEAT_LAUNCH(KIND_R64X2) break;
     case KIND_R128: NEAT_LAUNCH(KIND_R128) break;
     case KIND_R224: NEAT_LAUNCH(KIND_R224) break;
+    case KIND_R64REC: NEAT_LAUNCH2(KIND_R64REC, false) break;
     default: NEAT_LAUNCH(KIND_LDS) break;
     }
 #undef NEAT_LAUNCH

@@ -20,6 +20,8 @@ Variants (name: samples per lane, value slots, VGPRs of the value vectors):
   S2_64   2 samples, 64 slots,  v0..v63 (first) and v64..v127 (second)
   S1_128  1 sample, 128 slots,  v0..v127
   S1_224  1 sample, 224 slots,  v0..v223
+  S1_64R  1 sample,  64 slots,  v0..v63 read and v64..v127 written: the
+          recurrent calculation, %[nsw] synchronous sweeps of the node loop
 Scratch VGPRs follow the value vectors.
 
 Run as ``python gen_node_loop.py`` to rewrite node_loop_asm.h next to it;
@@ -31,11 +33,13 @@ import os
 import sys
 
 VARIANTS = [
-    # name, samples per lane, value-vector bases, first scratch VGPR
-    ("S1_64", 1, (0,), 64),
-    ("S2_64", 2, (0, 64), 128),
-    ("S1_128", 1, (0,), 128),
-    ("S1_224", 1, (0,), 224),
+    # name, samples per lane, value-vector bases, first scratch VGPR, and for
+    # the recurrent variant the base of the vector the sweep writes
+    ("S1_64", 1, (0,), 64, None),
+    ("S2_64", 2, (0, 64), 128, None),
+    ("S1_128", 1, (0,), 128, None),
+    ("S1_224", 1, (0,), 224, None),
+    ("S1_64R", 1, (0,), 128, (64,)),
 ]
 
 # scalar register map (shared by all variants)
@@ -88,9 +92,12 @@ class Regs:
     # full-size repeatability tests).
     ROLES = ("acc", "ta", "tb", "z", "p")
 
-    def __init__(self, spl, bases, scratch, group=8):
+    def __init__(self, spl, bases, scratch, wbases=None, group=8):
         self.spl = spl
         self.bases = ["v%d" % b for b in bases]
+        # recurrent: reads from v[bases], writes to v[wbases]
+        self.rec = wbases is not None
+        self.wbases = ["v%d" % b for b in (wbases if self.rec else bases)]
         self.names = {}
         for k, role in enumerate(self.ROLES[:4]):
             self.names[role] = ["v%d" % (scratch + k * spl + h) for h in range(spl)]
@@ -123,6 +130,7 @@ def per_sample(R, fmt):
     for h in range(R.spl):
         d = {k: v[h] for k, v in R.names.items()}
         d["val"] = R.bases[h]
+        d["wval"] = R.wbases[h]
         out.append(fmt.format(**d))
     return out
 
@@ -367,7 +375,7 @@ def act_blocks(R, rec, orec, obase, shift):
         # v[dst] = y (GPR-index mode uses the low 8 bits of the code word:
         # the destination slot); next node, once its record is in
         body += ["s_set_gpr_idx_on %s, gpr_idx(DST)" % CODE]
-        body += per_sample(R, "v_mov_b32_e32 {val}, {%s}" % y)
+        body += per_sample(R, "v_mov_b32_e32 {wval}, {%s}" % y)
         body += ["s_set_gpr_idx_off", "s_waitcnt lgkmcnt(0)"]
         body += jump(orec[3], obase, shift)
         blocks.append(body)
@@ -472,9 +480,10 @@ def place_inputs(R):
     out += ["s_waitcnt lgkmcnt(0)",
             "s_set_gpr_idx_on s40, gpr_idx(DST)"]
     for h in range(R.spl):
-        base = int(R.bases[h][1:])
-        for k in range(8):
-            out.append("v_mov_b32_e32 v%d, %s" % (base + k, R.buf[h][k]))
+        for vb in sorted(set([R.bases[h], R.wbases[h]])):
+            base = int(vb[1:])
+            for k in range(8):
+                out.append("v_mov_b32_e32 v%d, %s" % (base + k, R.buf[h][k]))
     out += ["s_set_gpr_idx_off",
             "s_add_u32 s40, s40, 8",
             "s_cmp_lt_u32 s40, %[ni]",
@@ -483,8 +492,9 @@ def place_inputs(R):
             # the constants 0 and 1 at the zero slot
             "s_set_gpr_idx_on %[zs], gpr_idx(DST)"]
     for h in range(R.spl):
-        base = int(R.bases[h][1:])
-        out += ["v_mov_b32_e32 v%d, 0" % base, "v_mov_b32_e32 v%d, 1.0" % (base + 1)]
+        for vb in sorted(set([R.bases[h], R.wbases[h]])):
+            base = int(vb[1:])
+            out += ["v_mov_b32_e32 v%d, 0" % base, "v_mov_b32_e32 v%d, 1.0" % (base + 1)]
     out += ["s_set_gpr_idx_off"]
     return out
 
@@ -564,7 +574,54 @@ def write_outputs(R):
     return out
 
 
+def zero_values(R):
+    """Recurrent variant: v0 = 0 at every slot of the read vector (the inputs
+    and constants are placed after)."""
+    base = int(R.bases[0][1:])
+    return ["v_mov_b32_e32 v%d, 0" % (base + k) for k in range(64)]
+
+
+def sweeps(R):
+    """Recurrent variant: %[nsw] sweeps of the node loop, each reading the
+    previous sweep's values (read vector) and writing the write vector, then
+    copying the write vector into the read vector (inputs and constants are
+    in both, so the copy keeps them)."""
+    rb, wb = int(R.bases[0][1:]), int(R.wbases[0][1:])
+    out = ["s_mov_b32 s91, %[nsw]",
+           "Lsw%=:",
+           "s_cmp_eq_u32 s91, 0",
+           "s_cbranch_scc1 Lsw_done%="]
+    out += node_loop(R)
+    out += ["v_mov_b32_e32 v%d, v%d" % (rb + k, wb + k) for k in range(64)]
+    out += ["s_sub_u32 s91, s91, 1",
+            "s_branch Lsw%=",
+            "Lsw_done%=:"]
+    return out
+
+
+def clear_past_inputs(R):
+    """Recurrent variant: place_inputs writes whole groups of eight, so the
+    read vector's slots from %[ni] up to the next multiple of eight (below
+    64) hold staging words; set them back to 0 (before the constants)."""
+    base = int(R.bases[0][1:])
+    return ["s_mov_b32 s41, %[ni]",
+            "Lcl%=:",
+            "s_and_b32 s40, s41, 7",
+            "s_cbranch_scc0 Lcl_done%=",
+            "s_set_gpr_idx_on s41, gpr_idx(DST)",
+            "v_mov_b32_e32 v%d, 0" % base,
+            "s_set_gpr_idx_off",
+            "s_add_u32 s41, s41, 1",
+            "s_branch Lcl%=",
+            "Lcl_done%=:"]
+
+
 def tile(R):
+    if R.rec:
+        pl = place_inputs(R)
+        k = pl.index("Lpl_done%=:") + 1
+        return (["s_mov_b32 s90, m0"] + zero_values(R) + pl[:k] + clear_past_inputs(R)
+                + pl[k:] + dma_next(R) + sweeps(R) + write_outputs(R) + ["s_mov_b32 m0, s90"])
     return (["s_mov_b32 s90, m0"] + place_inputs(R) + dma_next(R) + node_loop(R)
             + write_outputs(R) + ["s_mov_b32 m0, s90"])
 
@@ -630,8 +687,8 @@ def c_string(lines_):
 
 def generate():
     parts = [HEADER]
-    for name, spl, bases, scratch in VARIANTS:
-        R = Regs(spl, bases, scratch)
+    for name, spl, bases, scratch, wbases in VARIANTS:
+        R = Regs(spl, bases, scratch, wbases)
         body = tile(R)
         parts.append("// %s: %d sample(s) per lane, value vectors at %s, scratch v%d..v%d\n"
                      % (name, spl, ", ".join("v%d" % b for b in bases), scratch, R.last))

@@ -50,7 +50,9 @@ constexpr int FWD_LDS = 2;   // every genome in LDS rows
 constexpr int FWD_REG2 = 3;  // as FWD_REG, R64 genomes two samples per lane
 
 // Forward kernels, one per value store.
-enum FwdKind { KIND_R64 = 0, KIND_R64X2, KIND_R128, KIND_R224, KIND_LDS, N_KINDS };
+// KIND_R64REC: the recurrent calculation (K synchronous sweeps) with the
+// 64-slot register store, for populations of N_max <= 62.
+enum FwdKind { KIND_R64 = 0, KIND_R64X2, KIND_R128, KIND_R224, KIND_LDS, KIND_R64REC, N_KINDS };
 constexpr int FWD_MAX_WAVES = 4;  // waves per workgroup
 
 // One population of a forward call.
@@ -62,6 +64,8 @@ struct FwdJob {
     int64_t first;        // grid mode: first query
     int P, N, C, I, O, B;
     int side;             // > 0: grid mode (CPPN queries generated in the kernel)
+    int recurrent;        // 1: a recurrent program, sweeps synchronous sweeps
+    int sweeps;
 };
 
 // One population in one forward kernel (device-visible, read with scalar
@@ -76,6 +80,7 @@ struct FwdItem {
     long long gstride, first, unit0;
     int P, N, I, O, B, side, vec4, cls;
     int tiles, tpw, chunks, prog_words;
+    int sweeps;  // recurrent kernel: sweeps per sample
 };
 
 // Kernel argument: one item inline, or a device table of items.
