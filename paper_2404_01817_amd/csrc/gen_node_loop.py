@@ -673,6 +673,11 @@ HEADER = """\
 // write of v[dst] and the jump to the next node.  The C++ node loop of the
 // LDS store performs the same operations in the same order.
 //
+// The recurrent block (NEAT_TILE_S1_64R) zeroes the read vector v0..v63,
+// places the inputs and constants in it and in the write vector v64..v127,
+// then runs the node loop %[nsw] times: every sweep reads v0.. and writes
+// v64.., and 64 moves copy the write vector back (s91 counts the sweeps).
+//
 // Hazards: a transcendental's result is read no sooner than one instruction
 // later (with two samples the other sample's instruction sits between); a
 // write of M0 is followed by one wait state before the LDS DMA reads it.

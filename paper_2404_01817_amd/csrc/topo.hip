@@ -23,6 +23,10 @@
 //      then the program (program.h): records in topological order, in-edges
 //      sorted by source key, source slots, level starts.
 //
+// In recurrent mode (networks with cycles, evaluated by synchronous sweeps)
+// self-loops are not flagged, step 5 is skipped (position = key rank, level
+// 0) and step 6 gives every node its own slot (position).
+//
 // classify_kernel then lists the genomes of a population by slot class.
 #include <hip/hip_runtime.h>
 
