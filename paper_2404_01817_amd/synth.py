@@ -252,28 +252,40 @@ def served_pool(seed: int = 3, n_pops: int = 128, P_range=(64, 8192),
 GRID_SIDE = 16
 
 
-def grid_coords() -> np.ndarray:
-    """The 16 substrate coordinates -1 + 2 i / 15, rounded once to fp32."""
-    i = np.arange(GRID_SIDE, dtype=np.float64)
-    return ((2.0 * i - 15.0) / 15.0).astype(np.float32)
+def grid_coords(side: int = GRID_SIDE) -> np.ndarray:
+    """The side substrate coordinates -1 + 2 i / (side - 1), rounded once to
+    fp32."""
+    i = np.arange(side, dtype=np.float64)
+    return ((2.0 * i - (side - 1)) / (side - 1)).astype(np.float32)
 
 
-def grid_queries(first: int = 0, count: int = GRID_SIDE ** 4) -> np.ndarray:
-    """CPPN inputs [count, 5] for queries first .. first+count-1.
+def grid_queries(first: int = 0, count: int = None, side: int = GRID_SIDE) -> np.ndarray:
+    """CPPN inputs [count, 5] for queries first .. first+count-1 (all
+    side^4 of them by default).
 
-    Grid point p has x = coord[p % 16], y = coord[p // 16]; query q pairs
-    point q // 256 (x1, y1) with point q % 256 (x2, y2); the fifth input is
-    the constant 1."""
-    c = grid_coords()
+    Grid point p has x = coord[p % side], y = coord[p // side]; query q pairs
+    point q // side^2 (x1, y1) with point q % side^2 (x2, y2); the fifth
+    input is the constant 1."""
+    if count is None:
+        count = side ** 4 - first
+    c = grid_coords(side)
+    S = side * side
     q = np.arange(first, first + count, dtype=np.int64)
-    a, b = q // (GRID_SIDE * GRID_SIDE), q % (GRID_SIDE * GRID_SIDE)
+    a, b = q // S, q % S
     out = np.empty((count, 5), np.float32)
-    out[:, 0] = c[a % GRID_SIDE]
-    out[:, 1] = c[a // GRID_SIDE]
-    out[:, 2] = c[b % GRID_SIDE]
-    out[:, 3] = c[b // GRID_SIDE]
+    out[:, 0] = c[a % side]
+    out[:, 1] = c[a // side]
+    out[:, 2] = c[b % side]
+    out[:, 3] = c[b // side]
     out[:, 4] = 1.0
     return out
+
+
+def substrate_inputs(seed: int = 6, B: int = 256, side: int = GRID_SIDE) -> np.ndarray:
+    """B input planes for a HyperNEAT substrate of side x side points
+    ([B, side^2], U[-1, 1]), shared by every genome."""
+    rng = np.random.default_rng(seed)
+    return rng.uniform(-1.0, 1.0, size=(B, side * side)).astype(np.float32)
 
 
 def cppn(seed: int = 4, P: int = 1000) -> Population:
