@@ -64,11 +64,12 @@ def parse():
                     help="genomes of the workload the CPU oracle is timed on")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quiet", action="store_true")
-    ap.add_argument("--workloads", default="control,batched,served,cppn,recurrent",
+    ap.add_argument("--workloads", default="control,batched,served,cppn,recurrent,substrate",
                     help="comma list: control (the headline line), batched (64 uneven "
                          "populations in one recorded batch), served (Poisson request "
                          "stream over 128 resident populations), cppn (grid queries), "
-                         "recurrent (K sweeps of networks with cycles)")
+                         "recurrent (K sweeps of networks with cycles), substrate "
+                         "(HyperNEAT substrate layer on the matrix cores)")
     ap.add_argument("--served-seconds", type=float, default=20.0,
                     help="length of the served request stream (latency counted after "
                          "the first quarter)")
@@ -277,6 +278,56 @@ def bench_cppn(args, torch, neat, synth):
                          "flops_per_genome_input": round(flops / pop.P, 1)}}
 
 
+MFMA_F32_PEAK_TFLOPS = 157.3
+
+
+def bench_substrate(args, torch, neat, synth):
+    """HyperNEAT substrate: P=1000 CPPNs paint a 256 x 256 weight matrix each
+    (side 16 grid), threshold 0.2, then tanh(X W') for B=256 shared input
+    planes; CPPN queries + substrate layer per step."""
+    dev = torch.device("cuda:0")
+    pop = synth.cppn()
+    side, S = 16, 256
+    X = torch.from_numpy(synth.substrate_inputs(B=256, side=side)).to(dev)
+    tn = torch.from_numpy(pop.nodes).to(dev)
+    tc = torch.from_numpy(pop.conns).to(dev)
+    _, _, st, prog = neat.topo_sort(tn, tc, 5, 1, want_order=False)
+    d = neat.dims_of(tn, tc, 5, 1)
+    w = torch.empty((pop.P, S, S), dtype=torch.float32, device=dev)
+    y = torch.empty((pop.P, X.shape[0], S), dtype=torch.float32, device=dev)
+    for _ in range(max(1, args.warmup)):
+        neat.substrate_forward(d, prog, side, X, 0.2, weights=w, outputs=y)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.steps):
+        neat.substrate_forward(d, prog, side, X, 0.2, weights=w, outputs=y)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    # the CPPN part alone (the same grid calculation the call makes first)
+    g0, g1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    g0.record(stream)
+    for _ in range(args.steps):
+        neat.forward_grid(d, prog, side, 0, S * S, outputs=w)
+    g1.record(stream)
+    torch.cuda.synchronize()
+    ms_cppn = g0.elapsed_time(g1) / args.steps
+    ms_layer = max(ms - ms_cppn, 1e-6)
+    flops = 2.0 * pop.P * X.shape[0] * S * S
+    tflops = flops / (ms_layer / 1e3) / 1e12
+    return {"workload": "hyperneat substrate: P=1000 CPPNs (N_max=30), 16x16 grid (S=256), "
+                        "threshold 0.2, B=256 shared input planes, tanh layer",
+            "ms": round(ms, 4), "ms_cppn_weights": round(ms_cppn, 4),
+            "ms_substrate_layer": round(ms_layer, 4),
+            "value": round(pop.P * X.shape[0] / (ms / 1e3), 1), "unit": "genome-inputs/s",
+            "roofline": {"kernel": "substrate layer, fp32 MFMA 16x16x4", "bound": "mfma",
+                         "achieved": round(tflops, 2), "peak": MFMA_F32_PEAK_TFLOPS,
+                         "unit": "TFLOP/s", "frac": round(tflops / MFMA_F32_PEAK_TFLOPS, 4),
+                         "flops_per_launch": flops}}
+
+
 def bench_recurrent(args, torch, neat, synth):
     """Recurrent networks: the control shapes with cycles (P=10000, N_max=50,
     C_max=200, B=1000), K=4 synchronous sweeps; transformation + calculation
@@ -482,6 +533,8 @@ def main():
     cppn = bench_cppn(args, torch, neat, synth) if "cppn" in workloads else None
     recurrent = (bench_recurrent(args, torch, neat, synth) if "recurrent" in workloads
                  else None)
+    substrate = (bench_substrate(args, torch, neat, synth) if "substrate" in workloads
+                 else None)
 
     res = {
         "metric": "genome-input forwards/s", "value": round(value, 1),
@@ -503,6 +556,7 @@ def main():
         "served": served,
         "cppn": cppn,
         "recurrent": recurrent,
+        "substrate": substrate,
     }
     print(json.dumps(res), flush=True)
 

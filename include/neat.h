@@ -176,6 +176,29 @@ int neat_forward_grid(const neat_dims *dims, const void *program, int32_t side,
                       int64_t first, int32_t Q, float *outputs, void *stream);
 
 /*
+ * HyperNEAT substrate layer (the paper supports HyperNEAT, Section 1 and
+ * Section 4.3; the substrate reading follows the method it cites).  For a
+ * population of CPPNs (I = 5 inputs x1, y1, x2, y2, 1 and O = 1 output,
+ * program from neat_topo_sort) and the side x side grid of
+ * neat_forward_grid (S = side^2 points):
+ *   weights [P][S][S] f32 (written): w[g][p1][p2] = CPPN_g at the pair
+ *            (source point p1, target point p2), i.e. the grid queries
+ *            q = p1 S + p2 (exactly what neat_forward_grid writes for
+ *            first = 0, Q = S^2); caller-owned workspace, readable after;
+ *   x        [B][S] f32: B input planes shared by every genome;
+ *   outputs  [P][B][S] f32: y[g][b][p2] = tanh(sum_p1 w'[g][p1][p2] x[b][p1])
+ *            with w' = 0 where |w| < threshold, else w (NaN kept); genomes
+ *            with status != 0 give NaN rows.
+ * The contraction runs on the matrix cores in fp32 (v_mfma_f32_16x16x4).
+ * Requires 8 <= side <= 32 with side^2 a multiple of 64 (side 8, 16, 24,
+ * 32), threshold >= 0, 16-byte aligned x, weights and outputs.
+ * Errors: NEAT_E_INVALID, NEAT_E_HIP.
+ */
+int neat_substrate_forward(const neat_dims *dims, const void *program, int32_t side,
+                           float threshold, const float *x, int32_t B, float *weights,
+                           float *outputs, void *stream);
+
+/*
  * Recurrent networks.  The paper sorts networks into feedforward and
  * recurrent ones by whether their graph has cycles (Section 3.3; Appendix A's
  * network_type) and defines only the feedforward calculation; here a

@@ -15,7 +15,7 @@ from ._lib import (FWD_AUTO, FWD_LDS, FWD_REG, FWD_REG2, INPUT_GRID, INPUT_TENSO
                    Dims, NeatError, Request, Result, ServerCfg, Stats, check, lib)
 
 __all__ = ["Dims", "NeatError", "dims_of", "program_bytes", "topo_sort", "forward",
-           "forward_grid", "forward_recurrent"]
+           "forward_grid", "forward_recurrent", "substrate_forward"]
 
 
 def _torch():
@@ -116,6 +116,36 @@ def forward(dims: Dims, program, inputs, B: int, shared_inputs: bool = False,
     check(lib().neat_forward_ex(ctypes.byref(dims), _ptr(program), _ptr(inputs), stride, B,
                                 _ptr(outputs), variant, _stream(stream)))
     return outputs
+
+
+def substrate_forward(dims: Dims, program, side: int, x, threshold: float = 0.2,
+                      weights=None, outputs=None, stream=None):
+    """HyperNEAT substrate layer: CPPN weights on all side^2 x side^2 point
+    pairs (written to ``weights`` [P, S, S]), thresholded, then
+    tanh(x W') for the shared input planes x [B, S].  Returns
+    (outputs [P, B, S], weights)."""
+    torch = _torch()
+    _dev_f32(x, "x")
+    S = side * side
+    if x.dim() != 2 or x.shape[1] != S:
+        raise ValueError("x must be [B, side^2]")
+    B = x.shape[0]
+    if weights is None:
+        weights = torch.empty((dims.P, S, S), dtype=torch.float32, device=x.device)
+    else:
+        _dev_f32(weights, "weights")
+        if weights.numel() < dims.P * S * S:
+            raise ValueError("weights smaller than P * S * S")
+    if outputs is None:
+        outputs = torch.empty((dims.P, B, S), dtype=torch.float32, device=x.device)
+    else:
+        _dev_f32(outputs, "outputs")
+        if outputs.numel() < dims.P * B * S:
+            raise ValueError("outputs smaller than P * B * S")
+    check(lib().neat_substrate_forward(ctypes.byref(dims), _ptr(program), side,
+                                       ctypes.c_float(threshold), _ptr(x), B, _ptr(weights),
+                                       _ptr(outputs), _stream(stream)))
+    return outputs, weights
 
 
 def forward_recurrent(dims: Dims, program, inputs, B: int, K: int,

@@ -258,6 +258,36 @@ int neat_forward_recurrent(const neat_dims *d, const void *program, const float 
     return NEAT_OK;
 }
 
+int neat_substrate_forward(const neat_dims *d, const void *program, int32_t side,
+                           float threshold, const float *x, int32_t B, float *weights,
+                           float *outputs, void *stream) {
+    int rc = check_dims(d);
+    if (rc != NEAT_OK) return rc;
+    if (d->I != 5 || d->O != 1)
+        return fail(NEAT_E_INVALID, "substrate CPPNs need I = 5, O = 1 (got I=%d O=%d)", d->I,
+                    d->O);
+    if (side < 8 || side > 32 || (side * side) % 64 != 0)
+        return fail(NEAT_E_INVALID, "substrate side %d: need 8 <= side <= 32, side^2 a multiple "
+                                    "of 64", side);
+    if (B < 0) return fail(NEAT_E_INVALID, "B = %d < 0", B);
+    if (!(threshold >= 0.0f)) return fail(NEAT_E_INVALID, "threshold must be >= 0");
+    if (d->P == 0) return NEAT_OK;
+    if (!program || !weights || (B > 0 && (!x || !outputs)))
+        return fail(NEAT_E_INVALID, "program, x, weights or outputs is NULL");
+    if (!aligned(weights, 16) || (B > 0 && (!aligned(x, 16) || !aligned(outputs, 16))))
+        return fail(NEAT_E_INVALID, "x, weights and outputs must be 16-byte aligned");
+    const int S = side * side;
+    if ((long long)d->P * ((B + 63) / 64) * (S / 64) >= (1ll << 31))
+        return fail(NEAT_E_INVALID, "P * B too large for one launch");
+    // the weights: the CPPN on all S x S pairs of the grid
+    rc = neat_forward_grid(d, program, side, 0, S * S, weights, stream);
+    if (rc != NEAT_OK || B == 0) return rc;
+    neat::SubLaunch L{weights, x, outputs, threshold, d->P, S, B};
+    hipError_t e = neat::substrate_launch(L, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "substrate launch");
+    return NEAT_OK;
+}
+
 int neat_forward_grid(const neat_dims *d, const void *program, int32_t side, int64_t first,
                       int32_t Q, float *outputs, void *stream) {
     return forward_common(d, program, nullptr, 0, Q, outputs, NEAT_FWD_AUTO, true, side, first,

@@ -128,4 +128,16 @@ struct RecLaunch {
 size_t recurrent_lds_bytes(int N, int I);
 hipError_t recurrent_launch(const RecLaunch &L, hipStream_t stream);
 
+// HyperNEAT substrate layer: Y[g] = tanh(X W'[g]), W' = W with |w| < theta
+// set to 0.  W [P][S][S], X [B][S], Y [P][B][S]; S a multiple of 64; X, W
+// and the rows 16-byte aligned.
+struct SubLaunch {
+    const float *W;
+    const float *X;
+    float *Y;
+    float theta;
+    int P, S, B;
+};
+hipError_t substrate_launch(const SubLaunch &L, hipStream_t stream);
+
 }  // namespace neat
