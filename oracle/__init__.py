@@ -65,6 +65,8 @@ def _load():
             fn = getattr(lib, name)
             fn.argtypes = [i32] * 5 + [vp, vp, vp, i64, i32, vp, vp]
             fn.restype = i32
+        lib.oracle_distance.argtypes = [i32] * 4 + [vp] * 4 + [ctypes.c_double] * 2 + [vp] * 2
+        lib.oracle_distance.restype = i32
         for name in ("oracle_forward_recurrent_f64", "oracle_forward_recurrent_f32"):
             fn = getattr(lib, name)
             fn.argtypes = [i32] * 5 + [vp, vp, vp, i64, i32, i32, vp, vp]
@@ -166,6 +168,25 @@ def _forward(nodes, conns, inputs, I, O, shared_inputs, precision, with_beta, K)
             raise RuntimeError("oracle forward (f32) failed: %d" % rc)
         return y
     raise ValueError("precision must be 'f64' or 'f32'")
+
+
+def distance(nodes, conns, rnodes, rconns, c_disjoint=1.0, c_homologous=0.5):
+    """Compatibility distance of every genome to every representative
+    ([P, Q] float64) and its fp32 error bound (see neat_oracle.c)."""
+    nodes, conns = _check_genomes(nodes, conns, 1, 1)
+    rnodes, rconns = _check_genomes(rnodes, rconns, 1, 1)
+    if rnodes.shape[1:] != nodes.shape[1:] or rconns.shape[1:] != conns.shape[1:]:
+        raise ValueError("representatives must have the population's N_max and C_max")
+    P, N, _ = nodes.shape
+    Q, C = rnodes.shape[0], conns.shape[1]
+    out = np.empty((P, Q), np.float64)
+    bound = np.empty((P, Q), np.float64)
+    rc = _load().oracle_distance(P, Q, N, C, _ptr(nodes), _ptr(conns), _ptr(rnodes),
+                                 _ptr(rconns), float(c_disjoint), float(c_homologous),
+                                 _ptr(out), _ptr(bound))
+    if rc != 0:
+        raise RuntimeError("oracle_distance failed: %d" % rc)
+    return out, bound
 
 
 def order_keys(nodes, order):

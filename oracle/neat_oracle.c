@@ -366,3 +366,79 @@ static void incoming_free(o_incoming *in) {
 #undef R_EXP
 #undef R_SIN
 #undef R_FABS
+
+/*
+ * Compatibility distance (the step before the transformation in each
+ * generation: speciation divides the population by distances between
+ * networks, Appendix (NEAT algorithm); Appendix A names the coefficients
+ * compatibility_disjoint and compatibility_homologous).  The form is NEAT's
+ * (a reading; the paper gives no formula):
+ *   genes: node rows with a key, connection rows with an in key (enabled or
+ *   not); an A gene is homologous when B has a gene with the same key (node)
+ *   or (in, out) keys (connection), its partner being the first such B row;
+ *   node gene distance |bias - bias'| + |response - response'| + [act != act']
+ *   + [agg != agg']; connection gene distance |w - w'| + [enabled != enabled'];
+ *   per kind: (cd (|A| + |B| - 2 h) + ch sum of homologous distances) /
+ *   max(|A|, |B|), 0 when both are empty; distance = node part + connection
+ *   part.
+ * out [P][Q] is the distance of genome p to representative q; bound [P][Q]
+ * (nullable) a first-order bound on the error of an fp32 evaluation.
+ */
+static void kind_distance(const float *a, int na_rows, const float *b, int nb_rows, int w,
+                          int node, double cd, double ch, double *d, double *e) {
+    int na = 0, nb = 0, h = 0;
+    double hsum = 0.0;
+    for (int r = 0; r < nb_rows; ++r)
+        if (!isnan(b[(size_t)r * w])) nb++;
+    for (int r = 0; r < na_rows; ++r) {
+        const float *x = a + (size_t)r * w;
+        if (isnan(x[0])) continue;
+        na++;
+        for (int q = 0; q < nb_rows; ++q) {
+            const float *y = b + (size_t)q * w;
+            if (isnan(y[0])) continue;
+            if (node ? (x[0] == y[0]) : (x[0] == y[0] && x[1] == y[1])) {
+                h++;
+                if (node)
+                    hsum += fabs((double)x[1] - (double)y[1]) + fabs((double)x[2] - (double)y[2]) +
+                            (x[3] != y[3]) + (x[4] != y[4]);
+                else
+                    hsum += fabs((double)x[3] - (double)y[3]) + (x[2] != y[2]);
+                break;
+            }
+        }
+    }
+    const int m = na > nb ? na : nb;
+    if (m == 0) {
+        *d = 0.0;
+        *e = 0.0;
+        return;
+    }
+    const double num = cd * (double)(na + nb - 2 * h) + ch * hsum;
+    *d = num / (double)m;
+    /* fp32: each term rounded once, the sum of h terms, the products, the
+     * division: (h + 6) u relative to the absolute numerator */
+    const double u = 1.0 / 16777216.0;
+    *e = (double)(h + 6) * u * (fabs(cd) * fabs((double)(na + nb - 2 * h)) + fabs(ch) * hsum) /
+         (double)m;
+}
+
+int oracle_distance(int P, int Q, int N_max, int C_max, const float *nodes,
+                    const float *conns, const float *rnodes, const float *rconns, double cd,
+                    double ch, double *out, double *bound) {
+    if (P < 0 || Q < 0 || N_max < 1 || C_max < 0) return ORACLE_E_INVALID;
+    for (int p = 0; p < P; ++p)
+        for (int q = 0; q < Q; ++q) {
+            double dn, en, dc, ec;
+            kind_distance(nodes + (size_t)p * N_max * NODE_W, N_max,
+                          rnodes + (size_t)q * N_max * NODE_W, N_max, NODE_W, 1, cd, ch, &dn,
+                          &en);
+            kind_distance(conns + (size_t)p * C_max * CONN_W, C_max,
+                          rconns + (size_t)q * C_max * CONN_W, C_max, CONN_W, 0, cd, ch, &dc,
+                          &ec);
+            out[(size_t)p * Q + q] = dn + dc;
+            if (bound)
+                bound[(size_t)p * Q + q] = en + ec + fabs(dn + dc) / 16777216.0;
+        }
+    return 0;
+}
