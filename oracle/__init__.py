@@ -65,6 +65,8 @@ def _load():
             fn = getattr(lib, name)
             fn.argtypes = [i32] * 5 + [vp, vp, vp, i64, i32, vp, vp]
             fn.restype = i32
+        lib.oracle_crossover.argtypes = [i32] * 3 + [vp] * 7
+        lib.oracle_crossover.restype = i32
         lib.oracle_distance.argtypes = [i32] * 4 + [vp] * 4 + [ctypes.c_double] * 2 + [vp] * 2
         lib.oracle_distance.restype = i32
         for name in ("oracle_forward_recurrent_f64", "oracle_forward_recurrent_f32"):
@@ -187,6 +189,28 @@ def distance(nodes, conns, rnodes, rconns, c_disjoint=1.0, c_homologous=0.5):
     if rc != 0:
         raise RuntimeError("oracle_distance failed: %d" % rc)
     return out, bound
+
+
+def crossover(nodes, conns, pairs, rn, rc):
+    """Children of the parent pairs [Pc, 2] (fitter parent first) with the
+    per-row uniform numbers rn [Pc, N_max], rc [Pc, C_max] (see
+    neat_oracle.c); returns (child nodes, child conns)."""
+    nodes, conns = _check_genomes(nodes, conns, 1, 1)
+    pairs = np.ascontiguousarray(pairs, dtype=np.int32)
+    Pc = pairs.shape[0]
+    N, C = nodes.shape[1], conns.shape[1]
+    rn = np.ascontiguousarray(rn, dtype=np.float32).reshape(Pc, N)
+    rc = np.ascontiguousarray(rc, dtype=np.float32).reshape(Pc, C)
+    if pairs.ndim != 2 or pairs.shape[1] != 2 or pairs.min(initial=0) < 0 \
+            or pairs.max(initial=0) >= nodes.shape[0]:
+        raise ValueError("pairs must be [Pc, 2] parent indices")
+    cn = np.empty((Pc, N, 5), np.float32)
+    cc = np.empty((Pc, C, 4), np.float32)
+    rc_ = _load().oracle_crossover(Pc, N, C, _ptr(nodes), _ptr(conns), _ptr(pairs), _ptr(rn),
+                                   _ptr(rc), _ptr(cn), _ptr(cc))
+    if rc_ != 0:
+        raise RuntimeError("oracle_crossover failed: %d" % rc_)
+    return cn, cc
 
 
 def order_keys(nodes, order):

@@ -442,3 +442,55 @@ int oracle_distance(int P, int Q, int N_max, int C_max, const float *nodes,
         }
     return 0;
 }
+
+/*
+ * Crossover (Section 3.2: mutation and crossover become tensor writes of
+ * rows and attributes; the gene alignment is NEAT's, a reading): the child
+ * of (p1, p2), p1 the fitter parent, keeps p1's rows (keys, and the
+ * disjoint and excess genes of p1); a p1 gene that is homologous in p2
+ * (same node key, or same (in, out) keys; the partner is p2's first such
+ * row) takes all of its non-key columns from the partner when the gene's
+ * random number r < 0.5, else from p1.  Rows absent in p1 stay NaN.
+ *   parents: nodes [Pp][N][5], conns [Pp][C][4]; pairs [Pc][2] (p1, p2);
+ *   rn [Pc][N], rc [Pc][C] uniform numbers per p1 row; children written to
+ *   cn [Pc][N][5], cc [Pc][C][4].
+ */
+int oracle_crossover(int Pc, int N_max, int C_max, const float *nodes, const float *conns,
+                     const int32_t *pairs, const float *rn, const float *rc, float *cn,
+                     float *cc) {
+    if (Pc < 0 || N_max < 1 || C_max < 0) return ORACLE_E_INVALID;
+    for (int k = 0; k < Pc; ++k) {
+        const int a = pairs[2 * k], b = pairs[2 * k + 1];
+        const float *an = nodes + (size_t)a * N_max * NODE_W;
+        const float *bn = nodes + (size_t)b * N_max * NODE_W;
+        const float *ac = conns + (size_t)a * C_max * CONN_W;
+        const float *bc = conns + (size_t)b * C_max * CONN_W;
+        float *on = cn + (size_t)k * N_max * NODE_W;
+        float *oc = cc + (size_t)k * C_max * CONN_W;
+        for (int r = 0; r < N_max; ++r) {
+            const float *x = an + (size_t)r * NODE_W;
+            memcpy(on + (size_t)r * NODE_W, x, sizeof(float) * NODE_W);
+            if (isnan(x[0]) || !(rn[(size_t)k * N_max + r] < 0.5f)) continue;
+            for (int q = 0; q < N_max; ++q) {
+                const float *y = bn + (size_t)q * NODE_W;
+                if (!isnan(y[0]) && y[0] == x[0]) {
+                    memcpy(on + (size_t)r * NODE_W + 1, y + 1, sizeof(float) * (NODE_W - 1));
+                    break;
+                }
+            }
+        }
+        for (int r = 0; r < C_max; ++r) {
+            const float *x = ac + (size_t)r * CONN_W;
+            memcpy(oc + (size_t)r * CONN_W, x, sizeof(float) * CONN_W);
+            if (isnan(x[0]) || !(rc[(size_t)k * C_max + r] < 0.5f)) continue;
+            for (int q = 0; q < C_max; ++q) {
+                const float *y = bc + (size_t)q * CONN_W;
+                if (!isnan(y[0]) && y[0] == x[0] && y[1] == x[1]) {
+                    memcpy(oc + (size_t)r * CONN_W + 2, y + 2, sizeof(float) * (CONN_W - 2));
+                    break;
+                }
+            }
+        }
+    }
+    return 0;
+}
