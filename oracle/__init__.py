@@ -65,6 +65,8 @@ def _load():
             fn = getattr(lib, name)
             fn.argtypes = [i32] * 5 + [vp, vp, vp, i64, i32, vp, vp]
             fn.restype = i32
+        lib.oracle_edit.argtypes = [i32] * 3 + [vp, vp, i32, vp, vp]
+        lib.oracle_edit.restype = i32
         lib.oracle_crossover.argtypes = [i32] * 3 + [vp] * 7
         lib.oracle_crossover.restype = i32
         lib.oracle_distance.argtypes = [i32] * 4 + [vp] * 4 + [ctypes.c_double] * 2 + [vp] * 2
@@ -189,6 +191,25 @@ def distance(nodes, conns, rnodes, rconns, c_disjoint=1.0, c_homologous=0.5):
     if rc != 0:
         raise RuntimeError("oracle_distance failed: %d" % rc)
     return out, bound
+
+
+EDIT_DTYPE = np.dtype([("genome", "<i4"), ("op", "<i4"), ("row", "<i4"), ("column", "<i4"),
+                       ("v", "<f4", (5,))])
+NODE_ADD, NODE_DEL, CONN_ADD, CONN_DEL, NODE_SET, CONN_SET = range(6)
+
+
+def edit(nodes, conns, edits):
+    """Apply the tensorized edits (EDIT_DTYPE records, see neat_oracle.c) to
+    copies of nodes/conns; returns (nodes, conns, applied [n] i32)."""
+    nodes = np.array(nodes, dtype=np.float32, copy=True, order="C")
+    conns = np.array(conns, dtype=np.float32, copy=True, order="C")
+    edits = np.ascontiguousarray(edits, dtype=EDIT_DTYPE)
+    applied = np.empty((len(edits),), np.int32)
+    rc = _load().oracle_edit(nodes.shape[0], nodes.shape[1], conns.shape[1], _ptr(nodes),
+                             _ptr(conns), len(edits), _ptr(edits), _ptr(applied))
+    if rc != 0:
+        raise RuntimeError("oracle_edit failed: %d" % rc)
+    return nodes, conns, applied
 
 
 def crossover(nodes, conns, pairs, rn, rc):

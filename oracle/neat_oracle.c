@@ -494,3 +494,61 @@ int oracle_crossover(int Pc, int N_max, int C_max, const float *nodes, const flo
     }
     return 0;
 }
+
+/*
+ * Tensorized genome edits (Section 3.2): node addition writes the new row at
+ * the first NaN row of the node tensor, node removal writes NaN over a row,
+ * connection addition and removal do the same on the connection tensor,
+ * and an attribute write sets one column of a row (node columns 1..4 after
+ * the key; connection columns 2..3, the enabled flag and the weight).  The
+ * edits of a genome apply in their order; genomes are independent.
+ *   an edit is 9 words: genome, op, row, column (int32), then five floats
+ *   v: the new row for an addition (node: key, bias, response, act, agg;
+ *   connection: in, out, enabled, weight), v[0] for an attribute write;
+ *   op: 0 node add, 1 node removal, 2 connection add, 3 connection
+ *   removal, 4 node attribute, 5 connection attribute.
+ *   applied [n] i32 (written): 1 when the edit changed the tensors, 0 when
+ *   it could not apply (no NaN row left, a row, column, op or genome out of
+ *   range).
+ */
+typedef struct {
+    int32_t genome, op, row, column;
+    float v[5];
+} o_edit;
+
+int oracle_edit(int P, int N_max, int C_max, float *nodes, float *conns, int n,
+                const void *edits_, int32_t *applied) {
+    if (P < 0 || N_max < 1 || C_max < 0 || n < 0) return ORACLE_E_INVALID;
+    const o_edit *edits = (const o_edit *)edits_;
+    for (int e = 0; e < n; ++e) {
+        const o_edit *d = edits + e;
+        applied[e] = 0;
+        if (d->genome < 0 || d->genome >= P) continue;
+        float *gn = nodes + (size_t)d->genome * N_max * NODE_W;
+        float *gc = conns + (size_t)d->genome * C_max * CONN_W;
+        if (d->op == 0 || d->op == 2) {
+            float *t = d->op == 0 ? gn : gc;
+            const int rows = d->op == 0 ? N_max : C_max, w = d->op == 0 ? NODE_W : CONN_W;
+            int r = 0;
+            while (r < rows && !isnan(t[(size_t)r * w])) ++r;
+            if (r == rows) continue;
+            for (int c = 0; c < w; ++c) t[(size_t)r * w + c] = d->v[c];
+            applied[e] = 1;
+        } else if (d->op == 1 || d->op == 3) {
+            float *t = d->op == 1 ? gn : gc;
+            const int rows = d->op == 1 ? N_max : C_max, w = d->op == 1 ? NODE_W : CONN_W;
+            if (d->row < 0 || d->row >= rows) continue;
+            for (int c = 0; c < w; ++c) t[(size_t)d->row * w + c] = NAN;
+            applied[e] = 1;
+        } else if (d->op == 4) {
+            if (d->row < 0 || d->row >= N_max || d->column < 1 || d->column > 4) continue;
+            gn[(size_t)d->row * NODE_W + d->column] = d->v[0];
+            applied[e] = 1;
+        } else if (d->op == 5) {
+            if (d->row < 0 || d->row >= C_max || d->column < 2 || d->column > 3) continue;
+            gc[(size_t)d->row * CONN_W + d->column] = d->v[0];
+            applied[e] = 1;
+        }
+    }
+    return 0;
+}
