@@ -64,12 +64,16 @@ def parse():
                     help="genomes of the workload the CPU oracle is timed on")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quiet", action="store_true")
-    ap.add_argument("--workloads", default="control,batched,served,cppn,recurrent,substrate",
+    ap.add_argument("--workloads", default="control,batched,served,cppn,recurrent,substrate,distance,"
+                            "crossover,edit",
                     help="comma list: control (the headline line), batched (64 uneven "
                          "populations in one recorded batch), served (Poisson request "
                          "stream over 128 resident populations), cppn (grid queries), "
                          "recurrent (K sweeps of networks with cycles), substrate "
-                         "(HyperNEAT substrate layer on the matrix cores)")
+                         "(HyperNEAT substrate layer on the matrix cores), distance "
+                         "(compatibility distance to species representatives), "
+                         "crossover (children of genome pairs), edit (tensorized "
+                         "mutation edits)")
     ap.add_argument("--served-seconds", type=float, default=20.0,
                     help="length of the served request stream (latency counted after "
                          "the first quarter)")
@@ -328,6 +332,111 @@ def bench_substrate(args, torch, neat, synth):
                          "flops_per_launch": flops}}
 
 
+def bench_distance(args, torch, neat, synth):
+    """Compatibility distance (speciation): P=10000 control genomes against
+    Q=64 species representatives."""
+    dev = torch.device("cuda:0")
+    pop = synth.control(P=args.P, B=1, with_inputs=False)
+    rep = synth.control(seed=7, P=64, B=1, with_inputs=False)
+    t = [torch.from_numpy(a).to(dev) for a in (pop.nodes, pop.conns, rep.nodes, rep.conns)]
+    out = torch.empty((pop.P, rep.P), dtype=torch.float32, device=dev)
+    for _ in range(max(1, args.warmup)):
+        neat.distance(*t, out=out)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.steps):
+        neat.distance(*t, out=out)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    pairs = pop.P * rep.P
+    # algorithmic bytes: every genome's rows once (nodes 20 B, connections
+    # 16 B per row), every representative's rows once per genome (the
+    # kernel reads them from L2), the distances
+    gbytes = pop.P * (pop.nodes.shape[1] * 20 + pop.conns.shape[1] * 16)
+    rbytes = rep.P * (rep.nodes.shape[1] * 20 + rep.conns.shape[1] * 16)
+    return {"workload": "compatibility distance: P=%d control genomes (N_max=50, C_max=200) "
+                        "against Q=64 representatives" % pop.P,
+            "ms": round(ms, 4), "value": round(pairs / (ms / 1e3), 1), "unit": "pairs/s",
+            "hbm_GBps": round((gbytes + rbytes + pairs * 4) / (ms / 1e3) / 1e9, 1),
+            "l2_GBps": round((gbytes + pop.P * rbytes) / (ms / 1e3) / 1e9, 1)}
+
+
+def bench_crossover(args, torch, neat, synth):
+    """Crossover: P=10000 children of random pairs of control genomes."""
+    dev = torch.device("cuda:0")
+    pop = synth.control(P=args.P, B=1, with_inputs=False)
+    rng = np.random.default_rng(14)
+    pairs = torch.from_numpy(rng.integers(0, pop.P, (pop.P, 2)).astype(np.int32)).to(dev)
+    rn = torch.from_numpy(rng.random((pop.P, 50)).astype(np.float32)).to(dev)
+    rc = torch.from_numpy(rng.random((pop.P, 200)).astype(np.float32)).to(dev)
+    tn, tc = torch.from_numpy(pop.nodes).to(dev), torch.from_numpy(pop.conns).to(dev)
+    cn, cc = neat.crossover(tn, tc, pairs, rn, rc)
+    for _ in range(max(1, args.warmup)):
+        neat.crossover(tn, tc, pairs, rn, rc, cn, cc)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.steps):
+        neat.crossover(tn, tc, pairs, rn, rc, cn, cc)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    # algorithmic bytes per child: both parents' rows read, the child's rows
+    # written, one number per first-parent row, the pair
+    per = 3 * (50 * 20 + 200 * 16) + (50 + 200) * 4 + 8
+    return {"workload": "crossover: %d children of control-genome pairs (N_max=50, "
+                        "C_max=200)" % pop.P,
+            "ms": round(ms, 4), "value": round(pop.P / (ms / 1e3), 1), "unit": "children/s",
+            "roofline": {"bound": "hbm", "achieved": round(pop.P * per / (ms / 1e3) / 1e9, 1),
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(pop.P * per / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+                         "bytes_per_child": per}}
+
+
+def bench_edit(args, torch, neat, synth):
+    """Tensorized edits: a mutation-sized batch over P=10000 control genomes
+    (per genome one node addition, two connection additions, one connection
+    removal and four attribute writes), applied in place."""
+    dev = torch.device("cuda:0")
+    pop = synth.control(P=args.P, B=1, with_inputs=False)
+    rng = np.random.default_rng(16)
+    per = 8
+    rec = np.dtype([("genome", "<i4"), ("op", "<i4"), ("row", "<i4"), ("column", "<i4"),
+                    ("v", "<f4", (5,))])
+    e = np.zeros(pop.P * per, rec)
+    e["genome"] = np.repeat(np.arange(pop.P), per)
+    e["op"] = np.tile([0, 2, 2, 3, 4, 4, 5, 5], pop.P)
+    e["row"] = rng.integers(0, 50, pop.P * per)
+    e["column"] = np.tile([0, 0, 0, 0, 1, 2, 3, 2], pop.P)
+    e["v"] = rng.normal(size=(pop.P * per, 5)).astype(np.float32)
+    te = torch.from_numpy(e.view(np.uint8).copy()).to(dev)
+    tn0, tc0 = torch.from_numpy(pop.nodes).to(dev), torch.from_numpy(pop.conns).to(dev)
+    tn, tc = tn0.clone(), tc0.clone()
+    applied = neat.edit(tn, tc, te)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ms = []
+    for _ in range(args.steps):
+        tn.copy_(tn0)
+        tc.copy_(tc0)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        neat.edit(tn, tc, te, applied=applied)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    ms = float(np.median(ms))
+    return {"workload": "tensorized edits: %d control genomes x %d edits (node add, 2 "
+                        "connection adds, connection removal, 4 attribute writes)"
+                        % (pop.P, per),
+            "ms": round(ms, 4), "value": round(pop.P * per / (ms / 1e3), 1),
+            "unit": "edits/s", "applied": int(applied.sum().item())}
+
+
 def bench_recurrent(args, torch, neat, synth):
     """Recurrent networks: the control shapes with cycles (P=10000, N_max=50,
     C_max=200, B=1000), K=4 synchronous sweeps; transformation + calculation
@@ -535,6 +644,11 @@ def main():
                  else None)
     substrate = (bench_substrate(args, torch, neat, synth) if "substrate" in workloads
                  else None)
+    distance = (bench_distance(args, torch, neat, synth) if "distance" in workloads
+                else None)
+    crossover = (bench_crossover(args, torch, neat, synth) if "crossover" in workloads
+                 else None)
+    edits = bench_edit(args, torch, neat, synth) if "edit" in workloads else None
 
     res = {
         "metric": "genome-input forwards/s", "value": round(value, 1),
@@ -557,6 +671,9 @@ def main():
         "cppn": cppn,
         "recurrent": recurrent,
         "substrate": substrate,
+        "distance": distance,
+        "crossover": crossover,
+        "edit": edits,
     }
     print(json.dumps(res), flush=True)
 

@@ -176,6 +176,95 @@ int neat_forward_grid(const neat_dims *dims, const void *program, int32_t side,
                       int64_t first, int32_t Q, float *outputs, void *stream);
 
 /*
+ * Compatibility distance (speciation, the step before the transformation in
+ * each generation: the NEAT algorithm of the paper's appendix divides the
+ * population by distances between networks; Appendix A names the disjoint
+ * and homologous coefficients).  NEAT's form, per pair (genome A,
+ * representative B):
+ *   genes: node rows with a key and connection rows with an in key
+ *   (enabled or not); an A gene is homologous when B has a gene with the
+ *   same key (nodes) or (in, out) keys (connections), its partner being
+ *   B's first such row;
+ *   node gene distance |bias - bias'| + |response - response'| +
+ *   [act != act'] + [agg != agg']; connection gene distance |w - w'| +
+ *   [enabled != enabled'];
+ *   per kind (c_disjoint (|A| + |B| - 2 homologous) + c_homologous sum) /
+ *   max(|A|, |B|), 0 when both are empty; distance = nodes + connections.
+ *   nodes, conns   the population [P][N_max][5], [P][C_max][4] (read)
+ *   rnodes, rconns Q representatives with the same N_max, C_max (read)
+ *   out            [P][Q] f32 (written)
+ * Keys compare as floats (-0 equals +0; a NaN out key never matches).
+ * fp32 arithmetic; the wave's partial sums are added in tree order.
+ * Errors: NEAT_E_INVALID, NEAT_E_TOO_LARGE (the hash tables of one
+ * representative, 12 B per slot for 2 N_max and 2 C_max rounded up to
+ * powers of two, exceed the LDS of a workgroup: C_max beyond about 4096),
+ * NEAT_E_HIP.
+ */
+int neat_distance(const neat_dims *dims, const float *nodes, const float *conns, int32_t Q,
+                  const float *rnodes, const float *rconns, float c_disjoint,
+                  float c_homologous, float *out, void *stream);
+
+/*
+ * Tensorized genome edits (Section 3.2): the structural and attribute
+ * changes of mutation as tensor writes, applied in place to a population:
+ *   NEAT_EDIT_NODE_ADD  node row v[0..4] (key, bias, response, act, agg)
+ *                       written at the genome's first NaN node row (first
+ *                       row whose key is NaN);
+ *   NEAT_EDIT_NODE_DEL  NaN over node row `row`;
+ *   NEAT_EDIT_CONN_ADD  connection row v[0..3] (in, out, enabled, weight)
+ *                       at the first NaN connection row;
+ *   NEAT_EDIT_CONN_DEL  NaN over connection row `row`;
+ *   NEAT_EDIT_NODE_SET  node row `row`, column `column` (1..4: bias,
+ *                       response, act, agg) = v[0];
+ *   NEAT_EDIT_CONN_SET  connection row `row`, column `column` (2 enabled,
+ *                       3 weight) = v[0].
+ * The edits of a genome apply in their order, genomes independently.
+ *   edits    [n] (read, device memory), sorted by genome (stable: a
+ *            genome's edits in application order)
+ *   applied  [n] i32 (written, device memory): 1 when the edit changed the
+ *            tensors; 0 when it could not apply (no NaN row left, a row,
+ *            column, op or genome out of range, or edits not sorted)
+ * Values are not checked (a later neat_topo_sort validates the genome).
+ * Errors: NEAT_E_INVALID, NEAT_E_HIP.
+ */
+#define NEAT_EDIT_NODE_ADD 0
+#define NEAT_EDIT_NODE_DEL 1
+#define NEAT_EDIT_CONN_ADD 2
+#define NEAT_EDIT_CONN_DEL 3
+#define NEAT_EDIT_NODE_SET 4
+#define NEAT_EDIT_CONN_SET 5
+typedef struct {
+    int32_t genome, op, row, column;
+    float v[5];
+} neat_edit;
+
+int neat_apply_edits(const neat_dims *dims, float *nodes, float *conns, const neat_edit *edits,
+                     int32_t n, int32_t *applied, void *stream);
+
+/*
+ * Crossover (Section 3.2: mutation and crossover become row writes at the
+ * first NaN row, NaN writes and attribute writes of the tensors; the gene
+ * alignment is NEAT's).  Child k of the parent pair (p1, p2) =
+ * pairs[2k], pairs[2k+1] (p1 the fitter parent) keeps p1's rows: its keys,
+ * its NaN rows and its genes without a partner.  A p1 gene that is
+ * homologous in p2 (same node key, or same (in, out) keys; the partner is
+ * p2's first such row) takes all of its non-key columns (bias, response,
+ * act, agg; enabled, weight) from the partner when its number is below 0.5.
+ *   nodes, conns  the P parents [P][N_max][5], [P][C_max][4] (read)
+ *   pairs         [Pc][2] i32 parent indices (read, device memory); a pair
+ *                 with an index outside [0, P) gives an all-NaN child
+ *   rn, rc        [Pc][N_max], [Pc][C_max] f32 uniform numbers, one per
+ *                 first-parent row (the caller draws them)
+ *   child_nodes, child_conns  [Pc][N_max][5], [Pc][C_max][4] (written;
+ *                 child_conns 16-byte aligned); must not overlap the parents
+ * Keys compare as floats (-0 equals +0; a NaN out key never matches).
+ * Errors: NEAT_E_INVALID, NEAT_E_TOO_LARGE (as neat_distance), NEAT_E_HIP.
+ */
+int neat_crossover(const neat_dims *dims, const float *nodes, const float *conns, int32_t Pc,
+                   const int32_t *pairs, const float *rn, const float *rc, float *child_nodes,
+                   float *child_conns, void *stream);
+
+/*
  * HyperNEAT substrate layer (the paper supports HyperNEAT, Section 1 and
  * Section 4.3; the substrate reading follows the method it cites).  For a
  * population of CPPNs (I = 5 inputs x1, y1, x2, y2, 1 and O = 1 output,

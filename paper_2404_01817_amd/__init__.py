@@ -15,7 +15,8 @@ from ._lib import (FWD_AUTO, FWD_LDS, FWD_REG, FWD_REG2, INPUT_GRID, INPUT_TENSO
                    Dims, NeatError, Request, Result, ServerCfg, Stats, check, lib)
 
 __all__ = ["Dims", "NeatError", "dims_of", "program_bytes", "topo_sort", "forward",
-           "forward_grid", "forward_recurrent", "substrate_forward"]
+           "forward_grid", "forward_recurrent", "substrate_forward", "distance",
+           "crossover", "edit"]
 
 
 def _torch():
@@ -116,6 +117,74 @@ def forward(dims: Dims, program, inputs, B: int, shared_inputs: bool = False,
     check(lib().neat_forward_ex(ctypes.byref(dims), _ptr(program), _ptr(inputs), stride, B,
                                 _ptr(outputs), variant, _stream(stream)))
     return outputs
+
+
+def distance(nodes, conns, rnodes, rconns, c_disjoint: float = 1.0,
+             c_homologous: float = 0.5, out=None, stream=None):
+    """Compatibility distance of every genome (nodes [P,N,5], conns [P,C,4])
+    to every representative (rnodes [Q,N,5], rconns [Q,C,4]); returns
+    [P, Q] float32 (neat_distance)."""
+    torch = _torch()
+    for t, name in ((nodes, "nodes"), (conns, "conns"), (rnodes, "rnodes"), (rconns, "rconns")):
+        _dev_f32(t, name)
+    d = dims_of(nodes, conns, 1, 1)
+    if rnodes.shape[1:] != nodes.shape[1:] or rconns.shape[1:] != conns.shape[1:] \
+            or rnodes.shape[0] != rconns.shape[0]:
+        raise ValueError("representatives must have the population's N_max and C_max")
+    Q = rnodes.shape[0]
+    if out is None:
+        out = torch.empty((d.P, Q), dtype=torch.float32, device=nodes.device)
+    else:
+        _dev_f32(out, "out")
+        if out.numel() < d.P * Q:
+            raise ValueError("out smaller than P * Q")
+    check(lib().neat_distance(ctypes.byref(d), _ptr(nodes), _ptr(conns), Q, _ptr(rnodes),
+                              _ptr(rconns), ctypes.c_float(c_disjoint),
+                              ctypes.c_float(c_homologous), _ptr(out), _stream(stream)))
+    return out
+
+
+def edit(nodes, conns, edits, applied=None, stream=None):
+    """Apply tensorized edits in place (neat_apply_edits): ``edits`` is a device
+    uint8/int32 tensor holding neat_edit records (36 bytes each, sorted by
+    genome); returns applied [n] int32."""
+    torch = _torch()
+    _dev_f32(nodes, "nodes")
+    _dev_f32(conns, "conns")
+    if not (edits.is_cuda and edits.is_contiguous() and edits.numel() * edits.element_size()
+            % 36 == 0):
+        raise ValueError("edits must be a contiguous CUDA tensor of 36-byte records")
+    n = edits.numel() * edits.element_size() // 36
+    d = dims_of(nodes, conns, 1, 1)
+    if applied is None:
+        applied = torch.empty((n,), dtype=torch.int32, device=nodes.device)
+    check(lib().neat_apply_edits(ctypes.byref(d), _ptr(nodes), _ptr(conns), _ptr(edits), n,
+                          _ptr(applied), _stream(stream)))
+    return applied
+
+
+def crossover(nodes, conns, pairs, rn, rc, child_nodes=None, child_conns=None, stream=None):
+    """Children of the parent pairs [Pc, 2] (int32, fitter parent first) with
+    uniform numbers rn [Pc, N_max], rc [Pc, C_max] (neat_crossover);
+    returns (child nodes, child conns)."""
+    torch = _torch()
+    for t, name in ((nodes, "nodes"), (conns, "conns"), (rn, "rn"), (rc, "rc")):
+        _dev_f32(t, name)
+    if not (pairs.is_cuda and pairs.dtype == torch.int32 and pairs.is_contiguous()):
+        raise ValueError("pairs must be a contiguous int32 CUDA tensor")
+    d = dims_of(nodes, conns, 1, 1)
+    Pc = pairs.shape[0]
+    if pairs.dim() != 2 or pairs.shape[1] != 2 or rn.numel() < Pc * d.N_max \
+            or rc.numel() < Pc * d.C_max:
+        raise ValueError("pairs [Pc, 2], rn [Pc, N_max], rc [Pc, C_max]")
+    if child_nodes is None:
+        child_nodes = torch.empty((Pc, d.N_max, 5), dtype=torch.float32, device=nodes.device)
+    if child_conns is None:
+        child_conns = torch.empty((Pc, d.C_max, 4), dtype=torch.float32, device=nodes.device)
+    check(lib().neat_crossover(ctypes.byref(d), _ptr(nodes), _ptr(conns), Pc, _ptr(pairs),
+                               _ptr(rn), _ptr(rc), _ptr(child_nodes), _ptr(child_conns),
+                               _stream(stream)))
+    return child_nodes, child_conns
 
 
 def substrate_forward(dims: Dims, program, side: int, x, threshold: float = 0.2,

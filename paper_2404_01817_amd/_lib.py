@@ -82,6 +82,11 @@ SIGNATURES = {
     "neat_forward": (_i32, [ctypes.POINTER(Dims), _vp, _vp, _i64, _i32, _vp, _vp]),
     "neat_forward_ex": (_i32, [ctypes.POINTER(Dims), _vp, _vp, _i64, _i32, _vp, _i32, _vp]),
     "neat_forward_grid": (_i32, [ctypes.POINTER(Dims), _vp, _i32, _i64, _i32, _vp, _vp]),
+    "neat_apply_edits": (_i32, [ctypes.POINTER(Dims), _vp, _vp, _vp, _i32, _vp, _vp]),
+    "neat_crossover": (_i32, [ctypes.POINTER(Dims), _vp, _vp, _i32, _vp, _vp, _vp, _vp, _vp,
+                              _vp]),
+    "neat_distance": (_i32, [ctypes.POINTER(Dims), _vp, _vp, _i32, _vp, _vp, ctypes.c_float,
+                             ctypes.c_float, _vp, _vp]),
     "neat_substrate_forward": (_i32, [ctypes.POINTER(Dims), _vp, _i32, ctypes.c_float, _vp,
                                       _i32, _vp, _vp, _vp]),
     "neat_topo_sort_recurrent": (_i32, [ctypes.POINTER(Dims), _vp, _vp, _vp, _vp, _vp, _vp,

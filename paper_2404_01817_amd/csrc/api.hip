@@ -10,6 +10,7 @@
 #include <string>
 
 #include "abi.h"
+#include "genes.h"
 #include "launch.h"
 #include "neat.h"
 #include "program.h"
@@ -255,6 +256,73 @@ int neat_forward_recurrent(const neat_dims *d, const void *program, const float 
     L.vec4 = (aligned(inputs, 16) && input_genome_stride % 4 == 0) ? 1 : 0;
     hipError_t e = neat::recurrent_launch(L, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "forward_recurrent launch");
+    return NEAT_OK;
+}
+
+int neat_distance(const neat_dims *d, const float *nodes, const float *conns, int32_t Q,
+                  const float *rnodes, const float *rconns, float c_disjoint,
+                  float c_homologous, float *out, void *stream) {
+    int rc = check_dims(d);
+    if (rc != NEAT_OK) return rc;
+    if (Q < 0) return fail(NEAT_E_INVALID, "Q = %d < 0", Q);
+    if (d->P == 0 || Q == 0) return NEAT_OK;
+    if (!nodes || !rnodes || !out || (d->C_max > 0 && (!conns || !rconns)))
+        return fail(NEAT_E_INVALID, "nodes, conns, rnodes, rconns or out is NULL");
+    const size_t lds = neat::distance_lds_bytes(d->N_max, d->C_max);
+    if (lds > max_lds_bytes())
+        return fail(NEAT_E_TOO_LARGE,
+                    "distance with N_max=%d, C_max=%d needs %zu B of LDS, device allows %zu",
+                    d->N_max, d->C_max, lds, max_lds_bytes());
+    neat::DistLaunch L{};
+    L.nodes = nodes, L.conns = conns, L.rnodes = rnodes, L.rconns = rconns, L.out = out;
+    L.P = d->P, L.Q = Q, L.N = d->N_max, L.C = d->C_max;
+    L.cd = c_disjoint, L.ch = c_homologous;
+    hipError_t e = neat::distance_launch(L, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "distance launch");
+    return NEAT_OK;
+}
+
+int neat_apply_edits(const neat_dims *d, float *nodes, float *conns, const neat_edit *edits,
+                     int32_t n, int32_t *applied, void *stream) {
+    static_assert(sizeof(neat_edit) == sizeof(neat::EditRec), "edit record layout");
+    int rc = check_dims(d);
+    if (rc != NEAT_OK) return rc;
+    if (n < 0) return fail(NEAT_E_INVALID, "n = %d < 0", n);
+    if (n == 0) return NEAT_OK;
+    if (!edits || !applied || (d->P > 0 && (!nodes || (d->C_max > 0 && !conns))))
+        return fail(NEAT_E_INVALID, "a pointer argument is NULL");
+    neat::EditLaunch L{};
+    L.nodes = nodes, L.conns = conns, L.edits = (const neat::EditRec *)edits;
+    L.applied = applied, L.n = n, L.P = d->P, L.N = d->N_max, L.C = d->C_max;
+    hipError_t e = neat::edit_launch(L, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "edit launch");
+    return NEAT_OK;
+}
+
+int neat_crossover(const neat_dims *d, const float *nodes, const float *conns, int32_t Pc,
+                   const int32_t *pairs, const float *rn, const float *rc, float *child_nodes,
+                   float *child_conns, void *stream) {
+    int rc_ = check_dims(d);
+    if (rc_ != NEAT_OK) return rc_;
+    if (Pc < 0) return fail(NEAT_E_INVALID, "Pc = %d < 0", Pc);
+    if (Pc == 0) return NEAT_OK;
+    if (d->P == 0) return fail(NEAT_E_INVALID, "crossover needs parents (P = 0)");
+    if (!nodes || !pairs || !rn || !child_nodes ||
+        (d->C_max > 0 && (!conns || !rc || !child_conns)))
+        return fail(NEAT_E_INVALID, "a pointer argument is NULL");
+    if (child_conns && !aligned(child_conns, 16))
+        return fail(NEAT_E_INVALID, "child_conns must be 16-byte aligned");
+    const size_t lds = neat::distance_lds_bytes(d->N_max, d->C_max);
+    if (lds > max_lds_bytes())
+        return fail(NEAT_E_TOO_LARGE,
+                    "crossover with N_max=%d, C_max=%d needs %zu B of LDS, device allows %zu",
+                    d->N_max, d->C_max, lds, max_lds_bytes());
+    neat::CrossLaunch L{};
+    L.nodes = nodes, L.conns = conns, L.pairs = pairs, L.rn = rn, L.rc = rc;
+    L.cn = child_nodes, L.cc = child_conns;
+    L.Pc = Pc, L.P = d->P, L.N = d->N_max, L.C = d->C_max;
+    hipError_t e = neat::crossover_launch(L, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "crossover launch");
     return NEAT_OK;
 }
 

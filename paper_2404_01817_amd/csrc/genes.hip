@@ -1,0 +1,332 @@
+// genes.hip -- gene-level population operators: NEAT's compatibility
+// distance and crossover.
+//
+// Compatibility distance of every genome of a population to every species
+// representative (speciation divides the
+// population by distances between networks: the NEAT algorithm of the
+// paper's appendix; Appendix A names the disjoint and homologous
+// coefficients).  Per pair (genome A, representative B):
+//   genes: node rows with a key, connection rows with an in key;
+//   an A gene is homologous when B has a gene with the same key (nodes) or
+//   the same (in, out) keys (connections), its partner being the first
+//   such B row; node distance |bias - bias'| + |resp - resp'| + [act !=
+//   act'] + [agg != agg'], connection distance |w - w'| + [enabled !=
+//   enabled'];
+//   per kind (cd (|A| + |B| - 2 h) + ch sum) / max(|A|, |B|), 0 when both
+//   are empty; the distance is the node part plus the connection part.
+//
+// One wave per genome A, looping over the representatives: B's genes go
+// into LDS hash tables (key bits -> first row, by atomic min), then every
+// lane probes the table with its A genes and the wave sums counts and
+// attribute distances.  Keys are compared as floats: -0 is folded into +0
+// before hashing, and a connection whose out key is NaN never matches.
+#include <hip/hip_runtime.h>
+
+#include "genes.h"
+
+namespace neat {
+namespace {
+
+constexpr int WAVE = 64;
+constexpr unsigned long long EMPTY64 = ~0ull;
+constexpr unsigned EMPTY32 = ~0u;
+
+__device__ __forceinline__ unsigned key_bits(float k) {
+    return __float_as_uint(k == 0.0f ? 0.0f : k);  // -0 -> +0
+}
+
+__device__ __forceinline__ unsigned mix(unsigned long long x, int H) {
+    x ^= x >> 29;
+    x *= 0xbf58476d1ce4e5b9ull;
+    x ^= x >> 32;
+    return (unsigned)x & (unsigned)(H - 1);
+}
+
+__device__ __forceinline__ int wave_sum(int v) {
+    for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+__device__ __forceinline__ float wave_sum(float v) {
+    for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// insert key -> row (keeping the smallest row for a key)
+__device__ __forceinline__ void insert(unsigned long long *hk, int *hr, int H,
+                                       unsigned long long key, int row) {
+    unsigned s = mix(key, H);
+    for (;;) {
+        const unsigned long long prev = atomicCAS(hk + s, EMPTY64, key);
+        if (prev == EMPTY64 || prev == key) {
+            atomicMin(hr + s, row);
+            return;
+        }
+        s = (s + 1) & (unsigned)(H - 1);
+    }
+}
+
+__device__ __forceinline__ int lookup(const unsigned long long *hk, const int *hr, int H,
+                                      unsigned long long key) {
+    unsigned s = mix(key, H);
+    for (;;) {
+        const unsigned long long k = hk[s];
+        if (k == key) return hr[s];
+        if (k == EMPTY64) return -1;
+        s = (s + 1) & (unsigned)(H - 1);
+    }
+}
+
+__global__ __launch_bounds__(WAVE) void distance_kernel(DistLaunch L) {
+    extern __shared__ unsigned long long dsm[];
+    const int N = L.N, C = L.C, HN = L.hn, HC = L.hc;
+    unsigned long long *nk = dsm;            // node table: keys [HN]
+    unsigned long long *ck = nk + HN;        // connection table: keys [HC]
+    int *nr = (int *)(ck + HC);              // rows [HN]
+    int *cr = nr + HN;                       // rows [HC]
+    const long long g = blockIdx.x;
+    const int lane = (int)threadIdx.x;
+    const float *An = L.nodes + (size_t)g * N * 5;
+    const float *Ac = L.conns + (size_t)g * C * 4;
+
+    // A's gene counts (once)
+    int na = 0, ca = 0;
+    for (int r = lane; r < N; r += WAVE) na += !isnan(An[(size_t)r * 5]);
+    for (int r = lane; r < C; r += WAVE) ca += !isnan(Ac[(size_t)r * 4]);
+    na = wave_sum(na);
+    ca = wave_sum(ca);
+
+    for (int q = 0; q < L.Q; ++q) {
+        const float *Bn = L.rnodes + (size_t)q * N * 5;
+        const float *Bc = L.rconns + (size_t)q * C * 4;
+        for (int s = lane; s < HN; s += WAVE) nk[s] = EMPTY64, nr[s] = 0x7fffffff;
+        for (int s = lane; s < HC; s += WAVE) ck[s] = EMPTY64, cr[s] = 0x7fffffff;
+        __syncthreads();
+        int nb = 0, cb = 0;
+        for (int r = lane; r < N; r += WAVE) {
+            const float k = Bn[(size_t)r * 5];
+            if (isnan(k)) continue;
+            ++nb;
+            insert(nk, nr, HN, key_bits(k), r);
+        }
+        for (int r = lane; r < C; r += WAVE) {
+            const float ki = Bc[(size_t)r * 4], ko = Bc[(size_t)r * 4 + 1];
+            if (isnan(ki)) continue;
+            ++cb;
+            if (isnan(ko)) continue;  // can never match
+            insert(ck, cr, HC, ((unsigned long long)key_bits(ki) << 32) | key_bits(ko), r);
+        }
+        __syncthreads();
+        int hn = 0, hc = 0;
+        float sn = 0.0f, sc = 0.0f;
+        for (int r = lane; r < N; r += WAVE) {
+            const float *x = An + (size_t)r * 5;
+            if (isnan(x[0])) continue;
+            const int j = lookup(nk, nr, HN, key_bits(x[0]));
+            if (j < 0) continue;
+            const float *y = Bn + (size_t)j * 5;
+            ++hn;
+            sn += fabsf(x[1] - y[1]) + fabsf(x[2] - y[2]) + (float)(x[3] != y[3]) +
+                  (float)(x[4] != y[4]);
+        }
+        for (int r = lane; r < C; r += WAVE) {
+            const float *x = Ac + (size_t)r * 4;
+            if (isnan(x[0]) || isnan(x[1])) continue;
+            const int j = lookup(ck, cr, HC,
+                                 ((unsigned long long)key_bits(x[0]) << 32) | key_bits(x[1]));
+            if (j < 0) continue;
+            const float *y = Bc + (size_t)j * 4;
+            ++hc;
+            sc += fabsf(x[3] - y[3]) + (float)(x[2] != y[2]);
+        }
+        nb = wave_sum(nb);
+        cb = wave_sum(cb);
+        hn = wave_sum(hn);
+        hc = wave_sum(hc);
+        sn = wave_sum(sn);
+        sc = wave_sum(sc);
+        if (lane == 0) {
+            const int mn = max(na, nb), mc = max(ca, cb);
+            const float dn = mn ? (L.cd * (float)(na + nb - 2 * hn) + L.ch * sn) / (float)mn : 0.0f;
+            const float dc = mc ? (L.cd * (float)(ca + cb - 2 * hc) + L.ch * sc) / (float)mc : 0.0f;
+            L.out[(size_t)g * L.Q + q] = dn + dc;
+        }
+        __syncthreads();  // the tables are cleared for the next representative
+    }
+}
+
+// Crossover (Section 3.2: the genetic operators become row and attribute
+// writes of the tensors; the gene alignment is NEAT's): the child of
+// (p1, p2) keeps p1's rows; a p1 gene homologous in p2 (same node key, or
+// same (in, out) keys; partner = p2's first such row) takes the partner's
+// non-key columns when its uniform number is below 0.5.  One wave per
+// child: p2's genes go into the LDS hash tables, every lane writes its p1
+// rows.
+__global__ __launch_bounds__(WAVE) void crossover_kernel(CrossLaunch L) {
+    extern __shared__ unsigned long long dsm[];
+    const int N = L.N, C = L.C, HN = L.hn, HC = L.hc;
+    unsigned long long *nk = dsm;
+    unsigned long long *ck = nk + HN;
+    int *nr = (int *)(ck + HC);
+    int *cr = nr + HN;
+    const long long k = blockIdx.x;
+    const int lane = (int)threadIdx.x;
+    const int a = L.pairs[2 * k], b = L.pairs[2 * k + 1];
+    if (a < 0 || a >= L.P || b < 0 || b >= L.P) {  // uniform: the whole wave leaves
+        for (int e = lane; e < N * 5; e += WAVE) L.cn[(size_t)k * N * 5 + e] = __builtin_nanf("");
+        for (int e = lane; e < C * 4; e += WAVE) L.cc[(size_t)k * C * 4 + e] = __builtin_nanf("");
+        return;
+    }
+    const float *An = L.nodes + (size_t)a * N * 5, *Ac = L.conns + (size_t)a * C * 4;
+    const float *Bn = L.nodes + (size_t)b * N * 5, *Bc = L.conns + (size_t)b * C * 4;
+    float *On = L.cn + (size_t)k * N * 5, *Oc = L.cc + (size_t)k * C * 4;
+    for (int s = lane; s < HN; s += WAVE) nk[s] = EMPTY64, nr[s] = 0x7fffffff;
+    for (int s = lane; s < HC; s += WAVE) ck[s] = EMPTY64, cr[s] = 0x7fffffff;
+    __syncthreads();
+    for (int r = lane; r < N; r += WAVE) {
+        const float key = Bn[(size_t)r * 5];
+        if (!isnan(key)) insert(nk, nr, HN, key_bits(key), r);
+    }
+    for (int r = lane; r < C; r += WAVE) {
+        const float ki = Bc[(size_t)r * 4], ko = Bc[(size_t)r * 4 + 1];
+        if (!isnan(ki) && !isnan(ko))
+            insert(ck, cr, HC, ((unsigned long long)key_bits(ki) << 32) | key_bits(ko), r);
+    }
+    __syncthreads();
+    for (int r = lane; r < N; r += WAVE) {
+        const float *x = An + (size_t)r * 5;
+        const float *src = x;
+        if (!isnan(x[0]) && L.rn[(size_t)k * N + r] < 0.5f) {
+            const int j = lookup(nk, nr, HN, key_bits(x[0]));
+            if (j >= 0) src = Bn + (size_t)j * 5;
+        }
+        float *o = On + (size_t)r * 5;
+        o[0] = x[0];
+#pragma unroll
+        for (int c = 1; c < 5; ++c) o[c] = src[c];
+    }
+    for (int r = lane; r < C; r += WAVE) {
+        const float *x = Ac + (size_t)r * 4;
+        const float *src = x;
+        if (!isnan(x[0]) && !isnan(x[1]) && L.rc[(size_t)k * C + r] < 0.5f) {
+            const int j = lookup(ck, cr, HC,
+                                 ((unsigned long long)key_bits(x[0]) << 32) | key_bits(x[1]));
+            if (j >= 0) src = Bc + (size_t)j * 4;
+        }
+        float4 v = make_float4(x[0], x[1], src[2], src[3]);
+        *reinterpret_cast<float4 *>(Oc + (size_t)r * 4) = v;
+    }
+}
+
+// Tensorized edits (Section 3.2): additions at the first NaN row, NaN
+// removals, attribute writes; a genome's edits in their order, genomes in
+// parallel.  One wave per genome finds its edits by binary search over the
+// genome-sorted list and keeps its rows' key columns in LDS (the first-NaN
+// searches read only keys).  Column c of a row is always written by lane c,
+// so two edits of one address are ordered by that lane's program order.
+__global__ __launch_bounds__(256) void edit_clear_kernel(int32_t *applied, int n) {
+    const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) applied[i] = 0;
+}
+
+__device__ __forceinline__ int edits_lower_bound(const EditRec *e, int n, int g) {
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (e[mid].genome < g) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(WAVE) void edit_kernel(EditLaunch L) {
+    extern __shared__ float ks[];  // node keys [N], then connection in keys [C]
+    const int g = (int)blockIdx.x, lane = (int)threadIdx.x;
+    const int N = L.N, C = L.C;
+    const int lo = edits_lower_bound(L.edits, L.n, g), hi = edits_lower_bound(L.edits, L.n, g + 1);
+    if (lo >= hi) return;
+    float *gn = L.nodes + (size_t)g * N * 5, *gc = L.conns + (size_t)g * C * 4;
+    for (int r = lane; r < N; r += WAVE) ks[r] = gn[(size_t)r * 5];
+    for (int r = lane; r < C; r += WAVE) ks[N + r] = gc[(size_t)r * 4];
+    __syncthreads();
+    for (int e = lo; e < hi; ++e) {
+        const EditRec d = L.edits[e];
+        // this lane's column value of an added row (selects, not an indexed
+        // private array)
+        const float vl = lane == 0 ? d.v[0] : lane == 1 ? d.v[1] : lane == 2 ? d.v[2]
+                       : lane == 3 ? d.v[3] : d.v[4];
+        const bool node = d.op == 0 || d.op == 1 || d.op == 4;
+        float *t = node ? gn : gc;
+        const int rows = node ? N : C, w = node ? 5 : 4, kb = node ? 0 : N;
+        int row = -1;
+        if (d.genome == g && (d.op == 0 || d.op == 2)) {
+            // first NaN key, 64 rows at a time
+            for (int c0 = 0; c0 < rows && row < 0; c0 += WAVE) {
+                const bool nan_row = c0 + lane < rows && isnan(ks[kb + c0 + lane]);
+                const unsigned long long m = __ballot(nan_row);
+                if (m) row = c0 + __ffsll((long long)m) - 1;
+            }
+            if (row >= 0) {
+                if (lane < w) t[(size_t)row * w + lane] = vl;
+                if (lane == 0) ks[kb + row] = d.v[0];
+            }
+        } else if (d.genome == g && (d.op == 1 || d.op == 3)) {
+            if (d.row >= 0 && d.row < rows) {
+                row = d.row;
+                if (lane < w) t[(size_t)row * w + lane] = __builtin_nanf("");
+                if (lane == 0) ks[kb + row] = __builtin_nanf("");
+            }
+        } else if (d.genome == g && (d.op == 4 || d.op == 5)) {
+            const bool ok = d.row >= 0 && d.row < rows &&
+                            (node ? (d.column >= 1 && d.column <= 4) : (d.column >= 2 && d.column <= 3));
+            if (ok) {
+                row = d.row;
+                if (lane == d.column) t[(size_t)row * w + lane] = d.v[0];
+            }
+        }
+        if (lane == 0 && row >= 0) L.applied[e] = 1;
+        __syncthreads();  // key updates visible to the next edit's search
+    }
+}
+
+int pow2_at_least(int x) {
+    int h = 64;
+    while (h < x) h <<= 1;
+    return h;
+}
+
+}  // namespace
+
+size_t distance_lds_bytes(int N, int C) {
+    const int hn = pow2_at_least(2 * N), hc = pow2_at_least(2 * C);
+    return (size_t)(hn + hc) * (sizeof(unsigned long long) + sizeof(int));
+}
+
+hipError_t crossover_launch(CrossLaunch L, hipStream_t stream) {
+    L.hn = pow2_at_least(2 * L.N);
+    L.hc = pow2_at_least(2 * L.C);
+    if (L.Pc == 0) return hipSuccess;
+    hipLaunchKernelGGL(crossover_kernel, dim3((unsigned)L.Pc), dim3(WAVE),
+                       distance_lds_bytes(L.N, L.C), stream, L);
+    return hipGetLastError();
+}
+
+hipError_t edit_launch(EditLaunch L, hipStream_t stream) {
+    if (L.n == 0) return hipSuccess;
+    hipLaunchKernelGGL(edit_clear_kernel, dim3((unsigned)((L.n + 255) / 256)), dim3(256), 0,
+                       stream, L.applied, L.n);
+    if (L.P == 0) return hipGetLastError();
+    hipLaunchKernelGGL(edit_kernel, dim3((unsigned)L.P), dim3(WAVE),
+                       sizeof(float) * (size_t)(L.N + L.C), stream, L);
+    return hipGetLastError();
+}
+
+hipError_t distance_launch(DistLaunch L, hipStream_t stream) {
+    L.hn = pow2_at_least(2 * L.N);
+    L.hc = pow2_at_least(2 * L.C);
+    if (L.P == 0 || L.Q == 0) return hipSuccess;
+    hipLaunchKernelGGL(distance_kernel, dim3((unsigned)L.P), dim3(WAVE),
+                       distance_lds_bytes(L.N, L.C), stream, L);
+    return hipGetLastError();
+}
+
+}  // namespace neat

@@ -1,0 +1,227 @@
+"""GPU parity of the gene-level operators, through the C ABI, against the
+CPU oracle: the compatibility distance (neat_distance) within
+|d - d64| <= 1e-6 + 2 * bound (the oracle's fp32 bound; the kernel adds
+each wave's partial sums in tree order), and crossover (neat_crossover) bit
+for bit (it only moves data)."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2404_01817_amd import synth
+from tests.helpers import genome, stack
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _gpu(nodes, conns, rnodes, rconns, cd=1.0, ch=0.5):
+    import paper_2404_01817_amd as neat
+    dev = torch.device("cuda:0")
+    t = [torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in (nodes, conns, rnodes, rconns)]
+    d = neat.distance(*t, c_disjoint=cd, c_homologous=ch)
+    torch.cuda.synchronize()
+    return d.cpu().numpy()
+
+
+def _check(d, nodes, conns, rnodes, rconns, cd=1.0, ch=0.5):
+    d64, bound = oracle.distance(nodes, conns, rnodes, rconns, cd, ch)
+    both_nan = np.isnan(d64) & np.isnan(d)
+    err = np.abs(d.astype(np.float64) - d64)
+    bad = ~both_nan & ~(err <= 1e-6 + 2 * bound)
+    assert not bad.any(), (np.argwhere(bad)[:5], d[bad][:5], d64[bad][:5])
+
+
+@pytest.mark.parametrize("P,Q,N,C", [(50, 7, 12, 30), (40, 16, 50, 200), (9, 5, 150, 600),
+                                     (5, 3, 400, 1600), (70, 1, 8, 0)])
+def test_distance_parity(P, Q, N, C):
+    print("case", P, Q, N, C, flush=True)
+    rng = np.random.default_rng(P + N)
+    I, O = 3, 2
+    pop = synth.make_population(rng, P, N, C, I, O, N - I - O, synth._k_uniform(max(C, 1)),
+                                synth.CONTROL_ACTS, synth.ALL_AGGS)
+    # representatives: mutated copies of some genomes (homologous genes with
+    # moved attributes) and unrelated genomes
+    rn, rc = pop.nodes[:Q].copy(), pop.conns[:Q].copy()
+    rn[:, :, 1] += rng.normal(0, 0.3, rn.shape[:2]).astype(np.float32)
+    if C:
+        rc[:, :, 3] += rng.normal(0, 0.3, rc.shape[:2]).astype(np.float32)
+        rc[::2, ::3, 2] = 1.0 - rc[::2, ::3, 2]
+    _check(_gpu(pop.nodes, pop.conns, rn, rc), pop.nodes, pop.conns, rn, rc)
+
+
+def test_distance_hand_pair_and_special_keys():
+    """The oracle's hand-computed pair, plus -0 against +0 keys and NaN out
+    keys (which never match), planted in a second pair."""
+    from tests.test_oracle_distance import _pair
+    (an, ac), (bn, bc) = _pair()
+    an2, ac2, bn2, bc2 = an.copy(), ac.copy(), bn.copy(), bc.copy()
+    an2[0, 0, 0] = -0.0                       # key -0 matches B's key 0
+    ac2[0, 1, 1] = np.nan                     # present gene, never homologous
+    bc2[0, 0] = (-0.0, 5.0, 1.0, 0.5)         # matches A's 0 -> 5
+    n, c = stack([(an, ac), (an2, ac2)])
+    rn, rc = stack([(bn, bc), (bn2, bc2)])
+    d = _gpu(n, c, rn, rc)
+    assert d[0, 0] == pytest.approx(59.0 / 24.0, rel=1e-6)
+    _check(d, n, c, rn, rc)
+
+
+def test_distance_coefficients_and_identity():
+    pop = synth.control(seed=8, P=30, B=1)
+    d = _gpu(pop.nodes, pop.conns, pop.nodes[:10], pop.conns[:10], cd=2.0, ch=0.25)
+    assert np.all(np.diag(d[:10]) == 0.0)
+    _check(d, pop.nodes, pop.conns, pop.nodes[:10], pop.conns[:10], 2.0, 0.25)
+
+
+def test_distance_errors_and_empty():
+    import paper_2404_01817_amd as neat
+    dev = torch.device("cuda:0")
+    pop = synth.control(seed=9, P=4, B=1)
+    t = [torch.from_numpy(a).to(dev) for a in (pop.nodes, pop.conns)]
+    d = neat.distance(t[0], t[1], t[0][:0], t[1][:0])
+    assert d.shape == (4, 0)
+    big_n = torch.full((1, 64, 5), float("nan"), device=dev)
+    big_c = torch.full((1, 16384, 4), float("nan"), device=dev)
+    with pytest.raises(neat.NeatError) as e:
+        neat.distance(big_n, big_c, big_n, big_c)
+    assert e.value.code == -4  # NEAT_E_TOO_LARGE
+    torch.cuda.synchronize()
+
+
+def test_distance_full_size_sampled():
+    """The benchmark's distance workload (P=10000 control genomes against
+    Q=64 representatives) in its launch configuration; sampled rows checked
+    against the oracle."""
+    pop = synth.control(B=1)
+    rep = synth.control(seed=7, P=64, B=1)
+    d = _gpu(pop.nodes, pop.conns, rep.nodes, rep.conns)
+    rows = np.concatenate([np.random.default_rng(0).choice(pop.P, 200, replace=False),
+                           [0, pop.P - 1]])
+    _check(d[rows], pop.nodes[rows], pop.conns[rows], rep.nodes, rep.conns)
+
+
+# ------------------------------------------------------------- crossover
+def _gpu_cross(nodes, conns, pairs, rn, rc):
+    import paper_2404_01817_amd as neat
+    dev = torch.device("cuda:0")
+    t = [torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+         for a in (nodes, conns, pairs.astype(np.int32), rn.astype(np.float32),
+                   rc.astype(np.float32))]
+    cn, cc = neat.crossover(*t)
+    torch.cuda.synchronize()
+    return cn.cpu().numpy(), cc.cpu().numpy()
+
+
+def _bits(a):
+    return np.ascontiguousarray(a).view(np.uint32)
+
+
+@pytest.mark.parametrize("P,N,C", [(30, 12, 30), (40, 50, 200), (9, 150, 600), (6, 400, 1600),
+                                   (20, 8, 0)])
+def test_crossover_bit_exact(P, N, C):
+    print("case", P, N, C, flush=True)
+    rng = np.random.default_rng(N + C)
+    pop = synth.make_population(rng, P, N, C, 3, 2, N - 5, synth._k_uniform(max(C, 1)),
+                                synth.CONTROL_ACTS, synth.ALL_AGGS)
+    # second parents share genes with the first: mutated copies
+    n, c = pop.nodes.copy(), pop.conns.copy()
+    half = P // 2
+    n[half:] = pop.nodes[:P - half]
+    c[half:] = pop.conns[:P - half]
+    n[half:, :, 1] += rng.normal(0, 1, (P - half, N)).astype(np.float32)
+    if C:
+        c[half:, :, 3] += rng.normal(0, 1, (P - half, C)).astype(np.float32)
+    Pc = 2 * P
+    pairs = rng.integers(0, P, (Pc, 2)).astype(np.int32)
+    rn = rng.random((Pc, N)).astype(np.float32)
+    rc = rng.random((Pc, C)).astype(np.float32)
+    rn[::3, ::2] = 0.5          # exactly 0.5: the first parent's attributes
+    g = _gpu_cross(n, c, pairs, rn, rc)
+    o = oracle.crossover(n, c, pairs, rn, rc)
+    assert np.array_equal(_bits(g[0]), _bits(o[0]))
+    assert np.array_equal(_bits(g[1]), _bits(o[1]))
+
+
+def test_crossover_bad_pair_gives_nan_child():
+    pop = synth.control(seed=12, P=6, B=1)
+    pairs = np.array([[0, 1], [2, 6], [-1, 3], [4, 5]], np.int32)
+    rn = np.zeros((4, 50), np.float32)
+    rc = np.zeros((4, 200), np.float32)
+    cn, cc = _gpu_cross(pop.nodes, pop.conns, pairs, rn, rc)
+    assert np.all(np.isnan(cn[1])) and np.all(np.isnan(cn[2]))
+    assert np.all(np.isnan(cc[1])) and np.all(np.isnan(cc[2]))
+    o = oracle.crossover(pop.nodes, pop.conns, pairs[[0, 3]], rn[:2], rc[:2])
+    assert np.array_equal(_bits(cn[[0, 3]]), _bits(o[0]))
+    assert np.array_equal(_bits(cc[[0, 3]]), _bits(o[1]))
+
+
+def test_crossover_full_size():
+    """The benchmark's crossover workload: 10000 children of control-genome
+    pairs, every child compared bit for bit."""
+    pop = synth.control(B=1, with_inputs=False)
+    rng = np.random.default_rng(13)
+    pairs = rng.integers(0, pop.P, (pop.P, 2)).astype(np.int32)
+    rn = rng.random((pop.P, 50)).astype(np.float32)
+    rc = rng.random((pop.P, 200)).astype(np.float32)
+    g = _gpu_cross(pop.nodes, pop.conns, pairs, rn, rc)
+    o = oracle.crossover(pop.nodes, pop.conns, pairs, rn, rc)
+    assert np.array_equal(_bits(g[0]), _bits(o[0]))
+    assert np.array_equal(_bits(g[1]), _bits(o[1]))
+
+
+# --------------------------------------------------------- tensorized edits
+def _gpu_edit(nodes, conns, edits):
+    import paper_2404_01817_amd as neat
+    dev = torch.device("cuda:0")
+    tn = torch.from_numpy(np.ascontiguousarray(nodes)).to(dev)
+    tc = torch.from_numpy(np.ascontiguousarray(conns)).to(dev)
+    te = torch.from_numpy(np.ascontiguousarray(edits).view(np.uint8).copy()).to(dev)
+    applied = neat.edit(tn, tc, te)
+    torch.cuda.synchronize()
+    return tn.cpu().numpy(), tc.cpu().numpy(), applied.cpu().numpy()
+
+
+def _random_edits(rng, P, N, C, n):
+    e = np.zeros(n, oracle.EDIT_DTYPE)
+    e["genome"] = np.sort(rng.integers(0, P, n))
+    e["op"] = rng.integers(0, 6, n)
+    e["row"] = rng.integers(-2, max(N, C) + 2, n)
+    e["column"] = rng.integers(0, 5, n)
+    e["v"] = rng.normal(size=(n, 5)).astype(np.float32)
+    e["v"][:, 0] = rng.integers(100, 900, n)          # keys of added rows
+    return e
+
+
+@pytest.mark.parametrize("P,N,C,n", [(20, 12, 30, 400), (50, 50, 200, 3000),
+                                     (5, 300, 1200, 2000), (8, 8, 0, 100)])
+def test_edits_bit_exact(P, N, C, n):
+    print("case", P, N, C, n, flush=True)
+    rng = np.random.default_rng(P + n)
+    pop = synth.make_population(rng, P, N, C, 3, 2, N - 5, synth._k_uniform(max(C, 1)),
+                                synth.CONTROL_ACTS, synth.ALL_AGGS)
+    e = _random_edits(rng, P, N, C, n)
+    gn, gc, ga = _gpu_edit(pop.nodes, pop.conns, e)
+    on, oc, oa = oracle.edit(pop.nodes, pop.conns, e)
+    assert np.array_equal(ga, oa)
+    assert np.array_equal(_bits(gn), _bits(on)) and np.array_equal(_bits(gc), _bits(oc))
+    assert 0 < ga.sum() < n
+
+
+def test_edits_fill_and_overflow():
+    """More additions than NaN rows: the surplus does not apply; genomes
+    without edits are untouched."""
+    pop = synth.control(seed=15, P=6, B=1)
+    rows = []
+    for g in (1, 4):
+        for k in range(40):
+            rows.append((g, oracle.NODE_ADD, 0, 0, (500 + k, 0.5, 1, 1, 0, )))
+    e = np.zeros(len(rows), oracle.EDIT_DTYPE)
+    for i, (g, op, r, c, v) in enumerate(rows):
+        e[i] = (g, op, r, c, v)
+    gn, gc, ga = _gpu_edit(pop.nodes, pop.conns, e)
+    on, oc, oa = oracle.edit(pop.nodes, pop.conns, e)
+    assert np.array_equal(ga, oa) and np.array_equal(_bits(gn), _bits(on))
+    assert np.all(~np.isnan(gn[[1, 4], :, 0]))
+    assert np.array_equal(_bits(gn[[0, 2, 3, 5]]), _bits(pop.nodes[[0, 2, 3, 5]]))
