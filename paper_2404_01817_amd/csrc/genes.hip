@@ -15,10 +15,11 @@
 //   per kind (cd (|A| + |B| - 2 h) + ch sum) / max(|A|, |B|), 0 when both
 //   are empty; the distance is the node part plus the connection part.
 //
-// One wave per genome A, looping over the representatives: B's genes go
-// into LDS hash tables (key bits -> first row, by atomic min), then every
-// lane probes the table with its A genes and the wave sums counts and
-// attribute distances.  Keys are compared as floats: -0 is folded into +0
+// A workgroup takes eight genomes (two per wave) and loops over the
+// representatives: B's genes go into LDS hash tables (key bits -> first
+// row, by atomic min), built once for the eight, then every lane probes the
+// tables with its A genes and each wave sums counts and attribute
+// distances.  Keys are compared as floats: -0 is folded into +0
 // before hashing, and a connection whose out key is NaN never matches.
 #include <hip/hip_runtime.h>
 
@@ -76,79 +77,109 @@ __device__ __forceinline__ int lookup(const unsigned long long *hk, const int *h
     }
 }
 
-__global__ __launch_bounds__(WAVE) void distance_kernel(DistLaunch L) {
+// DIST_WAVES waves per workgroup, DIST_PER_WAVE genomes per wave: a
+// representative's tables are built once for DIST_WAVES * DIST_PER_WAVE
+// genomes.
+constexpr int DIST_WAVES = 4, DIST_PER_WAVE = 2;
+constexpr int DIST_GENOMES = DIST_WAVES * DIST_PER_WAVE;
+
+__global__ __launch_bounds__(WAVE *DIST_WAVES) void distance_kernel(DistLaunch L) {
     extern __shared__ unsigned long long dsm[];
     const int N = L.N, C = L.C, HN = L.hn, HC = L.hc;
     unsigned long long *nk = dsm;            // node table: keys [HN]
     unsigned long long *ck = nk + HN;        // connection table: keys [HC]
     int *nr = (int *)(ck + HC);              // rows [HN]
     int *cr = nr + HN;                       // rows [HC]
-    const long long g = blockIdx.x;
-    const int lane = (int)threadIdx.x;
-    const float *An = L.nodes + (size_t)g * N * 5;
-    const float *Ac = L.conns + (size_t)g * C * 4;
+    int *bcount = cr + HC;                   // B's node and connection genes
+    const int t = (int)threadIdx.x, lane = t & (WAVE - 1), wave = t / WAVE;
+    const int T = WAVE * DIST_WAVES;
 
-    // A's gene counts (once)
-    int na = 0, ca = 0;
-    for (int r = lane; r < N; r += WAVE) na += !isnan(An[(size_t)r * 5]);
-    for (int r = lane; r < C; r += WAVE) ca += !isnan(Ac[(size_t)r * 4]);
-    na = wave_sum(na);
-    ca = wave_sum(ca);
+    // this wave's genomes and their gene counts (once)
+    long long gs[DIST_PER_WAVE];
+    int na[DIST_PER_WAVE], ca[DIST_PER_WAVE];
+#pragma unroll
+    for (int i = 0; i < DIST_PER_WAVE; ++i) {
+        gs[i] = (long long)blockIdx.x * DIST_GENOMES + wave * DIST_PER_WAVE + i;
+        int a = 0, c = 0;
+        if (gs[i] < L.P) {
+            const float *An = L.nodes + (size_t)gs[i] * N * 5;
+            const float *Ac = L.conns + (size_t)gs[i] * C * 4;
+            for (int r = lane; r < N; r += WAVE) a += !isnan(An[(size_t)r * 5]);
+            for (int r = lane; r < C; r += WAVE) c += !isnan(Ac[(size_t)r * 4]);
+        }
+        na[i] = wave_sum(a);
+        ca[i] = wave_sum(c);
+    }
 
     for (int q = 0; q < L.Q; ++q) {
         const float *Bn = L.rnodes + (size_t)q * N * 5;
         const float *Bc = L.rconns + (size_t)q * C * 4;
-        for (int s = lane; s < HN; s += WAVE) nk[s] = EMPTY64, nr[s] = 0x7fffffff;
-        for (int s = lane; s < HC; s += WAVE) ck[s] = EMPTY64, cr[s] = 0x7fffffff;
+        for (int s = t; s < HN; s += T) nk[s] = EMPTY64, nr[s] = 0x7fffffff;
+        for (int s = t; s < HC; s += T) ck[s] = EMPTY64, cr[s] = 0x7fffffff;
+        if (t < 2) bcount[t] = 0;
         __syncthreads();
         int nb = 0, cb = 0;
-        for (int r = lane; r < N; r += WAVE) {
+        for (int r = t; r < N; r += T) {
             const float k = Bn[(size_t)r * 5];
             if (isnan(k)) continue;
             ++nb;
             insert(nk, nr, HN, key_bits(k), r);
         }
-        for (int r = lane; r < C; r += WAVE) {
+        for (int r = t; r < C; r += T) {
             const float ki = Bc[(size_t)r * 4], ko = Bc[(size_t)r * 4 + 1];
             if (isnan(ki)) continue;
             ++cb;
             if (isnan(ko)) continue;  // can never match
             insert(ck, cr, HC, ((unsigned long long)key_bits(ki) << 32) | key_bits(ko), r);
         }
-        __syncthreads();
-        int hn = 0, hc = 0;
-        float sn = 0.0f, sc = 0.0f;
-        for (int r = lane; r < N; r += WAVE) {
-            const float *x = An + (size_t)r * 5;
-            if (isnan(x[0])) continue;
-            const int j = lookup(nk, nr, HN, key_bits(x[0]));
-            if (j < 0) continue;
-            const float *y = Bn + (size_t)j * 5;
-            ++hn;
-            sn += fabsf(x[1] - y[1]) + fabsf(x[2] - y[2]) + (float)(x[3] != y[3]) +
-                  (float)(x[4] != y[4]);
-        }
-        for (int r = lane; r < C; r += WAVE) {
-            const float *x = Ac + (size_t)r * 4;
-            if (isnan(x[0]) || isnan(x[1])) continue;
-            const int j = lookup(ck, cr, HC,
-                                 ((unsigned long long)key_bits(x[0]) << 32) | key_bits(x[1]));
-            if (j < 0) continue;
-            const float *y = Bc + (size_t)j * 4;
-            ++hc;
-            sc += fabsf(x[3] - y[3]) + (float)(x[2] != y[2]);
-        }
         nb = wave_sum(nb);
         cb = wave_sum(cb);
-        hn = wave_sum(hn);
-        hc = wave_sum(hc);
-        sn = wave_sum(sn);
-        sc = wave_sum(sc);
         if (lane == 0) {
-            const int mn = max(na, nb), mc = max(ca, cb);
-            const float dn = mn ? (L.cd * (float)(na + nb - 2 * hn) + L.ch * sn) / (float)mn : 0.0f;
-            const float dc = mc ? (L.cd * (float)(ca + cb - 2 * hc) + L.ch * sc) / (float)mc : 0.0f;
-            L.out[(size_t)g * L.Q + q] = dn + dc;
+            atomicAdd(bcount, nb);
+            atomicAdd(bcount + 1, cb);
+        }
+        __syncthreads();
+        nb = bcount[0];
+        cb = bcount[1];
+#pragma unroll
+        for (int i = 0; i < DIST_PER_WAVE; ++i) {
+            if (gs[i] >= L.P) continue;  // uniform across the wave
+            const float *An = L.nodes + (size_t)gs[i] * N * 5;
+            const float *Ac = L.conns + (size_t)gs[i] * C * 4;
+            int hn = 0, hc = 0;
+            float sn = 0.0f, sc = 0.0f;
+            for (int r = lane; r < N; r += WAVE) {
+                const float *x = An + (size_t)r * 5;
+                if (isnan(x[0])) continue;
+                const int j = lookup(nk, nr, HN, key_bits(x[0]));
+                if (j < 0) continue;
+                const float *y = Bn + (size_t)j * 5;
+                ++hn;
+                sn += fabsf(x[1] - y[1]) + fabsf(x[2] - y[2]) + (float)(x[3] != y[3]) +
+                      (float)(x[4] != y[4]);
+            }
+            for (int r = lane; r < C; r += WAVE) {
+                const float *x = Ac + (size_t)r * 4;
+                if (isnan(x[0]) || isnan(x[1])) continue;
+                const int j = lookup(ck, cr, HC,
+                                     ((unsigned long long)key_bits(x[0]) << 32) | key_bits(x[1]));
+                if (j < 0) continue;
+                const float *y = Bc + (size_t)j * 4;
+                ++hc;
+                sc += fabsf(x[3] - y[3]) + (float)(x[2] != y[2]);
+            }
+            hn = wave_sum(hn);
+            hc = wave_sum(hc);
+            sn = wave_sum(sn);
+            sc = wave_sum(sc);
+            if (lane == 0) {
+                const int mn = max(na[i], nb), mc = max(ca[i], cb);
+                const float dn =
+                    mn ? (L.cd * (float)(na[i] + nb - 2 * hn) + L.ch * sn) / (float)mn : 0.0f;
+                const float dc =
+                    mc ? (L.cd * (float)(ca[i] + cb - 2 * hc) + L.ch * sc) / (float)mc : 0.0f;
+                L.out[(size_t)gs[i] * L.Q + q] = dn + dc;
+            }
         }
         __syncthreads();  // the tables are cleared for the next representative
     }
@@ -298,7 +329,7 @@ int pow2_at_least(int x) {
 
 size_t distance_lds_bytes(int N, int C) {
     const int hn = pow2_at_least(2 * N), hc = pow2_at_least(2 * C);
-    return (size_t)(hn + hc) * (sizeof(unsigned long long) + sizeof(int));
+    return (size_t)(hn + hc) * (sizeof(unsigned long long) + sizeof(int)) + 2 * sizeof(int);
 }
 
 hipError_t crossover_launch(CrossLaunch L, hipStream_t stream) {
@@ -324,8 +355,8 @@ hipError_t distance_launch(DistLaunch L, hipStream_t stream) {
     L.hn = pow2_at_least(2 * L.N);
     L.hc = pow2_at_least(2 * L.C);
     if (L.P == 0 || L.Q == 0) return hipSuccess;
-    hipLaunchKernelGGL(distance_kernel, dim3((unsigned)L.P), dim3(WAVE),
-                       distance_lds_bytes(L.N, L.C), stream, L);
+    hipLaunchKernelGGL(distance_kernel, dim3((unsigned)((L.P + DIST_GENOMES - 1) / DIST_GENOMES)),
+                       dim3(WAVE * DIST_WAVES), distance_lds_bytes(L.N, L.C), stream, L);
     return hipGetLastError();
 }
 
