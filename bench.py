@@ -352,16 +352,15 @@ def bench_distance(args, torch, neat, synth):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / args.steps
     pairs = pop.P * rep.P
-    # algorithmic bytes: every genome's rows once (nodes 20 B, connections
-    # 16 B per row), every representative's rows once per genome (the
-    # kernel reads them from L2), the distances
+    # algorithmic HBM bytes: every genome's rows once (nodes 20 B,
+    # connections 16 B per row), the representatives once (they stay in
+    # L2), the distances
     gbytes = pop.P * (pop.nodes.shape[1] * 20 + pop.conns.shape[1] * 16)
     rbytes = rep.P * (rep.nodes.shape[1] * 20 + rep.conns.shape[1] * 16)
     return {"workload": "compatibility distance: P=%d control genomes (N_max=50, C_max=200) "
                         "against Q=64 representatives" % pop.P,
             "ms": round(ms, 4), "value": round(pairs / (ms / 1e3), 1), "unit": "pairs/s",
-            "hbm_GBps": round((gbytes + rbytes + pairs * 4) / (ms / 1e3) / 1e9, 1),
-            "l2_GBps": round((gbytes + pop.P * rbytes) / (ms / 1e3) / 1e9, 1)}
+            "hbm_GBps": round((gbytes + rbytes + pairs * 4) / (ms / 1e3) / 1e9, 1)}
 
 
 def bench_crossover(args, torch, neat, synth):

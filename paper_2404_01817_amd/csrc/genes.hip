@@ -66,6 +66,16 @@ __device__ __forceinline__ void insert(unsigned long long *hk, int *hr, int H,
     }
 }
 
+__device__ __forceinline__ int lookup_from(const unsigned long long *hk, const int *hr, int H,
+                                           unsigned long long key, unsigned s) {
+    for (;;) {
+        const unsigned long long k = hk[s];
+        if (k == key) return hr[s];
+        if (k == EMPTY64) return -1;
+        s = (s + 1) & (unsigned)(H - 1);
+    }
+}
+
 __device__ __forceinline__ int lookup(const unsigned long long *hk, const int *hr, int H,
                                       unsigned long long key) {
     unsigned s = mix(key, H);
@@ -83,6 +93,12 @@ __device__ __forceinline__ int lookup(const unsigned long long *hk, const int *h
 constexpr int DIST_WAVES = 4, DIST_PER_WAVE = 2;
 constexpr int DIST_GENOMES = DIST_WAVES * DIST_PER_WAVE;
 
+// SMALL (N_max <= 64, C_max <= 256): every lane keeps its genes' keys,
+// attributes and first hash slots in registers for the whole loop over the
+// representatives (one node row and up to four connection rows per genome).
+constexpr int SMALL_CONN_ROWS = 4;
+
+template <bool SMALL>
 __global__ __launch_bounds__(WAVE *DIST_WAVES) void distance_kernel(DistLaunch L) {
     extern __shared__ unsigned long long dsm[];
     const int N = L.N, C = L.C, HN = L.hn, HC = L.hc;
@@ -97,6 +113,11 @@ __global__ __launch_bounds__(WAVE *DIST_WAVES) void distance_kernel(DistLaunch L
     // this wave's genomes and their gene counts (once)
     long long gs[DIST_PER_WAVE];
     int na[DIST_PER_WAVE], ca[DIST_PER_WAVE];
+    // SMALL: the lane's genes (node row lane, connection rows lane + 64 m)
+    float xn[DIST_PER_WAVE][5];
+    unsigned xns[DIST_PER_WAVE];
+    float xc[DIST_PER_WAVE][SMALL_CONN_ROWS][4];
+    unsigned xcs[DIST_PER_WAVE][SMALL_CONN_ROWS];
 #pragma unroll
     for (int i = 0; i < DIST_PER_WAVE; ++i) {
         gs[i] = (long long)blockIdx.x * DIST_GENOMES + wave * DIST_PER_WAVE + i;
@@ -106,6 +127,23 @@ __global__ __launch_bounds__(WAVE *DIST_WAVES) void distance_kernel(DistLaunch L
             const float *Ac = L.conns + (size_t)gs[i] * C * 4;
             for (int r = lane; r < N; r += WAVE) a += !isnan(An[(size_t)r * 5]);
             for (int r = lane; r < C; r += WAVE) c += !isnan(Ac[(size_t)r * 4]);
+            if constexpr (SMALL) {
+                const bool in = lane < N;
+#pragma unroll
+                for (int f = 0; f < 5; ++f)
+                    xn[i][f] = in ? An[(size_t)lane * 5 + f] : __builtin_nanf("");
+                xns[i] = mix(key_bits(xn[i][0]), HN);
+#pragma unroll
+                for (int m = 0; m < SMALL_CONN_ROWS; ++m) {
+                    const int r = lane + WAVE * m;
+#pragma unroll
+                    for (int f = 0; f < 4; ++f)
+                        xc[i][m][f] = r < C ? Ac[(size_t)r * 4 + f] : __builtin_nanf("");
+                    xcs[i][m] = mix(((unsigned long long)key_bits(xc[i][m][0]) << 32) |
+                                        key_bits(xc[i][m][1]),
+                                    HC);
+                }
+            }
         }
         na[i] = wave_sum(a);
         ca[i] = wave_sum(c);
@@ -148,25 +186,50 @@ __global__ __launch_bounds__(WAVE *DIST_WAVES) void distance_kernel(DistLaunch L
             const float *Ac = L.conns + (size_t)gs[i] * C * 4;
             int hn = 0, hc = 0;
             float sn = 0.0f, sc = 0.0f;
-            for (int r = lane; r < N; r += WAVE) {
-                const float *x = An + (size_t)r * 5;
-                if (isnan(x[0])) continue;
-                const int j = lookup(nk, nr, HN, key_bits(x[0]));
-                if (j < 0) continue;
-                const float *y = Bn + (size_t)j * 5;
-                ++hn;
-                sn += fabsf(x[1] - y[1]) + fabsf(x[2] - y[2]) + (float)(x[3] != y[3]) +
-                      (float)(x[4] != y[4]);
-            }
-            for (int r = lane; r < C; r += WAVE) {
-                const float *x = Ac + (size_t)r * 4;
-                if (isnan(x[0]) || isnan(x[1])) continue;
-                const int j = lookup(ck, cr, HC,
-                                     ((unsigned long long)key_bits(x[0]) << 32) | key_bits(x[1]));
-                if (j < 0) continue;
-                const float *y = Bc + (size_t)j * 4;
-                ++hc;
-                sc += fabsf(x[3] - y[3]) + (float)(x[2] != y[2]);
+            if constexpr (SMALL) {
+                const float *x = xn[i];
+                if (!isnan(x[0])) {
+                    const int j = lookup_from(nk, nr, HN, key_bits(x[0]), xns[i]);
+                    if (j >= 0) {
+                        const float *y = Bn + (size_t)j * 5;
+                        ++hn;
+                        sn += fabsf(x[1] - y[1]) + fabsf(x[2] - y[2]) + (float)(x[3] != y[3]) +
+                              (float)(x[4] != y[4]);
+                    }
+                }
+#pragma unroll
+                for (int m = 0; m < SMALL_CONN_ROWS; ++m) {
+                    const float *xm = xc[i][m];
+                    if (isnan(xm[0]) || isnan(xm[1])) continue;
+                    const int j = lookup_from(
+                        ck, cr, HC, ((unsigned long long)key_bits(xm[0]) << 32) | key_bits(xm[1]),
+                        xcs[i][m]);
+                    if (j < 0) continue;
+                    const float *y = Bc + (size_t)j * 4;
+                    ++hc;
+                    sc += fabsf(xm[3] - y[3]) + (float)(xm[2] != y[2]);
+                }
+            } else {
+                for (int r = lane; r < N; r += WAVE) {
+                    const float *x = An + (size_t)r * 5;
+                    if (isnan(x[0])) continue;
+                    const int j = lookup(nk, nr, HN, key_bits(x[0]));
+                    if (j < 0) continue;
+                    const float *y = Bn + (size_t)j * 5;
+                    ++hn;
+                    sn += fabsf(x[1] - y[1]) + fabsf(x[2] - y[2]) + (float)(x[3] != y[3]) +
+                          (float)(x[4] != y[4]);
+                }
+                for (int r = lane; r < C; r += WAVE) {
+                    const float *x = Ac + (size_t)r * 4;
+                    if (isnan(x[0]) || isnan(x[1])) continue;
+                    const int j = lookup(ck, cr, HC,
+                                         ((unsigned long long)key_bits(x[0]) << 32) | key_bits(x[1]));
+                    if (j < 0) continue;
+                    const float *y = Bc + (size_t)j * 4;
+                    ++hc;
+                    sc += fabsf(x[3] - y[3]) + (float)(x[2] != y[2]);
+                }
             }
             hn = wave_sum(hn);
             hc = wave_sum(hc);
@@ -355,8 +418,13 @@ hipError_t distance_launch(DistLaunch L, hipStream_t stream) {
     L.hn = pow2_at_least(2 * L.N);
     L.hc = pow2_at_least(2 * L.C);
     if (L.P == 0 || L.Q == 0) return hipSuccess;
-    hipLaunchKernelGGL(distance_kernel, dim3((unsigned)((L.P + DIST_GENOMES - 1) / DIST_GENOMES)),
-                       dim3(WAVE * DIST_WAVES), distance_lds_bytes(L.N, L.C), stream, L);
+    const dim3 grid((unsigned)((L.P + DIST_GENOMES - 1) / DIST_GENOMES)), block(WAVE * DIST_WAVES);
+    if (L.N <= WAVE && L.C <= WAVE * SMALL_CONN_ROWS)
+        hipLaunchKernelGGL(distance_kernel<true>, grid, block, distance_lds_bytes(L.N, L.C), stream,
+                           L);
+    else
+        hipLaunchKernelGGL(distance_kernel<false>, grid, block, distance_lds_bytes(L.N, L.C),
+                           stream, L);
     return hipGetLastError();
 }
 
