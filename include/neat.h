@@ -13,6 +13,14 @@
  *   calculation     neat_forward    -- many times: run every genome's program
  *                   over a batch of input vectors.
  *
+ * Around them: neat_forward_grid (CPPN queries made in the kernel),
+ * neat_substrate_forward (HyperNEAT substrate layer on the matrix cores),
+ * neat_topo_sort_recurrent / neat_forward_recurrent (networks with cycles),
+ * neat_forward_batch (many populations in one recorded graph), the server
+ * (neat_server_*, neat_submit, neat_poll: resident populations, continuous
+ * batching), and the gene-level operators of a generation: neat_distance,
+ * neat_crossover and neat_apply_edits.
+ *
  * ENCODING (Section 3.1).  A population of P genomes is two fp32 tensors,
  * row-major and contiguous:
  *   nodes [P][N_max][5] = (key, bias, response, act, agg)
