@@ -141,7 +141,7 @@ int neat_topo_sort(const neat_dims *dims, const float *nodes, const float *conns
  *            otherwise >= B * I)
  *   B        input vectors per genome (>= 0)
  *   outputs  [P][B][O] f32 (written); NaN for genomes with status != 0
- * Errors: NEAT_E_INVALID, NEAT_E_HIP.
+ * Errors: NEAT_E_INVALID, NEAT_E_TOO_LARGE (see neat_forward_ex), NEAT_E_HIP.
  */
 int neat_forward(const neat_dims *dims, const void *program, const float *inputs,
                  int64_t input_genome_stride, int32_t B, float *outputs,
@@ -162,8 +162,11 @@ int neat_forward(const neat_dims *dims, const void *program, const float *inputs
  * neat_forward with an explicit variant (NEAT_FWD_*); same arguments.  All
  * variants run the same operations in the same order and give identical
  * bits.  Errors as neat_forward, plus NEAT_E_INVALID for an unknown variant
- * and NEAT_E_TOO_LARGE when a genome's values do not fit in LDS (N_max
- * beyond about 600 for genomes whose live set exceeds 222 values).
+ * and NEAT_E_TOO_LARGE when the LDS-row store cannot fit one wave's values:
+ * populations with N_max > 222 (the only ones whose genomes can need that
+ * store) require 256 (I + N_max + 2) bytes of LDS per workgroup, i.e.
+ * I + N_max <= 638 on a device with 160 KiB; larger N_max is refused for
+ * the whole call (neat_forward included), before any launch.
  */
 int neat_forward_ex(const neat_dims *dims, const void *program, const float *inputs,
                     int64_t input_genome_stride, int32_t B, float *outputs, int32_t variant,

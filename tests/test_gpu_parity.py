@@ -486,3 +486,52 @@ def test_slot_allocation_is_the_largest_live_set():
             assert hdr[g, 8] == m, (pop.N_max, g, hdr[g, 8], m)
             cls = 0 if m <= 62 else 1 if m <= 126 else 2 if m <= 222 else 3
             assert hdr[g, 6] == cls
+
+
+@pytest.mark.parametrize("O", [4, 230])
+def test_largest_supported_sizes(O):
+    """N_max = 600 (I + N_max close to the LDS-row store's limit of 638) and
+    C_max = 2400: the multi-wave transformation at its widest and, with 230
+    outputs live to the end, genomes in the LDS-row store."""
+    rng = np.random.default_rng(600 + O)
+    P, N, C, I, B = 4, 600, 2400, 10, 70
+    nodes = np.full((P, N, 5), np.nan, np.float32)
+    conns = np.full((P, C, 4), np.nan, np.float32)
+    for p in range(P):
+        h = int(rng.integers(N // 2, N - I - O + 1))
+        synth.make_genome(rng, N, C, I, O, h, lambda na: int(rng.integers(C // 2, min(C, na) + 1)),
+                          synth.CONTROL_ACTS, synth.ALL_AGGS, nodes_out=nodes[p],
+                          conns_out=conns[p])
+    x = rng.standard_normal((P, B, I)).astype(np.float32)
+    print("case largest sizes O", O, flush=True)
+    order, level, status, y = _gpu(nodes, conns, I, O, x)
+    _assert_transform_exact(nodes, conns, I, O, order, level, status)
+    y64, beta = oracle.forward(nodes, conns, x, I, O)
+    _assert_outputs(y, y64, beta, "largest sizes O=%d" % O)
+
+
+def test_beyond_the_lds_row_store_is_refused():
+    """N_max = 1024 (the ABI's largest) transforms, but its forward needs
+    more LDS per wave than the device has: a clean NEAT_E_TOO_LARGE before
+    any launch; C_max = 16384 does not fit the transformation's LDS and is
+    refused by it."""
+    neat = _neat()
+    dev = torch.device("cuda:0")
+    pop = synth.tiny()
+    nodes = np.full((2, 1024, 5), np.nan, np.float32)
+    nodes[:, :8] = pop.nodes[:2]
+    conns = np.full((2, 64, 4), np.nan, np.float32)
+    conns[:, :16] = pop.conns[:2]
+    tn = torch.from_numpy(nodes).to(dev)
+    tc = torch.from_numpy(conns).to(dev)
+    order, level, status, prog = neat.topo_sort(tn, tc, 3, 1)
+    d = neat.dims_of(tn, tc, 3, 1)
+    with pytest.raises(neat.NeatError) as e:
+        neat.forward(d, prog, torch.zeros((2, 4, 3), device=dev), 4)
+    assert e.value.code == -4
+    torch.cuda.synchronize()
+    o_order, o_level, o_status = oracle.transform(nodes, conns, 3, 1)
+    assert np.array_equal(o_order, order.cpu().numpy())
+    big = torch.full((1, 64, 5), float("nan"), device=dev)
+    with pytest.raises(neat.NeatError):
+        neat.topo_sort(big, torch.full((1, 16384, 4), float("nan"), device=dev), 3, 1)
