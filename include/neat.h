@@ -162,11 +162,12 @@ int neat_forward(const neat_dims *dims, const void *program, const float *inputs
  * neat_forward with an explicit variant (NEAT_FWD_*); same arguments.  All
  * variants run the same operations in the same order and give identical
  * bits.  Errors as neat_forward, plus NEAT_E_INVALID for an unknown variant
- * and NEAT_E_TOO_LARGE when the LDS-row store cannot fit one wave's values:
- * populations with N_max > 222 (the only ones whose genomes can need that
- * store) require 256 (I + N_max + 2) bytes of LDS per workgroup, i.e.
- * I + N_max <= 638 on a device with 160 KiB; larger N_max is refused for
- * the whole call (neat_forward included), before any launch.
+ * and NEAT_E_TOO_LARGE when the LDS-row store cannot fit one wave's values.
+ * Populations with N_max > 222 (the only ones whose genomes can need that
+ * store) run it with tiles of 64 samples while 256 (I + N_max + 2) bytes fit
+ * in a workgroup's LDS (I + N_max <= 638 with 160 KiB), else with tiles of
+ * 32 samples (half the bytes: I + N_max <= 1278); beyond that the whole
+ * call (neat_forward included) is refused before any launch.
  */
 int neat_forward_ex(const neat_dims *dims, const void *program, const float *inputs,
                     int64_t input_genome_stride, int32_t B, float *outputs, int32_t variant,

@@ -71,21 +71,25 @@ __device__ __forceinline__ float maximum3(float a, float b, float c) {
 }
 
 // ---------------------------------------------------------------- stores
-struct LdsStore {
-    float *col;  // this lane's column: slot s at col[s * WAVE]
+// LDS rows of LD floats, one column per sample of the tile (LD = 64, or 32
+// for half-wave tiles when 64 columns of a large genome do not fit in LDS)
+template <int LD>
+struct LdsStoreT {
+    float *col;  // this lane's column: slot s at col[s * LD]
     template <int H>
     __device__ __forceinline__ float get(int s) const {
-        return col[s * WAVE];
+        return col[s * LD];
     }
     template <int H>
     __device__ __forceinline__ void set(int s, float x) {
-        col[s * WAVE] = x;
+        col[s * LD] = x;
     }
     __device__ __forceinline__ void init(int zs) {
-        col[zs * WAVE] = 0.0f;
-        col[(zs + 1) * WAVE] = 1.0f;
+        col[zs * LD] = 0.0f;
+        col[(zs + 1) * LD] = 1.0f;
     }
 };
+using LdsStore = LdsStoreT<WAVE>;
 
 // Register stores: one tile block of node_loop_asm.h per tile.  Operands as
 // documented there; every value register lives only inside the block.
@@ -144,10 +148,10 @@ struct AsmTile<KIND_R64REC> {
 // ---------------------------------------------------------------- nodes (C++)
 // The LDS store's node loop: the operations of node_loop_asm.h in the same
 // order, so both give identical bits.
-template <int ACLS>
+template <int ACLS, class Store>
 __device__ __forceinline__ void pair(float &acc, bool first, int s0, float w0, int s1, float w1,
-                                     const LdsStore &v) {
-    const float x0 = v.get<0>(s0), x1 = v.get<0>(s1);
+                                     const Store &v) {
+    const float x0 = v.template get<0>(s0), x1 = v.template get<0>(s1);
     if (ACLS == ACLS_SUM) {
         acc = first ? x0 * w0 : fmaf(x0, w0, acc);
         acc = fmaf(x1, w1, acc);
@@ -168,9 +172,9 @@ __device__ __forceinline__ void pair(float &acc, bool first, int s0, float w0, i
 
 // pairs (>= 1) edge pairs: the first three from the record r, then the
 // overflow array from e, four words per pair.
-template <int ACLS>
+template <int ACLS, class Store>
 __device__ __forceinline__ float aggregate(const i32x16 &r, cprog_t *e, int pairs,
-                                           const LdsStore &v) {
+                                           const Store &v) {
     float acc = 0.0f;
 #pragma unroll
     for (int k = 0; k < REC_INLINE_PAIRS; ++k) {
@@ -202,8 +206,9 @@ __device__ __forceinline__ float activation(int act, float z) {
 
 // Every computed node of the program in record order; the aggregations read
 // src and the results go to dst (the same store for a feedforward network).
-__device__ __forceinline__ void run_program(cprog_t *prog, int N, int O, int I,
-                                            const LdsStore &src, LdsStore &dst) {
+template <class Store>
+__device__ __forceinline__ void run_program(cprog_t *prog, int N, int O, int I, const Store &src,
+                                            Store &dst) {
     const int ncomp = prog[HDR_NVALID] - I;
     if (ncomp <= 0) return;
     cprog_t *rec = prog + rec_off(O);
@@ -223,7 +228,7 @@ __device__ __forceinline__ void run_program(cprog_t *prog, int N, int O, int I,
         else if (acls == ACLS_MAX) a = aggregate<ACLS_MAX>(r, e, pairs, src);
         else a = pairs == 0 ? 0.0f : aggregate<ACLS_SUM>(r, e, pairs, src);
         if (pairs > REC_INLINE_PAIRS) e += 4 * (pairs - REC_INLINE_PAIRS);
-        dst.set<0>(slot, activation(act, fmaf(resp, a, bias)));
+        dst.template set<0>(slot, activation(act, fmaf(resp, a, bias)));
         r = rn;
     }
 }
@@ -434,13 +439,15 @@ __device__ __forceinline__ void forward_unit_reg(citem_t *it, int g, int chunk, 
 
 // The waves of one unit with the LDS store.  stage: the wave's input
 // staging area (TS x I floats; unused for grid items).
-template <bool GRID>
+template <bool GRID, int LD>
 __device__ __forceinline__ void forward_unit_lds(citem_t *it, int g, int chunk, float *stage,
-                                                 LdsStore &v) {
-    constexpr int TS = WAVE;
+                                                 LdsStoreT<LD> &v) {
+    constexpr int TS = LD;
     int t0, t1;
     if (!wave_tiles(it, chunk, &t0, &t1)) return;
     const int lane = (int)(threadIdx.x & (WAVE - 1));
+    // half-wave tiles: lanes LD.. take no sample (their columns would alias)
+    const bool active = LD == WAVE || lane < LD;
     const int N = it->N, I = it->I, O = it->O, B = it->B, side = GRID ? it->side : 0;
     cprog_t *prog = (cprog_t *)(it->prog + (size_t)g * it->prog_words);
     float *out_g = it->outputs + (size_t)g * B * O;
@@ -451,14 +458,15 @@ __device__ __forceinline__ void forward_unit_lds(citem_t *it, int g, int chunk, 
     const float *in_g = GRID ? nullptr : it->inputs + (size_t)g * it->gstride;
     const int vec4 = it->vec4;
     if (!GRID) dma_inputs(in_g + (size_t)t0 * TS * I, stage, min(TS, B - t0 * TS) * I, vec4);
-    v.init(zero_slot(prog[HDR_CLASS], N));
+    if (active) v.init(zero_slot(prog[HDR_CLASS], N));
     for (int t = t0; t < t1; ++t) {
         const int nb = min(TS, B - t * TS);
         if (GRID) {
-            place_grid<0>(v, it->first + (long long)t * TS + lane, side);
+            if (active) place_grid<0>(v, it->first + (long long)t * TS + lane, side);
         } else {
             wait_dma();
-            for (int i = 0; i < I; ++i) v.set<0>(i, stage[lane * I + i]);
+            if (active)
+                for (int i = 0; i < I; ++i) v.template set<0>(i, stage[lane * I + i]);
             if (t + 1 < t1) {
                 // every lane has read its inputs before the buffer refills
                 __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0)
@@ -467,7 +475,7 @@ __device__ __forceinline__ void forward_unit_lds(citem_t *it, int g, int chunk, 
                            vec4);
             }
         }
-        run_program(prog, N, O, I, v, v);
+        if (active) run_program(prog, N, O, I, v, v);
         if (lane < nb) store_outputs<0>(v, prog, out_g + (size_t)(t * TS + lane) * O, O);
     }
 }
@@ -557,7 +565,11 @@ __device__ __forceinline__ void run_unit(long long u, float *wave_area) {
     if constexpr (K == KIND_LDS) {
         LdsStore v;
         v.col = wave_area + L->stage_floats + (threadIdx.x & (WAVE - 1));
-        forward_unit_lds<GRID>(it, g, chunk, wave_area, v);
+        forward_unit_lds<GRID, WAVE>(it, g, chunk, wave_area, v);
+    } else if constexpr (K == KIND_LDS32) {
+        LdsStoreT<WAVE / 2> v;
+        v.col = wave_area + L->stage_floats + (threadIdx.x & (WAVE / 2 - 1));
+        forward_unit_lds<GRID, WAVE / 2>(it, g, chunk, wave_area, v);
     } else {
         forward_unit_reg<K, GRID>(it, g, chunk, wave_area, L->stage_floats);
     }
@@ -606,7 +618,12 @@ int choose_chunks(long long P, int tiles, int *tpw) {
     return (tiles + *tpw - 1) / *tpw;
 }
 
-int samples_per_lane(int kind) { return kind == KIND_R64X2 ? 2 : 1; }
+// samples of one tile
+int tile_samples(int kind) {
+    return kind == KIND_R64X2 ? 2 * WAVE : (kind == KIND_LDS32 ? WAVE / 2 : WAVE);
+}
+
+bool lds_kind(int kind) { return kind == KIND_LDS || kind == KIND_LDS32; }
 
 // kernel of class c under a variant
 int kind_of(int variant, int cls, int B) {
@@ -624,7 +641,7 @@ int kind_of(int variant, int cls, int B) {
 }  // namespace
 
 const char *kind_name(int kind) {
-    static const char *names[] = {"r64", "r64x2", "r128", "r224", "lds", "r64rec"};
+    static const char *names[] = {"r64", "r64x2", "r128", "r224", "lds", "r64rec", "lds32"};
     return kind >= 0 && kind < N_KINDS ? names[kind] : "?";
 }
 
@@ -651,7 +668,11 @@ int forward_plan(const FwdJob *jobs, int n, int variant, size_t max_lds,
         const int c_lo = (variant == FWD_LDS || J.recurrent) ? -1 : 0;
         const int c_hi = (variant == FWD_LDS || J.recurrent) ? -1 : top;
         for (int c = c_lo; c <= c_hi; ++c) {
-            const int kind = J.recurrent ? KIND_R64REC : kind_of(variant, c < 0 ? CLS_LDS : c, J.B);
+            int kind = J.recurrent ? KIND_R64REC : kind_of(variant, c < 0 ? CLS_LDS : c, J.B);
+            // LDS rows too large for 64 columns per wave: half-wave tiles
+            if (kind == KIND_LDS &&
+                sizeof(float) * (size_t)WAVE * (J.I + class_slots(top, J.N)) > max_lds)
+                kind = KIND_LDS32;
             FwdItem it{};
             it.prog = J.prog;
             it.inputs = J.inputs;
@@ -664,7 +685,7 @@ int forward_plan(const FwdJob *jobs, int n, int variant, size_t max_lds,
             it.P = J.P, it.N = J.N, it.I = J.I, it.O = J.O, it.B = J.B, it.side = J.side;
             it.prog_words = prog_words(J.N, J.C, J.O);
             it.sweeps = J.recurrent ? J.sweeps : 0;
-            const int TS = WAVE * samples_per_lane(kind);
+            const int TS = tile_samples(kind);
             it.tiles = (J.B + TS - 1) / TS;
             it.chunks = choose_chunks(J.P, it.tiles, &it.tpw);
             it.vec4 = (!J.side && ((uintptr_t)J.inputs % 16 == 0) && (J.gstride % 4 == 0)) ? 1 : 0;
@@ -672,17 +693,18 @@ int forward_plan(const FwdJob *jobs, int n, int variant, size_t max_lds,
             k[x].items.push_back(it);
             // register kernels on grid queries keep the coordinates after
             // the staged inputs
-            if (!J.side || kind != KIND_LDS)
+            if (!J.side || !lds_kind(kind))
                 stage_max[x] = std::max(stage_max[x], TS * J.I + (J.side ? GRID_MAX_SIDE : 0));
-            if (kind != KIND_LDS) ostage_max[x] = std::max(ostage_max[x], TS * J.O);
-            if (kind == KIND_LDS) rows_max[x] = std::max(rows_max[x], class_slots(top, J.N));
+            if (!lds_kind(kind)) ostage_max[x] = std::max(ostage_max[x], TS * J.O);
+            if (lds_kind(kind)) rows_max[x] = std::max(rows_max[x], class_slots(top, J.N));
         }
     }
     for (int x = 0; x < NL; ++x) {
         FwdKernelLaunch &K = k[x];
         const int kind = K.kind;
         if (K.items.empty()) continue;
-        const size_t rows = kind == KIND_LDS ? (size_t)rows_max[x] * WAVE : (size_t)ostage_max[x];
+        const size_t rows = lds_kind(kind) ? (size_t)rows_max[x] * tile_samples(kind)
+                                           : (size_t)ostage_max[x];
         const size_t wave_floats = (size_t)stage_max[x] + rows;
         const size_t wave_bytes = wave_floats * sizeof(float);
         int waves = FWD_MAX_WAVES;
@@ -691,7 +713,7 @@ int forward_plan(const FwdJob *jobs, int n, int variant, size_t max_lds,
             snprintf(err, errlen,
                      "forward kernel %s needs %zu B of LDS per wave (value rows %d, input "
                      "staging %d floats), device allows %zu",
-                     kind_name(kind), wave_bytes, kind == KIND_LDS ? rows_max[x] : 0,
+                     kind_name(kind), wave_bytes, lds_kind(kind) ? rows_max[x] : 0,
                      stage_max[x], max_lds);
             return NEAT_E_TOO_LARGE;
         }
@@ -708,7 +730,7 @@ int forward_plan(const FwdJob *jobs, int n, int variant, size_t max_lds,
         K.lds = wave_bytes * waves;
         // the LDS store limits the workgroups a CU holds: loop over units with
         // a grid of a few per CU instead of one workgroup per unit
-        const long long cap = kind == KIND_LDS
+        const long long cap = lds_kind(kind)
                                   ? 256ll * 2 * std::max<long long>(1, (long long)(163840 / K.lds))
                                   : (1ll << 31) - 1;
         K.args.persistent = groups > cap ? 1 : 0;
@@ -759,6 +781,7 @@ hipError_t forward_launch(const FwdKernelLaunch &k, const FwdItem *dev_items, hi
     case KIND_R128: NEAT_LAUNCH(KIND_R128) break;
     case KIND_R224: NEAT_LAUNCH(KIND_R224) break;
     case KIND_R64REC: NEAT_LAUNCH2(KIND_R64REC, false) break;
+    case KIND_LDS32: NEAT_LAUNCH(KIND_LDS32) break;
     default: NEAT_LAUNCH(KIND_LDS) break;
     }
 #undef NEAT_LAUNCH

@@ -51,8 +51,12 @@ constexpr int FWD_REG2 = 3;  // as FWD_REG, R64 genomes two samples per lane
 
 // Forward kernels, one per value store.
 // KIND_R64REC: the recurrent calculation (K synchronous sweeps) with the
-// 64-slot register store, for populations of N_max <= 62.
-enum FwdKind { KIND_R64 = 0, KIND_R64X2, KIND_R128, KIND_R224, KIND_LDS, KIND_R64REC, N_KINDS };
+// 64-slot register store, for populations of N_max <= 62.  KIND_LDS32: the
+// LDS-row store with half-wave tiles (32 samples), for genomes whose rows
+// do not fit in LDS with 64 columns.
+enum FwdKind {
+    KIND_R64 = 0, KIND_R64X2, KIND_R128, KIND_R224, KIND_LDS, KIND_R64REC, KIND_LDS32, N_KINDS
+};
 constexpr int FWD_MAX_WAVES = 4;  // waves per workgroup
 
 // One population of a forward call.

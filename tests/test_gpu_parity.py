@@ -510,28 +510,54 @@ def test_largest_supported_sizes(O):
     _assert_outputs(y, y64, beta, "largest sizes O=%d" % O)
 
 
+def test_largest_nodes_in_half_wave_lds_tiles():
+    """N_max = 1024, the ABI's largest, with 230 outputs live to the end:
+    64 columns of 1026 rows exceed the LDS, so the LDS-row store runs tiles
+    of 32 samples; every value store agrees with the oracle and with each
+    other bit for bit."""
+    neat = _neat()
+    rng = np.random.default_rng(1024)
+    P, N, C, I, O, B = 3, 1024, 2048, 6, 230, 45
+    nodes = np.full((P, N, 5), np.nan, np.float32)
+    conns = np.full((P, C, 4), np.nan, np.float32)
+    for p in range(P):
+        synth.make_genome(rng, N, C, I, O, int(rng.integers(300, 700)),
+                          lambda na: int(rng.integers(C // 2, min(C, na) + 1)),
+                          synth.CONTROL_ACTS, synth.ALL_AGGS, nodes_out=nodes[p],
+                          conns_out=conns[p])
+    x = rng.standard_normal((P, B, I)).astype(np.float32)
+    print("case N_max 1024", flush=True)
+    order, level, status, y = _gpu(nodes, conns, I, O, x)
+    _assert_transform_exact(nodes, conns, I, O, order, level, status)
+    y64, beta = oracle.forward(nodes, conns, x, I, O)
+    _assert_outputs(y, y64, beta, "N_max 1024")
+    _, _, _, y_lds = _gpu(nodes, conns, I, O, x, variant=neat.FWD_LDS)
+    assert np.array_equal(y.view(np.uint32), y_lds.view(np.uint32))
+
+
 def test_beyond_the_lds_row_store_is_refused():
-    """N_max = 1024 (the ABI's largest) transforms, but its forward needs
-    more LDS per wave than the device has: a clean NEAT_E_TOO_LARGE before
-    any launch; C_max = 16384 does not fit the transformation's LDS and is
-    refused by it."""
+    """I + N_max beyond the half-wave store's 1278 (N_max = 1024 with 300
+    inputs) transforms but is refused by the forward with a clean
+    NEAT_E_TOO_LARGE before any launch; C_max = 16384 does not fit the
+    transformation's LDS and is refused by it."""
     neat = _neat()
     dev = torch.device("cuda:0")
-    pop = synth.tiny()
+    I = 300
     nodes = np.full((2, 1024, 5), np.nan, np.float32)
-    nodes[:, :8] = pop.nodes[:2]
+    nodes[:, :I + 1] = np.array([[k, 0.0, 1.0, 0, 0] for k in range(I + 1)], np.float32)
     conns = np.full((2, 64, 4), np.nan, np.float32)
-    conns[:, :16] = pop.conns[:2]
+    conns[:, 0] = (0, I, 1, 0.5)
     tn = torch.from_numpy(nodes).to(dev)
     tc = torch.from_numpy(conns).to(dev)
-    order, level, status, prog = neat.topo_sort(tn, tc, 3, 1)
-    d = neat.dims_of(tn, tc, 3, 1)
+    order, level, status, prog = neat.topo_sort(tn, tc, I, 1)
+    d = neat.dims_of(tn, tc, I, 1)
     with pytest.raises(neat.NeatError) as e:
-        neat.forward(d, prog, torch.zeros((2, 4, 3), device=dev), 4)
+        neat.forward(d, prog, torch.zeros((2, 4, I), device=dev), 4)
     assert e.value.code == -4
     torch.cuda.synchronize()
-    o_order, o_level, o_status = oracle.transform(nodes, conns, 3, 1)
+    o_order, o_level, o_status = oracle.transform(nodes, conns, I, 1)
     assert np.array_equal(o_order, order.cpu().numpy())
+    assert np.array_equal(o_status, status.cpu().numpy().astype(np.uint32))
     big = torch.full((1, 64, 5), float("nan"), device=dev)
     with pytest.raises(neat.NeatError):
         neat.topo_sort(big, torch.full((1, 16384, 4), float("nan"), device=dev), 3, 1)
