@@ -317,6 +317,10 @@ int neat_substrate_forward(const neat_dims *dims, const void *program, int32_t s
  * one value slot per node.  Arguments, ownership and errors as
  * neat_topo_sort.
  */
+/* Largest K of one neat_forward_recurrent call: the kernel's run time grows
+ * linearly with K, and every call starts again from v0. */
+#define NEAT_MAX_SWEEPS 65536
+
 int neat_topo_sort_recurrent(const neat_dims *dims, const float *nodes, const float *conns,
                              int32_t *order, int32_t *level, uint32_t *status, void *program,
                              void *stream);
@@ -330,7 +334,7 @@ int neat_topo_sort_recurrent(const neat_dims *dims, const float *nodes, const fl
  * 4 * 64 * (I + 2 * slots) bytes exceed the device's LDS per workgroup,
  * slots being N_max + 2 for N_max > 222 (so N_max up to about 300), else
  * 64, 128 or 224.  Errors: NEAT_E_INVALID (dims, NULL pointers, K < 0, a
- * stride below B * I), NEAT_E_TOO_LARGE, NEAT_E_HIP.
+ * stride below B * I, K > NEAT_MAX_SWEEPS), NEAT_E_TOO_LARGE, NEAT_E_HIP.
  */
 int neat_forward_recurrent(const neat_dims *dims, const void *program, const float *inputs,
                            int64_t input_genome_stride, int32_t B, int32_t K, float *outputs,

@@ -219,7 +219,8 @@ int neat_forward_recurrent(const neat_dims *d, const void *program, const float 
                            void *stream) {
     int rc = check_dims(d);
     if (rc != NEAT_OK) return rc;
-    if (K < 0) return fail(NEAT_E_INVALID, "K = %d < 0", K);
+    if (K < 0 || K > NEAT_MAX_SWEEPS)
+        return fail(NEAT_E_INVALID, "K = %d outside [0, %d]", K, NEAT_MAX_SWEEPS);
     rc = check_forward_args(d, program, inputs, input_genome_stride, B, outputs, false, 0, 0);
     if (rc != NEAT_OK || d->P == 0 || B == 0) return rc;
     if (neat::max_class(d->N_max) == neat::CLS_R64) {

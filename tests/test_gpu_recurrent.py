@@ -142,6 +142,8 @@ def test_recurrent_empty_and_too_large():
     assert y.shape == (3, 0, 2)
     with pytest.raises(neat.NeatError):
         neat.forward_recurrent(d, prog, torch.zeros((3, 5, 4), device=dev), 5, -1)
+    with pytest.raises(neat.NeatError):    # beyond NEAT_MAX_SWEEPS
+        neat.forward_recurrent(d, prog, torch.zeros((3, 5, 4), device=dev), 5, 65537)
     # N_max = 400 needs 2 x 402 LDS rows per lane: beyond 160 KiB
     big = neat.Dims(1, 400, 16, 4, 2)
     prog_b = torch.zeros((neat.program_bytes(big) // 4,), dtype=torch.int32, device=dev)
