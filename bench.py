@@ -156,7 +156,10 @@ def bench_batched(args, torch, neat, synth):
         "roofline_forward": {"bound": "hbm", "achieved": round(achieved, 1),
                              "peak": HBM_PEAK_GBS, "unit": "GB/s",
                              "frac": round(achieved / HBM_PEAK_GBS, 4),
-                             "algorithmic_bytes_per_launch": fwd_bytes},
+                             "algorithmic_bytes_per_launch": fwd_bytes,
+                             "note": "neither HBM nor ALU bounds this launch: with B of 1 "
+                                     "to 512 most tiles are partly empty and a wave's "
+                                     "time is the latency of its genome's node chain"},
     }
 
 
