@@ -5,14 +5,20 @@ TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
 code with the GPU library (``paper_2404_01817_amd``) and neither imports the
 other.
 
-Two independent formulations live here:
+What lives here:
 
 * ``neat_oracle.c`` (loaded through ctypes): the plain definition of the
   paper's inference (Section 3.3) on adjacency lists, in IEEE double, plus a
-  float instantiation of the same code and a first-order fp32 error bound.
+  float instantiation of the same code and a first-order fp32 error bound
+  (``transform``, ``forward``); the recurrent reading by synchronous sweeps
+  (``forward_recurrent``); and the gene-level operators of a generation:
+  compatibility distance, crossover and the tensorized edits of Section 3.2
+  (``distance``, ``crossover``, ``edit``).
 * ``dense.py``: the paper's own dense formulation (N_order and the expanded
   connection tensor C_exp of Section 3.3) written out in numpy, used to
   cross-check the C oracle.
+* ``substrate.py``: the HyperNEAT substrate layer (CPPN weights from the C
+  oracle, threshold, numpy contraction) with its fp32 bound.
 
 Status bits (per genome): BAD_VALUE 1, DUP_KEY 2, MISSING_IO 4, BAD_REF 8,
 INTO_INPUT 16, DUP_EDGE 32, CYCLE 64.
