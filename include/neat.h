@@ -329,11 +329,13 @@ int neat_topo_sort_recurrent(const neat_dims *dims, const float *nodes, const fl
  * neat_forward_recurrent: K >= 0 sweeps over a program built by
  * neat_topo_sort_recurrent for the same dims; inputs, input_genome_stride,
  * B and outputs as neat_forward (NaN outputs for genomes with status != 0;
- * K = 0 gives the initial values, 0).  The values of one sample live in
- * LDS, twice (previous and current sweep): NEAT_E_TOO_LARGE when
- * 4 * 64 * (I + 2 * slots) bytes exceed the device's LDS per workgroup,
- * slots being N_max + 2 for N_max > 222 (so N_max up to about 300), else
- * 64, 128 or 224.  Errors: NEAT_E_INVALID (dims, NULL pointers, K < 0, a
+ * K = 0 gives the initial values, 0).  For N_max <= 62 the values live in
+ * registers; otherwise each sample's values live in LDS twice (previous and
+ * current sweep), slots being 128 or 224, or N_max + 2 for N_max > 222.
+ * Tiles hold 64 samples while 4 * 64 * (I + 2 * slots) bytes fit the
+ * device's LDS per workgroup, else 32; NEAT_E_TOO_LARGE when even
+ * 4 * 32 * (I + 2 * slots) bytes do not fit (N_max beyond about 600).
+ * Errors: NEAT_E_INVALID (dims, NULL pointers, K < 0, a
  * stride below B * I, K > NEAT_MAX_SWEEPS), NEAT_E_TOO_LARGE, NEAT_E_HIP.
  */
 int neat_forward_recurrent(const neat_dims *dims, const void *program, const float *inputs,

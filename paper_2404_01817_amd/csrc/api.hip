@@ -238,7 +238,7 @@ int neat_forward_recurrent(const neat_dims *d, const void *program, const float 
         }
         return NEAT_OK;
     }
-    const size_t lds = neat::recurrent_lds_bytes(d->N_max, d->I);
+    const size_t lds = neat::recurrent_lds_bytes(d->N_max, d->I, 32);
     if (lds > max_lds_bytes())
         return fail(NEAT_E_TOO_LARGE,
                     "recurrent forward with N_max=%d, I=%d needs %zu B of LDS per wave, device "
@@ -251,11 +251,9 @@ int neat_forward_recurrent(const neat_dims *d, const void *program, const float 
     L.gstride = input_genome_stride;
     L.prog_words = neat::prog_words(d->N_max, d->C_max, d->O);
     L.P = d->P, L.N = d->N_max, L.I = d->I, L.O = d->O, L.B = B, L.K = K;
-    L.tiles = (B + 63) / 64;
     L.rows = neat::class_slots(neat::max_class(d->N_max), d->N_max);
-    L.stage_floats = 64 * d->I;
     L.vec4 = (aligned(inputs, 16) && input_genome_stride % 4 == 0) ? 1 : 0;
-    hipError_t e = neat::recurrent_launch(L, (hipStream_t)stream);
+    hipError_t e = neat::recurrent_launch(L, max_lds_bytes(), (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "forward_recurrent launch");
     return NEAT_OK;
 }

@@ -487,39 +487,45 @@ __device__ __forceinline__ void forward_unit_lds(citem_t *it, int g, int chunk, 
 // LDS columns, the previous sweep's (cur) and the one being written (nxt),
 // which swap after every sweep: v0 = the inputs at slots 0..I-1 and 0 at
 // the other nodes; every sweep runs all records reading cur and writing nxt.
+template <int LD>
 __global__ __launch_bounds__(WAVE) void recurrent_kernel(RecLaunch L) {
+    // tiles of LD samples (64, or 32 when two columns of 64 do not fit)
     extern __shared__ float smem[];
     const long long u = xcd_item(blockIdx.x, gridDim.x);
     if (u >= (long long)L.P * L.tiles) return;
     const int g = (int)(u / L.tiles), t = (int)(u - (long long)g * L.tiles);
     const int lane = (int)(threadIdx.x & (WAVE - 1));
+    const bool active = LD == WAVE || lane < LD;  // lanes LD.. take no sample
     const int I = L.I, O = L.O, N = L.N;
     cprog_t *prog = (cprog_t *)(L.prog + (size_t)g * L.prog_words);
     float *out_g = L.outputs + (size_t)g * L.B * O;
-    const int s0 = t * WAVE, nb = min(WAVE, L.B - s0);
+    const int s0 = t * LD, nb = min(LD, L.B - s0);
     if (prog[HDR_STATUS] != 0) {
         fill_nan(out_g, s0, s0 + nb, O);
         return;
     }
     float *stage = smem;
     dma_inputs(L.inputs + (size_t)g * L.gstride + (size_t)s0 * I, stage, nb * I, L.vec4);
-    LdsStore cur, nxt;
-    cur.col = smem + L.stage_floats + lane;
-    nxt.col = cur.col + (size_t)L.rows * WAVE;
+    LdsStoreT<LD> cur, nxt;
+    cur.col = smem + L.stage_floats + (lane & (LD - 1));
+    nxt.col = cur.col + (size_t)L.rows * LD;
     const int nvalid = prog[HDR_NVALID];
-    for (int s = I; s < nvalid; ++s) cur.set<0>(s, 0.0f);
-    cur.init(zero_slot(prog[HDR_CLASS], N));
-    nxt.init(zero_slot(prog[HDR_CLASS], N));
+    if (active) {
+        for (int s = I; s < nvalid; ++s) cur.template set<0>(s, 0.0f);
+        cur.init(zero_slot(prog[HDR_CLASS], N));
+        nxt.init(zero_slot(prog[HDR_CLASS], N));
+    }
     wait_dma();
     // lanes past the tile's last sample read stale staging words; their
     // results are never stored
-    for (int i = 0; i < I; ++i) {
-        const float x = stage[lane * I + i];
-        cur.set<0>(i, x);
-        nxt.set<0>(i, x);
-    }
+    if (active)
+        for (int i = 0; i < I; ++i) {
+            const float x = stage[lane * I + i];
+            cur.template set<0>(i, x);
+            nxt.template set<0>(i, x);
+        }
     for (int k = 0; k < L.K; ++k) {
-        run_program(prog, N, O, I, cur, nxt);
+        if (active) run_program(prog, N, O, I, cur, nxt);
         float *c = cur.col;
         cur.col = nxt.col;
         nxt.col = c;
@@ -741,15 +747,22 @@ int forward_plan(const FwdJob *jobs, int n, int variant, size_t max_lds,
     return NEAT_OK;
 }
 
-size_t recurrent_lds_bytes(int N, int I) {
-    return sizeof(float) * (size_t)WAVE * ((size_t)I + 2 * (size_t)class_slots(max_class(N), N));
+size_t recurrent_lds_bytes(int N, int I, int ld) {
+    return sizeof(float) * (size_t)ld * ((size_t)I + 2 * (size_t)class_slots(max_class(N), N));
 }
 
-hipError_t recurrent_launch(const RecLaunch &L, hipStream_t stream) {
+hipError_t recurrent_launch(RecLaunch L, size_t max_lds, hipStream_t stream) {
+    const int ld = recurrent_lds_bytes(L.N, L.I, WAVE) <= max_lds ? WAVE : WAVE / 2;
+    L.tiles = (L.B + ld - 1) / ld;
+    L.stage_floats = ld * L.I;
     const long long blocks = (long long)L.P * L.tiles;
     if (blocks == 0) return hipSuccess;
-    hipLaunchKernelGGL(recurrent_kernel, dim3((unsigned)blocks), dim3(WAVE),
-                       recurrent_lds_bytes(L.N, L.I), stream, L);
+    if (ld == WAVE)
+        hipLaunchKernelGGL(recurrent_kernel<WAVE>, dim3((unsigned)blocks), dim3(WAVE),
+                           recurrent_lds_bytes(L.N, L.I, WAVE), stream, L);
+    else
+        hipLaunchKernelGGL(recurrent_kernel<WAVE / 2>, dim3((unsigned)blocks), dim3(WAVE),
+                           recurrent_lds_bytes(L.N, L.I, WAVE / 2), stream, L);
     return hipGetLastError();
 }
 

@@ -119,9 +119,10 @@ int forward_plan(const FwdJob *jobs, int n, int variant, size_t max_lds,
 // (may be nullptr when the launch has a single item, passed inline).
 hipError_t forward_launch(const FwdKernelLaunch &k, const FwdItem *dev_items, hipStream_t stream);
 
-// Recurrent calculation: K synchronous sweeps, one wave per (genome, tile of
-// 64 samples), rows = class_slots(max_class(N), N) LDS rows per value
-// column, stage_floats = 64 I.
+// Recurrent calculation: K synchronous sweeps, one wave per (genome, tile),
+// rows = class_slots(max_class(N), N) LDS rows per value column; tiles of
+// 64 samples, or 32 when recurrent_lds_bytes(N, I, 64) exceeds max_lds
+// (recurrent_launch sets tiles and stage_floats).
 struct RecLaunch {
     const int32_t *prog;
     const float *inputs;
@@ -129,8 +130,8 @@ struct RecLaunch {
     long long gstride;
     int prog_words, P, N, I, O, B, K, tiles, rows, stage_floats, vec4;
 };
-size_t recurrent_lds_bytes(int N, int I);
-hipError_t recurrent_launch(const RecLaunch &L, hipStream_t stream);
+size_t recurrent_lds_bytes(int N, int I, int tile_samples);
+hipError_t recurrent_launch(RecLaunch L, size_t max_lds, hipStream_t stream);
 
 // HyperNEAT substrate layer: Y[g] = tanh(X W'[g]), W' = W with |w| < theta
 // set to 0.  W [P][S][S], X [B][S], Y [P][B][S]; S a multiple of 64; X, W

@@ -62,10 +62,10 @@ def _check(pop, K, label):
 
 
 # (P, N_max, C_max, I, O, B): one-wave transformation groups, multi-wave
-# groups, 128- and 224-slot rows and the N_max + 2 row layout; B spanning
-# several 64-sample tiles with a ragged last one
+# groups, 128- and 224-slot rows and the N_max + 2 row layout (N_max = 500
+# in tiles of 32 samples); B spanning several tiles with a ragged last one
 SHAPES = [(37, 12, 30, 3, 2, 70), (24, 50, 200, 17, 6, 130), (11, 100, 400, 8, 3, 65),
-          (7, 180, 720, 12, 4, 64), (5, 260, 1040, 10, 5, 33)]
+          (7, 180, 720, 12, 4, 64), (5, 260, 1040, 10, 5, 33), (3, 500, 1500, 6, 3, 40)]
 
 
 @pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "P%d_N%d_B%d" % (s[0], s[1], s[5]))
@@ -144,8 +144,9 @@ def test_recurrent_empty_and_too_large():
         neat.forward_recurrent(d, prog, torch.zeros((3, 5, 4), device=dev), 5, -1)
     with pytest.raises(neat.NeatError):    # beyond NEAT_MAX_SWEEPS
         neat.forward_recurrent(d, prog, torch.zeros((3, 5, 4), device=dev), 5, 65537)
-    # N_max = 400 needs 2 x 402 LDS rows per lane: beyond 160 KiB
-    big = neat.Dims(1, 400, 16, 4, 2)
+    # N_max = 700 needs 2 x 702 LDS rows per lane: beyond 160 KiB even with
+    # tiles of 32 samples
+    big = neat.Dims(1, 700, 16, 4, 2)
     prog_b = torch.zeros((neat.program_bytes(big) // 4,), dtype=torch.int32, device=dev)
     with pytest.raises(neat.NeatError) as e:
         neat.forward_recurrent(big, prog_b, torch.zeros((1, 8, 4), device=dev), 8, 2)
