@@ -142,3 +142,36 @@ def test_batch_argument_errors():
     with pytest.raises(neat.NeatError, match="item 1"):
         plan.run(items)
     assert plan.launches == 0
+
+
+def test_batch_with_the_largest_genomes():
+    """A batch mixing small populations with N_max = 600 (LDS rows, tiles of
+    64) and N_max = 1024 (LDS rows, half-wave tiles) populations, 230
+    outputs live to the end: the same bits as single calls, and the
+    oracle's values."""
+    neat = _neat()
+    rng = np.random.default_rng(77)
+    big = []
+    for N, C in ((600, 2400), (1024, 2048)):
+        P, I, O, B = 3, 6, 230, 37
+        nodes = np.full((P, N, 5), np.nan, np.float32)
+        conns = np.full((P, C, 4), np.nan, np.float32)
+        for p in range(P):
+            synth.make_genome(rng, N, C, I, O, int(rng.integers(200, N - I - O)),
+                              lambda na: int(rng.integers(C // 2, min(C, na) + 1)),
+                              synth.CONTROL_ACTS, synth.ALL_AGGS, nodes_out=nodes[p],
+                              conns_out=conns[p])
+        pop = synth.Population(nodes, conns, I, O)
+        pop.inputs = rng.standard_normal((P, B, I)).astype(np.float32)
+        big.append(pop)
+    pops = [_Pop(p) for p in _uneven(31, 3)] + [_Pop(p) for p in big]
+    plan = neat.BatchPlan()
+    plan.run([p.item() for p in pops])
+    torch.cuda.synchronize()
+    for k, p in enumerate(pops):
+        y = p.y.cpu().numpy()
+        assert _same_bits(y, p.single()), k
+        y64, beta = oracle.forward(p.pop.nodes, p.pop.conns, p.pop.inputs, p.pop.I, p.pop.O)
+        ok, stats = oracle.within_tolerance(y, y64, beta)
+        assert stats["n_fail"] == 0, (k, stats)
+    plan.free()
