@@ -99,6 +99,76 @@ def program_bytes_read(O, n_valid, n_edges, I):
     return int((64 + 4 * O + 16 * n_comp + 8 * n_edges).sum())
 
 
+def bench_control_forms(args, torch, neat, pop, tn, tc, tx, parts=10):
+    """The control workload (P=10000, N_max=50, B=1000) as `parts`
+    populations of P/parts genomes: plain (one neat_topo_sort and one
+    neat_forward per population) against batched (all populations as one
+    recorded batch, transformation + calculation per replay), and the whole
+    population as a single batch item."""
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    sp = ctypes.c_void_p(stream.cuda_stream)
+    lib = neat.lib()
+    bounds = [pop.P * k // parts for k in range(parts + 1)]
+    chunks = []
+    for k in range(parts):
+        g0, g1 = bounds[k], bounds[k + 1]
+        d = neat.Dims(g1 - g0, tn.shape[1], tc.shape[1], pop.I, pop.O)
+        prog = torch.empty((neat.program_bytes(d) // 4,), dtype=torch.int32, device=dev)
+        st = torch.empty((g1 - g0,), dtype=torch.int32, device=dev)
+        y = torch.empty((g1 - g0, pop.B, pop.O), dtype=torch.float32, device=dev)
+        chunks.append((d, tn[g0:g1], tc[g0:g1], tx[g0:g1], prog, st, y))
+
+    def plain():
+        for d, n, c, x, prog, st, y in chunks:
+            neat._lib.check(lib.neat_topo_sort(ctypes.byref(d), ctypes.c_void_p(n.data_ptr()),
+                                               ctypes.c_void_p(c.data_ptr()), None, None,
+                                               ctypes.c_void_p(st.data_ptr()),
+                                               ctypes.c_void_p(prog.data_ptr()), sp))
+            neat._lib.check(lib.neat_forward(ctypes.byref(d), ctypes.c_void_p(prog.data_ptr()),
+                                             ctypes.c_void_p(x.data_ptr()), pop.B * pop.I,
+                                             pop.B, ctypes.c_void_p(y.data_ptr()), sp))
+
+    items = [neat.batch_item(d, prog, y, inputs=x, B=pop.B, nodes=n, conns=c, status=st)
+             for d, n, c, x, prog, st, y in chunks]
+    d1 = neat.dims_of(tn, tc, pop.I, pop.O)
+    prog1 = torch.empty((neat.program_bytes(d1) // 4,), dtype=torch.int32, device=dev)
+    st1 = torch.empty((pop.P,), dtype=torch.int32, device=dev)
+    y1 = torch.empty((pop.P, pop.B, pop.O), dtype=torch.float32, device=dev)
+    one = [neat.batch_item(d1, prog1, y1, inputs=tx, B=pop.B, nodes=tn, conns=tc, status=st1)]
+    plan, plan1 = neat.BatchPlan(), neat.BatchPlan()
+
+    def timed(fn):
+        for _ in range(max(1, args.warmup)):
+            fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(args.steps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) * 1e3 / args.steps
+
+    ms_plain = timed(plain)
+    ms_batch = timed(lambda: plan.run(items))
+    ms_one = timed(lambda: plan1.run(one))
+    same = all(torch.equal(torch.nan_to_num(y, nan=7.5), torch.nan_to_num(y1[b0:b0 + y.shape[0]],
+                                                                          nan=7.5))
+               for (d, n, c, x, prog, st, y), b0 in zip(chunks, bounds))
+    plan.free()
+    plan1.free()
+    units = pop.P * pop.B
+    return {"workload": "the control workload as %d populations of %d genomes"
+                        % (parts, pop.P // parts),
+            "plain_ms": round(ms_plain, 4), "plain_launches": 2 * parts,
+            "plain_value": round(units / (ms_plain / 1e3), 1),
+            "batched_ms": round(ms_batch, 4),
+            "batched_value": round(units / (ms_batch / 1e3), 1),
+            "batched_speedup": round(ms_plain / ms_batch, 3),
+            "one_item_batched_ms": round(ms_one, 4),
+            "one_item_batched_value": round(units / (ms_one / 1e3), 1),
+            "outputs_identical": bool(same), "unit": "genome-inputs/s"}
+
+
 def bench_batched(args, torch, neat, synth):
     """64 uneven populations (P, N_max, B log-uniform; C_max = 4 N_max) run
     as one recorded batch: transformation + calculation of every population
@@ -639,6 +709,8 @@ def main():
                          % (g, pop.B, dt)}
 
     workloads = set(args.workloads.split(","))
+    forms = (bench_control_forms(args, torch, neat, pop, tn, tc, tx)
+             if "batched" in workloads else None)
     batched = bench_batched(args, torch, neat, synth) if "batched" in workloads else None
     served = bench_served(args, torch, neat, synth) if "served" in workloads else None
     cppn = bench_cppn(args, torch, neat, synth) if "cppn" in workloads else None
@@ -668,6 +740,7 @@ def main():
         "rejected_genomes": n_bad,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "control_batched_vs_plain": forms,
         "batched": batched,
         "served": served,
         "cppn": cppn,
