@@ -311,7 +311,7 @@ int neat_crossover(const neat_dims *d, const float *nodes, const float *conns, i
         return fail(NEAT_E_INVALID, "a pointer argument is NULL");
     if (child_conns && !aligned(child_conns, 16))
         return fail(NEAT_E_INVALID, "child_conns must be 16-byte aligned");
-    const size_t lds = neat::distance_lds_bytes(d->N_max, d->C_max);
+    const size_t lds = neat::gene_tables_lds_bytes(d->N_max, d->C_max);
     if (lds > max_lds_bytes())
         return fail(NEAT_E_TOO_LARGE,
                     "crossover with N_max=%d, C_max=%d needs %zu B of LDS, device allows %zu",

@@ -24,6 +24,8 @@ struct DistLaunch {
 };
 
 size_t distance_lds_bytes(int N, int C);
+// LDS of the two gene hash tables alone (what crossover uses)
+size_t gene_tables_lds_bytes(int N, int C);
 hipError_t distance_launch(DistLaunch L, hipStream_t stream);
 
 // children cn/cc [Pc][N][5] / [Pc][C][4] of the parent pairs [Pc][2] of

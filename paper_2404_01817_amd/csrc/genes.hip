@@ -47,9 +47,46 @@ __device__ __forceinline__ int wave_sum(int v) {
     for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
     return v;
 }
-__device__ __forceinline__ float wave_sum(float v) {
-    for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
+
+// Wave sums on the DPP lane network (register-to-register, no LDS round
+// trips): lanes pair up within rows of 16 (swap neighbours, swap pairs,
+// mirror each half row, mirror the row), after which every lane of a row
+// holds the row's sum; the four row sums are read out into scalars.  Called
+// with the whole wave active.
+constexpr int DPP_SWAP1 = 0xB1;      // quad_perm [1, 0, 3, 2]
+constexpr int DPP_SWAP2 = 0x4E;      // quad_perm [2, 3, 0, 1]
+constexpr int DPP_HALF_MIRROR = 0x141;
+constexpr int DPP_MIRROR = 0x140;
+
+__device__ __forceinline__ int row_sums(int v) {
+    v += __builtin_amdgcn_update_dpp(0, v, DPP_SWAP1, 0xF, 0xF, false);
+    v += __builtin_amdgcn_update_dpp(0, v, DPP_SWAP2, 0xF, 0xF, false);
+    v += __builtin_amdgcn_update_dpp(0, v, DPP_HALF_MIRROR, 0xF, 0xF, false);
+    v += __builtin_amdgcn_update_dpp(0, v, DPP_MIRROR, 0xF, 0xF, false);
     return v;
+}
+__device__ __forceinline__ float row_sums(float v) {
+#define NEAT_DPP_ADD(CTRL) \
+    v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false))
+    NEAT_DPP_ADD(DPP_SWAP1);
+    NEAT_DPP_ADD(DPP_SWAP2);
+    NEAT_DPP_ADD(DPP_HALF_MIRROR);
+    NEAT_DPP_ADD(DPP_MIRROR);
+#undef NEAT_DPP_ADD
+    return v;
+}
+__device__ __forceinline__ int wave_total(int v) {
+    v = row_sums(v);
+    return __builtin_amdgcn_readlane(v, 0) + __builtin_amdgcn_readlane(v, 16) +
+           __builtin_amdgcn_readlane(v, 32) + __builtin_amdgcn_readlane(v, 48);
+}
+__device__ __forceinline__ float wave_total(float v) {
+    v = row_sums(v);
+    const float r0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 0));
+    const float r1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 16));
+    const float r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 32));
+    const float r3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 48));
+    return (r0 + r1) + (r2 + r3);
 }
 
 // insert key -> row (keeping the smallest row for a key)
@@ -95,7 +132,10 @@ constexpr int DIST_GENOMES = DIST_WAVES * DIST_PER_WAVE;
 
 // SMALL (N_max <= 64, C_max <= 256): every lane keeps its genes' keys,
 // attributes and first hash slots in registers for the whole loop over the
-// representatives (one node row and up to four connection rows per genome).
+// representatives (one node row and up to four connection rows per genome),
+// B's rows are copied into LDS beside the tables (a partner's attributes
+// are an LDS read away, not a cache round trip), and the per-pair sums run
+// on the DPP lane network.
 constexpr int SMALL_CONN_ROWS = 4;
 
 template <bool SMALL>
@@ -107,6 +147,8 @@ __global__ __launch_bounds__(WAVE *DIST_WAVES) void distance_kernel(DistLaunch L
     int *nr = (int *)(ck + HC);              // rows [HN]
     int *cr = nr + HN;                       // rows [HC]
     int *bcount = cr + HC;                   // B's node and connection genes
+    float *bn_s = (float *)(bcount + 2);     // SMALL: B's rows [N][5], [C][4]
+    float *bc_s = bn_s + (SMALL ? N * 5 : 0);
     const int t = (int)threadIdx.x, lane = t & (WAVE - 1), wave = t / WAVE;
     const int T = WAVE * DIST_WAVES;
 
@@ -159,12 +201,20 @@ __global__ __launch_bounds__(WAVE *DIST_WAVES) void distance_kernel(DistLaunch L
         int nb = 0, cb = 0;
         for (int r = t; r < N; r += T) {
             const float k = Bn[(size_t)r * 5];
+            if constexpr (SMALL) {
+#pragma unroll
+                for (int f = 0; f < 5; ++f) bn_s[r * 5 + f] = Bn[(size_t)r * 5 + f];
+            }
             if (isnan(k)) continue;
             ++nb;
             insert(nk, nr, HN, key_bits(k), r);
         }
         for (int r = t; r < C; r += T) {
             const float ki = Bc[(size_t)r * 4], ko = Bc[(size_t)r * 4 + 1];
+            if constexpr (SMALL) {
+#pragma unroll
+                for (int f = 0; f < 4; ++f) bc_s[r * 4 + f] = Bc[(size_t)r * 4 + f];
+            }
             if (isnan(ki)) continue;
             ++cb;
             if (isnan(ko)) continue;  // can never match
@@ -191,7 +241,7 @@ __global__ __launch_bounds__(WAVE *DIST_WAVES) void distance_kernel(DistLaunch L
                 if (!isnan(x[0])) {
                     const int j = lookup_from(nk, nr, HN, key_bits(x[0]), xns[i]);
                     if (j >= 0) {
-                        const float *y = Bn + (size_t)j * 5;
+                        const float *y = bn_s + j * 5;
                         ++hn;
                         sn += fabsf(x[1] - y[1]) + fabsf(x[2] - y[2]) + (float)(x[3] != y[3]) +
                               (float)(x[4] != y[4]);
@@ -205,7 +255,7 @@ __global__ __launch_bounds__(WAVE *DIST_WAVES) void distance_kernel(DistLaunch L
                         ck, cr, HC, ((unsigned long long)key_bits(xm[0]) << 32) | key_bits(xm[1]),
                         xcs[i][m]);
                     if (j < 0) continue;
-                    const float *y = Bc + (size_t)j * 4;
+                    const float *y = bc_s + j * 4;
                     ++hc;
                     sc += fabsf(xm[3] - y[3]) + (float)(xm[2] != y[2]);
                 }
@@ -231,10 +281,10 @@ __global__ __launch_bounds__(WAVE *DIST_WAVES) void distance_kernel(DistLaunch L
                     sc += fabsf(x[3] - y[3]) + (float)(x[2] != y[2]);
                 }
             }
-            hn = wave_sum(hn);
-            hc = wave_sum(hc);
-            sn = wave_sum(sn);
-            sc = wave_sum(sc);
+            hn = wave_total(hn);
+            hc = wave_total(hc);
+            sn = wave_total(sn);
+            sc = wave_total(sc);
             if (lane == 0) {
                 const int mn = max(na[i], nb), mc = max(ca[i], cb);
                 const float dn =
@@ -390,9 +440,17 @@ int pow2_at_least(int x) {
 
 }  // namespace
 
-size_t distance_lds_bytes(int N, int C) {
+// the two hash tables and two counters
+size_t gene_tables_lds_bytes(int N, int C) {
     const int hn = pow2_at_least(2 * N), hc = pow2_at_least(2 * C);
     return (size_t)(hn + hc) * (sizeof(unsigned long long) + sizeof(int)) + 2 * sizeof(int);
+}
+
+static bool distance_small(int N, int C) { return N <= WAVE && C <= WAVE * SMALL_CONN_ROWS; }
+
+size_t distance_lds_bytes(int N, int C) {
+    return gene_tables_lds_bytes(N, C) +
+           (distance_small(N, C) ? sizeof(float) * (size_t)(5 * N + 4 * C) : 0);
 }
 
 hipError_t crossover_launch(CrossLaunch L, hipStream_t stream) {
@@ -400,7 +458,7 @@ hipError_t crossover_launch(CrossLaunch L, hipStream_t stream) {
     L.hc = pow2_at_least(2 * L.C);
     if (L.Pc == 0) return hipSuccess;
     hipLaunchKernelGGL(crossover_kernel, dim3((unsigned)L.Pc), dim3(WAVE),
-                       distance_lds_bytes(L.N, L.C), stream, L);
+                       gene_tables_lds_bytes(L.N, L.C), stream, L);
     return hipGetLastError();
 }
 
@@ -419,7 +477,7 @@ hipError_t distance_launch(DistLaunch L, hipStream_t stream) {
     L.hc = pow2_at_least(2 * L.C);
     if (L.P == 0 || L.Q == 0) return hipSuccess;
     const dim3 grid((unsigned)((L.P + DIST_GENOMES - 1) / DIST_GENOMES)), block(WAVE * DIST_WAVES);
-    if (L.N <= WAVE && L.C <= WAVE * SMALL_CONN_ROWS)
+    if (distance_small(L.N, L.C))
         hipLaunchKernelGGL(distance_kernel<true>, grid, block, distance_lds_bytes(L.N, L.C), stream,
                            L);
     else
