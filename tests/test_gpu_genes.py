@@ -35,7 +35,10 @@ def _check(d, nodes, conns, rnodes, rconns, cd=1.0, ch=0.5):
 
 
 @pytest.mark.parametrize("P,Q,N,C", [(50, 7, 12, 30), (40, 16, 50, 200), (9, 5, 150, 600),
-                                     (5, 3, 400, 1600), (70, 1, 8, 0)])
+                                     (5, 3, 400, 1600), (70, 1, 8, 0),
+                                     # largest shape with genes in registers and B's rows
+                                     # in LDS, and the first one past it
+                                     (17, 4, 64, 256), (11, 3, 65, 257)])
 def test_distance_parity(P, Q, N, C):
     print("case", P, Q, N, C, flush=True)
     rng = np.random.default_rng(P + N)
