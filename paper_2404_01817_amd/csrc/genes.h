@@ -31,7 +31,9 @@ hipError_t distance_launch(DistLaunch L, hipStream_t stream);
 // children cn/cc [Pc][N][5] / [Pc][C][4] of the parent pairs [Pc][2] of
 // nodes/conns [P][N][5] / [P][C][4], with uniform numbers rn [Pc][N], rc
 // [Pc][C] per first-parent row; a pair with an index outside [0, P) gives
-// an all-NaN child; hn, hc as for DistLaunch.
+// an all-NaN child; hn, hc as for DistLaunch (words: one wave's LDS tables
+// in 8-byte words; vec: conns is 16-byte aligned).  Both are set by
+// crossover_launch.
 struct CrossLaunch {
     const float *nodes;
     const float *conns;
@@ -42,6 +44,7 @@ struct CrossLaunch {
     float *cc;
     int Pc, P, N, C;
     int hn, hc;
+    int words, vec;
 };
 
 hipError_t crossover_launch(CrossLaunch L, hipStream_t stream);

@@ -303,39 +303,53 @@ __global__ __launch_bounds__(WAVE *DIST_WAVES) void distance_kernel(DistLaunch L
 // (p1, p2) keeps p1's rows; a p1 gene homologous in p2 (same node key, or
 // same (in, out) keys; partner = p2's first such row) takes the partner's
 // non-key columns when its uniform number is below 0.5.  One wave per
-// child: p2's genes go into the LDS hash tables, every lane writes its p1
-// rows.
-__global__ __launch_bounds__(WAVE) void crossover_kernel(CrossLaunch L) {
+// child, four children per workgroup while their tables fit in 64 KB of LDS
+// (else one): p2's genes go into the wave's own LDS hash tables, every lane
+// writes its p1 rows (connection rows as 16-byte loads and stores when the
+// tensor is 16-byte aligned).
+constexpr int CROSS_WAVES = 4;
+
+__global__ __launch_bounds__(WAVE *CROSS_WAVES) void crossover_kernel(CrossLaunch L) {
     extern __shared__ unsigned long long dsm[];
     const int N = L.N, C = L.C, HN = L.hn, HC = L.hc;
-    unsigned long long *nk = dsm;
+    const int lane = (int)threadIdx.x & (WAVE - 1), wave = (int)threadIdx.x / WAVE;
+    const int waves = (int)blockDim.x / WAVE;
+    unsigned long long *nk = dsm + (size_t)wave * L.words;  // this wave's tables
     unsigned long long *ck = nk + HN;
     int *nr = (int *)(ck + HC);
     int *cr = nr + HN;
-    const long long k = blockIdx.x;
-    const int lane = (int)threadIdx.x;
-    const int a = L.pairs[2 * k], b = L.pairs[2 * k + 1];
-    if (a < 0 || a >= L.P || b < 0 || b >= L.P) {  // uniform: the whole wave leaves
+    const long long k = (long long)blockIdx.x * waves + wave;
+    const bool live = k < L.Pc;
+    int a = 0, b = 0;
+    if (live) a = L.pairs[2 * k], b = L.pairs[2 * k + 1];
+    // uniform across the wave; every wave reaches both barriers
+    const bool ok = live && a >= 0 && a < L.P && b >= 0 && b < L.P;
+    if (live && !ok) {
         for (int e = lane; e < N * 5; e += WAVE) L.cn[(size_t)k * N * 5 + e] = __builtin_nanf("");
         for (int e = lane; e < C * 4; e += WAVE) L.cc[(size_t)k * C * 4 + e] = __builtin_nanf("");
-        return;
     }
+    if (!ok) a = b = 0;
     const float *An = L.nodes + (size_t)a * N * 5, *Ac = L.conns + (size_t)a * C * 4;
     const float *Bn = L.nodes + (size_t)b * N * 5, *Bc = L.conns + (size_t)b * C * 4;
+    if (ok) {
+        for (int s = lane; s < HN; s += WAVE) nk[s] = EMPTY64, nr[s] = 0x7fffffff;
+        for (int s = lane; s < HC; s += WAVE) ck[s] = EMPTY64, cr[s] = 0x7fffffff;
+    }
+    __syncthreads();
+    if (ok) {
+        for (int r = lane; r < N; r += WAVE) {
+            const float key = Bn[(size_t)r * 5];
+            if (!isnan(key)) insert(nk, nr, HN, key_bits(key), r);
+        }
+        for (int r = lane; r < C; r += WAVE) {
+            const float ki = Bc[(size_t)r * 4], ko = Bc[(size_t)r * 4 + 1];
+            if (!isnan(ki) && !isnan(ko))
+                insert(ck, cr, HC, ((unsigned long long)key_bits(ki) << 32) | key_bits(ko), r);
+        }
+    }
+    __syncthreads();
+    if (!ok) return;
     float *On = L.cn + (size_t)k * N * 5, *Oc = L.cc + (size_t)k * C * 4;
-    for (int s = lane; s < HN; s += WAVE) nk[s] = EMPTY64, nr[s] = 0x7fffffff;
-    for (int s = lane; s < HC; s += WAVE) ck[s] = EMPTY64, cr[s] = 0x7fffffff;
-    __syncthreads();
-    for (int r = lane; r < N; r += WAVE) {
-        const float key = Bn[(size_t)r * 5];
-        if (!isnan(key)) insert(nk, nr, HN, key_bits(key), r);
-    }
-    for (int r = lane; r < C; r += WAVE) {
-        const float ki = Bc[(size_t)r * 4], ko = Bc[(size_t)r * 4 + 1];
-        if (!isnan(ki) && !isnan(ko))
-            insert(ck, cr, HC, ((unsigned long long)key_bits(ki) << 32) | key_bits(ko), r);
-    }
-    __syncthreads();
     for (int r = lane; r < N; r += WAVE) {
         const float *x = An + (size_t)r * 5;
         const float *src = x;
@@ -350,13 +364,22 @@ __global__ __launch_bounds__(WAVE) void crossover_kernel(CrossLaunch L) {
     }
     for (int r = lane; r < C; r += WAVE) {
         const float *x = Ac + (size_t)r * 4;
-        const float *src = x;
-        if (!isnan(x[0]) && !isnan(x[1]) && L.rc[(size_t)k * C + r] < 0.5f) {
+        float4 v;
+        if (L.vec) v = *reinterpret_cast<const float4 *>(x);
+        else v = make_float4(x[0], x[1], x[2], x[3]);
+        if (!isnan(v.x) && !isnan(v.y) && L.rc[(size_t)k * C + r] < 0.5f) {
             const int j = lookup(ck, cr, HC,
-                                 ((unsigned long long)key_bits(x[0]) << 32) | key_bits(x[1]));
-            if (j >= 0) src = Bc + (size_t)j * 4;
+                                 ((unsigned long long)key_bits(v.x) << 32) | key_bits(v.y));
+            if (j >= 0) {
+                const float *y = Bc + (size_t)j * 4;
+                if (L.vec) {
+                    const float2 w = *reinterpret_cast<const float2 *>(y + 2);
+                    v.z = w.x, v.w = w.y;
+                } else {
+                    v.z = y[2], v.w = y[3];
+                }
+            }
         }
-        float4 v = make_float4(x[0], x[1], src[2], src[3]);
         *reinterpret_cast<float4 *>(Oc + (size_t)r * 4) = v;
     }
 }
@@ -456,9 +479,14 @@ size_t distance_lds_bytes(int N, int C) {
 hipError_t crossover_launch(CrossLaunch L, hipStream_t stream) {
     L.hn = pow2_at_least(2 * L.N);
     L.hc = pow2_at_least(2 * L.C);
+    L.words = L.hn + L.hc + (L.hn + L.hc) / 2;  // keys, then rows (hn + hc even)
+    L.vec = ((uintptr_t)L.conns % 16) == 0;
     if (L.Pc == 0) return hipSuccess;
-    hipLaunchKernelGGL(crossover_kernel, dim3((unsigned)L.Pc), dim3(WAVE),
-                       gene_tables_lds_bytes(L.N, L.C), stream, L);
+    // four children per workgroup while their tables stay small (≤ 64 KB)
+    const size_t wave_bytes = sizeof(unsigned long long) * (size_t)L.words;
+    const int waves = 4 * wave_bytes <= 65536 ? CROSS_WAVES : 1;
+    hipLaunchKernelGGL(crossover_kernel, dim3((unsigned)((L.Pc + waves - 1) / waves)),
+                       dim3(WAVE * waves), waves * wave_bytes, stream, L);
     return hipGetLastError();
 }
 
