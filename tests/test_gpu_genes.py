@@ -198,7 +198,10 @@ def _random_edits(rng, P, N, C, n):
 
 
 @pytest.mark.parametrize("P,N,C,n", [(20, 12, 30, 400), (50, 50, 200, 3000),
-                                     (5, 300, 1200, 2000), (8, 8, 0, 100)])
+                                     (5, 300, 1200, 2000), (8, 8, 0, 100),
+                                     # several rounds of the 64-way range search; most
+                                     # genomes without edits
+                                     (400, 12, 30, 20000), (2000, 8, 20, 300)])
 def test_edits_bit_exact(P, N, C, n):
     print("case", P, N, C, n, flush=True)
     rng = np.random.default_rng(P + n)
