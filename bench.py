@@ -76,7 +76,10 @@ def parse():
                          "(compatibility distance to species representatives), "
                          "crossover (children of genome pairs), edit (tensorized "
                          "mutation edits)")
-    ap.add_argument("--served-seconds", type=float, default=20.0,
+    ap.add_argument("--served-burst", type=int, default=512,
+                    help="requests of the saturation comparison (served burst against "
+                         "plain per-request launches); 0 skips it")
+    ap.add_argument("--served-seconds", type=float, default=60.0,
                     help="length of the served request stream (latency counted after "
                          "the first quarter)")
     ap.add_argument("--served-rate", type=float, default=200.0, help="requests per second")
@@ -298,6 +301,8 @@ def bench_served(args, torch, neat, synth):
         drain()
     wall = time.perf_counter() - t_start
     st = server.stats()
+    burst = served_burst(args, torch, neat, server, pool, ids, xpool, ypool) \
+        if args.served_burst > 0 else None
     server.close()
     lat = np.array([l for k, l in done if arrivals[k] >= 0.25 * args.served_seconds])
     gi = int(sum(pool[which[k]].P * int(Bs[k]) for k in range(n_req)))
@@ -310,7 +315,80 @@ def bench_served(args, torch, neat, synth):
         "latency_counted": int(len(lat)), "genome_inputs": gi,
         "throughput": round(gi / wall, 1), "unit": "genome-inputs/s",
         "batches": int(st.batches), "mean_requests_per_batch": round(n_req / max(1, st.batches), 2),
+        "burst_vs_plain": burst,
     }
+
+
+def served_burst(args, torch, neat, server, pool, ids, xpool, ypool):
+    """Saturation: the same requests (population and B drawn as in the
+    stream) once queued to the server all at once, once as plain
+    per-request forward launches one after another; programs are resident
+    in both forms (the plain form's transformed before timing).  Best of
+    three; the outputs of the two forms are compared bit for bit."""
+    dev = torch.device("cuda:0")
+    rng = np.random.default_rng(4)
+    reqs, xo, yo = [], 0, 0
+    while len(reqs) < args.served_burst:
+        j = int(rng.integers(0, len(pool)))
+        B = int(np.rint(np.exp(rng.uniform(0.0, np.log(256.0)))))
+        pop = pool[j]
+        nx, ny = pop.P * B * pop.I, pop.P * B * pop.O
+        if xo + nx > xpool.numel() or yo + ny > ypool.numel():
+            break
+        reqs.append((j, B, xo, nx, yo, ny))
+        xo, yo = xo + nx, yo + ny
+    progs = {}
+    for j in sorted({r[0] for r in reqs}):
+        pop = pool[j]
+        tn = torch.from_numpy(pop.nodes).to(dev)
+        tc = torch.from_numpy(pop.conns).to(dev)
+        _, _, _, pg = neat.topo_sort(tn, tc, pop.I, pop.O, want_order=False)
+        progs[j] = (neat.dims_of(tn, tc, pop.I, pop.O), pg)
+        del tn, tc
+    yplain = torch.empty((yo,), device=dev)
+
+    def plain():
+        for j, B, x0, nx, y0, ny in reqs:
+            pop = pool[j]
+            d, pg = progs[j]
+            neat.forward(d, pg, xpool[x0:x0 + nx].view(pop.P, B, pop.I), B,
+                         outputs=yplain[y0:y0 + ny].view(pop.P, B, pop.O))
+        torch.cuda.synchronize()
+
+    def served():
+        pending = set()
+        for k, (j, B, x0, nx, y0, ny) in enumerate(reqs):
+            pending.add(server.submit(ids[j], ypool[y0:y0 + ny], inputs=xpool[x0:x0 + nx],
+                                      B=B, I=pool[j].I, tag=k))
+        while pending:
+            for t in list(pending):
+                if server.poll(t) is not None:
+                    pending.discard(t)
+        torch.cuda.synchronize()
+
+    times = {}
+    for name, fn in (("plain", plain), ("served", served)):
+        fn()  # warm-up
+        best = float("inf")
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            fn()
+            best = min(best, time.perf_counter() - t)
+        times[name] = best
+    same = bool(torch.equal(ypool[:yo].view(torch.int32), yplain.view(torch.int32)))
+    gi = sum(pool[r[0]].P * r[1] for r in reqs)
+    b0 = server.stats().batches
+    served()
+    nb = server.stats().batches - b0
+    return {"requests": len(reqs), "genome_inputs": int(gi),
+            "plain_ms": round(times["plain"] * 1e3, 3),
+            "plain_value": round(gi / times["plain"], 1),
+            "served_ms": round(times["served"] * 1e3, 3),
+            "served_value": round(gi / times["served"], 1),
+            "served_speedup": round(times["plain"] / times["served"], 3),
+            "served_batches": int(nb), "outputs_identical": same,
+            "unit": "genome-inputs/s"}
 
 
 def bench_cppn(args, torch, neat, synth):
