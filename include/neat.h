@@ -157,6 +157,8 @@ int neat_forward(const neat_dims *dims, const void *program, const float *inputs
 #define NEAT_FWD_REG 1  /* registers, one sample per lane (LDS rows for the LDS class) */
 #define NEAT_FWD_LDS 2  /* every genome in LDS rows */
 #define NEAT_FWD_REG2 3 /* as NEAT_FWD_REG, two samples per lane for the smallest class */
+#define NEAT_FWD_TUNED 4 /* the variant neat_autotune_forward measured fastest for the
+                            call's bucket; NEAT_FWD_AUTO while none is recorded */
 
 /*
  * neat_forward with an explicit variant (NEAT_FWD_*); same arguments.  All
@@ -172,6 +174,31 @@ int neat_forward(const neat_dims *dims, const void *program, const float *inputs
 int neat_forward_ex(const neat_dims *dims, const void *program, const float *inputs,
                     int64_t input_genome_stride, int32_t B, float *outputs, int32_t variant,
                     void *stream);
+
+/*
+ * Autotuner of the calculation stage (not a passage of the paper: a tuning
+ * aid for the population-wide calculation of Section 3.3).  Times
+ * NEAT_FWD_REG, NEAT_FWD_REG2 and NEAT_FWD_LDS on the caller's buffers, one
+ * warm-up and `reps` launches each, with HIP events on `stream`, and records
+ * the fastest in a process-wide table under the call's bucket: N_max and
+ * C_max rounded up to powers of two, B to a power of two capped at 1024.
+ * neat_forward_ex with NEAT_FWD_TUNED and neat_forward_batch (per item)
+ * read that table; both fall back to NEAT_FWD_AUTO for buckets never tuned.
+ * Every variant gives identical bits, so tuning changes no result.
+ *   arguments as neat_forward_ex (outputs are overwritten);
+ *   reps         launches timed per variant, 1..1000
+ *   variant_out  (host, written) the fastest variant; NEAT_FWD_AUTO when
+ *                P = 0 or B = 0 (nothing is timed or recorded)
+ *   ms_out       [3] (host, written, nullable) mean ms per launch of REG,
+ *                REG2 and LDS
+ * Synchronizes `stream`; the table is shared by every thread of the
+ * process (guarded by a mutex).
+ * Errors: as neat_forward_ex; NEAT_E_INVALID for reps or a NULL
+ * variant_out; NEAT_E_HIP.
+ */
+int neat_autotune_forward(const neat_dims *dims, const void *program, const float *inputs,
+                          int64_t input_genome_stride, int32_t B, float *outputs, int32_t reps,
+                          int32_t *variant_out, float *ms_out, void *stream);
 
 /*
  * Calculation stage for CPPN substrate queries (the paper's CPPN/HyperNEAT

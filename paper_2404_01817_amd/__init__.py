@@ -11,11 +11,11 @@ from __future__ import annotations
 import ctypes
 from typing import Optional, Tuple
 
-from ._lib import (FWD_AUTO, FWD_LDS, FWD_REG, FWD_REG2, INPUT_GRID, INPUT_TENSOR, BatchItem,
-                   Dims, NeatError, Request, Result, ServerCfg, Stats, check, lib)
+from ._lib import (FWD_AUTO, FWD_LDS, FWD_REG, FWD_REG2, FWD_TUNED, INPUT_GRID, INPUT_TENSOR,
+                   BatchItem, Dims, NeatError, Request, Result, ServerCfg, Stats, check, lib)
 
 __all__ = ["Dims", "NeatError", "dims_of", "program_bytes", "topo_sort", "forward",
-           "forward_grid", "forward_recurrent", "substrate_forward", "distance",
+           "autotune_forward", "forward_grid", "forward_recurrent", "substrate_forward", "distance",
            "crossover", "edit"]
 
 
@@ -118,6 +118,20 @@ def forward(dims: Dims, program, inputs, B: int, shared_inputs: bool = False,
                                 _ptr(outputs), variant, _stream(stream)))
     return outputs
 
+
+
+def autotune_forward(dims: Dims, program, inputs, B: int, outputs=None, reps: int = 5,
+                     stream=None):
+    """Time the forward variants on these buffers and record the fastest for
+    the call's bucket (neat_autotune_forward); returns (variant, [ms of
+    FWD_REG, FWD_REG2, FWD_LDS]).  Later calls with variant=FWD_TUNED, and
+    batches, use the recorded variant."""
+    stride, outputs = _io(dims, inputs, B, False, outputs)
+    v = ctypes.c_int32(0)
+    ms = (ctypes.c_float * 3)()
+    check(lib().neat_autotune_forward(ctypes.byref(dims), _ptr(program), _ptr(inputs), stride, B,
+                                      _ptr(outputs), reps, ctypes.byref(v), ms, _stream(stream)))
+    return v.value, [float(x) for x in ms]
 
 def distance(nodes, conns, rnodes, rconns, c_disjoint: float = 1.0,
              c_homologous: float = 0.5, out=None, stream=None):

@@ -15,7 +15,7 @@ LIB_PATH = os.path.join(PKG, "libneat.so")
 
 NEAT_OK = 0
 NEAT_PENDING = 1
-FWD_AUTO, FWD_REG, FWD_LDS, FWD_REG2 = 0, 1, 2, 3
+FWD_AUTO, FWD_REG, FWD_LDS, FWD_REG2, FWD_TUNED = 0, 1, 2, 3, 4
 
 
 class NeatError(RuntimeError):
@@ -81,6 +81,8 @@ SIGNATURES = {
     "neat_topo_sort": (_i32, [ctypes.POINTER(Dims), _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "neat_forward": (_i32, [ctypes.POINTER(Dims), _vp, _vp, _i64, _i32, _vp, _vp]),
     "neat_forward_ex": (_i32, [ctypes.POINTER(Dims), _vp, _vp, _i64, _i32, _vp, _i32, _vp]),
+    "neat_autotune_forward": (_i32, [ctypes.POINTER(Dims), _vp, _vp, _i64, _i32, _vp, _i32,
+                                     _vp, _vp, _vp]),
     "neat_forward_grid": (_i32, [ctypes.POINTER(Dims), _vp, _i32, _i64, _i32, _vp, _vp]),
     "neat_apply_edits": (_i32, [ctypes.POINTER(Dims), _vp, _vp, _vp, _i32, _vp, _vp]),
     "neat_crossover": (_i32, [ctypes.POINTER(Dims), _vp, _vp, _i32, _vp, _vp, _vp, _vp, _vp,

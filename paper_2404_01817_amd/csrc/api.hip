@@ -5,13 +5,16 @@
 
 #include <cstdarg>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <string>
 
 #include "abi.h"
 #include "genes.h"
 #include "launch.h"
+#include "tune.h"
 #include "neat.h"
 #include "program.h"
 
@@ -123,6 +126,30 @@ FwdJob make_job(const neat_dims *d, const void *program, const float *inputs, in
 
 using namespace neat::abi;
 
+// ---- autotuner: the fastest variant per (N_max, C_max, B) bucket ----------
+namespace {
+std::mutex g_tune_mu;
+std::map<unsigned long long, int> g_tune;
+
+long long pow2_ceil(long long x) {
+    long long p = 1;
+    while (p < x) p <<= 1;
+    return p;
+}
+unsigned long long tune_key(int N, int C, int B) {
+    return ((unsigned long long)pow2_ceil(N) << 42) | ((unsigned long long)pow2_ceil(C) << 21) |
+           (unsigned long long)std::min(pow2_ceil(B), 1024ll);
+}
+}  // namespace
+
+namespace neat {
+int tuned_variant(int N, int C, int B) {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    const auto it = g_tune.find(tune_key(N, C, B));
+    return it == g_tune.end() ? FWD_AUTO : it->second;
+}
+}  // namespace neat
+
 extern "C" {
 
 const char *neat_last_error(void) { return g_last_error.c_str(); }
@@ -170,8 +197,9 @@ static int forward_common(const neat_dims *d, const void *program, const float *
                           int32_t side, int64_t first, void *stream) {
     int rc = check_dims(d);
     if (rc != NEAT_OK) return rc;
-    if (variant < NEAT_FWD_AUTO || variant > NEAT_FWD_REG2)
+    if (variant < NEAT_FWD_AUTO || variant > NEAT_FWD_TUNED)
         return fail(NEAT_E_INVALID, "unknown forward variant %d", variant);
+    if (variant == NEAT_FWD_TUNED) variant = neat::tuned_variant(d->N_max, d->C_max, B);
     rc = check_forward_args(d, program, inputs, stride, B, outputs, grid, side, first);
     if (rc != NEAT_OK || d->P == 0 || B == 0) return rc;
     const neat::FwdJob job =
@@ -198,6 +226,59 @@ int neat_forward(const neat_dims *d, const void *program, const float *inputs,
                  int64_t input_genome_stride, int32_t B, float *outputs, void *stream) {
     return neat_forward_ex(d, program, inputs, input_genome_stride, B, outputs, NEAT_FWD_AUTO,
                            stream);
+}
+
+int neat_autotune_forward(const neat_dims *d, const void *program, const float *inputs,
+                          int64_t input_genome_stride, int32_t B, float *outputs, int32_t reps,
+                          int32_t *variant_out, float *ms_out, void *stream) {
+    int rc = check_dims(d);
+    if (rc != NEAT_OK) return rc;
+    if (!variant_out) return fail(NEAT_E_INVALID, "variant_out is NULL");
+    if (reps < 1 || reps > 1000) return fail(NEAT_E_INVALID, "reps = %d outside [1, 1000]", reps);
+    rc = check_forward_args(d, program, inputs, input_genome_stride, B, outputs, false, 0, 0);
+    if (rc != NEAT_OK) return rc;
+    const int cand[3] = {NEAT_FWD_REG, NEAT_FWD_REG2, NEAT_FWD_LDS};
+    float ms[3] = {-1.0f, -1.0f, -1.0f};
+    int best = NEAT_FWD_AUTO;
+    float best_ms = 0.0f;
+    if (d->P > 0 && B > 0) {
+        hipEvent_t e0, e1;
+        if (hipEventCreate(&e0) != hipSuccess) return hip_fail(hipGetLastError(), "event");
+        if (hipEventCreate(&e1) != hipSuccess) {
+            hipEventDestroy(e0);
+            return hip_fail(hipGetLastError(), "event");
+        }
+        const hipStream_t s = (hipStream_t)stream;
+        for (int i = 0; i < 3 && rc == NEAT_OK; ++i) {
+            rc = forward_common(d, program, inputs, input_genome_stride, B, outputs, cand[i],
+                                false, 0, 0, stream);  // warm-up
+            if (rc != NEAT_OK) break;
+            hipError_t e = hipEventRecord(e0, s);
+            for (int r = 0; r < reps && rc == NEAT_OK && e == hipSuccess; ++r)
+                rc = forward_common(d, program, inputs, input_genome_stride, B, outputs,
+                                    cand[i], false, 0, 0, stream);
+            if (rc != NEAT_OK) break;
+            if (e == hipSuccess) e = hipEventRecord(e1, s);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float t = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+            if (e != hipSuccess) {
+                rc = hip_fail(e, "autotune timing");
+                break;
+            }
+            ms[i] = t / (float)reps;
+            if (best == NEAT_FWD_AUTO || ms[i] < best_ms) best = cand[i], best_ms = ms[i];
+        }
+        hipEventDestroy(e0);
+        hipEventDestroy(e1);
+        if (rc != NEAT_OK) return rc;
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        g_tune[tune_key(d->N_max, d->C_max, B)] = best;
+    }
+    *variant_out = best;
+    if (ms_out)
+        for (int i = 0; i < 3; ++i) ms_out[i] = ms[i];
+    return NEAT_OK;
 }
 
 int neat_topo_sort_recurrent(const neat_dims *d, const float *nodes, const float *conns,

@@ -22,6 +22,7 @@
 
 #include "abi.h"
 #include "launch.h"
+#include "tune.h"
 #include "neat.h"
 #include "program.h"
 
@@ -153,15 +154,28 @@ int build(const neat_batch_item *items, int32_t n, neat_batch_plan **out) {
     const size_t all_off = topo_host.size();
     topo_host.insert(topo_host.end(), all_topo.begin(), all_topo.end());
     const int topo_launches = (int)topo.size() + (all_topo.empty() ? 0 : 1);
+    std::vector<int> job_variant;
     for (const neat_batch_item &it : p->items) {
         if (it.dims.P == 0 || it.B == 0) continue;
         jobs.push_back(make_job(&it.dims, it.program, it.inputs, it.input_genome_stride, it.B,
                                 it.outputs, it.grid_side, it.grid_first));
+        job_variant.push_back(neat::tuned_variant(it.dims.N_max, it.dims.C_max, it.B));
     }
+    // one plan per variant tuned for the items' buckets (all FWD_AUTO, one
+    // plan, while nothing is tuned)
     std::vector<neat::FwdKernelLaunch> fw;
     char err[256] = "";
-    int rc = neat::forward_plan(jobs.data(), (int)jobs.size(), neat::FWD_AUTO, max_lds_bytes(),
-                                fw, err, sizeof(err));
+    int rc = NEAT_OK;
+    for (int v = neat::FWD_AUTO; v <= neat::FWD_REG2 && rc == NEAT_OK; ++v) {
+        std::vector<neat::FwdJob> group;
+        for (size_t j = 0; j < jobs.size(); ++j)
+            if (job_variant[j] == v) group.push_back(jobs[j]);
+        if (group.empty()) continue;
+        std::vector<neat::FwdKernelLaunch> part;
+        rc = neat::forward_plan(group.data(), (int)group.size(), v, max_lds_bytes(), part, err,
+                                sizeof(err));
+        fw.insert(fw.end(), part.begin(), part.end());
+    }
     if (rc != NEAT_OK) {
         destroy(p);
         return fail(rc, "%s", err);

@@ -1,0 +1,88 @@
+"""GPU tests of the forward autotuner (neat_autotune_forward, through the C
+ABI): the tuned variant is one of the three measured ones, tuning leaves
+the outputs bit-identical to the automatic rule, and later calls with
+FWD_TUNED and batches over tuned buckets give the same bits as untuned
+calls (every variant runs the same operations in the same order)."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+from paper_2404_01817_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _neat():
+    import paper_2404_01817_amd as neat
+    return neat
+
+
+def _bits(t):
+    return t.cpu().numpy().view(np.uint32)
+
+
+class _Pop:
+    def __init__(self, seed, P, B):
+        neat = _neat()
+        dev = torch.device("cuda:0")
+        pop = synth.control(seed=seed, P=P, B=B)
+        self.B = B
+        self.nodes = torch.from_numpy(pop.nodes).to(dev)
+        self.conns = torch.from_numpy(pop.conns).to(dev)
+        self.x = torch.from_numpy(pop.inputs).to(dev)
+        self.d = neat.dims_of(self.nodes, self.conns, pop.I, pop.O)
+        _, _, _, self.prog = neat.topo_sort(self.nodes, self.conns, pop.I, pop.O,
+                                            want_order=False)
+        self.y = torch.empty((P, B, pop.O), device=dev)
+
+    def auto(self):
+        return _neat().forward(self.d, self.prog, self.x, self.B)
+
+
+@pytest.mark.parametrize("P,B", [(300, 130), (64, 17)])
+def test_autotune_records_a_measured_variant(P, B):
+    neat = _neat()
+    p = _Pop(seed=P + B, P=P, B=B)
+    ref = p.auto()
+    v, ms = neat.autotune_forward(p.d, p.prog, p.x, B, outputs=p.y, reps=3)
+    torch.cuda.synchronize()
+    print("tuned", P, B, v, ms, flush=True)
+    assert v in (neat.FWD_REG, neat.FWD_REG2, neat.FWD_LDS)
+    assert all(m > 0 for m in ms)
+    assert ms[[neat.FWD_REG, neat.FWD_REG2, neat.FWD_LDS].index(v)] == min(ms)
+    assert np.array_equal(_bits(p.y), _bits(ref))
+    y2 = neat.forward(p.d, p.prog, p.x, B, variant=neat.FWD_TUNED)
+    assert np.array_equal(_bits(y2), _bits(ref))
+
+
+def test_batch_over_tuned_buckets_matches_single_calls():
+    neat = _neat()
+    pops = [_Pop(seed=s, P=P, B=B) for s, P, B in ((1, 200, 100), (2, 150, 40), (3, 90, 300))]
+    refs = [p.auto() for p in pops]
+    neat.autotune_forward(pops[0].d, pops[0].prog, pops[0].x, pops[0].B, reps=2)
+    neat.autotune_forward(pops[2].d, pops[2].prog, pops[2].x, pops[2].B, reps=2)
+    plan = neat.BatchPlan()
+    items = [neat.batch_item(p.d, p.prog, p.y, inputs=p.x, B=p.B) for p in pops]
+    for _ in range(2):  # record, then replay
+        for p in pops:
+            p.y.fill_(float("nan"))
+        plan.run(items)
+        torch.cuda.synchronize()
+        for p, r in zip(pops, refs):
+            assert np.array_equal(_bits(p.y), _bits(r))
+    plan.free()
+
+
+def test_autotune_arguments():
+    neat = _neat()
+    p = _Pop(seed=5, P=20, B=8)
+    with pytest.raises(neat.NeatError):
+        neat.autotune_forward(p.d, p.prog, p.x, 8, reps=0)
+    with pytest.raises(neat.NeatError):
+        neat.forward(p.d, p.prog, p.x, 8, variant=5)
+    v, ms = neat.autotune_forward(p.d, p.prog, p.x, 0, reps=2)
+    assert v == neat.FWD_AUTO and ms == [-1.0, -1.0, -1.0]
+    torch.cuda.synchronize()
