@@ -16,7 +16,9 @@
  * Around them: neat_forward_grid (CPPN queries made in the kernel),
  * neat_substrate_forward (HyperNEAT substrate layer on the matrix cores),
  * neat_topo_sort_recurrent / neat_forward_recurrent (networks with cycles),
- * neat_forward_batch (many populations in one recorded graph), the server
+ * neat_forward_ex / neat_autotune_forward (value-store variants and their
+ * per-bucket tuning), neat_forward_batch (many populations in one recorded
+ * graph), the server
  * (neat_server_*, neat_submit, neat_poll: resident populations, continuous
  * batching), and the gene-level operators of a generation: neat_distance,
  * neat_crossover and neat_apply_edits.
