@@ -6,6 +6,7 @@ import numpy as np
 import pytest
 
 import oracle
+from tests.parity import assert_parity
 from paper_2404_01817_amd import synth
 
 pytestmark = pytest.mark.gpu
@@ -94,8 +95,7 @@ def test_batch_matches_single_calls_and_oracle():
             q = synth.grid_queries(p.grid[1], p.grid[2])
             y64, beta = oracle.forward(p.pop.nodes, p.pop.conns, q, p.pop.I, p.pop.O,
                                        shared_inputs=True)
-        ok, stats = oracle.within_tolerance(y, y64, beta)
-        assert stats["n_fail"] == 0, (k, stats)
+        stats = assert_parity(y, y64, beta, "item %d" % k)
         st = p.status.cpu().numpy().astype(np.uint32)
         assert np.array_equal(st, oracle.transform(p.pop.nodes, p.pop.conns, p.pop.I,
                                                    p.pop.O)[2])
@@ -172,6 +172,5 @@ def test_batch_with_the_largest_genomes():
         y = p.y.cpu().numpy()
         assert _same_bits(y, p.single()), k
         y64, beta = oracle.forward(p.pop.nodes, p.pop.conns, p.pop.inputs, p.pop.I, p.pop.O)
-        ok, stats = oracle.within_tolerance(y, y64, beta)
-        assert stats["n_fail"] == 0, (k, stats)
+        stats = assert_parity(y, y64, beta, "item %d" % k)
     plan.free()

@@ -9,6 +9,7 @@ import numpy as np
 import pytest
 
 import oracle
+from tests.parity import assert_parity
 from paper_2404_01817_amd import synth
 from tests.helpers import genome, read_golden, stack
 
@@ -54,9 +55,7 @@ def _assert_transform_exact(nodes, conns, I, O, g_order, g_level, g_status):
 
 
 def _assert_outputs(y_gpu, y64, beta, label=""):
-    ok, stats = oracle.within_tolerance(y_gpu, y64, beta)
-    print(label, stats)
-    assert stats["n_fail"] == 0, (label, stats)
+    stats = assert_parity(y_gpu, y64, beta, label)
     return stats
 
 

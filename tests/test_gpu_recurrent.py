@@ -10,6 +10,7 @@ import numpy as np
 import pytest
 
 import oracle
+from tests.parity import assert_parity
 from paper_2404_01817_amd import synth
 from tests.helpers import genome, stack
 
@@ -56,9 +57,7 @@ def _check(pop, K, label):
     assert np.array_equal(order, o_order), label
     assert np.array_equal(level, o_level), label
     y64, beta = oracle.forward_recurrent(pop.nodes, pop.conns, pop.inputs, pop.I, pop.O, K)
-    ok, stats = oracle.within_tolerance(y, y64, beta)
-    print(label, stats)
-    assert stats["n_fail"] == 0, (label, stats)
+    stats = assert_parity(y, y64, beta, label)
 
 
 # (P, N_max, C_max, I, O, B): one-wave transformation groups, multi-wave
@@ -81,8 +80,7 @@ def test_recurrent_shared_inputs():
     x = np.random.default_rng(8).standard_normal((150, 5)).astype(np.float32)
     _, _, status, y = _gpu_rec(pop.nodes, pop.conns, 5, 3, x, 5, shared=True)
     y64, beta = oracle.forward_recurrent(pop.nodes, pop.conns, x, 5, 3, 5, shared_inputs=True)
-    ok, stats = oracle.within_tolerance(y, y64, beta)
-    assert stats["n_fail"] == 0, stats
+    stats = assert_parity(y, y64, beta, "")
 
 
 def test_recurrent_status_cases_bit_exact():
@@ -101,8 +99,7 @@ def test_recurrent_status_cases_bit_exact():
     assert status.tolist() == o_status.tolist() == [0, 8, 16, 32, 1, 2, 4]
     assert np.array_equal(order, o_order) and np.array_equal(level, o_level)
     y64, beta = oracle.forward_recurrent(n, c, x, 2, 1, 4)
-    ok, stats = oracle.within_tolerance(y, y64, beta)
-    assert stats["n_fail"] == 0, stats
+    stats = assert_parity(y, y64, beta, "")
     assert np.all(np.isnan(y[1:]))
 
 
@@ -177,6 +174,4 @@ def test_recurrent_full_size_sampled():
     sample = np.concatenate([sample, [0, pop.P - 1]])
     y64, beta = oracle.forward_recurrent(pop.nodes[sample], pop.conns[sample],
                                          pop.inputs[sample], pop.I, pop.O, K)
-    ok, stats = oracle.within_tolerance(y[sample], y64, beta)
-    print("full size sample", stats)
-    assert stats["n_fail"] == 0, stats
+    stats = assert_parity(y[sample], y64, beta, "")

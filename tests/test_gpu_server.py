@@ -1,11 +1,20 @@
 """GPU: the served path (resident populations, continuous batching)
-against single-population calls; admission, polling and shutdown."""
+against the fp64 oracle and against single-population calls; admission,
+polling and shutdown.
+
+A served result is the calculation of Section 3.3 for the request's
+population and inputs, so every served output is checked against
+``oracle.forward`` (tensor requests on their inputs, grid requests on the
+CPPN queries of ``synth.grid_queries``) under the parity rule, and must also
+equal the single ``neat_forward`` / ``neat_forward_grid`` call bit for bit."""
 from __future__ import annotations
 
 import numpy as np
 import pytest
 
+import oracle
 from paper_2404_01817_amd import synth
+from tests.parity import assert_parity
 
 pytestmark = pytest.mark.gpu
 
@@ -52,6 +61,17 @@ def _pool(server):
     return res
 
 
+def _oracle(req):
+    """fp64 oracle outputs and bounds of one request."""
+    r, B, x, grid = req
+    p = r.pop
+    if grid is None:
+        return oracle.forward(p.nodes, p.conns, x.cpu().numpy(), p.I, p.O)
+    side, first, Q = grid
+    q = synth.grid_queries(first, Q, side)
+    return oracle.forward(p.nodes, p.conns, q, p.I, p.O, shared_inputs=True)
+
+
 def _requests(pool, n, seed):
     """(resident, B, x or None, grid or None) for n random requests."""
     rng = np.random.default_rng(seed)
@@ -81,7 +101,8 @@ def _submit(server, req, tag):
 
 def test_served_requests_equal_single_calls():
     """Many requests of mixed populations, sizes and modes in flight at once
-    give the bits of one neat_forward / neat_forward_grid call each."""
+    match the oracle and give the bits of one neat_forward /
+    neat_forward_grid call each."""
     neat = _neat()
     server = neat.Server(max_inflight=3)
     pool = _pool(server)
@@ -93,7 +114,11 @@ def test_served_requests_equal_single_calls():
         assert res.t_submit_ns <= res.t_admit_ns <= res.t_done_ns
         r, B, x, grid = q
         ref = r.reference(x, B) if grid is None else r.reference(grid=grid)
-        assert _same_bits(y.cpu().numpy(), ref), k
+        got = y.cpu().numpy()
+        assert _same_bits(got, ref), k
+        y64, beta = _oracle(q)
+        assert_parity(got, y64, beta, "request %d N_max=%d B=%d %s" % (
+            k, r.pop.N_max, B, "grid" if grid else "tensor"))
     st = server.stats()
     assert st.submitted == st.completed == len(reqs) and st.queued == 0
     assert st.p99_ms >= st.p50_ms > 0 and st.batches >= 1
@@ -111,7 +136,13 @@ def test_request_alone_equals_request_in_mix():
     sub = [_submit(server, q, k) for k, q in enumerate(reqs)]
     for t, _ in sub:
         server.wait(t)
-    assert _same_bits(y_alone.cpu().numpy(), sub[7][1].cpu().numpy())
+    alone = y_alone.cpu().numpy()
+    assert _same_bits(alone, sub[7][1].cpu().numpy())
+    y64, beta = _oracle(probe)
+    assert_parity(alone, y64, beta, "request alone")
+    for k in (0, 13, 29):
+        y64, beta = _oracle(reqs[k])
+        assert_parity(sub[k][1].cpu().numpy(), y64, beta, "request %d in the mix" % k)
     server.close()
 
 
@@ -135,6 +166,8 @@ def test_admission_cap_and_rejection():
         y = torch.empty((pop.P, 64, pop.O), device=dev)
         ys.append((server.submit(r.id, y, inputs=x, B=64, I=pop.I), y))
     ref = r.reference(x, 64)
+    y64, beta = oracle.forward(pop.nodes, pop.conns, pop.inputs, pop.I, pop.O)
+    assert_parity(ref, y64, beta, "capped requests")
     for t, y in ys:
         assert server.wait(t).status == 0
         assert _same_bits(y.cpu().numpy(), ref)

@@ -10,6 +10,7 @@ import numpy as np
 import pytest
 
 import oracle
+from tests.parity import assert_parity
 from oracle import substrate
 from paper_2404_01817_amd import synth
 from tests.helpers import genome, stack
@@ -55,9 +56,7 @@ def test_substrate_parity(side, B):
     y, w, g = _run(n, c, side, X, substrate.THRESHOLD)
     assert np.array_equal(w.view(np.uint32), g.view(np.uint32))
     Y64, bound = substrate.forward(n, c, side, X)
-    ok, stats = oracle.within_tolerance(y, Y64, bound)
-    print(stats)
-    assert stats["n_fail"] == 0, stats
+    stats = assert_parity(y, Y64, bound, "")
     assert np.all(np.isnan(y[1]))
 
 
@@ -67,8 +66,7 @@ def test_substrate_thresholds(theta):
     X = synth.substrate_inputs(seed=5, B=40, side=8)
     y, _, _ = _run(n, c, 8, X, theta)
     Y64, bound = substrate.forward(n, c, 8, X, theta=theta)
-    ok, stats = oracle.within_tolerance(y, Y64, bound)
-    assert stats["n_fail"] == 0, stats
+    stats = assert_parity(y, Y64, bound, "")
     if theta == 1e30:
         assert np.all(y == 0.0)
 
@@ -123,6 +121,4 @@ def test_substrate_full_size_sampled():
     sample = np.concatenate([np.random.default_rng(0).choice(pop.P, 8, replace=False),
                              [0, pop.P - 1]])
     Y64, bound = substrate.forward(pop.nodes[sample], pop.conns[sample], 16, X)
-    ok, stats = oracle.within_tolerance(y[sample], Y64, bound)
-    print("full size sample", stats)
-    assert stats["n_fail"] == 0, stats
+    stats = assert_parity(y[sample], Y64, bound, "")
