@@ -415,6 +415,32 @@ void neat_batch_plan_free(neat_batch_plan *plan);
 int32_t neat_batch_plan_launches(const neat_batch_plan *plan);
 
 /*
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.
+ * neat_forward_batch_noalloc runs the same transformations and calculations
+ * as neat_forward_batch on the same items, with the same kernels and the
+ * same bits, but records no graph and keeps no plan: every call plans the
+ * batch on the host and launches it directly on `stream`.  The work-unit
+ * tables the kernels read live in a library-owned device array of
+ * NEAT_NOALLOC_SCRATCH_BYTES per GPU (static storage, held until the process
+ * ends; its address is looked up once per device on the first call there),
+ * written by small kernels whose table words travel as kernel arguments.
+ * The call allocates no device memory and calls no hipMalloc / hipFree or
+ * allocating library routine; its host-side planning uses the C++ heap.
+ *   items, n   as neat_forward_batch (caller-owned device tensors)
+ *   stream     HIP stream (may be capturing)
+ * Every call on one GPU shares that GPU's array, and each call rewrites
+ * the tables it uses before its kernels read them: calls on one stream are
+ * ordered and safe; calls that overlap on one GPU (different streams or
+ * threads) race on the array and must not be issued.
+ * Errors: as neat_forward_batch; NEAT_E_TOO_LARGE when the batch's tables
+ * (176 B per transformed population, plus 112 B per population and value
+ * store it uses) exceed NEAT_NOALLOC_SCRATCH_BYTES.
+ */
+#define NEAT_NOALLOC_SCRATCH_BYTES (256 * 1024)
+int neat_forward_batch_noalloc(const neat_batch_item *items, int32_t n, void *stream);
+
+/*
  * Served path: resident populations and continuous batching.
  *
  * neat_server_register copies a population's encoding into library-owned

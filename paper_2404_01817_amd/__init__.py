@@ -311,6 +311,14 @@ class BatchPlan:
             pass
 
 
+def forward_batch_noalloc(items, stream=None) -> None:
+    """The batch of ``BatchPlan.run`` without device allocation
+    (neat_forward_batch_noalloc): launched directly on the stream, work-unit
+    tables in the library's static scratch area."""
+    arr = (BatchItem * len(items))(*items) if items else None
+    check(lib().neat_forward_batch_noalloc(arr, len(items), _stream(stream)))
+
+
 class Server:
     """Resident populations and continuous batching (neat_server_*)."""
 

@@ -98,6 +98,7 @@ SIGNATURES = {
     "neat_forward_batch": (_i32, [ctypes.POINTER(BatchItem), _i32,
                                   ctypes.POINTER(ctypes.c_void_p), _vp]),
     "neat_batch_plan_free": (None, [_vp]),
+    "neat_forward_batch_noalloc": (_i32, [ctypes.POINTER(BatchItem), _i32, _vp]),
     "neat_batch_plan_launches": (_i32, [_vp]),
     "neat_server_create": (_i32, [ctypes.POINTER(ServerCfg), ctypes.POINTER(ctypes.c_void_p)]),
     "neat_server_destroy": (_i32, [_vp]),

@@ -13,10 +13,16 @@
 // The launches of each stage are independent and are recorded as parallel
 // branches of the graph (the forward kernels after the class lists), so a
 // long launch's tail overlaps the others.
+//
+// neat_forward_batch_noalloc plans the same launches and issues them
+// directly on the caller's stream, with the work-unit tables in a static
+// device array instead of allocated memory.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cstdint>
+#include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -115,17 +121,28 @@ int record(const std::vector<TopoLaunch> &topo, const neat::TopoItem *all_topo, 
     return e == hipSuccess ? NEAT_OK : hip_fail(e, "batch stream fork or join");
 }
 
-int build(const neat_batch_item *items, int32_t n, neat_batch_plan **out) {
-    neat_batch_plan *p = new (std::nothrow) neat_batch_plan;
-    if (!p) return fail(NEAT_E_NOMEM, "out of host memory");
-    p->items.assign(items, items + n);
-    (void)hipGetDevice(&p->device);
+// Everything one batch launches, planned on the host: the transformation
+// launches (their table fields are offsets into topo_host until resolved),
+// the class-list launch over topo_host[all_off ..], and the forward launches
+// with the items of the multi-item ones gathered in fw_host (fw_off: each
+// launch's first item there, -1 when its single item is passed inline).
+struct HostPlan {
+    std::vector<TopoLaunch> topo;
+    std::vector<neat::TopoItem> topo_host;
+    size_t all_off = 0;
+    int n_topo = 0;
+    std::vector<neat::FwdKernelLaunch> fw;
+    std::vector<neat::FwdItem> fw_host;
+    std::vector<long long> fw_off;
+    int launches() const { return (int)topo.size() + (n_topo ? 1 : 0) + (int)fw.size(); }
+};
 
-    std::vector<neat::FwdJob> jobs;
+int plan_host(const neat_batch_item *items, int32_t n, HostPlan &hp) {
     // transformations bucketed by workgroup size
     static const int bucket_threads[] = {64, 128, 256, 512, 1024};
     std::vector<neat::TopoItem> bucket[5], all_topo;
-    for (const neat_batch_item &it : p->items) {
+    for (int32_t k = 0; k < n; ++k) {
+        const neat_batch_item &it = items[k];
         if (!it.nodes || it.dims.P == 0) continue;
         const neat_dims &d = it.dims;
         neat::TopoItem ti{it.nodes, it.conns, nullptr, nullptr, it.status, (int32_t *)it.program,
@@ -136,8 +153,6 @@ int build(const neat_batch_item *items, int32_t n, neat_batch_plan **out) {
         bucket[b].push_back(ti);
         all_topo.push_back(ti);
     }
-    std::vector<TopoLaunch> topo;
-    std::vector<neat::TopoItem> topo_host;
     for (int b = 0; b < 5; ++b) {
         if (bucket[b].empty()) continue;
         TopoLaunch t{(int)bucket[b].size(), 0, 64, 0, nullptr};
@@ -147,15 +162,18 @@ int build(const neat_batch_item *items, int32_t n, neat_batch_plan **out) {
             t.threads = std::max(t.threads, neat::topo_block_threads(ti.N));
             t.lds = std::max(t.lds, neat::topo_lds_bytes(ti.N, ti.C));
         }
-        t.table = (const neat::TopoItem *)(uintptr_t)topo_host.size();  // offset for now
-        topo_host.insert(topo_host.end(), bucket[b].begin(), bucket[b].end());
-        topo.push_back(t);
+        t.table = (const neat::TopoItem *)(uintptr_t)hp.topo_host.size();  // offset for now
+        hp.topo_host.insert(hp.topo_host.end(), bucket[b].begin(), bucket[b].end());
+        hp.topo.push_back(t);
     }
-    const size_t all_off = topo_host.size();
-    topo_host.insert(topo_host.end(), all_topo.begin(), all_topo.end());
-    const int topo_launches = (int)topo.size() + (all_topo.empty() ? 0 : 1);
+    hp.all_off = hp.topo_host.size();
+    hp.topo_host.insert(hp.topo_host.end(), all_topo.begin(), all_topo.end());
+    hp.n_topo = (int)all_topo.size();
+
+    std::vector<neat::FwdJob> jobs;
     std::vector<int> job_variant;
-    for (const neat_batch_item &it : p->items) {
+    for (int32_t k = 0; k < n; ++k) {
+        const neat_batch_item &it = items[k];
         if (it.dims.P == 0 || it.B == 0) continue;
         jobs.push_back(make_job(&it.dims, it.program, it.inputs, it.input_genome_stride, it.B,
                                 it.outputs, it.grid_side, it.grid_first));
@@ -163,66 +181,76 @@ int build(const neat_batch_item *items, int32_t n, neat_batch_plan **out) {
     }
     // one plan per variant tuned for the items' buckets (all FWD_AUTO, one
     // plan, while nothing is tuned)
-    std::vector<neat::FwdKernelLaunch> fw;
     char err[256] = "";
-    int rc = NEAT_OK;
-    for (int v = neat::FWD_AUTO; v <= neat::FWD_REG2 && rc == NEAT_OK; ++v) {
+    for (int v = neat::FWD_AUTO; v <= neat::FWD_REG2; ++v) {
         std::vector<neat::FwdJob> group;
         for (size_t j = 0; j < jobs.size(); ++j)
             if (job_variant[j] == v) group.push_back(jobs[j]);
         if (group.empty()) continue;
         std::vector<neat::FwdKernelLaunch> part;
-        rc = neat::forward_plan(group.data(), (int)group.size(), v, max_lds_bytes(), part, err,
-                                sizeof(err));
-        fw.insert(fw.end(), part.begin(), part.end());
+        const int rc = neat::forward_plan(group.data(), (int)group.size(), v, max_lds_bytes(),
+                                          part, err, sizeof(err));
+        if (rc != NEAT_OK) return fail(rc, "%s", err);
+        hp.fw.insert(hp.fw.end(), part.begin(), part.end());
     }
+    // work-unit tables of the launches with more than one item
+    hp.fw_off.assign(hp.fw.size(), -1);
+    for (size_t k = 0; k < hp.fw.size(); ++k) {
+        if (hp.fw[k].items.size() <= 1) continue;
+        hp.fw_off[k] = (long long)hp.fw_host.size();
+        hp.fw_host.insert(hp.fw_host.end(), hp.fw[k].items.begin(), hp.fw[k].items.end());
+    }
+    return NEAT_OK;
+}
+
+// Point the launches at their tables in device memory (topo_dev: a copy of
+// topo_host, fw_dev: a copy of fw_host).
+void resolve_tables(HostPlan &hp, const neat::TopoItem *topo_dev, const neat::FwdItem *fw_dev,
+                    const neat::TopoItem **all_dev, std::vector<const neat::FwdItem *> &tab) {
+    for (TopoLaunch &t : hp.topo) t.table = topo_dev + (uintptr_t)t.table;
+    *all_dev = hp.n_topo ? topo_dev + hp.all_off : nullptr;
+    tab.assign(hp.fw.size(), nullptr);
+    for (size_t k = 0; k < hp.fw.size(); ++k)
+        if (hp.fw_off[k] >= 0) tab[k] = fw_dev + hp.fw_off[k];
+}
+
+int build(const neat_batch_item *items, int32_t n, neat_batch_plan **out) {
+    neat_batch_plan *p = new (std::nothrow) neat_batch_plan;
+    if (!p) return fail(NEAT_E_NOMEM, "out of host memory");
+    p->items.assign(items, items + n);
+    (void)hipGetDevice(&p->device);
+    HostPlan hp;
+    int rc = plan_host(items, n, hp);
     if (rc != NEAT_OK) {
         destroy(p);
-        return fail(rc, "%s", err);
+        return rc;
     }
-
-    // work-unit tables of the launches with more than one item
-    size_t n_tab = 0;
-    for (const neat::FwdKernelLaunch &k : fw)
-        if (k.items.size() > 1) n_tab += k.items.size();
-    std::vector<const neat::FwdItem *> tab(fw.size(), nullptr);
-    if (n_tab) {
-        hipError_t e = hipMalloc(&p->tables, n_tab * sizeof(neat::FwdItem));
-        if (e != hipSuccess) {
-            destroy(p);
-            return e == hipErrorOutOfMemory ? fail(NEAT_E_NOMEM, "batch tables: out of memory")
-                                            : hip_fail(e, "batch tables");
-        }
-        std::vector<neat::FwdItem> host;
-        host.reserve(n_tab);
-        for (size_t k = 0; k < fw.size(); ++k) {
-            if (fw[k].items.size() <= 1) continue;
-            tab[k] = (const neat::FwdItem *)p->tables + host.size();
-            host.insert(host.end(), fw[k].items.begin(), fw[k].items.end());
-        }
-        e = hipMemcpy(p->tables, host.data(), n_tab * sizeof(neat::FwdItem),
-                      hipMemcpyHostToDevice);
-        if (e != hipSuccess) {
-            destroy(p);
-            return hip_fail(e, "batch tables upload");
-        }
-    }
-
-    const neat::TopoItem *all_dev = nullptr;
-    if (!topo_host.empty()) {
-        hipError_t e = hipMalloc(&p->topo_tables, topo_host.size() * sizeof(neat::TopoItem));
+    if (!hp.fw_host.empty()) {
+        hipError_t e = hipMalloc(&p->tables, hp.fw_host.size() * sizeof(neat::FwdItem));
         if (e == hipSuccess)
-            e = hipMemcpy(p->topo_tables, topo_host.data(),
-                          topo_host.size() * sizeof(neat::TopoItem), hipMemcpyHostToDevice);
+            e = hipMemcpy(p->tables, hp.fw_host.data(), hp.fw_host.size() * sizeof(neat::FwdItem),
+                          hipMemcpyHostToDevice);
         if (e != hipSuccess) {
             destroy(p);
             return e == hipErrorOutOfMemory ? fail(NEAT_E_NOMEM, "batch tables: out of memory")
                                             : hip_fail(e, "batch tables");
         }
-        const neat::TopoItem *base = (const neat::TopoItem *)p->topo_tables;
-        for (TopoLaunch &t : topo) t.table = base + (uintptr_t)t.table;
-        all_dev = base + all_off;
     }
+    if (!hp.topo_host.empty()) {
+        hipError_t e = hipMalloc(&p->topo_tables, hp.topo_host.size() * sizeof(neat::TopoItem));
+        if (e == hipSuccess)
+            e = hipMemcpy(p->topo_tables, hp.topo_host.data(),
+                          hp.topo_host.size() * sizeof(neat::TopoItem), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            destroy(p);
+            return e == hipErrorOutOfMemory ? fail(NEAT_E_NOMEM, "batch tables: out of memory")
+                                            : hip_fail(e, "batch tables");
+        }
+    }
+    const neat::TopoItem *all_dev = nullptr;
+    std::vector<const neat::FwdItem *> tab;
+    resolve_tables(hp, (const neat::TopoItem *)p->topo_tables, (const neat::FwdItem *)p->tables,
+                   &all_dev, tab);
 
     // record the launches into a graph on private streams (default
     // priority), the branches of each stage on streams forked from cs[0]
@@ -250,7 +278,7 @@ int build(const neat_batch_item *items, int32_t n, neat_batch_plan **out) {
         destroy(p);
         return hip_fail(e, "begin capture");
     }
-    rc = record(topo, all_dev, (int)all_topo.size(), fw, tab, cs, ev);
+    rc = record(hp.topo, all_dev, hp.n_topo, hp.fw, tab, cs, ev);
     hipGraph_t g = nullptr;
     e = hipStreamEndCapture(cs[0], &g);
     release();
@@ -264,11 +292,65 @@ int build(const neat_batch_item *items, int32_t n, neat_batch_plan **out) {
         destroy(p);
         return hip_fail(e, "graph instantiate");
     }
-    p->launches = topo_launches + (int)fw.size();
+    p->launches = hp.launches();
     *out = p;
     return NEAT_OK;
 }
 
+// ---- the batch without device allocation ---------------------------------
+// The work-unit tables live in a file-scope device array (one copy per GPU,
+// held until the process ends).  Host code never passes the array's name to
+// a kernel or a copy: its device address comes from hipGetSymbolAddress,
+// once per device, and only that address is used.
+__device__ __align__(256) unsigned char scratch[NEAT_NOALLOC_SCRATCH_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[MAX_DEVICES] = {};
+
+int scratch_ptr(int dev, unsigned char **out) {
+    if (dev < 0 || dev >= MAX_DEVICES) return fail(NEAT_E_INVALID, "device %d unsupported", dev);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "address of the batch scratch area");
+        if (!ptr) return fail(NEAT_E_HIP, "address of the batch scratch area is NULL");
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = (unsigned char *)g_scratch_ptr[dev];
+    return NEAT_OK;
+}
+
+// Table words travel as kernel arguments (captured by value, no host buffer
+// has to outlive the call) and a small kernel stores them.
+constexpr int WR_WORDS = 896;
+struct WriteChunk {
+    uint32_t *dst;
+    uint32_t n;
+    uint32_t w[WR_WORDS];
+};
+
+__global__ __launch_bounds__(256) void write_words_kernel(WriteChunk c) {
+    for (uint32_t i = threadIdx.x; i < c.n; i += blockDim.x) c.dst[i] = c.w[i];
+}
+
+hipError_t write_words(unsigned char *dst, const void *src, size_t bytes, hipStream_t stream) {
+    const uint32_t *s = (const uint32_t *)src;
+    size_t words = bytes / 4;
+    WriteChunk c;
+    for (size_t off = 0; off < words; off += WR_WORDS) {
+        c.dst = (uint32_t *)dst + off;
+        c.n = (uint32_t)std::min<size_t>(WR_WORDS, words - off);
+        memcpy(c.w, s + off, c.n * sizeof(uint32_t));
+        hipLaunchKernelGGL(write_words_kernel, dim3(1), dim3(256), 0, stream, c);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 // Field by field (struct padding may hold anything).
 bool same_item(const neat_batch_item &a, const neat_batch_item &b) {
     return a.dims.P == b.dims.P && a.dims.N_max == b.dims.N_max && a.dims.C_max == b.dims.C_max &&
@@ -313,6 +395,52 @@ int neat_forward_batch(const neat_batch_item *items, int32_t n, neat_batch_plan 
 }
 
 void neat_batch_plan_free(neat_batch_plan *plan) { destroy(plan); }
+
+int neat_forward_batch_noalloc(const neat_batch_item *items, int32_t n, void *stream) {
+    if (n < 0 || (n > 0 && !items)) return fail(NEAT_E_INVALID, "bad item list (n = %d)", n);
+    for (int32_t k = 0; k < n; ++k) {
+        const int rc = check_item(items[k], k);
+        if (rc != NEAT_OK) return rc;
+    }
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "current device");
+    unsigned char *base = nullptr;
+    int rc = scratch_ptr(dev, &base);
+    if (rc != NEAT_OK) return rc;
+    HostPlan hp;
+    rc = plan_host(items, n, hp);
+    if (rc != NEAT_OK) return rc;
+    const size_t topo_bytes = hp.topo_host.size() * sizeof(neat::TopoItem);
+    const size_t fw_bytes = hp.fw_host.size() * sizeof(neat::FwdItem);
+    const size_t need = align256(topo_bytes) + fw_bytes;
+    if (need > NEAT_NOALLOC_SCRATCH_BYTES)
+        return fail(NEAT_E_TOO_LARGE,
+                    "the batch's work-unit tables need %zu B, the scratch area holds %d B",
+                    need, NEAT_NOALLOC_SCRATCH_BYTES);
+    hipStream_t s = (hipStream_t)stream;
+    unsigned char *fw_base = base + align256(topo_bytes);
+    if (topo_bytes) e = write_words(base, hp.topo_host.data(), topo_bytes, s);
+    if (e == hipSuccess && fw_bytes) e = write_words(fw_base, hp.fw_host.data(), fw_bytes, s);
+    if (e != hipSuccess) return hip_fail(e, "batch tables");
+    const neat::TopoItem *all_dev = nullptr;
+    std::vector<const neat::FwdItem *> tab;
+    resolve_tables(hp, (const neat::TopoItem *)base, (const neat::FwdItem *)fw_base, &all_dev,
+                   tab);
+    for (const TopoLaunch &t : hp.topo) {
+        e = neat::launch_topo_batch(t.table, t.n, t.blocks, t.threads, t.lds, s);
+        if (e != hipSuccess) return hip_fail(e, "batch transformation launch");
+    }
+    if (hp.n_topo) {
+        e = neat::launch_classify_batch(all_dev, hp.n_topo, s);
+        if (e != hipSuccess) return hip_fail(e, "batch class lists launch");
+    }
+    for (size_t k = 0; k < hp.fw.size(); ++k) {
+        e = neat::forward_launch(hp.fw[k], tab[k], s);
+        if (e != hipSuccess) return hip_fail(e, "batch forward launch");
+    }
+    return NEAT_OK;
+}
 
 int32_t neat_batch_plan_launches(const neat_batch_plan *plan) {
     return plan ? plan->launches : 0;
