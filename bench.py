@@ -653,6 +653,69 @@ def bench_recurrent(args, torch, neat, synth):
                          "hbm_GBps": round(fwd_bytes / (fwd_ms / 1e3) / 1e9, 1)}}
 
 
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_rate(pop, g, threads, precision, min_seconds):
+    """Genome-inputs/s of the oracle (transformation + calculation) over the
+    first g genomes, split into `threads` contiguous genome ranges evaluated
+    concurrently (the oracle is C called through ctypes, which releases the
+    GIL), repeated until min_seconds have passed."""
+    import concurrent.futures as cf
+    import oracle
+    bounds = np.linspace(0, g, threads + 1).astype(int)
+    parts = [(a, b) for a, b in zip(bounds[:-1], bounds[1:]) if b > a]
+
+    def run(ab):
+        a, b = ab
+        oracle.forward(pop.nodes[a:b], pop.conns[a:b], pop.inputs[a:b], pop.I, pop.O,
+                       precision=precision, with_beta=False)
+
+    passes, t = 0, time.perf_counter()
+    with cf.ThreadPoolExecutor(max_workers=len(parts)) as ex:
+        while True:
+            list(ex.map(run, parts))
+            passes += 1
+            dt = time.perf_counter() - t
+            if dt >= min_seconds or passes >= 50:
+                break
+    return passes * g * pop.B / dt, passes, dt
+
+
+def cpu_baseline(args, pop):
+    """The oracle timed on this machine's host cores: its fp32 instantiation
+    with genomes split over all usable cores (at most 16, the host share of
+    one GPU), the same on one core, and the fp64 reference on one core."""
+    usable = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    threads = max(1, min(usable, 16))
+    g_all = min(args.cpu_genomes, pop.P)
+    g_one = min(max(g_all // 8, 1), pop.P)
+    sec = args.cpu_seconds
+    v_all, n_all, t_all = _oracle_rate(pop, g_all, threads, "f32", sec)
+    v_one, n_one, t_one = _oracle_rate(pop, g_one, 1, "f32", sec / 2)
+    v_64, n_64, t_64 = _oracle_rate(pop, g_one, 1, "f64", sec / 2)
+    return {"value": round(v_all, 1), "unit": "genome-inputs/s", "cores": threads,
+            "kind": "oracle",
+            "sample": "%d genomes x %d inputs of the control workload, %d passes in %.1f s: "
+                      "the oracle's fp32 instantiation (transformation + calculation), "
+                      "genomes split over %d threads" % (g_all, pop.B, n_all, t_all, threads),
+            "os_cpu_count": os.cpu_count(), "usable_cpus": usable, "cpu_model": _cpu_model(),
+            "one_core_f32": {"value": round(v_one, 1), "cores": 1,
+                             "sample": "%d genomes x %d inputs, %d passes in %.1f s"
+                                       % (g_one, pop.B, n_one, t_one)},
+            "one_core_f64": {"value": round(v_64, 1), "cores": 1,
+                             "sample": "%d genomes x %d inputs, %d passes in %.1f s, the fp64 "
+                                       "parity reference" % (g_one, pop.B, n_64, t_64)}}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -776,22 +839,7 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        import oracle
-        g = min(args.cpu_genomes, pop.P)
-        passes, t = 0, time.perf_counter()
-        while True:
-            oracle.forward(pop.nodes[:g], pop.conns[:g], pop.inputs[:g], pop.I, pop.O,
-                           with_beta=False)
-            passes += 1
-            dt = time.perf_counter() - t
-            if dt >= args.cpu_seconds or passes >= 20:
-                break
-        cpu = {"value": round(passes * g * pop.B / dt, 1), "unit": "genome-inputs/s",
-               "cores": 1, "kind": "oracle",
-               "sample": "%d genomes x %d inputs of the same workload (%s), %d passes, fp64, "
-                         "transformation + calculation, single thread (%.1f s)"
-                         % (g, pop.B, "all of it" if g == pop.P else "its first genomes",
-                            passes, dt)}
+        cpu = cpu_baseline(args, pop)
 
     workloads = set(args.workloads.split(","))
     forms = (bench_control_forms(args, torch, neat, pop, tn, tc, tx)
