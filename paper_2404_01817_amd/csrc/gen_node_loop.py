@@ -89,7 +89,10 @@ class Regs:
     # on gfx950 a permutation of the same registers (c13, acc, z, ta, tb)
     # made the sine block's results vary from launch to launch under full
     # occupancy, while this placement gives repeatable bits (checked by the
-    # full-size repeatability tests).
+    # full-size repeatability tests).  Both placements pass every static
+    # check of check_node_loop.py (documented wait states, load completion,
+    # GPR-index mode, clobbers) and assemble to the same table layout, so
+    # the cause is not one of those rules and remains unknown.
     ROLES = ("acc", "ta", "tb", "z", "p")
 
     def __init__(self, spl, bases, scratch, wbases=None, group=8):
