@@ -149,7 +149,10 @@ int neat_forward(const neat_dims *dims, const void *program, const float *inputs
                  int64_t input_genome_stride, int32_t B, float *outputs,
                  void *stream);
 
-/* Forward variants: where the lane-per-sample kernels keep the node values.
+/* Forward variants: where the lane-per-sample kernels keep the node values,
+ * or (NEAT_FWD_LVL) the level mapping, which spreads a level's nodes over
+ * the lanes (Section 3.3 evaluates a network in topological order; nodes of
+ * one level depend only on earlier levels).
  * The program build gives every genome a slot class from its largest set of
  * simultaneously live values (<= 62, <= 126, <= 222 values in registers,
  * more in LDS rows); NEAT_FWD_AUTO runs each class's genomes with that
@@ -161,6 +164,11 @@ int neat_forward(const neat_dims *dims, const void *program, const float *inputs
 #define NEAT_FWD_REG2 3 /* as NEAT_FWD_REG, two samples per lane for the smallest class */
 #define NEAT_FWD_TUNED 4 /* the variant neat_autotune_forward measured fastest for the
                             call's bucket; NEAT_FWD_AUTO while none is recorded */
+#define NEAT_FWD_LVL 5   /* the level mapping, for few samples per genome: a wave takes
+                            a tile of up to 64 samples and evaluates a level's nodes x
+                            the tile's samples at once, one (node, sample) per lane,
+                            values in LDS (grid queries and recurrent calls run
+                            NEAT_FWD_AUTO instead) */
 
 /*
  * neat_forward with an explicit variant (NEAT_FWD_*); same arguments.  All
@@ -179,28 +187,52 @@ int neat_forward_ex(const neat_dims *dims, const void *program, const float *inp
 
 /*
  * Autotuner of the calculation stage (not a passage of the paper: a tuning
- * aid for the population-wide calculation of Section 3.3).  Times
- * NEAT_FWD_REG, NEAT_FWD_REG2 and NEAT_FWD_LDS on the caller's buffers, one
- * warm-up and `reps` launches each, with HIP events on `stream`, and records
- * the fastest in a process-wide table under the call's bucket: N_max and
- * C_max rounded up to powers of two, B to a power of two capped at 1024.
- * neat_forward_ex with NEAT_FWD_TUNED and neat_forward_batch (per item)
- * read that table; both fall back to NEAT_FWD_AUTO for buckets never tuned.
- * Every variant gives identical bits, so tuning changes no result.
+ * aid for the population-wide calculation of Section 3.3).  Times the
+ * NEAT_TUNE_CANDIDATES mappings -- NEAT_FWD_REG, NEAT_FWD_REG2, NEAT_FWD_LDS
+ * (lane per sample, three value stores) and NEAT_FWD_LVL (lanes over a
+ * level's nodes) -- on the caller's buffers, one warm-up and `reps`
+ * launches each, with HIP events on `stream`, in two ways: the population
+ * alone (latency), and as many copies of it in one launch as fill the GPU
+ * (about 16 waves per CU, at most 64 copies; throughput per copy).  It
+ * records both winners in process-wide tables under the call's bucket:
+ * N_max and C_max rounded up to powers of two, B to a power of two capped at
+ * 1024, tensor inputs (grid queries form buckets of their own, never tuned:
+ * they run NEAT_FWD_AUTO).  neat_forward_ex with NEAT_FWD_TUNED uses the
+ * latency winner; neat_forward_batch and neat_forward_batch_noalloc (per
+ * item), whose items share the GPU, use the throughput winner; both fall back
+ * to NEAT_FWD_AUTO for buckets never tuned.  A recorded batch plan is
+ * rebuilt when a table has changed since it was recorded.  Every variant
+ * gives identical bits, so tuning changes no result.
+ * With the environment variable NEAT_TUNE_CACHE naming a file (or a server
+ * created with tune_cache_path), the table is read from that file on first
+ * use and rewritten there after every tuning ("N_max C_max B grid variant"
+ * lines of bucket values); a file that cannot be read or written is
+ * skipped.
  *   arguments as neat_forward_ex (outputs are overwritten);
  *   reps         launches timed per variant, 1..1000
- *   variant_out  (host, written) the fastest variant; NEAT_FWD_AUTO when
+ *   variant_out  (host, written) the latency winner; NEAT_FWD_AUTO when
  *                P = 0 or B = 0 (nothing is timed or recorded)
- *   ms_out       [3] (host, written, nullable) mean ms per launch of REG,
- *                REG2 and LDS
+ *   ms_out       [2 * NEAT_TUNE_CANDIDATES] (host, written, nullable): mean
+ *                ms per launch of REG, REG2, LDS and LVL alone, then mean ms
+ *                per copy of the same four on a full GPU (-1 when untimed)
  * Synchronizes `stream`; the table is shared by every thread of the
  * process (guarded by a mutex).
  * Errors: as neat_forward_ex; NEAT_E_INVALID for reps or a NULL
  * variant_out; NEAT_E_HIP.
  */
+#define NEAT_TUNE_CANDIDATES 4
 int neat_autotune_forward(const neat_dims *dims, const void *program, const float *inputs,
                           int64_t input_genome_stride, int32_t B, float *outputs, int32_t reps,
                           int32_t *variant_out, float *ms_out, void *stream);
+
+/*
+ * The variant the autotuner recorded for the bucket of (dims->N_max,
+ * dims->C_max, B, grid != 0): the latency winner (throughput = 0) or the
+ * throughput winner (throughput != 0); NEAT_FWD_AUTO for a bucket never
+ * tuned.  Host only, thread-safe.  Errors: NEAT_E_INVALID (bad dims or
+ * B < 0).
+ */
+int32_t neat_tuned_variant(const neat_dims *dims, int32_t B, int32_t grid, int32_t throughput);
 
 /*
  * Calculation stage for CPPN substrate queries (the paper's CPPN/HyperNEAT
@@ -434,7 +466,7 @@ int32_t neat_batch_plan_launches(const neat_batch_plan *plan);
  * ordered and safe; calls that overlap on one GPU (different streams or
  * threads) race on the array and must not be issued.
  * Errors: as neat_forward_batch; NEAT_E_TOO_LARGE when the batch's tables
- * (176 B per transformed population, plus 112 B per population and value
+ * (176 B per transformed population, plus 120 B per population and value
  * store it uses) exceed NEAT_NOALLOC_SCRATCH_BYTES.
  */
 #define NEAT_NOALLOC_SCRATCH_BYTES (256 * 1024)

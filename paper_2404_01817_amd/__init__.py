@@ -11,7 +11,8 @@ from __future__ import annotations
 import ctypes
 from typing import Optional, Tuple
 
-from ._lib import (FWD_AUTO, FWD_LDS, FWD_REG, FWD_REG2, FWD_TUNED, INPUT_GRID, INPUT_TENSOR,
+from ._lib import (FWD_AUTO, FWD_LDS, FWD_LVL, FWD_REG, FWD_REG2, FWD_TUNED, TUNE_CANDIDATES,
+                   INPUT_GRID, INPUT_TENSOR,
                    BatchItem, Dims, NeatError, Request, Result, ServerCfg, Stats, check, lib)
 
 __all__ = ["Dims", "NeatError", "dims_of", "program_bytes", "topo_sort", "forward",
@@ -123,15 +124,22 @@ def forward(dims: Dims, program, inputs, B: int, shared_inputs: bool = False,
 def autotune_forward(dims: Dims, program, inputs, B: int, outputs=None, reps: int = 5,
                      stream=None):
     """Time the forward variants on these buffers and record the fastest for
-    the call's bucket (neat_autotune_forward); returns (variant, [ms of
-    FWD_REG, FWD_REG2, FWD_LDS]).  Later calls with variant=FWD_TUNED, and
+    the call's bucket (neat_autotune_forward); returns (latency winner, [ms
+    of FWD_REG, FWD_REG2, FWD_LDS, FWD_LVL alone, then per copy on a full
+    GPU]).  Later calls with variant=FWD_TUNED, and
     batches, use the recorded variant."""
     stride, outputs = _io(dims, inputs, B, False, outputs)
     v = ctypes.c_int32(0)
-    ms = (ctypes.c_float * 3)()
+    ms = (ctypes.c_float * (2 * TUNE_CANDIDATES))()
     check(lib().neat_autotune_forward(ctypes.byref(dims), _ptr(program), _ptr(inputs), stride, B,
                                       _ptr(outputs), reps, ctypes.byref(v), ms, _stream(stream)))
     return v.value, [float(x) for x in ms]
+
+
+def tuned_variant(dims: Dims, B: int, grid: bool = False, throughput: bool = False) -> int:
+    """The variant recorded for the call's bucket (neat_tuned_variant): the
+    latency winner, or the throughput winner that batches use."""
+    return check(lib().neat_tuned_variant(ctypes.byref(dims), B, int(grid), int(throughput)))
 
 def distance(nodes, conns, rnodes, rconns, c_disjoint: float = 1.0,
              c_homologous: float = 0.5, out=None, stream=None):

@@ -15,7 +15,8 @@ LIB_PATH = os.path.join(PKG, "libneat.so")
 
 NEAT_OK = 0
 NEAT_PENDING = 1
-FWD_AUTO, FWD_REG, FWD_LDS, FWD_REG2, FWD_TUNED = 0, 1, 2, 3, 4
+FWD_AUTO, FWD_REG, FWD_LDS, FWD_REG2, FWD_TUNED, FWD_LVL = 0, 1, 2, 3, 4, 5
+TUNE_CANDIDATES = 4  # REG, REG2, LDS, LVL
 
 
 class NeatError(RuntimeError):
@@ -83,6 +84,7 @@ SIGNATURES = {
     "neat_forward_ex": (_i32, [ctypes.POINTER(Dims), _vp, _vp, _i64, _i32, _vp, _i32, _vp]),
     "neat_autotune_forward": (_i32, [ctypes.POINTER(Dims), _vp, _vp, _i64, _i32, _vp, _i32,
                                      _vp, _vp, _vp]),
+    "neat_tuned_variant": (_i32, [ctypes.POINTER(Dims), _i32, _i32, _i32]),
     "neat_forward_grid": (_i32, [ctypes.POINTER(Dims), _vp, _i32, _i64, _i32, _vp, _vp]),
     "neat_apply_edits": (_i32, [ctypes.POINTER(Dims), _vp, _vp, _vp, _i32, _vp, _vp]),
     "neat_crossover": (_i32, [ctypes.POINTER(Dims), _vp, _vp, _i32, _vp, _vp, _vp, _vp, _vp,

@@ -5,6 +5,7 @@
 
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <algorithm>
 #include <cstring>
 #include <map>
@@ -126,27 +127,98 @@ FwdJob make_job(const neat_dims *d, const void *program, const float *inputs, in
 
 using namespace neat::abi;
 
-// ---- autotuner: the fastest variant per (N_max, C_max, B) bucket ----------
+// ---- autotuner: the fastest variant per (N_max, C_max, B, mode) bucket ---
+// The table lives in process memory; with NEAT_TUNE_CACHE set (or a server
+// created with a tune_cache_path) it is also read from and written to that
+// text file, one "N_max C_max B grid variant" line per bucket (bucket
+// values, powers of two), so tuning carries over between processes.
 namespace {
 std::mutex g_tune_mu;
-std::map<unsigned long long, int> g_tune;
+// per bucket: the variant fastest alone (single calls) and the one with the
+// most genome-inputs per second when the GPU is full (batches)
+std::map<unsigned long long, int> g_tune, g_tune_tp;
+std::string g_tune_path;
+bool g_tune_env_read = false;
+unsigned g_tune_gen = 0;
 
 long long pow2_ceil(long long x) {
     long long p = 1;
     while (p < x) p <<= 1;
     return p;
 }
-unsigned long long tune_key(int N, int C, int B) {
-    return ((unsigned long long)pow2_ceil(N) << 42) | ((unsigned long long)pow2_ceil(C) << 21) |
+unsigned long long tune_key(int N, int C, int B, int grid) {
+    return ((unsigned long long)(grid ? 1 : 0) << 63) |
+           ((unsigned long long)pow2_ceil(N) << 42) | ((unsigned long long)pow2_ceil(C) << 21) |
            (unsigned long long)std::min(pow2_ceil(B), 1024ll);
+}
+bool valid_tuned(int v) {
+    return v == NEAT_FWD_AUTO || v == NEAT_FWD_REG || v == NEAT_FWD_LDS || v == NEAT_FWD_REG2 ||
+           v == NEAT_FWD_LVL;
+}
+
+// Merge the cache file's entries into the table (caller holds the lock).
+void tune_read_locked(const std::string &path) {
+    FILE *f = fopen(path.c_str(), "r");
+    if (!f) return;
+    long long N, C, B;
+    int grid, v, vt;
+    while (fscanf(f, "%lld %lld %lld %d %d %d", &N, &C, &B, &grid, &v, &vt) == 6)
+        if (N > 0 && C >= 0 && B > 0 && valid_tuned(v) && valid_tuned(vt)) {
+            g_tune[tune_key((int)N, (int)C, (int)B, grid)] = v;
+            g_tune_tp[tune_key((int)N, (int)C, (int)B, grid)] = vt;
+        }
+    fclose(f);
+    ++g_tune_gen;
+}
+
+void tune_env_locked() {
+    if (g_tune_env_read) return;
+    g_tune_env_read = true;
+    const char *e = getenv("NEAT_TUNE_CACHE");
+    if (e && *e) {
+        g_tune_path = e;
+        tune_read_locked(g_tune_path);
+    }
+}
+
+// Rewrite the cache file from the table (caller holds the lock); a file
+// that cannot be written leaves the in-memory table as it is.
+void tune_write_locked() {
+    if (g_tune_path.empty()) return;
+    const std::string tmp = g_tune_path + ".tmp";
+    FILE *f = fopen(tmp.c_str(), "w");
+    if (!f) return;
+    for (const auto &kv : g_tune) {
+        const unsigned long long k = kv.first;
+        const auto tp = g_tune_tp.find(k);
+        fprintf(f, "%llu %llu %llu %d %d %d\n", (k >> 42) & ((1ull << 21) - 1),
+                (k >> 21) & ((1ull << 21) - 1), k & ((1ull << 21) - 1), (int)(k >> 63),
+                kv.second, tp == g_tune_tp.end() ? kv.second : tp->second);
+    }
+    if (fclose(f) == 0) rename(tmp.c_str(), g_tune_path.c_str());
 }
 }  // namespace
 
 namespace neat {
-int tuned_variant(int N, int C, int B) {
+int tuned_variant(int N, int C, int B, int grid, int throughput) {
     std::lock_guard<std::mutex> lock(g_tune_mu);
-    const auto it = g_tune.find(tune_key(N, C, B));
-    return it == g_tune.end() ? FWD_AUTO : it->second;
+    tune_env_locked();
+    const std::map<unsigned long long, int> &t = throughput ? g_tune_tp : g_tune;
+    const auto it = t.find(tune_key(N, C, B, grid));
+    return it == t.end() ? FWD_AUTO : it->second;
+}
+unsigned tune_generation() {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    tune_env_locked();
+    return g_tune_gen;
+}
+int tune_cache_use(const char *path) {
+    if (!path || !*path) return NEAT_OK;
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    tune_env_locked();
+    g_tune_path = path;
+    tune_read_locked(g_tune_path);
+    return NEAT_OK;
 }
 }  // namespace neat
 
@@ -197,9 +269,10 @@ static int forward_common(const neat_dims *d, const void *program, const float *
                           int32_t side, int64_t first, void *stream) {
     int rc = check_dims(d);
     if (rc != NEAT_OK) return rc;
-    if (variant < NEAT_FWD_AUTO || variant > NEAT_FWD_TUNED)
+    if (variant < NEAT_FWD_AUTO || variant > NEAT_FWD_LVL)
         return fail(NEAT_E_INVALID, "unknown forward variant %d", variant);
-    if (variant == NEAT_FWD_TUNED) variant = neat::tuned_variant(d->N_max, d->C_max, B);
+    if (variant == NEAT_FWD_TUNED)
+        variant = neat::tuned_variant(d->N_max, d->C_max, B, grid, 0);
     rc = check_forward_args(d, program, inputs, stride, B, outputs, grid, side, first);
     if (rc != NEAT_OK || d->P == 0 || B == 0) return rc;
     const neat::FwdJob job =
@@ -228,6 +301,57 @@ int neat_forward(const neat_dims *d, const void *program, const float *inputs,
                            stream);
 }
 
+// Launch `copies` copies of one population's calculation under one variant
+// in a single plan (copies > 1 share a device table of items; every copy
+// writes the same outputs with the same values).
+static int launch_copies(const neat::FwdJob &job, int copies, int variant,
+                         std::vector<void *> &tables, hipStream_t s) {
+    std::vector<neat::FwdJob> jobs(copies, job);
+    std::vector<neat::FwdKernelLaunch> plan;
+    char err[256] = "";
+    int rc = neat::forward_plan(jobs.data(), copies, variant, max_lds_bytes(), plan, err,
+                                sizeof(err));
+    if (rc != NEAT_OK) return fail(rc, "%s", err);
+    for (const neat::FwdKernelLaunch &k : plan) {
+        const neat::FwdItem *dev = nullptr;
+        if (k.items.size() > 1) {
+            void *t = nullptr;
+            hipError_t e = hipMalloc(&t, k.items.size() * sizeof(neat::FwdItem));
+            if (e == hipSuccess) {
+                tables.push_back(t);
+                e = hipMemcpy(t, k.items.data(), k.items.size() * sizeof(neat::FwdItem),
+                              hipMemcpyHostToDevice);
+            }
+            if (e != hipSuccess) return hip_fail(e, "autotune item table");
+            dev = (const neat::FwdItem *)t;
+        }
+        hipError_t e = neat::forward_launch(k, dev, s);
+        if (e != hipSuccess) return hip_fail(e, "autotune launch");
+    }
+    return NEAT_OK;
+}
+
+// Mean ms per launch of `reps` launches of `copies` copies (after one
+// warm-up), timed with events on s.
+static int time_copies(const neat::FwdJob &job, int copies, int variant, int reps,
+                       hipEvent_t e0, hipEvent_t e1, hipStream_t s, float *ms) {
+    std::vector<void *> tables;
+    int rc = launch_copies(job, copies, variant, tables, s);  // warm-up
+    hipError_t e = hipSuccess;
+    if (rc == NEAT_OK) e = hipEventRecord(e0, s);
+    for (int r = 0; r < reps && rc == NEAT_OK && e == hipSuccess; ++r)
+        rc = launch_copies(job, copies, variant, tables, s);
+    if (rc == NEAT_OK && e == hipSuccess) e = hipEventRecord(e1, s);
+    if (rc == NEAT_OK && e == hipSuccess) e = hipEventSynchronize(e1);
+    float t = 0.0f;
+    if (rc == NEAT_OK && e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+    if (rc == NEAT_OK && e != hipSuccess) rc = hip_fail(e, "autotune timing");
+    (void)hipStreamSynchronize(s);
+    for (void *t2 : tables) (void)hipFree(t2);
+    *ms = t / (float)reps;
+    return rc;
+}
+
 int neat_autotune_forward(const neat_dims *d, const void *program, const float *inputs,
                           int64_t input_genome_stride, int32_t B, float *outputs, int32_t reps,
                           int32_t *variant_out, float *ms_out, void *stream) {
@@ -237,11 +361,18 @@ int neat_autotune_forward(const neat_dims *d, const void *program, const float *
     if (reps < 1 || reps > 1000) return fail(NEAT_E_INVALID, "reps = %d outside [1, 1000]", reps);
     rc = check_forward_args(d, program, inputs, input_genome_stride, B, outputs, false, 0, 0);
     if (rc != NEAT_OK) return rc;
-    const int cand[3] = {NEAT_FWD_REG, NEAT_FWD_REG2, NEAT_FWD_LDS};
-    float ms[3] = {-1.0f, -1.0f, -1.0f};
-    int best = NEAT_FWD_AUTO;
-    float best_ms = 0.0f;
+    constexpr int NC = NEAT_TUNE_CANDIDATES;
+    const int cand[NC] = {NEAT_FWD_REG, NEAT_FWD_REG2, NEAT_FWD_LDS, NEAT_FWD_LVL};
+    float ms[2 * NC];
+    for (float &m : ms) m = -1.0f;
+    int best = NEAT_FWD_AUTO, best_tp = NEAT_FWD_AUTO;
     if (d->P > 0 && B > 0) {
+        // copies of the population that fill the GPU (about 16 waves per CU
+        // of lane-per-sample tiles), for the throughput timing
+        const long long waves = (long long)d->P * ((B + 63) / 64);
+        const int copies = (int)std::max(1ll, std::min(64ll, (16384 + waves - 1) / waves));
+        const neat::FwdJob job =
+            make_job(d, program, inputs, input_genome_stride, B, outputs, 0, 0);
         hipEvent_t e0, e1;
         if (hipEventCreate(&e0) != hipSuccess) return hip_fail(hipGetLastError(), "event");
         if (hipEventCreate(&e1) != hipSuccess) {
@@ -249,36 +380,38 @@ int neat_autotune_forward(const neat_dims *d, const void *program, const float *
             return hip_fail(hipGetLastError(), "event");
         }
         const hipStream_t s = (hipStream_t)stream;
-        for (int i = 0; i < 3 && rc == NEAT_OK; ++i) {
-            rc = forward_common(d, program, inputs, input_genome_stride, B, outputs, cand[i],
-                                false, 0, 0, stream);  // warm-up
+        float best_ms = 0.0f, best_tp_ms = 0.0f;
+        for (int i = 0; i < NC && rc == NEAT_OK; ++i) {
+            rc = time_copies(job, 1, cand[i], reps, e0, e1, s, &ms[i]);
+            if (rc == NEAT_OK) rc = time_copies(job, copies, cand[i], reps, e0, e1, s, &ms[NC + i]);
             if (rc != NEAT_OK) break;
-            hipError_t e = hipEventRecord(e0, s);
-            for (int r = 0; r < reps && rc == NEAT_OK && e == hipSuccess; ++r)
-                rc = forward_common(d, program, inputs, input_genome_stride, B, outputs,
-                                    cand[i], false, 0, 0, stream);
-            if (rc != NEAT_OK) break;
-            if (e == hipSuccess) e = hipEventRecord(e1, s);
-            if (e == hipSuccess) e = hipEventSynchronize(e1);
-            float t = 0.0f;
-            if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
-            if (e != hipSuccess) {
-                rc = hip_fail(e, "autotune timing");
-                break;
-            }
-            ms[i] = t / (float)reps;
+            ms[NC + i] /= (float)copies;
             if (best == NEAT_FWD_AUTO || ms[i] < best_ms) best = cand[i], best_ms = ms[i];
+            if (best_tp == NEAT_FWD_AUTO || ms[NC + i] < best_tp_ms)
+                best_tp = cand[i], best_tp_ms = ms[NC + i];
         }
         hipEventDestroy(e0);
         hipEventDestroy(e1);
         if (rc != NEAT_OK) return rc;
         std::lock_guard<std::mutex> lock(g_tune_mu);
-        g_tune[tune_key(d->N_max, d->C_max, B)] = best;
+        tune_env_locked();
+        const unsigned long long key = tune_key(d->N_max, d->C_max, B, 0);
+        int &slot = g_tune[key];
+        int &slot_tp = g_tune_tp[key];
+        if (slot != best || slot_tp != best_tp) ++g_tune_gen;
+        slot = best;
+        slot_tp = best_tp;
+        tune_write_locked();
     }
     *variant_out = best;
     if (ms_out)
-        for (int i = 0; i < 3; ++i) ms_out[i] = ms[i];
+        for (int i = 0; i < 2 * NC; ++i) ms_out[i] = ms[i];
     return NEAT_OK;
+}
+
+int32_t neat_tuned_variant(const neat_dims *d, int32_t B, int32_t grid, int32_t throughput) {
+    if (check_dims(d) != NEAT_OK || B < 0) return NEAT_E_INVALID;
+    return neat::tuned_variant(d->N_max, d->C_max, B, grid != 0, throughput != 0);
 }
 
 int neat_topo_sort_recurrent(const neat_dims *d, const float *nodes, const float *conns,

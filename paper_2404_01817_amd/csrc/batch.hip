@@ -42,6 +42,7 @@ struct neat_batch_plan {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     int launches = 0;
+    unsigned tune_gen = 0;  // the tune table's generation the plan was built with
 };
 
 namespace {
@@ -177,21 +178,18 @@ int plan_host(const neat_batch_item *items, int32_t n, HostPlan &hp) {
         if (it.dims.P == 0 || it.B == 0) continue;
         jobs.push_back(make_job(&it.dims, it.program, it.inputs, it.input_genome_stride, it.B,
                                 it.outputs, it.grid_side, it.grid_first));
-        job_variant.push_back(neat::tuned_variant(it.dims.N_max, it.dims.C_max, it.B));
+        job_variant.push_back(
+            neat::tuned_variant(it.dims.N_max, it.dims.C_max, it.B, it.grid_side > 0, 1));
     }
-    // one plan per variant tuned for the items' buckets (all FWD_AUTO, one
-    // plan, while nothing is tuned)
-    char err[256] = "";
-    for (int v = neat::FWD_AUTO; v <= neat::FWD_REG2; ++v) {
-        std::vector<neat::FwdJob> group;
-        for (size_t j = 0; j < jobs.size(); ++j)
-            if (job_variant[j] == v) group.push_back(jobs[j]);
-        if (group.empty()) continue;
-        std::vector<neat::FwdKernelLaunch> part;
-        const int rc = neat::forward_plan(group.data(), (int)group.size(), v, max_lds_bytes(),
-                                          part, err, sizeof(err));
+    // every item with the variant tuned for its bucket's throughput (the
+    // batch fills the GPU; FWD_AUTO while none is), one launch per kernel
+    // kind over all of them
+    for (size_t j = 0; j < jobs.size(); ++j) jobs[j].variant = job_variant[j];
+    if (!jobs.empty()) {
+        char err[256] = "";
+        const int rc = neat::forward_plan(jobs.data(), (int)jobs.size(), neat::FWD_AUTO,
+                                          max_lds_bytes(), hp.fw, err, sizeof(err));
         if (rc != NEAT_OK) return fail(rc, "%s", err);
-        hp.fw.insert(hp.fw.end(), part.begin(), part.end());
     }
     // work-unit tables of the launches with more than one item
     hp.fw_off.assign(hp.fw.size(), -1);
@@ -219,6 +217,7 @@ int build(const neat_batch_item *items, int32_t n, neat_batch_plan **out) {
     if (!p) return fail(NEAT_E_NOMEM, "out of host memory");
     p->items.assign(items, items + n);
     (void)hipGetDevice(&p->device);
+    p->tune_gen = neat::tune_generation();
     HostPlan hp;
     int rc = plan_host(items, n, hp);
     if (rc != NEAT_OK) {
@@ -365,6 +364,7 @@ bool same_items(const neat_batch_plan *p, const neat_batch_item *items, int32_t 
     int dev = -1;
     (void)hipGetDevice(&dev);
     if (p->device != dev || (size_t)n != p->items.size()) return false;
+    if (p->tune_gen != neat::tune_generation()) return false;  // re-tuned since recorded
     for (int32_t k = 0; k < n; ++k)
         if (!same_item(p->items[k], items[k])) return false;
     return true;

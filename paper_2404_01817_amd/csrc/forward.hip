@@ -148,10 +148,9 @@ struct AsmTile<KIND_R64REC> {
 // ---------------------------------------------------------------- nodes (C++)
 // The LDS store's node loop: the operations of node_loop_asm.h in the same
 // order, so both give identical bits.
-template <int ACLS, class Store>
-__device__ __forceinline__ void pair(float &acc, bool first, int s0, float w0, int s1, float w1,
-                                     const Store &v) {
-    const float x0 = v.template get<0>(s0), x1 = v.template get<0>(s1);
+template <int ACLS>
+__device__ __forceinline__ void pair_vals(float &acc, bool first, float x0, float w0, float x1,
+                                          float w1) {
     if (ACLS == ACLS_SUM) {
         acc = first ? x0 * w0 : fmaf(x0, w0, acc);
         acc = fmaf(x1, w1, acc);
@@ -170,11 +169,16 @@ __device__ __forceinline__ void pair(float &acc, bool first, int s0, float w0, i
     }
 }
 
+template <int ACLS, class Store>
+__device__ __forceinline__ void pair(float &acc, bool first, int s0, float w0, int s1, float w1,
+                                     const Store &v) {
+    pair_vals<ACLS>(acc, first, v.template get<0>(s0), w0, v.template get<0>(s1), w1);
+}
+
 // pairs (>= 1) edge pairs: the first three from the record r, then the
 // overflow array from e, four words per pair.
-template <int ACLS, class Store>
-__device__ __forceinline__ float aggregate(const i32x16 &r, cprog_t *e, int pairs,
-                                           const Store &v) {
+template <int ACLS, class Store, class EP>
+__device__ __forceinline__ float aggregate(const i32x16 &r, EP e, int pairs, const Store &v) {
     float acc = 0.0f;
 #pragma unroll
     for (int k = 0; k < REC_INLINE_PAIRS; ++k) {
@@ -480,6 +484,181 @@ __device__ __forceinline__ void forward_unit_lds(citem_t *it, int g, int chunk, 
     }
 }
 
+// ---------------------------------------------------------------- levels
+// Mapping "lanes over a level" (FWD_LVL), for genomes evaluated on few
+// samples, where a lane-per-sample tile would leave most lanes idle.  A
+// wave takes a tile of BW = 2^sh samples (BW <= 64) and walks the genome
+// level by level (Section 3.3's order groups nodes by level: a level's
+// nodes read only earlier levels).  Each step spreads 64 / BW of the
+// level's computed nodes over the lanes, node-major (lane = node * BW +
+// sample), so one step evaluates up to 64 (node, sample) pairs and a
+// genome costs about sum over levels of nodes * BW / 64 steps instead of
+// one node loop iteration per node.  A lane reads its node's 64-byte
+// record with vector loads and aggregates its in-edges in its own lane, in
+// the record's order with the operations of the other stores (identical
+// bits).  Values live in this wave's LDS area: slot s of the tile's sample
+// j at v[s * BW + j].  Every node of a step reads its sources before any
+// node of the step writes (a barrier-free wave step with the results held
+// in registers), and a slot the program reuses after its last reader
+// (liveness) is taken only by a later position, so no value is overwritten
+// before it is read.
+struct LvlStore {
+    float *v;
+    int sh;  // log2 BW
+    int j;   // this lane's sample in the tile
+    template <int H>
+    __device__ __forceinline__ float get(int s) const {
+        return v[(s << sh) + j];
+    }
+};
+
+typedef const __attribute__((address_space(1))) int32_t gint_t;
+typedef const __attribute__((address_space(1))) i32x16 gint16_t;
+
+// Order this wave's LDS accesses (the hardware keeps a wave's LDS
+// operations in order; this stops the compiler from moving them).
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Advance (l, kb, k1) to the next step: the next npw records of level l,
+// or the first records of the next level that has computed nodes (l =
+// nlev when none is left).  Start with l = -1.
+__device__ __forceinline__ void lvl_advance(cprog_t *lvl, int nlev, int I, int npw, int *l,
+                                            int *kb, int *k1) {
+    if (*l >= 0 && *kb + npw < *k1) {
+        *kb += npw;
+        return;
+    }
+    for (++*l; *l < nlev; ++*l) {
+        *kb = max(lvl[*l], I) - I, *k1 = lvl[*l + 1] - I;
+        if (*kb < *k1) return;
+    }
+}
+
+// Request the record (and its first overflow edge) of this lane's node in
+// step (l, kb, k1).
+__device__ __forceinline__ void lvl_load(gint16_t *recs, gint_t *ebeg, int nlev, int node, int l,
+                                         int kb, int k1, i32x16 *r, int *e) {
+    const int k = kb + node;
+    if (l < nlev && k < k1) {
+        *r = recs[k];
+        *e = ebeg[k];
+    }
+}
+
+// One step: this lane's node (record r, first overflow edge e) on its
+// sample, when active; then the write of every active lane's result once
+// all lanes of the step have read their sources.
+__device__ __forceinline__ void lvl_step(const i32x16 &r, int e, bool active, gint_t *edges,
+                                         const LvlStore &src, float *v, int sh, int j) {
+    // the sources of this step were written by earlier steps
+    wave_lds_sync();
+    float y = 0.0f;
+    int slot = -1;
+    if (active) {
+        const unsigned code = (unsigned)r[REC_CODE], np = (unsigned)r[REC_NPAIRS];
+        const int pairs = (int)(np & (unsigned)REC_NPAIRS_MASK);
+        const int acls = slot_class((int)(np >> REC_FIELD_SHIFT));
+        const int act = (int)(code >> REC_FIELD_SHIFT);
+        slot = (int)(code & (unsigned)REC_DST_MASK);
+        // the six inline sources at once (unused inline edges name the
+        // constant slot with weight 0)
+        float x[2 * REC_INLINE_PAIRS];
+#pragma unroll
+        for (int q = 0; q < 2 * REC_INLINE_PAIRS; ++q) x[q] = src.get<0>(r[REC_PAIRS + 2 * q]);
+        float a = 0.0f;
+        const int inl = min(pairs, REC_INLINE_PAIRS);
+        gint_t *ov = edges + EDGE_WORDS * e;
+#define NEAT_LVL_AGG(ACLS)                                                                   \
+    {                                                                                        \
+        _Pragma("unroll") for (int q = 0; q < REC_INLINE_PAIRS; ++q) if (q < inl)            \
+            pair_vals<ACLS>(a, q == 0, x[2 * q], fbits(r[REC_PAIRS + 4 * q + 1]), x[2 * q + 1], \
+                            fbits(r[REC_PAIRS + 4 * q + 3]));                                \
+        for (int p = 0; p < pairs - REC_INLINE_PAIRS; ++p)                                   \
+            pair<ACLS>(a, false, ov[4 * p], fbits(ov[4 * p + 1]), ov[4 * p + 2],             \
+                       fbits(ov[4 * p + 3]), src);                                           \
+    }
+        if (acls == ACLS_PROD) NEAT_LVL_AGG(ACLS_PROD)
+        else if (acls == ACLS_MAX) NEAT_LVL_AGG(ACLS_MAX)
+        else NEAT_LVL_AGG(ACLS_SUM)
+#undef NEAT_LVL_AGG
+        y = activation(act, fmaf(fbits(r[REC_RESP]), a, fbits(r[REC_BIAS])));
+    }
+    // every lane of the step has read its sources
+    wave_lds_sync();
+    if (slot >= 0) v[(slot << sh) + j] = y;
+}
+
+__device__ __forceinline__ void forward_unit_lvl(citem_t *it, int g, int chunk, float *v) {
+    int t0, t1;
+    if (!wave_tiles(it, chunk, &t0, &t1)) return;
+    const int lane = (int)(threadIdx.x & (WAVE - 1));
+    const int sh = it->lvl_sh, BW = 1 << sh;
+    const int N = it->N, C = it->C, I = it->I, O = it->O, B = it->B;
+    cprog_t *prog = (cprog_t *)(it->prog + (size_t)g * it->prog_words);
+    gint_t *gp = (gint_t *)(it->prog + (size_t)g * it->prog_words);
+    float *out_g = it->outputs + (size_t)g * B * O;
+    if (prog[HDR_STATUS] != 0) {
+        fill_nan(out_g, t0 * BW, min(B, t1 * BW), O);
+        return;
+    }
+    const float *in_g = it->inputs + (size_t)g * it->gstride;
+    const int nlev = prog[HDR_NLEVELS];
+    const int zs = zero_slot(prog[HDR_CLASS], N);
+    cprog_t *lvl = prog + lvl_off(N, C, O);
+    gint_t *ebeg = gp + ebeg_off(N, C, O);
+    gint_t *edges = gp + edge_off(N, O);
+    gint16_t *recs = (gint16_t *)(gp + rec_off(O));
+    const int j = lane & (BW - 1), node = lane >> sh, npw = WAVE >> sh;
+    const LvlStore src{v, sh, j};
+    for (int t = t0; t < t1; ++t) {
+        const int s0 = t * BW, nb = min(BW, B - s0);
+        // inputs of the tile (contiguous [nb][I] floats): v[i][j] = x[s0 + j][i];
+        // columns past the tile's last sample read 0
+        const float *x = in_g + (size_t)s0 * I;
+        for (int e = lane; e < BW * I; e += WAVE) {
+            const int jj = e / I, i = e - jj * I;
+            v[(i << sh) + jj] = jj < nb ? x[e] : 0.0f;
+        }
+        if (lane < BW) {
+            v[(zs << sh) + lane] = 0.0f;
+            v[((zs + 1) << sh) + lane] = 1.0f;
+        }
+        // the steps of every level in order: (level l, records kb ..
+        // kb + npw - 1 below k1), alternating two record buffers: the next
+        // step's records (and overflow offsets) are requested before the
+        // current step is aggregated
+        int l = -1, kb = 0, k1 = 0;
+        lvl_advance(lvl, nlev, I, npw, &l, &kb, &k1);
+        i32x16 ra = {}, rb = {};
+        int ea = 0, eb = 0;
+        lvl_load(recs, ebeg, nlev, node, l, kb, k1, &ra, &ea);
+        while (l < nlev) {
+            int l2 = l, kb2 = kb, k12 = k1;
+            lvl_advance(lvl, nlev, I, npw, &l2, &kb2, &k12);
+            lvl_load(recs, ebeg, nlev, node, l2, kb2, k12, &rb, &eb);
+            lvl_step(ra, ea, kb + node < k1, edges, src, v, sh, j);
+            l = l2, kb = kb2, k1 = k12;
+            if (l >= nlev) break;
+            lvl_advance(lvl, nlev, I, npw, &l2, &kb2, &k12);
+            lvl_load(recs, ebeg, nlev, node, l2, kb2, k12, &ra, &ea);
+            lvl_step(rb, eb, kb + node < k1, edges, src, v, sh, j);
+            l = l2, kb = kb2, k1 = k12;
+        }
+        wave_lds_sync();
+        // outputs of the tile: y[s0 + j][o] = v[out slot o][j]
+        float *o_t = out_g + (size_t)s0 * O;
+        for (int e = lane; e < nb * O; e += WAVE) {
+            const int jj = e / O, o = e - jj * O;
+            __builtin_nontemporal_store(v[(prog[out_off() + o] << sh) + jj], o_t + e);
+        }
+        wave_lds_sync();
+    }
+}
+
 // ---------------------------------------------------------------- recurrent
 // Recurrent networks (read as K synchronous sweeps; the program comes from
 // the recurrent transformation: records in key order, one slot per node).
@@ -568,7 +747,9 @@ __device__ __forceinline__ void run_unit(long long u, float *wave_area) {
         if (i >= pop[POP_COUNT + cls]) return;
         g = pop[POP_IDS + pop[POP_BEGIN + cls] + i];
     }
-    if constexpr (K == KIND_LDS) {
+    if constexpr (K == KIND_LVL) {
+        forward_unit_lvl(it, g, chunk, wave_area);
+    } else if constexpr (K == KIND_LDS) {
         LdsStore v;
         v.col = wave_area + L->stage_floats + (threadIdx.x & (WAVE - 1));
         forward_unit_lds<GRID, WAVE>(it, g, chunk, wave_area, v);
@@ -612,6 +793,18 @@ long long wave_target() {
     return t;
 }
 
+// LDS bytes of one wave's values in the level mapping: the tile width is
+// the widest that keeps rows x width within it (NEAT_LVL_WAVE_BYTES
+// overrides, for tuning).
+size_t lvl_wave_bytes() {
+    static const size_t b = [] {
+        const char *e = getenv("NEAT_LVL_WAVE_BYTES");
+        const long long v = e ? atoll(e) : 0;
+        return v >= 1024 && v <= 65536 ? (size_t)v : (size_t)8192;
+    }();
+    return b;
+}
+
 int choose_chunks(long long P, int tiles, int *tpw) {
     // aim at a wave count that fills 256 CUs several times over while a
     // wave still reuses its genome's program across a run of tiles (and
@@ -634,6 +827,7 @@ bool lds_kind(int kind) { return kind == KIND_LDS || kind == KIND_LDS32; }
 // kernel of class c under a variant
 int kind_of(int variant, int cls, int B) {
     if (variant == FWD_LDS) return KIND_LDS;
+    if (variant == FWD_LVL) variant = FWD_AUTO;  // grid and recurrent items
     switch (cls) {
     case CLS_R64:
         if (variant == FWD_REG2 || (variant == FWD_AUTO && B > WAVE)) return KIND_R64X2;
@@ -647,7 +841,8 @@ int kind_of(int variant, int cls, int B) {
 }  // namespace
 
 const char *kind_name(int kind) {
-    static const char *names[] = {"r64", "r64x2", "r128", "r224", "lds", "r64rec", "lds32"};
+    static const char *names[] = {"r64", "r64x2", "r128", "r224", "lds", "r64rec", "lds32",
+                                  "lvl"};
     return kind >= 0 && kind < N_KINDS ? names[kind] : "?";
 }
 
@@ -664,10 +859,38 @@ int forward_plan(const FwdJob *jobs, int n, int variant, size_t max_lds,
         k[x].grid_mode = x & 1;
         rows_max[x] = stage_max[x] = ostage_max[x] = 0;
     }
+    const int plan_variant = variant;
     for (int j = 0; j < n; ++j) {
         const FwdJob &J = jobs[j];
         if (J.P == 0 || J.B == 0) continue;
+        const int variant = J.variant >= 0 ? J.variant : plan_variant;
         const int top = max_class(J.N);
+        if (variant == FWD_LVL && !J.side && !J.recurrent) {
+            // the level mapping: every genome, one launch over all items;
+            // the widest power-of-two tile of samples (<= 64, <= B rounded
+            // up) whose values fit a wave's LDS budget
+            const int rows = class_slots(top, J.N);
+            int sh = 0;
+            while (sh < 6 && (1 << sh) < J.B &&
+                   sizeof(float) * (size_t)rows * (2u << sh) <= lvl_wave_bytes())
+                ++sh;
+            FwdItem it{};
+            it.prog = J.prog;
+            it.inputs = J.inputs;
+            it.outputs = J.outputs;
+            it.gstride = J.gstride;
+            it.pop = J.prog + pop_off(J.P, J.N, J.C, J.O);
+            it.cls = -1;
+            it.P = J.P, it.N = J.N, it.C = J.C, it.I = J.I, it.O = J.O, it.B = J.B;
+            it.prog_words = prog_words(J.N, J.C, J.O);
+            it.lvl_sh = sh;
+            it.tiles = (J.B + (1 << sh) - 1) >> sh;
+            it.chunks = choose_chunks(J.P, it.tiles, &it.tpw);
+            const int x = 2 * KIND_LVL;
+            k[x].items.push_back(it);
+            rows_max[x] = std::max(rows_max[x], rows << sh);
+            continue;
+        }
         // FWD_LDS takes every genome in one pass over all genomes; the other
         // variants take class c's genomes with class c's kernel; a recurrent
         // job (N_max <= 62) takes every genome with the recurrent kernel
@@ -688,7 +911,8 @@ int forward_plan(const FwdJob *jobs, int n, int variant, size_t max_lds,
             it.pop = J.prog + pop_off(J.P, J.N, J.C, J.O);
             // populations of N_max <= 62 are all R64 and have no class list
             it.cls = (c < 0 || top == CLS_R64) ? -1 : c;
-            it.P = J.P, it.N = J.N, it.I = J.I, it.O = J.O, it.B = J.B, it.side = J.side;
+            it.P = J.P, it.N = J.N, it.C = J.C, it.I = J.I, it.O = J.O, it.B = J.B;
+            it.side = J.side;
             it.prog_words = prog_words(J.N, J.C, J.O);
             it.sweeps = J.recurrent ? J.sweeps : 0;
             const int TS = tile_samples(kind);
@@ -709,8 +933,9 @@ int forward_plan(const FwdJob *jobs, int n, int variant, size_t max_lds,
         FwdKernelLaunch &K = k[x];
         const int kind = K.kind;
         if (K.items.empty()) continue;
-        const size_t rows = lds_kind(kind) ? (size_t)rows_max[x] * tile_samples(kind)
-                                           : (size_t)ostage_max[x];
+        const size_t rows = kind == KIND_LVL ? (size_t)rows_max[x]
+                            : lds_kind(kind) ? (size_t)rows_max[x] * tile_samples(kind)
+                                             : (size_t)ostage_max[x];
         const size_t wave_floats = (size_t)stage_max[x] + rows;
         const size_t wave_bytes = wave_floats * sizeof(float);
         int waves = FWD_MAX_WAVES;
@@ -736,7 +961,7 @@ int forward_plan(const FwdJob *jobs, int n, int variant, size_t max_lds,
         K.lds = wave_bytes * waves;
         // the LDS store limits the workgroups a CU holds: loop over units with
         // a grid of a few per CU instead of one workgroup per unit
-        const long long cap = lds_kind(kind)
+        const long long cap = (lds_kind(kind) || kind == KIND_LVL)
                                   ? 256ll * 2 * std::max<long long>(1, (long long)(163840 / K.lds))
                                   : (1ll << 31) - 1;
         K.args.persistent = groups > cap ? 1 : 0;
@@ -795,6 +1020,7 @@ hipError_t forward_launch(const FwdKernelLaunch &k, const FwdItem *dev_items, hi
     case KIND_R224: NEAT_LAUNCH(KIND_R224) break;
     case KIND_R64REC: NEAT_LAUNCH2(KIND_R64REC, false) break;
     case KIND_LDS32: NEAT_LAUNCH(KIND_LDS32) break;
+    case KIND_LVL: NEAT_LAUNCH2(KIND_LVL, false) break;
     default: NEAT_LAUNCH(KIND_LDS) break;
     }
 #undef NEAT_LAUNCH

@@ -48,14 +48,18 @@ constexpr int FWD_AUTO = 0;  // per slot class: registers, R64 with two samples 
 constexpr int FWD_REG = 1;   // registers, one sample per lane (LDS rows for the LDS class)
 constexpr int FWD_LDS = 2;   // every genome in LDS rows
 constexpr int FWD_REG2 = 3;  // as FWD_REG, R64 genomes two samples per lane
+constexpr int FWD_LVL = 5;   // lanes over a level's nodes x a tile of samples (values in LDS)
 
 // Forward kernels, one per value store.
 // KIND_R64REC: the recurrent calculation (K synchronous sweeps) with the
 // 64-slot register store, for populations of N_max <= 62.  KIND_LDS32: the
 // LDS-row store with half-wave tiles (32 samples), for genomes whose rows
 // do not fit in LDS with 64 columns.
+// KIND_LVL: the level mapping (FWD_LVL), every genome of an item, tiles of
+// 2^lvl_sh samples.
 enum FwdKind {
-    KIND_R64 = 0, KIND_R64X2, KIND_R128, KIND_R224, KIND_LDS, KIND_R64REC, KIND_LDS32, N_KINDS
+    KIND_R64 = 0, KIND_R64X2, KIND_R128, KIND_R224, KIND_LDS, KIND_R64REC, KIND_LDS32, KIND_LVL,
+    N_KINDS
 };
 constexpr int FWD_MAX_WAVES = 4;  // waves per workgroup
 
@@ -70,6 +74,7 @@ struct FwdJob {
     int side;             // > 0: grid mode (CPPN queries generated in the kernel)
     int recurrent;        // 1: a recurrent program, sweeps synchronous sweeps
     int sweeps;
+    int variant = -1;     // FWD_*: this job's variant; -1: the plan's
 };
 
 // One population in one forward kernel (device-visible, read with scalar
@@ -85,6 +90,8 @@ struct FwdItem {
     int P, N, I, O, B, side, vec4, cls;
     int tiles, tpw, chunks, prog_words;
     int sweeps;  // recurrent kernel: sweeps per sample
+    int C;       // C_max (program layout)
+    int lvl_sh;  // level mapping: log2 of the samples per tile
 };
 
 // Kernel argument: one item inline, or a device table of items.
@@ -110,8 +117,9 @@ struct FwdKernelLaunch {
 
 const char *kind_name(int kind);
 
-// Plan the kernels of a forward over n populations: one launch per value
-// store in use, each covering its genomes of every population.  Returns
+// Plan the kernels of a forward over n populations: one launch per kernel
+// kind in use, each covering its genomes of every population (jobs with
+// their own variant join the same launches as the others of their kind).  Returns
 // NEAT_OK or an error code with a message in err.
 int forward_plan(const FwdJob *jobs, int n, int variant, size_t max_lds,
                  std::vector<FwdKernelLaunch> &out, char *err, size_t errlen);

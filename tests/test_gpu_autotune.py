@@ -1,5 +1,5 @@
 """GPU tests of the forward autotuner (neat_autotune_forward, through the C
-ABI): the tuned variant is one of the three measured ones, tuning leaves
+ABI): the tuned variant is one of the four measured ones, tuning leaves
 the outputs bit-identical to the automatic rule, and later calls with
 FWD_TUNED and batches over tuned buckets give the same bits as untuned
 calls (every variant runs the same operations in the same order)."""
@@ -50,9 +50,14 @@ def test_autotune_records_a_measured_variant(P, B):
     v, ms = neat.autotune_forward(p.d, p.prog, p.x, B, outputs=p.y, reps=3)
     torch.cuda.synchronize()
     print("tuned", P, B, v, ms, flush=True)
-    assert v in (neat.FWD_REG, neat.FWD_REG2, neat.FWD_LDS)
+    cands = [neat.FWD_REG, neat.FWD_REG2, neat.FWD_LDS, neat.FWD_LVL]
+    nc = len(cands)
+    assert v in cands and len(ms) == 2 * nc
     assert all(m > 0 for m in ms)
-    assert ms[[neat.FWD_REG, neat.FWD_REG2, neat.FWD_LDS].index(v)] == min(ms)
+    assert ms[cands.index(v)] == min(ms[:nc])
+    vt = neat.tuned_variant(p.d, B, throughput=True)
+    assert ms[nc + cands.index(vt)] == min(ms[nc:])
+    assert neat.tuned_variant(p.d, B) == v
     assert np.array_equal(_bits(p.y), _bits(ref))
     y2 = neat.forward(p.d, p.prog, p.x, B, variant=neat.FWD_TUNED)
     assert np.array_equal(_bits(y2), _bits(ref))
@@ -82,7 +87,7 @@ def test_autotune_arguments():
     with pytest.raises(neat.NeatError):
         neat.autotune_forward(p.d, p.prog, p.x, 8, reps=0)
     with pytest.raises(neat.NeatError):
-        neat.forward(p.d, p.prog, p.x, 8, variant=5)
+        neat.forward(p.d, p.prog, p.x, 8, variant=6)
     v, ms = neat.autotune_forward(p.d, p.prog, p.x, 0, reps=2)
-    assert v == neat.FWD_AUTO and ms == [-1.0, -1.0, -1.0]
+    assert v == neat.FWD_AUTO and ms == [-1.0] * (2 * neat.TUNE_CANDIDATES)
     torch.cuda.synchronize()
