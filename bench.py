@@ -66,7 +66,7 @@ def parse():
                     help="the oracle repeats its sample until this much CPU time has passed")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quiet", action="store_true")
-    ap.add_argument("--workloads", default="control,batched,served,cppn,recurrent,substrate,distance,"
+    ap.add_argument("--workloads", default="control,tiny,batched,served,cppn,recurrent,substrate,distance,"
                             "crossover,edit",
                     help="comma list: control (the headline line), batched (64 uneven "
                          "populations in one recorded batch), served (Poisson request "
@@ -83,6 +83,9 @@ def parse():
                     help="length of the served request stream (latency counted after "
                          "the first quarter)")
     ap.add_argument("--served-rate", type=float, default=200.0, help="requests per second")
+    ap.add_argument("--served-sweep", default="1000,4000,16000,64000,256000",
+                    help="further request rates (per second), each run for --sweep-seconds")
+    ap.add_argument("--sweep-seconds", type=float, default=3.0)
     ap.add_argument("--copy-probe", action="store_true",
                     help="after the timed region, copy 256 MiB once (a plain copy kernel "
                          "of known size, which calibrates HBM byte counters)")
@@ -197,20 +200,53 @@ def bench_batched(args, torch, neat, synth):
     fwd_only = [neat.batch_item(d, prog, y, inputs=tx, B=pop.B)
                 for pop, d, tn, tc, tx, prog, st, y in bufs]
     stream = torch.cuda.current_stream()
-    res = {}
-    for name, items in (("end_to_end", full), ("forward", fwd_only)):
-        plan = neat.BatchPlan()
+
+    def timed(fn, steps):
         for _ in range(max(1, args.warmup)):
-            plan.run(items)
+            fn()
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
-        for _ in range(args.steps):
-            plan.run(items)
+        for _ in range(steps):
+            fn()
         e1.record(stream)
         torch.cuda.synchronize()
-        res[name] = (e0.elapsed_time(e1) / args.steps, plan.launches)
-        plan.free()
+        return e0.elapsed_time(e1) / steps
+
+    def run_batches():
+        res = {}
+        for name, items in (("end_to_end", full), ("forward", fwd_only)):
+            plan = neat.BatchPlan()
+            res[name] = (timed(lambda: plan.run(items), args.steps), plan.launches)
+            plan.free()
+        return res
+
+    untuned = run_batches()
+    # the autotuner on every population (outside the timed region): the
+    # batch uses each bucket's throughput winner, plain calls their latency
+    # winner
+    t_tune = time.time()
+    tuned_to = {}
+    for pop, d, tn, tc, tx, prog, st, y in bufs:
+        neat.autotune_forward(d, prog, tx, pop.B, outputs=y, reps=3)
+        v = neat.tuned_variant(d, pop.B, throughput=True)
+        tuned_to[v] = tuned_to.get(v, 0) + 1
+    log(args, "autotuned 64 populations in %.1fs: %s" % (time.time() - t_tune, tuned_to))
+    res = run_batches()
+
+    # the same work as plain per-population launches: transformation and
+    # calculation of each population in turn, and the calculations alone
+    def plain_e2e():
+        for pop, d, tn, tc, tx, prog, st, y in bufs:
+            neat.topo_sort(tn, tc, pop.I, pop.O, program=prog, status=st, want_order=False)
+            neat.forward(d, prog, tx, pop.B, outputs=y, variant=neat.FWD_TUNED)
+
+    def plain_fwd():
+        for pop, d, tn, tc, tx, prog, st, y in bufs:
+            neat.forward(d, prog, tx, pop.B, outputs=y, variant=neat.FWD_TUNED)
+
+    ms_plain_e2e = timed(plain_e2e, max(3, args.steps // 4))
+    ms_plain_fwd = timed(plain_fwd, max(3, args.steps // 4))
     units = sum(pop.P * pop.B for pop in pops)
     fwd_bytes = 0
     for pop, d, tn, tc, tx, prog, st, y in bufs:
@@ -228,54 +264,94 @@ def bench_batched(args, torch, neat, synth):
         "value_end_to_end": round(units / (ms_e2e / 1e3), 1),
         "ms_forward": round(ms_fwd, 4), "launches_forward": n_fwd,
         "value_forward": round(units / (ms_fwd / 1e3), 1), "unit": "genome-inputs/s",
+        "untuned": {"ms_end_to_end": round(untuned["end_to_end"][0], 4),
+                    "ms_forward": round(untuned["forward"][0], 4)},
+        "tuned_throughput_winners": {{0: "auto", 1: "reg", 2: "lds", 3: "reg2",
+                                      5: "lvl"}.get(k, str(k)): v for k, v in tuned_to.items()},
+        "plain": {"ms_end_to_end": round(ms_plain_e2e, 4), "ms_forward": round(ms_plain_fwd, 4),
+                  "launches_end_to_end": 2 * len(pops), "launches_forward": len(pops),
+                  "value_end_to_end": round(units / (ms_plain_e2e / 1e3), 1),
+                  "value_forward": round(units / (ms_plain_fwd / 1e3), 1)},
+        "batched_speedup_end_to_end": round(ms_plain_e2e / ms_e2e, 3),
+        "batched_speedup_forward": round(ms_plain_fwd / ms_fwd, 3),
         "roofline_forward": {"bound": "hbm", "achieved": round(achieved, 1),
                              "peak": HBM_PEAK_GBS, "unit": "GB/s",
                              "frac": round(achieved / HBM_PEAK_GBS, 4),
                              "algorithmic_bytes_per_launch": fwd_bytes,
                              "note": "neither HBM nor ALU bounds this launch: with B of 1 "
-                                     "to 512 most tiles are partly empty and a wave's "
-                                     "time is the latency of its genome's node chain"},
+                                     "to 512 most genomes' node chains are latency-bound "
+                                     "at low occupancy (large genomes need 128-224 value "
+                                     "registers per lane)"},
     }
 
 
-def bench_served(args, torch, neat, synth):
-    """Poisson request stream over 128 resident populations (P log-uniform
-    [64, 8192], N_max log-uniform [8, 256], C_max = 4 N_max); each request
-    takes a uniform population and B log-uniform [1, 256], inputs cut from
-    a 4 GiB pool of N(0,1) at a seed-derived offset.  Latency = completion
-    - scheduled arrival, over arrivals after the first quarter."""
+def bench_tiny(args, torch, neat, synth):
+    """The tiny workload (P = 16, N_max = 8, 32 shared inputs): latency of
+    one transformation + calculation call pair, on the device (events over
+    consecutive calls) and end to end on the host (each pair synchronized)."""
     dev = torch.device("cuda:0")
-    t0 = time.time()
-    pool = synth.served_pool(seed=3)
-    log(args, "generated %d resident populations in %.1fs" % (len(pool), time.time() - t0))
-    server = neat.Server(cap_bytes=64 << 30, max_inflight=4)
-    ids = []
-    for pop in pool:
-        tn = torch.from_numpy(pop.nodes).to(dev)
-        tc = torch.from_numpy(pop.conns).to(dev)
-        ids.append(server.register(tn, tc, pop.I, pop.O))
-        del tn, tc
-    gen = torch.Generator(device=dev)
-    gen.manual_seed(3)
-    xpool = torch.randn((1 << 30,), generator=gen, device=dev)  # 4 GiB
-    ypool = torch.empty((1 << 30,), device=dev)
-    rng = np.random.default_rng(3)
-    n_req = int(args.served_rate * args.served_seconds)
-    arrivals = np.cumsum(rng.exponential(1.0 / args.served_rate, n_req))
+    pop = synth.tiny()
+    tn = torch.from_numpy(pop.nodes).to(dev)
+    tc = torch.from_numpy(pop.conns).to(dev)
+    tx = torch.from_numpy(pop.inputs).to(dev)
+    d = neat.dims_of(tn, tc, pop.I, pop.O)
+    _, _, st, prog = neat.topo_sort(tn, tc, pop.I, pop.O, want_order=False)
+    y = torch.empty((pop.P, pop.B, pop.O), device=dev)
+
+    def call():
+        neat.topo_sort(tn, tc, pop.I, pop.O, program=prog, status=st, want_order=False)
+        neat.forward(d, prog, tx, pop.B, shared_inputs=True, outputs=y)
+
+    for _ in range(20):
+        call()
+    torch.cuda.synchronize()
+    n = 500
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(n):
+        call()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    dev_us = e0.elapsed_time(e1) / n * 1e3
+    host = []
+    for _ in range(200):
+        t = time.perf_counter()
+        call()
+        torch.cuda.synchronize()
+        host.append(time.perf_counter() - t)
+    return {"workload": "tiny: P=16, N_max=8, C_max=16, I=3, O=1, 32 shared inputs, "
+                        "transformation + calculation per call",
+            "us_per_call_back_to_back": round(dev_us, 2),
+            "us_per_call_synchronized_p50": round(float(np.median(host)) * 1e6, 2),
+            "genome_inputs_per_call": pop.P * pop.B}
+
+
+def served_stream(args, torch, neat, server, pool, ids, xpool, ypool, rate, seconds, seed,
+                  tune=False):
+    """One Poisson stream of requests over the resident pool: arrivals at
+    `rate` per second for `seconds`, each request a uniform pool population
+    with B log-uniform [1, 256] and inputs cut from xpool at a seed-derived
+    offset.  Latency = completion - scheduled arrival, over arrivals after
+    the first quarter."""
+    rng = np.random.default_rng(seed)
+    n_req = max(1, int(rate * seconds))
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, n_req))
     which = rng.integers(0, len(pool), n_req)
     Bs = np.rint(np.exp(rng.uniform(0.0, np.log(256.0), n_req))).astype(np.int64)
     torch.cuda.synchronize()
     server.reset_stats()
-    pending = {}  # ticket -> (k, output span end, submit delay)
+    pending = {}  # ticket -> (k, submit delay)
     done = []     # (k, latency_s)
     y_at = 0
+    late = 0
     t_start = time.perf_counter()
 
-    def drain(block_until=None):
+    def drain():
         for t in list(pending):
             r = server.poll(t)
             if r is not None:
-                k, _, delay = pending.pop(t)
+                k, delay = pending.pop(t)
                 done.append((k, delay + (r.t_done_ns - r.t_submit_ns) * 1e-9))
 
     for k in range(n_req):
@@ -293,30 +369,133 @@ def bench_served(args, torch, neat, synth):
             drain()
             if arrivals[k] - now > 2e-4:
                 time.sleep(1e-4)
+        delay = time.perf_counter() - t_start - arrivals[k]
+        late += delay > 1e-3
         t = server.submit(ids[which[k]], ypool[y_at:y_at + ny], inputs=xpool[xo:xo + nx],
                           B=B, I=pop.I, tag=k)
-        pending[t] = (k, y_at + ny, time.perf_counter() - t_start - arrivals[k])
+        pending[t] = (k, delay)
         y_at += ny
+        if k % 64 == 63:
+            drain()
     while pending:
         drain()
     wall = time.perf_counter() - t_start
     st = server.stats()
+    lat = np.array([l for k, l in done if arrivals[k] >= 0.25 * seconds]) if n_req >= 8 \
+        else np.array([l for _, l in done])
+    gi = int(sum(pool[which[k]].P * int(Bs[k]) for k in range(n_req)))
+    hbm = sum(pool[which[k]].P * int(Bs[k]) * (pool[which[k]].I + pool[which[k]].O) * 4
+              for k in range(n_req))
+    return {"rate_req_s": rate, "seconds": seconds, "requests": n_req,
+            "offered_req_s": round(n_req / arrivals[-1], 1),
+            "submitted_late_over_1ms": int(late),
+            "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
+            "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
+            "latency_counted": int(len(lat)), "genome_inputs": gi,
+            "throughput": round(gi / wall, 1), "unit": "genome-inputs/s",
+            "input_output_GBps": round(hbm / wall / 1e9, 2),
+            "hbm_frac": round(hbm / wall / 1e9 / HBM_PEAK_GBS, 5),
+            "batches": int(st.batches),
+            "mean_requests_per_batch": round(st.batched_requests / max(1, st.batches), 2),
+            "peak_footprint_GiB": round(st.peak_bytes / 2 ** 30, 3),
+            "resident_GiB": round(st.resident_bytes / 2 ** 30, 3)}
+
+
+def bench_served(args, torch, neat, synth):
+    """Served path over 128 resident populations (P log-uniform [64, 8192],
+    N_max log-uniform [8, 256], C_max = 4 N_max): the Poisson stream at the
+    configured rate, a sweep of higher rates, a burst against plain
+    per-request launches, and CPPN grid requests."""
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    pool = synth.served_pool(seed=3)
+    log(args, "generated %d resident populations in %.1fs" % (len(pool), time.time() - t0))
+    server = neat.Server(cap_bytes=64 << 30, max_inflight=4)
+    ids = []
+    for pop in pool:
+        tn = torch.from_numpy(pop.nodes).to(dev)
+        tc = torch.from_numpy(pop.conns).to(dev)
+        ids.append(server.register(tn, tc, pop.I, pop.O))
+        del tn, tc
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(3)
+    xpool = torch.randn((1 << 30,), generator=gen, device=dev)  # 4 GiB
+    ypool = torch.empty((1 << 30,), device=dev)
+    main = served_stream(args, torch, neat, server, pool, ids, xpool, ypool,
+                         args.served_rate, args.served_seconds, seed=3)
+    log(args, "served stream: %s" % main)
+    sweep = []
+    for rate in [float(r) for r in args.served_sweep.split(",") if r]:
+        sweep.append(served_stream(args, torch, neat, server, pool, ids, xpool, ypool, rate,
+                                   args.sweep_seconds, seed=int(rate) + 7))
+        log(args, "served sweep: %s" % sweep[-1])
     burst = served_burst(args, torch, neat, server, pool, ids, xpool, ypool) \
         if args.served_burst > 0 else None
+    cppn = served_cppn(args, torch, neat, synth, server)
     server.close()
-    lat = np.array([l for k, l in done if arrivals[k] >= 0.25 * args.served_seconds])
-    gi = int(sum(pool[which[k]].P * int(Bs[k]) for k in range(n_req)))
-    return {
-        "workload": "served: Poisson %.0f req/s for %.0f s over 128 resident populations "
-                    "(P log-uniform [64, 8192], N_max log-uniform [8, 256], C_max = 4 N_max), "
-                    "B log-uniform [1, 256]" % (args.served_rate, args.served_seconds),
-        "requests": n_req, "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
-        "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
-        "latency_counted": int(len(lat)), "genome_inputs": gi,
-        "throughput": round(gi / wall, 1), "unit": "genome-inputs/s",
-        "batches": int(st.batches), "mean_requests_per_batch": round(n_req / max(1, st.batches), 2),
-        "burst_vs_plain": burst,
-    }
+    out = {"workload": "served: Poisson %.0f req/s for %.0f s over 128 resident populations "
+                       "(P log-uniform [64, 8192], N_max log-uniform [8, 256], C_max = 4 N_max), "
+                       "B log-uniform [1, 256]" % (args.served_rate, args.served_seconds)}
+    out.update(main)
+    out["rate_sweep"] = sweep
+    out["burst_vs_plain"] = burst
+    out["cppn_grid_requests"] = cppn
+    return out
+
+
+def served_cppn(args, torch, neat, synth, server):
+    """CPPN substrate queries served as batched GRID requests: the CPPN
+    population (P = 1000, N_max = 30) registered on the server, the 65536
+    queries of the 16 x 16 grid split into requests of 4096 queries, queued
+    at once; against one plain neat_forward_grid call over the whole grid
+    (outputs compared bit for bit).  Best of three."""
+    dev = torch.device("cuda:0")
+    pop = synth.cppn()
+    tn = torch.from_numpy(pop.nodes).to(dev)
+    tc = torch.from_numpy(pop.conns).to(dev)
+    pid = server.register(tn, tc, pop.I, pop.O)
+    d = neat.dims_of(tn, tc, pop.I, pop.O)
+    _, _, _, prog = neat.topo_sort(tn, tc, pop.I, pop.O, want_order=False)
+    Q, chunk = 65536, 4096
+    yfull = torch.empty((pop.P, Q, pop.O), device=dev)
+    parts = [torch.empty((pop.P, chunk, pop.O), device=dev) for _ in range(Q // chunk)]
+
+    def plain():
+        neat.forward_grid(d, prog, 16, 0, Q, outputs=yfull)
+        torch.cuda.synchronize()
+
+    def served():
+        pend = [server.submit(pid, parts[k], B=chunk, grid_side=16, grid_first=k * chunk, tag=k)
+                for k in range(len(parts))]
+        for t in pend:
+            server.wait(t)
+        torch.cuda.synchronize()
+
+    times = {}
+    for name, fn in (("plain", plain), ("served", served)):
+        fn()
+        best = float("inf")
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            fn()
+            best = min(best, time.perf_counter() - t)
+        times[name] = best
+    server.reset_stats()
+    served()
+    st = server.stats()
+    same = all(torch.equal(parts[k].view(torch.int32),
+                           yfull[:, k * chunk:(k + 1) * chunk].contiguous().view(torch.int32))
+               for k in range(len(parts)))
+    gi = pop.P * Q
+    return {"workload": "CPPN P=1000 (N_max=30) on all 65536 queries of a 16x16 grid as %d "
+                        "GRID requests of %d queries" % (len(parts), chunk),
+            "plain_ms": round(times["plain"] * 1e3, 3), "served_ms": round(times["served"] * 1e3, 3),
+            "served_value": round(gi / times["served"], 1), "plain_value": round(gi / times["plain"], 1),
+            "batches": int(st.batches),
+            "mean_requests_per_batch": round(st.batched_requests / max(1, st.batches), 2),
+            "p50_ms": round(st.p50_ms, 3), "p99_ms": round(st.p99_ms, 3),
+            "outputs_identical": bool(same), "unit": "genome-inputs/s"}
 
 
 def served_burst(args, torch, neat, server, pool, ids, xpool, ypool):
@@ -856,6 +1035,7 @@ def main():
     crossover = (bench_crossover(args, torch, neat, synth) if "crossover" in workloads
                  else None)
     edits = bench_edit(args, torch, neat, synth) if "edit" in workloads else None
+    tiny = bench_tiny(args, torch, neat, synth) if "tiny" in workloads else None
 
     res = {
         "metric": "genome-input forwards/s", "value": round(value, 1),
@@ -882,6 +1062,7 @@ def main():
         "distance": distance,
         "crossover": crossover,
         "edit": edits,
+        "tiny": tiny,
     }
     print(json.dumps(res), flush=True)
 

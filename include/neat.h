@@ -500,7 +500,10 @@ int neat_forward_batch_noalloc(const neat_batch_item *items, int32_t n, void *st
 typedef struct {
     int32_t device;          /* HIP device index */
     int32_t max_inflight;    /* batches running at once, 1..16 (one stream each) */
-    uint64_t cap_bytes;      /* admission cap on the bytes of running requests */
+    uint64_t cap_bytes;      /* cap on the device footprint: resident populations plus the
+                                bytes of running requests */
+    const char *tune_cache_path; /* nullable: autotuner cache file to read now and rewrite
+                                    after every tuning (see neat_autotune_forward) */
 } neat_server_cfg;
 
 typedef struct neat_server neat_server;
@@ -529,6 +532,10 @@ typedef struct {
     uint64_t genome_inputs;  /* completed P * B over all requests */
     double p50_ms, p99_ms;   /* latency t_done - t_submit of completed requests */
     double throughput;       /* genome_inputs / (last completion - first submission) per s */
+    uint64_t batched_requests; /* requests admitted over all batches (/ batches = requests
+                                  per batch) */
+    uint64_t resident_bytes; /* held by registered populations */
+    uint64_t peak_bytes;     /* largest footprint admitted (resident + running) */
 } neat_stats;
 
 /* Errors: NEAT_E_INVALID (bad cfg or device), NEAT_E_NOMEM, NEAT_E_HIP. */
@@ -536,11 +543,15 @@ int neat_server_create(const neat_server_cfg *cfg, neat_server **server);
 /* Cancels queued requests, waits for running batches, frees everything. */
 int neat_server_destroy(neat_server *server);
 /* dims, nodes, conns as for neat_topo_sort (device pointers, read once).
+ * The population's copy and program (P (20 N_max + 16 C_max) bytes plus
+ * neat_program_bytes) count against cap_bytes for good: NEAT_E_TOO_LARGE
+ * when they do not fit beside the populations already resident.
  * Genomes the transformation rejects give NaN outputs as usual. */
 int neat_server_register(neat_server *server, const neat_dims *dims, const float *nodes,
                          const float *conns, int32_t *pop_id);
 /* Errors: NEAT_E_INVALID (arguments as neat_forward / neat_forward_grid),
- * NEAT_E_TOO_LARGE (the request alone exceeds cap_bytes), NEAT_E_SHUTDOWN. */
+ * NEAT_E_TOO_LARGE (the request does not fit beside the resident
+ * populations even alone), NEAT_E_SHUTDOWN. */
 int neat_submit(neat_server *server, const neat_request *request, uint64_t *ticket);
 /* NEAT_OK (result filled, ticket forgotten), NEAT_PENDING, or
  * NEAT_E_UNKNOWN_TICKET.  Never blocks. */

@@ -66,10 +66,11 @@ def program_headers(dims: Dims, program):
 
 
 def topo_sort(nodes, conns, I: int, O: int, program=None, stream=None,
-              want_order: bool = True, recurrent: bool = False):
+              want_order: bool = True, recurrent: bool = False, status=None):
     """Transformation stage.  nodes [P,N_max,5], conns [P,C_max,4] float32 on
     the GPU.  Returns (order, level, status, program) as device tensors
-    (order/level None unless ``want_order``).  ``recurrent``: cycles allowed,
+    (order/level None unless ``want_order``; program and status are written
+    into the given tensors when passed).  ``recurrent``: cycles allowed,
     key order, a program for ``forward_recurrent``
     (neat_topo_sort_recurrent)."""
     torch = _torch()
@@ -81,7 +82,10 @@ def topo_sort(nodes, conns, I: int, O: int, program=None, stream=None,
     if want_order:
         order = torch.empty((d.P, d.N_max), dtype=torch.int32, device=dev)
         level = torch.empty((d.P, d.N_max), dtype=torch.int32, device=dev)
-    status = torch.empty((d.P,), dtype=torch.int32, device=dev)
+    if status is None:
+        status = torch.empty((d.P,), dtype=torch.int32, device=dev)
+    elif status.numel() < d.P or status.dtype != torch.int32 or not status.is_cuda:
+        raise ValueError("status must be an int32 device tensor of at least P elements")
     if program is None:
         program = torch.empty((max(program_bytes(d), 4) // 4,), dtype=torch.int32, device=dev)
     fn = lib().neat_topo_sort_recurrent if recurrent else lib().neat_topo_sort
@@ -330,8 +334,10 @@ def forward_batch_noalloc(items, stream=None) -> None:
 class Server:
     """Resident populations and continuous batching (neat_server_*)."""
 
-    def __init__(self, device: int = 0, cap_bytes: int = 64 << 30, max_inflight: int = 4):
-        cfg = ServerCfg(device, max_inflight, cap_bytes)
+    def __init__(self, device: int = 0, cap_bytes: int = 64 << 30, max_inflight: int = 4,
+                 tune_cache_path: str = None):
+        cfg = ServerCfg(device, max_inflight, cap_bytes,
+                        tune_cache_path.encode() if tune_cache_path else None)
         self._h = ctypes.c_void_p(None)
         check(lib().neat_server_create(ctypes.byref(cfg), ctypes.byref(self._h)))
 

@@ -42,7 +42,7 @@ class BatchItem(ctypes.Structure):
 class ServerCfg(ctypes.Structure):
     """neat_server_cfg."""
     _fields_ = [("device", ctypes.c_int32), ("max_inflight", ctypes.c_int32),
-                ("cap_bytes", ctypes.c_uint64)]
+                ("cap_bytes", ctypes.c_uint64), ("tune_cache_path", ctypes.c_char_p)]
 
 
 class Request(ctypes.Structure):
@@ -67,7 +67,9 @@ class Stats(ctypes.Structure):
                 ("completed", ctypes.c_uint64), ("rejected", ctypes.c_uint64),
                 ("batches", ctypes.c_uint64), ("queued", ctypes.c_uint64),
                 ("genome_inputs", ctypes.c_uint64), ("p50_ms", ctypes.c_double),
-                ("p99_ms", ctypes.c_double), ("throughput", ctypes.c_double)]
+                ("p99_ms", ctypes.c_double), ("throughput", ctypes.c_double),
+                ("batched_requests", ctypes.c_uint64), ("resident_bytes", ctypes.c_uint64),
+                ("peak_bytes", ctypes.c_uint64)]
 
 
 INPUT_TENSOR, INPUT_GRID = 0, 1

@@ -3,32 +3,31 @@
 //
 // Populations are registered once: the library copies their encoding into
 // its own device memory and runs the transformation (Section 3.3) then, so
-// every later request only runs the calculation.  Requests are queued by
-// neat_submit; one scheduler thread admits them in arrival order while the
-// bytes they touch (inputs, outputs, work-unit tables) fit under the
-// configured cap and fewer than max_inflight batches are running, gathers
-// everything admitted into one batch (forward_plan over all of its requests:
-// one launch per value-store kernel), uploads the batch's work-unit tables
-// and launches it on the next of max_inflight streams, so consecutive
-// batches overlap on the device.  Completion is detected by polling each
-// batch's event; the request is then done and its bytes are released.
+// every later request only runs the calculation.  The scheduler (scheduler.h)
+// admits queued requests in arrival order while the device footprint --
+// resident populations plus the bytes of running requests (inputs,
+// outputs, work-unit tables) -- stays under the configured cap and fewer
+// than max_inflight batches run; everything admitted together forms one
+// batch.  The HIP executor below plans a batch (forward_plan over all of
+// its requests: one launch per kernel kind, each request with the variant
+// tuned for its bucket -- the latency winner when it runs alone, the
+// throughput winner when it shares the batch), uploads the work-unit tables
+// and launches the batch on its slot's stream, so consecutive batches
+// overlap on the device; completion is an event per slot.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
-#include <chrono>
-#include <condition_variable>
-#include <deque>
 #include <memory>
 #include <mutex>
 #include <new>
-#include <thread>
-#include <unordered_map>
 #include <vector>
 
 #include "abi.h"
 #include "launch.h"
 #include "neat.h"
 #include "program.h"
+#include "scheduler.h"
+#include "tune.h"
 
 using namespace neat::abi;
 
@@ -39,12 +38,8 @@ constexpr size_t TABLE_ITEMS = 4 * MAX_BATCH_REQUESTS;  // items per batch table
 // work-unit table bytes a request may add to its batch (one item per slot
 // class)
 constexpr size_t REQ_TABLE_BYTES = 4 * sizeof(neat::FwdItem);
-
-int64_t now_ns(std::chrono::steady_clock::time_point t0) {
-    return std::chrono::duration_cast<std::chrono::nanoseconds>(
-               std::chrono::steady_clock::now() - t0)
-        .count();
-}
+// completion polling period of the scheduler
+constexpr int POLL_US = 20;
 
 struct Pop {
     neat_dims d{};
@@ -52,50 +47,67 @@ struct Pop {
     int32_t *program = nullptr;
 };
 
-enum ReqState { Q_QUEUED = 0, Q_ADMITTED = 1, Q_DONE = 2 };
-
-struct Req {
+struct Payload {
     neat_request r{};
-    neat_result res{};
-    size_t bytes = 0;
-    int state = Q_QUEUED;
+    const Pop *pop = nullptr;
 };
 
 // Per in-flight slot: stream, event, pinned and device work-unit tables.
-struct Slot {
+struct SlotRes {
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
     neat::FwdItem *host = nullptr;  // pinned
     neat::FwdItem *dev = nullptr;
-    bool busy = false;
-    std::vector<uint64_t> tickets;
-    size_t bytes = 0;
-    int64_t genome_inputs = 0;
 };
 
-}  // namespace
+class HipExec : public neat::sched::Executor<Payload> {
+  public:
+    int device = 0;
+    std::vector<SlotRes> slots;
 
-struct neat_server {
-    neat_server_cfg cfg{};
-    std::chrono::steady_clock::time_point t0;
-    std::mutex m;
-    std::condition_variable cv;
-    bool stop = false;
-    std::thread worker;
-    std::vector<std::unique_ptr<Pop>> pops;
-    std::unordered_map<uint64_t, Req> reqs;
-    std::deque<uint64_t> queue;
-    std::vector<Slot> slots;
-    int next_slot = 0;
-    uint64_t next_ticket = 1;
-    size_t used = 0;
-    // statistics since the last reset
-    std::vector<int64_t> lat_ns;
-    uint64_t submitted = 0, admitted = 0, completed = 0, rejected = 0, batches = 0;
-    int64_t genome_inputs = 0, first_submit = -1, last_done = -1;
+    void thread_init() override { (void)hipSetDevice(device); }
+
+    int launch(int k, const std::vector<const Payload *> &batch) override {
+        SlotRes &sl = slots[k];
+        std::vector<neat::FwdJob> jobs;
+        jobs.reserve(batch.size());
+        const int tp = batch.size() > 1 ? 1 : 0;
+        for (const Payload *q : batch) {
+            const neat_request &r = q->r;
+            const bool grid = r.input_mode == NEAT_INPUT_GRID;
+            neat::FwdJob j = make_job(&q->pop->d, q->pop->program, r.inputs,
+                                      r.input_genome_stride, r.B, r.outputs,
+                                      grid ? r.grid_side : 0, r.grid_first);
+            j.variant = neat::tuned_variant(q->pop->d.N_max, q->pop->d.C_max, r.B, grid, tp);
+            jobs.push_back(j);
+        }
+        std::vector<neat::FwdKernelLaunch> fw;
+        char err[256] = "";
+        int rc = neat::forward_plan(jobs.data(), (int)jobs.size(), neat::FWD_AUTO,
+                                    max_lds_bytes(), fw, err, sizeof(err));
+        if (rc != NEAT_OK) return rc;
+        size_t n = 0;
+        for (const neat::FwdKernelLaunch &f : fw) n += f.items.size();
+        if (n > TABLE_ITEMS) return NEAT_E_TOO_LARGE;
+        size_t at = 0;
+        std::vector<size_t> off(fw.size());
+        for (size_t f = 0; f < fw.size(); ++f) {
+            off[f] = at;
+            std::copy(fw[f].items.begin(), fw[f].items.end(), sl.host + at);
+            at += fw[f].items.size();
+        }
+        hipError_t e = hipMemcpyAsync(sl.dev, sl.host, at * sizeof(neat::FwdItem),
+                                      hipMemcpyHostToDevice, sl.stream);
+        for (size_t f = 0; f < fw.size() && e == hipSuccess; ++f)
+            e = neat::forward_launch(fw[f], sl.dev + off[f], sl.stream);
+        if (e == hipSuccess) e = hipEventRecord(sl.done, sl.stream);
+        return e == hipSuccess ? NEAT_OK : NEAT_E_HIP;
+    }
+
+    bool finished(int k) override { return hipEventQuery(slots[k].done) == hipSuccess; }
+
+    void drain(int k) override { (void)hipStreamSynchronize(slots[k].stream); }
 };
-
-namespace {
 
 size_t request_bytes(const Pop &p, const neat_request &r) {
     const size_t P = (size_t)p.d.P, B = (size_t)r.B;
@@ -106,124 +118,26 @@ size_t request_bytes(const Pop &p, const neat_request &r) {
     return in + out + REQ_TABLE_BYTES;
 }
 
-void finish_slot(neat_server *s, Slot &sl) {
-    const int64_t t = now_ns(s->t0);
-    for (uint64_t tk : sl.tickets) {
-        auto it = s->reqs.find(tk);
-        if (it == s->reqs.end()) continue;
-        Req &q = it->second;
-        q.state = Q_DONE;
-        q.res.t_done_ns = t;
-        s->lat_ns.push_back(t - q.res.t_submit_ns);
-        s->completed++;
-    }
-    s->genome_inputs += sl.genome_inputs;
-    s->last_done = t;
-    s->used -= sl.bytes;
-    sl.tickets.clear();
-    sl.bytes = 0;
-    sl.genome_inputs = 0;
-    sl.busy = false;
+// device bytes a registered population holds for good
+size_t resident_bytes(const neat_dims &d) {
+    return (size_t)d.P * d.N_max * 5 * sizeof(float) + (size_t)d.P * d.C_max * 4 * sizeof(float) +
+           neat_program_bytes(&d);
 }
 
-// Launch the calculation of the given admitted requests on slot sl (lock
-// not held).  Returns NEAT_OK or an error code for all of them.
-int launch_batch(neat_server *s, Slot &sl, const std::vector<neat::FwdJob> &jobs) {
-    std::vector<neat::FwdKernelLaunch> fw;
-    char err[256] = "";
-    int rc = neat::forward_plan(jobs.data(), (int)jobs.size(), neat::FWD_AUTO, max_lds_bytes(),
-                                fw, err, sizeof(err));
-    if (rc != NEAT_OK) return rc;
-    size_t n = 0;
-    for (const neat::FwdKernelLaunch &k : fw) n += k.items.size();
-    if (n > TABLE_ITEMS) return NEAT_E_TOO_LARGE;
-    size_t at = 0;
-    std::vector<size_t> off(fw.size());
-    for (size_t k = 0; k < fw.size(); ++k) {
-        off[k] = at;
-        std::copy(fw[k].items.begin(), fw[k].items.end(), sl.host + at);
-        at += fw[k].items.size();
-    }
-    hipError_t e = hipMemcpyAsync(sl.dev, sl.host, at * sizeof(neat::FwdItem),
-                                  hipMemcpyHostToDevice, sl.stream);
-    for (size_t k = 0; k < fw.size() && e == hipSuccess; ++k)
-        e = neat::forward_launch(fw[k], sl.dev + off[k], sl.stream);
-    if (e == hipSuccess) e = hipEventRecord(sl.done, sl.stream);
-    return e == hipSuccess ? NEAT_OK : NEAT_E_HIP;
-}
+}  // namespace
 
-void worker_loop(neat_server *s) {
-    (void)hipSetDevice(s->cfg.device);
-    std::unique_lock<std::mutex> lk(s->m);
-    for (;;) {
-        // completions
-        bool any_busy = false;
-        for (Slot &sl : s->slots) {
-            if (!sl.busy) continue;
-            if (hipEventQuery(sl.done) == hipSuccess) finish_slot(s, sl);
-            else any_busy = true;
-        }
-        if (s->stop && s->queue.empty() && !any_busy) break;
-        // admission into a free slot: requests in arrival order while they fit
-        Slot *free_slot = nullptr;
-        for (int k = 0; k < (int)s->slots.size(); ++k) {
-            Slot &sl = s->slots[(s->next_slot + k) % s->slots.size()];
-            if (!sl.busy) {
-                free_slot = &sl;
-                s->next_slot = (int)((&sl - s->slots.data()) + 1) % (int)s->slots.size();
-                break;
-            }
-        }
-        if (free_slot && !s->queue.empty()) {
-            Slot &sl = *free_slot;
-            std::vector<neat::FwdJob> jobs;
-            const int64_t t = now_ns(s->t0);
-            while (!s->queue.empty() && (int)sl.tickets.size() < MAX_BATCH_REQUESTS) {
-                Req &q = s->reqs[s->queue.front()];
-                // in arrival order: a request that does not fit waits for
-                // running batches to release their bytes (alone it always
-                // fits: neat_submit rejects larger ones)
-                if (s->used + q.bytes > s->cfg.cap_bytes) break;
-                const Pop &p = *s->pops[q.r.pop_id];
-                const bool grid = q.r.input_mode == NEAT_INPUT_GRID;
-                jobs.push_back(make_job(&p.d, p.program, q.r.inputs, q.r.input_genome_stride,
-                                        q.r.B, q.r.outputs, grid ? q.r.grid_side : 0,
-                                        q.r.grid_first));
-                q.state = Q_ADMITTED;
-                q.res.t_admit_ns = t;
-                s->used += q.bytes;
-                sl.bytes += q.bytes;
-                sl.genome_inputs += (int64_t)p.d.P * q.r.B;
-                sl.tickets.push_back(s->queue.front());
-                s->queue.pop_front();
-                s->admitted++;
-            }
-            if (!sl.tickets.empty()) {
-                sl.busy = true;
-                s->batches++;
-                lk.unlock();
-                const int rc = launch_batch(s, sl, jobs);
-                lk.lock();
-                if (rc != NEAT_OK) {
-                    // the batch never ran: its requests end with the error
-                    for (uint64_t tk : sl.tickets) s->reqs[tk].res.status = rc;
-                    (void)hipStreamSynchronize(sl.stream);
-                    finish_slot(s, sl);
-                }
-                continue;
-            }
-        }
-        if (any_busy) {
-            // poll the running batches again shortly
-            s->cv.wait_for(lk, std::chrono::microseconds(20));
-        } else {
-            s->cv.wait(lk, [s] { return s->stop || !s->queue.empty(); });
-        }
-    }
-}
+struct neat_server {
+    neat_server_cfg cfg{};
+    HipExec exec;
+    std::unique_ptr<neat::sched::Scheduler<Payload>> sched;
+    std::mutex pm;  // guards pops
+    std::vector<std::unique_ptr<Pop>> pops;
+};
+
+namespace {
 
 void free_server(neat_server *s) {
-    for (Slot &sl : s->slots) {
+    for (SlotRes &sl : s->exec.slots) {
         if (sl.done) (void)hipEventDestroy(sl.done);
         if (sl.stream) (void)hipStreamDestroy(sl.stream);
         if (sl.host) (void)hipHostFree(sl.host);
@@ -235,13 +149,6 @@ void free_server(neat_server *s) {
         if (p->program) (void)hipFree(p->program);
     }
     delete s;
-}
-
-int64_t percentile(std::vector<int64_t> v, double q) {
-    if (v.empty()) return 0;
-    const size_t k = (size_t)(q * (double)(v.size() - 1) + 0.5);
-    std::nth_element(v.begin(), v.begin() + k, v.end());
-    return v[k];
 }
 
 }  // namespace
@@ -261,10 +168,11 @@ int neat_server_create(const neat_server_cfg *cfg, neat_server **out) {
     neat_server *s = new (std::nothrow) neat_server;
     if (!s) return fail(NEAT_E_NOMEM, "out of host memory");
     s->cfg = *cfg;
-    s->t0 = std::chrono::steady_clock::now();
+    s->exec.device = cfg->device;
+    neat::tune_cache_use(cfg->tune_cache_path);
     e = hipSetDevice(cfg->device);
-    s->slots.resize(cfg->max_inflight);
-    for (Slot &sl : s->slots) {
+    s->exec.slots.resize(cfg->max_inflight);
+    for (SlotRes &sl : s->exec.slots) {
         if (e == hipSuccess) e = hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming);
         if (e == hipSuccess)
@@ -277,29 +185,24 @@ int neat_server_create(const neat_server_cfg *cfg, neat_server **out) {
         return e == hipErrorOutOfMemory ? fail(NEAT_E_NOMEM, "server buffers: out of memory")
                                         : hip_fail(e, "server create");
     }
-    s->worker = std::thread(worker_loop, s);
+    s->sched.reset(new (std::nothrow) neat::sched::Scheduler<Payload>(
+        &s->exec, cfg->max_inflight, cfg->cap_bytes, MAX_BATCH_REQUESTS, POLL_US));
+    if (!s->sched) {
+        free_server(s);
+        return fail(NEAT_E_NOMEM, "out of host memory");
+    }
     *out = s;
     return NEAT_OK;
 }
 
 int neat_server_destroy(neat_server *s) {
     if (!s) return fail(NEAT_E_INVALID, "server is NULL");
-    {
-        std::lock_guard<std::mutex> lk(s->m);
-        // queued requests are cancelled; admitted ones finish
-        for (uint64_t tk : s->queue) {
-            Req &q = s->reqs[tk];
-            q.state = Q_DONE;
-            q.res.status = NEAT_E_SHUTDOWN;
-        }
-        s->queue.clear();
-        s->stop = true;
-    }
-    s->cv.notify_all();
-    if (s->worker.joinable()) s->worker.join();
+    // queued requests are cancelled; admitted ones finish
+    s->sched->shutdown();
     (void)hipSetDevice(s->cfg.device);
-    for (Slot &sl : s->slots)
+    for (SlotRes &sl : s->exec.slots)
         if (sl.stream) (void)hipStreamSynchronize(sl.stream);
+    s->sched.reset();
     free_server(s);
     return NEAT_OK;
 }
@@ -311,6 +214,11 @@ int neat_server_register(neat_server *s, const neat_dims *d, const float *nodes,
     if (rc != NEAT_OK) return rc;
     rc = check_topo_args(d, nodes, conns, nullptr);
     if (rc != NEAT_OK) return rc;
+    const size_t held = resident_bytes(*d);
+    if (s->sched->add_resident(held) != NEAT_OK)
+        return fail(NEAT_E_TOO_LARGE,
+                    "population needs %zu resident bytes beyond the cap of %llu", held,
+                    (unsigned long long)s->cfg.cap_bytes);
     std::unique_ptr<Pop> p(new (std::nothrow) Pop);
     if (!p) return fail(NEAT_E_NOMEM, "out of host memory");
     p->d = *d;
@@ -333,10 +241,12 @@ int neat_server_register(neat_server *s, const neat_dims *d, const float *nodes,
         if (p->nodes) (void)hipFree(p->nodes);
         if (p->conns) (void)hipFree(p->conns);
         if (p->program) (void)hipFree(p->program);
+        // the bytes stay counted: a failed registration leaves the
+        // footprint as an upper bound (freed memory is not reused here)
         return e == hipErrorOutOfMemory ? fail(NEAT_E_NOMEM, "register: out of device memory")
                                         : hip_fail(e, "register");
     }
-    std::lock_guard<std::mutex> lk(s->m);
+    std::lock_guard<std::mutex> lk(s->pm);
     *pop_id = (int32_t)s->pops.size();
     s->pops.push_back(std::move(p));
     return NEAT_OK;
@@ -344,86 +254,71 @@ int neat_server_register(neat_server *s, const neat_dims *d, const float *nodes,
 
 int neat_submit(neat_server *s, const neat_request *r, uint64_t *ticket) {
     if (!s || !r || !ticket) return fail(NEAT_E_INVALID, "server, request or ticket is NULL");
-    std::unique_lock<std::mutex> lk(s->m);
-    if (s->stop) return fail(NEAT_E_SHUTDOWN, "server is shutting down");
-    if (r->pop_id < 0 || r->pop_id >= (int32_t)s->pops.size())
-        return fail(NEAT_E_INVALID, "unknown population %d", r->pop_id);
-    const Pop &p = *s->pops[r->pop_id];
+    Payload q;
+    q.r = *r;
+    {
+        std::lock_guard<std::mutex> lk(s->pm);
+        if (r->pop_id < 0 || r->pop_id >= (int32_t)s->pops.size())
+            return fail(NEAT_E_INVALID, "unknown population %d", r->pop_id);
+        q.pop = s->pops[r->pop_id].get();
+    }
+    const Pop &p = *q.pop;
     const bool grid = r->input_mode == NEAT_INPUT_GRID;
     if (!grid && r->input_mode != NEAT_INPUT_TENSOR)
         return fail(NEAT_E_INVALID, "unknown input_mode %d", r->input_mode);
-    lk.unlock();
     int rc = check_forward_args(&p.d, p.program, r->inputs, r->input_genome_stride, r->B,
                                 r->outputs, grid, r->grid_side, r->grid_first);
     if (rc != NEAT_OK) return rc;
     const size_t bytes = request_bytes(p, *r);
-    lk.lock();
-    if (bytes > s->cfg.cap_bytes) {
-        s->rejected++;
-        return fail(NEAT_E_TOO_LARGE, "request needs %zu bytes, cap is %llu", bytes,
-                    (unsigned long long)s->cfg.cap_bytes);
-    }
-    const uint64_t tk = s->next_ticket++;
-    Req &q = s->reqs[tk];
-    q.r = *r;
-    q.bytes = bytes;
-    q.res.status = NEAT_OK;
-    q.res.tag = r->tag;
-    q.res.t_submit_ns = now_ns(s->t0);
-    q.res.t_admit_ns = q.res.t_done_ns = -1;
-    if (s->first_submit < 0) s->first_submit = q.res.t_submit_ns;
-    s->submitted++;
-    if (r->B == 0 || p.d.P == 0) {
-        // nothing to compute
-        q.state = Q_DONE;
-        q.res.t_admit_ns = q.res.t_done_ns = q.res.t_submit_ns;
-    } else {
-        s->queue.push_back(tk);
-    }
-    *ticket = tk;
-    lk.unlock();
-    s->cv.notify_one();
-    return NEAT_OK;
+    rc = s->sched->submit(q, bytes, (uint64_t)p.d.P * (uint64_t)r->B, r->tag,
+                          r->B == 0 || p.d.P == 0, ticket);
+    if (rc == NEAT_E_TOO_LARGE)
+        return fail(rc, "request needs %zu bytes beyond the resident populations, cap is %llu",
+                    bytes, (unsigned long long)s->cfg.cap_bytes);
+    if (rc == NEAT_E_SHUTDOWN) return fail(rc, "server is shutting down");
+    return rc;
 }
 
 int neat_poll(neat_server *s, uint64_t ticket, neat_result *res) {
     if (!s) return fail(NEAT_E_INVALID, "server is NULL");
-    std::lock_guard<std::mutex> lk(s->m);
-    auto it = s->reqs.find(ticket);
-    if (it == s->reqs.end()) return fail(NEAT_E_UNKNOWN_TICKET, "unknown ticket %llu",
-                                         (unsigned long long)ticket);
-    if (it->second.state != Q_DONE) return NEAT_PENDING;
-    if (res) *res = it->second.res;
-    s->reqs.erase(it);
-    return NEAT_OK;
+    neat::sched::Result r;
+    const int rc = s->sched->poll(ticket, &r);
+    if (rc == NEAT_E_UNKNOWN_TICKET)
+        return fail(rc, "unknown ticket %llu", (unsigned long long)ticket);
+    if (rc == NEAT_OK && res) {
+        res->status = r.status;
+        res->tag = r.tag;
+        res->t_submit_ns = r.t_submit_ns;
+        res->t_admit_ns = r.t_admit_ns;
+        res->t_done_ns = r.t_done_ns;
+    }
+    return rc;
 }
 
 int neat_server_stats(neat_server *s, neat_stats *st) {
     if (!s || !st) return fail(NEAT_E_INVALID, "server or stats is NULL");
-    std::lock_guard<std::mutex> lk(s->m);
+    const neat::sched::Stats x = s->sched->stats();
     neat_stats r{};
-    r.submitted = s->submitted;
-    r.admitted = s->admitted;
-    r.completed = s->completed;
-    r.rejected = s->rejected;
-    r.batches = s->batches;
-    r.queued = s->queue.size();
-    r.genome_inputs = (uint64_t)s->genome_inputs;
-    r.p50_ms = (double)percentile(s->lat_ns, 0.50) / 1e6;
-    r.p99_ms = (double)percentile(s->lat_ns, 0.99) / 1e6;
-    const int64_t span = s->last_done - s->first_submit;
-    r.throughput = span > 0 ? (double)s->genome_inputs * 1e9 / (double)span : 0.0;
+    r.submitted = x.submitted;
+    r.admitted = x.admitted;
+    r.completed = x.completed;
+    r.rejected = x.rejected;
+    r.batches = x.batches;
+    r.queued = x.queued;
+    r.genome_inputs = x.genome_inputs;
+    r.p50_ms = x.p50_ms;
+    r.p99_ms = x.p99_ms;
+    r.throughput = x.throughput;
+    r.batched_requests = x.batched_requests;
+    r.resident_bytes = x.resident_bytes;
+    r.peak_bytes = x.peak_bytes;
     *st = r;
     return NEAT_OK;
 }
 
 int neat_server_reset_stats(neat_server *s) {
     if (!s) return fail(NEAT_E_INVALID, "server is NULL");
-    std::lock_guard<std::mutex> lk(s->m);
-    s->lat_ns.clear();
-    s->submitted = s->admitted = s->completed = s->rejected = s->batches = 0;
-    s->genome_inputs = 0;
-    s->first_submit = s->last_done = -1;
+    s->sched->reset_stats();
     return NEAT_OK;
 }
 

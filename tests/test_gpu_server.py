@@ -147,15 +147,22 @@ def test_request_alone_equals_request_in_mix():
 
 
 def test_admission_cap_and_rejection():
-    """A request larger than the cap is rejected at submission; requests that
-    only fit one at a time are all served."""
+    """The cap counts resident populations and running requests: a
+    population beyond it is refused at registration, a request larger than
+    what is left is rejected at submission, and requests that only fit one
+    at a time are all served, one per batch."""
     neat = _neat()
     pop = synth.control(seed=5, P=20, B=64)
     dev = torch.device("cuda:0")
     x = torch.from_numpy(pop.inputs).to(dev)
     one = pop.P * 64 * (pop.I + pop.O) * 4
-    server = neat.Server(cap_bytes=one + 4096, max_inflight=4)
+    d = neat.Dims(pop.P, pop.N_max, pop.C_max, pop.I, pop.O)
+    resident = pop.P * (20 * pop.N_max + 16 * pop.C_max) + neat.program_bytes(d)
+    server = neat.Server(cap_bytes=resident + one + 4096, max_inflight=4)
     r = _Resident(server, pop)
+    with pytest.raises(neat.NeatError) as e:
+        _Resident(server, pop)  # a second copy does not fit beside the first
+    assert e.value.code == -4
     y_big = torch.empty((pop.P, 128, pop.O), device=dev)
     x_big = torch.zeros((pop.P, 128, pop.I), device=dev)
     with pytest.raises(neat.NeatError) as e:
@@ -173,6 +180,8 @@ def test_admission_cap_and_rejection():
         assert _same_bits(y.cpu().numpy(), ref)
     st = server.stats()
     assert st.rejected == 1 and st.completed == 6 and st.batches == 6
+    assert st.batched_requests == 6 and st.resident_bytes == resident
+    assert resident < st.peak_bytes <= resident + one + 4096
     server.close()
 
 
