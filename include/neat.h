@@ -169,11 +169,17 @@ int neat_forward(const neat_dims *dims, const void *program, const float *inputs
                             the tile's samples at once, one (node, sample) per lane,
                             values in LDS (grid queries and recurrent calls run
                             NEAT_FWD_AUTO instead) */
+#define NEAT_FWD_SEG 6   /* the segment mapping: as NEAT_FWD_LVL, but a level's
+                            in-edges x the tile's samples are spread over the lanes
+                            and combined by a segmented reduction per destination
+                            (sum, product, maximum); its sums and products are
+                            combined in a tree, so they round differently from the
+                            other variants (within the same error bound) */
 
 /*
  * neat_forward with an explicit variant (NEAT_FWD_*); same arguments.  All
- * variants run the same operations in the same order and give identical
- * bits.  Errors as neat_forward, plus NEAT_E_INVALID for an unknown variant
+ * variants but NEAT_FWD_SEG run the same operations in the same order and
+ * give identical bits.  Errors as neat_forward, plus NEAT_E_INVALID for an unknown variant
  * and NEAT_E_TOO_LARGE when the LDS-row store cannot fit one wave's values.
  * Populations with N_max > 222 (the only ones whose genomes can need that
  * store) run it with tiles of 64 samples while 256 (I + N_max + 2) bytes fit
@@ -189,8 +195,9 @@ int neat_forward_ex(const neat_dims *dims, const void *program, const float *inp
  * Autotuner of the calculation stage (not a passage of the paper: a tuning
  * aid for the population-wide calculation of Section 3.3).  Times the
  * NEAT_TUNE_CANDIDATES mappings -- NEAT_FWD_REG, NEAT_FWD_REG2, NEAT_FWD_LDS
- * (lane per sample, three value stores) and NEAT_FWD_LVL (lanes over a
- * level's nodes) -- on the caller's buffers, one warm-up and `reps`
+ * (lane per sample, three value stores), NEAT_FWD_LVL (lanes over a level's
+ * nodes) and NEAT_FWD_SEG (lanes over a level's in-edges, segmented
+ * reduction) -- on the caller's buffers, one warm-up and `reps`
  * launches each, with HIP events on `stream`, in two ways: the population
  * alone (latency), and as many copies of it in one launch as fill the GPU
  * (about 16 waves per CU, at most 64 copies; throughput per copy).  It
@@ -201,26 +208,28 @@ int neat_forward_ex(const neat_dims *dims, const void *program, const float *inp
  * latency winner; neat_forward_batch and neat_forward_batch_noalloc (per
  * item), whose items share the GPU, use the throughput winner; both fall back
  * to NEAT_FWD_AUTO for buckets never tuned.  A recorded batch plan is
- * rebuilt when a table has changed since it was recorded.  Every variant
- * gives identical bits, so tuning changes no result.
+ * rebuilt when a table has changed since it was recorded.  Tuning changes
+ * no result bit unless it records NEAT_FWD_SEG, whose sums and products
+ * round in a different order (within the parity rule).
  * With the environment variable NEAT_TUNE_CACHE naming a file (or a server
  * created with tune_cache_path), the table is read from that file on first
  * use and rewritten there after every tuning ("N_max C_max B grid variant"
  * lines of bucket values); a file that cannot be read or written is
  * skipped.
- *   arguments as neat_forward_ex (outputs are overwritten);
+ *   arguments as neat_forward_ex (outputs are overwritten; they end with the
+ *                latency winner's result);
  *   reps         launches timed per variant, 1..1000
  *   variant_out  (host, written) the latency winner; NEAT_FWD_AUTO when
  *                P = 0 or B = 0 (nothing is timed or recorded)
  *   ms_out       [2 * NEAT_TUNE_CANDIDATES] (host, written, nullable): mean
- *                ms per launch of REG, REG2, LDS and LVL alone, then mean ms
- *                per copy of the same four on a full GPU (-1 when untimed)
+ *                ms per launch of REG, REG2, LDS, LVL and SEG alone, then mean
+ *                ms per copy of the same five on a full GPU (-1 when untimed)
  * Synchronizes `stream`; the table is shared by every thread of the
  * process (guarded by a mutex).
  * Errors: as neat_forward_ex; NEAT_E_INVALID for reps or a NULL
  * variant_out; NEAT_E_HIP.
  */
-#define NEAT_TUNE_CANDIDATES 4
+#define NEAT_TUNE_CANDIDATES 5
 int neat_autotune_forward(const neat_dims *dims, const void *program, const float *inputs,
                           int64_t input_genome_stride, int32_t B, float *outputs, int32_t reps,
                           int32_t *variant_out, float *ms_out, void *stream);

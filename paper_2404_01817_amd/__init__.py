@@ -11,7 +11,8 @@ from __future__ import annotations
 import ctypes
 from typing import Optional, Tuple
 
-from ._lib import (FWD_AUTO, FWD_LDS, FWD_LVL, FWD_REG, FWD_REG2, FWD_TUNED, TUNE_CANDIDATES,
+from ._lib import (FWD_AUTO, FWD_LDS, FWD_LVL, FWD_REG, FWD_REG2, FWD_SEG, FWD_TUNED,
+                   TUNE_CANDIDATES,
                    INPUT_GRID, INPUT_TENSOR,
                    BatchItem, Dims, NeatError, Request, Result, ServerCfg, Stats, check, lib)
 
@@ -129,8 +130,8 @@ def autotune_forward(dims: Dims, program, inputs, B: int, outputs=None, reps: in
                      stream=None):
     """Time the forward variants on these buffers and record the fastest for
     the call's bucket (neat_autotune_forward); returns (latency winner, [ms
-    of FWD_REG, FWD_REG2, FWD_LDS, FWD_LVL alone, then per copy on a full
-    GPU]).  Later calls with variant=FWD_TUNED, and
+    of FWD_REG, FWD_REG2, FWD_LDS, FWD_LVL, FWD_SEG alone, then per copy on
+    a full GPU]).  Later calls with variant=FWD_TUNED, and
     batches, use the recorded variant."""
     stride, outputs = _io(dims, inputs, B, False, outputs)
     v = ctypes.c_int32(0)

@@ -15,8 +15,8 @@ LIB_PATH = os.path.join(PKG, "libneat.so")
 
 NEAT_OK = 0
 NEAT_PENDING = 1
-FWD_AUTO, FWD_REG, FWD_LDS, FWD_REG2, FWD_TUNED, FWD_LVL = 0, 1, 2, 3, 4, 5
-TUNE_CANDIDATES = 4  # REG, REG2, LDS, LVL
+FWD_AUTO, FWD_REG, FWD_LDS, FWD_REG2, FWD_TUNED, FWD_LVL, FWD_SEG = 0, 1, 2, 3, 4, 5, 6
+TUNE_CANDIDATES = 5  # REG, REG2, LDS, LVL, SEG
 
 
 class NeatError(RuntimeError):

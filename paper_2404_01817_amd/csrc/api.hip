@@ -153,7 +153,7 @@ unsigned long long tune_key(int N, int C, int B, int grid) {
 }
 bool valid_tuned(int v) {
     return v == NEAT_FWD_AUTO || v == NEAT_FWD_REG || v == NEAT_FWD_LDS || v == NEAT_FWD_REG2 ||
-           v == NEAT_FWD_LVL;
+           v == NEAT_FWD_LVL || v == NEAT_FWD_SEG;
 }
 
 // Merge the cache file's entries into the table (caller holds the lock).
@@ -269,7 +269,7 @@ static int forward_common(const neat_dims *d, const void *program, const float *
                           int32_t side, int64_t first, void *stream) {
     int rc = check_dims(d);
     if (rc != NEAT_OK) return rc;
-    if (variant < NEAT_FWD_AUTO || variant > NEAT_FWD_LVL)
+    if (variant < NEAT_FWD_AUTO || variant > NEAT_FWD_SEG)
         return fail(NEAT_E_INVALID, "unknown forward variant %d", variant);
     if (variant == NEAT_FWD_TUNED)
         variant = neat::tuned_variant(d->N_max, d->C_max, B, grid, 0);
@@ -362,7 +362,8 @@ int neat_autotune_forward(const neat_dims *d, const void *program, const float *
     rc = check_forward_args(d, program, inputs, input_genome_stride, B, outputs, false, 0, 0);
     if (rc != NEAT_OK) return rc;
     constexpr int NC = NEAT_TUNE_CANDIDATES;
-    const int cand[NC] = {NEAT_FWD_REG, NEAT_FWD_REG2, NEAT_FWD_LDS, NEAT_FWD_LVL};
+    const int cand[NC] = {NEAT_FWD_REG, NEAT_FWD_REG2, NEAT_FWD_LDS, NEAT_FWD_LVL,
+                          NEAT_FWD_SEG};
     float ms[2 * NC];
     for (float &m : ms) m = -1.0f;
     int best = NEAT_FWD_AUTO, best_tp = NEAT_FWD_AUTO;
@@ -402,6 +403,12 @@ int neat_autotune_forward(const neat_dims *d, const void *program, const float *
         slot = best;
         slot_tp = best_tp;
         tune_write_locked();
+    }
+    // the outputs end with the recorded latency winner's result
+    if (d->P > 0 && B > 0) {
+        rc = forward_common(d, program, inputs, input_genome_stride, B, outputs, best, false, 0, 0,
+                            stream);
+        if (rc != NEAT_OK) return rc;
     }
     *variant_out = best;
     if (ms_out)

@@ -659,6 +659,164 @@ __device__ __forceinline__ void forward_unit_lvl(citem_t *it, int g, int chunk, 
     }
 }
 
+// ---------------------------------------------------------------- segments
+// Mapping "lanes over a level's in-edges" (FWD_SEG).  As in the level
+// mapping, a wave takes a tile of BW = 2^sh samples and walks the levels,
+// values in LDS at v[s * BW + j].  Here a step spreads the level's
+// in-edges over the lanes: R = 64 / BW rows of edges, each row holding one
+// edge for the tile's BW samples (lane = row * BW + sample).  The level's
+// edges are laid out destination after destination (a node's edges in its
+// record's order, a node without in-edges contributing one edge w = 1 from
+// the constant 0), so every destination owns a run of consecutive rows: a
+// segment.  Each lane forms w * v[src] and a segmented inclusive scan over
+// the rows (Hillis-Steele, partner rows 1, 2, 4, ... back in the same
+// segment) combines the terms with the destination's aggregation: sum,
+// product or the NaN-propagating maximum (mean and min are folded into the
+// response, as in every store).  A segment cut by the end of a step passes
+// its partial result to the next step's first row (carry).  The lane
+// holding a segment's last edge applies bias, response and activation and
+// writes the value once every lane of the step has read its sources.  The
+// terms are combined in a tree rather than a chain, so sums and products
+// round differently from the other mappings (within the oracle's bound,
+// which holds for any order); maxima are exact.
+__device__ __forceinline__ float seg_combine(int acls, float early, float late) {
+    return acls == ACLS_PROD ? early * late
+                             : (acls == ACLS_MAX ? maximum3(early, late, late) : early + late);
+}
+
+// exclusive scan of one int per lane across the wave; *total = the sum
+__device__ __forceinline__ int wave_excl_scan(int v, int *total) {
+    const int lane = (int)(threadIdx.x & (WAVE - 1));
+    int x = v;
+#pragma unroll
+    for (int d = 1; d < WAVE; d <<= 1) {
+        const int y = __shfl_up(x, d, WAVE);
+        if (lane >= d) x += y;
+    }
+    *total = __shfl(x, WAVE - 1, WAVE);
+    return x - v;
+}
+
+__device__ __forceinline__ void forward_unit_seg(citem_t *it, int g, int chunk, float *v) {
+    int t0, t1;
+    if (!wave_tiles(it, chunk, &t0, &t1)) return;
+    const int lane = (int)(threadIdx.x & (WAVE - 1));
+    const int sh = it->lvl_sh, BW = 1 << sh, R = WAVE >> sh;
+    const int N = it->N, C = it->C, I = it->I, O = it->O, B = it->B;
+    cprog_t *prog = (cprog_t *)(it->prog + (size_t)g * it->prog_words);
+    gint_t *gp = (gint_t *)(it->prog + (size_t)g * it->prog_words);
+    float *out_g = it->outputs + (size_t)g * B * O;
+    if (prog[HDR_STATUS] != 0) {
+        fill_nan(out_g, t0 * BW, min(B, t1 * BW), O);
+        return;
+    }
+    const float *in_g = it->inputs + (size_t)g * it->gstride;
+    const int nlev = prog[HDR_NLEVELS];
+    const int zs = zero_slot(prog[HDR_CLASS], N);
+    cprog_t *lvl = prog + lvl_off(N, C, O);
+    gint_t *ebeg = gp + ebeg_off(N, C, O);
+    gint_t *edges = gp + edge_off(N, O);
+    gint_t *recs = gp + rec_off(O);
+    // the rows of v, then each level's edge offsets by node (N + 1 ints)
+    int *eoff = (int *)(v + ((size_t)it->lvl_rows << sh));
+    const int row = lane >> sh, j = lane & (BW - 1);
+    for (int t = t0; t < t1; ++t) {
+        const int s0 = t * BW, nb = min(BW, B - s0);
+        const float *x = in_g + (size_t)s0 * I;
+        for (int e = lane; e < BW * I; e += WAVE) {
+            const int jj = e / I, i = e - jj * I;
+            v[(i << sh) + jj] = jj < nb ? x[e] : 0.0f;
+        }
+        if (lane < BW) {
+            v[(zs << sh) + lane] = 0.0f;
+            v[((zs + 1) << sh) + lane] = 1.0f;
+        }
+        for (int l = 0; l < nlev; ++l) {
+            const int k0 = max(lvl[l], I) - I, k1 = lvl[l + 1] - I, nl = k1 - k0;
+            if (nl <= 0) continue;
+            // edges per node (at least one) and their offsets
+            int base = 0;
+            for (int c = 0; c < nl; c += WAVE) {
+                int ec = 0;
+                if (c + lane < nl) {
+                    const int pairs =
+                        recs[REC_WORDS * (k0 + c + lane) + REC_NPAIRS] & REC_NPAIRS_MASK;
+                    ec = pairs > 0 ? 2 * pairs : 1;
+                }
+                int tot;
+                const int ex = wave_excl_scan(ec, &tot);
+                if (c + lane < nl) eoff[c + lane] = base + ex;
+                base += tot;
+            }
+            if (lane == 0) eoff[nl] = base;
+            wave_lds_sync();
+            float carry = 0.0f;
+            for (int eb = 0; eb < base; eb += R) {
+                const int e = eb + row;
+                const bool active = e < base;
+                int node = 0, q = 0, ec = 1, acls = ACLS_SUM;
+                float xv = 0.0f;
+                unsigned code = 0;
+                float bias = 0.0f, resp = 0.0f;
+                if (active) {
+                    // the node owning edge e: the last offset <= e
+                    int lo = 0, hi = nl - 1;
+                    while (lo < hi) {
+                        const int mid = (lo + hi + 1) >> 1;
+                        if (eoff[mid] <= e) lo = mid;
+                        else hi = mid - 1;
+                    }
+                    node = lo;
+                    q = e - eoff[lo];
+                    ec = eoff[lo + 1] - eoff[lo];
+                    const int k = k0 + node;
+                    gint_t *r = recs + REC_WORDS * k;
+                    code = (unsigned)r[REC_CODE];
+                    bias = fbits(r[REC_BIAS]);
+                    resp = fbits(r[REC_RESP]);
+                    const unsigned np = (unsigned)r[REC_NPAIRS];
+                    const int pairs = (int)(np & (unsigned)REC_NPAIRS_MASK);
+                    acls = slot_class((int)(np >> REC_FIELD_SHIFT));
+                    int src = zs;
+                    float w = 1.0f;
+                    if (pairs > 0) {
+                        gint_t *ew = q < 2 * REC_INLINE_PAIRS
+                                         ? r + REC_PAIRS + 2 * q
+                                         : edges + EDGE_WORDS * (ebeg[k] + q - 2 * REC_INLINE_PAIRS);
+                        src = ew[0];
+                        w = fbits(ew[1]);
+                    }
+                    xv = v[(src << sh) + j] * w;
+                    // a segment begun in an earlier step continues from its carry
+                    if (row == 0 && q > 0) xv = seg_combine(acls, carry, xv);
+                }
+                // segmented inclusive scan over the rows (same sample)
+#pragma unroll
+                for (int d = 1; d < WAVE; d <<= 1) {
+                    if (d >= R) break;
+                    const float y = __shfl(xv, lane - d * BW >= 0 ? lane - d * BW : lane, WAVE);
+                    if (active && row >= d && q >= d) xv = seg_combine(acls, y, xv);
+                }
+                carry = __shfl(xv, (R - 1) * BW + j, WAVE);
+                const bool tail = active && q == ec - 1;
+                float yv = 0.0f;
+                if (tail)
+                    yv = activation((int)(code >> REC_FIELD_SHIFT), fmaf(resp, xv, bias));
+                // every lane of the step has read its sources
+                wave_lds_sync();
+                if (tail) v[((int)(code & (unsigned)REC_DST_MASK) << sh) + j] = yv;
+            }
+            wave_lds_sync();
+        }
+        float *o_t = out_g + (size_t)s0 * O;
+        for (int e = lane; e < nb * O; e += WAVE) {
+            const int jj = e / O, o = e - jj * O;
+            __builtin_nontemporal_store(v[(prog[out_off() + o] << sh) + jj], o_t + e);
+        }
+        wave_lds_sync();
+    }
+}
+
 // ---------------------------------------------------------------- recurrent
 // Recurrent networks (read as K synchronous sweeps; the program comes from
 // the recurrent transformation: records in key order, one slot per node).
@@ -749,6 +907,8 @@ __device__ __forceinline__ void run_unit(long long u, float *wave_area) {
     }
     if constexpr (K == KIND_LVL) {
         forward_unit_lvl(it, g, chunk, wave_area);
+    } else if constexpr (K == KIND_SEG) {
+        forward_unit_seg(it, g, chunk, wave_area);
     } else if constexpr (K == KIND_LDS) {
         LdsStore v;
         v.col = wave_area + L->stage_floats + (threadIdx.x & (WAVE - 1));
@@ -827,7 +987,7 @@ bool lds_kind(int kind) { return kind == KIND_LDS || kind == KIND_LDS32; }
 // kernel of class c under a variant
 int kind_of(int variant, int cls, int B) {
     if (variant == FWD_LDS) return KIND_LDS;
-    if (variant == FWD_LVL) variant = FWD_AUTO;  // grid and recurrent items
+    if (variant == FWD_LVL || variant == FWD_SEG) variant = FWD_AUTO;  // grid, recurrent items
     switch (cls) {
     case CLS_R64:
         if (variant == FWD_REG2 || (variant == FWD_AUTO && B > WAVE)) return KIND_R64X2;
@@ -842,7 +1002,7 @@ int kind_of(int variant, int cls, int B) {
 
 const char *kind_name(int kind) {
     static const char *names[] = {"r64", "r64x2", "r128", "r224", "lds", "r64rec", "lds32",
-                                  "lvl"};
+                                  "lvl", "seg"};
     return kind >= 0 && kind < N_KINDS ? names[kind] : "?";
 }
 
@@ -865,14 +1025,18 @@ int forward_plan(const FwdJob *jobs, int n, int variant, size_t max_lds,
         if (J.P == 0 || J.B == 0) continue;
         const int variant = J.variant >= 0 ? J.variant : plan_variant;
         const int top = max_class(J.N);
-        if (variant == FWD_LVL && !J.side && !J.recurrent) {
-            // the level mapping: every genome, one launch over all items;
-            // the widest power-of-two tile of samples (<= 64, <= B rounded
-            // up) whose values fit a wave's LDS budget
+        if ((variant == FWD_LVL || variant == FWD_SEG) && !J.side && !J.recurrent) {
+            // the level and segment mappings: every genome, one launch per
+            // mapping over all items; the widest power-of-two tile of
+            // samples (<= 64, <= B rounded up) whose values fit a wave's
+            // LDS budget (the segment mapping also keeps N_max + 1 edge
+            // offsets)
+            const bool seg = variant == FWD_SEG;
             const int rows = class_slots(top, J.N);
+            const size_t extra = seg ? sizeof(int) * (size_t)(J.N + 1) : 0;
             int sh = 0;
             while (sh < 6 && (1 << sh) < J.B &&
-                   sizeof(float) * (size_t)rows * (2u << sh) <= lvl_wave_bytes())
+                   sizeof(float) * (size_t)rows * (2u << sh) + extra <= lvl_wave_bytes())
                 ++sh;
             FwdItem it{};
             it.prog = J.prog;
@@ -884,11 +1048,12 @@ int forward_plan(const FwdJob *jobs, int n, int variant, size_t max_lds,
             it.P = J.P, it.N = J.N, it.C = J.C, it.I = J.I, it.O = J.O, it.B = J.B;
             it.prog_words = prog_words(J.N, J.C, J.O);
             it.lvl_sh = sh;
+            it.lvl_rows = rows;
             it.tiles = (J.B + (1 << sh) - 1) >> sh;
             it.chunks = choose_chunks(J.P, it.tiles, &it.tpw);
-            const int x = 2 * KIND_LVL;
+            const int x = 2 * (seg ? KIND_SEG : KIND_LVL);
             k[x].items.push_back(it);
-            rows_max[x] = std::max(rows_max[x], rows << sh);
+            rows_max[x] = std::max(rows_max[x], (rows << sh) + (seg ? J.N + 1 : 0));
             continue;
         }
         // FWD_LDS takes every genome in one pass over all genomes; the other
@@ -933,7 +1098,7 @@ int forward_plan(const FwdJob *jobs, int n, int variant, size_t max_lds,
         FwdKernelLaunch &K = k[x];
         const int kind = K.kind;
         if (K.items.empty()) continue;
-        const size_t rows = kind == KIND_LVL ? (size_t)rows_max[x]
+        const size_t rows = (kind == KIND_LVL || kind == KIND_SEG) ? (size_t)rows_max[x]
                             : lds_kind(kind) ? (size_t)rows_max[x] * tile_samples(kind)
                                              : (size_t)ostage_max[x];
         const size_t wave_floats = (size_t)stage_max[x] + rows;
@@ -961,7 +1126,7 @@ int forward_plan(const FwdJob *jobs, int n, int variant, size_t max_lds,
         K.lds = wave_bytes * waves;
         // the LDS store limits the workgroups a CU holds: loop over units with
         // a grid of a few per CU instead of one workgroup per unit
-        const long long cap = (lds_kind(kind) || kind == KIND_LVL)
+        const long long cap = (lds_kind(kind) || kind == KIND_LVL || kind == KIND_SEG)
                                   ? 256ll * 2 * std::max<long long>(1, (long long)(163840 / K.lds))
                                   : (1ll << 31) - 1;
         K.args.persistent = groups > cap ? 1 : 0;
@@ -1021,6 +1186,7 @@ hipError_t forward_launch(const FwdKernelLaunch &k, const FwdItem *dev_items, hi
     case KIND_R64REC: NEAT_LAUNCH2(KIND_R64REC, false) break;
     case KIND_LDS32: NEAT_LAUNCH(KIND_LDS32) break;
     case KIND_LVL: NEAT_LAUNCH2(KIND_LVL, false) break;
+    case KIND_SEG: NEAT_LAUNCH2(KIND_SEG, false) break;
     default: NEAT_LAUNCH(KIND_LDS) break;
     }
 #undef NEAT_LAUNCH

@@ -49,17 +49,18 @@ constexpr int FWD_REG = 1;   // registers, one sample per lane (LDS rows for the
 constexpr int FWD_LDS = 2;   // every genome in LDS rows
 constexpr int FWD_REG2 = 3;  // as FWD_REG, R64 genomes two samples per lane
 constexpr int FWD_LVL = 5;   // lanes over a level's nodes x a tile of samples (values in LDS)
+constexpr int FWD_SEG = 6;   // lanes over a level's in-edges x a tile, segmented reduction
 
 // Forward kernels, one per value store.
 // KIND_R64REC: the recurrent calculation (K synchronous sweeps) with the
 // 64-slot register store, for populations of N_max <= 62.  KIND_LDS32: the
 // LDS-row store with half-wave tiles (32 samples), for genomes whose rows
 // do not fit in LDS with 64 columns.
-// KIND_LVL: the level mapping (FWD_LVL), every genome of an item, tiles of
-// 2^lvl_sh samples.
+// KIND_LVL / KIND_SEG: the level and segment mappings (FWD_LVL, FWD_SEG),
+// every genome of an item, tiles of 2^lvl_sh samples.
 enum FwdKind {
     KIND_R64 = 0, KIND_R64X2, KIND_R128, KIND_R224, KIND_LDS, KIND_R64REC, KIND_LDS32, KIND_LVL,
-    N_KINDS
+    KIND_SEG, N_KINDS
 };
 constexpr int FWD_MAX_WAVES = 4;  // waves per workgroup
 
@@ -90,8 +91,9 @@ struct FwdItem {
     int P, N, I, O, B, side, vec4, cls;
     int tiles, tpw, chunks, prog_words;
     int sweeps;  // recurrent kernel: sweeps per sample
-    int C;       // C_max (program layout)
-    int lvl_sh;  // level mapping: log2 of the samples per tile
+    int C;         // C_max (program layout)
+    int lvl_sh;    // level and segment mappings: log2 of the samples per tile
+    int lvl_rows;  // segment mapping: value rows before the edge offsets
 };
 
 // Kernel argument: one item inline, or a device table of items.

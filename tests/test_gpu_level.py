@@ -1,8 +1,9 @@
 """GPU: the level mapping (NEAT_FWD_LVL, lanes over a level's nodes x a tile
-of samples) against the lane-per-sample stores bit for bit and against the
-oracle within the parity rule, over every slot class, aggregation and
-activation, tile widths from 1 to 64 samples, ragged tiles and rejected
-genomes."""
+of samples) against the lane-per-sample stores bit for bit, and the segment
+mapping (NEAT_FWD_SEG, lanes over a level's in-edges, segmented reduction)
+against the oracle; both within the parity rule, over every slot class,
+aggregation and activation, tile widths from 1 to 64 samples, ragged tiles,
+long in-edge lists and rejected genomes."""
 from __future__ import annotations
 
 import numpy as np
@@ -63,6 +64,11 @@ def test_level_mapping_matches_stores_and_oracle(P, N, B):
     assert _same_bits(y, ref)
     y64, beta = oracle.forward(pop.nodes, pop.conns, pop.inputs, pop.I, pop.O)
     assert_parity(y, y64, beta, "lvl P%d N%d B%d" % (P, N, B))
+    ys = _run(pop, neat.FWD_SEG)
+    assert_parity(ys, y64, beta, "seg P%d N%d B%d" % (P, N, B))
+    # maxima and minima are exact in any order: those outputs' nodes aside,
+    # the two mappings differ only by rounding
+    assert np.array_equal(np.isnan(ys), np.isnan(y))
 
 
 def test_level_mapping_every_activation_and_aggregation():
@@ -79,6 +85,10 @@ def test_level_mapping_every_activation_and_aggregation():
             assert _same_bits(y, _run(pop, neat.FWD_REG)), (act, agg)
             y64, beta = oracle.forward(pop.nodes, pop.conns, pop.inputs, pop.I, pop.O)
             assert_parity(y, y64, beta, "act %d agg %d" % (act, agg))
+            ys = _run(pop, neat.FWD_SEG)
+            assert_parity(ys, y64, beta, "seg act %d agg %d" % (act, agg))
+            if agg in (2, 3):  # max and min: exact in any order
+                assert _same_bits(ys, y), (act, agg)
 
 
 def test_level_mapping_rejected_genomes_and_shared_inputs():
@@ -91,8 +101,11 @@ def test_level_mapping_rejected_genomes_and_shared_inputs():
     y = _run(pop, neat.FWD_LVL)
     assert np.isnan(y[3]).all()
     assert _same_bits(y, _run(pop, neat.FWD_REG))
+    ys = _run(pop, neat.FWD_SEG)
+    assert np.isnan(ys[3]).all()
     y64, beta = oracle.forward(pop.nodes, pop.conns, pop.inputs, pop.I, pop.O)
     assert_parity(y, y64, beta, "rejected")
+    assert_parity(ys, y64, beta, "rejected, segment mapping")
     dev = torch.device("cuda:0")
     tn = torch.from_numpy(pop.nodes).to(dev)
     tc = torch.from_numpy(pop.conns).to(dev)
@@ -100,10 +113,13 @@ def test_level_mapping_rejected_genomes_and_shared_inputs():
     tx = torch.from_numpy(x).to(dev)
     _, _, _, prog = neat.topo_sort(tn, tc, pop.I, pop.O, want_order=False)
     d = neat.dims_of(tn, tc, pop.I, pop.O)
-    ys = neat.forward(d, prog, tx, pop.B, shared_inputs=True, variant=neat.FWD_LVL)
+    ysh = neat.forward(d, prog, tx, pop.B, shared_inputs=True, variant=neat.FWD_LVL)
     yr = neat.forward(d, prog, tx, pop.B, shared_inputs=True, variant=neat.FWD_REG)
+    yg = neat.forward(d, prog, tx, pop.B, shared_inputs=True, variant=neat.FWD_SEG)
     torch.cuda.synchronize()
-    assert _same_bits(ys.cpu().numpy(), yr.cpu().numpy())
+    assert _same_bits(ysh.cpu().numpy(), yr.cpu().numpy())
+    y64, beta = oracle.forward(pop.nodes, pop.conns, x, pop.I, pop.O, shared_inputs=True)
+    assert_parity(yg.cpu().numpy(), y64, beta, "shared inputs, segment mapping")
 
 
 def test_level_mapping_in_a_batch_after_tuning():
@@ -140,6 +156,38 @@ def test_level_mapping_in_a_batch_after_tuning():
         plan.run(items)
         torch.cuda.synchronize()
         for (pop, d, prog, tx, y), r in zip(bufs, refs):
-            assert _same_bits(y.cpu().numpy(), r)
+            if neat.tuned_variant(d, pop.B, throughput=True) == neat.FWD_SEG:
+                y64, beta = oracle.forward(pop.nodes, pop.conns, pop.inputs, pop.I, pop.O)
+                assert_parity(y.cpu().numpy(), y64, beta, "batch item, segment mapping")
+            else:
+                assert _same_bits(y.cpu().numpy(), r)
     print("launches before and after tuning", n0, plan.launches, flush=True)
     plan.free()
+
+
+def test_segment_mapping_long_in_edge_lists():
+    """Nodes with long in-edge lists (segments cut by the end of a step and
+    continued through the carry, overflow edges past the record) and levels
+    of more than 64 nodes, with one and with eight samples per tile."""
+    neat = _neat()
+    rng = np.random.default_rng(91)
+    for B in (1, 8, 40):
+        pop = synth.make_population(rng, 6, 300, 2400, 8, 4, 288,
+                                    lambda r, na: min(2400, na), synth.CONTROL_ACTS,
+                                    synth.ALL_AGGS)
+        pop.inputs = rng.standard_normal((6, B, 8), dtype=np.float32)
+        ys = _run(pop, neat.FWD_SEG)
+        y64, beta = oracle.forward(pop.nodes, pop.conns, pop.inputs, pop.I, pop.O)
+        assert_parity(ys, y64, beta, "seg long lists B=%d" % B)
+        assert _same_bits(_run(pop, neat.FWD_LVL), _run(pop, neat.FWD_REG))
+    # wide levels: few connections among many nodes, so most of the 580
+    # hidden nodes sit on levels 0 and 1 (more than 64 nodes per level)
+    pop = synth.make_population(rng, 4, 600, 600, 8, 4, 580, lambda r, na: min(300, na),
+                                synth.CONTROL_ACTS, synth.ALL_AGGS)
+    pop.inputs = rng.standard_normal((4, 3, 8), dtype=np.float32)
+    _, level, _ = oracle.transform(pop.nodes, pop.conns, pop.I, pop.O)
+    assert max(np.bincount(lv[lv >= 0]).max() for lv in level) > 64
+    ys = _run(pop, neat.FWD_SEG)
+    y64, beta = oracle.forward(pop.nodes, pop.conns, pop.inputs, pop.I, pop.O)
+    assert_parity(ys, y64, beta, "seg wide levels")
+    assert_parity(_run(pop, neat.FWD_LVL), y64, beta, "lvl wide levels")
