@@ -937,10 +937,24 @@ __global__ __launch_bounds__(WAVE *FWD_MAX_WAVES) void forward_kernel(FwdLaunch 
         if (u < L.units) run_unit<K, GRID>(u, wave_area);
         return;
     }
+    if (L.counter) {
+        // every wave takes the next unit until none is left
+        for (;;) {
+            unsigned u = 0;
+            if ((threadIdx.x & (WAVE - 1)) == 0) u = atomicAdd(L.counter, 1u);
+            u = (unsigned)__builtin_amdgcn_readfirstlane((int)u);  // lane 0's, uniform
+            if ((long long)u >= L.units) return;
+            run_unit<K, GRID>((long long)u, wave_area);
+        }
+    }
     for (long long b = b0; b * waves < L.units; b += gridDim.x) {
         const long long u = b * waves + wave;
         if (u < L.units) run_unit<K, GRID>(u, wave_area);
     }
+}
+
+__global__ void zero_counters_kernel(unsigned *c, int n) {
+    for (int i = (int)threadIdx.x; i < n; i += (int)blockDim.x) c[i] = 0u;
 }
 
 // Waves a forward launch aims at (NEAT_FWD_WAVES overrides, for tuning).
@@ -1156,8 +1170,16 @@ hipError_t recurrent_launch(RecLaunch L, size_t max_lds, hipStream_t stream) {
     return hipGetLastError();
 }
 
-hipError_t forward_launch(const FwdKernelLaunch &k, const FwdItem *dev_items, hipStream_t stream) {
+hipError_t launch_zero_counters(unsigned *c, int n, hipStream_t stream) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(zero_counters_kernel, dim3(1), dim3(64), 0, stream, c, n);
+    return hipGetLastError();
+}
+
+hipError_t forward_launch(const FwdKernelLaunch &k, const FwdItem *dev_items, hipStream_t stream,
+                          unsigned *counter) {
     FwdLaunch L = k.args;
+    L.counter = L.persistent ? counter : nullptr;
     if (k.items.size() == 1 && dev_items == nullptr) {
         L.items = nullptr;
         L.n_items = 1;

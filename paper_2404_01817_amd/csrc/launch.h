@@ -106,6 +106,9 @@ struct FwdLaunch {
                        // store) or the output staging (register stores)
     int stage_floats;
     int persistent;    // workgroups loop over units
+    unsigned *counter; // persistent launches: next unit, taken by each wave in turn
+                       // (device memory zeroed before the launch); nullptr: units
+                       // dealt to workgroups round robin
 };
 
 struct FwdKernelLaunch {
@@ -127,7 +130,10 @@ int forward_plan(const FwdJob *jobs, int n, int variant, size_t max_lds,
                  std::vector<FwdKernelLaunch> &out, char *err, size_t errlen);
 // Launch one planned kernel.  dev_items: the launch's items in device memory
 // (may be nullptr when the launch has a single item, passed inline).
-hipError_t forward_launch(const FwdKernelLaunch &k, const FwdItem *dev_items, hipStream_t stream);
+hipError_t forward_launch(const FwdKernelLaunch &k, const FwdItem *dev_items, hipStream_t stream,
+                          unsigned *counter = nullptr);
+// Zero n unit counters (a kernel, so it can be recorded into a graph).
+hipError_t launch_zero_counters(unsigned *c, int n, hipStream_t stream);
 
 // Recurrent calculation: K synchronous sweeps, one wave per (genome, tile),
 // rows = class_slots(max_class(N), N) LDS rows per value column; tiles of
