@@ -905,7 +905,7 @@ def main():
     import torch
 
     import paper_2404_01817_amd as neat
-    from paper_2404_01817_amd import synth
+    from workloads import synth
 
     dev = torch.device("cuda:0")
     t0 = time.time()

@@ -30,7 +30,7 @@ from __future__ import annotations
 import numpy as np
 
 import oracle
-from paper_2404_01817_amd import synth
+from workloads import synth
 
 THRESHOLD = 0.2
 U32 = 2.0 ** -24

@@ -10,7 +10,7 @@ import pytest
 
 import oracle
 from tests.parity import assert_parity
-from paper_2404_01817_amd import synth
+from workloads import synth
 from tests.helpers import genome, read_golden, stack
 
 pytestmark = pytest.mark.gpu

@@ -11,7 +11,7 @@ import pytest
 
 import oracle
 from tests.parity import assert_parity
-from paper_2404_01817_amd import synth
+from workloads import synth
 from tests.helpers import genome, stack
 
 pytestmark = pytest.mark.gpu

@@ -8,7 +8,7 @@ from __future__ import annotations
 import numpy as np
 
 import oracle
-from paper_2404_01817_amd import synth
+from workloads import synth
 from tests.helpers import stack
 from tests.test_oracle_distance import _pair
 

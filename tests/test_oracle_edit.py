@@ -9,7 +9,7 @@ import numpy as np
 
 import oracle
 from oracle import EDIT_DTYPE, NODE_ADD, NODE_DEL, CONN_ADD, CONN_DEL, NODE_SET, CONN_SET
-from paper_2404_01817_amd import synth
+from workloads import synth
 from tests.helpers import genome, stack
 
 

@@ -13,7 +13,7 @@ from hypothesis import given, settings, strategies as st, HealthCheck
 
 import oracle
 from oracle import dense
-from paper_2404_01817_amd import synth
+from workloads import synth
 from tests.helpers import genome, read_golden, stack
 
 NAN = float("nan")

@@ -11,7 +11,7 @@ import numpy as np
 import pytest
 
 import oracle
-from paper_2404_01817_amd import synth
+from workloads import synth
 from tests.helpers import genome
 
 NAN = float("nan")

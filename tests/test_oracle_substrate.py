@@ -9,7 +9,7 @@ import pytest
 
 import oracle
 from oracle import substrate
-from paper_2404_01817_amd import synth
+from workloads import synth
 from tests.helpers import genome, stack
 
 

@@ -4,7 +4,7 @@ generated genome is accepted."""
 import numpy as np
 
 import oracle
-from paper_2404_01817_amd import synth
+from workloads import synth
 
 
 def test_tiny_shape_and_values():
