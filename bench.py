@@ -35,11 +35,12 @@ ACT_FLOPS = (0, 5, 4, 1, 15, 3, 1)
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "forward_control_traffic.json")
 
 
-def measured_traffic():
-    """HBM bytes per launch of the control forward from the committed
-    counter profile (FETCH_SIZE and WRITE_SIZE, each scaled by what it reads
-    for a plain copy of known size), or None when the kernel sources have
-    changed since the counters were taken."""
+def measured_profile():
+    """From the committed counter profile of the control forward: HBM bytes
+    per launch (FETCH_SIZE and WRITE_SIZE, each scaled by what it reads for a
+    plain copy of known size) and the kernel's average launch time in the
+    rocprofv3 trace; (None, None) when the kernel sources have changed since
+    they were taken."""
     import hashlib
     try:
         prof = json.load(open(TRAFFIC_PROFILE))
@@ -47,10 +48,10 @@ def measured_traffic():
         for f in prof["sources"]:
             h.update(open(os.path.join(ROOT, f), "rb").read())
         if h.hexdigest()[:16] != prof["source_hash"]:
-            return None
-        return int(prof["traffic_bytes_per_launch"])
+            return None, None
+        return int(prof["traffic_bytes_per_launch"]), prof.get("rocprof_avg_launch_us")
     except (OSError, KeyError, ValueError):
-        return None
+        return None, None
 
 
 def parse():
@@ -969,12 +970,17 @@ def main():
     fwd_bytes = pop.P * pop.B * (pop.I + pop.O) * 4 + pbytes
     fwd_avg_s = float(fwd_ms.mean()) / 1e3
     achieved = fwd_bytes / fwd_avg_s / 1e9
+    traffic, prof_us = measured_profile()
     roofline = {"kernel": "forward, 64-slot register store, two samples per lane", "bound": "hbm",
                 "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(),
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "algorithmic_bytes_per_launch": fwd_bytes,
                 "bytes_per_genome_input": round(fwd_bytes / units, 2),
-                "avg_launch_us": round(fwd_avg_s * 1e6, 1)}
+                "avg_launch_us": round(fwd_avg_s * 1e6, 1),
+                # the same fraction from the committed rocprofv3 trace's average
+                "rocprof_avg_launch_us": prof_us,
+                "frac_rocprof": (round(fwd_bytes / (prof_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)
+                                 if prof_us else None)}
 
     # each forward variant on the same program, for the record
     variants = {}
