@@ -106,3 +106,27 @@ def test_autotune_arguments():
     v, ms = neat.autotune_forward(p.d, p.prog, p.x, 0, reps=2)
     assert v == neat.FWD_AUTO and ms == [-1.0] * (2 * neat.TUNE_CANDIDATES)
     torch.cuda.synchronize()
+
+
+def test_tune_cache_file_read_and_rewritten(tmp_path):
+    """A server created with tune_cache_path loads the autotuner's table
+    from that file (bucket values: N_max and C_max rounded up to powers of
+    two, B to a power of two), and a later tuning rewrites the file with
+    both winners of the tuned bucket."""
+    neat = _neat()
+    path = tmp_path / "tune.txt"
+    # bucket (64, 256, 8) -> level mapping alone, segment mapping on a full GPU
+    path.write_text("64 256 8 0 %d %d\n" % (neat.FWD_LVL, neat.FWD_SEG))
+    server = neat.Server(max_inflight=1, tune_cache_path=str(path))
+    d = neat.Dims(5, 50, 200, 17, 6)  # N_max 50 -> 64, C_max 200 -> 256
+    assert neat.tuned_variant(d, 7) == neat.FWD_LVL        # B 7 -> 8
+    assert neat.tuned_variant(d, 8, throughput=True) == neat.FWD_SEG
+    assert neat.tuned_variant(d, 9) == neat.FWD_AUTO       # bucket 16: never tuned
+    assert neat.tuned_variant(d, 7, grid=True) == neat.FWD_AUTO
+    server.close()
+    p = _Pop(seed=9, P=40, B=12)
+    v, ms = neat.autotune_forward(p.d, p.prog, p.x, 12, reps=2)
+    vt = neat.tuned_variant(p.d, 12, throughput=True)
+    lines = {tuple(int(x) for x in l.split()) for l in path.read_text().splitlines() if l}
+    assert (64, 256, 8, 0, neat.FWD_LVL, neat.FWD_SEG) in lines
+    assert (64, 256, 16, 0, v, vt) in lines
