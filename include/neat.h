@@ -244,6 +244,14 @@ int neat_autotune_forward(const neat_dims *dims, const void *program, const floa
 int32_t neat_tuned_variant(const neat_dims *dims, int32_t B, int32_t grid, int32_t throughput);
 
 /*
+ * Forget every recorded variant (both tables) and stop reading or writing a
+ * tune cache file; later calls use NEAT_FWD_AUTO until something is tuned
+ * again, and recorded batch plans are rebuilt on their next run.  Host only,
+ * thread-safe.
+ */
+void neat_tune_clear(void);
+
+/*
  * Calculation stage for CPPN substrate queries (the paper's CPPN/HyperNEAT
  * workloads, Section 1 and Section 4): genomes with I = 5 inputs are
  * evaluated on all pairs of a side x side grid of substrate points whose

@@ -141,6 +141,12 @@ def autotune_forward(dims: Dims, program, inputs, B: int, outputs=None, reps: in
     return v.value, [float(x) for x in ms]
 
 
+def tune_clear() -> None:
+    """Forget every tuned variant and detach any tune cache file
+    (neat_tune_clear)."""
+    lib().neat_tune_clear()
+
+
 def tuned_variant(dims: Dims, B: int, grid: bool = False, throughput: bool = False) -> int:
     """The variant recorded for the call's bucket (neat_tuned_variant): the
     latency winner, or the throughput winner that batches use."""

@@ -87,6 +87,7 @@ SIGNATURES = {
     "neat_autotune_forward": (_i32, [ctypes.POINTER(Dims), _vp, _vp, _i64, _i32, _vp, _i32,
                                      _vp, _vp, _vp]),
     "neat_tuned_variant": (_i32, [ctypes.POINTER(Dims), _i32, _i32, _i32]),
+    "neat_tune_clear": (None, []),
     "neat_forward_grid": (_i32, [ctypes.POINTER(Dims), _vp, _i32, _i64, _i32, _vp, _vp]),
     "neat_apply_edits": (_i32, [ctypes.POINTER(Dims), _vp, _vp, _vp, _i32, _vp, _vp]),
     "neat_crossover": (_i32, [ctypes.POINTER(Dims), _vp, _vp, _i32, _vp, _vp, _vp, _vp, _vp,

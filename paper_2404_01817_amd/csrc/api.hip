@@ -416,6 +416,15 @@ int neat_autotune_forward(const neat_dims *d, const void *program, const float *
     return NEAT_OK;
 }
 
+void neat_tune_clear(void) {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    g_tune.clear();
+    g_tune_tp.clear();
+    g_tune_path.clear();
+    g_tune_env_read = true;  // NEAT_TUNE_CACHE is not read again
+    ++g_tune_gen;
+}
+
 int32_t neat_tuned_variant(const neat_dims *d, int32_t B, int32_t grid, int32_t throughput) {
     if (check_dims(d) != NEAT_OK || B < 0) return NEAT_E_INVALID;
     return neat::tuned_variant(d->N_max, d->C_max, B, grid != 0, throughput != 0);

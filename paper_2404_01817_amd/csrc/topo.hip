@@ -78,6 +78,10 @@ __device__ __forceinline__ int find_row(float k, const int *hkey, const int *hro
     }
 }
 
+// The two rows of a resolved connection, packed in one LDS word (-1: none).
+__device__ __forceinline__ int src_of(int sd) { return (int)(short)(sd & 0xffff); }
+__device__ __forceinline__ int dst_of(int sd) { return sd >> 16; }
+
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63u); }
 __device__ __forceinline__ int wave_id() { return (int)(threadIdx.x >> 6); }
 
@@ -203,26 +207,30 @@ __device__ __forceinline__ void topo_genome(const TopoItem &a, size_t g, const G
     const int N = a.N, C = a.C, I = a.I, O = a.O;
     const int t = G.t, W = G.W;
 
+    // 32-bit words first (keys, atomics, packed words), then 16-bit arrays
+    // (rows, positions, slots, offsets: all below 2^15)
+    const int H = hash_size(N);
     int *s_key = smem;            // [N] key of row, -1 absent, -2 malformed
     int *s_skey = s_key + N;      // [N] well-formed keys by stable rank; later level of row
-    int *s_srow = s_skey + N;     // [N] row by rank
-    int *s_indeg = s_srow + N;    // [N] in-degree, consumed by Kahn
+    int *s_indeg = s_skey + N;    // [N] in-degree, consumed by Kahn
     int *s_deg = s_indeg + N;     // [N] in-degree kept for the program
-    int *s_inoff = s_deg + N;     // [N+1]
-    int *s_outoff = s_inoff + N + 1;  // [N+1]
-    int *s_curo = s_outoff + N + 1;   // [N] out-degree, out cursor, later edge begin by row
+    int *s_curo = s_deg + N;      // [N] out-degree, out cursor, later edge begin by row
     int *s_curi = s_curo + N;     // [N] io presence, in cursor, later row by position
-    int *s_pos = s_curi + N;      // [N] position of row
-    int *e_src = s_pos + N;       // [C] source row of connection row, -1 if unused
-    int *e_dst = e_src + C;       // [C]
-    int *in_list = e_dst + C;     // [C] connection rows grouped by destination
-    int *out_list = in_list + C;  // [C] destination rows grouped by source
-    int *s_slot = out_list + C;   // [N] value slot of row
-    int *s_stack = s_slot + N;    // [N] slot allocation scratch
-    int *s_oval = s_stack + N;    // [N] slot allocation scratch
-    const int H = hash_size(N);
-    int *h_key = s_oval + N;      // [H] key -> row table: keys
+    int *s_stack = s_curi + N;    // [N] packed (key, row) words; slot allocation scratch
+    int *e_sd = s_stack + N;      // [C] connection row: source row | destination row << 16,
+                                  //     -1 if unused (rows < 2^10)
+    int *out_list = e_sd + C;     // [C] destination rows grouped by source; later the
+                                  //     source key of every in-edge
+    int *h_key = out_list + C;    // [H] key -> row table: keys
     int *h_row = h_key + H;       // [H] rows
+    int16_t *s_srow = reinterpret_cast<int16_t *>(h_row + H);  // [N] row by rank
+    int16_t *s_inoff = s_srow + N;      // [N+1] in-edge offsets (<= C_max <= 2^14)
+    int16_t *s_outoff = s_inoff + N + 1;  // [N+1] out-edge offsets
+    int16_t *s_pos = s_outoff + N + 1;  // [N] position of row
+    int16_t *s_slot = s_pos + N;        // [N] value slot of row
+    int16_t *s_oval = s_slot + N;       // [N] slot allocation scratch
+    uint16_t *in_list = reinterpret_cast<uint16_t *>(s_oval + N);  // [C] connection rows
+                                        //     grouped by destination (rows < 2^14)
 
     const float *nodes = a.nodes + g * (size_t)N * 5;
     const float *conns = a.conns + g * (size_t)C * 4;
@@ -347,8 +355,7 @@ __device__ __forceinline__ void topo_genome(const TopoItem &a, size_t g, const G
                 }
             }
         }
-        e_src[c] = src;
-        e_dst[c] = dst;
+        e_sd[c] = src < 0 ? -1 : (src | (dst << 16));
     };
 #pragma unroll
     for (int k = 0; k < CPRE; ++k)
@@ -377,20 +384,22 @@ __device__ __forceinline__ void topo_genome(const TopoItem &a, size_t g, const G
     }
     gsync(G);
     for (int c = t; c < C; c += W) {
-        const int s = e_src[c];
+        const int sd = e_sd[c];
+        const int s = src_of(sd);
         if (s < 0) continue;
-        const int d = e_dst[c];
-        in_list[s_inoff[d] + atomicAdd(&s_curi[d], 1)] = c;
+        const int d = dst_of(sd);
+        in_list[s_inoff[d] + atomicAdd(&s_curi[d], 1)] = (uint16_t)c;
         out_list[s_outoff[s] + atomicAdd(&s_curo[s], 1)] = d;
     }
     gsync(G);
     for (int c = t; c < C; c += W) {
-        const int s = e_src[c];
+        const int sd = e_sd[c];
+        const int s = src_of(sd);
         if (s < 0) continue;
-        const int d = e_dst[c];
+        const int d = dst_of(sd);
         for (int k = s_inoff[d]; k < s_inoff[d + 1]; ++k) {
             const int c2 = in_list[k];
-            if (c2 != c && e_src[c2] == s) st |= NEAT_ST_DUP_EDGE;
+            if (c2 != c && src_of(e_sd[c2]) == s) st |= NEAT_ST_DUP_EDGE;
         }
     }
     if (st) atomicOr(&s_status, st);
@@ -582,7 +591,7 @@ __device__ __forceinline__ void topo_genome(const TopoItem &a, size_t g, const G
     // source key of every in-edge (the out lists are no longer needed), for
     // the per-node scans below
     int *in_key = out_list;
-    for (int k = t; k < s_inoff[N]; k += W) in_key[k] = s_key[e_src[in_list[k]]];
+    for (int k = t; k < s_inoff[N]; k += W) in_key[k] = s_key[src_of(e_sd[in_list[k]])];
     gsync(G);
     const int used = s_used;
     const int cls = class_of(used);
@@ -676,7 +685,7 @@ __device__ __forceinline__ void topo_genome(const TopoItem &a, size_t g, const G
             } else if (agg == AGG_PRODUCT) {
                 slot = zs + 1;
             } else {  // max / min: the first edge again (min stores -w)
-                slot = s_slot[e_src[first]];
+                slot = s_slot[src_of(e_sd[first])];
                 w = conns[(size_t)first * 4 + 3];
                 if (agg == AGG_MIN) w = -w;
             }
@@ -695,9 +704,10 @@ __device__ __forceinline__ void topo_genome(const TopoItem &a, size_t g, const G
     // rest in the overflow array.  The thread that read a connection row
     // writes its edge (weights of the prefetched rows are still in registers)
     auto edge = [&](int c, float w) {
-        const int s = e_src[c];
+        const int sd = e_sd[c];
+        const int s = src_of(sd);
         if (s < 0) return;
-        const int d = e_dst[c];
+        const int d = dst_of(sd);
         const int ks = s_key[s];
         int j = 0;
         for (int k = s_inoff[d]; k < s_inoff[d + 1]; ++k) j += (in_key[k] < ks);
@@ -802,8 +812,11 @@ __global__ __launch_bounds__(1024) void classify_batch_kernel(const TopoItem *it
 }  // namespace
 
 size_t topo_lds_bytes(int N, int C) {
-    return sizeof(int) *
-           ((size_t)SH_WORDS + (size_t)13 * N + 2 + (size_t)4 * C + 2 * (size_t)hash_size(N));
+    // 32-bit: 7 N node words, 2 C connection words, the key table (2 H);
+    // 16-bit: 6 N + 2 node entries, C connection entries
+    return sizeof(int) * ((size_t)SH_WORDS + (size_t)7 * N + (size_t)2 * C +
+                          2 * (size_t)hash_size(N)) +
+           sizeof(int16_t) * ((size_t)6 * N + 2 + (size_t)C);
 }
 
 

@@ -16,6 +16,15 @@ from tests.parity import assert_parity
 
 pytestmark = pytest.mark.gpu
 
+
+@pytest.fixture(autouse=True)
+def _clean_tune_table():
+    """Every test here tunes: leave the process-wide table empty for the
+    tests after it, which compare untuned bits."""
+    yield
+    import paper_2404_01817_amd as neat
+    neat.tune_clear()
+
 torch = pytest.importorskip("torch")
 
 

@@ -163,6 +163,7 @@ def test_level_mapping_in_a_batch_after_tuning():
                 assert _same_bits(y.cpu().numpy(), r)
     print("launches before and after tuning", n0, plan.launches, flush=True)
     plan.free()
+    neat.tune_clear()  # later tests compare untuned bits
 
 
 def test_segment_mapping_long_in_edge_lists():
