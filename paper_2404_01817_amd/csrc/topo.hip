@@ -56,18 +56,21 @@ __host__ __device__ constexpr int hash_size(int N) {
 __device__ __forceinline__ int hash_slot(int key, int H) {
     return (int)(((unsigned)key * 2654435761u) >> 8) & (H - 1);
 }
-__device__ __forceinline__ void hash_insert(int *hkey, int *hrow, int H, int key, int row) {
+// Returns the key's slot.
+__device__ __forceinline__ int hash_insert(int *hkey, int *hrow, int H, int key, int row) {
     int h = hash_slot(key, H);
     for (;;) {
         const int old = atomicCAS(&hkey[h], HASH_EMPTY, key);
         if (old == HASH_EMPTY || old == key) {
             atomicMin(&hrow[h], row);
-            return;
+            return h;
         }
         h = (h + 1) & (H - 1);
     }
 }
-// Row of the well-formed key equal to k (first row among duplicates), or -1.
+// Table word of the well-formed key equal to k, or -1.  The word's low 16
+// bits are the first row among duplicates; one-wave groups later add the
+// key's rank above them.
 __device__ __forceinline__ int find_row(float k, const int *hkey, const int *hrow, int H) {
     if (!is_int_in(k, 0.0f, KEY_LIMIT)) return -1;
     const int key = (int)k;
@@ -91,16 +94,36 @@ __device__ __forceinline__ int mbcnt(unsigned long long m) {
                                           __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u));
 }
 
+// Inclusive prefix sum and minimum over the 64 lanes of a wave, by DPP
+// (no LDS traffic): row shifts by 1, 2, 4 and 8 within each row of 16
+// lanes, then the row results carried on by broadcasts of lanes 15 (to
+// rows 1 and 3) and 31 (to rows 2 and 3).  A lane whose source is out of
+// its row, or whose row is masked, takes the identity.
+__device__ __forceinline__ int wave_incl_add(int x) {
+    x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, false);  // row_shr:1
+    x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, false);  // row_shr:2
+    x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, false);  // row_shr:4
+    x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, false);  // row_shr:8
+    x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xa, 0xf, false);  // row_bcast:15
+    x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xc, 0xf, false);  // row_bcast:31
+    return x;
+}
+__device__ __forceinline__ int wave_incl_min(int x) {
+    constexpr int ID = 0x7fffffff;
+    x = min(x, __builtin_amdgcn_update_dpp(ID, x, 0x111, 0xf, 0xf, false));
+    x = min(x, __builtin_amdgcn_update_dpp(ID, x, 0x112, 0xf, 0xf, false));
+    x = min(x, __builtin_amdgcn_update_dpp(ID, x, 0x114, 0xf, 0xf, false));
+    x = min(x, __builtin_amdgcn_update_dpp(ID, x, 0x118, 0xf, 0xf, false));
+    x = min(x, __builtin_amdgcn_update_dpp(ID, x, 0x142, 0xa, 0xf, false));
+    x = min(x, __builtin_amdgcn_update_dpp(ID, x, 0x143, 0xc, 0xf, false));
+    return x;
+}
+
 // Block-wide exclusive scan of one value per thread; *total receives the sum.
 // Contains two barriers; every thread of the block must call it.
 __device__ int block_excl_scan(int v, int *s_wave, int *total) {
     const int lane = lane_id(), wave = wave_id(), nw = (int)(blockDim.x >> 6);
-    int x = v;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const int y = __shfl_up(x, d, 64);
-        if (lane >= d) x += y;
-    }
+    const int x = wave_incl_add(v);
     if (lane == 63) s_wave[wave] = x;
     __syncthreads();
     int base = 0, tot = 0;
@@ -155,14 +178,9 @@ __device__ __forceinline__ bool gsync_or(const Grp<ONE> &G, bool x) {
 // the sum.  Every thread of the group must call it.
 template <bool ONE>
 __device__ __forceinline__ int group_excl_scan(const Grp<ONE> &G, int v, int *total) {
-    int x = v;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const int y = __shfl_up(x, d, 64);
-        if (G.lane >= d) x += y;
-    }
+    const int x = wave_incl_add(v);
     if (ONE) {
-        *total = __shfl(x, 63, 64);
+        *total = __builtin_amdgcn_readlane(x, 63);
         return x - v;
     }
     if (G.lane == 63) G.sh[SH_WAVE + G.wave] = x;
@@ -181,12 +199,7 @@ __device__ __forceinline__ int group_excl_scan(const Grp<ONE> &G, int v, int *to
 // Inclusive prefix minimum of one value per thread over the group.
 template <bool ONE>
 __device__ __forceinline__ int group_incl_min(const Grp<ONE> &G, int v) {
-    int x = v;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        const int y = __shfl_up(x, d, 64);
-        if (G.lane >= d) x = min(x, y);
-    }
+    const int x = wave_incl_min(v);
     if (ONE) return x;
     if (G.lane == 63) G.sh[SH_WAVE + G.wave] = x;
     gsync(G);
@@ -208,20 +221,23 @@ __device__ __forceinline__ void topo_genome(const TopoItem &a, size_t g, const G
     const int t = G.t, W = G.W;
 
     // 32-bit words first (keys, atomics, packed words), then 16-bit arrays
-    // (rows, positions, slots, offsets: all below 2^15)
+    // (rows, positions, slots, offsets: all below 2^15).  s_stack comes
+    // first so that it is 16-byte aligned for the rank's vector reads.
     const int H = hash_size(N);
-    int *s_key = smem;            // [N] key of row, -1 absent, -2 malformed
+    const int N4 = (N + 3) & ~3;
+    int *s_stack = smem;          // [N4] packed (key, row) words (padding: -1); slot
+                                  //      allocation scratch
+    int *s_key = s_stack + N4;    // [N] key of row, -1 absent, -2 malformed
     int *s_skey = s_key + N;      // [N] well-formed keys by stable rank; later level of row
     int *s_indeg = s_skey + N;    // [N] in-degree, consumed by Kahn
     int *s_deg = s_indeg + N;     // [N] in-degree kept for the program
     int *s_curo = s_deg + N;      // [N] out-degree, out cursor, later edge begin by row
     int *s_curi = s_curo + N;     // [N] io presence, in cursor, later row by position
-    int *s_stack = s_curi + N;    // [N] packed (key, row) words; slot allocation scratch
-    int *e_sd = s_stack + N;      // [C] connection row: source row | destination row << 16,
-                                  //     -1 if unused (rows < 2^10)
-    int *out_list = e_sd + C;     // [C] destination rows grouped by source; later the
-                                  //     source key of every in-edge
-    int *h_key = out_list + C;    // [H] key -> row table: keys
+    int *e_sd = s_curi + N;       // [C] connection row: source row | destination row << 16,
+                                  //     -1 if unused (rows < 2^10); written only for the
+                                  //     rows a thread does not keep in registers
+    int *in_key = e_sd + C;       // [C] source keys of the in-edges, grouped by destination
+    int *h_key = in_key + C;      // [H] key -> row table: keys
     int *h_row = h_key + H;       // [H] rows
     int16_t *s_srow = reinterpret_cast<int16_t *>(h_row + H);  // [N] row by rank
     int16_t *s_inoff = s_srow + N;      // [N+1] in-edge offsets (<= C_max <= 2^14)
@@ -229,8 +245,8 @@ __device__ __forceinline__ void topo_genome(const TopoItem &a, size_t g, const G
     int16_t *s_pos = s_outoff + N + 1;  // [N] position of row
     int16_t *s_slot = s_pos + N;        // [N] value slot of row
     int16_t *s_oval = s_slot + N;       // [N] slot allocation scratch
-    uint16_t *in_list = reinterpret_cast<uint16_t *>(s_oval + N);  // [C] connection rows
-                                        //     grouped by destination (rows < 2^14)
+    uint16_t *out_list = reinterpret_cast<uint16_t *>(s_oval + N);  // [C] destination rows
+                                        //     grouped by source
 
     const float *nodes = a.nodes + g * (size_t)N * 5;
     const float *conns = a.conns + g * (size_t)C * 4;
@@ -265,12 +281,13 @@ __device__ __forceinline__ void topo_genome(const TopoItem &a, size_t g, const G
         h_key[i] = HASH_EMPTY;
         h_row[i] = 0x7fffffff;
     }
+    if (t >= N && t < N4) s_stack[t] = -1;
     gsync(G);
 
     // ---- 1. node rows
     const int rb = N <= 256 ? 8 : 10;  // row bits of the packed (key, row) words
     unsigned st = 0u;
-    int key = -1, act = 0, agg = 0;
+    int key = -1, act = 0, agg = 0, my_h = -1;
     float bias = 0.0f, resp = 0.0f;
     if (t < N) {
         const float kf = nrow[0];
@@ -288,7 +305,7 @@ __device__ __forceinline__ void topo_genome(const TopoItem &a, size_t g, const G
                 agg = (int)gf;
             }
             key = key_ok ? (int)kf : -2;
-            if (key_ok) hash_insert(h_key, h_row, H, key, t);
+            if (key_ok) my_h = hash_insert(h_key, h_row, H, key, t);
         }
         s_key[t] = key;
         // (key, row) in one word: rows take rb bits, keys the rest (always
@@ -306,12 +323,16 @@ __device__ __forceinline__ void topo_genome(const TopoItem &a, size_t g, const G
     if (key >= 0) {
         if (packed) {
             // rank = number of (key, row) words below this row's (the words
-            // are distinct; absent and malformed rows hold the largest)
+            // are distinct; absent and malformed rows and the padding hold
+            // the largest), read four at a time (every lane the same address)
             const unsigned mine = ((unsigned)key << rb) | (unsigned)t;
-            const unsigned *comp = reinterpret_cast<const unsigned *>(s_stack);
+            const uint4 *comp = reinterpret_cast<const uint4 *>(s_stack);
             int less = 0;
-#pragma unroll 8
-            for (int q = 0; q < N; ++q) less += comp[q] < mine;
+#pragma unroll 4
+            for (int q = 0; q < (N4 >> 2); ++q) {
+                const uint4 v = comp[q];
+                less += (v.x < mine) + (v.y < mine) + (v.z < mine) + (v.w < mine);
+            }
             rank = less;
         } else {
             int less = 0, eq_before = 0;
@@ -333,73 +354,234 @@ __device__ __forceinline__ void topo_genome(const TopoItem &a, size_t g, const G
                       (rank + 1 < N && s_skey[rank + 1] == key)))
         st |= NEAT_ST_DUP_KEY;
     if (t < I + O && s_curi[t] == 0) st |= NEAT_ST_MISSING_IO;
+    // One-wave groups hold the graph as bit masks over key ranks (at most
+    // 64): row d's sources, bits 0-31 in s_stack[d] and 32-63 in s_skey[d]
+    // (both free until Kahn's levels are written).  Every key's table word
+    // gets the key's rank above its row.
+    if constexpr (ONE) {
+        gsync(G);  // the duplicate-key check has read s_skey
+        if (key >= 0 && h_row[my_h] == t) h_row[my_h] = t | (rank << 16);
+        if (t < N) {
+            s_stack[t] = 0;
+            s_skey[t] = 0;
+        }
+        gsync(G);
+    }
 
-    // ---- 3. connection rows (the prefetched ones first)
-    auto connection = [&](int c, const float4 row) {
-        int src = -1, dst = -1;
-        if (!isnan(row.x) && row.z != 0.0f) {
-            if (row.z != 1.0f) {
-                st |= NEAT_ST_BAD_VALUE;
-            } else {
-                const int s = find_row(row.x, h_key, h_row, H);
-                const int d = find_row(row.y, h_key, h_row, H);
-                if (s < 0 || d < 0) {
-                    st |= NEAT_ST_BAD_REF;
-                } else {
-                    if (s_key[d] < I) st |= NEAT_ST_INTO_INPUT;
-                    if (s == d && !a.recurrent) st |= NEAT_ST_CYCLE;
-                    src = s;
-                    dst = d;
-                    atomicAdd(&s_indeg[d], 1);
-                    atomicAdd(&s_curo[s], 1);
-                }
+    // ---- 3. connection rows.  A resolved row counts into the degrees (in
+    // one-wave groups: sets its source's bit in the destination's mask, and
+    // a bit already set is a duplicate edge); the thread keeps its
+    // prefetched rows (rows packed as in e_sd, source key) in registers, the
+    // others go to e_sd.  One-wave groups pack the source's rank too:
+    // source | rank << 8 | destination << 16.
+    auto resolved = [&](int ws, int wd, int kd) {
+        if (ws < 0 || wd < 0) {
+            st |= NEAT_ST_BAD_REF;
+            return -1;
+        }
+        const int s = ws & 0xffff, d = wd & 0xffff;
+        // d holds key kd (the table maps a key to a row holding it)
+        if (kd < I) st |= NEAT_ST_INTO_INPUT;
+        if (s == d && !a.recurrent) st |= NEAT_ST_CYCLE;
+        if constexpr (ONE) {
+            const int rs = ws >> 16;
+            const unsigned bit = 1u << (rs & 31);
+            unsigned *mask = reinterpret_cast<unsigned *>(rs < 32 ? s_stack : s_skey);
+            if (atomicOr(&mask[d], bit) & bit) st |= NEAT_ST_DUP_EDGE;
+            return s | (rs << 8) | (d << 16);
+        } else {
+            atomicAdd(&s_indeg[d], 1);
+            atomicAdd(&s_curo[s], 1);
+            return s | (d << 16);
+        }
+    };
+    // an enabled row's endpoint keys, or false (padding, disabled, or a bad
+    // enabled flag, which is flagged)
+    auto enabled = [&](const float4 row) {
+        if (isnan(row.x) || row.z == 0.0f) return false;
+        if (row.z != 1.0f) {
+            st |= NEAT_ST_BAD_VALUE;
+            return false;
+        }
+        return true;
+    };
+    int sdp[CPRE], ksp[CPRE];
+    {
+        // all endpoints of the prefetched rows: first probes read together,
+        // then the (rare) further probes, then the rows together
+        int key2[2 * CPRE], hs[2 * CPRE], hk[2 * CPRE];
+#pragma unroll
+        for (int k = 0; k < CPRE; ++k) {
+            const bool on = t + k * W < C && enabled(cpre[k]);
+            key2[k] = on && is_int_in(cpre[k].x, 0.0f, KEY_LIMIT) ? (int)cpre[k].x : -1;
+            key2[CPRE + k] = on && is_int_in(cpre[k].y, 0.0f, KEY_LIMIT) ? (int)cpre[k].y : -1;
+            sdp[k] = on ? -2 : -1;  // -2: enabled, endpoints to resolve
+        }
+#pragma unroll
+        for (int i = 0; i < 2 * CPRE; ++i) {
+            hs[i] = key2[i] >= 0 ? hash_slot(key2[i], H) : 0;
+            hk[i] = h_key[hs[i]];
+        }
+        for (;;) {
+            bool more = false;
+#pragma unroll
+            for (int i = 0; i < 2 * CPRE; ++i) {
+                const bool go = key2[i] >= 0 && hk[i] != key2[i] && hk[i] != HASH_EMPTY;
+                if (go) hs[i] = (hs[i] + 1) & (H - 1);
+                more |= go;
+            }
+            if (!more) break;
+#pragma unroll
+            for (int i = 0; i < 2 * CPRE; ++i) hk[i] = h_key[hs[i]];
+        }
+        int r2[2 * CPRE];
+#pragma unroll
+        for (int i = 0; i < 2 * CPRE; ++i) r2[i] = h_row[hs[i]];
+        // every read is needed as issued (a select on a fresh load would
+        // otherwise become a branch around it, and the reads one wait each)
+#pragma unroll
+        for (int i = 0; i < 2 * CPRE; ++i) asm volatile("" : "+v"(r2[i]));
+#pragma unroll
+        for (int i = 0; i < 2 * CPRE; ++i) r2[i] = (key2[i] >= 0 && hk[i] == key2[i]) ? r2[i] : -1;
+        if constexpr (ONE) {
+            // the mask updates of all four rows in flight together; a row
+            // without an edge ORs 0 into row 0's mask
+            unsigned bits[CPRE], old[CPRE];
+#pragma unroll
+            for (int k = 0; k < CPRE; ++k) {
+                const int ws = r2[k], wd = r2[CPRE + k];
+                const bool ok = sdp[k] == -2 && ws >= 0 && wd >= 0;
+                if (sdp[k] == -2 && !ok) st |= NEAT_ST_BAD_REF;
+                const int s = ws & 0xffff, d = wd & 0xffff, rs = (ws >> 16) & 0xff;
+                if (ok && key2[CPRE + k] < I) st |= NEAT_ST_INTO_INPUT;
+                if (ok && s == d && !a.recurrent) st |= NEAT_ST_CYCLE;
+                bits[k] = ok ? 1u << (rs & 31) : 0u;
+                unsigned *mask = reinterpret_cast<unsigned *>(ok && rs >= 32 ? s_skey : s_stack);
+                old[k] = atomicOr(&mask[ok ? d : 0], bits[k]);
+                sdp[k] = ok ? s | (rs << 8) | (d << 16) : -1;
+            }
+#pragma unroll
+            for (int k = 0; k < CPRE; ++k)
+                if (old[k] & bits[k]) st |= NEAT_ST_DUP_EDGE;
+        } else {
+#pragma unroll
+            for (int k = 0; k < CPRE; ++k)
+                if (sdp[k] == -2) sdp[k] = resolved(r2[k], r2[CPRE + k], key2[CPRE + k]);
+        }
+#pragma unroll
+        for (int k = 0; k < CPRE; ++k) ksp[k] = key2[k];
+    }
+    for (int c = t + CPRE * W; c < C; c += W) {
+        const float4 row = conns4[c];
+        int sd = -1;
+        if (enabled(row))
+            sd = resolved(find_row(row.x, h_key, h_row, H), find_row(row.y, h_key, h_row, H),
+                          is_int_in(row.y, 0.0f, KEY_LIMIT) ? (int)row.y : -1);
+        e_sd[c] = sd;
+    }
+    gsync(G);
+
+    // ---- 4. adjacency (one-wave groups: in-degrees and indices from the
+    // masks; other groups: counting sort by destination and by source)
+    int jp[CPRE];     // index of each prefetched edge among its destination's
+                      // in-edges by source key
+    int deg1 = 0;     // one-wave groups: in-degree of row t
+    int nreal = 0;    // one-wave groups: edges
+    if constexpr (ONE) {
+        // ranks follow keys, so an edge's index is the number of its
+        // destination's sources of smaller rank
+        auto below = [&](int d, int rs) {
+            const unsigned lo = (unsigned)s_stack[d], hi = (unsigned)s_skey[d];
+            return rs < 32 ? __popc(lo & ((1u << rs) - 1u))
+                           : __popc(lo) + __popc(hi & ((1u << (rs - 32)) - 1u));
+        };
+        if (t < N) deg1 = __popc((unsigned)s_stack[t]) + __popc((unsigned)s_skey[t]);
+        group_excl_scan(G, deg1, &nreal);
+#pragma unroll
+        for (int k = 0; k < CPRE; ++k)
+            jp[k] = sdp[k] >= 0 ? below(sdp[k] >> 16, (sdp[k] >> 8) & 0xff) : 0;
+        // the other rows keep their index in place of the rank
+        for (int c = t + CPRE * W; c < C; c += W) {
+            const int sd = e_sd[c];
+            if (sd >= 0) e_sd[c] = (sd & ~0xff00) | (below(sd >> 16, (sd >> 8) & 0xff) << 8);
+        }
+    } else {
+        {
+            const int din = (t < N) ? s_indeg[t] : 0;
+            const int dout = (t < N) ? s_curo[t] : 0;
+            int tin, tout;
+            const int ein = group_excl_scan(G, din, &tin);
+            const int eout = group_excl_scan(G, dout, &tout);
+            if (t < N) {
+                s_inoff[t] = ein;
+                s_outoff[t] = eout;
+                s_deg[t] = din;
+                s_curo[t] = 0;
+                s_curi[t] = 0;
+            }
+            if (t == 0) {
+                s_inoff[N] = tin;
+                s_outoff[N] = tout;
             }
         }
-        e_sd[c] = src < 0 ? -1 : (src | (dst << 16));
-    };
-#pragma unroll
-    for (int k = 0; k < CPRE; ++k)
-        if (t + k * W < C) connection(t + k * W, cpre[k]);
-    for (int c = t + CPRE * W; c < C; c += W) connection(c, conns4[c]);
-    gsync(G);
-
-    // ---- 4. adjacency lists (counting sort by destination and by source)
-    {
-        const int din = (t < N) ? s_indeg[t] : 0;
-        const int dout = (t < N) ? s_curo[t] : 0;
-        int tin, tout;
-        const int ein = group_excl_scan(G, din, &tin);
-        const int eout = group_excl_scan(G, dout, &tout);
-        if (t < N) {
-            s_inoff[t] = ein;
-            s_outoff[t] = eout;
-            s_deg[t] = din;
-            s_curo[t] = 0;
-            s_curi[t] = 0;
+        gsync(G);
+        // scatter: a destination's in-list holds the source keys, a source's
+        // out-list the destination rows
+        auto scatter = [&](int sd, int ks) {
+            const int s = src_of(sd), d = dst_of(sd);
+            in_key[s_inoff[d] + atomicAdd(&s_curi[d], 1)] = ks;
+            out_list[s_outoff[s] + atomicAdd(&s_curo[s], 1)] = (uint16_t)d;
+        };
+    #pragma unroll
+        for (int k = 0; k < CPRE; ++k)
+            if (sdp[k] >= 0) scatter(sdp[k], ksp[k]);
+        for (int c = t + CPRE * W; c < C; c += W) {
+            const int sd = e_sd[c];
+            if (sd >= 0) scatter(sd, s_key[src_of(sd)]);
         }
-        if (t == 0) {
-            s_inoff[N] = tin;
-            s_outoff[N] = tout;
+        gsync(G);
+        // every edge's index among its destination's in-edges by source key (the
+        // number of smaller source keys) and duplicate edges (an equal source
+        // key besides its own).  The prefetched rows walk their in-lists side by
+        // side, so their reads overlap; their indices stay in registers.
+        {
+            int base[CPRE], cnt[CPRE], eq[CPRE];
+            int m = 0;
+    #pragma unroll
+            for (int k = 0; k < CPRE; ++k) {
+                base[k] = 0;
+                cnt[k] = 0;
+                if (sdp[k] >= 0) {
+                    const int d = dst_of(sdp[k]);
+                    base[k] = s_inoff[d];
+                    cnt[k] = s_inoff[d + 1] - base[k];
+                }
+                m = max(m, cnt[k]);
+                jp[k] = 0;
+                eq[k] = 0;
+            }
+            for (int i = 0; i < m; ++i) {
+    #pragma unroll
+                for (int k = 0; k < CPRE; ++k) {
+                    // an exhausted list re-reads its last entry (or entry 0 of
+                    // a row with no list, which exists since m > 0)
+                    const int q = in_key[base[k] + min(i, max(cnt[k] - 1, 0))];
+                    const bool v = i < cnt[k];
+                    jp[k] += (v && q < ksp[k]) ? 1 : 0;
+                    eq[k] += (v && q == ksp[k]) ? 1 : 0;
+                }
+            }
+    #pragma unroll
+            for (int k = 0; k < CPRE; ++k)
+                if (eq[k] > 1) st |= NEAT_ST_DUP_EDGE;
         }
-    }
-    gsync(G);
-    for (int c = t; c < C; c += W) {
-        const int sd = e_sd[c];
-        const int s = src_of(sd);
-        if (s < 0) continue;
-        const int d = dst_of(sd);
-        in_list[s_inoff[d] + atomicAdd(&s_curi[d], 1)] = (uint16_t)c;
-        out_list[s_outoff[s] + atomicAdd(&s_curo[s], 1)] = d;
-    }
-    gsync(G);
-    for (int c = t; c < C; c += W) {
-        const int sd = e_sd[c];
-        const int s = src_of(sd);
-        if (s < 0) continue;
-        const int d = dst_of(sd);
-        for (int k = s_inoff[d]; k < s_inoff[d + 1]; ++k) {
-            const int c2 = in_list[k];
-            if (c2 != c && src_of(e_sd[c2]) == s) st |= NEAT_ST_DUP_EDGE;
+        for (int c = t + CPRE * W; c < C; c += W) {
+            const int sd = e_sd[c];
+            if (sd < 0) continue;
+            const int d = dst_of(sd), ks = s_key[src_of(sd)];
+            int eq = 0;
+            for (int k = s_inoff[d]; k < s_inoff[d + 1]; ++k) eq += in_key[k] == ks;
+            if (eq > 1) st |= NEAT_ST_DUP_EDGE;
         }
     }
     if (st) atomicOr(&s_status, st);
@@ -419,31 +601,62 @@ __device__ __forceinline__ void topo_genome(const TopoItem &a, size_t g, const G
         }
         n_levels = nvalid > 0 ? 1 : 0;
     } else if (status == 0u) {
-        const int lane = G.lane, wave = G.wave, nw = G.nw;
-        bool emitted = false;
         int base = 0;
-        for (;;) {
-            const bool ready = my_row >= 0 && !emitted && s_indeg[my_row] == 0;
-            const unsigned long long m = __ballot(ready);
-            if (lane == 0) G.sh[SH_WAVE + wave] = __popcll(m);
-            gsync(G);
-            int wbase = 0, total = 0;
-            for (int w = 0; w < nw; ++w) {
-                const int c = G.sh[SH_WAVE + w];
-                wbase += (w < wave) ? c : 0;
-                total += c;
+        if constexpr (ONE) {
+            // a node is ready once every source's rank bit is in done (the
+            // ranks emitted so far); lane t holds rank t
+            unsigned long long pm = 0ull, done = 0ull;
+            if (my_row >= 0)
+                pm = (unsigned long long)(unsigned)s_stack[my_row] |
+                     ((unsigned long long)(unsigned)s_skey[my_row] << 32);
+            bool emitted = false;
+            for (;;) {
+                const bool ready = my_row >= 0 && !emitted && (pm & ~done) == 0ull;
+                const unsigned long long m = __ballot(ready);
+                if (m == 0ull) break;
+                if (ready) {
+                    s_pos[my_row] = base + mbcnt(m);
+                    my_level = n_levels;
+                    emitted = true;
+                }
+                done |= m;
+                base += __popcll(m);
+                ++n_levels;
             }
-            if (total == 0) break;  // uniform across the block
-            if (ready) {
-                s_pos[my_row] = base + wbase + mbcnt(m);
-                my_level = n_levels;
-                emitted = true;
-                for (int k = s_outoff[my_row]; k < s_outoff[my_row + 1]; ++k)
-                    atomicSub(&s_indeg[out_list[k]], 1);
+        } else {
+            const int lane = G.lane, wave = G.wave, nw = G.nw;
+            bool emitted = false;
+            const int ob = my_row >= 0 ? s_outoff[my_row] : 0;
+            const int oe = my_row >= 0 ? s_outoff[my_row + 1] : 0;
+            for (;;) {
+                const bool ready = my_row >= 0 && !emitted && s_indeg[my_row] == 0;
+                const unsigned long long m = __ballot(ready);
+                if (lane == 0) G.sh[SH_WAVE + wave] = __popcll(m);
+                gsync(G);
+                int wbase = 0, total = 0;
+                for (int w = 0; w < nw; ++w) {
+                    const int c = G.sh[SH_WAVE + w];
+                    wbase += (w < wave) ? c : 0;
+                    total += c;
+                }
+                if (total == 0) break;  // uniform across the block
+                if (ready) {
+                    s_pos[my_row] = base + wbase + mbcnt(m);
+                    my_level = n_levels;
+                    emitted = true;
+                    // successors read two at a time, then decremented
+                    int k = ob;
+                    for (; k + 1 < oe; k += 2) {
+                        const int d0 = out_list[k], d1 = out_list[k + 1];
+                        atomicSub(&s_indeg[d0], 1);
+                        atomicSub(&s_indeg[d1], 1);
+                    }
+                    if (k < oe) atomicSub(&s_indeg[out_list[k]], 1);
+                }
+                gsync(G);
+                base += total;
+                ++n_levels;
             }
-            gsync(G);
-            base += total;
-            ++n_levels;
         }
         if (base < nvalid) status |= NEAT_ST_CYCLE;
     }
@@ -480,22 +693,36 @@ __device__ __forceinline__ void topo_genome(const TopoItem &a, size_t g, const G
         }
         return;  // uniform
     }
-    // last reading position of every value (s_indeg is free after Kahn);
-    // outputs are read after the last node
-    int *s_last = s_indeg;
-    if (t < N && s_key[t] != -1) {
-        int last = s_pos[t];
-        for (int k = s_outoff[t]; k < s_outoff[t + 1]; ++k) last = max(last, s_pos[out_list[k]]);
-        if (s_key[t] >= I && s_key[t] < I + O) last = nvalid;
-        s_last[t] = last;
-    }
-    gsync(G);
     if (max_class(N) == CLS_R64 || a.recurrent) {
         // every genome fits the 64-slot class, or every value stays live
         // from one sweep to the next: slot = position
         if (t < nvalid) s_slot[s_curi[t]] = t;
         if (t == 0) s_used = nvalid;
     } else {
+        // last reading position of every value (s_indeg is free after
+        // Kahn, and unused by one-wave groups); outputs are read after the
+        // last node
+        int *s_last = s_indeg;
+        if constexpr (ONE) {
+            // every edge raises its source's last position to its own
+            if (t < N && s_key[t] != -1)
+                s_last[t] = (s_key[t] >= I && s_key[t] < I + O) ? nvalid : (int)s_pos[t];
+            gsync(G);
+#pragma unroll
+            for (int k = 0; k < CPRE; ++k)
+                if (sdp[k] >= 0) atomicMax(&s_last[sdp[k] & 0xff], (int)s_pos[sdp[k] >> 16]);
+            for (int c = t + CPRE * W; c < C; c += W) {
+                const int sd = e_sd[c];
+                if (sd >= 0) atomicMax(&s_last[sd & 0xff], (int)s_pos[sd >> 16]);
+            }
+        } else if (t < N && s_key[t] != -1) {
+            int last = s_pos[t];
+            for (int k = s_outoff[t]; k < s_outoff[t + 1]; ++k)
+                last = max(last, (int)s_pos[out_list[k]]);
+            if (s_key[t] >= I && s_key[t] < I + O) last = nvalid;
+            s_last[t] = last;
+        }
+        gsync(G);
         // Slots by liveness, in parallel.  A value frees its slot for the
         // position free_at: its last reader (which reads before writing),
         // the next position when nothing reads it, I for unread inputs;
@@ -588,11 +815,6 @@ __device__ __forceinline__ void topo_genome(const TopoItem &a, size_t g, const G
         }
     }
     gsync(G);
-    // source key of every in-edge (the out lists are no longer needed), for
-    // the per-node scans below
-    int *in_key = out_list;
-    for (int k = t; k < s_inoff[N]; k += W) in_key[k] = s_key[src_of(e_sd[in_list[k]])];
-    gsync(G);
     const int used = s_used;
     const int cls = class_of(used);
     const int zs = zero_slot(cls, N);
@@ -603,26 +825,17 @@ __device__ __forceinline__ void topo_genome(const TopoItem &a, size_t g, const G
         prog[HDR_I] = I;
         prog[HDR_O] = O;
         prog[HDR_CLASS] = cls;
-        prog[HDR_NREAL] = s_inoff[N];
+        prog[HDR_NREAL] = ONE ? nreal : (int)s_inoff[N];
         prog[HDR_SLOTS] = used;
     }
     // output slots: rank I + j holds key I + j
     if (t < O) prog[out_off() + t] = s_slot[s_srow[I + t]];
-    // owner of a computed row: in-degree, first in-edge (min source key),
-    // pairs after padding to an even count, overflow edges beyond the record
+    // owner of a computed row: in-degree, pairs after padding to an even
+    // count, overflow edges beyond the record
     const bool computed = t < N && s_key[t] >= 0 && s_pos[t] >= I;
-    int deg = 0, first = -1;
-    if (computed) {
-        int kmin = 0x7fffffff;
-        for (int k = s_inoff[t]; k < s_inoff[t + 1]; ++k) {
-            const int ks = in_key[k];
-            ++deg;
-            if (ks < kmin) kmin = ks, first = in_list[k];
-        }
-    }
+    const int deg = !computed ? 0 : (ONE ? deg1 : s_inoff[t + 1] - s_inoff[t]);
     const int pairs = (deg + 1) >> 1;
     const int over = pairs > REC_INLINE_PAIRS ? 2 * (pairs - REC_INLINE_PAIRS) : 0;
-    gsync(G);
     if (computed) s_deg[t] = over;
     gsync(G);
     // first overflow edge of every position, in topological order; level starts
@@ -676,58 +889,65 @@ __device__ __forceinline__ void topo_genome(const TopoItem &a, size_t g, const G
             prog[r0 + REC_PAIRS + 2 * j] = zs;
             progf[r0 + REC_PAIRS + 2 * j + 1] = 0.0f;
         }
-        // neutral padding edge when the in-degree is odd
-        if (deg & 1) {
-            int slot;
-            float w = 1.0f;
-            if (agg == AGG_SUM || agg == AGG_MEAN) {
-                slot = zs;
-            } else if (agg == AGG_PRODUCT) {
-                slot = zs + 1;
-            } else {  // max / min: the first edge again (min stores -w)
-                slot = s_slot[src_of(e_sd[first])];
-                w = conns[(size_t)first * 4 + 3];
-                if (agg == AGG_MIN) w = -w;
-            }
+        // neutral padding edge when the in-degree is odd: the constant 0
+        // (sum, mean) or 1 (product); for max and min the writer of the first
+        // in-edge repeats it
+        if ((deg & 1) && agg != AGG_MAX && agg != AGG_MIN) {
             const int widx = deg < 2 * REC_INLINE_PAIRS ? r0 + REC_PAIRS + 2 * deg
                                                          : eoff + EDGE_WORDS * (ob + deg - 2 * REC_INLINE_PAIRS);
-            prog[widx] = slot;
-            progf[widx + 1] = w;
+            prog[widx] = agg == AGG_PRODUCT ? zs + 1 : zs;
+            progf[widx + 1] = 1.0f;
         }
     }
-    // aggregation code and overflow begin by row for the edge writers
+    // aggregation code and in-degree by row for the edge writers (the
+    // overflow begin by row is in s_curo)
     int *s_agg = s_deg;
-    if (computed) s_agg[t] = agg;
+    if (computed) s_agg[t] = agg | (deg << 8);
     gsync(G);
-    // real edges: index j = number of in-edges of the destination with a
-    // smaller source key (keys are unique here); j < 6 in the record, the
-    // rest in the overflow array.  The thread that read a connection row
-    // writes its edge (weights of the prefetched rows are still in registers)
-    auto edge = [&](int c, float w) {
-        const int sd = e_sd[c];
-        const int s = src_of(sd);
-        if (s < 0) return;
-        const int d = dst_of(sd);
-        const int ks = s_key[s];
-        int j = 0;
-        for (int k = s_inoff[d]; k < s_inoff[d + 1]; ++k) j += (in_key[k] < ks);
+    // real edges at their index j among the destination's in-edges (found
+    // above; source keys are unique here): j < 6 in the record, the rest in
+    // the overflow array.  The thread that read a connection row writes its
+    // edge (the prefetched rows' weights are still in registers).
+    auto edge = [&](int sd, int j, float w) {
+        const int s = src_of(sd), d = dst_of(sd);
+        const int ad = s_agg[d], aggd = ad & 0xff, degd = ad >> 8;
         const int rd = rec_off(O) + REC_WORDS * (s_pos[d] - I);
-        const int widx = j < 2 * REC_INLINE_PAIRS ? rd + REC_PAIRS + 2 * j
-                                                   : eoff + EDGE_WORDS * (s_curo[d] + j - 2 * REC_INLINE_PAIRS);
+        const int ob = s_curo[d];
+        const int slot = s_slot[s];
         // min is stored as max over negated weights (negation is exact)
-        prog[widx] = s_slot[s];
-        progf[widx + 1] = s_agg[d] == AGG_MIN ? -w : w;
+        const float wv = aggd == AGG_MIN ? -w : w;
+        auto put = [&](int jj) {
+            const int widx = jj < 2 * REC_INLINE_PAIRS ? rd + REC_PAIRS + 2 * jj
+                                                        : eoff + EDGE_WORDS * (ob + jj - 2 * REC_INLINE_PAIRS);
+            prog[widx] = slot;
+            progf[widx + 1] = wv;
+        };
+        put(j);
+        // max / min of an odd in-degree: the first edge once more
+        if (j == 0 && (degd & 1) && (aggd == AGG_MAX || aggd == AGG_MIN)) put(degd);
     };
+    // (one-wave groups pack a rank or an index in bits 8-15)
 #pragma unroll
     for (int k = 0; k < CPRE; ++k)
-        if (t + k * W < C) edge(t + k * W, cpre[k].w);
-    for (int c = t + CPRE * W; c < C; c += W) edge(c, conns[(size_t)c * 4 + 3]);
+        if (sdp[k] >= 0) edge(ONE ? sdp[k] & ~0xff00 : sdp[k], jp[k], cpre[k].w);
+    for (int c = t + CPRE * W; c < C; c += W) {
+        const int sd = e_sd[c];
+        if (sd < 0) continue;
+        int j = 0;
+        if constexpr (ONE) {
+            j = (sd >> 8) & 0xff;
+        } else {
+            const int d = dst_of(sd), ks = s_key[src_of(sd)];
+            for (int k = s_inoff[d]; k < s_inoff[d + 1]; ++k) j += in_key[k] < ks;
+        }
+        edge(ONE ? sd & ~0xff00 : sd, j, conns[(size_t)c * 4 + 3]);
+    }
 }
 
 // Genome g by the workgroup (ONE: a single wave, N_max <= 64).
 template <bool ONE>
 __device__ __forceinline__ void topo_group(const TopoItem &a, long long g) {
-    extern __shared__ int smem[];
+    extern __shared__ __align__(16) int smem[];
     Grp<ONE> G;
     G.t = (int)threadIdx.x, G.W = ONE ? 64 : (int)blockDim.x, G.lane = G.t & 63;
     G.wave = ONE ? 0 : G.t >> 6, G.nw = ONE ? 1 : G.W >> 6;
@@ -812,10 +1032,11 @@ __global__ __launch_bounds__(1024) void classify_batch_kernel(const TopoItem *it
 }  // namespace
 
 size_t topo_lds_bytes(int N, int C) {
-    // 32-bit: 7 N node words, 2 C connection words, the key table (2 H);
-    // 16-bit: 6 N + 2 node entries, C connection entries
-    return sizeof(int) * ((size_t)SH_WORDS + (size_t)7 * N + (size_t)2 * C +
-                          2 * (size_t)hash_size(N)) +
+    // 32-bit: 7 N node words (the packed words padded to a multiple of 4),
+    // 2 C connection words, the key table (2 H); 16-bit: 6 N + 2 node
+    // entries, C connection entries
+    return sizeof(int) * ((size_t)SH_WORDS + (size_t)((N + 3) & ~3) + (size_t)6 * N +
+                          (size_t)2 * C + 2 * (size_t)hash_size(N)) +
            sizeof(int16_t) * ((size_t)6 * N + 2 + (size_t)C);
 }
 
