@@ -3,25 +3,31 @@
 // One workgroup per genome; thread t owns node row t (the block has
 // round_up(N_max, 64) threads).  Everything of one genome lives in LDS:
 //
-//   1. node rows: presence (key not NaN), key / act / agg validity;
-//   2. key -> row map: a stable rank of every well-formed key (counting the
-//      smaller keys), which gives the keys in sorted order for binary search
-//      and detects duplicate keys; presence of the input/output keys;
+//   1. node rows: presence (key not NaN), key / act / agg validity; every
+//      well-formed key goes into an open-addressing key -> row table;
+//   2. a stable rank of every well-formed key (the number of smaller
+//      (key, row) words), which gives the keys in sorted order and detects
+//      duplicate keys; presence of the input/output keys;
 //   3. connection rows, read as one float4 each: padding and disabled rows
-//      are dropped, enabled rows are resolved through the key map into
-//      (source row, destination row) and counted into in/out degrees;
-//   4. exclusive scans of the degrees (wave shuffles + a cross-wave pass) and
-//      a scatter into in- and out-adjacency lists; duplicate edges are found
-//      inside each destination's in-list;
-//   5. level-synchronous Kahn: every round, the nodes with in-degree 0 form
-//      the frontier; lanes are assigned to nodes in key-rank order, so a
-//      ballot + mbcnt prefix count gives each frontier node its position in
-//      (level, key) order; emitted nodes decrement their successors' in-degree
-//      with LDS atomics; nodes never emitted mean a cycle;
-//   6. value slots by liveness (a sequential scan over the positions that
-//      hands each value a free slot and frees it after its last reader),
-//      then the program (program.h): records in topological order, in-edges
-//      sorted by source key, source slots, level starts.
+//      are dropped, enabled rows are resolved through the table into
+//      (source row, destination row);
+//   4. adjacency: groups of more than one wave count degrees, scan them and
+//      scatter in-lists (source keys) and out-lists (destination rows); an
+//      edge's index among its destination's in-edges is the number of
+//      smaller source keys there, and an equal one is a duplicate edge.
+//      One-wave groups (N_max <= 64) keep each row's sources as a 64-bit
+//      mask over key ranks instead: setting a bit already set is a
+//      duplicate edge, and an edge's index is a popcount;
+//   5. level-synchronous Kahn: every round, the nodes whose sources have all
+//      been emitted form the frontier; lanes are assigned to nodes in
+//      key-rank order, so a ballot + mbcnt prefix count gives each frontier
+//      node its position in (level, key) order; nodes never emitted mean a
+//      cycle.  One-wave groups test their masks against the ranks emitted
+//      so far; larger groups decrement in-degrees with LDS atomics;
+//   6. value slots (position, or by liveness in parallel when the largest
+//      genomes need more than 64 slots), then the program (program.h):
+//      records in topological order, in-edges sorted by source key, source
+//      slots, level starts.
 //
 // In recurrent mode (networks with cycles, evaluated by synchronous sweeps)
 // self-loops are not flagged, step 5 is skipped (position = key rank, level
@@ -81,6 +87,12 @@ __device__ __forceinline__ int find_row(float k, const int *hkey, const int *hro
     }
 }
 
+// Packed (key, row) words in LDS: a multiple of 4 (read four at a time), or
+// whole 64-word lists when ranks come from merging per-wave lists.
+__host__ __device__ constexpr int stack_words(int N) {
+    return N <= 256 ? (N + 3) & ~3 : (N + 63) & ~63;
+}
+
 // The two rows of a resolved connection, packed in one LDS word (-1: none).
 __device__ __forceinline__ int src_of(int sd) { return (int)(short)(sd & 0xffff); }
 __device__ __forceinline__ int dst_of(int sd) { return sd >> 16; }
@@ -126,14 +138,11 @@ __device__ int block_excl_scan(int v, int *s_wave, int *total) {
     const int x = wave_incl_add(v);
     if (lane == 63) s_wave[wave] = x;
     __syncthreads();
-    int base = 0, tot = 0;
-    for (int w = 0; w < nw; ++w) {
-        const int c = s_wave[w];
-        base += (w < wave) ? c : 0;
-        tot += c;
-    }
+    // lane w reads wave w's sum; a wave scan adds them up
+    const int incl = wave_incl_add(lane < nw ? s_wave[lane] : 0);
+    const int base = wave > 0 ? __builtin_amdgcn_readlane(incl, wave - 1) : 0;
+    *total = __builtin_amdgcn_readlane(incl, nw - 1);
     __syncthreads();
-    *total = tot;
     return base + x - v;
 }
 
@@ -174,6 +183,17 @@ __device__ __forceinline__ bool gsync_or(const Grp<ONE> &G, bool x) {
     return __syncthreads_or(x);
 }
 
+// The sum of the per-wave values in G.sh[SH_WAVE + w] over the waves before
+// this one (*before) and over all (*total): lane w reads wave w's value, and a
+// wave scan adds them up.
+template <bool ONE>
+__device__ __forceinline__ void wave_partials(const Grp<ONE> &G, int *before, int *total) {
+    const int part = G.lane < G.nw ? G.sh[SH_WAVE + G.lane] : 0;
+    const int incl = wave_incl_add(part);
+    *before = G.wave > 0 ? __builtin_amdgcn_readlane(incl, G.wave - 1) : 0;
+    *total = __builtin_amdgcn_readlane(incl, G.nw - 1);
+}
+
 // Exclusive scan of one value per thread over the group; *total receives
 // the sum.  Every thread of the group must call it.
 template <bool ONE>
@@ -185,14 +205,9 @@ __device__ __forceinline__ int group_excl_scan(const Grp<ONE> &G, int v, int *to
     }
     if (G.lane == 63) G.sh[SH_WAVE + G.wave] = x;
     gsync(G);
-    int base = 0, tot = 0;
-    for (int w = 0; w < G.nw; ++w) {
-        const int c = G.sh[SH_WAVE + w];
-        base += (w < G.wave) ? c : 0;
-        tot += c;
-    }
+    int base;
+    wave_partials(G, &base, total);
     gsync(G);
-    *total = tot;
     return base + x - v;
 }
 
@@ -203,8 +218,9 @@ __device__ __forceinline__ int group_incl_min(const Grp<ONE> &G, int v) {
     if (ONE) return x;
     if (G.lane == 63) G.sh[SH_WAVE + G.wave] = x;
     gsync(G);
-    int before = 0x7fffffff;
-    for (int w = 0; w < G.wave; ++w) before = min(before, G.sh[SH_WAVE + w]);
+    // the minimum over the waves before this one
+    const int part = G.lane < G.wave ? G.sh[SH_WAVE + G.lane] : 0x7fffffff;
+    const int before = __builtin_amdgcn_readlane(wave_incl_min(part), 63);
     gsync(G);
     return min(before, x);
 }
@@ -224,10 +240,14 @@ __device__ __forceinline__ void topo_genome(const TopoItem &a, size_t g, const G
     // (rows, positions, slots, offsets: all below 2^15).  s_stack comes
     // first so that it is 16-byte aligned for the rank's vector reads.
     const int H = hash_size(N);
-    const int N4 = (N + 3) & ~3;
-    int *s_stack = smem;          // [N4] packed (key, row) words (padding: -1); slot
+    const int NS = stack_words(N);
+    // Ranks by merging sorted per-wave lists beat counting all N words for
+    // more than 256 rows.
+    const bool merge = !ONE && N > 256;
+    int *s_stack = smem;          // [NS] packed (key, row) words: by row (padding
+                                  //      -1), or sorted per wave when merging; slot
                                   //      allocation scratch
-    int *s_key = s_stack + N4;    // [N] key of row, -1 absent, -2 malformed
+    int *s_key = s_stack + NS;    // [N] key of row, -1 absent, -2 malformed
     int *s_skey = s_key + N;      // [N] well-formed keys by stable rank; later level of row
     int *s_indeg = s_skey + N;    // [N] in-degree, consumed by Kahn
     int *s_deg = s_indeg + N;     // [N] in-degree kept for the program
@@ -281,7 +301,7 @@ __device__ __forceinline__ void topo_genome(const TopoItem &a, size_t g, const G
         h_key[i] = HASH_EMPTY;
         h_row[i] = 0x7fffffff;
     }
-    if (t >= N && t < N4) s_stack[t] = -1;
+    if (!merge && t >= N && t < NS) s_stack[t] = -1;
     gsync(G);
 
     // ---- 1. node rows
@@ -312,7 +332,7 @@ __device__ __forceinline__ void topo_genome(const TopoItem &a, size_t g, const G
         // room when rows fit in 8 bits, keys being below 2^24; with 10 row
         // bits a key of 2^22 or more marks the genome as wide)
         if (key >= 0 && rb == 10 && key >= (1 << 22)) G.sh[SH_WIDE] = 1;
-        s_stack[t] = key >= 0 ? (int)(((unsigned)key << rb) | (unsigned)t) : -1;
+        if (!merge) s_stack[t] = key >= 0 ? (int)(((unsigned)key << rb) | (unsigned)t) : -1;
     }
     gsync(G);
 
@@ -320,8 +340,52 @@ __device__ __forceinline__ void topo_genome(const TopoItem &a, size_t g, const G
     // input/output presence
     int rank = -1;
     const bool packed = G.sh[SH_WIDE] == 0;
+    if (merge && packed) {
+        // Every wave sorts its rows' (key, row) words in
+        // registers (bitonic network; absent rows and lanes beyond N_max hold
+        // the largest word) into its own list, and a row's rank is the sum
+        // over the lists of the number of words below its own (binary
+        // searches, all lists side by side).
+        const unsigned mine =
+            (t < N && key >= 0) ? (((unsigned)key << rb) | (unsigned)t) : 0xffffffffu;
+        unsigned x = mine;
+#pragma unroll
+        for (int k = 2; k <= 64; k <<= 1)
+#pragma unroll
+            for (int j = k >> 1; j > 0; j >>= 1) {
+                const unsigned y = (unsigned)__shfl_xor((int)x, j, 64);
+                x = (((G.lane & j) == 0) == ((G.lane & k) == 0)) ? min(x, y) : max(x, y);
+            }
+        const int nl = (N + 63) >> 6;  // lists (waves holding rows)
+        if (G.wave < nl) s_stack[G.wave * 64 + G.lane] = (int)x;
+        gsync(G);
+        if (key >= 0) {
+            // eight lists at a time, branch-free (a group's lists past the
+            // last search the last one again and are not counted)
+            const unsigned *sl = reinterpret_cast<const unsigned *>(s_stack);
+            rank = 0;
+            for (int w0 = 0; w0 < nl; w0 += 8) {
+                int pos[8];
+#pragma unroll
+                for (int w = 0; w < 8; ++w) pos[w] = 0;
+#pragma unroll
+                for (int d = 64; d > 0; d >>= 1) {
+                    unsigned v[8];
+#pragma unroll
+                    for (int w = 0; w < 8; ++w)
+                        v[w] = sl[min(w0 + w, nl - 1) * 64 + min(pos[w] + d - 1, 63)];
+#pragma unroll
+                    for (int w = 0; w < 8; ++w) pos[w] += (pos[w] + d <= 64 && v[w] < mine) ? d : 0;
+                }
+#pragma unroll
+                for (int w = 0; w < 8; ++w) rank += w0 + w < nl ? pos[w] : 0;
+            }
+        }
+    }
     if (key >= 0) {
-        if (packed) {
+        if (merge && packed) {
+            // ranked above
+        } else if (packed) {
             // rank = number of (key, row) words below this row's (the words
             // are distinct; absent and malformed rows and the padding hold
             // the largest), read four at a time (every lane the same address)
@@ -329,7 +393,7 @@ __device__ __forceinline__ void topo_genome(const TopoItem &a, size_t g, const G
             const uint4 *comp = reinterpret_cast<const uint4 *>(s_stack);
             int less = 0;
 #pragma unroll 4
-            for (int q = 0; q < (N4 >> 2); ++q) {
+            for (int q = 0; q < (NS >> 2); ++q) {
                 const uint4 v = comp[q];
                 less += (v.x < mine) + (v.y < mine) + (v.z < mine) + (v.w < mine);
             }
@@ -624,7 +688,7 @@ __device__ __forceinline__ void topo_genome(const TopoItem &a, size_t g, const G
                 ++n_levels;
             }
         } else {
-            const int lane = G.lane, wave = G.wave, nw = G.nw;
+            const int lane = G.lane, wave = G.wave;
             bool emitted = false;
             const int ob = my_row >= 0 ? s_outoff[my_row] : 0;
             const int oe = my_row >= 0 ? s_outoff[my_row + 1] : 0;
@@ -633,25 +697,24 @@ __device__ __forceinline__ void topo_genome(const TopoItem &a, size_t g, const G
                 const unsigned long long m = __ballot(ready);
                 if (lane == 0) G.sh[SH_WAVE + wave] = __popcll(m);
                 gsync(G);
-                int wbase = 0, total = 0;
-                for (int w = 0; w < nw; ++w) {
-                    const int c = G.sh[SH_WAVE + w];
-                    wbase += (w < wave) ? c : 0;
-                    total += c;
-                }
+                int wbase, total;
+                wave_partials(G, &wbase, &total);
                 if (total == 0) break;  // uniform across the block
                 if (ready) {
                     s_pos[my_row] = base + wbase + mbcnt(m);
                     my_level = n_levels;
                     emitted = true;
-                    // successors read two at a time, then decremented
+                    // successors read four at a time, then decremented
                     int k = ob;
-                    for (; k + 1 < oe; k += 2) {
+                    for (; k + 3 < oe; k += 4) {
                         const int d0 = out_list[k], d1 = out_list[k + 1];
+                        const int d2 = out_list[k + 2], d3 = out_list[k + 3];
                         atomicSub(&s_indeg[d0], 1);
                         atomicSub(&s_indeg[d1], 1);
+                        atomicSub(&s_indeg[d2], 1);
+                        atomicSub(&s_indeg[d3], 1);
                     }
-                    if (k < oe) atomicSub(&s_indeg[out_list[k]], 1);
+                    for (; k < oe; ++k) atomicSub(&s_indeg[out_list[k]], 1);
                 }
                 gsync(G);
                 base += total;
@@ -1032,10 +1095,10 @@ __global__ __launch_bounds__(1024) void classify_batch_kernel(const TopoItem *it
 }  // namespace
 
 size_t topo_lds_bytes(int N, int C) {
-    // 32-bit: 7 N node words (the packed words padded to a multiple of 4),
-    // 2 C connection words, the key table (2 H); 16-bit: 6 N + 2 node
-    // entries, C connection entries
-    return sizeof(int) * ((size_t)SH_WORDS + (size_t)((N + 3) & ~3) + (size_t)6 * N +
+    // 32-bit: 7 N node words (the packed words padded, stack_words), 2 C
+    // connection words, the key table (2 H); 16-bit: 6 N + 2 node entries,
+    // C connection entries
+    return sizeof(int) * ((size_t)SH_WORDS + (size_t)stack_words(N) + (size_t)6 * N +
                           (size_t)2 * C + 2 * (size_t)hash_size(N)) +
            sizeof(int16_t) * ((size_t)6 * N + 2 + (size_t)C);
 }
