@@ -54,11 +54,30 @@ def measured_profile():
         return None, None
 
 
+def ramp(args, torch, fn):
+    """Run fn untimed until args.ramp_ms of wall time has passed, so that the
+    GPU's clocks have left their idle state before the warmup and the timed
+    steps: a GPU that was idle runs its first tens of milliseconds of work
+    slower (the control step measured 0.234 ms over 20 steps after 3 warmup
+    steps, 0.202 ms once warm)."""
+    if args.ramp_ms <= 0:
+        return
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    while (time.perf_counter() - t) * 1e3 < args.ramp_ms:
+        for _ in range(4):
+            fn()
+        torch.cuda.synchronize()
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--ramp-ms", type=float, default=50.0,
+                    help="untimed run of each workload's step before its warmup steps, "
+                         "until this much wall time has passed (GPU clock ramp); 0: none")
     ap.add_argument("--P", type=int, default=10000)
     ap.add_argument("--B", type=int, default=1000)
     ap.add_argument("--cpu-genomes", type=int, default=10000,
@@ -148,6 +167,7 @@ def bench_control_forms(args, torch, neat, pop, tn, tc, tx, parts=10):
     plan, plan1 = neat.BatchPlan(), neat.BatchPlan()
 
     def timed(fn):
+        ramp(args, torch, fn)
         for _ in range(max(1, args.warmup)):
             fn()
         torch.cuda.synchronize()
@@ -203,6 +223,7 @@ def bench_batched(args, torch, neat, synth):
     stream = torch.cuda.current_stream()
 
     def timed(fn, steps):
+        ramp(args, torch, fn)
         for _ in range(max(1, args.warmup)):
             fn()
         torch.cuda.synchronize()
@@ -303,6 +324,7 @@ def bench_tiny(args, torch, neat, synth):
         neat.topo_sort(tn, tc, pop.I, pop.O, program=prog, status=st, want_order=False)
         neat.forward(d, prog, tx, pop.B, shared_inputs=True, outputs=y)
 
+    ramp(args, torch, call)
     for _ in range(20):
         call()
     torch.cuda.synchronize()
@@ -583,6 +605,7 @@ def bench_cppn(args, torch, neat, synth):
     _, _, st, prog = neat.topo_sort(tn, tc, pop.I, pop.O, want_order=False)
     Q = 65536
     y = torch.empty((pop.P, Q, pop.O), device=dev)
+    ramp(args, torch, lambda: neat.forward_grid(d, prog, 16, 0, Q, outputs=y))
     for _ in range(max(1, args.warmup)):
         neat.forward_grid(d, prog, 16, 0, Q, outputs=y)
     torch.cuda.synchronize()
@@ -632,6 +655,7 @@ def bench_substrate(args, torch, neat, synth):
     d = neat.dims_of(tn, tc, 5, 1)
     w = torch.empty((pop.P, S, S), dtype=torch.float32, device=dev)
     y = torch.empty((pop.P, X.shape[0], S), dtype=torch.float32, device=dev)
+    ramp(args, torch, lambda: neat.substrate_forward(d, prog, side, X, 0.2, weights=w, outputs=y))
     for _ in range(max(1, args.warmup)):
         neat.substrate_forward(d, prog, side, X, 0.2, weights=w, outputs=y)
     torch.cuda.synchronize()
@@ -673,6 +697,7 @@ def bench_distance(args, torch, neat, synth):
     rep = synth.control(seed=7, P=64, B=1, with_inputs=False)
     t = [torch.from_numpy(a).to(dev) for a in (pop.nodes, pop.conns, rep.nodes, rep.conns)]
     out = torch.empty((pop.P, rep.P), dtype=torch.float32, device=dev)
+    ramp(args, torch, lambda: neat.distance(*t, out=out))
     for _ in range(max(1, args.warmup)):
         neat.distance(*t, out=out)
     torch.cuda.synchronize()
@@ -706,6 +731,7 @@ def bench_crossover(args, torch, neat, synth):
     rc = torch.from_numpy(rng.random((pop.P, 200)).astype(np.float32)).to(dev)
     tn, tc = torch.from_numpy(pop.nodes).to(dev), torch.from_numpy(pop.conns).to(dev)
     cn, cc = neat.crossover(tn, tc, pairs, rn, rc)
+    ramp(args, torch, lambda: neat.crossover(tn, tc, pairs, rn, rc, cn, cc))
     for _ in range(max(1, args.warmup)):
         neat.crossover(tn, tc, pairs, rn, rc, cn, cc)
     torch.cuda.synchronize()
@@ -788,6 +814,7 @@ def bench_recurrent(args, torch, neat, synth):
         neat.topo_sort(tn, tc, pop.I, pop.O, program=prog, want_order=False, recurrent=True)
         neat.forward_recurrent(d, prog, tx, pop.B, K, outputs=out)
 
+    ramp(args, torch, step)
     for _ in range(max(1, args.warmup)):
         step()
     torch.cuda.synchronize()
@@ -934,6 +961,7 @@ def main():
                                          ctypes.c_void_p(tx.data_ptr()), pop.B * pop.I, pop.B,
                                          ctypes.c_void_p(out.data_ptr()), sp))
 
+    ramp(args, torch, lambda: (topo(), fwd()))
     for _ in range(args.warmup):
         topo()
         fwd()
@@ -1046,7 +1074,7 @@ def main():
     res = {
         "metric": "genome-input forwards/s", "value": round(value, 1),
         "unit": "genome-inputs/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": round(step_ms, 4),
+        "warmup": args.warmup, "ramp_ms": args.ramp_ms, "ms_per_step": round(step_ms, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": "control-policy population: P=%d genomes, N_max=50, "
