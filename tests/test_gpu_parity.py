@@ -362,6 +362,49 @@ def test_forward_kernel_shapes(N, I, O, variant):
     _assert_outputs(y, y64, beta, "shape N=%d I=%d O=%d variant=%d" % (N, I, O, variant))
 
 
+@pytest.mark.parametrize("N", [50, 64])
+def test_one_wave_genomes_with_long_connection_lists(N):
+    """One-wave genomes (N_max <= 64) with C_max = 700 connection rows, more
+    than the four rows per lane the transformation keeps in registers: rows
+    256 and beyond go through LDS.  Duplicate edges are planted within the
+    first 256 rows, within the rest and across the two ranges (a duplicate
+    is the same source and destination keys on two enabled rows), and
+    enabled rows are disabled at random; transformation bit-exact, outputs
+    within the parity rule.  N_max = 64 also takes the liveness slots."""
+    rng = np.random.default_rng(700 + N)
+    P, B, C, I, O = 48, 70, 700, 9, 4
+    nodes = np.full((P, N, 5), np.nan, np.float32)
+    conns = np.full((P, C, 4), np.nan, np.float32)
+    for p in range(P):
+        synth.make_genome(rng, N, C, I, O, N - I - O,
+                          lambda na: int(rng.integers(min(C, na) // 2, min(C, na) + 1)),
+                          synth.CONTROL_ACTS, synth.ALL_AGGS, nodes_out=nodes[p],
+                          conns_out=conns[p])
+    # a few rows disabled first (their edges neither count nor duplicate)
+    off = (rng.random((P, C)) < 0.05) & (conns[:, :, 2] == 1.0)
+    conns[:, :, 2][off] = 0.0
+    lo, hi = set(range(256)), list(range(256, C))
+    for p in range(P):
+        kind = p % 4
+        if kind == 0:
+            continue
+        enabled = np.nonzero(conns[p, :, 2] == 1.0)[0]
+        a = [r for r in enabled if (r in lo) == (kind in (1, 3))]
+        dst_range = hi if kind in (1, 2) else sorted(lo)
+        ra = a[0]
+        rb = next(r for r in dst_range if r != ra)
+        conns[p, rb, :3] = conns[p, ra, :3]
+        conns[p, rb, 3] = conns[p, ra, 3] + 0.5
+    x = rng.standard_normal((P, B, I)).astype(np.float32)
+    order, level, status, y = _gpu(nodes, conns, I, O, x)
+    _assert_transform_exact(nodes, conns, I, O, order, level, status)
+    assert (status[0::4] == 0).all()
+    assert all(status[k::4].astype(bool).all() for k in (1, 2, 3))
+    assert all((status[k::4] & oracle.DUP_EDGE).all() for k in (1, 2, 3))
+    y64, beta = oracle.forward(nodes, conns, x, I, O)
+    _assert_outputs(y, y64, beta, "one-wave N=%d C=%d" % (N, C))
+
+
 def test_wide_fan_in_every_aggregation():
     """Nodes with more incoming edges than the eight the forward keeps in
     registers (24 and 40 terms), for every aggregation."""
