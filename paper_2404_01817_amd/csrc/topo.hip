@@ -74,6 +74,14 @@ __device__ __forceinline__ int hash_insert(int *hkey, int *hrow, int H, int key,
         h = (h + 1) & (H - 1);
     }
 }
+// k as a well-formed key (an integer in [0, 2^24)), else -1, without
+// branches: the clamp keeps the conversion in range (NaN becomes -1), and
+// the conversion back must give k again.
+__device__ __forceinline__ int key_of(float k) {
+    const int i = (int)fminf(fmaxf(k, -1.0f), KEY_LIMIT);
+    return ((float)i == k && (unsigned)i < (1u << 24)) ? i : -1;
+}
+
 // Table word of the well-formed key equal to k, or -1.  The word's low 16
 // bits are the first row among duplicates; one-wave groups later add the
 // key's rank above them.
@@ -277,8 +285,11 @@ __device__ __forceinline__ void topo_genome(const TopoItem &a, size_t g, const G
     constexpr int CPRE = 4;
     float4 cpre[CPRE];
 #pragma unroll
-    for (int k = 0; k < CPRE; ++k)
+    for (int k = 0; k < CPRE; ++k) {
+        const float nan = __builtin_nanf("");
+        cpre[k] = make_float4(nan, nan, nan, nan);  // past C_max: a padding row
         if (t + k * W < C) cpre[k] = conns4[t + k * W];
+    }
     float nrow[5];
     if (t < N) {
 #pragma unroll
@@ -291,10 +302,12 @@ __device__ __forceinline__ void topo_genome(const TopoItem &a, size_t g, const G
         G.sh[SH_WIDE] = 0;
     }
     for (int i = t; i < N; i += W) {
-        s_indeg[i] = 0;
-        s_curo[i] = 0;
+        if (!ONE) {  // one-wave groups write these before any read
+            s_indeg[i] = 0;
+            s_curo[i] = 0;
+            s_pos[i] = -1;
+        }
         s_curi[i] = 0;
-        s_pos[i] = -1;
         s_skey[i] = -1;
     }
     for (int i = t; i < H; i += W) {
@@ -424,7 +437,9 @@ __device__ __forceinline__ void topo_genome(const TopoItem &a, size_t g, const G
     // gets the key's rank above its row.
     if constexpr (ONE) {
         gsync(G);  // the duplicate-key check has read s_skey
-        if (key >= 0 && h_row[my_h] == t) h_row[my_h] = t | (rank << 16);
+        // (with duplicated keys the last writer wins; such a genome is
+        // rejected, and its other status bits depend on keys only)
+        if (key >= 0) h_row[my_h] = t | (rank << 16);
         if (t < N) {
             s_stack[t] = 0;
             s_skey[t] = 0;
@@ -476,9 +491,15 @@ __device__ __forceinline__ void topo_genome(const TopoItem &a, size_t g, const G
         int key2[2 * CPRE], hs[2 * CPRE], hk[2 * CPRE];
 #pragma unroll
         for (int k = 0; k < CPRE; ++k) {
-            const bool on = t + k * W < C && enabled(cpre[k]);
-            key2[k] = on && is_int_in(cpre[k].x, 0.0f, KEY_LIMIT) ? (int)cpre[k].x : -1;
-            key2[CPRE + k] = on && is_int_in(cpre[k].y, 0.0f, KEY_LIMIT) ? (int)cpre[k].y : -1;
+            // enabled (flag 1), padding or disabled (NaN source, flag 0), or a
+            // bad flag; branch-free
+            const float4 r = cpre[k];
+            const bool live = !isnan(r.x) & (r.z != 0.0f);
+            const bool bad = live & (r.z != 1.0f);
+            st |= bad ? (unsigned)NEAT_ST_BAD_VALUE : 0u;
+            const bool on = live & !bad;
+            key2[k] = on ? key_of(r.x) : -1;
+            key2[CPRE + k] = on ? key_of(r.y) : -1;
             sdp[k] = on ? -2 : -1;  // -2: enabled, endpoints to resolve
         }
 #pragma unroll
@@ -674,12 +695,13 @@ __device__ __forceinline__ void topo_genome(const TopoItem &a, size_t g, const G
                 pm = (unsigned long long)(unsigned)s_stack[my_row] |
                      ((unsigned long long)(unsigned)s_skey[my_row] << 32);
             bool emitted = false;
+            int my_pos = -1;
             for (;;) {
                 const bool ready = my_row >= 0 && !emitted && (pm & ~done) == 0ull;
                 const unsigned long long m = __ballot(ready);
                 if (m == 0ull) break;
                 if (ready) {
-                    s_pos[my_row] = base + mbcnt(m);
+                    my_pos = base + mbcnt(m);
                     my_level = n_levels;
                     emitted = true;
                 }
@@ -687,6 +709,7 @@ __device__ __forceinline__ void topo_genome(const TopoItem &a, size_t g, const G
                 base += __popcll(m);
                 ++n_levels;
             }
+            if (emitted) s_pos[my_row] = my_pos;
         } else {
             const int lane = G.lane, wave = G.wave;
             bool emitted = false;
