@@ -95,10 +95,45 @@ __device__ __forceinline__ int find_row(float k, const int *hkey, const int *hro
     }
 }
 
+// Threads of a genome's group, and the connection rows kept in LDS: none
+// when every row stays in a thread's registers (at most four per thread).
+__host__ __device__ constexpr int group_threads(int N) { return N <= 64 ? 64 : (N + 63) & ~63; }
+__host__ __device__ constexpr int stored_conns(int N, int C) {
+    return C > 4 * group_threads(N) ? C : 0;
+}
+
+// Ranks by merging sorted per-wave lists take fewer instructions than
+// counting all N words for more than MERGE_MIN rows.
+constexpr int MERGE_MIN = 128;
+
 // Packed (key, row) words in LDS: a multiple of 4 (read four at a time), or
 // whole 64-word lists when ranks come from merging per-wave lists.
 __host__ __device__ constexpr int stack_words(int N) {
-    return N <= 256 ? (N + 3) & ~3 : (N + 63) & ~63;
+    return N <= MERGE_MIN ? (N + 3) & ~3 : (N + 63) & ~63;
+}
+
+// The number of words below mine over nl sorted lists of 64 words at sl:
+// branch-free binary searches, G lists side by side (a group's lists past
+// the last search the last one again and are not counted).
+template <int G>
+__device__ __forceinline__ int merged_rank(const unsigned *sl, int nl, unsigned mine) {
+    int rank = 0;
+    for (int w0 = 0; w0 < nl; w0 += G) {
+        int pos[G];
+#pragma unroll
+        for (int w = 0; w < G; ++w) pos[w] = 0;
+#pragma unroll
+        for (int d = 64; d > 0; d >>= 1) {
+            unsigned v[G];
+#pragma unroll
+            for (int w = 0; w < G; ++w) v[w] = sl[min(w0 + w, nl - 1) * 64 + min(pos[w] + d - 1, 63)];
+#pragma unroll
+            for (int w = 0; w < G; ++w) pos[w] += (pos[w] + d <= 64 && v[w] < mine) ? d : 0;
+        }
+#pragma unroll
+        for (int w = 0; w < G; ++w) rank += w0 + w < nl ? pos[w] : 0;
+    }
+    return rank;
 }
 
 // The two rows of a resolved connection, packed in one LDS word (-1: none).
@@ -249,9 +284,7 @@ __device__ __forceinline__ void topo_genome(const TopoItem &a, size_t g, const G
     // first so that it is 16-byte aligned for the rank's vector reads.
     const int H = hash_size(N);
     const int NS = stack_words(N);
-    // Ranks by merging sorted per-wave lists beat counting all N words for
-    // more than 256 rows.
-    const bool merge = !ONE && N > 256;
+    const bool merge = !ONE && N > MERGE_MIN;
     int *s_stack = smem;          // [NS] packed (key, row) words: by row (padding
                                   //      -1), or sorted per wave when merging; slot
                                   //      allocation scratch
@@ -261,11 +294,12 @@ __device__ __forceinline__ void topo_genome(const TopoItem &a, size_t g, const G
     int *s_deg = s_indeg + N;     // [N] in-degree kept for the program
     int *s_curo = s_deg + N;      // [N] out-degree, out cursor, later edge begin by row
     int *s_curi = s_curo + N;     // [N] io presence, in cursor, later row by position
-    int *e_sd = s_curi + N;       // [C] connection row: source row | destination row << 16,
-                                  //     -1 if unused (rows < 2^10); written only for the
-                                  //     rows a thread does not keep in registers
-    int *in_key = e_sd + C;       // [C] source keys of the in-edges, grouped by destination
-    int *h_key = in_key + C;      // [H] key -> row table: keys
+    const int CE = stored_conns(N, C);
+    int *e_sd = s_curi + N;       // [CE] connection row: source row | destination row << 16,
+                                  //      -1 if unused (rows < 2^10): the rows a thread
+                                  //      does not keep in registers
+    int *h_key = e_sd + CE;       // [H] key -> row table: keys; after the lookups
+                                  //     (larger groups) the key rank of every row
     int *h_row = h_key + H;       // [H] rows
     int16_t *s_srow = reinterpret_cast<int16_t *>(h_row + H);  // [N] row by rank
     int16_t *s_inoff = s_srow + N;      // [N+1] in-edge offsets (<= C_max <= 2^14)
@@ -275,6 +309,9 @@ __device__ __forceinline__ void topo_genome(const TopoItem &a, size_t g, const G
     int16_t *s_oval = s_slot + N;       // [N] slot allocation scratch
     uint16_t *out_list = reinterpret_cast<uint16_t *>(s_oval + N);  // [C] destination rows
                                         //     grouped by source
+    int16_t *in_rank = reinterpret_cast<int16_t *>(out_list + C);  // [C] source key ranks of
+                                        //     the in-edges, grouped by destination
+    int16_t *s_rnk = reinterpret_cast<int16_t *>(h_key);  // [N] key rank of row (-1: none)
 
     const float *nodes = a.nodes + g * (size_t)N * 5;
     const float *conns = a.conns + g * (size_t)C * 4;
@@ -373,26 +410,8 @@ __device__ __forceinline__ void topo_genome(const TopoItem &a, size_t g, const G
         if (G.wave < nl) s_stack[G.wave * 64 + G.lane] = (int)x;
         gsync(G);
         if (key >= 0) {
-            // eight lists at a time, branch-free (a group's lists past the
-            // last search the last one again and are not counted)
             const unsigned *sl = reinterpret_cast<const unsigned *>(s_stack);
-            rank = 0;
-            for (int w0 = 0; w0 < nl; w0 += 8) {
-                int pos[8];
-#pragma unroll
-                for (int w = 0; w < 8; ++w) pos[w] = 0;
-#pragma unroll
-                for (int d = 64; d > 0; d >>= 1) {
-                    unsigned v[8];
-#pragma unroll
-                    for (int w = 0; w < 8; ++w)
-                        v[w] = sl[min(w0 + w, nl - 1) * 64 + min(pos[w] + d - 1, 63)];
-#pragma unroll
-                    for (int w = 0; w < 8; ++w) pos[w] += (pos[w] + d <= 64 && v[w] < mine) ? d : 0;
-                }
-#pragma unroll
-                for (int w = 0; w < 8; ++w) rank += w0 + w < nl ? pos[w] : 0;
-            }
+            rank = nl <= 4 ? merged_rank<4>(sl, nl, mine) : merged_rank<8>(sl, nl, mine);
         }
     }
     if (key >= 0) {
@@ -591,6 +610,9 @@ __device__ __forceinline__ void topo_genome(const TopoItem &a, size_t g, const G
             if (sd >= 0) e_sd[c] = (sd & ~0xff00) | (below(sd >> 16, (sd >> 8) & 0xff) << 8);
         }
     } else {
+        // the key table is done with: it now holds every row's key rank, and
+        // the in-lists compare ranks (the same order as keys, 16 bits)
+        if (t < N) s_rnk[t] = (int16_t)rank;
         {
             const int din = (t < N) ? s_indeg[t] : 0;
             const int dout = (t < N) ? s_curo[t] : 0;
@@ -610,29 +632,31 @@ __device__ __forceinline__ void topo_genome(const TopoItem &a, size_t g, const G
             }
         }
         gsync(G);
-        // scatter: a destination's in-list holds the source keys, a source's
-        // out-list the destination rows
-        auto scatter = [&](int sd, int ks) {
+        // scatter: a destination's in-list holds the source key ranks, a
+        // source's out-list the destination rows
+        auto scatter = [&](int sd, int rs) {
             const int s = src_of(sd), d = dst_of(sd);
-            in_key[s_inoff[d] + atomicAdd(&s_curi[d], 1)] = ks;
+            in_rank[s_inoff[d] + atomicAdd(&s_curi[d], 1)] = (int16_t)rs;
             out_list[s_outoff[s] + atomicAdd(&s_curo[s], 1)] = (uint16_t)d;
         };
-    #pragma unroll
+#pragma unroll
+        for (int k = 0; k < CPRE; ++k) ksp[k] = sdp[k] >= 0 ? s_rnk[src_of(sdp[k])] : -1;
+#pragma unroll
         for (int k = 0; k < CPRE; ++k)
             if (sdp[k] >= 0) scatter(sdp[k], ksp[k]);
         for (int c = t + CPRE * W; c < C; c += W) {
             const int sd = e_sd[c];
-            if (sd >= 0) scatter(sd, s_key[src_of(sd)]);
+            if (sd >= 0) scatter(sd, s_rnk[src_of(sd)]);
         }
         gsync(G);
         // every edge's index among its destination's in-edges by source key (the
-        // number of smaller source keys) and duplicate edges (an equal source
-        // key besides its own).  The prefetched rows walk their in-lists side by
-        // side, so their reads overlap; their indices stay in registers.
+        // number of smaller source ranks) and duplicate edges (an equal source
+        // rank besides its own).  The prefetched rows walk their in-lists side
+        // by side, so their reads overlap; their indices stay in registers.
         {
             int base[CPRE], cnt[CPRE], eq[CPRE];
             int m = 0;
-    #pragma unroll
+#pragma unroll
             for (int k = 0; k < CPRE; ++k) {
                 base[k] = 0;
                 cnt[k] = 0;
@@ -646,26 +670,26 @@ __device__ __forceinline__ void topo_genome(const TopoItem &a, size_t g, const G
                 eq[k] = 0;
             }
             for (int i = 0; i < m; ++i) {
-    #pragma unroll
+#pragma unroll
                 for (int k = 0; k < CPRE; ++k) {
                     // an exhausted list re-reads its last entry (or entry 0 of
                     // a row with no list, which exists since m > 0)
-                    const int q = in_key[base[k] + min(i, max(cnt[k] - 1, 0))];
+                    const int q = in_rank[base[k] + min(i, max(cnt[k] - 1, 0))];
                     const bool v = i < cnt[k];
                     jp[k] += (v && q < ksp[k]) ? 1 : 0;
                     eq[k] += (v && q == ksp[k]) ? 1 : 0;
                 }
             }
-    #pragma unroll
+#pragma unroll
             for (int k = 0; k < CPRE; ++k)
                 if (eq[k] > 1) st |= NEAT_ST_DUP_EDGE;
         }
         for (int c = t + CPRE * W; c < C; c += W) {
             const int sd = e_sd[c];
             if (sd < 0) continue;
-            const int d = dst_of(sd), ks = s_key[src_of(sd)];
+            const int d = dst_of(sd), rs = s_rnk[src_of(sd)];
             int eq = 0;
-            for (int k = s_inoff[d]; k < s_inoff[d + 1]; ++k) eq += in_key[k] == ks;
+            for (int k = s_inoff[d]; k < s_inoff[d + 1]; ++k) eq += in_rank[k] == rs;
             if (eq > 1) st |= NEAT_ST_DUP_EDGE;
         }
     }
@@ -1023,8 +1047,8 @@ __device__ __forceinline__ void topo_genome(const TopoItem &a, size_t g, const G
         if constexpr (ONE) {
             j = (sd >> 8) & 0xff;
         } else {
-            const int d = dst_of(sd), ks = s_key[src_of(sd)];
-            for (int k = s_inoff[d]; k < s_inoff[d + 1]; ++k) j += in_key[k] < ks;
+            const int d = dst_of(sd), rs = s_rnk[src_of(sd)];
+            for (int k = s_inoff[d]; k < s_inoff[d + 1]; ++k) j += in_rank[k] < rs;
         }
         edge(ONE ? sd & ~0xff00 : sd, j, conns[(size_t)c * 4 + 3]);
     }
@@ -1118,12 +1142,12 @@ __global__ __launch_bounds__(1024) void classify_batch_kernel(const TopoItem *it
 }  // namespace
 
 size_t topo_lds_bytes(int N, int C) {
-    // 32-bit: 7 N node words (the packed words padded, stack_words), 2 C
-    // connection words, the key table (2 H); 16-bit: 6 N + 2 node entries,
-    // C connection entries
+    // 32-bit: 7 N node words (the packed words padded, stack_words), the
+    // connection rows kept in LDS (stored_conns), the key table (2 H);
+    // 16-bit: 6 N + 2 node entries, 2 C connection entries
     return sizeof(int) * ((size_t)SH_WORDS + (size_t)stack_words(N) + (size_t)6 * N +
-                          (size_t)2 * C + 2 * (size_t)hash_size(N)) +
-           sizeof(int16_t) * ((size_t)6 * N + 2 + (size_t)C);
+                          (size_t)stored_conns(N, C) + 2 * (size_t)hash_size(N)) +
+           sizeof(int16_t) * ((size_t)6 * N + 2 + (size_t)2 * C);
 }
 
 

@@ -580,8 +580,9 @@ def test_largest_nodes_in_half_wave_lds_tiles():
 def test_beyond_the_lds_row_store_is_refused():
     """I + N_max beyond the half-wave store's 1278 (N_max = 1024 with 300
     inputs) transforms but is refused by the forward with a clean
-    NEAT_E_TOO_LARGE before any launch; C_max = 16384 does not fit the
-    transformation's LDS and is refused by it."""
+    NEAT_E_TOO_LARGE before any launch; N_max = 1024 with C_max = 16384 does
+    not fit the transformation's LDS and is refused by it, while a one-wave
+    genome with C_max = 16384 fits and transforms exactly."""
     neat = _neat()
     dev = torch.device("cuda:0")
     I = 300
@@ -600,6 +601,15 @@ def test_beyond_the_lds_row_store_is_refused():
     o_order, o_level, o_status = oracle.transform(nodes, conns, I, 1)
     assert np.array_equal(o_order, order.cpu().numpy())
     assert np.array_equal(o_status, status.cpu().numpy().astype(np.uint32))
-    big = torch.full((1, 64, 5), float("nan"), device=dev)
-    with pytest.raises(neat.NeatError):
+    big = torch.full((1, 1024, 5), float("nan"), device=dev)
+    with pytest.raises(neat.NeatError) as e:
         neat.topo_sort(big, torch.full((1, 16384, 4), float("nan"), device=dev), 3, 1)
+    assert e.value.code == -1  # NEAT_E_INVALID: the working set does not fit in LDS
+    rng = np.random.default_rng(16384)
+    nodes = np.full((3, 64, 5), np.nan, np.float32)
+    conns = np.full((3, 16384, 4), np.nan, np.float32)
+    for p in range(3):
+        synth.make_genome(rng, 64, 16384, 7, 3, 54, lambda na: na, synth.CONTROL_ACTS,
+                          synth.ALL_AGGS, nodes_out=nodes[p], conns_out=conns[p])
+    order, level, status, _ = _gpu(nodes, conns, 7, 3)
+    _assert_transform_exact(nodes, conns, 7, 3, order, level, status)
