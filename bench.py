@@ -127,12 +127,13 @@ def program_bytes_read(O, n_valid, n_edges, I):
     return int((64 + 4 * O + 16 * n_comp + 8 * n_edges).sum())
 
 
-def bench_control_forms(args, torch, neat, pop, tn, tc, tx, parts=10):
+def bench_control_forms(args, torch, neat, pop, tn, tc, tx, step_bytes, parts=10):
     """The control workload (P=10000, N_max=50, B=1000) as `parts`
     populations of P/parts genomes: plain (one neat_topo_sort and one
     neat_forward per population) against batched (all populations as one
     recorded batch, transformation + calculation per replay), and the whole
-    population as a single batch item."""
+    population as a single batch item; each form's end-to-end HBM fraction
+    from the step's algorithmic bytes (step_bytes)."""
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream()
     sp = ctypes.c_void_p(stream.cuda_stream)
@@ -195,6 +196,10 @@ def bench_control_forms(args, torch, neat, pop, tn, tc, tx, parts=10):
             "batched_speedup": round(ms_plain / ms_batch, 3),
             "one_item_batched_ms": round(ms_one, 4),
             "one_item_batched_value": round(units / (ms_one / 1e3), 1),
+            "hbm_frac_end_to_end": {
+                k: round(step_bytes / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)
+                for k, ms in (("plain", ms_plain), ("batched", ms_batch),
+                              ("one_item_batched", ms_one))},
             "outputs_identical": bool(same), "unit": "genome-inputs/s"}
 
 
@@ -1009,6 +1014,14 @@ def main():
                 "rocprof_avg_launch_us": prof_us,
                 "frac_rocprof": (round(fwd_bytes / (prof_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)
                                  if prof_us else None)}
+    # the whole step against the same peak: the transformation reads the
+    # node and connection rows and writes the status and the program (at
+    # least what the forward reads of it), then the forward's bytes
+    step_bytes = (pop.P * (20 * pop.N_max + 16 * pop.C_max + 4) + pbytes) + fwd_bytes
+    step_roofline = {"bound": "hbm", "algorithmic_bytes_per_step": step_bytes,
+                     "achieved": round(step_bytes / (step_ms / 1e3) / 1e9, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(step_bytes / (step_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
 
     # each forward variant on the same program, for the record
     variants = {}
@@ -1055,7 +1068,7 @@ def main():
         cpu = cpu_baseline(args, pop)
 
     workloads = set(args.workloads.split(","))
-    forms = (bench_control_forms(args, torch, neat, pop, tn, tc, tx)
+    forms = (bench_control_forms(args, torch, neat, pop, tn, tc, tx, step_bytes)
              if "batched" in workloads else None)
     batched = bench_batched(args, torch, neat, synth) if "batched" in workloads else None
     served = bench_served(args, torch, neat, synth) if "served" in workloads else None
@@ -1086,6 +1099,7 @@ def main():
         "forward_variant_ms": variants,
         "rejected_genomes": n_bad,
         "roofline": roofline,
+        "step_roofline": step_roofline,
         "cpu_baseline": cpu,
         "control_batched_vs_plain": forms,
         "batched": batched,
