@@ -23,7 +23,9 @@
 // node operations in C++.
 //
 // Work units.  A launch covers one or more populations ("items"); item j
-// contributes P_j x chunks_j wave units, unit (i, c) being run c of the
+// contributes P_j x chunks_j wave units (chunks_j from the item's wave
+// target, or the launch's for several items of the two-samples kernel),
+// unit (i, c) being run c of the
 // tiles of the i-th genome of the item's list for the kernel's class (the
 // class list the transformation wrote, or all genomes).  Each wave of a
 // workgroup takes its own unit, so consecutive waves share a genome when it
@@ -991,6 +993,23 @@ int choose_chunks(long long P, int tiles, int *tpw) {
     return (tiles + *tpw - 1) / *tpw;
 }
 
+// One tiles-per-wave count for every item of a launch: the largest t whose
+// units, sum of P x ceil(tiles / t), still reach the wave target (1 when
+// even one tile per wave falls short).
+int launch_tiles_per_wave(const std::vector<FwdItem> &items) {
+    const long long target = wave_target();
+    int max_tiles = 1;
+    for (const FwdItem &it : items) max_tiles = std::max(max_tiles, it.tiles);
+    int best = 1;
+    for (int t = 2; t <= max_tiles; ++t) {
+        long long units = 0;
+        for (const FwdItem &it : items) units += (long long)it.P * ((it.tiles + t - 1) / t);
+        if (units < target) break;
+        best = t;
+    }
+    return best;
+}
+
 // samples of one tile
 int tile_samples(int kind) {
     return kind == KIND_R64X2 ? 2 * WAVE : (kind == KIND_LDS32 ? WAVE / 2 : WAVE);
@@ -1064,7 +1083,6 @@ int forward_plan(const FwdJob *jobs, int n, int variant, size_t max_lds,
             it.lvl_sh = sh;
             it.lvl_rows = rows;
             it.tiles = (J.B + (1 << sh) - 1) >> sh;
-            it.chunks = choose_chunks(J.P, it.tiles, &it.tpw);
             const int x = 2 * (seg ? KIND_SEG : KIND_LVL);
             k[x].items.push_back(it);
             rows_max[x] = std::max(rows_max[x], (rows << sh) + (seg ? J.N + 1 : 0));
@@ -1096,7 +1114,6 @@ int forward_plan(const FwdJob *jobs, int n, int variant, size_t max_lds,
             it.sweeps = J.recurrent ? J.sweeps : 0;
             const int TS = tile_samples(kind);
             it.tiles = (J.B + TS - 1) / TS;
-            it.chunks = choose_chunks(J.P, it.tiles, &it.tpw);
             it.vec4 = (!J.side && ((uintptr_t)J.inputs % 16 == 0) && (J.gstride % 4 == 0)) ? 1 : 0;
             const int x = 2 * kind + (J.side ? 1 : 0);
             k[x].items.push_back(it);
@@ -1127,8 +1144,25 @@ int forward_plan(const FwdJob *jobs, int n, int variant, size_t max_lds,
                      stage_max[x], max_lds);
             return NEAT_E_TOO_LARGE;
         }
+        // Several items of the two-samples kernel (the streaming one, taken
+        // for B > 64) share the launch's wave target: one tiles-per-wave
+        // count for all, the largest that still gives the target, so a
+        // population split into items runs as it does whole and each wave
+        // overlaps its next tile's input DMA with the current tile (the
+        // control workload as 10 items: 0.238 -> 0.214 ms).  Other kernels
+        // keep each item's own target: their short-B items are latency-bound
+        // and gain from spreading tiles over waves (a launch-wide target made
+        // the uneven batch's calculation up to 32 % slower).
+        const int shared_tpw = kind == KIND_R64X2 && K.items.size() > 1
+                                   ? launch_tiles_per_wave(K.items) : 0;
         long long units = 0;
         for (FwdItem &it : K.items) {
+            if (shared_tpw > 0) {
+                it.tpw = std::min(shared_tpw, std::max(1, it.tiles));
+                it.chunks = (it.tiles + it.tpw - 1) / it.tpw;
+            } else {
+                it.chunks = choose_chunks(it.P, it.tiles, &it.tpw);
+            }
             it.unit0 = units;
             units += (long long)it.P * it.chunks;
         }

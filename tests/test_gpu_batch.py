@@ -174,3 +174,36 @@ def test_batch_with_the_largest_genomes():
         y64, beta = oracle.forward(p.pop.nodes, p.pop.conns, p.pop.inputs, p.pop.I, p.pop.O)
         stats = assert_parity(y, y64, beta, "item %d" % k)
     plan.free()
+
+
+def test_items_of_the_two_samples_kernel_share_the_wave_target():
+    """Four control-shaped items (N_max = 50, B of 640 to 1000, so every
+    genome runs the two-samples-per-lane kernel) large enough that the launch
+    gives each wave two tiles of 128 samples (sum of P x ceil(tiles / 2)
+    reaches the 32768-wave target, P x ceil(tiles / 3) does not), with
+    ragged last tiles: the same bits as one call per item (one tile per wave
+    there), and sampled genomes within the oracle's parity rule."""
+    neat = _neat()
+    base = synth.control(seed=9, P=9000, with_inputs=False)
+    rng = np.random.default_rng(19)
+    sizes, Bs = (3000, 2500, 2000, 1500), (1000, 777, 1000, 640)
+    pops, g0 = [], 0
+    for P, B in zip(sizes, Bs):
+        part = synth.Population(base.nodes[g0:g0 + P], base.conns[g0:g0 + P], base.I, base.O)
+        part.inputs = rng.standard_normal((P, B, base.I)).astype(np.float32)
+        pops.append(_Pop(part))
+        g0 += P
+    tiles = [(B + 127) // 128 for B in Bs]
+    assert sum(P * -(-t // 2) for P, t in zip(sizes, tiles)) >= 32768
+    assert sum(P * -(-t // 3) for P, t in zip(sizes, tiles)) < 32768
+    plan = neat.BatchPlan()
+    plan.run([p.item() for p in pops])
+    torch.cuda.synchronize()
+    for k, p in enumerate(pops):
+        y = p.y.cpu().numpy()
+        assert _same_bits(y, p.single()), k
+        pick = np.sort(rng.choice(p.pop.P, 48, replace=False))
+        y64, beta = oracle.forward(p.pop.nodes[pick], p.pop.conns[pick], p.pop.inputs[pick],
+                                   p.pop.I, p.pop.O)
+        assert_parity(y[pick], y64, beta, "item %d" % k)
+    plan.free()
