@@ -9,7 +9,8 @@
 // plan.  Transformations (items with nodes) are recorded before the
 // calculations, batched the same way: one launch per workgroup-size bucket
 // (64, 128, 256, 512, 1024 threads) over the genomes of every population in
-// it, then one launch listing the genomes of every population by class.
+// it, then one launch listing the genomes of every population by class
+// (populations of N_max <= 62 need no list: all their genomes are R64).
 // The launches of each stage are independent and are recorded as parallel
 // branches of the graph (the forward kernels after the class lists), so a
 // long launch's tail overlaps the others.
@@ -89,9 +90,10 @@ struct TopoLaunch {
 // parallel branches of the graph; the class lists wait for every bucket.
 constexpr int N_BRANCH = 6;
 
-// Every stream of cs joins stream 0 (fork: 0 -> others; join: others -> 0).
-hipError_t link(hipStream_t *cs, bool fork, hipEvent_t *ev) {
-    for (int i = 1; i < N_BRANCH; ++i) {
+// Streams 1 .. m-1 of cs join stream 0 (fork: 0 -> others; join: others ->
+// 0); a stage of one launch stays on stream 0 with no fork at all.
+hipError_t link(hipStream_t *cs, bool fork, hipEvent_t *ev, int m) {
+    for (int i = 1; i < std::min(m, N_BRANCH); ++i) {
         hipStream_t from = fork ? cs[0] : cs[i], to = fork ? cs[i] : cs[0];
         hipError_t e = hipEventRecord(ev[i], from);
         if (e == hipSuccess) e = hipStreamWaitEvent(to, ev[i], 0);
@@ -106,24 +108,25 @@ int record(const std::vector<TopoLaunch> &topo, const neat::TopoItem *all_topo, 
            const std::vector<neat::FwdKernelLaunch> &fw,
            const std::vector<const neat::FwdItem *> &tab, unsigned *counters, hipStream_t *cs,
            hipEvent_t *ev) {
-    hipError_t e = link(cs, true, ev);
+    const int mt = (int)topo.size(), mf = (int)fw.size();
+    hipError_t e = link(cs, true, ev, mt);
     for (size_t k = 0; e == hipSuccess && k < topo.size(); ++k) {
         const TopoLaunch &t = topo[k];
         e = neat::launch_topo_batch(t.table, t.n, t.blocks, t.threads, t.lds, cs[k % N_BRANCH]);
         if (e != hipSuccess) return hip_fail(e, "batch transformation launch");
     }
-    if (e == hipSuccess) e = link(cs, false, ev);
+    if (e == hipSuccess) e = link(cs, false, ev, mt);
     if (e == hipSuccess && n_topo) {
         e = neat::launch_classify_batch(all_topo, n_topo, cs[0]);
         if (e != hipSuccess) return hip_fail(e, "batch class lists launch");
     }
     if (e == hipSuccess && counters) e = neat::launch_zero_counters(counters, (int)fw.size(), cs[0]);
-    if (e == hipSuccess) e = link(cs, true, ev);
+    if (e == hipSuccess) e = link(cs, true, ev, mf);
     for (size_t k = 0; e == hipSuccess && k < fw.size(); ++k) {
         e = neat::forward_launch(fw[k], tab[k], cs[k % N_BRANCH], counters ? counters + k : nullptr);
         if (e != hipSuccess) return hip_fail(e, "batch forward launch");
     }
-    if (e == hipSuccess) e = link(cs, false, ev);
+    if (e == hipSuccess) e = link(cs, false, ev, mf);
     return e == hipSuccess ? NEAT_OK : hip_fail(e, "batch stream fork or join");
 }
 
@@ -157,7 +160,8 @@ int plan_host(const neat_batch_item *items, int32_t n, HostPlan &hp) {
         int b = 0;
         while (bucket_threads[b] < neat::topo_block_threads(d.N_max)) ++b;
         bucket[b].push_back(ti);
-        all_topo.push_back(ti);
+        // class lists only where genomes can need more than 64 value slots
+        if (neat::max_class(d.N_max) != neat::CLS_R64) all_topo.push_back(ti);
     }
     for (int b = 0; b < 5; ++b) {
         if (bucket[b].empty()) continue;

@@ -120,7 +120,9 @@ def test_noalloc_refuses_tables_beyond_the_scratch_area():
     from paper_2404_01817_amd import _lib
     pop = synth.uneven(seed=43, n_pops=1, P_range=(2, 2), N_range=(12, 12), B_range=(3, 3))[0]
     buf = _Buffers(pop)
-    items = [buf.item() for _ in range(1200)]  # 1200 x (176 + 112) B > 256 KiB
+    # a transformation item (88 B) and a work-unit item (120 B) each; N_max =
+    # 12 needs no class list: 1300 x 208 B > 256 KiB
+    items = [buf.item() for _ in range(1300)]
     arr = (_lib.BatchItem * len(items))(*items)
     rc = _lib.lib().neat_forward_batch_noalloc(arr, len(items), None)
     assert rc == -4, rc  # NEAT_E_TOO_LARGE
