@@ -203,6 +203,81 @@ def bench_control_forms(args, torch, neat, pop, tn, tc, tx, step_bytes, parts=10
             "outputs_identical": bool(same), "unit": "genome-inputs/s"}
 
 
+def served_control(args, torch, neat, pop, tn, tc, tx, fwd_bytes, parts=10, bursts=20):
+    """The control workload (P=10000, N_max=50, B=1000) served: its genomes
+    registered as `parts` resident populations, then `bursts` rounds of one
+    request per population (B=1000 inputs each) queued back to back and
+    waited for at the end, against the same calculations as plain
+    neat_forward launches one after another (programs resident in both
+    forms).  Each round writes its own output buffers; the last round's
+    outputs are compared bit for bit.  HBM fraction from the forward's
+    algorithmic bytes (fwd_bytes per round)."""
+    dev = torch.device("cuda:0")
+    server = neat.Server(cap_bytes=64 << 30, max_inflight=4)
+    bounds = [pop.P * k // parts for k in range(parts + 1)]
+    ids, progs = [], []
+    for k in range(parts):
+        g0, g1 = bounds[k], bounds[k + 1]
+        ids.append(server.register(tn[g0:g1].contiguous(), tc[g0:g1].contiguous(), pop.I, pop.O))
+        _, _, _, pg = neat.topo_sort(tn[g0:g1], tc[g0:g1], pop.I, pop.O, want_order=False)
+        progs.append((neat.dims_of(tn[g0:g1], tc[g0:g1], pop.I, pop.O), pg))
+    xs = [tx[bounds[k]:bounds[k + 1]] for k in range(parts)]
+    ys = [[torch.empty((bounds[k + 1] - bounds[k], pop.B, pop.O), device=dev)
+           for k in range(parts)] for _ in range(bursts)]
+    yp = [torch.empty_like(y) for y in ys[0]]
+
+    def plain():
+        for _ in range(bursts):
+            for k in range(parts):
+                neat.forward(progs[k][0], progs[k][1], xs[k], pop.B, outputs=yp[k])
+
+    def served():
+        pend = [server.submit(ids[k], ys[r][k], inputs=xs[k], B=pop.B, I=pop.I, tag=r * parts + k)
+                for r in range(bursts) for k in range(parts)]
+        for t in pend:
+            server.wait(t)
+
+    times = {}
+    for name, fn in (("plain", plain), ("served", served)):
+        ramp(args, torch, fn)
+        fn()
+        torch.cuda.synchronize()
+        best = float("inf")
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            best = min(best, time.perf_counter() - t)
+        times[name] = best
+    server.reset_stats()
+    served()
+    torch.cuda.synchronize()
+    st = server.stats()
+    same = all(torch.equal(ys[-1][k].view(torch.int32), yp[k].view(torch.int32))
+               for k in range(parts))
+    server.close()
+    gi = pop.P * pop.B * bursts
+
+    def frac(sec):
+        return round(fwd_bytes * bursts / sec / 1e9 / HBM_PEAK_GBS, 4)
+
+    return {"workload": "the control workload served: %d resident populations of %d genomes, "
+                        "%d rounds of one request each (B=%d) queued at once"
+                        % (parts, pop.P // parts, bursts, pop.B),
+            "plain_ms": round(times["plain"] * 1e3, 3),
+            "plain_launches": parts * bursts,
+            "plain_value": round(gi / times["plain"], 1),
+            "served_ms": round(times["served"] * 1e3, 3),
+            "served_value": round(gi / times["served"], 1),
+            "served_speedup": round(times["plain"] / times["served"], 3),
+            "hbm_frac_forward": {"plain": frac(times["plain"]), "served": frac(times["served"])},
+            "batches": int(st.batches),
+            "mean_requests_per_batch": round(st.batched_requests / max(1, st.batches), 2),
+            "p50_ms": round(st.p50_ms, 3), "p99_ms": round(st.p99_ms, 3),
+            "outputs_identical": bool(same), "unit": "genome-inputs/s"}
+
+
 def bench_batched(args, torch, neat, synth):
     """64 uneven populations (P, N_max, B log-uniform; C_max = 4 N_max) run
     as one recorded batch: transformation + calculation of every population
@@ -1072,6 +1147,8 @@ def main():
              if "batched" in workloads else None)
     batched = bench_batched(args, torch, neat, synth) if "batched" in workloads else None
     served = bench_served(args, torch, neat, synth) if "served" in workloads else None
+    served_ctl = (served_control(args, torch, neat, pop, tn, tc, tx, fwd_bytes)
+                  if "served" in workloads else None)
     cppn = bench_cppn(args, torch, neat, synth) if "cppn" in workloads else None
     recurrent = (bench_recurrent(args, torch, neat, synth) if "recurrent" in workloads
                  else None)
@@ -1102,6 +1179,7 @@ def main():
         "step_roofline": step_roofline,
         "cpu_baseline": cpu,
         "control_batched_vs_plain": forms,
+        "control_served_vs_plain": served_ctl,
         "batched": batched,
         "served": served,
         "cppn": cppn,
