@@ -10,10 +10,14 @@
 // started on that slot by the executor; up to `slots` batches run at once,
 // so requests that arrive while others run are admitted as slots and bytes
 // free up and their work overlaps on the device.  Completions are polled
-// through the executor without holding the scheduler's lock.
+// through the executor without holding the scheduler's lock: while batches
+// run, the worker polls without sleeping for up to spin_us (a timed wait
+// wakes tens of microseconds after its deadline, which would add to every
+// request's latency), then sleeps in poll_us steps.
 #pragma once
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <condition_variable>
 #include <cstdint>
@@ -63,10 +67,12 @@ template <class Payload>
 class Scheduler {
   public:
     // slots: batches running at once; cap: device footprint in bytes;
-    // max_batch: requests per batch; poll_us: completion polling period.
-    Scheduler(Executor<Payload> *ex, int slots, uint64_t cap, int max_batch, int poll_us)
-        : ex_(ex), cap_(cap), max_batch_(max_batch), poll_us_(poll_us), slots_(slots),
-          t0_(std::chrono::steady_clock::now()) {
+    // max_batch: requests per batch; poll_us: completion polling period
+    // once spin_us of polling without sleeping found nothing.
+    Scheduler(Executor<Payload> *ex, int slots, uint64_t cap, int max_batch, int poll_us,
+              int spin_us = 0)
+        : ex_(ex), cap_(cap), max_batch_(max_batch), poll_us_(poll_us), spin_us_(spin_us),
+          slots_(slots), t0_(std::chrono::steady_clock::now()) {
         worker_ = std::thread([this] { loop(); });
     }
     Scheduler(const Scheduler &) = delete;
@@ -128,6 +134,7 @@ class Scheduler {
             q.res.t_admit_ns = q.res.t_done_ns = q.res.t_submit_ns;
         } else {
             queue_.push_back(tk);
+            queued_.fetch_add(1, std::memory_order_release);
         }
         *ticket = tk;
         lk.unlock();
@@ -225,6 +232,29 @@ class Scheduler {
         sl.busy = false;
     }
 
+    // Caller holds the lock (released while polling, held again on return).
+    // Poll the busy slots without sleeping for up to spin_us, finishing those
+    // that report completion (each report is acted on once); true once one
+    // has finished or a request was queued meanwhile.
+    bool spin(std::unique_lock<std::mutex> &lk) {
+        std::vector<int> busy, done;
+        for (int k = 0; k < (int)slots_.size(); ++k)
+            if (slots_[k].busy) busy.push_back(k);
+        const uint64_t seen = queued_.load(std::memory_order_acquire);
+        lk.unlock();
+        const auto until = std::chrono::steady_clock::now() + std::chrono::microseconds(spin_us_);
+        bool queued = false;
+        while (done.empty() && !queued && std::chrono::steady_clock::now() < until) {
+            for (int k : busy)
+                if (ex_->finished(k)) done.push_back(k);
+            queued = queued_.load(std::memory_order_acquire) != seen;
+            if (done.empty() && !queued) std::this_thread::yield();
+        }
+        lk.lock();
+        for (int k : done) finish(k, NEAT_OK);
+        return !done.empty() || queued;
+    }
+
     void loop() {
         ex_->thread_init();
         std::unique_lock<std::mutex> lk(m_);
@@ -287,6 +317,7 @@ class Scheduler {
                     continue;
                 }
             }
+            if (any_busy && spin_us_ > 0 && spin(lk)) continue;
             // (a system-clock deadline: pthread_cond_timedwait, which thread
             // checkers follow, unlike the clock-selecting wait)
             if (any_busy)
@@ -299,7 +330,7 @@ class Scheduler {
 
     Executor<Payload> *ex_;
     const uint64_t cap_;
-    const int max_batch_, poll_us_;
+    const int max_batch_, poll_us_, spin_us_;
     std::vector<Slot> slots_;
     const std::chrono::steady_clock::time_point t0_;
     std::mutex m_;
@@ -309,6 +340,7 @@ class Scheduler {
     std::deque<uint64_t> queue_;
     int next_slot_ = 0;
     uint64_t next_ticket_ = 1;
+    std::atomic<uint64_t> queued_{0};  // requests ever queued (read while spinning)
     uint64_t used_ = 0, resident_ = 0, peak_ = 0;
     std::vector<int64_t> lat_ns_;
     uint64_t submitted_ = 0, admitted_ = 0, completed_ = 0, rejected_ = 0, batches_ = 0;

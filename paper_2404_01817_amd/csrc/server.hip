@@ -38,8 +38,10 @@ constexpr size_t TABLE_ITEMS = 4 * MAX_BATCH_REQUESTS;  // items per batch table
 // work-unit table bytes a request may add to its batch (one item per slot
 // class)
 constexpr size_t REQ_TABLE_BYTES = 4 * sizeof(neat::FwdItem);
-// completion polling period of the scheduler
+// completion polling of the scheduler: without sleeping for up to SPIN_US
+// after each admission or completion, then every POLL_US
 constexpr int POLL_US = 20;
+constexpr int SPIN_US = 250;
 
 struct Pop {
     neat_dims d{};
@@ -186,7 +188,7 @@ int neat_server_create(const neat_server_cfg *cfg, neat_server **out) {
                                         : hip_fail(e, "server create");
     }
     s->sched.reset(new (std::nothrow) neat::sched::Scheduler<Payload>(
-        &s->exec, cfg->max_inflight, cfg->cap_bytes, MAX_BATCH_REQUESTS, POLL_US));
+        &s->exec, cfg->max_inflight, cfg->cap_bytes, MAX_BATCH_REQUESTS, POLL_US, SPIN_US));
     if (!s->sched) {
         free_server(s);
         return fail(NEAT_E_NOMEM, "out of host memory");

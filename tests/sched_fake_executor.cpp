@@ -111,11 +111,12 @@ class FakeExec : public Executor<Req> {
     size_t max_batch_ = 0;
 };
 
-void stream_test() {
+// spin: the scheduler's polling without sleeping (0: timed waits only)
+void stream_test(int spin) {
     const int slots = 4, threads = 6, per = 300;
     const uint64_t cap = 1000, resident = 200;
     FakeExec fx(slots, cap, resident, 20, 400, 41);
-    Scheduler<Req> s(&fx, slots, cap, 16, 5);
+    Scheduler<Req> s(&fx, slots, cap, 16, 5, spin);
     CHECK(s.add_resident(resident) == NEAT_OK);
     CHECK(s.add_resident(cap) == NEAT_E_TOO_LARGE);  // nothing held by the refusal
     std::atomic<int> rejected{0}, ok{0}, errored{0};
@@ -167,17 +168,17 @@ void stream_test() {
     CHECK(st.batches == (uint64_t)fx.launches());
     // continuous batching: under this load some batch held several requests
     CHECK(fx.max_batch() > 1);
-    std::printf("stream: %d requests, %d rejected, %llu batches (%.2f requests per batch, "
-                "largest %zu), %d failed launches' requests, p50 %.3f ms p99 %.3f ms\n",
-                threads * per, rejected.load(), (unsigned long long)st.batches,
+    std::printf("stream (spin %d us): %d requests, %d rejected, %llu batches (%.2f requests per "
+                "batch, largest %zu), %d failed launches' requests, p50 %.3f ms p99 %.3f ms\n",
+                spin, threads * per, rejected.load(), (unsigned long long)st.batches,
                 (double)st.batched_requests / (double)st.batches, fx.max_batch(),
                 errored.load(), st.p50_ms, st.p99_ms);
 }
 
-void shutdown_test() {
+void shutdown_test(int spin) {
     const int slots = 2;
     FakeExec fx(slots, 1u << 30, 0, 20000, 30000, 0);
-    auto *s = new Scheduler<Req>(&fx, slots, 1u << 30, 4, 5);
+    auto *s = new Scheduler<Req>(&fx, slots, 1u << 30, 4, 5, spin);
     std::vector<uint64_t> tickets;
     for (int i = 0; i < 100; ++i) {
         Req q;
@@ -204,7 +205,7 @@ void shutdown_test() {
     q.seq = 1000;
     CHECK(s->submit(q, 1, 1, 0, false, &tk) == NEAT_E_SHUTDOWN);
     delete s;
-    std::printf("shutdown: %d finished, %d cancelled\n", done, cancelled);
+    std::printf("shutdown (spin %d us): %d finished, %d cancelled\n", spin, done, cancelled);
 }
 
 void empty_request_test() {
@@ -224,8 +225,10 @@ void empty_request_test() {
 }  // namespace
 
 int main() {
-    stream_test();
-    shutdown_test();
+    for (int spin : {0, 100}) {
+        stream_test(spin);
+        shutdown_test(spin);
+    }
     empty_request_test();
     if (g_fail) {
         std::fprintf(stderr, "%d check(s) failed\n", g_fail.load());
