@@ -7,8 +7,8 @@
 // (or four) per population, and small populations fill the GPU together.
 // The work-unit tables of those launches live in device memory owned by the
 // plan.  Transformations (items with nodes) are recorded before the
-// calculations, batched the same way: one launch per workgroup-size bucket
-// (64, 128, 256, 512, 1024 threads) over the genomes of every population in
+// calculations, batched the same way: one launch per workgroup size (64 to
+// 1024 threads, in steps of 64) over the genomes of every population in
 // it, then one launch listing the genomes of every population by class
 // (populations of N_max <= 62 need no list: all their genomes are R64).
 // The launches of each stage are independent and are recorded as parallel
@@ -147,9 +147,11 @@ struct HostPlan {
 };
 
 int plan_host(const neat_batch_item *items, int32_t n, HostPlan &hp) {
-    // transformations bucketed by workgroup size
-    static const int bucket_threads[] = {64, 128, 256, 512, 1024};
-    std::vector<neat::TopoItem> bucket[5], all_topo;
+    // transformations bucketed by workgroup size (64 x (b + 1) threads): each
+    // genome runs with the waves its N_max needs, and a launch reserves the
+    // LDS of its own genomes only
+    constexpr int NB = 16;
+    std::vector<neat::TopoItem> bucket[NB], all_topo;
     for (int32_t k = 0; k < n; ++k) {
         const neat_batch_item &it = items[k];
         if (!it.nodes || it.dims.P == 0) continue;
@@ -157,13 +159,12 @@ int plan_host(const neat_batch_item *items, int32_t n, HostPlan &hp) {
         neat::TopoItem ti{it.nodes, it.conns, nullptr, nullptr, it.status, (int32_t *)it.program,
                           d.P, d.N_max, d.C_max, d.I, d.O, neat::prog_words(d.N_max, d.C_max, d.O),
                           0};
-        int b = 0;
-        while (bucket_threads[b] < neat::topo_block_threads(d.N_max)) ++b;
+        const int b = neat::topo_block_threads(d.N_max) / 64 - 1;
         bucket[b].push_back(ti);
         // class lists only where genomes can need more than 64 value slots
         if (neat::max_class(d.N_max) != neat::CLS_R64) all_topo.push_back(ti);
     }
-    for (int b = 0; b < 5; ++b) {
+    for (int b = 0; b < NB; ++b) {
         if (bucket[b].empty()) continue;
         TopoLaunch t{(int)bucket[b].size(), 0, 64, 0, nullptr};
         for (neat::TopoItem &ti : bucket[b]) {

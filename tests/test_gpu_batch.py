@@ -83,9 +83,10 @@ def test_batch_matches_single_calls_and_oracle():
     plan = neat.BatchPlan()
     plan.run([p.item() for p in pops])
     torch.cuda.synchronize()
-    # transformations: at most five size buckets and one class listing;
-    # calculations: at most one launch per value store and input mode
-    assert 2 <= plan.launches <= 6 + 10
+    # transformations: at most one launch per workgroup size (16) and one
+    # class listing; calculations: at most one launch per kernel kind and
+    # input mode
+    assert 2 <= plan.launches <= 16 + 1 + 18
     for k, p in enumerate(pops):
         y = p.y.cpu().numpy()
         assert _same_bits(y, p.single()), k
