@@ -85,6 +85,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="the oracle repeats its sample until this much CPU time has passed")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-p-sweep", action="store_true",
+                    help="skip the control step over P = 50 .. 10000 genomes")
     ap.add_argument("--quiet", action="store_true")
     ap.add_argument("--workloads", default="control,tiny,batched,served,cppn,recurrent,substrate,distance,"
                             "crossover,edit",
@@ -125,6 +127,57 @@ def program_bytes_read(O, n_valid, n_edges, I):
     with the first edges inline); this counts what the method needs."""
     n_comp = np.maximum(n_valid - I, 0)
     return int((64 + 4 * O + 16 * n_comp + 8 * n_edges).sum())
+
+
+def bench_p_sweep(args, torch, neat, pop, tn, tc, tx, hdr,
+                  sizes=(50, 100, 200, 500, 1000, 2000, 5000, 10000)):
+    """The control step (transformation + forward, B=1000) on the first P
+    genomes of the control population for P from 50 to 10000, the paper's
+    population axis: ms per step (median of 5 runs of 20 steps after a
+    warmup), genome-inputs/s and the end-to-end HBM fraction of the step's
+    algorithmic bytes (as step_roofline, over the P genomes)."""
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    sp = ctypes.c_void_p(stream.cuda_stream)
+    lib = neat.lib()
+    out = []
+    for P in sizes:
+        if P > pop.P:
+            continue
+        d = neat.Dims(P, tn.shape[1], tc.shape[1], pop.I, pop.O)
+        prog = torch.empty((neat.program_bytes(d) // 4,), dtype=torch.int32, device=dev)
+        st = torch.empty((P,), dtype=torch.int32, device=dev)
+        y = torch.empty((P, pop.B, pop.O), dtype=torch.float32, device=dev)
+        n, c, x = tn[:P], tc[:P], tx[:P]
+
+        def step():
+            neat._lib.check(lib.neat_topo_sort(ctypes.byref(d), ctypes.c_void_p(n.data_ptr()),
+                                               ctypes.c_void_p(c.data_ptr()), None, None,
+                                               ctypes.c_void_p(st.data_ptr()),
+                                               ctypes.c_void_p(prog.data_ptr()), sp))
+            neat._lib.check(lib.neat_forward(ctypes.byref(d), ctypes.c_void_p(prog.data_ptr()),
+                                             ctypes.c_void_p(x.data_ptr()), pop.B * pop.I, pop.B,
+                                             ctypes.c_void_p(y.data_ptr()), sp))
+
+        for _ in range(3):
+            step()
+        runs = []
+        for _ in range(5):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for _ in range(20):
+                step()
+            torch.cuda.synchronize()
+            runs.append((time.perf_counter() - t) * 1e3 / 20)
+        ms = float(np.median(runs))
+        pb = program_bytes_read(pop.O, hdr[:P, 0], hdr[:P, 7], pop.I)
+        step_bytes = P * (20 * pop.N_max + 16 * pop.C_max + 4) + pb + \
+            P * pop.B * (pop.I + pop.O) * 4 + pb
+        out.append({"P": P, "ms_per_step": round(ms, 4), "min_ms": round(min(runs), 4),
+                    "value": round(P * pop.B / (ms / 1e3), 1),
+                    "hbm_frac_end_to_end": round(step_bytes / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)})
+    return {"workload": "control step on the first P genomes of the control population, B=1000",
+            "unit": "genome-inputs/s", "points": out}
 
 
 def bench_control_forms(args, torch, neat, pop, tn, tc, tx, step_bytes, parts=10):
@@ -389,8 +442,10 @@ def bench_batched(args, torch, neat, synth):
 
 def bench_tiny(args, torch, neat, synth):
     """The tiny workload (P = 16, N_max = 8, 32 shared inputs): latency of
-    one transformation + calculation call pair, on the device (events over
-    consecutive calls) and end to end on the host (each pair synchronized)."""
+    one transformation + calculation call pair through the C ABI, on the
+    device (events over consecutive calls) and end to end on the host (each
+    pair synchronized); and the same pair through the Python wrappers
+    (argument checks on torch tensors included)."""
     dev = torch.device("cuda:0")
     pop = synth.tiny()
     tn = torch.from_numpy(pop.nodes).to(dev)
@@ -399,34 +454,46 @@ def bench_tiny(args, torch, neat, synth):
     d = neat.dims_of(tn, tc, pop.I, pop.O)
     _, _, st, prog = neat.topo_sort(tn, tc, pop.I, pop.O, want_order=False)
     y = torch.empty((pop.P, pop.B, pop.O), device=dev)
+    stream = torch.cuda.current_stream()
+    lib = neat.lib()
+    sp = ctypes.c_void_p(stream.cuda_stream)
+    dref = ctypes.byref(d)
+    a_n, a_c, a_s, a_p, a_x, a_y = [ctypes.c_void_p(t.data_ptr()) for t in (tn, tc, st, prog, tx, y)]
 
     def call():
+        neat._lib.check(lib.neat_topo_sort(dref, a_n, a_c, None, None, a_s, a_p, sp))
+        neat._lib.check(lib.neat_forward(dref, a_p, a_x, 0, pop.B, a_y, sp))
+
+    def call_wrapped():
         neat.topo_sort(tn, tc, pop.I, pop.O, program=prog, status=st, want_order=False)
         neat.forward(d, prog, tx, pop.B, shared_inputs=True, outputs=y)
 
+    def back_to_back(fn, n=500):
+        for _ in range(20):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(n):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / n * 1e3
+
     ramp(args, torch, call)
-    for _ in range(20):
-        call()
-    torch.cuda.synchronize()
-    n = 500
-    stream = torch.cuda.current_stream()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(n):
-        call()
-    e1.record(stream)
-    torch.cuda.synchronize()
-    dev_us = e0.elapsed_time(e1) / n * 1e3
+    dev_us = back_to_back(call)
     host = []
     for _ in range(200):
         t = time.perf_counter()
         call()
         torch.cuda.synchronize()
         host.append(time.perf_counter() - t)
+    wrapped_us = back_to_back(call_wrapped)
     return {"workload": "tiny: P=16, N_max=8, C_max=16, I=3, O=1, 32 shared inputs, "
                         "transformation + calculation per call",
             "us_per_call_back_to_back": round(dev_us, 2),
             "us_per_call_synchronized_p50": round(float(np.median(host)) * 1e6, 2),
+            "us_per_call_back_to_back_python_wrappers": round(wrapped_us, 2),
             "genome_inputs_per_call": pop.P * pop.B}
 
 
@@ -1142,6 +1209,8 @@ def main():
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(args, pop)
 
+    psweep = bench_p_sweep(args, torch, neat, pop, tn, tc, tx, hdr) if not args.no_p_sweep else None
+
     workloads = set(args.workloads.split(","))
     forms = (bench_control_forms(args, torch, neat, pop, tn, tc, tx, step_bytes)
              if "batched" in workloads else None)
@@ -1178,6 +1247,7 @@ def main():
         "roofline": roofline,
         "step_roofline": step_roofline,
         "cpu_baseline": cpu,
+        "p_sweep": psweep,
         "control_batched_vs_plain": forms,
         "control_served_vs_plain": served_ctl,
         "batched": batched,

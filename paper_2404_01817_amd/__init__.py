@@ -27,9 +27,15 @@ def _torch():
 
 
 def _stream(stream=None):
+    if stream is not None:
+        return ctypes.c_void_p(stream.cuda_stream)
     torch = _torch()
-    s = stream if stream is not None else torch.cuda.current_stream()
-    return ctypes.c_void_p(s.cuda_stream)
+    # the current stream's handle without building a Stream object (a few
+    # microseconds per call otherwise); the public path where torch lacks it
+    raw = getattr(torch._C, "_cuda_getCurrentRawStream", None)
+    if raw is not None:
+        return ctypes.c_void_p(raw(torch.cuda.current_device()))
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
 def _ptr(t) -> Optional[ctypes.c_void_p]:
