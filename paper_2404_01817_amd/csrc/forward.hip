@@ -995,19 +995,24 @@ int choose_chunks(long long P, int tiles, int *tpw) {
 
 // One tiles-per-wave count for every item of a launch: the largest t whose
 // units, sum of P x ceil(tiles / t), still reach the wave target (1 when
-// even one tile per wave falls short).
+// even one tile per wave falls short).  The units never grow with t, so a
+// binary search finds it.
 int launch_tiles_per_wave(const std::vector<FwdItem> &items) {
     const long long target = wave_target();
     int max_tiles = 1;
     for (const FwdItem &it : items) max_tiles = std::max(max_tiles, it.tiles);
-    int best = 1;
-    for (int t = 2; t <= max_tiles; ++t) {
-        long long units = 0;
-        for (const FwdItem &it : items) units += (long long)it.P * ((it.tiles + t - 1) / t);
-        if (units < target) break;
-        best = t;
+    auto units = [&](int t) {
+        long long u = 0;
+        for (const FwdItem &it : items) u += (long long)it.P * ((it.tiles + t - 1) / t);
+        return u;
+    };
+    int lo = 1, hi = max_tiles;  // units(lo) >= target unless lo = 1
+    while (lo < hi) {
+        const int mid = lo + (hi - lo + 1) / 2;
+        if (units(mid) >= target) lo = mid;
+        else hi = mid - 1;
     }
-    return best;
+    return lo;
 }
 
 // samples of one tile
