@@ -25,8 +25,8 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 # fp32 vector peak without packed math: 256 CUs x 4 SIMDs x 16 lanes x 2 flops
-# (fused multiply-add) x 2.4 GHz (packed fp32 would double it; this build does
-# not use packed fp32 instructions)
+# (fused multiply-add) x 2.4 GHz (packed fp32 would double it; the kernels are
+# compiled without packed fp32 instructions)
 VALU_PEAK_TFLOPS = 78.6
 # algorithmic flops of an activation (identity, tanh, sigmoid, relu, sin,
 # gaussian, abs): the arithmetic of its definition on the hardware's base-2

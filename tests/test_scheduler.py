@@ -4,7 +4,7 @@ threads, built twice with g++: plain, and with ThreadSanitizer.  The fake
 executor checks at every launch that the slot is idle, that at most
 max_inflight batches run, that the footprint (resident populations plus
 running requests) stays under the cap and that each submitter's requests
-are admitted in submission order; the driver checks tickets, results,
+are admitted in submission order; the test program checks tickets, results,
 statistics, rejection by footprint, launch errors, continuous batching
 (several requests per batch under load) and shutdown with queued
 requests."""
