@@ -483,8 +483,9 @@ int32_t neat_batch_plan_launches(const neat_batch_plan *plan);
  * ordered and safe; calls that overlap on one GPU (different streams or
  * threads) race on the array and must not be issued.
  * Errors: as neat_forward_batch; NEAT_E_TOO_LARGE when the batch's tables
- * (176 B per transformed population, plus 120 B per population and value
- * store it uses) exceed NEAT_NOALLOC_SCRATCH_BYTES.
+ * (176 B per transformed population, 88 B for one of N_max <= 62, which
+ * needs no class list, plus 120 B per population and value store it uses)
+ * exceed NEAT_NOALLOC_SCRATCH_BYTES.
  */
 #define NEAT_NOALLOC_SCRATCH_BYTES (256 * 1024)
 int neat_forward_batch_noalloc(const neat_batch_item *items, int32_t n, void *stream);
