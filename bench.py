@@ -1214,6 +1214,10 @@ def main():
     workloads = set(args.workloads.split(","))
     forms = (bench_control_forms(args, torch, neat, pop, tn, tc, tx, step_bytes)
              if "batched" in workloads else None)
+    # the latency-bound regime of small populations (the population sweep's
+    # plain step is launch-bound below about 500 genomes)
+    forms_small = (bench_control_forms(args, torch, neat, pop, tn, tc, tx, step_bytes, parts=100)
+                   if "batched" in workloads else None)
     batched = bench_batched(args, torch, neat, synth) if "batched" in workloads else None
     served = bench_served(args, torch, neat, synth) if "served" in workloads else None
     served_ctl = (served_control(args, torch, neat, pop, tn, tc, tx, fwd_bytes)
@@ -1249,6 +1253,7 @@ def main():
         "cpu_baseline": cpu,
         "p_sweep": psweep,
         "control_batched_vs_plain": forms,
+        "control_batched_vs_plain_100_populations": forms_small,
         "control_served_vs_plain": served_ctl,
         "batched": batched,
         "served": served,
