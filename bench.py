@@ -259,8 +259,8 @@ def bench_control_forms(args, torch, neat, pop, tn, tc, tx, step_bytes, parts=10
 def served_control(args, torch, neat, pop, tn, tc, tx, fwd_bytes, parts=10, bursts=20):
     """The control workload (P=10000, N_max=50, B=1000) served: its genomes
     registered as `parts` resident populations, then `bursts` rounds of one
-    request per population (B=1000 inputs each) queued back to back and
-    waited for at the end, against the same calculations as plain
+    request per population (B=1000 inputs each, a round per neat_submit_many
+    call) queued back to back and waited for at the end, against the same calculations as plain
     neat_forward launches one after another (programs resident in both
     forms).  Each round writes its own output buffers; the last round's
     outputs are compared bit for bit.  HBM fraction from the forward's
@@ -284,9 +284,15 @@ def served_control(args, torch, neat, pop, tn, tc, tx, fwd_bytes, parts=10, burs
             for k in range(parts):
                 neat.forward(progs[k][0], progs[k][1], xs[k], pop.B, outputs=yp[k])
 
+    # each round handed over in one neat_submit_many call (one crossing per
+    # round rather than per request), records built in advance
+    rounds = [[server.request(ids[k], ys[r][k], inputs=xs[k], B=pop.B, I=pop.I,
+                              tag=r * parts + k) for k in range(parts)] for r in range(bursts)]
+
     def served():
-        pend = [server.submit(ids[k], ys[r][k], inputs=xs[k], B=pop.B, I=pop.I, tag=r * parts + k)
-                for r in range(bursts) for k in range(parts)]
+        pend = []
+        for recs in rounds:
+            pend += server.submit_many(recs)
         for t in pend:
             server.wait(t)
 
@@ -1222,6 +1228,8 @@ def main():
     served = bench_served(args, torch, neat, synth) if "served" in workloads else None
     served_ctl = (served_control(args, torch, neat, pop, tn, tc, tx, fwd_bytes)
                   if "served" in workloads else None)
+    served_ctl_small = (served_control(args, torch, neat, pop, tn, tc, tx, fwd_bytes, parts=100)
+                        if "served" in workloads else None)
     cppn = bench_cppn(args, torch, neat, synth) if "cppn" in workloads else None
     recurrent = (bench_recurrent(args, torch, neat, synth) if "recurrent" in workloads
                  else None)
@@ -1255,6 +1263,7 @@ def main():
         "control_batched_vs_plain": forms,
         "control_batched_vs_plain_100_populations": forms_small,
         "control_served_vs_plain": served_ctl,
+        "control_served_vs_plain_100_populations": served_ctl_small,
         "batched": batched,
         "served": served,
         "cppn": cppn,

@@ -571,6 +571,14 @@ int neat_server_register(neat_server *server, const neat_dims *dims, const float
  * NEAT_E_TOO_LARGE (the request does not fit beside the resident
  * populations even alone), NEAT_E_SHUTDOWN. */
 int neat_submit(neat_server *server, const neat_request *request, uint64_t *ticket);
+/* Queues requests[0..n) in order, as n calls of neat_submit would, in one
+ * call: a client handing over a burst crosses the boundary once instead of
+ * n times.  tickets: caller-owned host array of n.  Stops at the first
+ * request neat_submit would refuse and returns that error (the message names
+ * its index): the requests before it are queued and their tickets valid,
+ * the tickets from it on are set to 0.  n = 0 does nothing. */
+int neat_submit_many(neat_server *server, const neat_request *requests, int32_t n,
+                     uint64_t *tickets);
 /* NEAT_OK (result filled, ticket forgotten), NEAT_PENDING, or
  * NEAT_E_UNKNOWN_TICKET.  Never blocks. */
 int neat_poll(neat_server *server, uint64_t ticket, neat_result *result);

@@ -365,6 +365,38 @@ class Server:
                                          ctypes.byref(pid)))
         return pid.value
 
+    @staticmethod
+    def request(pop_id: int, outputs, inputs=None, B: int = 0, shared_inputs=False,
+                grid_side: int = 0, grid_first: int = 0, tag: int = 0, I: int = 0):
+        """A request record for submit_many (arguments as submit)."""
+        r = Request()
+        r.pop_id = pop_id
+        if grid_side:
+            r.input_mode = INPUT_GRID
+            r.grid_side, r.grid_first = grid_side, grid_first
+        else:
+            r.input_mode = INPUT_TENSOR
+            r.inputs = inputs.data_ptr()
+            r.input_genome_stride = 0 if shared_inputs else B * I
+        r.B = B
+        r.outputs = outputs.data_ptr()
+        r.tag = tag
+        return r
+
+    def submit_many(self, requests) -> list:
+        """Queue a list of request records (Server.request) in one call;
+        returns their tickets.  On a refused request it raises: the ones
+        before it are queued (their tickets are in the error's `tickets`)."""
+        n = len(requests)
+        arr = (Request * n)(*requests)
+        tickets = (ctypes.c_uint64 * n)()
+        rc = lib().neat_submit_many(self._h, arr, n, tickets)
+        if rc < 0:
+            err = NeatError(rc, lib().neat_last_error().decode())
+            err.tickets = [t for t in tickets if t]
+            raise err
+        return list(tickets)
+
     def submit(self, pop_id: int, outputs, inputs=None, B: int = 0, shared_inputs=False,
                grid_side: int = 0, grid_first: int = 0, tag: int = 0, I: int = 0) -> int:
         """Queue one request; returns its ticket.  TENSOR mode needs I (the

@@ -110,6 +110,8 @@ SIGNATURES = {
     "neat_server_register": (_i32, [_vp, ctypes.POINTER(Dims), _vp, _vp,
                                     ctypes.POINTER(ctypes.c_int32)]),
     "neat_submit": (_i32, [_vp, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]),
+    "neat_submit_many": (_i32, [_vp, ctypes.POINTER(Request), _i32,
+                                ctypes.POINTER(ctypes.c_uint64)]),
     "neat_poll": (_i32, [_vp, ctypes.c_uint64, ctypes.POINTER(Result)]),
     "neat_server_stats": (_i32, [_vp, ctypes.POINTER(Stats)]),
     "neat_server_reset_stats": (_i32, [_vp]),

@@ -281,6 +281,19 @@ int neat_submit(neat_server *s, const neat_request *r, uint64_t *ticket) {
     return rc;
 }
 
+int neat_submit_many(neat_server *s, const neat_request *reqs, int32_t n, uint64_t *tickets) {
+    if (!s || n < 0 || (n > 0 && (!reqs || !tickets)))
+        return fail(NEAT_E_INVALID, "server, requests or tickets is NULL, or n = %d", n);
+    for (int32_t k = 0; k < n; ++k) {
+        const int rc = neat_submit(s, &reqs[k], &tickets[k]);
+        if (rc != NEAT_OK) {
+            for (int32_t j = k; j < n; ++j) tickets[j] = 0;
+            return fail(rc, "request %d of %d: %s", k, n, neat_last_error());
+        }
+    }
+    return NEAT_OK;
+}
+
 int neat_poll(neat_server *s, uint64_t ticket, neat_result *res) {
     if (!s) return fail(NEAT_E_INVALID, "server is NULL");
     neat::sched::Result r;

@@ -125,6 +125,49 @@ def test_served_requests_equal_single_calls():
     server.close()
 
 
+def test_submit_many_queues_in_order_and_stops_at_a_refused_request():
+    """neat_submit_many: a burst of mixed requests handed over in one call
+    gives the same bits as one single call each (and the oracle's values);
+    a refused request (an unknown population) in the middle raises, the
+    requests before it are queued and finish, the tickets from it on are
+    0."""
+    neat = _neat()
+    server = neat.Server(max_inflight=3)
+    pool = _pool(server)
+    reqs = _requests(pool, 40, seed=5)
+    outs, recs = [], []
+    for k, (r, B, x, grid) in enumerate(reqs):
+        y = torch.full((r.pop.P, B, r.pop.O), 7.0, dtype=torch.float32, device="cuda:0")
+        outs.append(y)
+        if grid is None:
+            recs.append(server.request(r.id, y, inputs=x, B=B, I=r.pop.I, tag=k))
+        else:
+            recs.append(server.request(r.id, y, B=B, grid_side=grid[0], grid_first=grid[1],
+                                       tag=k))
+    tickets = server.submit_many(recs)
+    assert len(tickets) == len(reqs) and all(t > 0 for t in tickets)
+    for k, (t, q) in enumerate(zip(tickets, reqs)):
+        res = server.wait(t)
+        assert res.status == 0 and res.tag == k
+        r, B, x, grid = q
+        ref = r.reference(x, B) if grid is None else r.reference(grid=grid)
+        got = outs[k].cpu().numpy()
+        assert _same_bits(got, ref), k
+        if k % 8 == 0:
+            y64, beta = _oracle(q)
+            assert_parity(got, y64, beta, "submit_many request %d" % k)
+    # a refused request at index 3 of 6
+    bad = list(recs[:6])
+    bad[3] = server.request(9999, outs[3], inputs=torch.zeros(16, device="cuda:0"), B=1, I=1)
+    with pytest.raises(neat.NeatError, match="request 3 of 6") as e:
+        server.submit_many(bad)
+    assert len(e.value.tickets) == 3
+    for t in e.value.tickets:
+        assert server.wait(t).status == 0
+    assert server.submit_many([]) == []
+    server.close()
+
+
 def test_request_alone_equals_request_in_mix():
     neat = _neat()
     server = neat.Server(max_inflight=2)
