@@ -623,7 +623,7 @@ def served_cppn(args, torch, neat, synth, server):
     """CPPN substrate queries served as batched GRID requests: the CPPN
     population (P = 1000, N_max = 30) registered on the server, the 65536
     queries of the 16 x 16 grid split into requests of 4096 queries, queued
-    at once; against one plain neat_forward_grid call over the whole grid
+    in one neat_submit_many call; against one plain neat_forward_grid call over the whole grid
     (outputs compared bit for bit).  Best of three."""
     dev = torch.device("cuda:0")
     pop = synth.cppn()
@@ -640,10 +640,11 @@ def served_cppn(args, torch, neat, synth, server):
         neat.forward_grid(d, prog, 16, 0, Q, outputs=yfull)
         torch.cuda.synchronize()
 
+    recs = [server.request(pid, parts[k], B=chunk, grid_side=16, grid_first=k * chunk, tag=k)
+            for k in range(len(parts))]
+
     def served():
-        pend = [server.submit(pid, parts[k], B=chunk, grid_side=16, grid_first=k * chunk, tag=k)
-                for k in range(len(parts))]
-        for t in pend:
+        for t in server.submit_many(recs):
             server.wait(t)
         torch.cuda.synchronize()
 

@@ -1163,8 +1163,12 @@ int forward_plan(const FwdJob *jobs, int n, int variant, size_t max_lds,
         long long units = 0;
         for (FwdItem &it : K.items) {
             if (shared_tpw > 0) {
-                it.tpw = std::min(shared_tpw, std::max(1, it.tiles));
-                it.chunks = (it.tiles + it.tpw - 1) / it.tpw;
+                // as many units as the shared count gives, their tiles
+                // balanced (32 tiles at 15 per wave: 11 + 11 + 10, not
+                // 15 + 15 + 2), as choose_chunks balances an item's own
+                const int t = std::min(shared_tpw, std::max(1, it.tiles));
+                it.chunks = (it.tiles + t - 1) / t;
+                it.tpw = (it.tiles + it.chunks - 1) / it.chunks;
             } else {
                 it.chunks = choose_chunks(it.P, it.tiles, &it.tpw);
             }
