@@ -677,7 +677,8 @@ def served_cppn(args, torch, neat, synth, server):
 
 def served_burst(args, torch, neat, server, pool, ids, xpool, ypool):
     """Saturation: the same requests (population and B drawn as in the
-    stream) once queued to the server all at once, once as plain
+    stream) once queued to the server all at once (one neat_submit_many
+    call), once as plain
     per-request forward launches one after another; programs are resident
     in both forms (the plain form's transformed before timing).  Best of
     three; the outputs of the two forms are compared bit for bit."""
@@ -711,11 +712,12 @@ def served_burst(args, torch, neat, server, pool, ids, xpool, ypool):
                          outputs=yplain[y0:y0 + ny].view(pop.P, B, pop.O))
         torch.cuda.synchronize()
 
+    recs = [server.request(ids[j], ypool[y0:y0 + ny], inputs=xpool[x0:x0 + nx], B=B,
+                           I=pool[j].I, tag=k)
+            for k, (j, B, x0, nx, y0, ny) in enumerate(reqs)]
+
     def served():
-        pending = set()
-        for k, (j, B, x0, nx, y0, ny) in enumerate(reqs):
-            pending.add(server.submit(ids[j], ypool[y0:y0 + ny], inputs=xpool[x0:x0 + nx],
-                                      B=B, I=pool[j].I, tag=k))
+        pending = set(server.submit_many(recs))
         while pending:
             for t in list(pending):
                 if server.poll(t) is not None:
