@@ -88,20 +88,28 @@ class HipExec : public neat::sched::Executor<Payload> {
         int rc = neat::forward_plan(jobs.data(), (int)jobs.size(), neat::FWD_AUTO,
                                     max_lds_bytes(), fw, err, sizeof(err));
         if (rc != NEAT_OK) return rc;
+        // only launches of several items read a table; a launch of one item
+        // takes it inline in its arguments, so a batch of single-item
+        // launches (a request alone, the common case at low rates) starts
+        // without a copy ahead of it on the stream
         size_t n = 0;
-        for (const neat::FwdKernelLaunch &f : fw) n += f.items.size();
+        for (const neat::FwdKernelLaunch &f : fw)
+            if (f.items.size() > 1) n += f.items.size();
         if (n > TABLE_ITEMS) return NEAT_E_TOO_LARGE;
         size_t at = 0;
-        std::vector<size_t> off(fw.size());
+        std::vector<long long> off(fw.size(), -1);
         for (size_t f = 0; f < fw.size(); ++f) {
-            off[f] = at;
+            if (fw[f].items.size() <= 1) continue;
+            off[f] = (long long)at;
             std::copy(fw[f].items.begin(), fw[f].items.end(), sl.host + at);
             at += fw[f].items.size();
         }
-        hipError_t e = hipMemcpyAsync(sl.dev, sl.host, at * sizeof(neat::FwdItem),
-                                      hipMemcpyHostToDevice, sl.stream);
+        hipError_t e = hipSuccess;
+        if (at)
+            e = hipMemcpyAsync(sl.dev, sl.host, at * sizeof(neat::FwdItem), hipMemcpyHostToDevice,
+                               sl.stream);
         for (size_t f = 0; f < fw.size() && e == hipSuccess; ++f)
-            e = neat::forward_launch(fw[f], sl.dev + off[f], sl.stream);
+            e = neat::forward_launch(fw[f], off[f] >= 0 ? sl.dev + off[f] : nullptr, sl.stream);
         if (e == hipSuccess) e = hipEventRecord(sl.done, sl.stream);
         return e == hipSuccess ? NEAT_OK : NEAT_E_HIP;
     }
