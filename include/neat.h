@@ -496,8 +496,11 @@ int neat_forward_batch_noalloc(const neat_batch_item *items, int32_t n, void *st
  * neat_server_register copies a population's encoding into library-owned
  * device memory and runs its transformation once (Section 3.3: transform
  * once, calculate many times); requests then name it by pop_id.
- * neat_submit queues a calculation request and returns at once with a
- * ticket.  A scheduler thread admits queued requests in arrival order while
+ * neat_submit queues a calculation request and returns with a ticket
+ * without waiting for the device: when nothing is queued and a stream is
+ * free, it admits and launches the request itself (the scheduler would start
+ * it alone anyway; this saves waking the scheduler thread), else it only
+ * queues it.  A scheduler thread admits queued requests in arrival order while
  * the bytes they touch (inputs, outputs and a small work-unit table per
  * request, counted against cap_bytes) fit and fewer than max_inflight
  * batches run; everything admitted together forms one batch (one launch per

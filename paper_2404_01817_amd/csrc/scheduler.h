@@ -13,7 +13,12 @@
 // through the executor without holding the scheduler's lock: while batches
 // run, the worker polls without sleeping for up to spin_us (a timed wait
 // wakes tens of microseconds after its deadline, which would add to every
-// request's latency), then sleeps in poll_us steps.
+// request's latency), then sleeps in poll_us steps.  With `direct`, a
+// request that finds the scheduler idle (nothing queued, no slot busy, so
+// the worker is asleep) is admitted and launched by the submitting thread
+// itself (the worker would admit it alone anyway; this saves waking it),
+// and the worker then polls its completion as any other.  Launches never
+// overlap, so their order is the admission order.
 #pragma once
 
 #include <algorithm>
@@ -48,8 +53,10 @@ struct Stats {
     uint64_t peak_bytes = 0;          // largest footprint (resident + running) admitted
 };
 
-// The device side of the scheduler.  Every call comes from the worker
-// thread (thread_init first), without the scheduler's lock held.
+// The device side of the scheduler.  Calls come from the worker thread
+// (thread_init first) or, for a request admitted at submission, from the
+// submitting thread; never with the scheduler's lock held, and a slot is
+// never polled (finished) while its launch is in progress.
 template <class Payload>
 struct Executor {
     virtual ~Executor() = default;
@@ -68,11 +75,12 @@ class Scheduler {
   public:
     // slots: batches running at once; cap: device footprint in bytes;
     // max_batch: requests per batch; poll_us: completion polling period
-    // once spin_us of polling without sleeping found nothing.
+    // once spin_us of polling without sleeping found nothing; direct: admit
+    // and launch a request on the submitting thread when nothing waits.
     Scheduler(Executor<Payload> *ex, int slots, uint64_t cap, int max_batch, int poll_us,
-              int spin_us = 0)
+              int spin_us = 0, bool direct = false)
         : ex_(ex), cap_(cap), max_batch_(max_batch), poll_us_(poll_us), spin_us_(spin_us),
-          slots_(slots), t0_(std::chrono::steady_clock::now()) {
+          direct_(direct), slots_(slots), t0_(std::chrono::steady_clock::now()) {
         worker_ = std::thread([this] { loop(); });
     }
     Scheduler(const Scheduler &) = delete;
@@ -129,14 +137,19 @@ class Scheduler {
         q.res.t_submit_ns = now_ns();
         if (first_submit_ < 0) first_submit_ = q.res.t_submit_ns;
         submitted_++;
+        *ticket = tk;
         if (empty) {
             q.state = DONE;
             q.res.t_admit_ns = q.res.t_done_ns = q.res.t_submit_ns;
+        } else if (direct_ && idle() && used_ + bytes <= cap_) {
+            const int fs = free_slot();
+            admit(fs, tk);
+            run(lk, fs, {&q.payload});
+            return NEAT_OK;
         } else {
             queue_.push_back(tk);
-            queued_.fetch_add(1, std::memory_order_release);
         }
-        *ticket = tk;
+        wake_.fetch_add(1, std::memory_order_release);
         lk.unlock();
         cv_.notify_one();
         return NEAT_OK;
@@ -193,6 +206,7 @@ class Scheduler {
     };
     struct Slot {
         bool busy = false;
+        bool launching = false;  // its launch is in progress (not polled meanwhile)
         std::vector<uint64_t> tickets;
         uint64_t bytes = 0, genome_inputs = 0;
     };
@@ -232,27 +246,93 @@ class Scheduler {
         sl.busy = false;
     }
 
+    // Caller holds the lock.  Nothing queued and no slot busy: the worker is
+    // asleep, not polling (a launch on another thread beside its polling
+    // would contend with it for the runtime).
+    bool idle() const {
+        if (!queue_.empty()) return false;
+        for (const Slot &sl : slots_)
+            if (sl.busy) return false;
+        return true;
+    }
+
+    // Caller holds the lock.  A free slot (next in turn), or -1.
+    int free_slot() const {
+        for (int k = 0; k < (int)slots_.size(); ++k) {
+            const int c = (next_slot_ + k) % (int)slots_.size();
+            if (!slots_[c].busy) return c;
+        }
+        return -1;
+    }
+
+    // Caller holds the lock.  Admit queued-or-new request tk into slot fs.
+    void admit(int fs, uint64_t tk) {
+        Slot &sl = slots_[fs];
+        Req &q = reqs_[tk];
+        q.state = ADMITTED;
+        q.res.t_admit_ns = now_ns();
+        used_ += q.bytes;
+        sl.bytes += q.bytes;
+        sl.genome_inputs += q.genome_inputs;
+        sl.tickets.push_back(tk);
+        admitted_++;
+    }
+
+    // Caller holds the lock, which is released around the launch of slot fs
+    // (its admitted requests' payloads in `batch`) and held again on return.
+    // The slot is marked busy and launching first, so that nobody polls it
+    // or launches beside it until the executor has started it.
+    void run(std::unique_lock<std::mutex> &lk, int fs,
+             const std::vector<const Payload *> &batch) {
+        Slot &sl = slots_[fs];
+        peak_ = std::max(peak_, used_);
+        sl.busy = true;
+        sl.launching = true;
+        launching_++;
+        next_slot_ = (fs + 1) % (int)slots_.size();
+        batches_++;
+        batched_ += sl.tickets.size();
+        // payloads of admitted requests stay in place (the map keeps its
+        // nodes; they are erased only once done)
+        lk.unlock();
+        const int rc = ex_->launch(fs, batch);
+        if (rc != NEAT_OK) ex_->drain(fs);
+        lk.lock();
+        sl.launching = false;
+        launching_--;
+        if (rc != NEAT_OK) finish(fs, rc);
+        // the worker polls the slot from now on
+        wake_.fetch_add(1, std::memory_order_release);
+        cv_.notify_one();
+    }
+
+    // Caller holds the lock.  Slots the worker may poll.
+    void pollable(std::vector<int> &out) const {
+        out.clear();
+        for (int k = 0; k < (int)slots_.size(); ++k)
+            if (slots_[k].busy && !slots_[k].launching) out.push_back(k);
+    }
+
     // Caller holds the lock (released while polling, held again on return).
-    // Poll the busy slots without sleeping for up to spin_us, finishing those
-    // that report completion (each report is acted on once); true once one
-    // has finished or a request was queued meanwhile.
+    // Poll the running slots without sleeping for up to spin_us, finishing
+    // those that report completion (each report is acted on once); true once
+    // one has finished, or a request was queued or a slot started meanwhile.
     bool spin(std::unique_lock<std::mutex> &lk) {
         std::vector<int> busy, done;
-        for (int k = 0; k < (int)slots_.size(); ++k)
-            if (slots_[k].busy) busy.push_back(k);
-        const uint64_t seen = queued_.load(std::memory_order_acquire);
+        pollable(busy);
+        const uint64_t seen = wake_.load(std::memory_order_acquire);
         lk.unlock();
         const auto until = std::chrono::steady_clock::now() + std::chrono::microseconds(spin_us_);
-        bool queued = false;
-        while (done.empty() && !queued && std::chrono::steady_clock::now() < until) {
+        bool woken = false;
+        while (done.empty() && !woken && std::chrono::steady_clock::now() < until) {
             for (int k : busy)
                 if (ex_->finished(k)) done.push_back(k);
-            queued = queued_.load(std::memory_order_acquire) != seen;
-            if (done.empty() && !queued) std::this_thread::yield();
+            woken = wake_.load(std::memory_order_acquire) != seen;
+            if (done.empty() && !woken) std::this_thread::yield();
         }
         lk.lock();
         for (int k : done) finish(k, NEAT_OK);
-        return !done.empty() || queued;
+        return !done.empty() || woken;
     }
 
     void loop() {
@@ -262,9 +342,7 @@ class Scheduler {
         std::vector<const Payload *> batch;
         for (;;) {
             // completions, polled without the lock
-            busy.clear();
-            for (int k = 0; k < (int)slots_.size(); ++k)
-                if (slots_[k].busy) busy.push_back(k);
+            pollable(busy);
             if (!busy.empty()) {
                 lk.unlock();
                 done.clear();
@@ -278,42 +356,21 @@ class Scheduler {
             if (stop_ && queue_.empty() && !any_busy) break;
             // admission into a free slot, in arrival order, while the
             // footprint fits (a request alone always fits beside the
-            // resident bytes: submit refuses the others)
-            int fs = -1;
-            for (int k = 0; k < (int)slots_.size() && fs < 0; ++k) {
-                const int c = (next_slot_ + k) % (int)slots_.size();
-                if (!slots_[c].busy) fs = c;
-            }
+            // resident bytes: submit refuses the others); one launch at a
+            // time, so launches follow admission order
+            const int fs = launching_ == 0 ? free_slot() : -1;
             if (fs >= 0 && !queue_.empty()) {
                 Slot &sl = slots_[fs];
                 batch.clear();
-                const int64_t t = now_ns();
                 while (!queue_.empty() && (int)sl.tickets.size() < max_batch_) {
                     Req &q = reqs_[queue_.front()];
                     if (used_ + q.bytes > cap_) break;
-                    q.state = ADMITTED;
-                    q.res.t_admit_ns = t;
-                    used_ += q.bytes;
-                    sl.bytes += q.bytes;
-                    sl.genome_inputs += q.genome_inputs;
-                    sl.tickets.push_back(queue_.front());
+                    admit(fs, queue_.front());
                     batch.push_back(&q.payload);
                     queue_.pop_front();
-                    admitted_++;
                 }
                 if (!sl.tickets.empty()) {
-                    peak_ = std::max(peak_, used_);
-                    sl.busy = true;
-                    next_slot_ = (fs + 1) % (int)slots_.size();
-                    batches_++;
-                    batched_ += sl.tickets.size();
-                    // payloads of admitted requests stay in place (the map
-                    // keeps its nodes; they are erased only once done)
-                    lk.unlock();
-                    const int rc = ex_->launch(fs, batch);
-                    if (rc != NEAT_OK) ex_->drain(fs);
-                    lk.lock();
-                    if (rc != NEAT_OK) finish(fs, rc);
+                    run(lk, fs, batch);
                     continue;
                 }
             }
@@ -324,13 +381,21 @@ class Scheduler {
                 cv_.wait_until(lk, std::chrono::system_clock::now() +
                                        std::chrono::microseconds(poll_us_));
             else
-                cv_.wait(lk, [this] { return stop_ || !queue_.empty(); });
+                // (a request admitted at submission starts a slot without
+                // queueing anything: wake for a busy slot too)
+                cv_.wait(lk, [this] {
+                    if (stop_ || !queue_.empty()) return true;
+                    for (const Slot &sl : slots_)
+                        if (sl.busy) return true;
+                    return false;
+                });
         }
     }
 
     Executor<Payload> *ex_;
     const uint64_t cap_;
     const int max_batch_, poll_us_, spin_us_;
+    const bool direct_;
     std::vector<Slot> slots_;
     const std::chrono::steady_clock::time_point t0_;
     std::mutex m_;
@@ -340,7 +405,8 @@ class Scheduler {
     std::deque<uint64_t> queue_;
     int next_slot_ = 0;
     uint64_t next_ticket_ = 1;
-    std::atomic<uint64_t> queued_{0};  // requests ever queued (read while spinning)
+    int launching_ = 0;                // slots whose launch is in progress
+    std::atomic<uint64_t> wake_{0};    // requests queued or slots started (read while spinning)
     uint64_t used_ = 0, resident_ = 0, peak_ = 0;
     std::vector<int64_t> lat_ns_;
     uint64_t submitted_ = 0, admitted_ = 0, completed_ = 0, rejected_ = 0, batches_ = 0;

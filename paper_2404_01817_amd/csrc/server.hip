@@ -39,9 +39,11 @@ constexpr size_t TABLE_ITEMS = 4 * MAX_BATCH_REQUESTS;  // items per batch table
 // class)
 constexpr size_t REQ_TABLE_BYTES = 4 * sizeof(neat::FwdItem);
 // completion polling of the scheduler: without sleeping for up to SPIN_US
-// after each admission or completion, then every POLL_US
+// after each admission or completion, then every POLL_US; a request that
+// finds the server idle is launched by the submitting thread
 constexpr int POLL_US = 20;
 constexpr int SPIN_US = 250;
+constexpr bool DIRECT = true;
 
 struct Pop {
     neat_dims d{};
@@ -69,7 +71,18 @@ class HipExec : public neat::sched::Executor<Payload> {
 
     void thread_init() override { (void)hipSetDevice(device); }
 
+    // A request admitted at submission is launched on the caller's thread:
+    // the server's device for the launch, the caller's current device kept.
     int launch(int k, const std::vector<const Payload *> &batch) override {
+        int prev = device;
+        if (hipGetDevice(&prev) != hipSuccess) prev = device;
+        if (prev != device && hipSetDevice(device) != hipSuccess) return NEAT_E_HIP;
+        const int rc = launch_on(k, batch);
+        if (prev != device) (void)hipSetDevice(prev);
+        return rc;
+    }
+
+    int launch_on(int k, const std::vector<const Payload *> &batch) {
         SlotRes &sl = slots[k];
         std::vector<neat::FwdJob> jobs;
         jobs.reserve(batch.size());
@@ -196,7 +209,7 @@ int neat_server_create(const neat_server_cfg *cfg, neat_server **out) {
                                         : hip_fail(e, "server create");
     }
     s->sched.reset(new (std::nothrow) neat::sched::Scheduler<Payload>(
-        &s->exec, cfg->max_inflight, cfg->cap_bytes, MAX_BATCH_REQUESTS, POLL_US, SPIN_US));
+        &s->exec, cfg->max_inflight, cfg->cap_bytes, MAX_BATCH_REQUESTS, POLL_US, SPIN_US, DIRECT));
     if (!s->sched) {
         free_server(s);
         return fail(NEAT_E_NOMEM, "out of host memory");

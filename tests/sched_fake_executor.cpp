@@ -51,8 +51,24 @@ class FakeExec : public Executor<Req> {
           fail_every_(fail_every), end_(slots, -1), bytes_(slots, 0), last_seq_(64, -1),
           rng_(12345) {}
 
-    int launch(int k, const std::vector<const Req *> &batch) override {
+    void thread_init() override {
         std::lock_guard<std::mutex> lk(m_);
+        worker_ = std::this_thread::get_id();
+    }
+    int launch(int k, const std::vector<const Req *> &batch) override {
+        {
+            std::lock_guard<std::mutex> lk(m_);
+            CHECK(launching_ == 0);  // launches never overlap
+            launching_++;
+            launching_slot_ = k;
+            if (std::this_thread::get_id() != worker_) off_worker_++;
+        }
+        // a launch takes a while (as a real one does): nobody may poll the
+        // slot or launch beside it meanwhile
+        std::this_thread::sleep_for(std::chrono::microseconds(3));
+        std::lock_guard<std::mutex> lk(m_);
+        launching_--;
+        launching_slot_ = -1;
         CHECK(k >= 0 && k < (int)end_.size());
         CHECK(end_[k] < 0);  // the slot is idle
         uint64_t b = 0;
@@ -78,6 +94,7 @@ class FakeExec : public Executor<Req> {
     }
     bool finished(int k) override {
         std::lock_guard<std::mutex> lk(m_);
+        CHECK(k != launching_slot_);  // never polled while its launch runs
         if (end_[k] >= 0 && now_us() >= end_[k]) {
             end_[k] = -1;
             bytes_[k] = 0;
@@ -94,6 +111,11 @@ class FakeExec : public Executor<Req> {
         std::lock_guard<std::mutex> lk(m_);
         return launches_;
     }
+    // launches made by a thread other than the worker (direct admissions)
+    int off_worker() {
+        std::lock_guard<std::mutex> lk(m_);
+        return off_worker_;
+    }
     size_t max_batch() {
         std::lock_guard<std::mutex> lk(m_);
         return max_batch_;
@@ -109,14 +131,46 @@ class FakeExec : public Executor<Req> {
     std::mt19937 rng_;
     int launches_ = 0;
     size_t max_batch_ = 0;
+    int launching_ = 0, launching_slot_ = -1;
+    std::thread::id worker_;
+    int off_worker_ = 0;
 };
 
-// spin: the scheduler's polling without sleeping (0: timed waits only)
-void stream_test(int spin) {
+// Light load: one submitter waits for each result before the next request,
+// so every request finds the scheduler idle.  With direct admission each is
+// launched by the submitting thread; without, by the worker.
+void light_test(bool direct) {
+    FakeExec fx(2, 1000, 0, 20, 60, 0);
+    Scheduler<Req> s(&fx, 2, 1000, 16, 5, 100, direct);
+    for (int i = 0; i < 200; ++i) {
+        Req q;
+        q.submitter = 0;
+        q.seq = i;
+        q.bytes = 10;
+        uint64_t tk = 0;
+        CHECK(s.submit(q, q.bytes, 1, (uint64_t)i, false, &tk) == NEAT_OK);
+        Result r;
+        int rc;
+        while ((rc = s.poll(tk, &r)) == NEAT_PENDING) std::this_thread::yield();
+        CHECK(rc == NEAT_OK && r.status == NEAT_OK && r.tag == (uint64_t)i);
+        CHECK(r.t_submit_ns <= r.t_admit_ns && r.t_admit_ns <= r.t_done_ns);
+    }
+    const neat::sched::Stats st = s.stats();
+    CHECK(st.completed == 200 && st.batches == 200 && st.queued == 0);
+    CHECK(fx.launches() == 200);
+    CHECK(direct ? fx.off_worker() == 200 : fx.off_worker() == 0);
+    std::printf("light load (direct %d): %d of 200 launches on the submitting thread, p50 %.3f ms\n",
+                (int)direct, fx.off_worker(), st.p50_ms);
+}
+
+// spin: the scheduler's polling without sleeping (0: timed waits only);
+// direct: requests admitted and launched by the submitting thread when
+// nothing waits
+void stream_test(int spin, bool direct) {
     const int slots = 4, threads = 6, per = 300;
     const uint64_t cap = 1000, resident = 200;
     FakeExec fx(slots, cap, resident, 20, 400, 41);
-    Scheduler<Req> s(&fx, slots, cap, 16, 5, spin);
+    Scheduler<Req> s(&fx, slots, cap, 16, 5, spin, direct);
     CHECK(s.add_resident(resident) == NEAT_OK);
     CHECK(s.add_resident(cap) == NEAT_E_TOO_LARGE);  // nothing held by the refusal
     std::atomic<int> rejected{0}, ok{0}, errored{0};
@@ -168,17 +222,18 @@ void stream_test(int spin) {
     CHECK(st.batches == (uint64_t)fx.launches());
     // continuous batching: under this load some batch held several requests
     CHECK(fx.max_batch() > 1);
-    std::printf("stream (spin %d us): %d requests, %d rejected, %llu batches (%.2f requests per "
-                "batch, largest %zu), %d failed launches' requests, p50 %.3f ms p99 %.3f ms\n",
-                spin, threads * per, rejected.load(), (unsigned long long)st.batches,
+    std::printf("stream (spin %d us, direct %d): %d requests, %d rejected, %llu batches (%.2f "
+                "requests per batch, largest %zu), %d failed launches' requests, p50 %.3f ms p99 "
+                "%.3f ms\n",
+                spin, (int)direct, threads * per, rejected.load(), (unsigned long long)st.batches,
                 (double)st.batched_requests / (double)st.batches, fx.max_batch(),
                 errored.load(), st.p50_ms, st.p99_ms);
 }
 
-void shutdown_test(int spin) {
+void shutdown_test(int spin, bool direct) {
     const int slots = 2;
     FakeExec fx(slots, 1u << 30, 0, 20000, 30000, 0);
-    auto *s = new Scheduler<Req>(&fx, slots, 1u << 30, 4, 5, spin);
+    auto *s = new Scheduler<Req>(&fx, slots, 1u << 30, 4, 5, spin, direct);
     std::vector<uint64_t> tickets;
     for (int i = 0; i < 100; ++i) {
         Req q;
@@ -205,7 +260,8 @@ void shutdown_test(int spin) {
     q.seq = 1000;
     CHECK(s->submit(q, 1, 1, 0, false, &tk) == NEAT_E_SHUTDOWN);
     delete s;
-    std::printf("shutdown (spin %d us): %d finished, %d cancelled\n", spin, done, cancelled);
+    std::printf("shutdown (spin %d us, direct %d): %d finished, %d cancelled\n", spin, (int)direct,
+                done, cancelled);
 }
 
 void empty_request_test() {
@@ -225,10 +281,12 @@ void empty_request_test() {
 }  // namespace
 
 int main() {
-    for (int spin : {0, 100}) {
-        stream_test(spin);
-        shutdown_test(spin);
-    }
+    for (int spin : {0, 100})
+        for (bool direct : {false, true}) {
+            stream_test(spin, direct);
+            shutdown_test(spin, direct);
+        }
+    for (bool direct : {false, true}) light_test(direct);
     empty_request_test();
     if (g_fail) {
         std::fprintf(stderr, "%d check(s) failed\n", g_fail.load());
