@@ -7,7 +7,8 @@ running requests) stays under the cap and that each submitter's requests
 are admitted in submission order; the test program checks tickets, results,
 statistics, rejection by footprint, launch errors, continuous batching
 (several requests per batch under load) and shutdown with queued
-requests."""
+requests; each with and without admission by the submitting thread, plus
+a light load where every request finds the scheduler idle."""
 from __future__ import annotations
 
 import os
