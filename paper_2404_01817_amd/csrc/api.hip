@@ -377,7 +377,7 @@ int neat_autotune_forward(const neat_dims *d, const void *program, const float *
         hipEvent_t e0, e1;
         if (hipEventCreate(&e0) != hipSuccess) return hip_fail(hipGetLastError(), "event");
         if (hipEventCreate(&e1) != hipSuccess) {
-            hipEventDestroy(e0);
+            (void)hipEventDestroy(e0);
             return hip_fail(hipGetLastError(), "event");
         }
         const hipStream_t s = (hipStream_t)stream;
@@ -391,8 +391,8 @@ int neat_autotune_forward(const neat_dims *d, const void *program, const float *
             if (best_tp == NEAT_FWD_AUTO || ms[NC + i] < best_tp_ms)
                 best_tp = cand[i], best_tp_ms = ms[NC + i];
         }
-        hipEventDestroy(e0);
-        hipEventDestroy(e1);
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
         if (rc != NEAT_OK) return rc;
         std::lock_guard<std::mutex> lock(g_tune_mu);
         tune_env_locked();

@@ -30,7 +30,6 @@ namespace {
 
 constexpr int WAVE = 64;
 constexpr unsigned long long EMPTY64 = ~0ull;
-constexpr unsigned EMPTY32 = ~0u;
 
 __device__ __forceinline__ unsigned key_bits(float k) {
     return __float_as_uint(k == 0.0f ? 0.0f : k);  // -0 -> +0
