@@ -112,8 +112,8 @@ size_t neat_program_bytes(const neat_dims *dims);
  * edges including padding, [2] status, [3] levels, [4] I, [5] O, [6] slot
  * class (0..3, see NEAT_FWD_AUTO), [7] enabled edges, [8] value slots in use
  * (the largest set of simultaneously live values; for N_max <= 62, where
- * every genome fits the smallest class, the nodes in use).  0 on invalid
- * dims. */
+ * every genome fits the smallest class, the nodes in use); words 9..15 are
+ * reserved and left unwritten.  0 on invalid dims. */
 size_t neat_program_stride(const neat_dims *dims);
 
 /*
@@ -126,6 +126,10 @@ size_t neat_program_stride(const neat_dims *dims);
  *   program neat_program_bytes(dims) bytes, or NULL to skip building it
  * order, level and status may each be NULL when not wanted.  The program is
  * what neat_forward consumes; it stays valid as long as the caller keeps it.
+ * order, level, status, the program headers and every output computed from
+ * the program are the same on every call; for N_max > 64 the value-slot
+ * numbers inside the program may differ from call to call (which freed slot
+ * a value takes follows the order of LDS atomics across the group's waves).
  * Errors: NEAT_E_INVALID (bad dims, NULL nodes/conns with P > 0, or a
  * population whose per-genome working set does not fit in LDS), NEAT_E_HIP.
  */

@@ -530,6 +530,40 @@ def test_slot_allocation_is_the_largest_live_set():
             assert hdr[g, 6] == cls
 
 
+def test_retransformation_changes_only_slot_numbers():
+    """Transforming the same populations of N_max > 64 again gives the same
+    order, levels, status and program headers (slot count and class among
+    them) and bit-identical outputs.  Only which free slot a value takes may
+    change between calls (extra frees at one position are ranked by the
+    order of LDS atomics across the group's waves), and every such program
+    still computes the oracle's outputs."""
+    neat = _neat()
+    dev = torch.device("cuda:0")
+    rng = np.random.default_rng(77)
+    for lo, hi in ((65, 120), (260, 420)):
+        pop = synth.uneven_population(rng, (40, 80), (lo, hi), (1, 2), with_inputs=False)
+        print("case retransform N_max", pop.N_max, "P", pop.P, flush=True)
+        tn = torch.from_numpy(pop.nodes).to(dev)
+        tc = torch.from_numpy(pop.conns).to(dev)
+        d = neat.dims_of(tn, tc, pop.I, pop.O)
+        B = 40
+        x = rng.standard_normal((pop.P, B, pop.I)).astype(np.float32)
+        tx = torch.from_numpy(x).to(dev)
+        runs = []
+        for _ in range(4):
+            order, level, status, prog = neat.topo_sort(tn, tc, pop.I, pop.O)
+            # the defined header words (9..15 are not written)
+            hdr = neat.program_headers(d, prog).cpu().numpy()[:, :9]
+            y = neat.forward(d, prog, tx, B).cpu().numpy()
+            runs.append((order.cpu().numpy(), level.cpu().numpy(), status.cpu().numpy(), hdr, y))
+        for r in runs[1:]:
+            for a, b in zip(runs[0][:4], r[:4]):
+                assert np.array_equal(a, b)
+            assert np.array_equal(runs[0][4].view(np.uint32), r[4].view(np.uint32))
+        y64, beta = oracle.forward(pop.nodes, pop.conns, x, pop.I, pop.O)
+        _assert_outputs(runs[0][4], y64, beta, "retransform N_max=%d" % pop.N_max)
+
+
 @pytest.mark.parametrize("O", [4, 230])
 def test_largest_supported_sizes(O):
     """N_max = 600 (I + N_max close to the LDS-row store's limit of 638) and
