@@ -62,7 +62,9 @@
  * stream (hipStream_t passed as void*, NULL = the default stream) and return
  * only argument and launch errors.  Return codes: 0 OK, > 0 pending, < 0
  * error (NEAT_E_*); neat_last_error() gives the calling thread's last error
- * message.  Entry points are reentrant; no exception crosses the ABI.
+ * message.  A NULL handle, dims, item list or result pointer, and dims out
+ * of range, give NEAT_E_INVALID before any device work (also with no GPU
+ * present).  Entry points are reentrant; no exception crosses the ABI.
  */
 #ifndef NEAT_H
 #define NEAT_H

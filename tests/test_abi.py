@@ -84,3 +84,43 @@ def test_server_create_reports_errors_without_crashing():
     assert lib.neat_submit(None, None, None) == -1
     assert lib.neat_poll(None, 1, None) == -1
     assert lib.neat_server_destroy(None) == -1
+
+
+_COMPUTE = ["neat_topo_sort", "neat_forward", "neat_forward_ex", "neat_autotune_forward",
+            "neat_forward_grid", "neat_distance", "neat_apply_edits", "neat_crossover",
+            "neat_substrate_forward", "neat_topo_sort_recurrent", "neat_forward_recurrent",
+            "neat_forward_batch", "neat_forward_batch_noalloc", "neat_server_create",
+            "neat_server_destroy", "neat_server_register", "neat_submit", "neat_submit_many",
+            "neat_poll", "neat_server_stats", "neat_server_reset_stats"]
+_INTS = (ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_float)
+
+
+def test_every_entry_point_refuses_null_arguments():
+    """Every compute and server entry point, given NULL for each pointer
+    (and 1 for each count), fails with NEAT_E_INVALID and a message before
+    touching a device, so it behaves the same with or without a GPU."""
+    lib = _lib.lib()
+    for name in _COMPUTE:
+        _, args = _lib.SIGNATURES[name]
+        vals = [1 if a in _INTS else None for a in args]
+        rc = getattr(lib, name)(*vals)
+        assert rc == -1, (name, rc)
+        assert lib.neat_last_error().decode(), name
+
+
+def test_invalid_dims_are_refused_before_any_access():
+    """Out-of-range dims fail with NEAT_E_INVALID naming the field; the
+    (host) pointers passed are never dereferenced."""
+    lib = _lib.lib()
+    buf = (ctypes.c_float * 16)()
+    p = ctypes.cast(buf, ctypes.c_void_p)
+    cases = [((1, 0, 4, 1, 1), "N_max"), ((1, 20000, 4, 1, 1), "N_max"),
+             ((-1, 8, 4, 1, 1), "P"), ((1, 8, -1, 1, 1), "C_max"),
+             ((1, 8, 1 << 20, 1, 1), "C_max"), ((1, 8, 4, 0, 1), "I"), ((1, 8, 4, 6, 3), "I")]
+    for dims, field in cases:
+        d = _lib.Dims(*dims)
+        rc = lib.neat_topo_sort(ctypes.byref(d), p, p, p, p, p, p, None)
+        assert rc == -1, dims
+        assert field in lib.neat_last_error().decode(), (dims, lib.neat_last_error())
+        rc = lib.neat_forward(ctypes.byref(d), p, p, 0, 1, p, None)
+        assert rc == -1, dims
