@@ -62,9 +62,9 @@
  * stream (hipStream_t passed as void*, NULL = the default stream) and return
  * only argument and launch errors.  Return codes: 0 OK, > 0 pending, < 0
  * error (NEAT_E_*); neat_last_error() gives the calling thread's last error
- * message.  A NULL handle, dims, item list or result pointer, and dims out
- * of range, give NEAT_E_INVALID before any device work (also with no GPU
- * present).  Entry points are reentrant; no exception crosses the ABI.
+ * message.  A NULL server, dims or item list, a NULL pointer that an entry
+ * point requires, and dims out of range give NEAT_E_INVALID before any
+ * device work (also with no GPU present).  Entry points are reentrant; no exception crosses the ABI.
  */
 #ifndef NEAT_H
 #define NEAT_H
@@ -588,7 +588,7 @@ int neat_submit(neat_server *server, const neat_request *request, uint64_t *tick
  * the tickets from it on are set to 0.  n = 0 does nothing. */
 int neat_submit_many(neat_server *server, const neat_request *requests, int32_t n,
                      uint64_t *tickets);
-/* NEAT_OK (result filled, ticket forgotten), NEAT_PENDING, or
+/* NEAT_OK (result filled unless NULL, ticket forgotten), NEAT_PENDING, or
  * NEAT_E_UNKNOWN_TICKET.  Never blocks. */
 int neat_poll(neat_server *server, uint64_t ticket, neat_result *result);
 /* Counters and latency percentiles since creation or the last reset. */
